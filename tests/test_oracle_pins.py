@@ -1,0 +1,382 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every oracle function is checked here against something other than itself:
+closed forms, invariants, textbook routines, brute force on tiny meshes and
+exact finite differences.  No GPU.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from synth import make_system, make_walkers, make_fields
+from oracle import kpoint as kp
+from oracle import supercell as sc
+from oracle import molecular as mol
+
+# meshes that exercise: molecular, self-inverse Q, only Q=0 self-inverse,
+# anisotropic linearisation, and mixed
+MESHES = [(1, 1, 1), (1, 1, 2), (2, 2, 2), (3, 1, 1), (2, 3, 1), (1, 2, 3)]
+
+
+def tiny(mesh, m=4, nocc=2, nchol=5, seed=11, trial="random", walkers="dense", nw=2):
+    s, rng = make_system(mesh, m, nocc, nchol, seed=seed, trial=trial)
+    U = make_walkers(s, nw, rng, kind=walkers)
+    x = make_fields(s, nw, 1, rng)[0]
+    return s, U, x
+
+
+def supercell_objects(s):
+    LL = sc.unfold_cholesky(s.L, s.mesh)
+    return LL, sc.eri(LL), sc.block_diag(s.H1), sc.block_diag(s.A)
+
+
+# ---------------------------------------------------------------------------
+# index algebra and generator
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mesh", MESHES + [(4, 4, 4)])
+def test_kpoint_tables_brute_force(mesh):
+    kmq, negq = kp.kpoint_tables(mesh)
+    nk = int(np.prod(mesh))
+    vec = [(a, b, c) for a in range(mesh[0]) for b in range(mesh[1]) for c in range(mesh[2])]
+    for Q in range(nk):
+        assert vec[negq[Q]] == tuple((-vec[Q][i]) % mesh[i] for i in range(3))
+        for k in range(nk):
+            assert vec[kmq[Q, k]] == tuple((vec[k][i] - vec[Q][i]) % mesh[i] for i in range(3))
+    assert np.all(negq[negq] == np.arange(nk))
+
+
+@pytest.mark.parametrize("mesh", MESHES)
+def test_generator_time_reversal_and_hermiticity(mesh):
+    s, _, _ = tiny(mesh)
+    kmq, negq = kp.kpoint_tables(mesh)
+    for Q in range(s.nk):
+        for k in range(s.nk):
+            part = s.L[negq[Q], kmq[Q, k]].transpose(1, 0, 2)
+            assert np.array_equal(np.conj(s.L[Q, k]), part)
+    assert np.array_equal(s.H1, s.H1.conj().transpose(0, 2, 1))
+    for k in range(s.nk):
+        assert np.allclose(s.A[k].conj().T @ s.A[k], np.eye(s.nocc), atol=1e-13)
+
+
+def test_generator_reproducible():
+    a, ua, xa = tiny((2, 1, 1), seed=5)
+    b, ub, xb = tiny((2, 1, 1), seed=5)
+    assert np.array_equal(a.L, b.L) and np.array_equal(ua, ub) and np.array_equal(xa, xb)
+    c, _, _ = tiny((2, 1, 1), seed=6)
+    assert not np.array_equal(a.L, c.L)
+
+
+def test_eri_hermitian_and_pair_symmetric():
+    s, _, _ = tiny((2, 3, 1), m=3, nchol=4)
+    _, v, _, _ = supercell_objects(s)
+    # Hermiticity of H2 and exchange of the two electrons
+    assert np.abs(v - v.transpose(2, 3, 0, 1).conj()).max() < 1e-14
+    assert np.abs(v - v.transpose(1, 0, 3, 2)).max() < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# P-1: trial determinant = Hartree-Fock energy
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mesh", [(1, 1, 1), (2, 2, 2), (2, 3, 1)])
+@pytest.mark.parametrize("trial", ["identity", "random"])
+def test_trial_energy_equals_slater_condon(mesh, trial):
+    s, _, _ = tiny(mesh, m=4, nocc=2, nchol=5, trial=trial)
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    LL, v, h, Af = supercell_objects(s)
+    Gh, _ = kp.greens(Af[None], s.A)
+    E = kp.local_energy(pre["Lh"], pre["h1h"], Gh, mesh)[0]
+    e1, ec, ex = sc.slater_condon_energy(h, v, Af)
+    assert abs(E[0] - e1) < 1e-12 * max(1.0, abs(e1))
+    assert abs(E[1] - ec) < 1e-12 * max(1.0, abs(ec))
+    assert abs(E[2] - ex) < 1e-12 * max(1.0, abs(ex))
+    assert abs(E.imag).max() < 1e-12
+    assert E[2].real < 0.0
+
+
+def test_trial_energy_closed_form_identity_trial():
+    s, _, _ = tiny((2, 2, 2), m=5, nocc=2, nchol=6, trial="identity")
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    Af = sc.block_diag(s.A)
+    Gh, _ = kp.greens(Af[None], s.A)
+    E = kp.local_energy(pre["Lh"], pre["h1h"], Gh, s.mesh)[0]
+    n = s.nocc
+    e1 = 2.0 * sum(s.H1[k, a, a] for k in range(s.nk) for a in range(n))
+    x0 = 2.0 * np.einsum("kaag->g", s.L[0][:, :n, :n, :])
+    ec = 0.5 * np.sum(x0 * x0)
+    ex = -np.sum(np.abs(s.L[:, :, :n, :n, :]) ** 2)
+    np.testing.assert_allclose(E, [e1, ec, ex], rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# P-2: Green's function invariants
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mesh", [(2, 1, 1), (2, 3, 1)])
+def test_greens_invariants(mesh):
+    s, U, _ = tiny(mesh, trial="random")
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    Af = sc.block_diag(s.A)
+    Gh, logdet = kp.greens(U, s.A)
+    for w in range(U.shape[0]):
+        assert np.abs(Gh[w] @ Af.conj() - np.eye(Af.shape[1])).max() < 1e-12
+        G = Af.conj() @ Gh[w]
+        assert np.abs(G @ G - G).max() < 1e-12
+        assert abs(np.trace(G) - s.nk * s.nocc) < 1e-12
+        # independent determinant: product of LU pivots from scipy
+        lu, piv = scipy.linalg.lu_factor(Af.conj().T @ U[w])
+        sign = (-1) ** np.sum(piv != np.arange(len(piv)))
+        ld = np.sum(np.log(np.diag(lu).astype(complex))) + (0 if sign > 0 else 1j * np.pi)
+        assert abs(np.exp(ld - logdet[w]) - 1.0) < 1e-12
+    # invariance under U -> U R
+    rng = np.random.default_rng(0)
+    R = rng.standard_normal((U.shape[2], U.shape[2])) + 1j * rng.standard_normal((U.shape[2],) * 2)
+    Gh2, logdet2 = kp.greens(U @ R, s.A)
+    assert np.abs(Gh2 - Gh).max() < 1e-11
+    dl = np.linalg.slogdet(R)
+    expect = logdet + dl[1] + 1j * np.angle(dl[0])
+    assert np.abs(np.exp(logdet2 - expect) - 1.0).max() < 1e-11
+    E1 = kp.local_energy(pre["Lh"], pre["h1h"], Gh, mesh)
+    E2 = kp.local_energy(pre["Lh"], pre["h1h"], Gh2, mesh)
+    assert np.abs(E1 - E2).max() < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# P-3: force bias = derivative of the log overlap
+# ---------------------------------------------------------------------------
+
+def test_force_bias_is_log_overlap_derivative():
+    mesh = (2, 3, 1)
+    s, U, _ = tiny(mesh, m=3, nocc=1, nchol=3, trial="random")
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    LL, _, _, Af = supercell_objects(s)
+    Gh, _ = kp.greens(U, s.A)
+    _, X = kp.force_bias(pre["Lh"], Gh, mesh, s.dt)
+    eps = 1e-5
+    w = 0
+    for gam in range(LL.shape[0]):
+        Q, g = divmod(gam, s.nchol)
+
+        def f(e):
+            M = Af.conj().T @ scipy.linalg.expm(e * LL[gam]) @ U[w]
+            sgn, la = np.linalg.slogdet(M)
+            return 2.0 * (la + 1j * np.angle(sgn))
+
+        fd = (f(eps) - f(-eps)) / (2 * eps)
+        assert abs(fd - X[w, Q, g]) < 1e-7 * max(1.0, abs(X[w, Q, g]))
+
+
+# ---------------------------------------------------------------------------
+# P-4: Hartree identity links force bias and Coulomb energy
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mesh", [(2, 2, 2), (3, 1, 1), (1, 2, 3)])
+def test_hartree_identity(mesh):
+    s, U, _ = tiny(mesh, trial="random")
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    Gh, _ = kp.greens(U, s.A)
+    xbar, _ = kp.force_bias(pre["Lh"], Gh, mesh, s.dt)
+    E = kp.local_energy(pre["Lh"], pre["h1h"], Gh, mesh)
+    hart = -np.sum(xbar ** 2, axis=(1, 2, 3)) / (2.0 * s.dt)
+    assert np.abs(E[:, 1] - hart).max() < 1e-11 * max(1.0, np.abs(hart).max())
+
+
+# ---------------------------------------------------------------------------
+# P-5: the HS exponent is anti-Hermitian for real fields (unitary propagator)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mesh", [(2, 2, 2), (3, 1, 1), (2, 3, 1)])
+def test_hs_exponent_antihermitian(mesh):
+    s, U, x = tiny(mesh, trial="random")
+    zeta = kp.combined_field(x, np.zeros_like(x, dtype=complex), mesh)
+    vhs = kp.hs_potential(s.L, zeta, mesh)
+    V = -math.sqrt(s.dt) * vhs
+    for w in range(V.shape[0]):
+        assert np.abs(V[w] + V[w].conj().T).max() < 1e-15
+        nv = np.linalg.norm(V[w], 2)
+        T = kp.taylor_exp_apply(V[w], np.eye(V.shape[1]), 6)
+        bound = nv ** 7 / math.factorial(7) * math.exp(nv)
+        dev = np.linalg.norm(T.conj().T @ T - np.eye(V.shape[1]), 2)
+        # T^H T - I = -(e^V)^H R - R^H e^V + R^H R with ||R|| <= bound
+        assert dev <= 2.0 * bound + bound ** 2 + 1e-14
+
+
+# ---------------------------------------------------------------------------
+# P-6: 6th-order Taylor against scipy expm, within the remainder bound
+# ---------------------------------------------------------------------------
+
+def test_taylor_against_expm_bound():
+    s, U, x = tiny((2, 2, 2), m=4, nocc=2, nchol=5, trial="random")
+    rng = np.random.default_rng(3)
+    for scale in (0.05, 0.5, 2.0):
+        V = scale * (rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8)))
+        Uw = U[0][:8]
+        nv = np.linalg.norm(V, 2)
+        err = np.linalg.norm(kp.taylor_exp_apply(V, Uw, 6) - scipy.linalg.expm(V) @ Uw, 2)
+        bound = nv ** 7 / math.factorial(7) * math.exp(nv) * np.linalg.norm(Uw, 2)
+        assert err <= bound * (1 + 1e-12) + 1e-14
+
+
+# ---------------------------------------------------------------------------
+# P-7: Nk = 1 reduces to the standard (molecular) representation
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("trial", ["identity", "random"])
+def test_nk1_reduces_to_standard_representation(trial):
+    s, U, x = tiny((1, 1, 1), m=6, nocc=3, nchol=9, trial=trial, nw=3)
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    Gh, _ = kp.greens(U, s.A)
+    E = kp.local_energy(pre["Lh"], pre["h1h"], Gh, s.mesh)
+    xbar, _ = kp.force_bias(pre["Lh"], Gh, s.mesh, s.dt)
+    for w in range(U.shape[0]):
+        Em = mol.energy_standard(s.L[0, 0], s.H1[0], s.A[0], Gh[w])
+        assert np.abs(E[w] - Em).max() < 1e-12 * max(1.0, np.abs(Em).max())
+        xm = mol.force_bias_standard(s.L[0, 0], s.A[0], Gh[w], s.dt)
+        assert np.abs(xbar[w, 0] - xm).max() < 1e-14
+        # self-inverse Q: no (-) component
+        assert np.abs(xbar[w, :, :, 1]).max() < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# P-8: k-block-diagonal walkers
+# ---------------------------------------------------------------------------
+
+def test_block_diagonal_walker_special_cases():
+    mesh = (2, 3, 1)
+    s, U, _ = tiny(mesh, m=5, nocc=2, nchol=4, trial="identity", walkers="blockdiag")
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    Gh, _ = kp.greens(U, s.A)
+    Gb = Gh.reshape(U.shape[0], s.nk, s.nocc, s.nk, s.m)
+    for k1 in range(s.nk):
+        for k2 in range(s.nk):
+            if k1 != k2:
+                assert np.abs(Gb[:, k1, :, k2, :]).max() == 0.0
+    xbar, X = kp.force_bias(pre["Lh"], Gh, mesh, s.dt)
+    assert np.abs(X[:, 1:, :]).max() == 0.0
+    _, negq = kp.kpoint_tables(mesh)
+    for Q in range(s.nk):
+        if negq[Q] == Q:
+            assert np.abs(xbar[:, Q, :, 1]).max() == 0.0
+
+
+# ---------------------------------------------------------------------------
+# P-9: blocked formulas = unfolded supercell for every quantity
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mesh", MESHES)
+def test_blocked_equals_supercell(mesh):
+    s, U, x = tiny(mesh, m=4, nocc=2, nchol=5, trial="random", walkers="dense")
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    LL, v, h, Af = supercell_objects(s)
+    Gh, logdet = kp.greens(U, s.A)
+    xbar, _ = kp.force_bias(pre["Lh"], Gh, mesh, s.dt)
+    zeta = kp.combined_field(x, xbar, mesh)
+    vhs = kp.hs_potential(s.L, zeta, mesh)
+    U2 = kp.propagate(U, vhs, pre["bhalf"], s.dt)
+    E = kp.local_energy(pre["Lh"], pre["h1h"], Gh, mesh)
+    D = kp.energy_gradient(pre["Lh"], pre["h1h"], Gh, mesh)
+    V0 = sc.v0_full(LL)
+    assert np.abs(V0 - sc.block_diag(pre["V0"])).max() < 1e-13
+    Bfull = scipy.linalg.expm(-0.5 * s.dt * (h + V0))
+    assert np.abs(Bfull - sc.block_diag(pre["bhalf"])).max() < 1e-13
+    for w in range(U.shape[0]):
+        assert np.abs(sc.half_greens_full(U[w], Af) - Gh[w]).max() < 1e-12
+        G = sc.greens_full(U[w], Af)
+        xb1 = sc.force_bias_full(LL, G, s.dt).reshape(s.nk, s.nchol, 2)
+        assert np.abs(xb1 - xbar[w]).max() < 1e-14
+        V1 = sc.hs_matrix_full(LL, x[w].reshape(-1, 2), xbar[w].reshape(-1, 2), s.dt)
+        assert np.abs(V1 + math.sqrt(s.dt) * vhs[w]).max() < 1e-15
+        Up = sc.propagate_full(U[w], V1, h, V0, s.dt)
+        assert np.abs(Up - U2[w]).max() < 1e-13
+        E1 = sc.energy_4index(h, v, G)
+        assert np.abs(E1 - E[w]).max() < 1e-12 * max(1.0, np.abs(E1).max())
+        F = sc.fock(h, v, G)
+        assert np.abs(2.0 * Af.conj().T @ F - D[w]).max() < 1e-12 * max(1.0, np.abs(D[w]).max())
+
+
+# ---------------------------------------------------------------------------
+# P-10: adjoint = exact central difference (E is quadratic in Gh)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mesh", [(2, 2, 2), (2, 3, 1)])
+def test_adjoint_exact_central_difference(mesh):
+    s, U, _ = tiny(mesh, trial="random")
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    Gh, _ = kp.greens(U, s.A)
+    D = kp.energy_gradient(pre["Lh"], pre["h1h"], Gh, mesh)
+    rng = np.random.default_rng(7)
+    for _ in range(3):
+        dl = rng.standard_normal(Gh.shape) + 1j * rng.standard_normal(Gh.shape)
+        h = 1e-3  # quadratic: no truncation error at any step
+        Ep = kp.local_energy(pre["Lh"], pre["h1h"], Gh + h * dl, mesh).sum(1)
+        Em = kp.local_energy(pre["Lh"], pre["h1h"], Gh - h * dl, mesh).sum(1)
+        fd = (Ep - Em) / (2 * h)
+        an = np.sum(D * dl, axis=(1, 2))
+        assert np.abs(fd - an).max() < 1e-9 * max(1.0, np.abs(an).max())
+    # entrywise on one walker, a few entries
+    for (i, j) in [(0, 0), (1, 3), (Gh.shape[1] - 1, Gh.shape[2] - 1)]:
+        e = np.zeros_like(Gh)
+        e[0, i, j] = 1.0
+        h = 1e-6
+        Ep = kp.local_energy(pre["Lh"], pre["h1h"], Gh + h * e, mesh)[0].sum()
+        Em = kp.local_energy(pre["Lh"], pre["h1h"], Gh - h * e, mesh)[0].sum()
+        assert abs((Ep - Em) / (2 * h) - D[0, i, j]) < 1e-6 * max(1.0, abs(D[0, i, j]))
+
+
+def test_adjoint_at_trial_is_fock_matrix():
+    s, _, _ = tiny((2, 2, 2), m=4, nocc=2, nchol=5, trial="identity")
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    _, v, h, Af = supercell_objects(s)
+    Gh, _ = kp.greens(Af[None], s.A)
+    D = kp.energy_gradient(pre["Lh"], pre["h1h"], Gh, s.mesh)[0]
+    # at the trial, G is the projector onto the occupied orbitals
+    P = Af @ Af.conj().T
+    F = sc.fock(h, v, P.T)
+    occ = [k * s.m + a for k in range(s.nk) for a in range(s.nocc)]
+    assert np.abs(D - 2.0 * F[occ, :]).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# orthonormalisation and weights
+# ---------------------------------------------------------------------------
+
+def test_orthonormalize_preserves_g_and_energy():
+    mesh = (2, 3, 1)
+    s, U, x = tiny(mesh, trial="random")
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    Ub = U * 3.0 + 0.5 * np.roll(U, 1, axis=2)
+    Q = kp.orthonormalize(Ub)
+    for w in range(U.shape[0]):
+        assert np.abs(Q[w].conj().T @ Q[w] - np.eye(U.shape[2])).max() < 1e-13
+        R = Q[w].conj().T @ Ub[w]
+        assert np.abs(np.tril(R, -1)).max() < 1e-12
+        assert np.all(np.diag(R).real > 0) and np.abs(np.diag(R).imag).max() < 1e-12
+    G1, _ = kp.greens(Ub, s.A)
+    G2, _ = kp.greens(Q, s.A)
+    assert np.abs(G1 - G2).max() < 1e-11
+
+
+def test_weight_update_cases():
+    nw = 4
+    x = np.zeros((nw, 2, 3, 2))
+    xbar = np.zeros_like(x, dtype=complex)
+    ld0 = np.zeros(nw, dtype=complex)
+    ld1 = np.array([0.1, 0.1 + 0.3j, 0.0 + 1.0j, -0.2 + 0.5j])
+    w0 = np.array([1.0, 2.0, 1.0, 0.5])
+    w1, logI, dth = kp.weight_update(ld0, ld1, x, xbar, w0)
+    # ratio = exp(2 dlogdet); angle of ratio; cos cut
+    np.testing.assert_allclose(dth, [0.0, 0.6, 2.0, 1.0], atol=1e-15)
+    assert w1[2] == 0.0
+    np.testing.assert_allclose(w1[0], math.exp(0.2), rtol=1e-15)
+    np.testing.assert_allclose(w1[1], 2.0 * math.exp(0.2) * math.cos(0.6), rtol=1e-15)
+    # importance factor with a force bias: exp(x xbar - xbar^2/2)
+    x2 = np.full((1, 1, 1, 2), 0.5)
+    xb2 = np.full((1, 1, 1, 2), 0.25 + 0.1j)
+    w2, logI2, _ = kp.weight_update(np.zeros(1), np.zeros(1), x2, xb2, np.ones(1))
+    s = 2 * (0.5 * (0.25 + 0.1j) - 0.5 * (0.25 + 0.1j) ** 2)
+    np.testing.assert_allclose(logI2[0], s, rtol=1e-15)
+    np.testing.assert_allclose(w2[0], math.exp(s.real), rtol=1e-15)
