@@ -1,0 +1,212 @@
+/*
+ * afqmc_kpt.h -- C ABI of the k-point AFQMC walker-batch step on MI355X (gfx950).
+ *
+ * Method: phaseless auxiliary-field QMC with the two-electron integrals held as
+ * momentum-blocked Cholesky vectors (Malone, Zhang, Morales, "Accelerating
+ * Auxiliary-Field Quantum Monte Carlo Simulations of Solids with Graphical
+ * Processing Units", arXiv:2003.09468).  Section references below are to that
+ * paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - k-points form a Gamma-centred Monkhorst-Pack mesh; k is linearised
+ *    row-major, k = (k0*mesh[1] + k1)*mesh[2] + k2; k - Q and -Q are taken
+ *    componentwise modulo the mesh.
+ *  - Complex numbers are interleaved (re, im) pairs: complex128 = 2 doubles,
+ *    complex64 = 2 floats.  All arrays are row-major, last index fastest.
+ *  - L[Q][k][i][l][g]: Cholesky block for momentum transfer Q, band i at k and
+ *    band l at k - Q ("k-Point Representation", momentum convention of L^{Q,k}).
+ *    The caller guarantees the time-reversal relation
+ *    conj(L[Q][k][i][l][g]) == L[-Q][k-Q][l][i][g] (same section).
+ *  - Closed shell: one walker determinant U[w] ((nk*m) x (nk*nocc), dense)
+ *    serves both spins; the overlap with the trial is det(A^H U)^2.
+ *  - Every pointer is a DEVICE pointer unless marked "host".  The caller owns
+ *    and frees every buffer; the library allocates nothing.  Complex arrays
+ *    must be 16-byte aligned, float64 arrays 8-byte, int32 arrays 4-byte and
+ *    workspaces 256-byte aligned (AFQMC_EALIGN otherwise).
+ *  - Calls are asynchronous and ordered on the given HIP stream (a
+ *    hipStream_t passed as void*; NULL is the default stream).
+ *  - Arguments are validated on the host before any HIP call; a failed check
+ *    returns a negative status and launches nothing.  A HIP launch error
+ *    returns AFQMC_EHIP.  No call aborts, exits or throws.
+ *  - Per-walker numerical failures (singular overlap, non-finite values,
+ *    phaseless kill) are reported in status[w] and never fail the call.
+ *  - Energies are per supercell; per cell = E / nk.  The ion-ion energy is 0.
+ *  - nprob > 1 runs the problems of the array one after another on the stream.
+ */
+#ifndef AFQMC_KPT_H
+#define AFQMC_KPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AFQMC_OK = 0,
+  AFQMC_EINVAL = -1,      /* bad dimension, dt or flag */
+  AFQMC_ENULL = -2,       /* a required pointer is NULL */
+  AFQMC_EALIGN = -3,      /* a pointer is not 16-byte aligned */
+  AFQMC_EWORKSPACE = -4,  /* workspace NULL or smaller than afqmc_kpt_workspace_bytes */
+  AFQMC_ENODEV = -5,      /* no usable gfx950 device */
+  AFQMC_EHIP = -6,        /* a HIP call or kernel launch failed */
+  AFQMC_EUNSUPPORTED = -7 /* sizes outside what the kernels implement */
+} afqmc_status;
+
+/* Precision of the large complex contractions (force bias L.G, HS potential,
+ * Taylor propagation, exchange).  Overlap, Green's function inverse, QR and
+ * all energy sums are FP64 in every mode. */
+typedef enum {
+  AFQMC_PREC_FP64 = 0,
+  AFQMC_PREC_FP32 = 1
+} afqmc_prec;
+
+/* Per-walker status bits. */
+#define AFQMC_WALKER_SINGULAR 1  /* overlap matrix A^H U had a zero pivot */
+#define AFQMC_WALKER_NONFINITE 2 /* a non-finite overlap or weight */
+#define AFQMC_WALKER_KILLED 4    /* phaseless cut: cos(dtheta) <= 0 set the weight to 0 */
+
+/* Flags of afqmc_kpt_propagate. */
+#define AFQMC_PROPAGATE_ORTHO 1  /* re-orthonormalise the walkers after the step */
+
+/* Entry-point ids for afqmc_kpt_workspace_bytes. */
+typedef enum {
+  AFQMC_ENTRY_PREPARE = 0,
+  AFQMC_ENTRY_GREENS = 1,
+  AFQMC_ENTRY_VBIAS = 2,
+  AFQMC_ENTRY_VHS = 3,
+  AFQMC_ENTRY_PROPAGATE = 4,
+  AFQMC_ENTRY_ORTHO = 5,
+  AFQMC_ENTRY_ENERGY = 6,
+  AFQMC_ENTRY_ENERGY_BACKWARD = 7
+} afqmc_entry;
+
+/* One system and its walker batch. */
+typedef struct afqmc_kpt_problem {
+  int32_t mesh[3];   /* Monkhorst-Pack mesh */
+  int32_t nk;        /* = mesh[0]*mesh[1]*mesh[2] */
+  int32_t m;         /* bands per k-point */
+  int32_t nocc;      /* occupied orbitals per spin per k-point, nocc <= m */
+  int32_t nchol;     /* Cholesky vectors per Q */
+  int32_t nwalk;     /* walkers in the batch */
+  int32_t prec;      /* afqmc_prec */
+  double dt;         /* imaginary time step, > 0 */
+  /* static data */
+  const void* L;     /* [nk][nk][m][m][nchol] complex128, input */
+  const void* A;     /* [nk][m][nocc] complex128 trial orbitals (block diagonal in k), input */
+  void* Lh;          /* [nk][nk][nocc][m][nchol] complex128, written by prepare:
+                        Lh[Q][k][a][r][g] = sum_p conj(A[k][p][a]) L[Q][k][p][r][g] */
+  void* h1h;         /* [nk][nocc][m] complex128, written by prepare: A[k]^H H1[k] */
+  void* bhalf;       /* [nk][m][m] complex128, written by prepare: exp(-dt/2 (H1 + V0)) */
+  void* L32;         /* [nk][nk][m][m][nchol] complex64 copy of L; prec FP32 only (else NULL) */
+  void* Lh32;        /* [nk][nk][nocc][m][nchol] complex64 copy of Lh; prec FP32 only */
+  /* walker state */
+  void* U;           /* [nwalk][nk*m][nk*nocc] complex128 walker orbitals, in/out */
+  void* Gh;          /* [nwalk][nk*nocc][nk*m] complex128 half-rotated Green's function */
+  void* logdet;      /* [nwalk] complex128, log det(A^H U) (imaginary part in (-pi, pi]) */
+  double* weight;    /* [nwalk] walker weights */
+  int32_t* status;   /* [nwalk] AFQMC_WALKER_* bits (sticky: OR-ed in, never cleared) */
+} afqmc_kpt_problem;
+
+/* Workspace (device bytes) the given entry point needs for these problems.
+ * bytes: host pointer.  The same workspace may be reused across calls that
+ * are ordered on one stream. */
+afqmc_status afqmc_kpt_workspace_bytes(const afqmc_kpt_problem* p, int nprob, int entry,
+                                       size_t* bytes);
+
+/* One-time preparation ("k-Point Representation": half-rotated Cholesky
+ * matrix; "Introduction to AFQMC": one-body propagator with H1' = H1 + v0).
+ *   H1: [nk][m][m] complex128 Hermitian one-body blocks (device).
+ * Writes Lh, h1h, bhalf (and L32, Lh32 when prec = FP32), with
+ *   V0[k] = -1/2 sum_{Q,g} L[Q][k][:,:,g] L[Q][k][:,:,g]^H and
+ *   bhalf[k] = exp(-dt/2 (H1[k] + V0[k])) (FP64 Taylor series with scaling
+ *   and squaring).  Does not touch the walker state. */
+afqmc_status afqmc_kpt_prepare(const afqmc_kpt_problem* p, int nprob, const void* H1,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/* Overlap and half-rotated Green's function (Green's-function equations of the
+ * standard representation; blocked by the trial's k structure):
+ *   O = A^H U (nk*nocc square), logdet = log det O, Gh = (U O^{-1})^T,
+ * all FP64, via Gauss-Jordan inversion with partial pivoting.
+ * Reads U; writes Gh, logdet and ORs status.  Requires nk*nocc <= 128. */
+afqmc_status afqmc_kpt_greens(const afqmc_kpt_problem* p, int nprob,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* Force bias (k-point force-bias equation, with the -sqrt(dt) of the standard
+ * force bias and phases c+ = i, c- = 1):
+ *   X[w][Q][g]    = 2 sum_k sum_{a,r} Lh[Q][k][a][r][g] Gh[w][(k a), ((k-Q) r)]
+ *   xbar[w][Q][g][0] = -sqrt(dt) (i/2) (X[w][Q][g] + X[w][-Q][g])
+ *   xbar[w][Q][g][1] = -sqrt(dt) (1/2) (X[w][Q][g] - X[w][-Q][g])
+ * xbar: [nwalk][nk][nchol][2] complex128 out; X: [nwalk][nk][nchol] complex128
+ * out.  Reads Gh and Lh (Lh32 for FP32). */
+afqmc_status afqmc_kpt_vbias(const afqmc_kpt_problem* p, int nprob, void* xbar, void* X,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* HS potential (k-point HS matrix, single contraction over the combined field):
+ *   xt = x - xbar, xi[w][Q][g] = 1/2 [ i (xt+_Q + xt+_-Q) + (xt-_Q - xt-_-Q) ],
+ *   vhs[w][(k p), ((k-Q) r)] = -sum_g L[Q][k][p][r][g] xi[w][Q][g]
+ * so that the two-body propagator is exp(-sqrt(dt) vhs).
+ *   x:    [nwalk][nk][nchol][2] float64 auxiliary fields (the +/- potentials)
+ *   xbar: [nwalk][nk][nchol][2] complex128 from afqmc_kpt_vbias
+ *   vhs:  [nwalk][nk*m][nk*m], complex128 (FP64) or complex64 (FP32), out. */
+afqmc_status afqmc_kpt_vhs(const afqmc_kpt_problem* p, int nprob, const double* x,
+                           const void* xbar, void* vhs, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/* Walker propagation and hybrid phaseless weights ("Introduction to AFQMC":
+ * symmetric propagator, importance function and weight update):
+ *   U <- bhalf . T6(-sqrt(dt) vhs) . bhalf . U,  T6(V) U = sum_{j<=6} V^j U / j!
+ * computed term by term (T_j = V T_{j-1} / j); then the new Gh and logdet, and
+ *   log I = 2 (logdet' - logdet) + sum_{Q,g,+/-} (x xbar - xbar^2 / 2),
+ *   dtheta = arg exp(2 (logdet' - logdet)),
+ *   weight <- |I| max(0, cos dtheta) weight.
+ * With AFQMC_PROPAGATE_ORTHO the walkers are re-orthonormalised afterwards
+ * (see afqmc_kpt_orthonormalize).  vhs, x, xbar as in afqmc_kpt_vhs. */
+afqmc_status afqmc_kpt_propagate(const afqmc_kpt_problem* p, int nprob, const void* vhs,
+                                 const double* x, const void* xbar, int flags,
+                                 void* ws, size_t ws_bytes, void* stream);
+
+/* Walker re-orthonormalisation (once per block, "Scaling and Performance"):
+ * U <- Q of the thin QR factorisation U = Q R with diag(R) real positive
+ * (FP64 Cholesky-QR applied twice), then Gh and logdet are recomputed.
+ * Gh and the local energy are unchanged by it.  Requires nk*nocc <= 128. */
+afqmc_status afqmc_kpt_orthonormalize(const afqmc_kpt_problem* p, int nprob,
+                                      void* ws, size_t ws_bytes, void* stream);
+
+/* Local energy (k-point local-energy equation, evaluated with the paper's
+ * energy algorithm, steps 1-3):
+ *   E[w][0] = E1B = 2 sum_k sum_{a,r} h1h[k][a][r] Gh[w][(k a), (k r)]
+ *   E[w][1] = EC  = 1/2 sum_{Q,g} X[w][Q][g] X[w][-Q][g]
+ *   E[w][2] = EX  = -sum_{Q,k,k'} sum_{a,b,g} T1[b,a,g] T2[a,b,g],
+ *     T1[b,a,g] = sum_r Lh[Q][k][a][r][g]      Gh[w][((k'-Q) b), ((k-Q) r)]
+ *     T2[a,b,g] = sum_s Lh[-Q][k'-Q][b][s][g]  Gh[w][(k a), (k' s)]
+ * E: [nwalk][3] complex128 out, per supercell.  The T intermediates never
+ * reach memory; all sums are FP64.  Requires nocc <= 16. */
+afqmc_status afqmc_kpt_energy(const afqmc_kpt_problem* p, int nprob, void* E,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of the local energy with respect to Gh (generalized Fock matrix):
+ *   gGh[w][(k1 al), (k2 rho)] = gE[w] * dE_L[w] / dGh[w][(k1 al), (k2 rho)],
+ *   E_L = E1B + EC + EX (holomorphic in Gh, so this is the plain complex
+ *   derivative), which equals
+ *   2 [ h1h[k1][al][rho] d(k1,k2) + sum_g Lh[Q0][k1][al][rho][g] X[w][-Q0][g]
+ *       - sum_{Q,b,g} T1_{(Q,k1,k2)}[b,al,g] Lh[-Q][k2-Q][b][rho][g] ],  Q0 = k1 - k2.
+ * The exchange intermediates T1 are recomputed, not stored.
+ *   gE:  [nwalk] complex128 cotangent, or NULL for 1.
+ *   gGh: [nwalk][nk*nocc][nk*m] complex128 out. */
+afqmc_status afqmc_kpt_energy_backward(const afqmc_kpt_problem* p, int nprob, const void* gE,
+                                       void* gGh, void* ws, size_t ws_bytes, void* stream);
+
+/* Static string for a status code (host). */
+const char* afqmc_kpt_strerror(int status);
+
+/* Library version string (host). */
+const char* afqmc_kpt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFQMC_KPT_H */

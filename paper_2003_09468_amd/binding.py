@@ -1,0 +1,325 @@
+"""ctypes binding of libafqmc_kpt.so (argument marshalling only).
+
+Each method of KptProblem fills the C problem descriptor from the torch tensors
+it owns, calls the entry point of the same name on the current torch stream,
+and raises AfqmcError on a negative status.  All arithmetic runs in the gfx950
+kernels of the library.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBNAME = "libafqmc_kpt.so"
+
+PREC_FP64 = 0
+PREC_FP32 = 1
+
+WALKER_SINGULAR = 1
+WALKER_NONFINITE = 2
+WALKER_KILLED = 4
+
+PROPAGATE_ORTHO = 1
+
+ENTRIES = {
+    "prepare": 0,
+    "greens": 1,
+    "vbias": 2,
+    "vhs": 3,
+    "propagate": 4,
+    "ortho": 5,
+    "energy": 6,
+    "energy_backward": 7,
+}
+
+EXPORTS = [
+    "afqmc_kpt_workspace_bytes",
+    "afqmc_kpt_prepare",
+    "afqmc_kpt_greens",
+    "afqmc_kpt_vbias",
+    "afqmc_kpt_vhs",
+    "afqmc_kpt_propagate",
+    "afqmc_kpt_orthonormalize",
+    "afqmc_kpt_energy",
+    "afqmc_kpt_energy_backward",
+    "afqmc_kpt_strerror",
+    "afqmc_kpt_version",
+]
+
+
+class AfqmcError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn} failed with status {status}: {msg}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    """Mirror of afqmc_kpt_problem (include/afqmc_kpt.h)."""
+
+    _fields_ = [
+        ("mesh", ctypes.c_int32 * 3),
+        ("nk", ctypes.c_int32),
+        ("m", ctypes.c_int32),
+        ("nocc", ctypes.c_int32),
+        ("nchol", ctypes.c_int32),
+        ("nwalk", ctypes.c_int32),
+        ("prec", ctypes.c_int32),
+        ("dt", ctypes.c_double),
+        ("L", ctypes.c_void_p),
+        ("A", ctypes.c_void_p),
+        ("Lh", ctypes.c_void_p),
+        ("h1h", ctypes.c_void_p),
+        ("bhalf", ctypes.c_void_p),
+        ("L32", ctypes.c_void_p),
+        ("Lh32", ctypes.c_void_p),
+        ("U", ctypes.c_void_p),
+        ("Gh", ctypes.c_void_p),
+        ("logdet", ctypes.c_void_p),
+        ("weight", ctypes.c_void_p),
+        ("status", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return os.path.join(HERE, _LIBNAME)
+
+
+def lib():
+    """Load the library once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build it with `python -m paper_2003_09468_amd.build` "
+            "(there is no CPU fallback)")
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER(Problem)
+    vp, sz, i = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+    sig = {
+        "afqmc_kpt_workspace_bytes": [P, i, i, ctypes.POINTER(sz)],
+        "afqmc_kpt_prepare": [P, i, vp, vp, sz, vp],
+        "afqmc_kpt_greens": [P, i, vp, sz, vp],
+        "afqmc_kpt_vbias": [P, i, vp, vp, vp, sz, vp],
+        "afqmc_kpt_vhs": [P, i, vp, vp, vp, vp, sz, vp],
+        "afqmc_kpt_propagate": [P, i, vp, vp, vp, i, vp, sz, vp],
+        "afqmc_kpt_orthonormalize": [P, i, vp, sz, vp],
+        "afqmc_kpt_energy": [P, i, vp, vp, sz, vp],
+        "afqmc_kpt_energy_backward": [P, i, vp, vp, vp, sz, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.afqmc_kpt_strerror.argtypes = [ctypes.c_int]
+    L.afqmc_kpt_strerror.restype = ctypes.c_char_p
+    L.afqmc_kpt_version.argtypes = []
+    L.afqmc_kpt_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def check(fn: str, status: int) -> None:
+    if status != 0:
+        msg = lib().afqmc_kpt_strerror(status).decode()
+        raise AfqmcError(fn, status, msg)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+class KptProblem:
+    """One k-point system and its walker batch, with device buffers owned by torch.
+
+    L: [nk][nk][m][m][nchol] complex128, A: [nk][m][nocc] complex128 (device tensors).
+    """
+
+    def __init__(self, mesh, m, nocc, nchol, nwalk, dt, L, A, prec=PREC_FP64, device="cuda"):
+        self.mesh = tuple(int(v) for v in mesh)
+        self.nk = self.mesh[0] * self.mesh[1] * self.mesh[2]
+        self.m, self.nocc, self.nchol, self.nwalk = int(m), int(nocc), int(nchol), int(nwalk)
+        self.dt = float(dt)
+        self.prec = int(prec)
+        self.device = torch.device(device)
+        nk, c128 = self.nk, torch.complex128
+        kw = dict(device=self.device)
+        self.L = L.to(**kw, dtype=c128).contiguous()
+        self.A = A.to(**kw, dtype=c128).contiguous()
+        self.Lh = torch.empty((nk, nk, nocc, m, nchol), dtype=c128, **kw)
+        self.h1h = torch.empty((nk, nocc, m), dtype=c128, **kw)
+        self.bhalf = torch.empty((nk, m, m), dtype=c128, **kw)
+        if self.prec == PREC_FP32:
+            self.L32 = torch.empty(self.L.shape, dtype=torch.complex64, **kw)
+            self.Lh32 = torch.empty(self.Lh.shape, dtype=torch.complex64, **kw)
+        else:
+            self.L32 = self.Lh32 = None
+        N, n = nk * m, nk * nocc
+        self.U = torch.zeros((nwalk, N, n), dtype=c128, **kw)
+        self.Gh = torch.zeros((nwalk, n, N), dtype=c128, **kw)
+        self.logdet = torch.zeros(nwalk, dtype=c128, **kw)
+        self.weight = torch.ones(nwalk, dtype=torch.float64, **kw)
+        self.status = torch.zeros(nwalk, dtype=torch.int32, **kw)
+        self._ws = None
+        self.struct = self._make_struct()
+
+    # -- descriptor and workspace ------------------------------------------------
+    def _make_struct(self, Gh=None) -> Problem:
+        p = Problem()
+        p.mesh[0], p.mesh[1], p.mesh[2] = self.mesh
+        p.nk, p.m, p.nocc, p.nchol, p.nwalk = self.nk, self.m, self.nocc, self.nchol, self.nwalk
+        p.prec, p.dt = self.prec, self.dt
+        p.L, p.A, p.Lh, p.h1h, p.bhalf = (_ptr(self.L), _ptr(self.A), _ptr(self.Lh),
+                                          _ptr(self.h1h), _ptr(self.bhalf))
+        p.L32, p.Lh32 = _ptr(self.L32), _ptr(self.Lh32)
+        p.U = _ptr(self.U)
+        p.Gh = _ptr(self.Gh if Gh is None else Gh)
+        p.logdet, p.weight, p.status = _ptr(self.logdet), _ptr(self.weight), _ptr(self.status)
+        return p
+
+    def workspace_bytes(self, entry: str) -> int:
+        out = ctypes.c_size_t(0)
+        check("afqmc_kpt_workspace_bytes",
+              lib().afqmc_kpt_workspace_bytes(ctypes.byref(self.struct), 1, ENTRIES[entry],
+                                              ctypes.byref(out)))
+        return int(out.value)
+
+    def workspace(self):
+        if self._ws is None:
+            need = max(self.workspace_bytes(e) for e in ENTRIES)
+            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def _ws_args(self):
+        ws = self.workspace()
+        return ws.data_ptr(), ws.numel()
+
+    # -- entry points ----------------------------------------------------------------
+    def set_walkers(self, U, weight=None):
+        self.U.copy_(U.to(self.U.dtype))
+        if weight is not None:
+            self.weight.copy_(weight)
+        self.status.zero_()
+
+    def prepare(self, H1):
+        H1 = H1.to(device=self.device, dtype=torch.complex128).contiguous()
+        ws, nb = self._ws_args()
+        check("afqmc_kpt_prepare",
+              lib().afqmc_kpt_prepare(ctypes.byref(self.struct), 1, H1.data_ptr(), ws, nb,
+                                      _stream()))
+
+    def greens(self):
+        ws, nb = self._ws_args()
+        check("afqmc_kpt_greens",
+              lib().afqmc_kpt_greens(ctypes.byref(self.struct), 1, ws, nb, _stream()))
+
+    def vbias(self, xbar=None, X=None):
+        W, nk, C = self.nwalk, self.nk, self.nchol
+        if xbar is None:
+            xbar = torch.empty((W, nk, C, 2), dtype=torch.complex128, device=self.device)
+        if X is None:
+            X = torch.empty((W, nk, C), dtype=torch.complex128, device=self.device)
+        ws, nb = self._ws_args()
+        check("afqmc_kpt_vbias",
+              lib().afqmc_kpt_vbias(ctypes.byref(self.struct), 1, xbar.data_ptr(),
+                                    X.data_ptr(), ws, nb, _stream()))
+        return xbar, X
+
+    def vhs(self, x, xbar, out=None):
+        N = self.nk * self.m
+        dt = torch.complex64 if self.prec == PREC_FP32 else torch.complex128
+        if out is None:
+            out = torch.empty((self.nwalk, N, N), dtype=dt, device=self.device)
+        x = x.to(device=self.device, dtype=torch.float64).contiguous()
+        ws, nb = self._ws_args()
+        check("afqmc_kpt_vhs",
+              lib().afqmc_kpt_vhs(ctypes.byref(self.struct), 1, x.data_ptr(), xbar.data_ptr(),
+                                  out.data_ptr(), ws, nb, _stream()))
+        return out
+
+    def propagate(self, vhs, x, xbar, ortho=False):
+        x = x.to(device=self.device, dtype=torch.float64).contiguous()
+        ws, nb = self._ws_args()
+        check("afqmc_kpt_propagate",
+              lib().afqmc_kpt_propagate(ctypes.byref(self.struct), 1, vhs.data_ptr(),
+                                        x.data_ptr(), xbar.data_ptr(),
+                                        PROPAGATE_ORTHO if ortho else 0, ws, nb, _stream()))
+
+    def orthonormalize(self):
+        ws, nb = self._ws_args()
+        check("afqmc_kpt_orthonormalize",
+              lib().afqmc_kpt_orthonormalize(ctypes.byref(self.struct), 1, ws, nb, _stream()))
+
+    def energy(self, out=None, Gh=None):
+        if out is None:
+            out = torch.empty((self.nwalk, 3), dtype=torch.complex128, device=self.device)
+        st = self.struct if Gh is None else self._make_struct(Gh)
+        ws, nb = self._ws_args()
+        check("afqmc_kpt_energy",
+              lib().afqmc_kpt_energy(ctypes.byref(st), 1, out.data_ptr(), ws, nb, _stream()))
+        return out
+
+    def energy_backward(self, gE=None, out=None, Gh=None):
+        if gE is not None:
+            gE = gE.resolve_conj().to(device=self.device, dtype=torch.complex128).contiguous()
+        if out is None:
+            out = torch.empty_like(self.Gh)
+        st = self.struct if Gh is None else self._make_struct(Gh)
+        ws, nb = self._ws_args()
+        check("afqmc_kpt_energy_backward",
+              lib().afqmc_kpt_energy_backward(ctypes.byref(st), 1, _ptr(gE), out.data_ptr(),
+                                              ws, nb, _stream()))
+        return out
+
+    def step(self, x, ortho=False, bufs=None):
+        """force bias -> HS potential -> propagate (new Gh, logdet, weights)."""
+        if bufs is None:
+            bufs = {}
+        xbar, _ = self.vbias(bufs.get("xbar"), bufs.get("X"))
+        v = self.vhs(x, xbar, bufs.get("vhs"))
+        self.propagate(v, x, xbar, ortho=ortho)
+        return xbar, v
+
+
+class _LocalEnergy(torch.autograd.Function):
+    """E_L[w] = E1B + EC + EX as a holomorphic function of Gh.
+
+    Backward follows torch's convention for complex inputs:
+    grad_Gh = grad_E * conj(dE/dGh) = conj(conj(grad_E) * dE/dGh); the library
+    returns gE * dE/dGh for a given per-walker cotangent gE.
+    """
+
+    @staticmethod
+    def forward(ctx, Gh, problem):
+        Gh = Gh.contiguous()
+        E = problem.energy(Gh=Gh)
+        ctx.problem = problem
+        ctx.save_for_backward(Gh)
+        return E.sum(dim=1)
+
+    @staticmethod
+    def backward(ctx, grad):
+        (Gh,) = ctx.saved_tensors
+        # resolve_conj: a lazy conjugate view would hand the library unconjugated memory
+        gE = grad.conj().resolve_conj().to(torch.complex128).contiguous()
+        g = ctx.problem.energy_backward(gE=gE, Gh=Gh)
+        return g.conj(), None
+
+
+def local_energy(problem: KptProblem, Gh) -> torch.Tensor:
+    """Differentiable local energy per walker (recomputes the exchange intermediates in backward)."""
+    return _LocalEnergy.apply(Gh, problem)

@@ -1,0 +1,176 @@
+// Batched complex GEMM core on gfx950 MFMA (16x16x4, FP64 or FP32 accumulate).
+//
+// C[b](BM x BN tile) = sum_k A[b](row, k) B[b](k, col): operands are reached through an
+// operation functor Op that maps (batch, row, k) / (batch, k, col) to memory and owns the
+// epilogue, so that each hot contraction of the k-point step (force bias, HS potential,
+// Taylor terms, one-body half steps, Green's function solve, Gram matrices, half rotation)
+// is one instantiation with its own index map and fused epilogue.
+//
+// Tiles are staged through LDS as separate real and imaginary planes; the next K slice is
+// prefetched into registers while the MFMAs of the current one run.  Complex products take
+// four real MFMAs (Dre += Are Bre - Aim Bim, Dim += Are Bim + Aim Bre).  The 1-D grid is
+// remapped so that consecutive logical tiles (same batch) land on the same XCD, which keeps
+// the shared operand of a batch in one L2.
+#pragma once
+
+#include "kcommon.h"
+
+namespace afqmc {
+
+// Op requirements (device, by value in kernel arguments):
+//   typedef T;                        storage/compute type of the MFMA (double or float)
+//   static constexpr bool A_KCONTIG;  A(row, k) contiguous along k (else along row)
+//   static constexpr bool B_NCONTIG;  B(k, col) contiguous along col (else along k)
+//   int M, N, K, nbatch;
+//   void load_a(int b, int row, int k, T& re, T& im) const;   // 0 <= row < M, 0 <= k < K
+//   void load_b(int b, int k, int col, T& re, T& im) const;   // 0 <= k < K, 0 <= col < N
+//   void store(int b, int row, int col, T re, T im) const;    // 0 <= row < M, 0 <= col < N
+
+template <class Op, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void cgemm_kernel(Op op, int tiles_m, int tiles_n) {
+  typedef typename Op::T T;
+  typedef typename mfma16<T>::acc_t acc_t;
+  constexpr int NT = WM * WN * 64;
+  constexpr int TM = BM / (WM * 16);
+  constexpr int TN = BN / (WN * 16);
+  constexpr int EA = (BM * BK) / NT;
+  constexpr int EB = (BK * BN) / NT;
+  constexpr int PA = (sizeof(T) == 8) ? 1 : 2;
+  constexpr int PB = (sizeof(T) == 8) ? 1 : 2;
+  static_assert(TM * WM * 16 == BM && TN * WN * 16 == BN, "tile must split into 16x16 blocks");
+  static_assert(EA * NT == BM * BK && EB * NT == BK * BN, "tile must split over threads");
+  static_assert(BK % 4 == 0, "BK multiple of the MFMA K");
+
+  __shared__ T sA[2][BK][BM + PA];
+  __shared__ T sB[2][BK][BN + PB];
+
+  // XCD-aware remap of the flat block index: workgroups are dealt round-robin over the
+  // 8 XCDs, so block b runs on XCD b % 8; give each XCD a contiguous range of tiles.
+  const int ntiles = tiles_m * tiles_n;
+  const int64_t total = (int64_t)ntiles * op.nbatch;
+  int64_t bid = blockIdx.x;
+  if ((total & 7) == 0) bid = (bid & 7) * (total >> 3) + (bid >> 3);
+  const int b = (int)(bid / ntiles);
+  const int rem = (int)(bid % ntiles);
+  const int tm = rem / tiles_n;
+  const int tn = rem % tiles_n;
+  const int row0 = tm * BM, col0 = tn * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int M = op.M, N = op.N, K = op.K;
+
+  acc_t accr[TM][TN], acci[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      accr[i][j] = mfma16<T>::zero();
+      acci[i][j] = mfma16<T>::zero();
+    }
+
+  T pa_r[EA], pa_i[EA], pb_r[EB], pb_i[EB];
+
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * NT;
+      int r, kk;
+      if (Op::A_KCONTIG) { r = idx / BK; kk = idx % BK; }
+      else { kk = idx / BM; r = idx % BM; }
+      const int row = row0 + r, k = k0 + kk;
+      T re = 0, im = 0;
+      if (row < M && k < K) op.load_a(b, row, k, re, im);
+      pa_r[e] = re; pa_i[e] = im;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * NT;
+      int c, kk;
+      if (Op::B_NCONTIG) { kk = idx / BN; c = idx % BN; }
+      else { c = idx / BK; kk = idx % BK; }
+      const int col = col0 + c, k = k0 + kk;
+      T re = 0, im = 0;
+      if (col < N && k < K) op.load_b(b, k, col, re, im);
+      pb_r[e] = re; pb_i[e] = im;
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * NT;
+      int r, kk;
+      if (Op::A_KCONTIG) { r = idx / BK; kk = idx % BK; }
+      else { kk = idx / BM; r = idx % BM; }
+      sA[0][kk][r] = pa_r[e];
+      sA[1][kk][r] = pa_i[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * NT;
+      int c, kk;
+      if (Op::B_NCONTIG) { kk = idx / BN; c = idx % BN; }
+      else { c = idx / BK; kk = idx % BK; }
+      sB[0][kk][c] = pb_r[e];
+      sB[1][kk][c] = pb_i[e];
+    }
+  };
+
+  const int rbase = wm * TM * 16 + (lane & 15);
+  const int cbase = wn * TN * 16 + (lane & 15);
+  const int klane = lane >> 4;
+
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    stash();
+    __syncthreads();
+    if (k0 + BK < K) fetch(k0 + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      T ar[TM], ai[TM], br[TN], bi[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        ar[i] = sA[0][ks + klane][rbase + i * 16];
+        ai[i] = sA[1][ks + klane][rbase + i * 16];
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        br[j] = sB[0][ks + klane][cbase + j * 16];
+        bi[j] = sB[1][ks + klane][cbase + j * 16];
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) cmfma<T>(ar[i], ai[i], br[j], bi[j], accr[i][j], acci[i][j]);
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = row0 + wm * TM * 16 + i * 16 + mfma16<T>::drow(lane, v);
+        const int col = col0 + wn * TN * 16 + j * 16 + (lane & 15);
+        if (row < M && col < N) op.store(b, row, col, accr[i][j][v], acci[i][j][v]);
+      }
+}
+
+// Host launcher: grid = nbatch * tiles.
+template <int BM, int BN, int BK, int WM, int WN, class Op>
+hipError_t launch_cgemm(const Op& op, hipStream_t s) {
+  if (op.M <= 0 || op.N <= 0 || op.K <= 0 || op.nbatch <= 0) return hipSuccess;
+  const int tm = (op.M + BM - 1) / BM;
+  const int tn = (op.N + BN - 1) / BN;
+  const int64_t total = (int64_t)tm * tn * op.nbatch;
+  if (total > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((cgemm_kernel<Op, BM, BN, BK, WM, WN>), dim3((unsigned)total),
+                     dim3(WM * WN * 64), 0, s, op, tm, tn);
+  return hipGetLastError();
+}
+
+}  // namespace afqmc

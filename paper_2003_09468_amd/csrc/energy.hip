@@ -1,0 +1,550 @@
+// Local energy and its adjoint (k-point local-energy equation; energy-evaluation
+// algorithm of the GPU-implementation section, steps 1-3).
+//
+// Exchange.  For t = (Q, k, k') the algorithm forms
+//   T1_t[w][b][a][g] = sum_r Lh[Q][k][a][r][g]      Gh[w][((k'-Q) b), ((k-Q) r)]
+//   T2_t[w][a][b][g] = sum_s Lh[-Q][k'-Q][b][s][g]  Gh[w][(k a), (k' s)]
+// and accumulates -sum T1_t[b,a,g] T2_t[a,b,g].  With pi(t) = (-Q, k'-Q, k-Q), the time-
+// reversal partner, T2_t[a][b] = T1_{pi(t)}[a][b] and the summand of pi(t) equals that of t,
+// so one workgroup per unordered pair {t, pi(t)} computes the two T1 tiles on MFMA (K = m),
+// pairs element (b, a) of one with (a, b) of the other through a wave-private LDS tile, and
+// accumulates in FP64.  T1 never reaches memory.  Work per pair: one GEMM per triple
+// instead of two.
+//
+// Layout of one 16 x 16 MFMA tile: rows (g, a) with 16/nocc values of g, columns (w, b)
+// with 16/nocc walkers; each of the 4 waves of a workgroup owns its walkers (their Gh
+// blocks stay in registers for the whole g loop) and all waves share LDS-staged slabs of
+// the half-rotated Cholesky vectors, double buffered over g.
+#include <math.h>
+
+#include "cgemm.h"
+#include "internal.h"
+
+namespace afqmc {
+
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t total) {
+  return ((total & 7) == 0) ? (bid & 7) * (total >> 3) + (bid >> 3) : bid;
+}
+
+template <typename T, int KSMAX>
+__global__ __launch_bounds__(256) void exchange_kernel(int nk, int m, int nocc, int C, int W,
+                                                       KMesh mesh, int nchunk_w,
+                                                       const cpx<T>* __restrict__ Lh,
+                                                       const cpx<double>* __restrict__ Gh,
+                                                       cpx<double>* __restrict__ part) {
+  typedef typename mfma16<T>::acc_t acc_t;
+  constexpr int RP = 4 * KSMAX;
+  constexpr int NLD = (2 * 16 * RP) / 256;  // slab elements per thread (both slabs)
+
+  __shared__ T LA[2][2][2][RP][16];  // [buf][slab][re/im][r][(g, a)]
+  __shared__ T XB[4][2][16][17];     // per-wave exchange tile
+  __shared__ double red[2][256];
+
+  const int64_t total = (int64_t)nk * nk * nk * nchunk_w;
+  const int64_t bid = xcd_remap(blockIdx.x, total);
+  const int chunk = (int)(bid % nchunk_w);
+  const int t = (int)(bid / nchunk_w);
+  const int kp = t % nk, k = (t / nk) % nk, Q = t / (nk * nk);
+  const int mQ = mesh.neg(Q), kpq = mesh.kmq(kp, Q), kq = mesh.kmq(k, Q);
+  const int tp = (mQ * nk + kpq) * nk + kq;  // partner triple (-Q, k'-Q, k-Q)
+  if (t > tp) return;
+  const double mult = (t == tp) ? 1.0 : 2.0;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int Gs = 16 / nocc, Ws = 16 / nocc;
+  const int KS = (m + 3) >> 2;
+  const int col = lane & 15;
+  const int ws_l = col / nocc, b_l = col % nocc;
+  const int wl = chunk * 4 * Ws + wave * Ws + ws_l;
+  const bool colok = (ws_l < Ws) && (wl < W);
+  const int64_t Nn = (int64_t)nk * m, nn = (int64_t)nk * nocc;
+
+  // Gh fragments of this lane's column, for both GEMMs (B operand: B[r][(w, b)])
+  T b1r[KSMAX], b1i[KSMAX], b2r[KSMAX], b2i[KSMAX];
+#pragma unroll
+  for (int s = 0; s < KSMAX; ++s) {
+    const int r = 4 * s + (lane >> 4);
+    T x1r = 0, x1i = 0, x2r = 0, x2i = 0;
+    if (s < KS && r < m && colok) {
+      const cpx<double> g1 = Gh[((int64_t)wl * nn + (int64_t)kpq * nocc + b_l) * Nn + (int64_t)kq * m + r];
+      const cpx<double> g2 = Gh[((int64_t)wl * nn + (int64_t)k * nocc + b_l) * Nn + (int64_t)kp * m + r];
+      x1r = (T)g1.re; x1i = (T)g1.im; x2r = (T)g2.re; x2i = (T)g2.im;
+    }
+    b1r[s] = x1r; b1i[s] = x1i; b2r[s] = x2r; b2i[s] = x2i;
+  }
+
+  const cpx<T>* slab0 = Lh + ((int64_t)Q * nk + k) * nocc * m * C;
+  const cpx<T>* slab1 = Lh + ((int64_t)mQ * nk + kpq) * nocc * m * C;
+  const int nch = (C + Gs - 1) / Gs;
+
+  // slab element e of this thread: idx = (sl, r, q), q = a * Gs + g_s (g fastest in memory)
+  T pr[NLD], pi[NLD];
+  auto fetch = [&](int c) {
+    const int g0 = c * Gs;
+#pragma unroll
+    for (int e = 0; e < NLD; ++e) {
+      const int idx = tid + 256 * e;
+      const int sl = idx / (16 * RP), rem = idx % (16 * RP);
+      const int r = rem / 16, q = rem % 16;
+      const int a = q / Gs, g_s = q % Gs;
+      T vr = 0, vi = 0;
+      if (a < nocc && r < m && g0 + g_s < C) {
+        const cpx<T>* sb = sl ? slab1 : slab0;
+        const cpx<T> v = sb[((int64_t)a * m + r) * C + g0 + g_s];
+        vr = v.re; vi = v.im;
+      }
+      pr[e] = vr; pi[e] = vi;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < NLD; ++e) {
+      const int idx = tid + 256 * e;
+      const int sl = idx / (16 * RP), rem = idx % (16 * RP);
+      const int r = rem / 16, q = rem % 16;
+      const int a = q / Gs, g_s = q % Gs;
+      if (a < nocc) {
+        LA[buf][sl][0][r][g_s * nocc + a] = pr[e];
+        LA[buf][sl][1][r][g_s * nocc + a] = pi[e];
+      }
+    }
+  };
+  // rows (g, a) beyond Gs * nocc stay zero
+  for (int i = tid; i < 2 * 2 * 2 * RP * 16; i += 256) (&LA[0][0][0][0][0])[i] = (T)0;
+  __syncthreads();
+
+  double sr = 0.0, si = 0.0;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) fetch(c + 1);
+    acc_t a1r = mfma16<T>::zero(), a1i = mfma16<T>::zero();
+    acc_t a2r = mfma16<T>::zero(), a2i = mfma16<T>::zero();
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s) {
+      if (s < KS) {
+        const int r = 4 * s + (lane >> 4);
+        const T x1r = LA[buf][0][0][r][col], x1i = LA[buf][0][1][r][col];
+        const T x2r = LA[buf][1][0][r][col], x2i = LA[buf][1][1][r][col];
+        cmfma<T>(x1r, x1i, b1r[s], b1i[s], a1r, a1i);
+        cmfma<T>(x2r, x2i, b2r[s], b2i[s], a2r, a2i);
+      }
+    }
+    // T1 of the partner triple to the wave-private tile
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = mfma16<T>::drow(lane, v);
+      XB[wave][0][row][col] = a2r[v];
+      XB[wave][1][row][col] = a2i[v];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int g0 = c * Gs;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = mfma16<T>::drow(lane, v);
+      const int g_s = row / nocc, a = row % nocc;
+      if (colok && g_s < Gs && g0 + g_s < C) {
+        const int rp = g_s * nocc + b_l, cp = ws_l * nocc + a;
+        const double pr2 = (double)XB[wave][0][rp][cp], pi2 = (double)XB[wave][1][rp][cp];
+        const double p1r = (double)a1r[v], p1i = (double)a1i[v];
+        sr += p1r * pr2 - p1i * pi2;
+        si += p1r * pi2 + p1i * pr2;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (c + 1 < nch) stash(buf ^ 1);
+    __syncthreads();
+  }
+
+  // per-walker reduction: lanes of a wave with the same column walker
+  red[0][tid] = sr;
+  red[1][tid] = si;
+  __syncthreads();
+  if (tid < 4 * Ws) {
+    const int wv = tid / Ws, wsi = tid % Ws;
+    const int w = chunk * 4 * Ws + wv * Ws + wsi;
+    if (w < W) {
+      double ar = 0.0, ai = 0.0;
+      for (int grp = 0; grp < 4; ++grp)
+        for (int b = 0; b < nocc; ++b) {
+          const int l = wv * 64 + grp * 16 + wsi * nocc + b;
+          ar += red[0][l];
+          ai += red[1][l];
+        }
+      part[(int64_t)t * W + w] = cpx<double>{-mult * ar, -mult * ai};
+    }
+  }
+}
+
+// E1B[w] = 2 sum_k sum_{a,r} h1h[k][a][r] Gh[w][(k a),(k r)];  EC[w] = 1/2 sum X_Q X_-Q;
+// EX[w] = sum over canonical triples of the exchange partials.  One workgroup per walker.
+__global__ __launch_bounds__(256) void energy_final_kernel(int nk, int m, int nocc, int C, int W,
+                                                           KMesh mesh,
+                                                           const cpx<double>* __restrict__ h1h,
+                                                           const cpx<double>* __restrict__ Gh,
+                                                           const cpx<double>* __restrict__ X,
+                                                           const cpx<double>* __restrict__ part,
+                                                           cpx<double>* __restrict__ E) {
+  const int w = blockIdx.x, tid = threadIdx.x;
+  __shared__ double red[6][256];
+  const int64_t Nn = (int64_t)nk * m, nn = (int64_t)nk * nocc;
+  double e1r = 0, e1i = 0, ecr = 0, eci = 0, exr = 0, exi = 0;
+  for (int64_t i = tid; i < (int64_t)nk * nocc * m; i += 256) {
+    const int kk = (int)(i / (nocc * m)), ar = (int)(i % (nocc * m));
+    const int a = ar / m, r = ar % m;
+    const cpx<double> h = h1h[i];
+    const cpx<double> g = Gh[((int64_t)w * nn + (int64_t)kk * nocc + a) * Nn + (int64_t)kk * m + r];
+    e1r += h.re * g.re - h.im * g.im;
+    e1i += h.re * g.im + h.im * g.re;
+  }
+  for (int64_t i = tid; i < (int64_t)nk * C; i += 256) {
+    const int Q = (int)(i / C), g = (int)(i % C);
+    const cpx<double> x1 = X[((int64_t)w * nk + Q) * C + g];
+    const cpx<double> x2 = X[((int64_t)w * nk + mesh.neg(Q)) * C + g];
+    ecr += x1.re * x2.re - x1.im * x2.im;
+    eci += x1.re * x2.im + x1.im * x2.re;
+  }
+  const int64_t nt = (int64_t)nk * nk * nk;
+  for (int64_t t = tid; t < nt; t += 256) {
+    const int kp = (int)(t % nk), k = (int)((t / nk) % nk), Q = (int)(t / ((int64_t)nk * nk));
+    const int64_t tp = ((int64_t)mesh.neg(Q) * nk + mesh.kmq(kp, Q)) * nk + mesh.kmq(k, Q);
+    if (t > tp) continue;
+    const cpx<double> v = part[t * W + w];
+    exr += v.re;
+    exi += v.im;
+  }
+  red[0][tid] = e1r; red[1][tid] = e1i; red[2][tid] = ecr;
+  red[3][tid] = eci; red[4][tid] = exr; red[5][tid] = exi;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (tid < o)
+      for (int j = 0; j < 6; ++j) red[j][tid] += red[j][tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    E[3 * (int64_t)w + 0] = cpx<double>{2.0 * red[0][0], 2.0 * red[1][0]};
+    E[3 * (int64_t)w + 1] = cpx<double>{0.5 * red[2][0], 0.5 * red[3][0]};
+    E[3 * (int64_t)w + 2] = cpx<double>{red[4][0], red[5][0]};
+  }
+}
+
+static size_t carve_energy(Carve& c, const afqmc_kpt_problem& p, void** X, void** parts,
+                           void** xpart) {
+  Dims d = dims_of(p);
+  *X = c.take(16 * (size_t)d.W * d.nk * d.C);
+  VbiasWs v;
+  carve_vbias(c, d, v);
+  *parts = v.parts;
+  *xpart = c.take(16 * (size_t)d.nk * d.nk * d.nk * d.W);
+  return c.off;
+}
+
+size_t energy_ws_bytes(const afqmc_kpt_problem& p) {
+  Carve c(nullptr);
+  void *a, *b, *x;
+  return carve_energy(c, p, &a, &b, &x);
+}
+
+template <typename T>
+static hipError_t launch_exchange(const afqmc_kpt_problem& p, void* xpart, hipStream_t s) {
+  const int Ws = 16 / p.nocc;
+  const int nchunk = (p.nwalk + 4 * Ws - 1) / (4 * Ws);
+  const int64_t grid = (int64_t)p.nk * p.nk * p.nk * nchunk;
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  const int KS = (p.m + 3) / 4;
+  const cpx<T>* Lh = (const cpx<T>*)(sizeof(T) == 8 ? p.Lh : p.Lh32);
+  const cpx<double>* Gh = (const cpx<double>*)p.Gh;
+  cpx<double>* part = (cpx<double>*)xpart;
+  KMesh mesh = make_mesh(p);
+  if (KS <= 4)
+    hipLaunchKernelGGL((exchange_kernel<T, 4>), dim3((unsigned)grid), dim3(256), 0, s, p.nk, p.m,
+                       p.nocc, p.nchol, p.nwalk, mesh, nchunk, Lh, Gh, part);
+  else if (KS <= 8)
+    hipLaunchKernelGGL((exchange_kernel<T, 8>), dim3((unsigned)grid), dim3(256), 0, s, p.nk, p.m,
+                       p.nocc, p.nchol, p.nwalk, mesh, nchunk, Lh, Gh, part);
+  else if (KS <= 16)
+    hipLaunchKernelGGL((exchange_kernel<T, 16>), dim3((unsigned)grid), dim3(256), 0, s, p.nk, p.m,
+                       p.nocc, p.nchol, p.nwalk, mesh, nchunk, Lh, Gh, part);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t run_energy(const afqmc_kpt_problem& p, void* E, void* ws, hipStream_t s) {
+  Carve c(ws);
+  void *X, *parts, *xpart;
+  carve_energy(c, p, &X, &parts, &xpart);
+  hipError_t e = launch_cholesky_trace(p, X, parts, s);
+  if (e != hipSuccess) return e;
+  e = (p.prec == AFQMC_PREC_FP32) ? launch_exchange<float>(p, xpart, s)
+                                  : launch_exchange<double>(p, xpart, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(energy_final_kernel, dim3(p.nwalk), dim3(256), 0, s, p.nk, p.m, p.nocc,
+                     p.nchol, p.nwalk, make_mesh(p), (const cpx<double>*)p.h1h,
+                     (const cpx<double>*)p.Gh, (const cpx<double>*)X,
+                     (const cpx<double>*)xpart, (cpx<double>*)E);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint.  One workgroup per (k1, k2, walker chunk) accumulates over Q and g
+//   K[(w al), rho] = sum_{b,g} T1_{(Q,k1,k2)}[w][b][al][g] Lh[-Q][k2-Q][b][rho][g]
+// with T1 recomputed per g chunk (GEMM 1, K = m) and fed through a wave-private LDS tile
+// into GEMM 2 (K = (b, g) of the chunk).  The epilogue adds the one-body and Coulomb terms
+// and scales by 2 gE[w].
+template <typename T, int KSMAX, int MT>
+__global__ __launch_bounds__(256) void exchange_bwd_kernel(
+    int nk, int m, int nocc, int C, int W, KMesh mesh, int nchunk_w, const cpx<T>* __restrict__ Lh,
+    const cpx<double>* __restrict__ LhD, const cpx<double>* __restrict__ h1h,
+    const cpx<double>* __restrict__ Gh, const cpx<double>* __restrict__ X,
+    const cpx<double>* __restrict__ gE, cpx<double>* __restrict__ gGh) {
+  typedef typename mfma16<T>::acc_t acc_t;
+  constexpr int RP = 4 * KSMAX;
+  constexpr int NC = MT * 16;
+  constexpr int NLA = (16 * RP) / 256 > 0 ? (16 * RP) / 256 : 1;
+  constexpr int NLB = (16 * NC) / 256;
+
+  __shared__ T LA[2][2][RP][16];      // [buf][re/im][r][(g, al)]
+  __shared__ T LB[2][2][16][NC + 1];  // [buf][re/im][(b, g)][rho]
+  __shared__ T XB[4][2][16][17];
+
+  const int64_t total = (int64_t)nk * nk * nchunk_w;
+  const int64_t bid = xcd_remap(blockIdx.x, total);
+  const int chunk = (int)(bid % nchunk_w);
+  const int k2 = (int)((bid / nchunk_w) % nk);
+  const int k1 = (int)(bid / ((int64_t)nchunk_w * nk));
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int Gs = 16 / nocc, Ws = 16 / nocc;
+  const int KS = (m + 3) >> 2;
+  const int col = lane & 15;
+  const int ws_l = col / nocc, b_l = col % nocc;
+  const int wl = chunk * 4 * Ws + wave * Ws + ws_l;
+  const bool colok = (ws_l < Ws) && (wl < W);
+  const int64_t Nn = (int64_t)nk * m, nn = (int64_t)nk * nocc;
+  const int nch = (C + Gs - 1) / Gs;
+
+  acc_t o_r[MT], o_i[MT];
+#pragma unroll
+  for (int j = 0; j < MT; ++j) { o_r[j] = mfma16<T>::zero(); o_i[j] = mfma16<T>::zero(); }
+
+  // LDS rows never written by a slab (beyond nocc * Gs) stay zero
+  for (int i = tid; i < 2 * 2 * RP * 16; i += 256) (&LA[0][0][0][0])[i] = (T)0;
+  for (int i = tid; i < 2 * 2 * 16 * (NC + 1); i += 256) (&LB[0][0][0][0])[i] = (T)0;
+  __syncthreads();
+
+  T par[NLA], pai[NLA], pbr[NLB], pbi[NLB];
+  for (int Q = 0; Q < nk; ++Q) {
+    const int mQ = mesh.neg(Q), kq1 = mesh.kmq(k1, Q), kq2 = mesh.kmq(k2, Q);
+    T b1r[KSMAX], b1i[KSMAX];
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s) {
+      const int r = 4 * s + (lane >> 4);
+      T xr = 0, xi = 0;
+      if (s < KS && r < m && colok) {
+        const cpx<double> g1 =
+            Gh[((int64_t)wl * nn + (int64_t)kq2 * nocc + b_l) * Nn + (int64_t)kq1 * m + r];
+        xr = (T)g1.re; xi = (T)g1.im;
+      }
+      b1r[s] = xr; b1i[s] = xi;
+    }
+    const cpx<T>* sa = Lh + ((int64_t)Q * nk + k1) * nocc * m * C;
+    const cpx<T>* sb = Lh + ((int64_t)mQ * nk + kq2) * nocc * m * C;
+    // LA element: (r, q = al * Gs + g_s); LB element: (b, rho, g_s), g fastest in memory
+    auto fetch = [&](int c) {
+      const int g0 = c * Gs;
+#pragma unroll
+      for (int e = 0; e < NLA; ++e) {
+        const int idx = tid + 256 * e;
+        const int r = idx / 16, q = idx % 16;
+        const int al = q / Gs, g_s = q % Gs;
+        T vr = 0, vi = 0;
+        if (idx < 16 * RP && al < nocc && r < m && g0 + g_s < C) {
+          const cpx<T> v = sa[((int64_t)al * m + r) * C + g0 + g_s];
+          vr = v.re; vi = v.im;
+        }
+        par[e] = vr; pai[e] = vi;
+      }
+#pragma unroll
+      for (int e = 0; e < NLB; ++e) {
+        const int idx = tid + 256 * e;
+        const int g_s = idx % Gs, rest = idx / Gs;
+        const int rho = rest % NC, b = rest / NC;
+        T vr = 0, vi = 0;
+        if (b < nocc && rho < m && g0 + g_s < C) {
+          const cpx<T> v = sb[((int64_t)b * m + rho) * C + g0 + g_s];
+          vr = v.re; vi = v.im;
+        }
+        pbr[e] = vr; pbi[e] = vi;
+      }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+      for (int e = 0; e < NLA; ++e) {
+        const int idx = tid + 256 * e;
+        const int r = idx / 16, q = idx % 16;
+        const int al = q / Gs, g_s = q % Gs;
+        if (idx < 16 * RP && al < nocc) {
+          LA[buf][0][r][g_s * nocc + al] = par[e];
+          LA[buf][1][r][g_s * nocc + al] = pai[e];
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < NLB; ++e) {
+        const int idx = tid + 256 * e;
+        const int g_s = idx % Gs, rest = idx / Gs;
+        const int rho = rest % NC, b = rest / NC;
+        if (b < nocc) {
+          LB[buf][0][b * Gs + g_s][rho] = pbr[e];
+          LB[buf][1][b * Gs + g_s][rho] = pbi[e];
+        }
+      }
+    };
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+      const int buf = c & 1;
+      if (c + 1 < nch) fetch(c + 1);
+      acc_t tr_ = mfma16<T>::zero(), ti_ = mfma16<T>::zero();
+#pragma unroll
+      for (int s = 0; s < KSMAX; ++s) {
+        if (s < KS) {
+          const int r = 4 * s + (lane >> 4);
+          cmfma<T>(LA[buf][0][r][col], LA[buf][1][r][col], b1r[s], b1i[s], tr_, ti_);
+        }
+      }
+      // T1 tile: rows (g, al), cols (w, b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = mfma16<T>::drow(lane, v);
+        XB[wave][0][row][col] = tr_[v];
+        XB[wave][1][row][col] = ti_[v];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // GEMM 2: A[(w, al)][(b, g)] = T1[(g, al)][(w, b)], B[(b, g)][rho] from LB
+      const int rw = lane & 15;  // A row for this lane: (w_s, al)
+      const int w_s = rw / nocc, al = rw % nocc;
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int kk = 4 * ks + (lane >> 4);
+        const int b = kk / Gs, g_s = kk % Gs;
+        T xr = 0, xi = 0;
+        if (w_s < Ws && b < nocc) {
+          xr = XB[wave][0][g_s * nocc + al][w_s * nocc + b];
+          xi = XB[wave][1][g_s * nocc + al][w_s * nocc + b];
+        }
+#pragma unroll
+        for (int j = 0; j < MT; ++j)
+          cmfma<T>(xr, xi, LB[buf][0][kk][j * 16 + col], LB[buf][1][kk][j * 16 + col], o_r[j], o_i[j]);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (c + 1 < nch) stash(buf ^ 1);
+      __syncthreads();
+    }
+  }
+
+  // epilogue: rows (w, al), cols rho
+  const int Q0 = mesh.kmq(k1, k2);  // k1 - k2
+  const int mQ0 = mesh.neg(Q0);
+#pragma unroll
+  for (int j = 0; j < MT; ++j)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = mfma16<T>::drow(lane, v);
+      const int w_s = row / nocc, al = row % nocc;
+      const int rho = j * 16 + col;
+      const int w = chunk * 4 * Ws + wave * Ws + w_s;
+      if (w_s >= Ws || w >= W || rho >= m) continue;
+      double vr = -(double)o_r[j][v], vi = -(double)o_i[j][v];
+      if (k1 == k2) {
+        const cpx<double> h = h1h[((int64_t)k1 * nocc + al) * m + rho];
+        vr += h.re; vi += h.im;
+      }
+      const cpx<double>* lc = LhD + ((((int64_t)Q0 * nk + k1) * nocc + al) * m + rho) * C;
+      const cpx<double>* xc = X + ((int64_t)w * nk + mQ0) * C;
+      double cr = 0, ci = 0;
+      for (int g = 0; g < C; ++g) {
+        const cpx<double> l = lc[g], x = xc[g];
+        cr += l.re * x.re - l.im * x.im;
+        ci += l.re * x.im + l.im * x.re;
+      }
+      vr += cr; vi += ci;
+      double sr = 2.0, si = 0.0;
+      if (gE) { sr = 2.0 * gE[w].re; si = 2.0 * gE[w].im; }
+      gGh[((int64_t)w * nn + (int64_t)k1 * nocc + al) * Nn + (int64_t)k2 * m + rho] =
+          cpx<double>{sr * vr - si * vi, sr * vi + si * vr};
+    }
+}
+
+static size_t carve_backward(Carve& c, const afqmc_kpt_problem& p, void** X, void** parts) {
+  Dims d = dims_of(p);
+  *X = c.take(16 * (size_t)d.W * d.nk * d.C);
+  VbiasWs v;
+  carve_vbias(c, d, v);
+  *parts = v.parts;
+  return c.off;
+}
+
+size_t backward_ws_bytes(const afqmc_kpt_problem& p) {
+  Carve c(nullptr);
+  void *a, *b;
+  return carve_backward(c, p, &a, &b);
+}
+
+template <typename T, int KSMAX>
+static hipError_t launch_bwd_k(const afqmc_kpt_problem& p, const void* gE, void* gGh, void* X,
+                               hipStream_t s, dim3 grid, int nchunk) {
+  const cpx<T>* Lh = (const cpx<T>*)(sizeof(T) == 8 ? p.Lh : p.Lh32);
+  const int MT = (p.m + 15) / 16;
+  KMesh mesh = make_mesh(p);
+#define AFQMC_BWD(MTV)                                                                        \
+  hipLaunchKernelGGL((exchange_bwd_kernel<T, KSMAX, MTV>), grid, dim3(256), 0, s, p.nk, p.m,     \
+                     p.nocc, p.nchol, p.nwalk, mesh, nchunk, Lh, (const cpx<double>*)p.Lh,      \
+                     (const cpx<double>*)p.h1h, (const cpx<double>*)p.Gh,                       \
+                     (const cpx<double>*)X, (const cpx<double>*)gE, (cpx<double>*)gGh)
+  switch (MT) {
+    case 1: AFQMC_BWD(1); break;
+    case 2: AFQMC_BWD(2); break;
+    case 3: AFQMC_BWD(3); break;
+    case 4: AFQMC_BWD(4); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef AFQMC_BWD
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_bwd(const afqmc_kpt_problem& p, const void* gE, void* gGh, void* X,
+                             hipStream_t s) {
+  const int Ws = 16 / p.nocc;
+  const int nchunk = (p.nwalk + 4 * Ws - 1) / (4 * Ws);
+  const int64_t g = (int64_t)p.nk * p.nk * nchunk;
+  if (g > 0x7fffffff) return hipErrorInvalidValue;
+  const int KS = (p.m + 3) / 4;
+  if (KS <= 4) return launch_bwd_k<T, 4>(p, gE, gGh, X, s, dim3((unsigned)g), nchunk);
+  if (KS <= 8) return launch_bwd_k<T, 8>(p, gE, gGh, X, s, dim3((unsigned)g), nchunk);
+  if (KS <= 16) return launch_bwd_k<T, 16>(p, gE, gGh, X, s, dim3((unsigned)g), nchunk);
+  return hipErrorInvalidValue;
+}
+
+hipError_t run_energy_backward(const afqmc_kpt_problem& p, const void* gE, void* gGh, void* ws,
+                               hipStream_t s) {
+  Carve c(ws);
+  void *X, *parts;
+  carve_backward(c, p, &X, &parts);
+  hipError_t e = launch_cholesky_trace(p, X, parts, s);
+  if (e != hipSuccess) return e;
+  return (p.prec == AFQMC_PREC_FP32) ? launch_bwd<float>(p, gE, gGh, X, s)
+                                     : launch_bwd<double>(p, gE, gGh, X, s);
+}
+
+}  // namespace afqmc

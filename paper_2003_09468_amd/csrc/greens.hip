@@ -1,0 +1,427 @@
+// Overlap, Green's function and walker weights (FP64 on gfx950).
+//
+// Green's-function equations of the standard representation, blocked by the trial's
+// k structure: O = A^H U (nk*nocc square), log det O, Gh = (U O^{-1})^T.
+//
+// The (nk*nocc)^2 overlap matrix (108^2 complex128 = 187 KB for a 3x3x3 mesh with
+// 4 occupied bands) does not fit the 160 KB LDS, so one 1024-thread workgroup per walker
+// keeps it in registers: thread (tr, tc) of a 32 x 32 grid owns rows tr + 32 i and
+// columns tc + 32 j.  Gauss-Jordan elimination with partial (row) pivoting inverts it in
+// place, exchanging only the pivot column and two rows per step through LDS; the log
+// determinant is the sum of the pivot logarithms plus i*pi per row swap.  The same engine
+// factorises the Gram matrix of the re-orthonormalisation (Cholesky, then inversion of
+// the triangular factor).  The solve Gh = O^{-T} U^T is a batched MFMA GEMM.
+#include <math.h>
+
+#include "cgemm.h"
+#include "internal.h"
+
+namespace afqmc {
+
+#define AFQMC_PI 3.14159265358979323846
+
+template <int NS>
+__device__ __forceinline__ double pick(const double (&a)[NS][NS], int si, int sj) {
+  double v = 0.0;
+#pragma unroll
+  for (int x = 0; x < NS; ++x)
+#pragma unroll
+    for (int y = 0; y < NS; ++y)
+      if (x == si && y == sj) v = a[x][y];
+  return v;
+}
+
+template <int NS>
+__global__ __launch_bounds__(1024) void small_gj_kernel(int mode, int n, int nk, int m, int nocc,
+                                                        const cpx<double>* __restrict__ U,
+                                                        const cpx<double>* __restrict__ A,
+                                                        const cpx<double>* __restrict__ S_in,
+                                                        cpx<double>* __restrict__ out,
+                                                        cpx<double>* __restrict__ logdet_out,
+                                                        int* __restrict__ status) {
+  const int w = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int tr = tid >> 5, tc = tid & 31;
+  const int lane = tid & 63;
+  const int64_t N = (int64_t)nk * m;
+
+  __shared__ double colr[2][128], coli[2][128];
+  __shared__ double rowr[2][128], rowi[2][128];
+  __shared__ double rjr[2][128], rji[2][128];
+  __shared__ int perm[128];
+  __shared__ int cols[128], pos[128];
+  __shared__ int flag_s;
+
+  double re[NS][NS], im[NS][NS];
+
+  if (tid == 0) flag_s = 0;
+
+  // ---- load the matrix
+  if (mode == GJ_MODE_GREENS) {
+    const cpx<double>* Uw = U + (int64_t)w * N * n;
+#pragma unroll
+    for (int si = 0; si < NS; ++si)
+#pragma unroll
+      for (int sj = 0; sj < NS; ++sj) {
+        const int row = tr + 32 * si, col = tc + 32 * sj;
+        double sr = 0.0, sim = 0.0;
+        if (row < n && col < n) {
+          const int k = row / nocc, a = row % nocc;
+          // O[(k a)][col] = sum_p conj(A[k][p][a]) U[(k p)][col]
+          for (int p = 0; p < m; ++p) {
+            const cpx<double> av = A[((int64_t)k * m + p) * nocc + a];
+            const cpx<double> uv = Uw[((int64_t)k * m + p) * n + col];
+            sr += av.re * uv.re + av.im * uv.im;
+            sim += av.re * uv.im - av.im * uv.re;
+          }
+        }
+        re[si][sj] = sr;
+        im[si][sj] = sim;
+      }
+  } else {
+    const cpx<double>* Sw = S_in + (int64_t)w * n * n;
+#pragma unroll
+    for (int si = 0; si < NS; ++si)
+#pragma unroll
+      for (int sj = 0; sj < NS; ++sj) {
+        const int row = tr + 32 * si, col = tc + 32 * sj;
+        cpx<double> v{0.0, 0.0};
+        if (row < n && col < n) v = Sw[(int64_t)row * n + col];
+        re[si][sj] = v.re;
+        im[si][sj] = v.im;
+      }
+  }
+  __syncthreads();
+
+  int bad = 0;  // 1: zero pivot, 2: non-finite
+
+  // ---- Cholesky S = L L^H (lower), in place, for the re-orthonormalisation
+  if (mode == GJ_MODE_CHOL_INV) {
+    for (int j = 0; j < n; ++j) {
+      const int buf = j & 1, js = j >> 5, jl = j & 31;
+      if (tc == jl) {
+#pragma unroll
+        for (int si = 0; si < NS; ++si) {
+          const int row = tr + 32 * si;
+          if (row < n) {
+            colr[buf][row] = pick<NS>(re, si, js);
+            coli[buf][row] = pick<NS>(im, si, js);
+          }
+        }
+      }
+      __syncthreads();
+      double d = colr[buf][j];
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad |= isfinite(d) ? 1 : 2;
+        d = 1.0;
+      }
+      const double sd = sqrt(d), isd = 1.0 / sd;
+#pragma unroll
+      for (int si = 0; si < NS; ++si)
+#pragma unroll
+        for (int sj = 0; sj < NS; ++sj) {
+          const int row = tr + 32 * si, col = tc + 32 * sj;
+          if (row >= n || col >= n || row < j || col < j) continue;
+          if (col == j) {
+            if (row == j) { re[si][sj] = sd; im[si][sj] = 0.0; }
+            else { re[si][sj] = colr[buf][row] * isd; im[si][sj] = coli[buf][row] * isd; }
+          } else if (row == j) {
+            re[si][sj] = 0.0; im[si][sj] = 0.0;  // upper part of the factor
+          } else {
+            // S[row][col] -= l_row conj(l_col), l = S[:, j] / sqrt(S[j][j])
+            const double ar = colr[buf][row] * isd, ai = coli[buf][row] * isd;
+            const double br = colr[buf][col] * isd, bi = coli[buf][col] * isd;
+            re[si][sj] -= ar * br + ai * bi;
+            im[si][sj] -= ai * br - ar * bi;
+          }
+        }
+    }
+    __syncthreads();
+  }
+
+  // ---- Gauss-Jordan inversion with partial pivoting, in place
+  double ldr = 0.0, ldi = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const int buf = j & 1, js = j >> 5, jl = j & 31;
+    if (tc == jl) {
+#pragma unroll
+      for (int si = 0; si < NS; ++si) {
+        const int row = tr + 32 * si;
+        if (row < n) {
+          colr[buf][row] = pick<NS>(re, si, js);
+          coli[buf][row] = pick<NS>(im, si, js);
+        }
+      }
+    }
+    __syncthreads();
+    // pivot: largest |column entry| among rows j..n-1 (lowest index on ties), per wave
+    double best = -1.0;
+    int bi = n;
+    for (int i = j + lane; i < n; i += 64) {
+      const double v = colr[buf][i] * colr[buf][i] + coli[buf][i] * coli[buf][i];
+      if (v > best) { best = v; bi = i; }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    const int p = (bi < n) ? bi : j;
+    if (tr == (p & 31)) {
+      const int ps = p >> 5;
+#pragma unroll
+      for (int sj = 0; sj < NS; ++sj) {
+        const int col = tc + 32 * sj;
+        if (col < n) {
+          double vr = 0.0, vi = 0.0;
+#pragma unroll
+          for (int si = 0; si < NS; ++si)
+            if (si == ps) { vr = re[si][sj]; vi = im[si][sj]; }
+          rowr[buf][col] = vr;
+          rowi[buf][col] = vi;
+        }
+      }
+    }
+    if (tr == jl) {
+#pragma unroll
+      for (int sj = 0; sj < NS; ++sj) {
+        const int col = tc + 32 * sj;
+        if (col < n) {
+          double vr = 0.0, vi = 0.0;
+#pragma unroll
+          for (int si = 0; si < NS; ++si)
+            if (si == js) { vr = re[si][sj]; vi = im[si][sj]; }
+          rjr[buf][col] = vr;
+          rji[buf][col] = vi;
+        }
+      }
+    }
+    __syncthreads();
+    double pr = rowr[buf][j], pim = rowi[buf][j];
+    double den = pr * pr + pim * pim;
+    if (!(den > 0.0) || !isfinite(den)) {
+      bad |= isfinite(den) ? 1 : 2;
+      pr = 1.0; pim = 0.0; den = 1.0;
+    }
+    const double ivr = pr / den, ivi = -pim / den;  // 1 / pivot
+#pragma unroll
+    for (int si = 0; si < NS; ++si)
+#pragma unroll
+      for (int sj = 0; sj < NS; ++sj) {
+        const int row = tr + 32 * si, col = tc + 32 * sj;
+        if (row >= n || col >= n) continue;
+        double vr, vi;
+        if (row == j) {
+          if (col == j) { vr = ivr; vi = ivi; }
+          else {
+            const double ar = rowr[buf][col], ai = rowi[buf][col];
+            vr = ar * ivr - ai * ivi;
+            vi = ar * ivi + ai * ivr;
+          }
+        } else {
+          const bool swapped = (row == p);
+          const double ar = swapped ? rjr[buf][col] : re[si][sj];
+          const double ai = swapped ? rji[buf][col] : im[si][sj];
+          const double fr = swapped ? colr[buf][j] : colr[buf][row];
+          const double fi = swapped ? coli[buf][j] : coli[buf][row];
+          // g = f / pivot
+          const double gr = fr * ivr - fi * ivi, gi = fr * ivi + fi * ivr;
+          if (col == j) { vr = -gr; vi = -gi; }
+          else {
+            const double br = rowr[buf][col], bim = rowi[buf][col];
+            vr = ar - (gr * br - gi * bim);
+            vi = ai - (gr * bim + gi * br);
+          }
+        }
+        re[si][sj] = vr;
+        im[si][sj] = vi;
+      }
+    if (tid == 0) {
+      perm[j] = p;
+      ldr += 0.5 * log(den);
+      ldi += atan2(pim, pr) + ((p != j) ? AFQMC_PI : 0.0);
+    }
+  }
+  if (bad) atomicOr(&flag_s, bad);
+  __syncthreads();
+  if (tid == 0) {
+    for (int c = 0; c < n; ++c) cols[c] = c;
+    for (int j = n - 1; j >= 0; --j) {
+      const int p = perm[j];
+      const int t = cols[j]; cols[j] = cols[p]; cols[p] = t;
+    }
+    for (int c = 0; c < n; ++c) pos[cols[c]] = c;
+  }
+  __syncthreads();
+  const int fl = flag_s;
+
+  // ---- write out: the inverse's column c sits in working column cols[c]
+  cpx<double>* Ow = out + (int64_t)w * n * n;
+#pragma unroll
+  for (int si = 0; si < NS; ++si)
+#pragma unroll
+    for (int sj = 0; sj < NS; ++sj) {
+      const int row = tr + 32 * si, col = tc + 32 * sj;
+      if (row >= n || col >= n) continue;
+      const int c = pos[col];
+      double vr = re[si][sj], vi = im[si][sj];
+      if (mode == GJ_MODE_CHOL_INV) vi = -vi;  // R^{-1} = (L^{-1})^H
+      if (fl) {
+        // degenerate walker: Gh = 0 / leave U unchanged (identity R^{-1})
+        vr = (mode == GJ_MODE_CHOL_INV && c == row) ? 1.0 : 0.0;
+        vi = 0.0;
+      }
+      // GREENS: out = O^{-T}, i.e. out[c][row] = Oinv[row][c];
+      // CHOL_INV: out[c][row] = conj(Linv[row][c]) = Rinv[c][row]
+      Ow[(int64_t)c * n + row] = cpx<double>{vr, vi};
+    }
+  if (tid == 0) {
+    if (mode == GJ_MODE_GREENS) {
+      double wi = remainder(ldi, 2.0 * AFQMC_PI);
+      if (wi <= -AFQMC_PI) wi += 2.0 * AFQMC_PI;
+      logdet_out[w] = fl ? cpx<double>{0.0, 0.0} : cpx<double>{ldr, wi};
+    }
+    if (fl) {
+      int bits = 0;
+      if (fl & 1) bits |= AFQMC_WALKER_SINGULAR;
+      if (fl & 2) bits |= AFQMC_WALKER_NONFINITE;
+      status[w] |= bits;
+    }
+  }
+}
+
+hipError_t launch_small_gj(const afqmc_kpt_problem& p, int mode, const void* S_in, void* out,
+                           void* logdet_out, hipStream_t s) {
+  const int n = p.nk * p.nocc;
+  const int ns = (n + 31) / 32;
+  const cpx<double>* U = (const cpx<double>*)p.U;
+  const cpx<double>* A = (const cpx<double>*)p.A;
+  const cpx<double>* S = (const cpx<double>*)S_in;
+  cpx<double>* o = (cpx<double>*)out;
+  cpx<double>* ld = (cpx<double>*)logdet_out;
+  dim3 g(p.nwalk), b(1024);
+  switch (ns) {
+    case 1: hipLaunchKernelGGL(small_gj_kernel<1>, g, b, 0, s, mode, n, p.nk, p.m, p.nocc, U, A, S, o, ld, p.status); break;
+    case 2: hipLaunchKernelGGL(small_gj_kernel<2>, g, b, 0, s, mode, n, p.nk, p.m, p.nocc, U, A, S, o, ld, p.status); break;
+    case 3: hipLaunchKernelGGL(small_gj_kernel<3>, g, b, 0, s, mode, n, p.nk, p.m, p.nocc, U, A, S, o, ld, p.status); break;
+    case 4: hipLaunchKernelGGL(small_gj_kernel<4>, g, b, 0, s, mode, n, p.nk, p.m, p.nocc, U, A, S, o, ld, p.status); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Gh[w][i][R] = sum_j OinvT[w][i][j] U[w][R][j]
+struct OpGreensSolve {
+  typedef double T;
+  static constexpr bool A_KCONTIG = true;
+  static constexpr bool B_NCONTIG = false;
+  int M, N, K, nbatch;
+  const cpx<double>* oinvT;
+  const cpx<double>* U;
+  cpx<double>* Gh;
+  __device__ void load_a(int b, int row, int k, double& re, double& im) const {
+    const cpx<double> v = oinvT[((int64_t)b * M + row) * K + k];
+    re = v.re; im = v.im;
+  }
+  __device__ void load_b(int b, int k, int col, double& re, double& im) const {
+    const cpx<double> v = U[((int64_t)b * N + col) * K + k];
+    re = v.re; im = v.im;
+  }
+  __device__ void store(int b, int row, int col, double re, double im) const {
+    Gh[((int64_t)b * M + row) * N + col] = cpx<double>{re, im};
+  }
+};
+
+hipError_t launch_greens_solve(const afqmc_kpt_problem& p, const void* oinvT, hipStream_t s) {
+  OpGreensSolve op;
+  op.M = p.nk * p.nocc;
+  op.N = p.nk * p.m;
+  op.K = p.nk * p.nocc;
+  op.nbatch = p.nwalk;
+  op.oinvT = (const cpx<double>*)oinvT;
+  op.U = (const cpx<double>*)p.U;
+  op.Gh = (cpx<double>*)p.Gh;
+  return launch_cgemm<64, 64, 16, 2, 2>(op, s);
+}
+
+size_t carve_greens(Carve& c, const Dims& d, GreensWs& g) {
+  g.oinvT = c.take(sizeof(double) * 2 * d.W * d.n() * d.n());
+  g.logdet_new = c.take(sizeof(double) * 2 * d.W);
+  return c.off;
+}
+
+// Greens for the current U.  With write_logdet_new_only the log determinant goes to the
+// workspace slot (the weight update then moves it into p.logdet), else into p.logdet.
+hipError_t run_greens(const afqmc_kpt_problem& p, void* ws, bool write_logdet_new_only,
+                      hipStream_t s) {
+  Carve c(ws);
+  GreensWs g;
+  carve_greens(c, dims_of(p), g);
+  hipError_t e = launch_small_gj(p, GJ_MODE_GREENS, nullptr, g.oinvT,
+                                 write_logdet_new_only ? g.logdet_new : p.logdet, s);
+  if (e != hipSuccess) return e;
+  return launch_greens_solve(p, g.oinvT, s);
+}
+
+// ---------------------------------------------------------------------------
+// Hybrid phaseless weight update, one workgroup per walker:
+//   log I = 2 (logdet' - logdet) + sum_{Q,g,+/-} (x xbar - xbar^2/2),
+//   dtheta = arg exp(2 (logdet' - logdet)), w <- |I| max(0, cos dtheta) w.
+__global__ __launch_bounds__(256) void weight_kernel(int64_t nf, const double* __restrict__ x,
+                                                     const cpx<double>* __restrict__ xbar,
+                                                     cpx<double>* __restrict__ logdet,
+                                                     const cpx<double>* __restrict__ logdet_new,
+                                                     double* __restrict__ weight,
+                                                     int* __restrict__ status) {
+  const int w = blockIdx.x;
+  const int tid = threadIdx.x;
+  __shared__ double sr[256], si[256];
+  double ar = 0.0, ai = 0.0;
+  const double* xw = x + (int64_t)w * nf;
+  const cpx<double>* bw = xbar + (int64_t)w * nf;
+  for (int64_t i = tid; i < nf; i += 256) {
+    const double xv = xw[i];
+    const cpx<double> b = bw[i];
+    // x b - b^2 / 2
+    ar += xv * b.re - 0.5 * (b.re * b.re - b.im * b.im);
+    ai += xv * b.im - b.re * b.im;
+  }
+  sr[tid] = ar;
+  si[tid] = ai;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (tid < o) { sr[tid] += sr[tid + o]; si[tid] += si[tid + o]; }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const cpx<double> l0 = logdet[w], l1 = logdet_new[w];
+    const double lrr = 2.0 * (l1.re - l0.re), lri = 2.0 * (l1.im - l0.im);
+    const double lIr = lrr + sr[0];
+    const double dth = atan2(sin(lri), cos(lri));
+    const double c = cos(dth);
+    int st = status[w];
+    double wn = weight[w];
+    if (st & (AFQMC_WALKER_SINGULAR | AFQMC_WALKER_NONFINITE)) {
+      wn = 0.0;
+    } else {
+      if (!(c > 0.0)) st |= AFQMC_WALKER_KILLED;
+      wn = exp(lIr) * fmax(0.0, c) * wn;
+      if (!isfinite(wn)) { st |= AFQMC_WALKER_NONFINITE; wn = 0.0; }
+    }
+    weight[w] = wn;
+    status[w] = st;
+    logdet[w] = l1;
+  }
+}
+
+hipError_t launch_weights(const afqmc_kpt_problem& p, const double* x, const void* xbar,
+                          const void* logdet_new, hipStream_t s) {
+  const int64_t nf = (int64_t)p.nk * p.nchol * 2;
+  hipLaunchKernelGGL(weight_kernel, dim3(p.nwalk), dim3(256), 0, s, nf, x,
+                     (const cpx<double>*)xbar, (cpx<double>*)p.logdet,
+                     (const cpx<double>*)logdet_new, p.weight, p.status);
+  return hipGetLastError();
+}
+
+}  // namespace afqmc

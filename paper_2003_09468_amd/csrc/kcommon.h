@@ -1,0 +1,94 @@
+// Internal device helpers shared by the gfx950 kernels of the k-point AFQMC library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/afqmc_kpt.h"
+
+namespace afqmc {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Complex values as plain (re, im) pairs of the storage type.
+template <typename T>
+struct cpx {
+  T re, im;
+};
+
+// MFMA 16x16x4 wrappers.  Lane l of a wave supplies A[l%16][l/16] and B[l/16][l%16]
+// and receives four entries of column l%16 of D; their rows depend on the instruction
+// (measured on gfx950): FP32 rows 4*(l/16) + v, FP64 rows l/16 + 4*v, v = 0..3.
+// drow(lane, v) gives that row.
+template <typename T>
+struct mfma16;
+
+template <>
+struct mfma16<double> {
+  typedef v4d acc_t;
+  static __device__ __forceinline__ acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ acc_t mac(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+
+template <>
+struct mfma16<float> {
+  typedef v4f acc_t;
+  static __device__ __forceinline__ acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ acc_t mac(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// Complex multiply-accumulate of one 16x16x4 block on real MFMA:
+//   Dre += Are Bre - Aim Bim,  Dim += Are Bim + Aim Bre.
+template <typename T>
+__device__ __forceinline__ void cmfma(T ar, T ai, T br, T bi, typename mfma16<T>::acc_t& dr,
+                                      typename mfma16<T>::acc_t& di) {
+  dr = mfma16<T>::mac(ar, br, dr);
+  di = mfma16<T>::mac(ar, bi, di);
+  dr = mfma16<T>::mac(-ai, bi, dr);
+  di = mfma16<T>::mac(ai, br, di);
+}
+
+// k-point index algebra on the device (mesh row-major linearisation).
+struct KMesh {
+  int m0, m1, m2;
+  __host__ __device__ __forceinline__ int kmq(int k, int q) const {  // index of k - q
+    int k0 = k / (m1 * m2), k1 = (k / m2) % m1, k2 = k % m2;
+    int q0 = q / (m1 * m2), q1 = (q / m2) % m1, q2 = q % m2;
+    int a = k0 - q0; a += (a < 0) ? m0 : 0;
+    int b = k1 - q1; b += (b < 0) ? m1 : 0;
+    int c = k2 - q2; c += (c < 0) ? m2 : 0;
+    return (a * m1 + b) * m2 + c;
+  }
+  __host__ __device__ __forceinline__ int neg(int q) const {  // index of -q
+    int q0 = q / (m1 * m2), q1 = (q / m2) % m1, q2 = q % m2;
+    int a = q0 ? m0 - q0 : 0, b = q1 ? m1 - q1 : 0, c = q2 ? m2 - q2 : 0;
+    return (a * m1 + b) * m2 + c;
+  }
+};
+
+__host__ __device__ __forceinline__ KMesh make_mesh(const afqmc_kpt_problem& p) {
+  return KMesh{p.mesh[0], p.mesh[1], p.mesh[2]};
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T> ld(const void* base, int64_t idx) {
+  const cpx<T>* b = reinterpret_cast<const cpx<T>*>(base);
+  return b[idx];
+}
+
+// Load a complex128 and return it in the storage precision T.
+template <typename T>
+__device__ __forceinline__ cpx<T> ld_d(const void* base, int64_t idx) {
+  const cpx<double>* b = reinterpret_cast<const cpx<double>*>(base);
+  cpx<double> v = b[idx];
+  return cpx<T>{(T)v.re, (T)v.im};
+}
+
+}  // namespace afqmc

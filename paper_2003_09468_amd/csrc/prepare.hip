@@ -1,0 +1,226 @@
+// One-time preparation of the static data (k-point section: half-transformed Cholesky
+// matrix; introduction: one-body propagator exp(-dt/2 H1') with H1' = H1 + v0).
+//
+//   Lh[Q][k][a][r][g] = sum_p conj(A[k][p][a]) L[Q][k][p][r][g]      (batched GEMM)
+//   h1h[k]            = A[k]^H H1[k]                                 (batched GEMM)
+//   V0[k]             = -1/2 sum_{Q,g} L[Q][k][:,:,g] L[Q][k][:,:,g]^H (GEMM, K = nk*m*nchol)
+//   bhalf[k]          = exp(-dt/2 (H1[k] + V0[k]))
+// The exponential uses the Taylor series with scaling and squaring (Moler and Van Loan,
+// "Nineteen dubious ways to compute the exponential of a matrix"): the matrix is scaled
+// by 2^-s so that its 1-norm is at most 1/4, summed to 18th order (remainder below 1e-27
+// relative) and squared s times, all in FP64.
+#include <math.h>
+
+#include "cgemm.h"
+#include "internal.h"
+
+namespace afqmc {
+
+// Y[b][row][col] = sum_p conj(A[kb][p][row]) X[b][p][col]; batch b over (Q, k) or k.
+struct OpHalfRot {
+  typedef double T;
+  static constexpr bool A_KCONTIG = false;  // A(row=a, k=p) = conj(A[k][p][a]): along a
+  static constexpr bool B_NCONTIG = true;
+  int M, N, K, nbatch;  // M = nocc, K = m, N = cols of X
+  int nk;
+  const cpx<double>* Atr;  // [nk][m][nocc]
+  const cpx<double>* X;    // [nbatch][m][N]
+  cpx<double>* Y;          // [nbatch][nocc][N]
+  cpx<float>* Y32;         // optional complex64 copy
+  __device__ void load_a(int b, int row, int k, double& re, double& im) const {
+    const cpx<double> v = Atr[((int64_t)(b % nk) * K + k) * M + row];
+    re = v.re; im = -v.im;
+  }
+  __device__ void load_b(int b, int k, int col, double& re, double& im) const {
+    const cpx<double> v = X[((int64_t)b * K + k) * N + col];
+    re = v.re; im = v.im;
+  }
+  __device__ void store(int b, int row, int col, double re, double im) const {
+    const int64_t idx = ((int64_t)b * M + row) * N + col;
+    Y[idx] = cpx<double>{re, im};
+    if (Y32) Y32[idx] = cpx<float>{(float)re, (float)im};
+  }
+};
+
+// V0[k][p][q] = -1/2 sum_{Q, (r g)} L[Q][k][p][(r g)] conj(L[Q][k][q][(r g)])
+struct OpV0 {
+  typedef double T;
+  static constexpr bool A_KCONTIG = true;
+  static constexpr bool B_NCONTIG = false;
+  int M, N, K, nbatch;  // M = N = m, K = nk * m * C, nbatch = nk
+  int nk, m;
+  int64_t mc;  // m * C
+  const cpx<double>* L;
+  cpx<double>* V0;
+  __device__ const cpx<double>& at(int kb, int row, int k) const {
+    const int Q = (int)(k / mc);
+    const int64_t rg = k % mc;
+    return L[(((int64_t)Q * nk + kb) * m + row) * mc + rg];
+  }
+  __device__ void load_a(int b, int row, int k, double& re, double& im) const {
+    const cpx<double> v = at(b, row, k);
+    re = v.re; im = v.im;
+  }
+  __device__ void load_b(int b, int k, int col, double& re, double& im) const {
+    const cpx<double> v = at(b, col, k);
+    re = v.re; im = -v.im;
+  }
+  __device__ void store(int b, int row, int col, double re, double im) const {
+    V0[((int64_t)b * M + row) * N + col] = cpx<double>{-0.5 * re, -0.5 * im};
+  }
+};
+
+__global__ void to_c64_kernel(int64_t n, const cpx<double>* __restrict__ x, cpx<float>* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = cpx<float>{(float)x[i].re, (float)x[i].im};
+}
+
+// One workgroup per k.  Scratch: [nk][4][m][m] complex128 (X, T, E, tmp).
+__global__ __launch_bounds__(256) void expm_kernel(int m, double scale,
+                                                   const cpx<double>* __restrict__ H1,
+                                                   const cpx<double>* __restrict__ V0,
+                                                   cpx<double>* __restrict__ scr,
+                                                   cpx<double>* __restrict__ out) {
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const int mm = m * m;
+  cpx<double>* X = scr + (int64_t)k * 4 * mm;
+  cpx<double>* Tm = X + mm;
+  cpx<double>* E = Tm + mm;
+  cpx<double>* Y = E + mm;
+  __shared__ double red[256];
+  __shared__ int s_sh;
+  // X = scale * (H1 + V0)
+  for (int i = tid; i < mm; i += 256) {
+    const cpx<double> h = H1[(int64_t)k * mm + i], v = V0[(int64_t)k * mm + i];
+    X[i] = cpx<double>{scale * (h.re + v.re), scale * (h.im + v.im)};
+  }
+  __syncthreads();
+  // 1-norm (max column sum)
+  double cmax = 0.0;
+  for (int c = tid; c < m; c += 256) {
+    double sum = 0.0;
+    for (int r = 0; r < m; ++r) sum += hypot(X[r * m + c].re, X[r * m + c].im);
+    cmax = fmax(cmax, sum);
+  }
+  red[tid] = cmax;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (tid < o) red[tid] = fmax(red[tid], red[tid + o]);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    int s = 0;
+    double nrm = red[0];
+    while (nrm > 0.25 && s < 60) { nrm *= 0.5; ++s; }
+    s_sh = s;
+  }
+  __syncthreads();
+  const int s = s_sh;
+  const double f = ldexp(1.0, -s);
+  for (int i = tid; i < mm; i += 256) {
+    X[i].re *= f; X[i].im *= f;
+    const int r = i / m, c = i % m;
+    Tm[i] = X[i];
+    E[i] = cpx<double>{X[i].re + (r == c ? 1.0 : 0.0), X[i].im};
+  }
+  __syncthreads();
+  for (int j = 2; j <= 18; ++j) {
+    // Y = X T / j
+    for (int i = tid; i < mm; i += 256) {
+      const int r = i / m, c = i % m;
+      double ar = 0, ai = 0;
+      for (int q = 0; q < m; ++q) {
+        const cpx<double> a = X[r * m + q], b = Tm[q * m + c];
+        ar += a.re * b.re - a.im * b.im;
+        ai += a.re * b.im + a.im * b.re;
+      }
+      Y[i] = cpx<double>{ar / j, ai / j};
+    }
+    __syncthreads();
+    for (int i = tid; i < mm; i += 256) {
+      Tm[i] = Y[i];
+      E[i].re += Y[i].re;
+      E[i].im += Y[i].im;
+    }
+    __syncthreads();
+  }
+  for (int it = 0; it < s; ++it) {
+    for (int i = tid; i < mm; i += 256) {
+      const int r = i / m, c = i % m;
+      double ar = 0, ai = 0;
+      for (int q = 0; q < m; ++q) {
+        const cpx<double> a = E[r * m + q], b = E[q * m + c];
+        ar += a.re * b.re - a.im * b.im;
+        ai += a.re * b.im + a.im * b.re;
+      }
+      Y[i] = cpx<double>{ar, ai};
+    }
+    __syncthreads();
+    for (int i = tid; i < mm; i += 256) E[i] = Y[i];
+    __syncthreads();
+  }
+  for (int i = tid; i < mm; i += 256) out[(int64_t)k * mm + i] = E[i];
+}
+
+size_t prepare_ws_bytes(const afqmc_kpt_problem& p) {
+  return align_up(16 * (size_t)p.nk * p.m * p.m) + align_up(16 * 4 * (size_t)p.nk * p.m * p.m);
+}
+
+hipError_t run_prepare(const afqmc_kpt_problem& p, const void* H1, void* ws, hipStream_t s) {
+  Carve c(ws);
+  void* V0 = c.take(16 * (size_t)p.nk * p.m * p.m);
+  void* scr = c.take(16 * 4 * (size_t)p.nk * p.m * p.m);
+  const bool f32 = (p.prec == AFQMC_PREC_FP32);
+  hipError_t e;
+  {  // Lh = A^H L, batch (Q, k)
+    OpHalfRot op;
+    op.M = p.nocc; op.K = p.m; op.N = p.m * p.nchol;
+    op.nbatch = p.nk * p.nk;
+    op.nk = p.nk;
+    op.Atr = (const cpx<double>*)p.A;
+    op.X = (const cpx<double>*)p.L;
+    op.Y = (cpx<double>*)p.Lh;
+    op.Y32 = f32 ? (cpx<float>*)p.Lh32 : nullptr;
+    e = launch_cgemm<16, 64, 16, 1, 4>(op, s);
+    if (e != hipSuccess) return e;
+  }
+  {  // h1h = A^H H1, batch k
+    OpHalfRot op;
+    op.M = p.nocc; op.K = p.m; op.N = p.m;
+    op.nbatch = p.nk;
+    op.nk = p.nk;
+    op.Atr = (const cpx<double>*)p.A;
+    op.X = (const cpx<double>*)H1;
+    op.Y = (cpx<double>*)p.h1h;
+    op.Y32 = nullptr;
+    e = launch_cgemm<16, 64, 16, 1, 4>(op, s);
+    if (e != hipSuccess) return e;
+  }
+  {  // V0
+    OpV0 op;
+    op.M = p.m; op.N = p.m;
+    op.K = p.nk * p.m * p.nchol;
+    op.nbatch = p.nk;
+    op.nk = p.nk; op.m = p.m;
+    op.mc = (int64_t)p.m * p.nchol;
+    op.L = (const cpx<double>*)p.L;
+    op.V0 = (cpx<double>*)V0;
+    e = launch_cgemm<32, 32, 16, 2, 2>(op, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(expm_kernel, dim3(p.nk), dim3(256), 0, s, p.m, -0.5 * p.dt,
+                     (const cpx<double>*)H1, (const cpx<double>*)V0, (cpx<double>*)scr,
+                     (cpx<double>*)p.bhalf);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (f32) {
+    const int64_t n = (int64_t)p.nk * p.nk * p.m * p.m * p.nchol;
+    hipLaunchKernelGGL(to_c64_kernel, dim3(4096), dim3(256), 0, s, n, (const cpx<double>*)p.L,
+                       (cpx<float>*)p.L32);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+}  // namespace afqmc
