@@ -1,0 +1,268 @@
+#!/usr/bin/env python3
+"""Walker-steps/s of the k-point AFQMC block on one MI355X.
+
+Workload (3x3x3 mesh, m = 26 bands per k, nocc = 4, nchol = 208 per Q, 64 walkers,
+dt = 0.005): seeded synthetic inputs shaped like carbon in the diamond structure with
+a GTH-DZVP basis.  One timed step is one block as the paper times it: 20 propagation
+steps (force bias, HS potential, 6th-order Taylor propagation, new Green's function and
+phaseless weights), one walker re-orthonormalisation, one local-energy evaluation.
+
+Two precisions of the large contractions run on the same inputs: FP64 and FP32 MFMA
+(overlap, inverse, QR and energy sums stay FP64).  The reported value is the FP32
+path's walker-steps/s when its local energies stay within 1e-5 Ha/cell of the FP64
+path after the same block, else the FP64 path's.  The FP64 path itself matches the
+FP64 CPU oracle to 1e-10 Ha/cell (GPU parity tests).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "walker-steps/s at Nk=27 M=26, mixed vs FP64 GPU, |ΔE_loc|≤1e-5 Ha/cell"
+PEAK = {"fp64": 78.6, "fp32": 157.3}  # dense MFMA TFLOP/s, MI355X
+TOL = 1e-5  # Ha per cell
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_flops(name, c):
+    """Algorithmic (executed) flops of one launch of a kernel class; 8 flops per complex MAC."""
+    nk, m, nocc, C, W = c["nk"], c["m"], c["nocc"], c["nchol"], c["nwalk"]
+    N, n = nk * m, nk * nocc
+    if name == "taylor":
+        return 8.0 * W * N * N * n
+    if name == "vhs":
+        return 8.0 * W * nk * nk * m * m * C
+    if name == "vbias":
+        return 8.0 * W * nk * nk * nocc * m * C
+    if name == "exchange":
+        # one T1 GEMM per (Q, k, k') triple: time-reversal pairs share the second GEMM
+        return 8.0 * W * nk ** 3 * nocc * nocc * C * m
+    return None
+
+
+def run_block(p, xs, bufs, E):
+    nsteps = xs.shape[0]
+    for s in range(nsteps):
+        p.step(xs[s], ortho=(s == nsteps - 1), bufs=bufs)
+    return p.energy(out=E)
+
+
+def make_problem(s, U0, prec, torch):
+    from paper_2003_09468_amd import KptProblem
+    p = KptProblem(s.mesh, s.m, s.nocc, s.nchol, U0.shape[0], s.dt, torch.from_numpy(s.L),
+                   torch.from_numpy(s.A), prec=prec)
+    p.prepare(torch.from_numpy(s.H1))
+    return p
+
+
+def reset(p, U0d):
+    p.set_walkers(U0d)
+    p.weight.fill_(1.0)
+    p.greens()
+
+
+def bench_path(name, p, U0d, xs, args, torch, cfg):
+    import paper_2003_09468_amd as lib
+    W, N = p.nwalk, p.nk * p.m
+    vdt = torch.complex64 if p.prec == lib.PREC_FP32 else torch.complex128
+    bufs = {
+        "xbar": torch.empty((W, p.nk, p.nchol, 2), dtype=torch.complex128, device="cuda"),
+        "X": torch.empty((W, p.nk, p.nchol), dtype=torch.complex128, device="cuda"),
+        "vhs": torch.empty((W, N, N), dtype=vdt, device="cuda"),
+    }
+    E = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+    reset(p, U0d)
+    E0 = run_block(p, xs, bufs, E).clone()  # first block from the common start: accuracy
+    w0 = p.weight.clone()
+    for _ in range(args.warmup):
+        run_block(p, xs, bufs, E)
+    torch.cuda.synchronize()
+    lib.timing_enable(True, 1 << 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run_block(p, xs, bufs, E)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lib.timing_enable(False)
+    kern = {}
+    for kc in lib.KERNEL_CLASSES:
+        ms, n = lib.timing_read(kc)
+        if n:
+            kern[kc] = {"ms_total": ms / args.steps, "launches": n // args.steps,
+                        "ms_per_launch": ms / n}
+    dt = (t1 - t0) / args.steps
+    ws = W * xs.shape[0] / dt
+    log(f"[{name}] block {dt * 1e3:.2f} ms  -> {ws:.1f} walker-steps/s")
+    for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms_total"]):
+        log(f"    {k:13s} {v['ms_total']:9.3f} ms/block  {v['launches']:4d} launches  "
+            f"{v['ms_per_launch']:.4f} ms/launch")
+    return {"ms_per_block": dt * 1e3, "walker_steps_per_s": ws, "kernels": kern}, E0, w0
+
+
+def roofline(path_res, prec_key, cfg):
+    kern = path_res["kernels"]
+    dom = max(kern, key=lambda k: kern[k]["ms_total"])
+    fl = kernel_flops(dom, cfg)
+    if fl is None:
+        return {"kernel": dom, "bound": "alu", "achieved": None, "peak": None, "unit": None,
+                "frac": None, "traffic": None}
+    ach = fl / (kern[dom]["ms_per_launch"] * 1e-3) / 1e12
+    return {"kernel": dom, "bound": "mfma", "achieved": round(ach, 3), "peak": PEAK[prec_key],
+            "unit": "TFLOP/s", "frac": round(ach / PEAK[prec_key], 4), "traffic": None,
+            "flops_per_launch": fl}
+
+
+def energy_evals(v, cfg):
+    """Walker energy evaluations per second: walkers / (exchange + one-body/Coulomb/reduction time)."""
+    k = v["kernels"]
+    ms = sum(k[c]["ms_total"] for c in ("exchange", "energy_rest") if c in k)
+    return round(cfg["nwalk"] * 1e3 / ms, 2) if ms > 0 else None
+
+
+def cpu_baseline(s, U0, xs_host):
+    """The FP64 oracle on the host cores, on a bounded sample of the same block."""
+    import numpy as np
+    from oracle import kpoint as kp
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = None
+    cores = len(os.sched_getaffinity(0))
+    nw = 4
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    U = U0[:nw]
+    Gh, ld = kp.greens(U, s.A)
+    t = time.perf_counter()
+    out = kp.step(U, ld, np.ones(nw), xs_host[0][:nw], pre, s.A, s.L, s.mesh, s.dt)
+    t_step = time.perf_counter() - t
+    t = time.perf_counter()
+    Q = kp.orthonormalize(out["U"])
+    kp.greens(Q, s.A)
+    t_qr = time.perf_counter() - t
+    t = time.perf_counter()
+    kp.local_energy(pre["Lh"], pre["h1h"], out["Gh"], s.mesh, walkers=[0])
+    t_e = time.perf_counter() - t
+    nsteps = xs_host.shape[0]
+    per_ws = t_step / nw + (t_qr / nw + t_e) / nsteps
+    return {"value": round(1.0 / per_ws, 3), "unit": "walker-steps/s",
+            "cores": threads if threads else cores, "host_cores": cores, "kind": "oracle",
+            "sample": (f"1 propagation step of {nw} walkers ({t_step:.2f} s), QR+G of {nw} "
+                       f"walkers ({t_qr:.2f} s), local energy of 1 walker ({t_e:.2f} s); "
+                       f"walker-steps/s = 1/(t_step/{nw} + (t_qr/{nw} + t_E)/{nsteps})")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed blocks")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed blocks")
+    ap.add_argument("--config", default="c1")
+    ap.add_argument("--prec", choices=["both", "fp64", "fp32"], default="both")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding walkers or Q blocks across GPUs is not built).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from synth.kpt_inputs import config_shapes, make_system, make_walkers, make_fields
+    import paper_2003_09468_amd as lib
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    cfg = config_shapes(args.config)
+    log(f"generating {args.config}: {cfg}")
+    t = time.perf_counter()
+    s, rng = make_system(cfg["mesh"], cfg["m"], cfg["nocc"], cfg["nchol"], seed=cfg["seed"])
+    U0 = make_walkers(s, cfg["nwalk"], rng)
+    xs_host = make_fields(s, cfg["nwalk"], cfg["nsteps"], rng)
+    log(f"  inputs in {time.perf_counter() - t:.1f} s")
+    U0d = torch.from_numpy(U0).cuda()
+    xs = torch.from_numpy(xs_host).cuda()
+
+    res, E0, W0 = {}, {}, {}
+    paths = ["fp64", "fp32"] if args.prec == "both" else [args.prec]
+    for name in paths:
+        prec = lib.PREC_FP64 if name == "fp64" else lib.PREC_FP32
+        p = make_problem(s, U0, prec, torch)
+        res[name], E0[name], W0[name] = bench_path(name, p, U0d, xs, args, torch, cfg)
+        del p
+        torch.cuda.empty_cache()
+
+    acc = None
+    if "fp64" in res and "fp32" in res:
+        e64 = E0["fp64"].sum(1).cpu().numpy() / cfg["nk"]
+        e32 = E0["fp32"].sum(1).cpu().numpy() / cfg["nk"]
+        d = np.abs(e32 - e64)
+        parts = np.abs(E0["fp32"].cpu().numpy() - E0["fp64"].cpu().numpy()).max(0) / cfg["nk"]
+        acc = {"max_abs_dE_per_cell": float(d.max()), "median_abs_dE_per_cell":
+               float(np.median(d)), "max_abs_dE_parts_per_cell": [float(v) for v in parts],
+               "tolerance": TOL, "compared": "FP32-contraction vs FP64 GPU path, E_L per "
+               "walker after one block from the same start (FP64 path = oracle to 1e-10)"}
+        log(f"accuracy: max |dE_L| = {d.max():.3e} Ha/cell (median {np.median(d):.3e})")
+
+    use = "fp64"
+    if acc is not None and acc["max_abs_dE_per_cell"] <= TOL:
+        use = "fp32"
+    elif args.prec == "fp32":
+        use = "fp32"
+    main_res = res[use]
+    out = {
+        "metric": METRIC,
+        "value": round(main_res["walker_steps_per_s"], 2),
+        "unit": "walker-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_block"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if use == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: mesh {'x'.join(map(str, cfg['mesh']))}, "
+                               f"m={cfg['m']}, nocc={cfg['nocc']}, nchol={cfg['nchol']}, "
+                               f"{cfg['nwalk']} walkers, dt={cfg['dt']}; one step = one block "
+                               f"of {cfg['nsteps']} propagation steps + QR + local energy",
+                   "nk": cfg["nk"], "m": cfg["m"], "nocc": cfg["nocc"], "nchol": cfg["nchol"],
+                   "walkers": cfg["nwalk"], "steps_per_block": cfg["nsteps"],
+                   "path": use},
+        "roofline": roofline(main_res, use, cfg),
+        "paths": {k: {"walker_steps_per_s": round(v["walker_steps_per_s"], 2),
+                      "ms_per_block": round(v["ms_per_block"], 3),
+                      "energy_evals_per_s": energy_evals(v, cfg),
+                      "kernels": {kk: {"ms_per_block": round(vv["ms_total"], 4),
+                                       "launches": vv["launches"],
+                                       "ms_per_launch": round(vv["ms_per_launch"], 5)}
+                                  for kk, vv in v["kernels"].items()},
+                      "roofline_dominant": roofline(v, k, cfg)}
+                  for k, v in res.items()},
+        "accuracy": acc,
+    }
+    if "fp64" in res and "fp32" in res:
+        out["speedup_fp32_vs_fp64"] = round(res["fp32"]["walker_steps_per_s"] /
+                                            res["fp64"]["walker_steps_per_s"], 3)
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(s, U0, xs_host)
+        log(f"  cpu baseline {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -32,7 +32,9 @@
  *  - Per-walker numerical failures (singular overlap, non-finite values,
  *    phaseless kill) are reported in status[w] and never fail the call.
  *  - Energies are per supercell; per cell = E / nk.  The ion-ion energy is 0.
- *  - nprob > 1 runs the problems of the array one after another on the stream.
+ *  - nprob > 1 runs the problems of the array one after another on the stream
+ *    (prepare, greens, orthonormalize); entry points whose outputs are separate
+ *    arguments (vbias, vhs, propagate, energy, energy_backward) take nprob = 1.
  */
 #ifndef AFQMC_KPT_H
 #define AFQMC_KPT_H
@@ -198,6 +200,32 @@ afqmc_status afqmc_kpt_energy(const afqmc_kpt_problem* p, int nprob, void* E,
  *   gGh: [nwalk][nk*nocc][nk*m] complex128 out. */
 afqmc_status afqmc_kpt_energy_backward(const afqmc_kpt_problem* p, int nprob, const void* gE,
                                        void* gGh, void* ws, size_t ws_bytes, void* stream);
+
+/* Kernel classes of the optional event timing. */
+typedef enum {
+  AFQMC_KC_TAYLOR = 0,        /* one Taylor term of the two-body propagator */
+  AFQMC_KC_VHS = 1,           /* HS-potential contraction (with the field combination) */
+  AFQMC_KC_VBIAS = 2,         /* force-bias contraction and reduction */
+  AFQMC_KC_GREENS = 3,        /* overlap inverse / log det and the Gh solve */
+  AFQMC_KC_BHALF = 4,         /* one-body half step */
+  AFQMC_KC_WEIGHTS = 5,       /* phaseless weight update */
+  AFQMC_KC_ORTHO = 6,         /* Cholesky-QR passes */
+  AFQMC_KC_EXCHANGE = 7,      /* paired exchange contraction of the local energy */
+  AFQMC_KC_ENERGY_REST = 8,   /* one-body, Coulomb and final energy reduction */
+  AFQMC_KC_EXCHANGE_BWD = 9,  /* exchange part of the energy adjoint */
+  AFQMC_KC_COUNT = 10
+} afqmc_kernel_class;
+
+/* Diagnostics for callers that measure kernels (host).  While enabled, every launch of
+ * a kernel class is bracketed by two hipEvents recorded on the launch stream; at most
+ * `capacity` launches are recorded between reads (later ones are not timed).  Enabling
+ * resets the totals; disabling keeps them readable.  Calls that overlap on one process
+ * share the recorder. */
+afqmc_status afqmc_kpt_timing_enable(int enable, int capacity);
+
+/* Accumulated time (ms) and number of timed launches of one kernel class since the last
+ * enable; waits for the recorded events. */
+afqmc_status afqmc_kpt_timing_read(int kclass, double* total_ms, long long* launches);
 
 /* Static string for a status code (host). */
 const char* afqmc_kpt_strerror(int status);

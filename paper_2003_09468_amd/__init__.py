@@ -19,4 +19,7 @@ from .binding import (  # noqa: F401
     WALKER_KILLED,
     ENTRIES,
     local_energy,
+    timing_enable,
+    timing_read,
+    KERNEL_CLASSES,
 )

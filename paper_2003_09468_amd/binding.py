@@ -46,9 +46,14 @@ EXPORTS = [
     "afqmc_kpt_orthonormalize",
     "afqmc_kpt_energy",
     "afqmc_kpt_energy_backward",
+    "afqmc_kpt_timing_enable",
+    "afqmc_kpt_timing_read",
     "afqmc_kpt_strerror",
     "afqmc_kpt_version",
 ]
+
+KERNEL_CLASSES = ["taylor", "vhs", "vbias", "greens", "bhalf", "weights", "ortho", "exchange",
+                  "energy_rest", "exchange_bwd"]
 
 
 class AfqmcError(RuntimeError):
@@ -114,6 +119,9 @@ def lib():
         "afqmc_kpt_orthonormalize": [P, i, vp, sz, vp],
         "afqmc_kpt_energy": [P, i, vp, vp, sz, vp],
         "afqmc_kpt_energy_backward": [P, i, vp, vp, vp, sz, vp],
+        "afqmc_kpt_timing_enable": [i, i],
+        "afqmc_kpt_timing_read": [i, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_longlong)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -131,6 +139,20 @@ def check(fn: str, status: int) -> None:
     if status != 0:
         msg = lib().afqmc_kpt_strerror(status).decode()
         raise AfqmcError(fn, status, msg)
+
+
+def timing_enable(enable: bool, capacity: int = 65536) -> None:
+    """Bracket every kernel launch with HIP events on its stream (see the header)."""
+    check("afqmc_kpt_timing_enable", lib().afqmc_kpt_timing_enable(int(enable), int(capacity)))
+
+
+def timing_read(kclass: str) -> tuple[float, int]:
+    """(total ms, launches) of a kernel class since timing was enabled."""
+    ms, n = ctypes.c_double(), ctypes.c_longlong()
+    check("afqmc_kpt_timing_read",
+          lib().afqmc_kpt_timing_read(KERNEL_CLASSES.index(kclass), ctypes.byref(ms),
+                                      ctypes.byref(n)))
+    return float(ms.value), int(n.value)
 
 
 def _ptr(t) -> int | None:

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libafqmc_kpt.so")
-SOURCES = ["abi.hip", "greens.hip", "fields.hip", "propagate.hip", "energy.hip", "prepare.hip"]
+SOURCES = ["abi.hip", "greens.hip", "fields.hip", "propagate.hip", "energy.hip", "prepare.hip",
+           "timing.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -261,6 +261,7 @@ static hipError_t launch_exchange(const afqmc_kpt_problem& p, void* xpart, hipSt
   const cpx<double>* Gh = (const cpx<double>*)p.Gh;
   cpx<double>* part = (cpx<double>*)xpart;
   KMesh mesh = make_mesh(p);
+  TimedScope ts(KC_EXCHANGE, s);
   if (KS <= 4)
     hipLaunchKernelGGL((exchange_kernel<T, 4>), dim3((unsigned)grid), dim3(256), 0, s, p.nk, p.m,
                        p.nocc, p.nchol, p.nwalk, mesh, nchunk, Lh, Gh, part);
@@ -284,6 +285,7 @@ hipError_t run_energy(const afqmc_kpt_problem& p, void* E, void* ws, hipStream_t
   e = (p.prec == AFQMC_PREC_FP32) ? launch_exchange<float>(p, xpart, s)
                                   : launch_exchange<double>(p, xpart, s);
   if (e != hipSuccess) return e;
+  TimedScope ts(KC_ENERGY_REST, s);
   hipLaunchKernelGGL(energy_final_kernel, dim3(p.nwalk), dim3(256), 0, s, p.nk, p.m, p.nocc,
                      p.nchol, p.nwalk, make_mesh(p), (const cpx<double>*)p.h1h,
                      (const cpx<double>*)p.Gh, (const cpx<double>*)X,
@@ -506,6 +508,7 @@ static hipError_t launch_bwd_k(const afqmc_kpt_problem& p, const void* gE, void*
   const cpx<T>* Lh = (const cpx<T>*)(sizeof(T) == 8 ? p.Lh : p.Lh32);
   const int MT = (p.m + 15) / 16;
   KMesh mesh = make_mesh(p);
+  TimedScope ts(KC_EXCHANGE_BWD, s);
 #define AFQMC_BWD(MTV)                                                                        \
   hipLaunchKernelGGL((exchange_bwd_kernel<T, KSMAX, MTV>), grid, dim3(256), 0, s, p.nk, p.m,     \
                      p.nocc, p.nchol, p.nwalk, mesh, nchunk, Lh, (const cpx<double>*)p.Lh,      \

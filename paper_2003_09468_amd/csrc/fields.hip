@@ -106,6 +106,7 @@ static hipError_t launch_vbias_gemm(const afqmc_kpt_problem& p, void* parts, hip
 // X (and optionally xbar) for the current Gh.
 hipError_t launch_cholesky_trace_x(const afqmc_kpt_problem& p, void* X, void* xbar, void* parts,
                                    hipStream_t s) {
+  TimedScope ts(KC_VBIAS, s);
   hipError_t e = (p.prec == AFQMC_PREC_FP32) ? launch_vbias_gemm<float>(p, parts, s)
                                              : launch_vbias_gemm<double>(p, parts, s);
   if (e != hipSuccess) return e;
@@ -185,6 +186,7 @@ struct OpVhs {
 template <typename T>
 static hipError_t launch_vhs_typed(const afqmc_kpt_problem& p, const double* x, const void* xbar,
                                    void* vhs, void* zeta, hipStream_t s) {
+  TimedScope ts(KC_VHS, s);
   const int64_t total = (int64_t)p.nwalk * p.nk * p.nchol;
   hipLaunchKernelGGL(field_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
                      p.nwalk, p.nk, p.nchol, make_mesh(p), x, (const cpx<double>*)xbar,

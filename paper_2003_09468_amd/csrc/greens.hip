@@ -358,6 +358,7 @@ hipError_t run_greens(const afqmc_kpt_problem& p, void* ws, bool write_logdet_ne
   Carve c(ws);
   GreensWs g;
   carve_greens(c, dims_of(p), g);
+  TimedScope ts(KC_GREENS, s);
   hipError_t e = launch_small_gj(p, GJ_MODE_GREENS, nullptr, g.oinvT,
                                  write_logdet_new_only ? g.logdet_new : p.logdet, s);
   if (e != hipSuccess) return e;
@@ -418,6 +419,7 @@ __global__ __launch_bounds__(256) void weight_kernel(int64_t nf, const double* _
 hipError_t launch_weights(const afqmc_kpt_problem& p, const double* x, const void* xbar,
                           const void* logdet_new, hipStream_t s) {
   const int64_t nf = (int64_t)p.nk * p.nchol * 2;
+  TimedScope ts(KC_WEIGHTS, s);
   hipLaunchKernelGGL(weight_kernel, dim3(p.nwalk), dim3(256), 0, s, nf, x,
                      (const cpx<double>*)xbar, (cpx<double>*)p.logdet,
                      (const cpx<double>*)logdet_new, p.weight, p.status);

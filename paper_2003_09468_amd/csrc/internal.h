@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "../../include/afqmc_kpt.h"
+#include "timing.h"
 
 namespace afqmc {
 

@@ -89,6 +89,7 @@ static hipError_t launch_bhalf(const afqmc_kpt_problem& p, const void* in, void*
   op.in = (const cpx<double>*)in;
   op.out = (cpx<double>*)out;
   op.outT = (cpx<TO>*)outT;
+  TimedScope ts(KC_BHALF, s);
   if (p.m <= 16) return launch_cgemm<16, 64, 16, 1, 4>(op, s);
   return launch_cgemm<32, 64, 16, 2, 2>(op, s);
 }
@@ -104,6 +105,7 @@ static hipError_t launch_taylor(const afqmc_kpt_problem& p, const void* vhs, con
   op.Tin = (const cpx<T>*)tin;
   op.Tout = (cpx<T>*)tout;
   op.acc = (cpx<double>*)acc;
+  TimedScope ts(KC_TAYLOR, s);
   return launch_cgemm<64, 64, 16, 2, 2>(op, s);
 }
 
@@ -238,6 +240,7 @@ hipError_t run_ortho(const afqmc_kpt_problem& p, void* ws, hipStream_t s) {
   hipError_t e;
   // pass 0: U -> Ut, pass 1: Ut -> U
   for (int pass = 0; pass < 2; ++pass) {
+    TimedScope ts(KC_ORTHO, s);
     const cpx<double>* src = (const cpx<double>*)(pass == 0 ? p.U : Ut);
     cpx<double>* dst = (cpx<double>*)(pass == 0 ? Ut : p.U);
     OpGram gm;
