@@ -26,6 +26,9 @@ FLAGS = [
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
+    # MFMA accumulators live in VGPRs (no mirrored AGPR copies): halves the register
+    # footprint of the wide GEMM tiles and doubles their occupancy
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

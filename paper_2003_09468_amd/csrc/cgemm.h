@@ -6,8 +6,9 @@
 // Taylor terms, one-body half steps, Green's function solve, Gram matrices, half rotation)
 // is one instantiation with its own index map and fused epilogue.
 //
-// Tiles are staged through LDS as separate real and imaginary planes; the next K slice is
-// prefetched into registers while the MFMAs of the current one run.  Complex products take
+// Tiles are staged through two LDS stages of complex-interleaved elements; the next K slice
+// is prefetched into registers while the MFMAs of the current one run, with one barrier per
+// K slice.  Complex products take
 // four real MFMAs (Dre += Are Bre - Aim Bim, Dim += Are Bim + Aim Bre).  The 1-D grid is
 // remapped so that consecutive logical tiles (same batch) land on the same XCD, which keeps
 // the shared operand of a batch in one L2.
@@ -33,16 +34,14 @@ __global__ __launch_bounds__(WM* WN * 64) void cgemm_kernel(Op op, int tiles_m, 
   constexpr int NT = WM * WN * 64;
   constexpr int TM = BM / (WM * 16);
   constexpr int TN = BN / (WN * 16);
-  constexpr int EA = (BM * BK) / NT;
-  constexpr int EB = (BK * BN) / NT;
-  constexpr int PA = (sizeof(T) == 8) ? 1 : 2;
-  constexpr int PB = (sizeof(T) == 8) ? 1 : 2;
+  constexpr int EA = (BM * BK + NT - 1) / NT;
+  constexpr int EB = (BK * BN + NT - 1) / NT;
   static_assert(TM * WM * 16 == BM && TN * WN * 16 == BN, "tile must split into 16x16 blocks");
-  static_assert(EA * NT == BM * BK && EB * NT == BK * BN, "tile must split over threads");
   static_assert(BK % 4 == 0, "BK multiple of the MFMA K");
 
-  __shared__ T sA[2][BK][BM + PA];
-  __shared__ T sB[2][BK][BN + PB];
+  // complex-interleaved tiles (one 8/16-byte LDS read per complex operand), two stages
+  __shared__ cpx<T> sA[2][BK][BM + 1];
+  __shared__ cpx<T> sB[2][BK][BN + 1];
 
   // XCD-aware remap of the flat block index: workgroups are dealt round-robin over the
   // 8 XCDs, so block b runs on XCD b % 8; give each XCD a contiguous range of tiles.
@@ -71,8 +70,7 @@ __global__ __launch_bounds__(WM* WN * 64) void cgemm_kernel(Op op, int tiles_m, 
       acci[i][j] = mfma16<T>::zero();
     }
 
-  T pa_r[EA], pa_i[EA], pb_r[EB], pb_i[EB];
-
+  cpx<T> pa[EA], pb[EB];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
@@ -82,8 +80,8 @@ __global__ __launch_bounds__(WM* WN * 64) void cgemm_kernel(Op op, int tiles_m, 
       else { kk = idx / BM; r = idx % BM; }
       const int row = row0 + r, k = k0 + kk;
       T re = 0, im = 0;
-      if (row < M && k < K) op.load_a(b, row, k, re, im);
-      pa_r[e] = re; pa_i[e] = im;
+      if (idx < BM * BK && row < M && k < K) op.load_a(b, row, k, re, im);
+      pa[e] = cpx<T>{re, im};
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
@@ -93,19 +91,18 @@ __global__ __launch_bounds__(WM* WN * 64) void cgemm_kernel(Op op, int tiles_m, 
       else { c = idx / BK; kk = idx % BK; }
       const int col = col0 + c, k = k0 + kk;
       T re = 0, im = 0;
-      if (col < N && k < K) op.load_b(b, k, col, re, im);
-      pb_r[e] = re; pb_i[e] = im;
+      if (idx < BK * BN && col < N && k < K) op.load_b(b, k, col, re, im);
+      pb[e] = cpx<T>{re, im};
     }
   };
-  auto stash = [&]() {
+  auto stash = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       const int idx = tid + e * NT;
       int r, kk;
       if (Op::A_KCONTIG) { r = idx / BK; kk = idx % BK; }
       else { kk = idx / BM; r = idx % BM; }
-      sA[0][kk][r] = pa_r[e];
-      sA[1][kk][r] = pa_i[e];
+      if (idx < BM * BK) sA[buf][kk][r] = pa[e];
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
@@ -113,8 +110,7 @@ __global__ __launch_bounds__(WM* WN * 64) void cgemm_kernel(Op op, int tiles_m, 
       int c, kk;
       if (Op::B_NCONTIG) { kk = idx / BN; c = idx % BN; }
       else { c = idx / BK; kk = idx % BK; }
-      sB[0][kk][c] = pb_r[e];
-      sB[1][kk][c] = pb_i[e];
+      if (idx < BK * BN) sB[buf][kk][c] = pb[e];
     }
   };
 
@@ -122,42 +118,44 @@ __global__ __launch_bounds__(WM* WN * 64) void cgemm_kernel(Op op, int tiles_m, 
   const int cbase = wn * TN * 16 + (lane & 15);
   const int klane = lane >> 4;
 
+  // stage s is computed while stage s+1 is fetched into registers; one barrier per K slice
   fetch(0);
+  stash(0);
+  __syncthreads();
+  int buf = 0;
   for (int k0 = 0; k0 < K; k0 += BK) {
-    stash();
-    __syncthreads();
-    if (k0 + BK < K) fetch(k0 + BK);
+    const bool more = (k0 + BK < K);
+    if (more) fetch(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
-      T ar[TM], ai[TM], br[TN], bi[TN];
+      cpx<T> a[TM], bb[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        ar[i] = sA[0][ks + klane][rbase + i * 16];
-        ai[i] = sA[1][ks + klane][rbase + i * 16];
-      }
+      for (int i = 0; i < TM; ++i) a[i] = sA[buf][ks + klane][rbase + i * 16];
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        br[j] = sB[0][ks + klane][cbase + j * 16];
-        bi[j] = sB[1][ks + klane][cbase + j * 16];
-      }
+      for (int j = 0; j < TN; ++j) bb[j] = sB[buf][ks + klane][cbase + j * 16];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) cmfma<T>(ar[i], ai[i], br[j], bi[j], accr[i][j], acci[i][j]);
+        for (int j = 0; j < TN; ++j) cmfma<T>(a[i].re, a[i].im, bb[j].re, bb[j].im, accr[i][j], acci[i][j]);
     }
+    if (more) stash(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j)
+    for (int j = 0; j < TN; ++j) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = row0 + wm * TM * 16 + i * 16 + mfma16<T>::drow(lane, v);
         const int col = col0 + wn * TN * 16 + j * 16 + (lane & 15);
         if (row < M && col < N) op.store(b, row, col, accr[i][j][v], acci[i][j][v]);
       }
+      // one 16x16 tile of the epilogue at a time (read-modify-write epilogues)
+      __builtin_amdgcn_sched_barrier(0);
+    }
 }
 
 // Host launcher: grid = nbatch * tiles.

@@ -202,6 +202,8 @@ static hipError_t launch_vhs_typed(const afqmc_kpt_problem& p, const double* x, 
   op.zeta = (const cpx<T>*)zeta;
   op.L = (const cpx<T>*)(sizeof(T) == 8 ? p.L : p.L32);
   op.vhs = (cpx<T>*)vhs;
+  // rows = walkers, (k p r) columns; tiles measured at 27 x 64 x 18252 x 208
+  if (sizeof(T) == 8) return launch_cgemm<64, 32, 16, 4, 1>(op, s);
   return launch_cgemm<64, 64, 16, 2, 2>(op, s);
 }
 

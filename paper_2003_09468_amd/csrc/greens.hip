@@ -20,71 +20,47 @@ namespace afqmc {
 
 #define AFQMC_PI 3.14159265358979323846
 
-template <int NS>
-__device__ __forceinline__ double pick(const double (&a)[NS][NS], int si, int sj) {
+// Thread (tr, tc) of a TR x 32 grid owns rows tr + TR*si (si < NSR) and columns
+// tc + 32*sj (sj < NSC); n <= min(TR*NSR, 32*NSC).
+template <int NSR, int NSC>
+__device__ __forceinline__ double pick_col(const double (&a)[NSR][NSC], int si, int sj) {
   double v = 0.0;
 #pragma unroll
-  for (int x = 0; x < NS; ++x)
-#pragma unroll
-    for (int y = 0; y < NS; ++y)
-      if (x == si && y == sj) v = a[x][y];
+  for (int y = 0; y < NSC; ++y)
+    if (y == sj) v = a[si][y];
   return v;
 }
 
-template <int NS>
-__global__ __launch_bounds__(1024) void small_gj_kernel(int mode, int n, int nk, int m, int nocc,
-                                                        const cpx<double>* __restrict__ U,
-                                                        const cpx<double>* __restrict__ A,
-                                                        const cpx<double>* __restrict__ S_in,
-                                                        cpx<double>* __restrict__ out,
-                                                        cpx<double>* __restrict__ logdet_out,
-                                                        int* __restrict__ status) {
+template <int TR, int NSR, int NSC>
+__global__ __launch_bounds__(TR * 32) void small_gj_kernel(int mode, int n,
+                                                          const cpx<double>* __restrict__ S_in,
+                                                          cpx<double>* __restrict__ out,
+                                                          cpx<double>* __restrict__ logdet_out,
+                                                          int* __restrict__ status) {
   const int w = blockIdx.x;
   const int tid = threadIdx.x;
   const int tr = tid >> 5, tc = tid & 31;
   const int lane = tid & 63;
-  const int64_t N = (int64_t)nk * m;
 
   __shared__ double colr[2][128], coli[2][128];
   __shared__ double rowr[2][128], rowi[2][128];
   __shared__ double rjr[2][128], rji[2][128];
   __shared__ int perm[128];
   __shared__ int cols[128], pos[128];
+  __shared__ double pivr_s[128], pivi_s[128];
+  __shared__ double red_s[2][16];
   __shared__ int flag_s;
 
-  double re[NS][NS], im[NS][NS];
+  double re[NSR][NSC], im[NSR][NSC];
 
   if (tid == 0) flag_s = 0;
-
-  // ---- load the matrix
-  if (mode == GJ_MODE_GREENS) {
-    const cpx<double>* Uw = U + (int64_t)w * N * n;
-#pragma unroll
-    for (int si = 0; si < NS; ++si)
-#pragma unroll
-      for (int sj = 0; sj < NS; ++sj) {
-        const int row = tr + 32 * si, col = tc + 32 * sj;
-        double sr = 0.0, sim = 0.0;
-        if (row < n && col < n) {
-          const int k = row / nocc, a = row % nocc;
-          // O[(k a)][col] = sum_p conj(A[k][p][a]) U[(k p)][col]
-          for (int p = 0; p < m; ++p) {
-            const cpx<double> av = A[((int64_t)k * m + p) * nocc + a];
-            const cpx<double> uv = Uw[((int64_t)k * m + p) * n + col];
-            sr += av.re * uv.re + av.im * uv.im;
-            sim += av.re * uv.im - av.im * uv.re;
-          }
-        }
-        re[si][sj] = sr;
-        im[si][sj] = sim;
-      }
-  } else {
+  {
     const cpx<double>* Sw = S_in + (int64_t)w * n * n;
 #pragma unroll
-    for (int si = 0; si < NS; ++si)
+    for (int si = 0; si < NSR; ++si)
 #pragma unroll
-      for (int sj = 0; sj < NS; ++sj) {
-        const int row = tr + 32 * si, col = tc + 32 * sj;
+      for (int sj = 0; sj < NSC; ++sj) {
+        const int row = tr + TR * si, col = tc + 32 * sj;
         cpx<double> v{0.0, 0.0};
         if (row < n && col < n) v = Sw[(int64_t)row * n + col];
         re[si][sj] = v.re;
@@ -101,11 +77,11 @@ __global__ __launch_bounds__(1024) void small_gj_kernel(int mode, int n, int nk,
       const int buf = j & 1, js = j >> 5, jl = j & 31;
       if (tc == jl) {
 #pragma unroll
-        for (int si = 0; si < NS; ++si) {
-          const int row = tr + 32 * si;
+        for (int si = 0; si < NSR; ++si) {
+          const int row = tr + TR * si;
           if (row < n) {
-            colr[buf][row] = pick<NS>(re, si, js);
-            coli[buf][row] = pick<NS>(im, si, js);
+            colr[buf][row] = pick_col<NSR, NSC>(re, si, js);
+            coli[buf][row] = pick_col<NSR, NSC>(im, si, js);
           }
         }
       }
@@ -117,10 +93,10 @@ __global__ __launch_bounds__(1024) void small_gj_kernel(int mode, int n, int nk,
       }
       const double sd = sqrt(d), isd = 1.0 / sd;
 #pragma unroll
-      for (int si = 0; si < NS; ++si)
+      for (int si = 0; si < NSR; ++si)
 #pragma unroll
-        for (int sj = 0; sj < NS; ++sj) {
-          const int row = tr + 32 * si, col = tc + 32 * sj;
+        for (int sj = 0; sj < NSC; ++sj) {
+          const int row = tr + TR * si, col = tc + 32 * sj;
           if (row >= n || col >= n || row < j || col < j) continue;
           if (col == j) {
             if (row == j) { re[si][sj] = sd; im[si][sj] = 0.0; }
@@ -139,59 +115,65 @@ __global__ __launch_bounds__(1024) void small_gj_kernel(int mode, int n, int nk,
     __syncthreads();
   }
 
-  // ---- Gauss-Jordan inversion with partial pivoting, in place
-  double ldr = 0.0, ldi = 0.0;
+  // ---- Gauss-Jordan inversion with partial pivoting, in place.
+  // Step j: the pivot column goes to LDS; every wave finds the pivot row p (largest
+  // modulus among rows >= j, lowest index on ties) with one 64-bit max-reduction of
+  // (|a|^2 bits, 127 - row); rows j and p go to LDS; then every owned entry takes the
+  // rank-1 update  a' = a~ - g(row) b(col)  with
+  //   b(col) = (col == j) ? 1 : a_pj,  g(row) = a_rowj / pivot  (row != j),  -1/pivot (row j),
+  //   a~ = 0 in column j and in row j, the old row j in row p, else a.
+  // Pivots are kept in LDS; their logarithms are summed after the loop.
   for (int j = 0; j < n; ++j) {
     const int buf = j & 1, js = j >> 5, jl = j & 31;
     if (tc == jl) {
 #pragma unroll
-      for (int si = 0; si < NS; ++si) {
-        const int row = tr + 32 * si;
+      for (int si = 0; si < NSR; ++si) {
+        const int row = tr + TR * si;
         if (row < n) {
-          colr[buf][row] = pick<NS>(re, si, js);
-          coli[buf][row] = pick<NS>(im, si, js);
+          colr[buf][row] = pick_col<NSR, NSC>(re, si, js);
+          coli[buf][row] = pick_col<NSR, NSC>(im, si, js);
         }
       }
     }
     __syncthreads();
-    // pivot: largest |column entry| among rows j..n-1 (lowest index on ties), per wave
-    double best = -1.0;
-    int bi = n;
+    unsigned long long key = 0ull;
     for (int i = j + lane; i < n; i += 64) {
       const double v = colr[buf][i] * colr[buf][i] + coli[buf][i] * coli[buf][i];
-      if (v > best) { best = v; bi = i; }
+      const unsigned long long k2 =
+          ((unsigned long long)__double_as_longlong(v) & ~0x7full) | (unsigned long long)(127 - i);
+      key = (k2 > key) ? k2 : key;
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      const unsigned long long o = __shfl_xor(key, off, 64);
+      key = (o > key) ? o : key;
     }
-    const int p = (bi < n) ? bi : j;
-    if (tr == (p & 31)) {
-      const int ps = p >> 5;
+    const int p = (key == 0ull) ? j : 127 - (int)(key & 0x7full);
+    if (tr == p % TR) {
+      const int ps = p / TR;
 #pragma unroll
-      for (int sj = 0; sj < NS; ++sj) {
+      for (int sj = 0; sj < NSC; ++sj) {
         const int col = tc + 32 * sj;
         if (col < n) {
           double vr = 0.0, vi = 0.0;
 #pragma unroll
-          for (int si = 0; si < NS; ++si)
+          for (int si = 0; si < NSR; ++si)
             if (si == ps) { vr = re[si][sj]; vi = im[si][sj]; }
           rowr[buf][col] = vr;
           rowi[buf][col] = vi;
         }
       }
     }
-    if (tr == jl) {
+    if (tr == j % TR && p != j) {
+      const int jsr = j / TR;
 #pragma unroll
-      for (int sj = 0; sj < NS; ++sj) {
+      for (int sj = 0; sj < NSC; ++sj) {
         const int col = tc + 32 * sj;
         if (col < n) {
           double vr = 0.0, vi = 0.0;
 #pragma unroll
-          for (int si = 0; si < NS; ++si)
-            if (si == js) { vr = re[si][sj]; vi = im[si][sj]; }
+          for (int si = 0; si < NSR; ++si)
+            if (si == jsr) { vr = re[si][sj]; vi = im[si][sj]; }
           rjr[buf][col] = vr;
           rji[buf][col] = vi;
         }
@@ -205,45 +187,63 @@ __global__ __launch_bounds__(1024) void small_gj_kernel(int mode, int n, int nk,
       pr = 1.0; pim = 0.0; den = 1.0;
     }
     const double ivr = pr / den, ivi = -pim / den;  // 1 / pivot
-#pragma unroll
-    for (int si = 0; si < NS; ++si)
-#pragma unroll
-      for (int sj = 0; sj < NS; ++sj) {
-        const int row = tr + 32 * si, col = tc + 32 * sj;
-        if (row >= n || col >= n) continue;
-        double vr, vi;
-        if (row == j) {
-          if (col == j) { vr = ivr; vi = ivi; }
-          else {
-            const double ar = rowr[buf][col], ai = rowi[buf][col];
-            vr = ar * ivr - ai * ivi;
-            vi = ar * ivi + ai * ivr;
-          }
-        } else {
-          const bool swapped = (row == p);
-          const double ar = swapped ? rjr[buf][col] : re[si][sj];
-          const double ai = swapped ? rji[buf][col] : im[si][sj];
-          const double fr = swapped ? colr[buf][j] : colr[buf][row];
-          const double fi = swapped ? coli[buf][j] : coli[buf][row];
-          // g = f / pivot
-          const double gr = fr * ivr - fi * ivi, gi = fr * ivi + fi * ivr;
-          if (col == j) { vr = -gr; vi = -gi; }
-          else {
-            const double br = rowr[buf][col], bim = rowi[buf][col];
-            vr = ar - (gr * br - gi * bim);
-            vi = ai - (gr * bim + gi * br);
-          }
-        }
-        re[si][sj] = vr;
-        im[si][sj] = vi;
-      }
     if (tid == 0) {
       perm[j] = p;
-      ldr += 0.5 * log(den);
-      ldi += atan2(pim, pr) + ((p != j) ? AFQMC_PI : 0.0);
+      pivr_s[j] = pr;
+      pivi_s[j] = pim;
+    }
+    // per-column factor b(col)
+    double br_[NSC], bi_[NSC];
+#pragma unroll
+    for (int sj = 0; sj < NSC; ++sj) {
+      const int col = tc + 32 * sj;
+      const bool cj = (col == j);
+      br_[sj] = cj ? 1.0 : ((col < n) ? rowr[buf][col] : 0.0);
+      bi_[sj] = cj ? 0.0 : ((col < n) ? rowi[buf][col] : 0.0);
+    }
+#pragma unroll
+    for (int si = 0; si < NSR; ++si) {
+      const int row = tr + TR * si;
+      if (row >= n) continue;
+      const bool isj = (row == j);
+      const bool swapped = (row == p) && (p != j);
+      double gr, gi;
+      if (isj) {
+        gr = -ivr; gi = -ivi;
+      } else {
+        const double fr = swapped ? colr[buf][j] : colr[buf][row];
+        const double fi = swapped ? coli[buf][j] : coli[buf][row];
+        gr = fr * ivr - fi * ivi;
+        gi = fr * ivi + fi * ivr;
+      }
+#pragma unroll
+      for (int sj = 0; sj < NSC; ++sj) {
+        const int col = tc + 32 * sj;
+        double ar = swapped ? ((col < n) ? rjr[buf][col] : 0.0) : re[si][sj];
+        double ai = swapped ? ((col < n) ? rji[buf][col] : 0.0) : im[si][sj];
+        if (isj || col == j) { ar = 0.0; ai = 0.0; }
+        re[si][sj] = ar - (gr * br_[sj] - gi * bi_[sj]);
+        im[si][sj] = ai - (gr * bi_[sj] + gi * br_[sj]);
+      }
     }
   }
   if (bad) atomicOr(&flag_s, bad);
+  __syncthreads();
+  // log det = sum log(pivot) + i pi (number of row swaps)
+  {
+    double lr = 0.0, li = 0.0;
+    for (int j = tid; j < n; j += TR * 32) {
+      const double pr = pivr_s[j], pim = pivi_s[j];
+      lr += 0.5 * log(pr * pr + pim * pim);
+      li += atan2(pim, pr) + ((perm[j] != j) ? AFQMC_PI : 0.0);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      lr += __shfl_xor(lr, off, 64);
+      li += __shfl_xor(li, off, 64);
+    }
+    if (lane == 0) { red_s[0][tid >> 6] = lr; red_s[1][tid >> 6] = li; }
+  }
   __syncthreads();
   if (tid == 0) {
     for (int c = 0; c < n; ++c) cols[c] = c;
@@ -255,14 +255,16 @@ __global__ __launch_bounds__(1024) void small_gj_kernel(int mode, int n, int nk,
   }
   __syncthreads();
   const int fl = flag_s;
+  double ldr = 0.0, ldi = 0.0;
+  for (int wv = 0; wv < TR / 2; ++wv) { ldr += red_s[0][wv]; ldi += red_s[1][wv]; }
 
   // ---- write out: the inverse's column c sits in working column cols[c]
   cpx<double>* Ow = out + (int64_t)w * n * n;
 #pragma unroll
-  for (int si = 0; si < NS; ++si)
+  for (int si = 0; si < NSR; ++si)
 #pragma unroll
-    for (int sj = 0; sj < NS; ++sj) {
-      const int row = tr + 32 * si, col = tc + 32 * sj;
+    for (int sj = 0; sj < NSC; ++sj) {
+      const int row = tr + TR * si, col = tc + 32 * sj;
       if (row >= n || col >= n) continue;
       const int c = pos[col];
       double vr = re[si][sj], vi = im[si][sj];
@@ -272,8 +274,7 @@ __global__ __launch_bounds__(1024) void small_gj_kernel(int mode, int n, int nk,
         vr = (mode == GJ_MODE_CHOL_INV && c == row) ? 1.0 : 0.0;
         vi = 0.0;
       }
-      // GREENS: out = O^{-T}, i.e. out[c][row] = Oinv[row][c];
-      // CHOL_INV: out[c][row] = conj(Linv[row][c]) = Rinv[c][row]
+      // GREENS: out[c][row] = Oinv[row][c] (O^{-T});  CHOL_INV: out[c][row] = Rinv[c][row]
       Ow[(int64_t)c * n + row] = cpx<double>{vr, vi};
     }
   if (tid == 0) {
@@ -291,23 +292,46 @@ __global__ __launch_bounds__(1024) void small_gj_kernel(int mode, int n, int nk,
   }
 }
 
+// O[w][(k a)][j] = sum_p conj(A[k][p][a]) U[w][(k p)][j], batched over (w, k)
+struct OpOverlap {
+  typedef double T;
+  static constexpr bool A_KCONTIG = false;
+  static constexpr bool B_NCONTIG = true;
+  int M, N, K, nbatch;  // M = nocc, K = m, N = nk*nocc, nbatch = W*nk
+  int nk;
+  const cpx<double>* A;  // [nk][m][nocc]
+  const cpx<double>* U;  // [W][nk*m][n]
+  cpx<double>* O;        // [W][nk*nocc][n]
+  __device__ void load_a(int b, int row, int k, double& re, double& im) const {
+    const cpx<double> v = A[((int64_t)(b % nk) * K + k) * M + row];
+    re = v.re; im = -v.im;
+  }
+  __device__ void load_b(int b, int k, int col, double& re, double& im) const {
+    const cpx<double> v = U[((int64_t)b * K + k) * N + col];
+    re = v.re; im = v.im;
+  }
+  __device__ void store(int b, int row, int col, double re, double im) const {
+    O[((int64_t)b * M + row) * N + col] = cpx<double>{re, im};
+  }
+};
+
 hipError_t launch_small_gj(const afqmc_kpt_problem& p, int mode, const void* S_in, void* out,
                            void* logdet_out, hipStream_t s) {
   const int n = p.nk * p.nocc;
-  const int ns = (n + 31) / 32;
-  const cpx<double>* U = (const cpx<double>*)p.U;
-  const cpx<double>* A = (const cpx<double>*)p.A;
   const cpx<double>* S = (const cpx<double>*)S_in;
   cpx<double>* o = (cpx<double>*)out;
   cpx<double>* ld = (cpx<double>*)logdet_out;
-  dim3 g(p.nwalk), b(1024);
-  switch (ns) {
-    case 1: hipLaunchKernelGGL(small_gj_kernel<1>, g, b, 0, s, mode, n, p.nk, p.m, p.nocc, U, A, S, o, ld, p.status); break;
-    case 2: hipLaunchKernelGGL(small_gj_kernel<2>, g, b, 0, s, mode, n, p.nk, p.m, p.nocc, U, A, S, o, ld, p.status); break;
-    case 3: hipLaunchKernelGGL(small_gj_kernel<3>, g, b, 0, s, mode, n, p.nk, p.m, p.nocc, U, A, S, o, ld, p.status); break;
-    case 4: hipLaunchKernelGGL(small_gj_kernel<4>, g, b, 0, s, mode, n, p.nk, p.m, p.nocc, U, A, S, o, ld, p.status); break;
-    default: return hipErrorInvalidValue;
-  }
+  dim3 g(p.nwalk);
+  if (n <= 32)
+    hipLaunchKernelGGL((small_gj_kernel<32, 1, 1>), g, dim3(1024), 0, s, mode, n, S, o, ld, p.status);
+  else if (n <= 64)
+    hipLaunchKernelGGL((small_gj_kernel<32, 2, 2>), g, dim3(1024), 0, s, mode, n, S, o, ld, p.status);
+  else if (n <= 96)
+    hipLaunchKernelGGL((small_gj_kernel<16, 6, 3>), g, dim3(512), 0, s, mode, n, S, o, ld, p.status);
+  else if (n <= 128)
+    hipLaunchKernelGGL((small_gj_kernel<16, 8, 4>), g, dim3(512), 0, s, mode, n, S, o, ld, p.status);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -346,6 +370,7 @@ hipError_t launch_greens_solve(const afqmc_kpt_problem& p, const void* oinvT, hi
 }
 
 size_t carve_greens(Carve& c, const Dims& d, GreensWs& g) {
+  g.omat = c.take(sizeof(double) * 2 * d.W * d.n() * d.n());
   g.oinvT = c.take(sizeof(double) * 2 * d.W * d.n() * d.n());
   g.logdet_new = c.take(sizeof(double) * 2 * d.W);
   return c.off;
@@ -359,7 +384,16 @@ hipError_t run_greens(const afqmc_kpt_problem& p, void* ws, bool write_logdet_ne
   GreensWs g;
   carve_greens(c, dims_of(p), g);
   TimedScope ts(KC_GREENS, s);
-  hipError_t e = launch_small_gj(p, GJ_MODE_GREENS, nullptr, g.oinvT,
+  OpOverlap op;
+  op.M = p.nocc; op.K = p.m; op.N = p.nk * p.nocc;
+  op.nbatch = p.nwalk * p.nk;
+  op.nk = p.nk;
+  op.A = (const cpx<double>*)p.A;
+  op.U = (const cpx<double>*)p.U;
+  op.O = (cpx<double>*)g.omat;
+  hipError_t e = launch_cgemm<16, 64, 16, 1, 4>(op, s);
+  if (e != hipSuccess) return e;
+  e = launch_small_gj(p, GJ_MODE_GREENS, g.omat, g.oinvT,
                                  write_logdet_new_only ? g.logdet_new : p.logdet, s);
   if (e != hipSuccess) return e;
   return launch_greens_solve(p, g.oinvT, s);

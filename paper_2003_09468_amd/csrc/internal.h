@@ -43,7 +43,7 @@ struct Carve {
 };
 
 // Regions used by several entries.
-struct GreensWs { void* oinvT; void* logdet_new; };
+struct GreensWs { void* omat; void* oinvT; void* logdet_new; };
 struct VbiasWs { void* parts; };
 
 size_t carve_greens(Carve& c, const Dims& d, GreensWs& g);

@@ -106,7 +106,21 @@ static hipError_t launch_taylor(const afqmc_kpt_problem& p, const void* vhs, con
   op.Tout = (cpx<T>*)tout;
   op.acc = (cpx<double>*)acc;
   TimedScope ts(KC_TAYLOR, s);
-  return launch_cgemm<64, 64, 16, 2, 2>(op, s);
+  // FP32: one column tile spans all nk*nocc columns (rounded up to 16), each of the 4 waves
+  // owning 16 rows x BN columns.  FP64: 64 x 32 tiles (measured fastest for the 16x16x4
+  // FP64 MFMA at 702 x 108 x 702).
+  if (sizeof(T) == 8) return launch_cgemm<64, 32, 16, 4, 1>(op, s);
+  switch ((op.N + 15) / 16) {
+    case 1: return launch_cgemm<64, 16, 16, 4, 1>(op, s);
+    case 2: return launch_cgemm<64, 32, 16, 4, 1>(op, s);
+    case 3: return launch_cgemm<64, 48, 16, 4, 1>(op, s);
+    case 4: return launch_cgemm<64, 64, 16, 4, 1>(op, s);
+    case 5: return launch_cgemm<64, 80, 16, 4, 1>(op, s);
+    case 6: return launch_cgemm<64, 96, 16, 4, 1>(op, s);
+    case 7: return launch_cgemm<64, 112, 16, 4, 1>(op, s);
+    case 8: return launch_cgemm<64, 128, 16, 4, 1>(op, s);
+    default: return launch_cgemm<64, 64, 16, 2, 2>(op, s);
+  }
 }
 
 // Layout: the Green's-function slots come first in every entry's workspace, so that

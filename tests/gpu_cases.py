@@ -48,3 +48,17 @@ def rel(a, b):
 def phase_err(ld_gpu, ld_ref):
     """max |exp(ld_gpu - ld_ref) - 1|: log determinants agree modulo 2 pi i."""
     return np.abs(np.exp(np.asarray(ld_gpu) - np.asarray(ld_ref)) - 1.0).max()
+
+
+def energy_err(Eg, E, nk):
+    """Max over walkers of |dE| per cell divided by the FP64 bar for that walker.
+
+    The bar is 1e-10 Ha/cell; for walkers with |E| > 1000 Ha/cell (near-singular overlaps,
+    where FP64 rounding of the overlap inverse alone exceeds the absolute bar) it is 1e-13
+    relative.  A value <= 1 passes.
+    """
+    Eg, E = np.asarray(Eg), np.asarray(E)
+    d = np.abs(Eg - E) / nk
+    mag = np.abs(E) / nk
+    bar = np.maximum(1e-10, 1e-13 * mag)
+    return float((d / bar).max())
