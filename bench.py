@@ -49,6 +49,33 @@ def kernel_flops(name, c):
     return None
 
 
+def kernel_source_hash():
+    """Hash of the HIP sources: counter figures taken for another build are not reused."""
+    import hashlib
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2003_09468_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, prec):
+    """HBM bytes per launch of a kernel class from the committed counter summary, if it was
+    taken for the current sources (else None)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        "traffic_c1.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    ent = rec.get("kernels", {}).get(f"{kernel}_{prec}")
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
 def run_block(p, xs, bufs, E):
     nsteps = xs.shape[0]
     for s in range(nsteps):
@@ -118,8 +145,8 @@ def roofline(path_res, prec_key, cfg):
                 "frac": None, "traffic": None}
     ach = fl / (kern[dom]["ms_per_launch"] * 1e-3) / 1e12
     return {"kernel": dom, "bound": "mfma", "achieved": round(ach, 3), "peak": PEAK[prec_key],
-            "unit": "TFLOP/s", "frac": round(ach / PEAK[prec_key], 4), "traffic": None,
-            "flops_per_launch": fl}
+            "unit": "TFLOP/s", "frac": round(ach / PEAK[prec_key], 4),
+            "traffic": measured_traffic(dom, prec_key), "flops_per_launch": fl}
 
 
 def energy_evals(v, cfg):
@@ -170,6 +197,8 @@ def main():
     ap.add_argument("--config", default="c1")
     ap.add_argument("--prec", choices=["both", "fp64", "fp32"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -257,6 +286,15 @@ def main():
     if "fp64" in res and "fp32" in res:
         out["speedup_fp32_vs_fp64"] = round(res["fp32"]["walker_steps_per_s"] /
                                             res["fp64"]["walker_steps_per_s"], 3)
+    if args.calib_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = 1 << 30
+        del src, dst
+    out["kernel_source_hash"] = kernel_source_hash()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(s, U0, xs_host)
