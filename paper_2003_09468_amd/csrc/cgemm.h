@@ -28,7 +28,7 @@ namespace afqmc {
 //   void store(int b, int row, int col, T re, T im) const;    // 0 <= row < M, 0 <= col < N
 
 template <class Op, int BM, int BN, int BK, int WM, int WN>
-__global__ __launch_bounds__(WM* WN * 64) void cgemm_kernel(Op op, int tiles_m, int tiles_n) {
+__device__ __forceinline__ void cgemm_tile(const Op& op, int b, int tm, int tn) {
   typedef typename Op::T T;
   typedef typename mfma16<T>::acc_t acc_t;
   constexpr int NT = WM * WN * 64;
@@ -43,16 +43,6 @@ __global__ __launch_bounds__(WM* WN * 64) void cgemm_kernel(Op op, int tiles_m, 
   __shared__ cpx<T> sA[2][BK][BM + 1];
   __shared__ cpx<T> sB[2][BK][BN + 1];
 
-  // XCD-aware remap of the flat block index: workgroups are dealt round-robin over the
-  // 8 XCDs, so block b runs on XCD b % 8; give each XCD a contiguous range of tiles.
-  const int ntiles = tiles_m * tiles_n;
-  const int64_t total = (int64_t)ntiles * op.nbatch;
-  int64_t bid = blockIdx.x;
-  if ((total & 7) == 0) bid = (bid & 7) * (total >> 3) + (bid >> 3);
-  const int b = (int)(bid / ntiles);
-  const int rem = (int)(bid % ntiles);
-  const int tm = rem / tiles_n;
-  const int tn = rem % tiles_n;
   const int row0 = tm * BM, col0 = tn * BN;
 
   const int tid = threadIdx.x;
@@ -158,14 +148,80 @@ __global__ __launch_bounds__(WM* WN * 64) void cgemm_kernel(Op op, int tiles_m, 
     }
 }
 
-// Host launcher: grid = nbatch * tiles.
+// Up to AFQMC_MAXP problems (systems) in one launch: each problem's index map, its tile
+// grid and the first global tile index of each problem.  Problems are enumerated in the
+// order given (callers put the longest-K problems first).
+#define AFQMC_MAXP 8
+template <class Op>
+struct OpSet {
+  Op op[AFQMC_MAXP];
+  int tiles_m[AFQMC_MAXP], tiles_n[AFQMC_MAXP];
+  long long first[AFQMC_MAXP + 1];
+  int nprob;
+};
+
+// One problem: one workgroup per tile.  Workgroups are dealt round-robin over the 8 XCDs
+// (block i on XCD i % 8); the remap gives each XCD a contiguous range of tiles, so tiles
+// sharing an operand (same batch) stay in one L2.
+template <class Op, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void cgemm_kernel(Op op, int tiles_m, int tiles_n) {
+  const int ntiles = tiles_m * tiles_n;
+  const long long total = (long long)ntiles * op.nbatch;
+  long long bid = blockIdx.x;
+  if ((total & 7) == 0) bid = (bid & 7) * (total >> 3) + (bid >> 3);
+  const int b = (int)(bid / ntiles);
+  const int rem = (int)(bid % ntiles);
+  cgemm_tile<Op, BM, BN, BK, WM, WN>(op, b, rem / tiles_n, rem % tiles_n);
+}
+
+// Several problems in one launch: one workgroup per tile of every problem (the hardware
+// dispatcher hands tiles to CUs as they free up), same XCD remap over the global tile index.
+template <class Op, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void cgemm_set_kernel(const OpSet<Op> set) {
+  const long long total = set.first[set.nprob];
+  long long lt = blockIdx.x;
+  if ((total & 7) == 0) lt = (lt & 7) * (total >> 3) + (lt >> 3);
+  int p = 0;
+  while (p + 1 < set.nprob && lt >= set.first[p + 1]) ++p;
+  p = __builtin_amdgcn_readfirstlane(p);
+  const long long loc = lt - set.first[p];
+  const int ntiles = set.tiles_m[p] * set.tiles_n[p];
+  const int b = (int)(loc / ntiles);
+  const int rem = (int)(loc % ntiles);
+  cgemm_tile<Op, BM, BN, BK, WM, WN>(set.op[p], b, rem / set.tiles_n[p], rem % set.tiles_n[p]);
+}
+
+// Host launcher for a set of problems.
+template <int BM, int BN, int BK, int WM, int WN, class Op>
+hipError_t launch_cgemm_set(OpSet<Op>& set, hipStream_t s) {
+  long long total = 0;
+  for (int p = 0; p < set.nprob; ++p) {
+    const Op& op = set.op[p];
+    set.first[p] = total;
+    if (op.M <= 0 || op.N <= 0 || op.K <= 0 || op.nbatch <= 0) {
+      set.tiles_m[p] = set.tiles_n[p] = 1;
+      continue;
+    }
+    set.tiles_m[p] = (op.M + BM - 1) / BM;
+    set.tiles_n[p] = (op.N + BN - 1) / BN;
+    total += (long long)set.tiles_m[p] * set.tiles_n[p] * op.nbatch;
+  }
+  set.first[set.nprob] = total;
+  if (total == 0) return hipSuccess;
+  if (total > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((cgemm_set_kernel<Op, BM, BN, BK, WM, WN>), dim3((unsigned)total),
+                     dim3(WM * WN * 64), 0, s, set);
+  return hipGetLastError();
+}
+
+// One problem.
 template <int BM, int BN, int BK, int WM, int WN, class Op>
 hipError_t launch_cgemm(const Op& op, hipStream_t s) {
   if (op.M <= 0 || op.N <= 0 || op.K <= 0 || op.nbatch <= 0) return hipSuccess;
   const int tm = (op.M + BM - 1) / BM;
   const int tn = (op.N + BN - 1) / BN;
-  const int64_t total = (int64_t)tm * tn * op.nbatch;
-  if (total > 0x7fffffff) return hipErrorInvalidValue;
+  const long long total = (long long)tm * tn * op.nbatch;
+  if (total > 0x7fffffffLL) return hipErrorInvalidValue;
   hipLaunchKernelGGL((cgemm_kernel<Op, BM, BN, BK, WM, WN>), dim3((unsigned)total),
                      dim3(WM * WN * 64), 0, s, op, tm, tn);
   return hipGetLastError();
