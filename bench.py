@@ -189,12 +189,194 @@ def cpu_baseline(s, U0, xs_host):
                        f"walker-steps/s = 1/(t_step/{nw} + (t_qr/{nw} + t_E)/{nsteps})")}
 
 
+def gen_system(name, torch):
+    from synth.kpt_inputs import config_shapes, make_system, make_walkers, make_fields
+    cfg = config_shapes(name)
+    s, rng = make_system(cfg["mesh"], cfg["m"], cfg["nocc"], cfg["nchol"], seed=cfg["seed"])
+    U0 = make_walkers(s, cfg["nwalk"], rng)
+    xs = make_fields(s, cfg["nwalk"], max(cfg["nsteps"], 1), rng)
+    return cfg, s, U0, xs
+
+
+def bench_batch(args, torch):
+    """Uneven batch: systems A (2x2x2, m=26, 128 walkers), B (3x3x3, m=26, 64 walkers) and
+    C (3x3x3, m=52, nchol=416, 32 walkers), FP64, one block = 10 steps + QR + energy.
+    Modes: each system on its own (three calls per block), one batched call, the batched
+    block captured in a HIP graph, and the graph recaptured after autotuning."""
+    import numpy as np
+    import paper_2003_09468_amd as lib
+    names = ["c3A", "c3B", "c3C"]
+    sysd = []
+    for nm in names:
+        t = time.perf_counter()
+        cfg, s, U0, xs = gen_system(nm, torch)
+        log(f"generated {nm} {cfg} in {time.perf_counter() - t:.1f} s")
+        p = make_problem(s, U0, lib.PREC_FP64, torch)
+        sysd.append((cfg, s, torch.from_numpy(U0).cuda(), torch.from_numpy(xs), p))
+        del s
+    ps = [d[4] for d in sysd]
+    walkers = sum(d[0]["nwalk"] for d in sysd)
+    nsteps = sysd[0][0]["nsteps"]
+    singles = [lib.KptBatch([p]) for p in ps]
+    fsingle = [b.fields([d[3]]) for b, d in zip(singles, sysd)]
+    allb = lib.KptBatch(ps)
+    fall = allb.fields([d[3] for d in sysd])
+
+    def reset_all():
+        for d in sysd:
+            reset(d[4], d[2])
+
+    def run_separate():
+        for b, f in zip(singles, fsingle):
+            b.step(f, ortho=True, energy=True)
+
+    def energies(batches):
+        if batches is allb:
+            return [allb.energy(i).cpu().numpy().copy() for i in range(len(ps))]
+        return [b.energy(0).cpu().numpy().copy() for b in batches]
+
+    graph = {"g": None}
+
+    def run_batched():
+        allb.step(fall, ortho=True, energy=True)
+
+    def run_graph():
+        graph["g"].launch()
+
+    res, Es = {}, {}
+    modes = [("separate", run_separate, singles), ("batched", run_batched, allb),
+             ("graph", run_graph, allb), ("graph_autotuned", run_graph, allb)]
+    for mode, fn, owner in modes:
+        if mode == "graph":
+            graph["g"] = allb.graph(fall, ortho=True, energy=True)
+        if mode == "graph_autotuned":
+            graph["g"].close()
+            reset_all()
+            allb.autotune()
+            graph["g"] = allb.graph(fall, ortho=True, energy=True)
+        reset_all()
+        fn()
+        torch.cuda.synchronize()
+        Es[mode] = energies(owner)
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        lib.timing_enable(True, 1 << 16)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lib.timing_enable(False)
+        kern = {}
+        for kc in lib.KERNEL_CLASSES:
+            ms, n = lib.timing_read(kc)
+            if n:
+                kern[kc] = {"ms_per_block": round(ms / args.steps, 4),
+                            "launches": n // args.steps}
+        dt = (t1 - t0) / args.steps
+        res[mode] = {"ms_per_block": round(dt * 1e3, 3),
+                     "walker_steps_per_s": round(walkers * nsteps / dt, 2), "kernels": kern}
+        log(f"[{mode}] block {dt * 1e3:.2f} ms -> {walkers * nsteps / dt:.1f} walker-steps/s")
+    graph["g"].close()
+    ref = Es["separate"]
+    agree = max(float(np.abs(Es[m][i] - ref[i]).max()) for m in Es for i in range(len(ref)))
+    best = max(res, key=lambda m: res[m]["walker_steps_per_s"])
+    return {
+        "metric": "walker-steps/s, uneven batch of three systems, 10-step block",
+        "value": res[best]["walker_steps_per_s"],
+        "unit": "walker-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res[best]["ms_per_block"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "c3: A mesh 2x2x2 m=26 nchol=208 W=128; B mesh 3x3x3 m=26 "
+                               "nchol=208 W=64; C mesh 3x3x3 m=52 nchol=416 W=32; nocc=4; one "
+                               "step = one block of 10 propagation steps + QR + local energy",
+                   "path": best},
+        "modes": res,
+        "speedup_vs_separate": {m: round(res[m]["walker_steps_per_s"] /
+                                         res["separate"]["walker_steps_per_s"], 3) for m in res},
+        "max_abs_energy_difference_between_modes": agree,
+        "kernel_source_hash": kernel_source_hash(),
+    }
+
+
+def bench_adjoint(args, torch):
+    """Local energy and its adjoint dE/dGh at 3x3x3, m=26, 16 walkers, FP64 and FP32."""
+    import numpy as np
+    import paper_2003_09468_amd as lib
+    cfg, s, U0, _ = gen_system("c4", torch)
+    U0d = torch.from_numpy(U0).cuda()
+    res, D = {}, {}
+    for name, prec in (("fp64", lib.PREC_FP64), ("fp32", lib.PREC_FP32)):
+        p = make_problem(s, U0, prec, torch)
+        reset(p, U0d)
+        gE = torch.ones(p.nwalk, dtype=torch.complex128, device="cuda")
+        E = torch.empty((p.nwalk, 3), dtype=torch.complex128, device="cuda")
+        G = torch.empty_like(p.Gh)
+        p.energy(out=E)
+        p.energy_backward(gE=gE, out=G)
+        torch.cuda.synchronize()
+        D[name] = (E.cpu().numpy().copy(), G.cpu().numpy().copy())
+        for _ in range(args.warmup):
+            p.energy(out=E)
+            p.energy_backward(gE=gE, out=G)
+        torch.cuda.synchronize()
+        reps = max(args.steps, 1) * 5
+        lib.timing_enable(True, 1 << 16)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            p.energy(out=E)
+            p.energy_backward(gE=gE, out=G)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lib.timing_enable(False)
+        kern = {}
+        for kc in lib.KERNEL_CLASSES:
+            ms, n = lib.timing_read(kc)
+            if n:
+                kern[kc] = {"ms_per_launch": round(ms / n, 5), "launches": n // reps}
+        dt = (t1 - t0) / reps
+        W = cfg["nwalk"]
+        flb = 16.0 * W * cfg["nk"] ** 3 * cfg["nocc"] ** 2 * cfg["nchol"] * cfg["m"]
+        ach = flb / (kern["exchange_bwd"]["ms_per_launch"] * 1e-3) / 1e12
+        res[name] = {"ms_per_eval": round(dt * 1e3, 4),
+                     "walker_evals_per_s": round(W / dt, 2), "kernels": kern,
+                     "roofline": {"kernel": "exchange_bwd", "bound": "mfma",
+                                  "achieved": round(ach, 3), "peak": PEAK[name],
+                                  "unit": "TFLOP/s", "frac": round(ach / PEAK[name], 4),
+                                  "traffic": None, "flops_per_launch": flb}}
+        log(f"[{name}] energy+adjoint {dt * 1e3:.3f} ms -> {W / dt:.1f} walker evals/s; "
+            f"adjoint kernel {kern['exchange_bwd']['ms_per_launch']:.3f} ms ({ach:.1f} TF)")
+        del p
+        torch.cuda.empty_cache()
+    e64, g64 = D["fp64"]
+    e32, g32 = D["fp32"]
+    acc = {"max_abs_dE_per_cell": float(np.abs(e32.sum(1) - e64.sum(1)).max() / cfg["nk"]),
+           "max_rel_dgrad": float(np.abs(g32 - g64).max() / np.abs(g64).max()),
+           "compared": "FP32-contraction vs FP64 GPU path on the same walkers"}
+    return {
+        "metric": "walker energy+adjoint evaluations/s at Nk=27 M=26",
+        "value": res["fp64"]["walker_evals_per_s"], "unit": "walker evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["fp64"]["ms_per_eval"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "c4: mesh 3x3x3, m=26, nocc=4, nchol=208, 16 walkers; one "
+                               "step = local energy + its adjoint for all walkers",
+                   "path": "fp64"},
+        "roofline": res["fp64"]["roofline"], "paths": res, "accuracy": acc,
+        "kernel_source_hash": kernel_source_hash(),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3, help="timed blocks")
     ap.add_argument("--warmup", type=int, default=1, help="untimed blocks")
-    ap.add_argument("--config", default="c1")
+    ap.add_argument("--config", default="c1",
+                    help="c1 (headline), c0, c3 (uneven batch modes) or c4 (energy adjoint)")
     ap.add_argument("--prec", choices=["both", "fp64", "fp32"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -214,6 +396,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.config == "c3":
+        print(json.dumps(bench_batch(args, torch)), flush=True)
+        return
+    if args.config == "c4":
+        print(json.dumps(bench_adjoint(args, torch)), flush=True)
+        return
     cfg = config_shapes(args.config)
     log(f"generating {args.config}: {cfg}")
     t = time.perf_counter()

@@ -32,9 +32,16 @@
  *  - Per-walker numerical failures (singular overlap, non-finite values,
  *    phaseless kill) are reported in status[w] and never fail the call.
  *  - Energies are per supercell; per cell = E / nk.  The ion-ion energy is 0.
- *  - nprob > 1 runs the problems of the array one after another on the stream
- *    (prepare, greens, orthonormalize); entry points whose outputs are separate
- *    arguments (vbias, vhs, propagate, energy, energy_backward) take nprob = 1.
+ *  - Batches ("Implementation on GPUs": batched processing of walkers and of
+ *    independent small operations).  Every entry point takes an array of nprob
+ *    problems, which may differ in mesh, m, nocc, nchol, nwalk, prec and dt.
+ *    Each stage of the entry runs as one launch for up to 8 problems that share
+ *    a kernel variant (precision, size class); stages follow one another on the
+ *    stream.  The workspace of a batch is the concatenation of the problems'
+ *    workspaces (afqmc_kpt_workspace_bytes returns the total).  Per-call buffers
+ *    that are separate arguments (x, xbar, X, vhs, E, gE, gGh) hold the
+ *    problems' slices packed one after another at the byte offsets given by
+ *    afqmc_kpt_buffer_layout; for nprob = 1 the slice is the whole buffer.
  */
 #ifndef AFQMC_KPT_H
 #define AFQMC_KPT_H
@@ -82,8 +89,24 @@ typedef enum {
   AFQMC_ENTRY_PROPAGATE = 4,
   AFQMC_ENTRY_ORTHO = 5,
   AFQMC_ENTRY_ENERGY = 6,
-  AFQMC_ENTRY_ENERGY_BACKWARD = 7
+  AFQMC_ENTRY_ENERGY_BACKWARD = 7,
+  AFQMC_ENTRY_STEP = 8            /* afqmc_kpt_step, graphs and afqmc_kpt_autotune */
 } afqmc_entry;
+
+/* Flags of afqmc_kpt_step and afqmc_kpt_graph_create (AFQMC_PROPAGATE_ORTHO
+ * re-orthonormalises after the last step). */
+#define AFQMC_STEP_ENERGY 2      /* local energy after the last step (into E) */
+
+/* Per-call buffers, for afqmc_kpt_buffer_layout. */
+typedef enum {
+  AFQMC_BUF_FIELDS = 0,  /* x    [nwalk][nk][nchol][2] float64 (one step) */
+  AFQMC_BUF_XBAR = 1,    /* xbar [nwalk][nk][nchol][2] complex128 */
+  AFQMC_BUF_X = 2,       /* X    [nwalk][nk][nchol] complex128 */
+  AFQMC_BUF_VHS = 3,     /* vhs  [nwalk][nk*m][nk*m] complex128 (FP64) or complex64 (FP32) */
+  AFQMC_BUF_ENERGY = 4,  /* E    [nwalk][3] complex128 */
+  AFQMC_BUF_GE = 5,      /* gE   [nwalk] complex128 */
+  AFQMC_BUF_GGH = 6      /* gGh  [nwalk][nk*nocc][nk*m] complex128 */
+} afqmc_buffer;
 
 /* One system and its walker batch. */
 typedef struct afqmc_kpt_problem {
@@ -200,6 +223,50 @@ afqmc_status afqmc_kpt_energy(const afqmc_kpt_problem* p, int nprob, void* E,
  *   gGh: [nwalk][nk*nocc][nk*m] complex128 out. */
 afqmc_status afqmc_kpt_energy_backward(const afqmc_kpt_problem* p, int nprob, const void* gE,
                                        void* gGh, void* ws, size_t ws_bytes, void* stream);
+
+/* Packed layout of one per-call buffer for a batch (host).  offsets: host
+ * array of nprob + 1 entries; offsets[i] is the byte offset of problem i's
+ * slice (a multiple of 256) and offsets[nprob] the end of the last slice, i.e.
+ * the bytes to allocate. */
+afqmc_status afqmc_kpt_buffer_layout(const afqmc_kpt_problem* p, int nprob, int buf,
+                                     size_t* offsets);
+
+/* nsteps walker steps of every problem of the batch (the propagation of
+ * "Introduction to AFQMC" with the k-point force bias and HS potential), each
+ * step being afqmc_kpt_vbias, afqmc_kpt_vhs and afqmc_kpt_propagate in turn:
+ *   x:    fields of all steps; step s, problem i at byte offset
+ *         s * offsets[nprob] + offsets[i] (AFQMC_BUF_FIELDS layout)
+ *   xbar: force bias of the current step (AFQMC_BUF_XBAR layout), out
+ *   vhs:  HS potential of the current step (AFQMC_BUF_VHS layout), out
+ *   E:    local energy after the last step (AFQMC_BUF_ENERGY layout), out,
+ *         with AFQMC_STEP_ENERGY, else may be NULL.
+ * flags: AFQMC_PROPAGATE_ORTHO (after the last step), AFQMC_STEP_ENERGY.
+ * Workspace: AFQMC_ENTRY_STEP. */
+afqmc_status afqmc_kpt_step(const afqmc_kpt_problem* p, int nprob, const double* x, int nsteps,
+                            void* xbar, void* vhs, void* E, int flags, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* Times the compiled tile candidates of the Taylor, HS-potential and
+ * force-bias contractions on this batch and keeps the fastest for later calls
+ * with the same shapes (process-wide cache, thread-safe).  Overwrites vhs
+ * (AFQMC_BUF_VHS layout) and the workspace (AFQMC_ENTRY_STEP); the walker
+ * state is not touched.  Synchronises the stream; not allowed while the
+ * stream is being captured. */
+afqmc_status afqmc_kpt_autotune(const afqmc_kpt_problem* p, int nprob, void* vhs, void* ws,
+                                size_t ws_bytes, void* stream);
+
+/* A captured block of steps: afqmc_kpt_step with these exact arguments,
+ * recorded once into a HIP graph and replayed by afqmc_kpt_graph_launch.  The
+ * graph keeps the addresses: the buffers and workspace must stay allocated
+ * until afqmc_kpt_graph_destroy, and the caller refreshes the fields in x
+ * between launches.  The problem array is copied.  Creation records launches
+ * only (nothing runs); it must not overlap a capture on the same thread. */
+typedef struct afqmc_kpt_graph_s* afqmc_kpt_graph;
+afqmc_status afqmc_kpt_graph_create(const afqmc_kpt_problem* p, int nprob, const double* x,
+                                    int nsteps, void* xbar, void* vhs, void* E, int flags,
+                                    void* ws, size_t ws_bytes, afqmc_kpt_graph* graph);
+afqmc_status afqmc_kpt_graph_launch(afqmc_kpt_graph graph, void* stream);
+afqmc_status afqmc_kpt_graph_destroy(afqmc_kpt_graph graph);
 
 /* Kernel classes of the optional event timing. */
 typedef enum {

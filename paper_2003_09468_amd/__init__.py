@@ -10,6 +10,8 @@ call fails loudly when the library or a gfx950 device is missing.
 from .binding import (  # noqa: F401
     AfqmcError,
     KptProblem,
+    KptBatch,
+    KptGraph,
     lib,
     library_path,
     PREC_FP64,

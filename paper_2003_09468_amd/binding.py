@@ -24,6 +24,7 @@ WALKER_NONFINITE = 2
 WALKER_KILLED = 4
 
 PROPAGATE_ORTHO = 1
+STEP_ENERGY = 2
 
 ENTRIES = {
     "prepare": 0,
@@ -34,7 +35,10 @@ ENTRIES = {
     "ortho": 5,
     "energy": 6,
     "energy_backward": 7,
+    "step": 8,
 }
+
+BUFFERS = {"fields": 0, "xbar": 1, "X": 2, "vhs": 3, "energy": 4, "gE": 5, "gGh": 6}
 
 EXPORTS = [
     "afqmc_kpt_workspace_bytes",
@@ -46,6 +50,12 @@ EXPORTS = [
     "afqmc_kpt_orthonormalize",
     "afqmc_kpt_energy",
     "afqmc_kpt_energy_backward",
+    "afqmc_kpt_buffer_layout",
+    "afqmc_kpt_step",
+    "afqmc_kpt_autotune",
+    "afqmc_kpt_graph_create",
+    "afqmc_kpt_graph_launch",
+    "afqmc_kpt_graph_destroy",
     "afqmc_kpt_timing_enable",
     "afqmc_kpt_timing_read",
     "afqmc_kpt_strerror",
@@ -119,6 +129,12 @@ def lib():
         "afqmc_kpt_orthonormalize": [P, i, vp, sz, vp],
         "afqmc_kpt_energy": [P, i, vp, vp, sz, vp],
         "afqmc_kpt_energy_backward": [P, i, vp, vp, vp, sz, vp],
+        "afqmc_kpt_buffer_layout": [P, i, i, ctypes.POINTER(sz)],
+        "afqmc_kpt_step": [P, i, vp, i, vp, vp, vp, i, vp, sz, vp],
+        "afqmc_kpt_autotune": [P, i, vp, vp, sz, vp],
+        "afqmc_kpt_graph_create": [P, i, vp, i, vp, vp, vp, i, vp, sz, ctypes.POINTER(vp)],
+        "afqmc_kpt_graph_launch": [vp, vp],
+        "afqmc_kpt_graph_destroy": [vp],
         "afqmc_kpt_timing_enable": [i, i],
         "afqmc_kpt_timing_read": [i, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_longlong)],
@@ -315,6 +331,142 @@ class KptProblem:
         v = self.vhs(x, xbar, bufs.get("vhs"))
         self.propagate(v, x, xbar, ortho=ortho)
         return xbar, v
+
+
+class KptBatch:
+    """Several systems (KptProblem objects, possibly of different sizes and precisions)
+    driven as one batch: each stage of an entry point is one launch for up to 8 systems.
+
+    Per-call buffers are packed problem after problem at the offsets the library reports
+    (afqmc_kpt_buffer_layout); xbar(i), vhs(i) and energy(i) are views of system i's slice.
+    """
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        if not self.problems:
+            raise ValueError("empty batch")
+        self.n = len(self.problems)
+        self.device = self.problems[0].device
+        self.arr = (Problem * self.n)(*[p.struct for p in self.problems])
+        self.layout = {b: self.buffer_layout(b) for b in BUFFERS}
+        self._xbar = self._alloc("xbar")
+        self._vhs = self._alloc("vhs")
+        self._E = self._alloc("energy")
+        self._ws = None
+
+    def buffer_layout(self, buf: str) -> list[int]:
+        off = (ctypes.c_size_t * (self.n + 1))()
+        check("afqmc_kpt_buffer_layout",
+              lib().afqmc_kpt_buffer_layout(self.arr, self.n, BUFFERS[buf], off))
+        return [int(v) for v in off]
+
+    def _alloc(self, buf: str, count: int = 1):
+        nbytes = self.layout[buf][-1] * count
+        return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+
+    def _view(self, raw, buf: str, i: int, dtype, shape):
+        off = self.layout[buf][i]
+        count = 1
+        for v in shape:
+            count *= v
+        nbytes = count * torch.empty((), dtype=dtype).element_size()
+        return raw[off:off + nbytes].view(dtype).view(shape)
+
+    def workspace_bytes(self, entry: str) -> int:
+        out = ctypes.c_size_t(0)
+        check("afqmc_kpt_workspace_bytes",
+              lib().afqmc_kpt_workspace_bytes(self.arr, self.n, ENTRIES[entry], ctypes.byref(out)))
+        return int(out.value)
+
+    def workspace(self):
+        if self._ws is None:
+            need = max(self.workspace_bytes(e) for e in ENTRIES)
+            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def fields(self, xs):
+        """Pack per-system fields ([nsteps][W][nk][C][2] float64 each) for step()/graph()."""
+        nsteps = int(xs[0].shape[0])
+        raw = self._alloc("fields", nsteps)
+        stride = self.layout["fields"][-1]
+        for i, x in enumerate(xs):
+            off = self.layout["fields"][i]
+            nb = x[0].numel() * 8
+            xd = x.to(device=self.device, dtype=torch.float64).contiguous()
+            for s_ in range(nsteps):
+                raw[s_ * stride + off:s_ * stride + off + nb].view(torch.float64).copy_(
+                    xd[s_].reshape(-1))
+        return raw, nsteps
+
+    def xbar(self, i):
+        p = self.problems[i]
+        return self._view(self._xbar, "xbar", i, torch.complex128, (p.nwalk, p.nk, p.nchol, 2))
+
+    def vhs(self, i):
+        p = self.problems[i]
+        N = p.nk * p.m
+        dt = torch.complex64 if p.prec == PREC_FP32 else torch.complex128
+        return self._view(self._vhs, "vhs", i, dt, (p.nwalk, N, N))
+
+    def energy(self, i):
+        p = self.problems[i]
+        return self._view(self._E, "energy", i, torch.complex128, (p.nwalk, 3))
+
+    def greens(self):
+        ws = self.workspace()
+        check("afqmc_kpt_greens",
+              lib().afqmc_kpt_greens(self.arr, self.n, ws.data_ptr(), ws.numel(), _stream()))
+
+    def step(self, fields, ortho=False, energy=False):
+        """Run the packed fields' nsteps steps of every system (afqmc_kpt_step)."""
+        raw, nsteps = fields
+        ws = self.workspace()
+        flags = (PROPAGATE_ORTHO if ortho else 0) | (STEP_ENERGY if energy else 0)
+        check("afqmc_kpt_step",
+              lib().afqmc_kpt_step(self.arr, self.n, raw.data_ptr(), nsteps, self._xbar.data_ptr(),
+                                   self._vhs.data_ptr(), self._E.data_ptr(), flags,
+                                   ws.data_ptr(), ws.numel(), _stream()))
+
+    def autotune(self):
+        ws = self.workspace()
+        check("afqmc_kpt_autotune",
+              lib().afqmc_kpt_autotune(self.arr, self.n, self._vhs.data_ptr(), ws.data_ptr(),
+                                       ws.numel(), _stream()))
+
+    def graph(self, fields, ortho=False, energy=False):
+        """Capture the step block over these packed fields (refresh them between launches)."""
+        return KptGraph(self, fields, ortho, energy)
+
+
+class KptGraph:
+    """A captured block of steps of a KptBatch (afqmc_kpt_graph_*)."""
+
+    def __init__(self, batch, fields, ortho, energy):
+        raw, nsteps = fields
+        ws = batch.workspace()
+        flags = (PROPAGATE_ORTHO if ortho else 0) | (STEP_ENERGY if energy else 0)
+        h = ctypes.c_void_p()
+        check("afqmc_kpt_graph_create",
+              lib().afqmc_kpt_graph_create(batch.arr, batch.n, raw.data_ptr(), nsteps,
+                                           batch._xbar.data_ptr(), batch._vhs.data_ptr(),
+                                           batch._E.data_ptr(), flags, ws.data_ptr(), ws.numel(),
+                                           ctypes.byref(h)))
+        self.handle = h
+        self._keep = (batch, raw, ws)  # the graph holds their addresses
+
+    def launch(self):
+        check("afqmc_kpt_graph_launch", lib().afqmc_kpt_graph_launch(self.handle, _stream()))
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            check("afqmc_kpt_graph_destroy", lib().afqmc_kpt_graph_destroy(self.handle))
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class _LocalEnergy(torch.autograd.Function):

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <vector>
 
 #include "internal.h"
 
@@ -29,9 +30,43 @@ size_t ws_bytes_entry(const afqmc_kpt_problem& p, int entry) {
     case AFQMC_ENTRY_ORTHO: return ortho_ws_bytes(p);
     case AFQMC_ENTRY_ENERGY: return energy_ws_bytes(p);
     case AFQMC_ENTRY_ENERGY_BACKWARD: return backward_ws_bytes(p);
+    case AFQMC_ENTRY_STEP: {
+      size_t b = ws_bytes_entry(p, AFQMC_ENTRY_VBIAS);
+      const size_t e[3] = {ws_bytes_entry(p, AFQMC_ENTRY_VHS), ws_bytes_entry(p, AFQMC_ENTRY_PROPAGATE),
+                           ws_bytes_entry(p, AFQMC_ENTRY_ENERGY)};
+      for (size_t v : e) b = v > b ? v : b;
+      return b;
+    }
     default: return 0;
   }
 }
+// Bytes of one problem's slice of a per-call buffer.
+size_t buf_bytes(const afqmc_kpt_problem& p, int buf) {
+  const size_t W = (size_t)p.nwalk, nk = (size_t)p.nk, C = (size_t)p.nchol;
+  const size_t N = nk * p.m, n = nk * p.nocc;
+  switch (buf) {
+    case AFQMC_BUF_FIELDS: return 8 * W * nk * C * 2;
+    case AFQMC_BUF_XBAR: return 16 * W * nk * C * 2;
+    case AFQMC_BUF_X: return 16 * W * nk * C;
+    case AFQMC_BUF_VHS: return (p.prec == AFQMC_PREC_FP32 ? 8 : 16) * W * N * N;
+    case AFQMC_BUF_ENERGY: return 16 * W * 3;
+    case AFQMC_BUF_GE: return 16 * W;
+    case AFQMC_BUF_GGH: return 16 * W * n * N;
+    default: return 0;
+  }
+}
+
+// offsets[i] (multiples of 256) and offsets[nprob] = end of the last slice.
+void buf_offsets(const afqmc_kpt_problem* p, int nprob, int buf, size_t* off) {
+  size_t o = 0;
+  for (int i = 0; i < nprob; ++i) {
+    off[i] = o;
+    const size_t b = buf_bytes(p[i], buf);
+    off[i + 1] = o + b;
+    o = align_up(o + b);
+  }
+}
+
 }  // namespace afqmc
 
 using namespace afqmc;
@@ -105,10 +140,7 @@ afqmc_status check_problems(const afqmc_kpt_problem* p, int nprob, unsigned need
 afqmc_status check_ws(const afqmc_kpt_problem* p, int nprob, int entry, const void* ws,
                       size_t ws_bytes) {
   size_t need = 0;
-  for (int i = 0; i < nprob; ++i) {
-    const size_t b = ws_bytes_entry(p[i], entry);
-    if (b > need) need = b;
-  }
+  for (int i = 0; i < nprob; ++i) need += align_up(ws_bytes_entry(p[i], entry));
   if (need == 0) return AFQMC_OK;
   if (!ws || ws_bytes < need) return AFQMC_EWORKSPACE;
   if (misaligned(ws, 256)) return AFQMC_EALIGN;
@@ -133,7 +165,90 @@ afqmc_status check_device() {
 
 afqmc_status hip_status(hipError_t e) { return e == hipSuccess ? AFQMC_OK : AFQMC_EHIP; }
 
+// Per-call buffer arguments of an entry (packed over the batch).
+struct Bufs {
+  const double* x = nullptr;
+  void* xbar = nullptr;
+  void* X = nullptr;
+  void* vhs = nullptr;
+  void* E = nullptr;
+  const void* gE = nullptr;
+  void* gGh = nullptr;
+};
+
+template <typename P>
+P slice(P base, const afqmc_kpt_problem* p, int nprob, int buf, int i,
+        std::vector<size_t>& off) {
+  if (!base) return nullptr;
+  off.resize(nprob + 1);
+  buf_offsets(p, nprob, buf, off.data());
+  return (P)((const char*)base + off[i]);
+}
+
+// Jobs of a batch: workspace regions and buffer slices.
+std::vector<Job> make_jobs(const afqmc_kpt_problem* p, int nprob, int entry, void* ws,
+                           const Bufs& b) {
+  std::vector<Job> jobs(nprob);
+  std::vector<size_t> off;
+  size_t wo = 0;
+  for (int i = 0; i < nprob; ++i) {
+    Job& j = jobs[i];
+    j.p = p[i];
+    j.ws = ws ? (char*)ws + wo : nullptr;
+    wo += align_up(ws_bytes_entry(p[i], entry));
+    j.x = slice(b.x, p, nprob, AFQMC_BUF_FIELDS, i, off);
+    j.xbar = slice(b.xbar, p, nprob, AFQMC_BUF_XBAR, i, off);
+    j.X = slice(b.X, p, nprob, AFQMC_BUF_X, i, off);
+    j.vhs = slice(b.vhs, p, nprob, AFQMC_BUF_VHS, i, off);
+    j.E = slice(b.E, p, nprob, AFQMC_BUF_ENERGY, i, off);
+    j.gE = slice(b.gE, p, nprob, AFQMC_BUF_GE, i, off);
+    j.gGh = slice(b.gGh, p, nprob, AFQMC_BUF_GGH, i, off);
+  }
+  return jobs;
+}
+
+// The step sequence; fields of step s at x + s * stride bytes.
+hipError_t run_steps(std::vector<Job>& jobs, const double* x, size_t stride, int nsteps,
+                     int flags, hipStream_t s) {
+  const int n = (int)jobs.size();
+  std::vector<const double*> x0(n);
+  for (int i = 0; i < n; ++i) x0[i] = jobs[i].x;
+  hipError_t e = hipSuccess;
+  for (int st = 0; st < nsteps && e == hipSuccess; ++st) {
+    for (int i = 0; i < n; ++i)
+      jobs[i].x = (const double*)((const char*)x0[i] + (size_t)st * stride);
+    e = run_vbias(jobs.data(), n, s);
+    if (e == hipSuccess) e = run_vhs(jobs.data(), n, s);
+    const int pf = (st == nsteps - 1) ? (flags & AFQMC_PROPAGATE_ORTHO) : 0;
+    if (e == hipSuccess) e = run_propagate(jobs.data(), n, pf, s);
+  }
+  for (int i = 0; i < n; ++i) jobs[i].x = x0[i];
+  if (e == hipSuccess && (flags & AFQMC_STEP_ENERGY)) e = run_energy(jobs.data(), n, s);
+  return e;
+}
+
+afqmc_status check_step_args(const afqmc_kpt_problem* p, int nprob, const double* x, int nsteps,
+                             void* xbar, void* vhs, void* E, int flags, void* ws,
+                             size_t ws_bytes) {
+  unsigned need = N_L | N_LH | N_A | N_BHALF | N_U | N_GH | N_LOGDET | N_WEIGHT | N_STATUS;
+  if (flags & AFQMC_STEP_ENERGY) need |= N_H1H;
+  AFQMC_TRY(check_problems(p, nprob, need));
+  if (nsteps < 1) return AFQMC_EINVAL;
+  if (flags & ~(AFQMC_PROPAGATE_ORTHO | AFQMC_STEP_ENERGY)) return AFQMC_EINVAL;
+  AFQMC_TRY(check_ptr(x, 8));
+  AFQMC_TRY(check_ptr(xbar, 16));
+  AFQMC_TRY(check_ptr(vhs, 16));
+  if (flags & AFQMC_STEP_ENERGY) AFQMC_TRY(check_ptr(E, 16));
+  AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_STEP, ws, ws_bytes));
+  return AFQMC_OK;
+}
+
 }  // namespace
+
+// Captured step block.
+struct afqmc_kpt_graph_s {
+  hipGraphExec_t exec;
+};
 
 extern "C" {
 
@@ -141,13 +256,12 @@ afqmc_status afqmc_kpt_workspace_bytes(const afqmc_kpt_problem* p, int nprob, in
                                        size_t* bytes) {
   if (!bytes) return AFQMC_ENULL;
   if (!p) return AFQMC_ENULL;
-  if (nprob < 1 || entry < AFQMC_ENTRY_PREPARE || entry > AFQMC_ENTRY_ENERGY_BACKWARD)
+  if (nprob < 1 || entry < AFQMC_ENTRY_PREPARE || entry > AFQMC_ENTRY_STEP)
     return AFQMC_EINVAL;
   size_t need = 0;
   for (int i = 0; i < nprob; ++i) {
     AFQMC_TRY(check_dims(p[i]));
-    const size_t b = ws_bytes_entry(p[i], entry);
-    if (b > need) need = b;
+    need += align_up(ws_bytes_entry(p[i], entry));
   }
   *bytes = need;
   return AFQMC_OK;
@@ -164,7 +278,9 @@ afqmc_status afqmc_kpt_prepare(const afqmc_kpt_problem* p, int nprob, const void
   AFQMC_TRY(check_ptr(H1, 16));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_PREPARE, ws, ws_bytes));
   AFQMC_TRY(check_device());
-  for (int i = 0; i < nprob; ++i) AFQMC_TRY(hip_status(run_prepare(p[i], H1, ws, (hipStream_t)stream)));
+  std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_PREPARE, ws, Bufs());
+  for (int i = 0; i < nprob; ++i)
+    AFQMC_TRY(hip_status(run_prepare(p[i], H1, jobs[i].ws, (hipStream_t)stream)));
   return AFQMC_OK;
 }
 
@@ -173,8 +289,8 @@ afqmc_status afqmc_kpt_greens(const afqmc_kpt_problem* p, int nprob, void* ws, s
   AFQMC_TRY(check_problems(p, nprob, N_A | N_U | N_GH | N_LOGDET | N_STATUS));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_GREENS, ws, ws_bytes));
   AFQMC_TRY(check_device());
-  for (int i = 0; i < nprob; ++i) AFQMC_TRY(hip_status(run_greens(p[i], ws, false, (hipStream_t)stream)));
-  return AFQMC_OK;
+  std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_GREENS, ws, Bufs());
+  return hip_status(run_greens(jobs.data(), nprob, false, (hipStream_t)stream));
 }
 
 afqmc_status afqmc_kpt_vbias(const afqmc_kpt_problem* p, int nprob, void* xbar, void* X, void* ws,
@@ -184,8 +300,11 @@ afqmc_status afqmc_kpt_vbias(const afqmc_kpt_problem* p, int nprob, void* xbar, 
   if (X) AFQMC_TRY(check_ptr(X, 16));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_VBIAS, ws, ws_bytes));
   AFQMC_TRY(check_device());
-  if (nprob > 1) return AFQMC_EUNSUPPORTED;  // per-problem output arrays are not expressible
-  return hip_status(run_vbias(p[0], xbar, X, ws, (hipStream_t)stream));
+  Bufs b;
+  b.xbar = xbar;
+  b.X = X;
+  std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_VBIAS, ws, b);
+  return hip_status(run_vbias(jobs.data(), nprob, (hipStream_t)stream));
 }
 
 afqmc_status afqmc_kpt_vhs(const afqmc_kpt_problem* p, int nprob, const double* x,
@@ -196,8 +315,12 @@ afqmc_status afqmc_kpt_vhs(const afqmc_kpt_problem* p, int nprob, const double* 
   AFQMC_TRY(check_ptr(vhs, 16));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_VHS, ws, ws_bytes));
   AFQMC_TRY(check_device());
-  if (nprob > 1) return AFQMC_EUNSUPPORTED;
-  return hip_status(run_vhs(p[0], x, xbar, vhs, ws, (hipStream_t)stream));
+  Bufs b;
+  b.x = x;
+  b.xbar = (void*)xbar;
+  b.vhs = vhs;
+  std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_VHS, ws, b);
+  return hip_status(run_vhs(jobs.data(), nprob, (hipStream_t)stream));
 }
 
 afqmc_status afqmc_kpt_propagate(const afqmc_kpt_problem* p, int nprob, const void* vhs,
@@ -210,8 +333,12 @@ afqmc_status afqmc_kpt_propagate(const afqmc_kpt_problem* p, int nprob, const vo
   if (flags & ~AFQMC_PROPAGATE_ORTHO) return AFQMC_EINVAL;
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_PROPAGATE, ws, ws_bytes));
   AFQMC_TRY(check_device());
-  if (nprob > 1) return AFQMC_EUNSUPPORTED;
-  return hip_status(run_propagate(p[0], vhs, x, xbar, flags, ws, (hipStream_t)stream));
+  Bufs b;
+  b.x = x;
+  b.xbar = (void*)xbar;
+  b.vhs = (void*)vhs;
+  std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_PROPAGATE, ws, b);
+  return hip_status(run_propagate(jobs.data(), nprob, flags, (hipStream_t)stream));
 }
 
 afqmc_status afqmc_kpt_orthonormalize(const afqmc_kpt_problem* p, int nprob, void* ws,
@@ -219,8 +346,8 @@ afqmc_status afqmc_kpt_orthonormalize(const afqmc_kpt_problem* p, int nprob, voi
   AFQMC_TRY(check_problems(p, nprob, N_A | N_U | N_GH | N_LOGDET | N_STATUS));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_ORTHO, ws, ws_bytes));
   AFQMC_TRY(check_device());
-  for (int i = 0; i < nprob; ++i) AFQMC_TRY(hip_status(run_ortho(p[i], ws, (hipStream_t)stream)));
-  return AFQMC_OK;
+  std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_ORTHO, ws, Bufs());
+  return hip_status(run_ortho(jobs.data(), nprob, (hipStream_t)stream));
 }
 
 afqmc_status afqmc_kpt_energy(const afqmc_kpt_problem* p, int nprob, void* E, void* ws,
@@ -229,8 +356,10 @@ afqmc_status afqmc_kpt_energy(const afqmc_kpt_problem* p, int nprob, void* E, vo
   AFQMC_TRY(check_ptr(E, 16));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_ENERGY, ws, ws_bytes));
   AFQMC_TRY(check_device());
-  if (nprob > 1) return AFQMC_EUNSUPPORTED;
-  return hip_status(run_energy(p[0], E, ws, (hipStream_t)stream));
+  Bufs b;
+  b.E = E;
+  std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_ENERGY, ws, b);
+  return hip_status(run_energy(jobs.data(), nprob, (hipStream_t)stream));
 }
 
 afqmc_status afqmc_kpt_energy_backward(const afqmc_kpt_problem* p, int nprob, const void* gE,
@@ -240,8 +369,104 @@ afqmc_status afqmc_kpt_energy_backward(const afqmc_kpt_problem* p, int nprob, co
   AFQMC_TRY(check_ptr(gGh, 16));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_ENERGY_BACKWARD, ws, ws_bytes));
   AFQMC_TRY(check_device());
-  if (nprob > 1) return AFQMC_EUNSUPPORTED;
-  return hip_status(run_energy_backward(p[0], gE, gGh, ws, (hipStream_t)stream));
+  Bufs b;
+  b.gE = gE;
+  b.gGh = gGh;
+  std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_ENERGY_BACKWARD, ws, b);
+  return hip_status(run_energy_backward(jobs.data(), nprob, (hipStream_t)stream));
+}
+
+afqmc_status afqmc_kpt_buffer_layout(const afqmc_kpt_problem* p, int nprob, int buf,
+                                     size_t* offsets) {
+  if (!p || !offsets) return AFQMC_ENULL;
+  if (nprob < 1 || buf < AFQMC_BUF_FIELDS || buf > AFQMC_BUF_GGH) return AFQMC_EINVAL;
+  for (int i = 0; i < nprob; ++i) AFQMC_TRY(check_dims(p[i]));
+  buf_offsets(p, nprob, buf, offsets);
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_kpt_step(const afqmc_kpt_problem* p, int nprob, const double* x, int nsteps,
+                            void* xbar, void* vhs, void* E, int flags, void* ws,
+                            size_t ws_bytes, void* stream) {
+  AFQMC_TRY(check_step_args(p, nprob, x, nsteps, xbar, vhs, E, flags, ws, ws_bytes));
+  AFQMC_TRY(check_device());
+  Bufs b;
+  b.x = x;
+  b.xbar = xbar;
+  b.vhs = vhs;
+  b.E = E;
+  std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_STEP, ws, b);
+  std::vector<size_t> off(nprob + 1);
+  buf_offsets(p, nprob, AFQMC_BUF_FIELDS, off.data());
+  return hip_status(run_steps(jobs, x, off[nprob], nsteps, flags, (hipStream_t)stream));
+}
+
+afqmc_status afqmc_kpt_autotune(const afqmc_kpt_problem* p, int nprob, void* vhs, void* ws,
+                                size_t ws_bytes, void* stream) {
+  AFQMC_TRY(check_problems(p, nprob, N_L | N_LH | N_GH | N_U));
+  AFQMC_TRY(check_ptr(vhs, 16));
+  AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_STEP, ws, ws_bytes));
+  AFQMC_TRY(check_device());
+  hipStream_t s = (hipStream_t)stream;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  AFQMC_TRY(hip_status(hipStreamIsCapturing(s, &cs)));
+  if (cs != hipStreamCaptureStatusNone) return AFQMC_EINVAL;
+  Bufs b;
+  b.vhs = vhs;
+  std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_STEP, ws, b);
+  AFQMC_TRY(hip_status(tune_vbias(jobs.data(), nprob, s)));
+  AFQMC_TRY(hip_status(tune_vhs(jobs.data(), nprob, s)));
+  AFQMC_TRY(hip_status(tune_taylor(jobs.data(), nprob, s)));
+  return hip_status(hipStreamSynchronize(s));
+}
+
+afqmc_status afqmc_kpt_graph_create(const afqmc_kpt_problem* p, int nprob, const double* x,
+                                    int nsteps, void* xbar, void* vhs, void* E, int flags,
+                                    void* ws, size_t ws_bytes, afqmc_kpt_graph* graph) {
+  if (!graph) return AFQMC_ENULL;
+  *graph = nullptr;
+  AFQMC_TRY(check_step_args(p, nprob, x, nsteps, xbar, vhs, E, flags, ws, ws_bytes));
+  AFQMC_TRY(check_device());
+  Bufs b;
+  b.x = x;
+  b.xbar = xbar;
+  b.vhs = vhs;
+  b.E = E;
+  std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_STEP, ws, b);
+  std::vector<size_t> off(nprob + 1);
+  buf_offsets(p, nprob, AFQMC_BUF_FIELDS, off.data());
+  // record on a private stream (a capture cannot use the legacy default stream)
+  hipStream_t cs;
+  AFQMC_TRY(hip_status(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)));
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const hipError_t er = run_steps(jobs, x, off[nprob], nsteps, flags, cs);
+    e = hipStreamEndCapture(cs, &g);
+    if (er != hipSuccess) e = er;
+  }
+  hipGraphExec_t exec = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    return AFQMC_EHIP;
+  }
+  *graph = new afqmc_kpt_graph_s{exec};
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_kpt_graph_launch(afqmc_kpt_graph graph, void* stream) {
+  if (!graph) return AFQMC_ENULL;
+  return hip_status(hipGraphLaunch(graph->exec, (hipStream_t)stream));
+}
+
+afqmc_status afqmc_kpt_graph_destroy(afqmc_kpt_graph graph) {
+  if (!graph) return AFQMC_ENULL;
+  const hipError_t e = hipGraphExecDestroy(graph->exec);
+  delete graph;
+  return hip_status(e);
 }
 
 const char* afqmc_kpt_strerror(int status) {

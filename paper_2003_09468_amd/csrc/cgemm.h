@@ -14,7 +14,7 @@
 // the shared operand of a batch in one L2.
 #pragma once
 
-#include "kcommon.h"
+#include "batch.h"
 
 namespace afqmc {
 
@@ -151,7 +151,6 @@ __device__ __forceinline__ void cgemm_tile(const Op& op, int b, int tm, int tn) 
 // Up to AFQMC_MAXP problems (systems) in one launch: each problem's index map, its tile
 // grid and the first global tile index of each problem.  Problems are enumerated in the
 // order given (callers put the longest-K problems first).
-#define AFQMC_MAXP 8
 template <class Op>
 struct OpSet {
   Op op[AFQMC_MAXP];
@@ -225,6 +224,18 @@ hipError_t launch_cgemm(const Op& op, hipStream_t s) {
   hipLaunchKernelGGL((cgemm_kernel<Op, BM, BN, BK, WM, WN>), dim3((unsigned)total),
                      dim3(WM * WN * 64), 0, s, op, tm, tn);
   return hipGetLastError();
+}
+
+// n <= AFQMC_MAXP problems of one stage: the single-problem kernel for one, else one set
+// launch.
+template <int BM, int BN, int BK, int WM, int WN, class Op>
+hipError_t launch_ops(const Op* ops, int n, hipStream_t s) {
+  if (n == 1) return launch_cgemm<BM, BN, BK, WM, WN>(ops[0], s);
+  if (n < 1 || n > AFQMC_MAXP) return hipErrorInvalidValue;
+  OpSet<Op> set;
+  set.nprob = n;
+  for (int i = 0; i < n; ++i) set.op[i] = ops[i];
+  return launch_cgemm_set<BM, BN, BK, WM, WN>(set, s);
 }
 
 }  // namespace afqmc

@@ -26,12 +26,16 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t total) {
   return ((total & 7) == 0) ? (bid & 7) * (total >> 3) + (bid >> 3) : bid;
 }
 
+struct ExchArgs {
+  int nk, m, nocc, C, W, nchunk_w;
+  KMesh mesh;
+  const void* Lh;           // [nk][nk][nocc][m][C] in the contraction precision
+  const cpx<double>* Gh;    // [W][nk*nocc][nk*m]
+  cpx<double>* part;        // [nk^3][W]
+};
+
 template <typename T, int KSMAX>
-__global__ __launch_bounds__(256) void exchange_kernel(int nk, int m, int nocc, int C, int W,
-                                                       KMesh mesh, int nchunk_w,
-                                                       const cpx<T>* __restrict__ Lh,
-                                                       const cpx<double>* __restrict__ Gh,
-                                                       cpx<double>* __restrict__ part) {
+__global__ __launch_bounds__(256) void exchange_kernel(const Batch<ExchArgs> B) {
   typedef typename mfma16<T>::acc_t acc_t;
   constexpr int RP = 4 * KSMAX;
   constexpr int NLD = (2 * 16 * RP) / 256;  // slab elements per thread (both slabs)
@@ -40,8 +44,14 @@ __global__ __launch_bounds__(256) void exchange_kernel(int nk, int m, int nocc, 
   __shared__ T XB[4][2][16][17];     // per-wave exchange tile
   __shared__ double red[2][256];
 
-  const int64_t total = (int64_t)nk * nk * nk * nchunk_w;
-  const int64_t bid = xcd_remap(blockIdx.x, total);
+  long long bid;
+  const int pb = batch_find(B, xcd_remap(blockIdx.x, B.first[B.nprob]), bid);
+  const int nk = B.a[pb].nk, m = B.a[pb].m, nocc = B.a[pb].nocc, C = B.a[pb].C, W = B.a[pb].W;
+  const int nchunk_w = B.a[pb].nchunk_w;
+  const KMesh mesh = B.a[pb].mesh;
+  const cpx<T>* __restrict__ Lh = (const cpx<T>*)B.a[pb].Lh;
+  const cpx<double>* __restrict__ Gh = B.a[pb].Gh;
+  cpx<double>* __restrict__ part = B.a[pb].part;
   const int chunk = (int)(bid % nchunk_w);
   const int t = (int)(bid / nchunk_w);
   const int kp = t % nk, k = (t / nk) % nk, Q = t / (nk * nk);
@@ -183,14 +193,27 @@ __global__ __launch_bounds__(256) void exchange_kernel(int nk, int m, int nocc, 
 
 // E1B[w] = 2 sum_k sum_{a,r} h1h[k][a][r] Gh[w][(k a),(k r)];  EC[w] = 1/2 sum X_Q X_-Q;
 // EX[w] = sum over canonical triples of the exchange partials.  One workgroup per walker.
-__global__ __launch_bounds__(256) void energy_final_kernel(int nk, int m, int nocc, int C, int W,
-                                                           KMesh mesh,
-                                                           const cpx<double>* __restrict__ h1h,
-                                                           const cpx<double>* __restrict__ Gh,
-                                                           const cpx<double>* __restrict__ X,
-                                                           const cpx<double>* __restrict__ part,
-                                                           cpx<double>* __restrict__ E) {
-  const int w = blockIdx.x, tid = threadIdx.x;
+struct EfinArgs {
+  int nk, m, nocc, C, W;
+  KMesh mesh;
+  const cpx<double>* h1h;   // [nk][nocc][m]
+  const cpx<double>* Gh;    // [W][nk*nocc][nk*m]
+  const cpx<double>* X;     // [W][nk][C]
+  const cpx<double>* part;  // [nk^3][W]
+  cpx<double>* E;           // [W][3]
+};
+
+__global__ __launch_bounds__(256) void energy_final_kernel(const Batch<EfinArgs> B) {
+  long long wloc;
+  const int pb = batch_find(B, blockIdx.x, wloc);
+  const int nk = B.a[pb].nk, m = B.a[pb].m, nocc = B.a[pb].nocc, C = B.a[pb].C, W = B.a[pb].W;
+  const KMesh mesh = B.a[pb].mesh;
+  const cpx<double>* __restrict__ h1h = B.a[pb].h1h;
+  const cpx<double>* __restrict__ Gh = B.a[pb].Gh;
+  const cpx<double>* __restrict__ X = B.a[pb].X;
+  const cpx<double>* __restrict__ part = B.a[pb].part;
+  cpx<double>* __restrict__ E = B.a[pb].E;
+  const int w = (int)wloc, tid = threadIdx.x;
   __shared__ double red[6][256];
   const int64_t Nn = (int64_t)nk * m, nn = (int64_t)nk * nocc;
   double e1r = 0, e1i = 0, ecr = 0, eci = 0, exr = 0, exi = 0;
@@ -250,47 +273,98 @@ size_t energy_ws_bytes(const afqmc_kpt_problem& p) {
   return carve_energy(c, p, &a, &b, &x);
 }
 
-template <typename T>
-static hipError_t launch_exchange(const afqmc_kpt_problem& p, void* xpart, hipStream_t s) {
-  const int Ws = 16 / p.nocc;
-  const int nchunk = (p.nwalk + 4 * Ws - 1) / (4 * Ws);
-  const int64_t grid = (int64_t)p.nk * p.nk * p.nk * nchunk;
-  if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  const int KS = (p.m + 3) / 4;
-  const cpx<T>* Lh = (const cpx<T>*)(sizeof(T) == 8 ? p.Lh : p.Lh32);
-  const cpx<double>* Gh = (const cpx<double>*)p.Gh;
-  cpx<double>* part = (cpx<double>*)xpart;
-  KMesh mesh = make_mesh(p);
-  TimedScope ts(KC_EXCHANGE, s);
-  if (KS <= 4)
-    hipLaunchKernelGGL((exchange_kernel<T, 4>), dim3((unsigned)grid), dim3(256), 0, s, p.nk, p.m,
-                       p.nocc, p.nchol, p.nwalk, mesh, nchunk, Lh, Gh, part);
-  else if (KS <= 8)
-    hipLaunchKernelGGL((exchange_kernel<T, 8>), dim3((unsigned)grid), dim3(256), 0, s, p.nk, p.m,
-                       p.nocc, p.nchol, p.nwalk, mesh, nchunk, Lh, Gh, part);
-  else if (KS <= 16)
-    hipLaunchKernelGGL((exchange_kernel<T, 16>), dim3((unsigned)grid), dim3(256), 0, s, p.nk, p.m,
-                       p.nocc, p.nchol, p.nwalk, mesh, nchunk, Lh, Gh, part);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+static int ks_class(int m) {
+  const int KS = (m + 3) / 4;
+  return KS <= 4 ? 4 : (KS <= 8 ? 8 : (KS <= 16 ? 16 : -1));
 }
 
-hipError_t run_energy(const afqmc_kpt_problem& p, void* E, void* ws, hipStream_t s) {
-  Carve c(ws);
-  void *X, *parts, *xpart;
-  carve_energy(c, p, &X, &parts, &xpart);
-  hipError_t e = launch_cholesky_trace(p, X, parts, s);
-  if (e != hipSuccess) return e;
-  e = (p.prec == AFQMC_PREC_FP32) ? launch_exchange<float>(p, xpart, s)
-                                  : launch_exchange<double>(p, xpart, s);
-  if (e != hipSuccess) return e;
-  TimedScope ts(KC_ENERGY_REST, s);
-  hipLaunchKernelGGL(energy_final_kernel, dim3(p.nwalk), dim3(256), 0, s, p.nk, p.m, p.nocc,
-                     p.nchol, p.nwalk, make_mesh(p), (const cpx<double>*)p.h1h,
-                     (const cpx<double>*)p.Gh, (const cpx<double>*)X,
-                     (const cpx<double>*)xpart, (cpx<double>*)E);
-  return hipGetLastError();
+static int exch_nchunk(const afqmc_kpt_problem& p) {
+  const int Ws = 16 / p.nocc;
+  return (p.nwalk + 4 * Ws - 1) / (4 * Ws);
+}
+
+// Exchange partials of every job; one launch per (precision, K-slice class).
+static hipError_t launch_exchange(const Job* jobs, int n, void* const* xpart, hipStream_t s) {
+  TimedScope ts(KC_EXCHANGE, s);
+  return for_groups(
+      n, [&](int i) { return jobs[i].p.prec * 64 + ks_class(jobs[i].p.m); },
+      [&](const int* ids, int c) -> hipError_t {
+        Batch<ExchArgs> B;
+        B.nprob = c;
+        long long cnt[AFQMC_MAXP];
+        for (int q = 0; q < c; ++q) {
+          const afqmc_kpt_problem& p = jobs[ids[q]].p;
+          ExchArgs& a = B.a[q];
+          a.nk = p.nk; a.m = p.m; a.nocc = p.nocc; a.C = p.nchol; a.W = p.nwalk;
+          a.nchunk_w = exch_nchunk(p);
+          a.mesh = make_mesh(p);
+          a.Lh = (p.prec == AFQMC_PREC_FP32) ? p.Lh32 : p.Lh;
+          a.Gh = (const cpx<double>*)p.Gh;
+          a.part = (cpx<double>*)xpart[ids[q]];
+          cnt[q] = (long long)p.nk * p.nk * p.nk * a.nchunk_w;
+        }
+        const long long g = batch_close(B, cnt);
+        if (g < 0) return hipErrorInvalidValue;
+        if (g == 0) return hipSuccess;
+        const bool f32 = jobs[ids[0]].p.prec == AFQMC_PREC_FP32;
+        const dim3 grid((unsigned)g), blk(256);
+        switch (ks_class(jobs[ids[0]].p.m)) {
+          case 4:
+            if (f32) hipLaunchKernelGGL((exchange_kernel<float, 4>), grid, blk, 0, s, B);
+            else hipLaunchKernelGGL((exchange_kernel<double, 4>), grid, blk, 0, s, B);
+            break;
+          case 8:
+            if (f32) hipLaunchKernelGGL((exchange_kernel<float, 8>), grid, blk, 0, s, B);
+            else hipLaunchKernelGGL((exchange_kernel<double, 8>), grid, blk, 0, s, B);
+            break;
+          case 16:
+            if (f32) hipLaunchKernelGGL((exchange_kernel<float, 16>), grid, blk, 0, s, B);
+            else hipLaunchKernelGGL((exchange_kernel<double, 16>), grid, blk, 0, s, B);
+            break;
+          default:
+            return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+      });
+}
+
+hipError_t run_energy(const Job* jobs, int n, hipStream_t s) {
+  for (int c0 = 0; c0 < n; c0 += AFQMC_MAXP) {
+    const int c = (n - c0 < AFQMC_MAXP) ? n - c0 : AFQMC_MAXP;
+    const Job* J = jobs + c0;
+    void *X[AFQMC_MAXP], *parts[AFQMC_MAXP], *xpart[AFQMC_MAXP];
+    for (int q = 0; q < c; ++q) {
+      Carve cv(J[q].ws);
+      carve_energy(cv, J[q].p, &X[q], &parts[q], &xpart[q]);
+    }
+    hipError_t e = launch_cholesky_trace(J, c, X, nullptr, parts, s);
+    if (e != hipSuccess) return e;
+    e = launch_exchange(J, c, xpart, s);
+    if (e != hipSuccess) return e;
+    TimedScope ts(KC_ENERGY_REST, s);
+    Batch<EfinArgs> B;
+    B.nprob = c;
+    long long cnt[AFQMC_MAXP];
+    for (int q = 0; q < c; ++q) {
+      const afqmc_kpt_problem& p = J[q].p;
+      EfinArgs& a = B.a[q];
+      a.nk = p.nk; a.m = p.m; a.nocc = p.nocc; a.C = p.nchol; a.W = p.nwalk;
+      a.mesh = make_mesh(p);
+      a.h1h = (const cpx<double>*)p.h1h;
+      a.Gh = (const cpx<double>*)p.Gh;
+      a.X = (const cpx<double>*)X[q];
+      a.part = (const cpx<double>*)xpart[q];
+      a.E = (cpx<double>*)J[q].E;
+      cnt[q] = p.nwalk;
+    }
+    const long long g = batch_close(B, cnt);
+    if (g < 0) return hipErrorInvalidValue;
+    if (g == 0) continue;
+    hipLaunchKernelGGL(energy_final_kernel, dim3((unsigned)g), dim3(256), 0, s, B);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
@@ -299,12 +373,20 @@ hipError_t run_energy(const afqmc_kpt_problem& p, void* E, void* ws, hipStream_t
 // with T1 recomputed per g chunk (GEMM 1, K = m) and fed through a wave-private LDS tile
 // into GEMM 2 (K = (b, g) of the chunk).  The epilogue adds the one-body and Coulomb terms
 // and scales by 2 gE[w].
+struct BwdArgs {
+  int nk, m, nocc, C, W, nchunk_w;
+  KMesh mesh;
+  const void* Lh;            // [nk][nk][nocc][m][C] in the contraction precision
+  const cpx<double>* LhD;    // the same in complex128 (Coulomb term)
+  const cpx<double>* h1h;    // [nk][nocc][m]
+  const cpx<double>* Gh;     // [W][nk*nocc][nk*m]
+  const cpx<double>* X;      // [W][nk][C]
+  const cpx<double>* gE;     // [W] or null (gE = 1)
+  cpx<double>* gGh;          // like Gh
+};
+
 template <typename T, int KSMAX, int MT>
-__global__ __launch_bounds__(256) void exchange_bwd_kernel(
-    int nk, int m, int nocc, int C, int W, KMesh mesh, int nchunk_w, const cpx<T>* __restrict__ Lh,
-    const cpx<double>* __restrict__ LhD, const cpx<double>* __restrict__ h1h,
-    const cpx<double>* __restrict__ Gh, const cpx<double>* __restrict__ X,
-    const cpx<double>* __restrict__ gE, cpx<double>* __restrict__ gGh) {
+__global__ __launch_bounds__(256) void exchange_bwd_kernel(const Batch<BwdArgs> B) {
   typedef typename mfma16<T>::acc_t acc_t;
   constexpr int RP = 4 * KSMAX;
   constexpr int NC = MT * 16;
@@ -315,11 +397,21 @@ __global__ __launch_bounds__(256) void exchange_bwd_kernel(
   __shared__ T LB[2][2][16][NC + 1];  // [buf][re/im][(b, g)][rho]
   __shared__ T XB[4][2][16][17];
 
-  const int64_t total = (int64_t)nk * nk * nchunk_w;
-  const int64_t bid = xcd_remap(blockIdx.x, total);
+  long long bid;
+  const int pb = batch_find(B, xcd_remap(blockIdx.x, B.first[B.nprob]), bid);
+  const int nk = B.a[pb].nk, m = B.a[pb].m, nocc = B.a[pb].nocc, C = B.a[pb].C, W = B.a[pb].W;
+  const int nchunk_w = B.a[pb].nchunk_w;
+  const KMesh mesh = B.a[pb].mesh;
+  const cpx<T>* __restrict__ Lh = (const cpx<T>*)B.a[pb].Lh;
+  const cpx<double>* __restrict__ LhD = B.a[pb].LhD;
+  const cpx<double>* __restrict__ h1h = B.a[pb].h1h;
+  const cpx<double>* __restrict__ Gh = B.a[pb].Gh;
+  const cpx<double>* __restrict__ X = B.a[pb].X;
+  const cpx<double>* __restrict__ gE = B.a[pb].gE;
+  cpx<double>* __restrict__ gGh = B.a[pb].gGh;
   const int chunk = (int)(bid % nchunk_w);
   const int k2 = (int)((bid / nchunk_w) % nk);
-  const int k1 = (int)(bid / ((int64_t)nchunk_w * nk));
+  const int k1 = (int)(bid / ((long long)nchunk_w * nk));
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int Gs = 16 / nocc, Ws = 16 / nocc;
@@ -502,52 +594,70 @@ size_t backward_ws_bytes(const afqmc_kpt_problem& p) {
   return carve_backward(c, p, &a, &b);
 }
 
-template <typename T, int KSMAX>
-static hipError_t launch_bwd_k(const afqmc_kpt_problem& p, const void* gE, void* gGh, void* X,
-                               hipStream_t s, dim3 grid, int nchunk) {
-  const cpx<T>* Lh = (const cpx<T>*)(sizeof(T) == 8 ? p.Lh : p.Lh32);
-  const int MT = (p.m + 15) / 16;
-  KMesh mesh = make_mesh(p);
+static hipError_t launch_bwd(const Job* jobs, int n, void* const* X, hipStream_t s) {
   TimedScope ts(KC_EXCHANGE_BWD, s);
-#define AFQMC_BWD(MTV)                                                                        \
-  hipLaunchKernelGGL((exchange_bwd_kernel<T, KSMAX, MTV>), grid, dim3(256), 0, s, p.nk, p.m,     \
-                     p.nocc, p.nchol, p.nwalk, mesh, nchunk, Lh, (const cpx<double>*)p.Lh,      \
-                     (const cpx<double>*)p.h1h, (const cpx<double>*)p.Gh,                       \
-                     (const cpx<double>*)X, (const cpx<double>*)gE, (cpx<double>*)gGh)
-  switch (MT) {
-    case 1: AFQMC_BWD(1); break;
-    case 2: AFQMC_BWD(2); break;
-    case 3: AFQMC_BWD(3); break;
-    case 4: AFQMC_BWD(4); break;
-    default: return hipErrorInvalidValue;
+  return for_groups(
+      n,
+      [&](int i) {
+        return (jobs[i].p.prec * 64 + ks_class(jobs[i].p.m)) * 8 + (jobs[i].p.m + 15) / 16;
+      },
+      [&](const int* ids, int c) -> hipError_t {
+        Batch<BwdArgs> B;
+        B.nprob = c;
+        long long cnt[AFQMC_MAXP];
+        for (int q = 0; q < c; ++q) {
+          const Job& j = jobs[ids[q]];
+          const afqmc_kpt_problem& p = j.p;
+          BwdArgs& a = B.a[q];
+          a.nk = p.nk; a.m = p.m; a.nocc = p.nocc; a.C = p.nchol; a.W = p.nwalk;
+          a.nchunk_w = exch_nchunk(p);
+          a.mesh = make_mesh(p);
+          a.Lh = (p.prec == AFQMC_PREC_FP32) ? p.Lh32 : p.Lh;
+          a.LhD = (const cpx<double>*)p.Lh;
+          a.h1h = (const cpx<double>*)p.h1h;
+          a.Gh = (const cpx<double>*)p.Gh;
+          a.X = (const cpx<double>*)X[ids[q]];
+          a.gE = (const cpx<double>*)j.gE;
+          a.gGh = (cpx<double>*)j.gGh;
+          cnt[q] = (long long)p.nk * p.nk * a.nchunk_w;
+        }
+        const long long g = batch_close(B, cnt);
+        if (g < 0) return hipErrorInvalidValue;
+        if (g == 0) return hipSuccess;
+        const afqmc_kpt_problem& p0 = jobs[ids[0]].p;
+        const bool f32 = p0.prec == AFQMC_PREC_FP32;
+        const int ks = ks_class(p0.m), MT = (p0.m + 15) / 16;
+        const dim3 grid((unsigned)g), blk(256);
+#define AFQMC_BWD(KSV, MTV)                                                                \
+  if (ks == KSV && MT == MTV) {                                                            \
+    if (f32) hipLaunchKernelGGL((exchange_bwd_kernel<float, KSV, MTV>), grid, blk, 0, s, B); \
+    else hipLaunchKernelGGL((exchange_bwd_kernel<double, KSV, MTV>), grid, blk, 0, s, B);    \
+    return hipGetLastError();                                                              \
   }
+        AFQMC_BWD(4, 1)
+        AFQMC_BWD(8, 2)
+        AFQMC_BWD(16, 3)
+        AFQMC_BWD(16, 4)
 #undef AFQMC_BWD
-  return hipGetLastError();
+        return hipErrorInvalidValue;
+      });
 }
 
-template <typename T>
-static hipError_t launch_bwd(const afqmc_kpt_problem& p, const void* gE, void* gGh, void* X,
-                             hipStream_t s) {
-  const int Ws = 16 / p.nocc;
-  const int nchunk = (p.nwalk + 4 * Ws - 1) / (4 * Ws);
-  const int64_t g = (int64_t)p.nk * p.nk * nchunk;
-  if (g > 0x7fffffff) return hipErrorInvalidValue;
-  const int KS = (p.m + 3) / 4;
-  if (KS <= 4) return launch_bwd_k<T, 4>(p, gE, gGh, X, s, dim3((unsigned)g), nchunk);
-  if (KS <= 8) return launch_bwd_k<T, 8>(p, gE, gGh, X, s, dim3((unsigned)g), nchunk);
-  if (KS <= 16) return launch_bwd_k<T, 16>(p, gE, gGh, X, s, dim3((unsigned)g), nchunk);
-  return hipErrorInvalidValue;
-}
-
-hipError_t run_energy_backward(const afqmc_kpt_problem& p, const void* gE, void* gGh, void* ws,
-                               hipStream_t s) {
-  Carve c(ws);
-  void *X, *parts;
-  carve_backward(c, p, &X, &parts);
-  hipError_t e = launch_cholesky_trace(p, X, parts, s);
-  if (e != hipSuccess) return e;
-  return (p.prec == AFQMC_PREC_FP32) ? launch_bwd<float>(p, gE, gGh, X, s)
-                                     : launch_bwd<double>(p, gE, gGh, X, s);
+hipError_t run_energy_backward(const Job* jobs, int n, hipStream_t s) {
+  for (int c0 = 0; c0 < n; c0 += AFQMC_MAXP) {
+    const int c = (n - c0 < AFQMC_MAXP) ? n - c0 : AFQMC_MAXP;
+    const Job* J = jobs + c0;
+    void *X[AFQMC_MAXP], *parts[AFQMC_MAXP];
+    for (int q = 0; q < c; ++q) {
+      Carve cv(J[q].ws);
+      carve_backward(cv, J[q].p, &X[q], &parts[q]);
+    }
+    hipError_t e = launch_cholesky_trace(J, c, X, nullptr, parts, s);
+    if (e != hipSuccess) return e;
+    e = launch_bwd(J, c, X, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace afqmc

@@ -53,10 +53,25 @@ struct OpVbias {
   }
 };
 
-__global__ void vbias_reduce_kernel(int W, int nk, int C, int S, KMesh mesh, double sdt,
-                                    const cpx<double>* __restrict__ part,
-                                    cpx<double>* __restrict__ X, cpx<double>* __restrict__ xbar) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+struct VredArgs {
+  int W, nk, C, S;
+  KMesh mesh;
+  double sdt;
+  const cpx<double>* part;  // [S][W][nk][C]
+  cpx<double>* X;           // [W][nk][C] (may be null)
+  cpx<double>* xbar;        // [W][nk][C][2] (may be null)
+};
+
+__global__ __launch_bounds__(256) void vbias_reduce_kernel(const Batch<VredArgs> B) {
+  long long bloc;
+  const int pb = batch_find(B, blockIdx.x, bloc);
+  const int W = B.a[pb].W, nk = B.a[pb].nk, C = B.a[pb].C, S = B.a[pb].S;
+  const KMesh mesh = B.a[pb].mesh;
+  const double sdt = B.a[pb].sdt;
+  const cpx<double>* __restrict__ part = B.a[pb].part;
+  cpx<double>* __restrict__ X = B.a[pb].X;
+  cpx<double>* __restrict__ xbar = B.a[pb].xbar;
+  const int64_t idx = bloc * 256 + threadIdx.x;
   const int64_t total = (int64_t)W * nk * C;
   if (idx >= total) return;
   const int g = (int)(idx % C);
@@ -86,7 +101,7 @@ size_t carve_vbias(Carve& c, const Dims& d, VbiasWs& v) {
 }
 
 template <typename T>
-static hipError_t launch_vbias_gemm(const afqmc_kpt_problem& p, void* parts, hipStream_t s) {
+static OpVbias<T> vbias_op(const afqmc_kpt_problem& p, void* parts) {
   Dims d = dims_of(p);
   OpVbias<T> op;
   op.nk = p.nk; op.m = p.m; op.nocc = p.nocc; op.C = p.nchol;
@@ -100,42 +115,133 @@ static hipError_t launch_vbias_gemm(const afqmc_kpt_problem& p, void* parts, hip
   op.Lh = (const cpx<T>*)(sizeof(T) == 8 ? p.Lh : p.Lh32);
   op.Gh = (const cpx<double>*)p.Gh;
   op.part = (cpx<double>*)parts;
-  return launch_cgemm<64, 64, 16, 2, 2>(op, s);
+  return op;
 }
 
-// X (and optionally xbar) for the current Gh.
-hipError_t launch_cholesky_trace_x(const afqmc_kpt_problem& p, void* X, void* xbar, void* parts,
-                                   hipStream_t s) {
+template <typename T>
+static hipError_t vbias_tiles(const OpVbias<T>* ops, int c, int choice, hipStream_t s) {
+  switch (choice) {
+    case 1: return launch_ops<32, 64, 16, 2, 2>(ops, c, s);
+    case 2: return launch_ops<64, 32, 16, 4, 1>(ops, c, s);
+    default: return launch_ops<64, 64, 16, 2, 2>(ops, c, s);
+  }
+}
+
+// Split-K partial traces of a group of jobs of one precision.
+hipError_t launch_vbias_group(const Job* jobs, const int* ids, int c, int choice,
+                              void* const* parts, hipStream_t s) {
+  if (jobs[ids[0]].p.prec == AFQMC_PREC_FP32) {
+    OpVbias<float> ops[AFQMC_MAXP];
+    for (int q = 0; q < c; ++q) ops[q] = vbias_op<float>(jobs[ids[q]].p, parts[ids[q]]);
+    return vbias_tiles<float>(ops, c, choice, s);
+  }
+  OpVbias<double> ops[AFQMC_MAXP];
+  for (int q = 0; q < c; ++q) ops[q] = vbias_op<double>(jobs[ids[q]].p, parts[ids[q]]);
+  return vbias_tiles<double>(ops, c, choice, s);
+}
+
+// X (and xbar where requested) for the current Gh of every job.
+hipError_t launch_cholesky_trace(const Job* jobs, int n, void* const* X, void* const* xbar,
+                                 void* const* parts, hipStream_t s) {
   TimedScope ts(KC_VBIAS, s);
-  hipError_t e = (p.prec == AFQMC_PREC_FP32) ? launch_vbias_gemm<float>(p, parts, s)
-                                             : launch_vbias_gemm<double>(p, parts, s);
+  hipError_t e = for_groups(
+      n, [&](int i) { return jobs[i].p.prec; },
+      [&](const int* ids, int c) -> hipError_t {
+        const int choice = tune_lookup(tune_key(TS_VBIAS, jobs, ids, c));
+        return launch_vbias_group(jobs, ids, c, choice, parts, s);
+      });
   if (e != hipSuccess) return e;
-  Dims d = dims_of(p);
-  const int64_t total = d.W * d.nk * d.C;
-  const int S = vbias_splits(d);
-  hipLaunchKernelGGL(vbias_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                     p.nwalk, p.nk, p.nchol, S, make_mesh(p), sqrt(p.dt),
-                     (const cpx<double>*)parts, (cpx<double>*)X, (cpx<double>*)xbar);
-  return hipGetLastError();
+  for (int c0 = 0; c0 < n; c0 += AFQMC_MAXP) {
+    const int c = (n - c0 < AFQMC_MAXP) ? n - c0 : AFQMC_MAXP;
+    Batch<VredArgs> B;
+    B.nprob = c;
+    long long cnt[AFQMC_MAXP];
+    for (int q = 0; q < c; ++q) {
+      const afqmc_kpt_problem& p = jobs[c0 + q].p;
+      VredArgs& a = B.a[q];
+      a.W = p.nwalk; a.nk = p.nk; a.C = p.nchol;
+      a.S = vbias_splits(dims_of(p));
+      a.mesh = make_mesh(p);
+      a.sdt = sqrt(p.dt);
+      a.part = (const cpx<double>*)parts[c0 + q];
+      a.X = X ? (cpx<double>*)X[c0 + q] : nullptr;
+      a.xbar = xbar ? (cpx<double>*)xbar[c0 + q] : nullptr;
+      cnt[q] = ((int64_t)p.nwalk * p.nk * p.nchol + 255) / 256;
+    }
+    const long long g = batch_close(B, cnt);
+    if (g < 0) return hipErrorInvalidValue;
+    if (g == 0) continue;
+    hipLaunchKernelGGL(vbias_reduce_kernel, dim3((unsigned)g), dim3(256), 0, s, B);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
-hipError_t launch_cholesky_trace(const afqmc_kpt_problem& p, void* X, void* parts, hipStream_t s) {
-  return launch_cholesky_trace_x(p, X, nullptr, parts, s);
+hipError_t run_vbias(const Job* jobs, int n, hipStream_t s) {
+  void* X[64];
+  void* xb[64];
+  void* parts[64];
+  for (int c0 = 0; c0 < n; c0 += 64) {
+    const int c = (n - c0 < 64) ? n - c0 : 64;
+    for (int q = 0; q < c; ++q) {
+      const Job& j = jobs[c0 + q];
+      Carve cv(j.ws);
+      VbiasWs v;
+      carve_vbias(cv, dims_of(j.p), v);
+      X[q] = j.X;
+      xb[q] = j.xbar;
+      parts[q] = v.parts;
+    }
+    hipError_t e = launch_cholesky_trace(jobs + c0, c, X, xb, parts, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
-hipError_t run_vbias(const afqmc_kpt_problem& p, void* xbar, void* X, void* ws, hipStream_t s) {
-  Carve c(ws);
-  VbiasWs v;
-  carve_vbias(c, dims_of(p), v);
-  return launch_cholesky_trace_x(p, X, xbar, v.parts, s);
+hipError_t tune_vbias(const Job* jobs, int n, hipStream_t s) {
+  void* parts[64];
+  for (int c0 = 0; c0 < n; c0 += 64) {
+    const int c = (n - c0 < 64) ? n - c0 : 64;
+    const Job* J = jobs + c0;
+    for (int q = 0; q < c; ++q) {
+      Carve cv(J[q].ws);
+      VbiasWs v;
+      carve_vbias(cv, dims_of(J[q].p), v);
+      parts[q] = v.parts;
+    }
+    const hipError_t e = for_groups(
+        c, [&](int i) { return J[i].p.prec; },
+        [&](const int* ids, int g) -> hipError_t {
+          return tune_group(
+              TS_VBIAS, J, ids, g,
+              [&](int ch) { return launch_vbias_group(J, ids, g, ch, parts, s); }, s);
+        });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
 // combined field: zeta = -xi, xi = 1/2 [ i (xt+_Q + xt+_-Q) + (xt-_Q - xt-_-Q) ]
+struct FieldArgs {
+  int W, nk, C;
+  KMesh mesh;
+  const double* x;           // [W][nk][C][2]
+  const cpx<double>* xbar;   // [W][nk][C][2]
+  void* zeta;                // [W][nk][C] in the contraction precision
+};
+
 template <typename T>
-__global__ void field_kernel(int W, int nk, int C, KMesh mesh, const double* __restrict__ x,
-                             const cpx<double>* __restrict__ xbar, cpx<T>* __restrict__ zeta) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void field_kernel(const Batch<FieldArgs> B) {
+  long long bloc;
+  const int pb = batch_find(B, blockIdx.x, bloc);
+  const int W = B.a[pb].W, nk = B.a[pb].nk, C = B.a[pb].C;
+  const KMesh mesh = B.a[pb].mesh;
+  const double* __restrict__ x = B.a[pb].x;
+  const cpx<double>* __restrict__ xbar = B.a[pb].xbar;
+  cpx<T>* __restrict__ zeta = (cpx<T>*)B.a[pb].zeta;
+  const int64_t idx = bloc * 256 + threadIdx.x;
   const int64_t total = (int64_t)W * nk * C;
   if (idx >= total) return;
   const int g = (int)(idx % C);
@@ -184,15 +290,8 @@ struct OpVhs {
 };
 
 template <typename T>
-static hipError_t launch_vhs_typed(const afqmc_kpt_problem& p, const double* x, const void* xbar,
-                                   void* vhs, void* zeta, hipStream_t s) {
-  TimedScope ts(KC_VHS, s);
-  const int64_t total = (int64_t)p.nwalk * p.nk * p.nchol;
-  hipLaunchKernelGGL(field_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                     p.nwalk, p.nk, p.nchol, make_mesh(p), x, (const cpx<double>*)xbar,
-                     (cpx<T>*)zeta);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+static OpVhs<T> vhs_op(const Job& j, void* zeta) {
+  const afqmc_kpt_problem& p = j.p;
   OpVhs<T> op;
   op.nk = p.nk; op.m = p.m; op.mesh = make_mesh(p);
   op.M = p.nwalk;
@@ -201,18 +300,102 @@ static hipError_t launch_vhs_typed(const afqmc_kpt_problem& p, const double* x, 
   op.nbatch = p.nk;
   op.zeta = (const cpx<T>*)zeta;
   op.L = (const cpx<T>*)(sizeof(T) == 8 ? p.L : p.L32);
-  op.vhs = (cpx<T>*)vhs;
-  // rows = walkers, (k p r) columns; tiles measured at 27 x 64 x 18252 x 208
-  if (sizeof(T) == 8) return launch_cgemm<64, 32, 16, 4, 1>(op, s);
-  return launch_cgemm<64, 64, 16, 2, 2>(op, s);
+  op.vhs = (cpx<T>*)j.vhs;
+  return op;
 }
 
-hipError_t run_vhs(const afqmc_kpt_problem& p, const double* x, const void* xbar, void* vhs,
-                   void* ws, hipStream_t s) {
-  Carve c(ws);
-  void* zeta = c.take(sizeof(double) * 2 * (size_t)p.nwalk * p.nk * p.nchol);
-  if (p.prec == AFQMC_PREC_FP32) return launch_vhs_typed<float>(p, x, xbar, vhs, zeta, s);
-  return launch_vhs_typed<double>(p, x, xbar, vhs, zeta, s);
+// Rows = walkers, (k p r) columns.  Default tiles measured at 27 x 64 x 18252 x 208.
+template <typename T>
+static hipError_t vhs_tiles(const OpVhs<T>* ops, int c, int choice, hipStream_t s) {
+  if (sizeof(T) == 8) {
+    switch (choice) {
+      case 1: return launch_ops<64, 64, 16, 2, 2>(ops, c, s);
+      case 2: return launch_ops<32, 64, 16, 2, 2>(ops, c, s);
+      default: return launch_ops<64, 32, 16, 4, 1>(ops, c, s);
+    }
+  }
+  switch (choice) {
+    case 1: return launch_ops<64, 32, 16, 4, 1>(ops, c, s);
+    case 2: return launch_ops<64, 128, 16, 2, 2>(ops, c, s);
+    default: return launch_ops<64, 64, 16, 2, 2>(ops, c, s);
+  }
+}
+
+hipError_t launch_vhs_group(const Job* jobs, const int* ids, int c, int choice,
+                            void* const* zeta, hipStream_t s) {
+  if (jobs[ids[0]].p.prec == AFQMC_PREC_FP32) {
+    OpVhs<float> ops[AFQMC_MAXP];
+    for (int q = 0; q < c; ++q) ops[q] = vhs_op<float>(jobs[ids[q]], zeta[ids[q]]);
+    return vhs_tiles<float>(ops, c, choice, s);
+  }
+  OpVhs<double> ops[AFQMC_MAXP];
+  for (int q = 0; q < c; ++q) ops[q] = vhs_op<double>(jobs[ids[q]], zeta[ids[q]]);
+  return vhs_tiles<double>(ops, c, choice, s);
+}
+
+hipError_t run_vhs(const Job* jobs, int n, hipStream_t s) {
+  TimedScope ts(KC_VHS, s);
+  void* zeta[64];
+  for (int c0 = 0; c0 < n; c0 += 64) {
+    const int c = (n - c0 < 64) ? n - c0 : 64;
+    const Job* J = jobs + c0;
+    for (int q = 0; q < c; ++q) {
+      Carve cv(J[q].ws);
+      zeta[q] = cv.take(sizeof(double) * 2 * (size_t)J[q].p.nwalk * J[q].p.nk * J[q].p.nchol);
+    }
+    hipError_t e = for_groups(
+        c, [&](int i) { return J[i].p.prec; },
+        [&](const int* ids, int g) -> hipError_t {
+          Batch<FieldArgs> B;
+          B.nprob = g;
+          long long cnt[AFQMC_MAXP];
+          for (int q = 0; q < g; ++q) {
+            const Job& j = J[ids[q]];
+            FieldArgs& a = B.a[q];
+            a.W = j.p.nwalk; a.nk = j.p.nk; a.C = j.p.nchol;
+            a.mesh = make_mesh(j.p);
+            a.x = j.x;
+            a.xbar = (const cpx<double>*)j.xbar;
+            a.zeta = zeta[ids[q]];
+            cnt[q] = ((int64_t)j.p.nwalk * j.p.nk * j.p.nchol + 255) / 256;
+          }
+          const long long grid = batch_close(B, cnt);
+          if (grid < 0) return hipErrorInvalidValue;
+          if (grid > 0) {
+            if (J[ids[0]].p.prec == AFQMC_PREC_FP32)
+              hipLaunchKernelGGL(field_kernel<float>, dim3((unsigned)grid), dim3(256), 0, s, B);
+            else
+              hipLaunchKernelGGL(field_kernel<double>, dim3((unsigned)grid), dim3(256), 0, s, B);
+            const hipError_t e2 = hipGetLastError();
+            if (e2 != hipSuccess) return e2;
+          }
+          const int choice = tune_lookup(tune_key(TS_VHS, J, ids, g));
+          return launch_vhs_group(J, ids, g, choice, zeta, s);
+        });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t tune_vhs(const Job* jobs, int n, hipStream_t s) {
+  void* zeta[64];
+  for (int c0 = 0; c0 < n; c0 += 64) {
+    const int c = (n - c0 < 64) ? n - c0 : 64;
+    const Job* J = jobs + c0;
+    for (int q = 0; q < c; ++q) {
+      Carve cv(J[q].ws);
+      zeta[q] = cv.take(sizeof(double) * 2 * (size_t)J[q].p.nwalk * J[q].p.nk * J[q].p.nchol);
+    }
+    const hipError_t e = for_groups(
+        c, [&](int i) { return J[i].p.prec; },
+        [&](const int* ids, int g) -> hipError_t {
+          return tune_group(
+              TS_VHS, J, ids, g, [&](int ch) { return launch_vhs_group(J, ids, g, ch, zeta, s); },
+              s);
+        });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace afqmc

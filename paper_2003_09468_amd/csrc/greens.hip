@@ -31,13 +31,26 @@ __device__ __forceinline__ double pick_col(const double (&a)[NSR][NSC], int si, 
   return v;
 }
 
+// Arguments of one problem: n x n matrices of nwalk walkers.
+struct GjArgs {
+  int n;
+  const cpx<double>* S;  // [W][n][n]
+  cpx<double>* out;      // [W][n][n]
+  cpx<double>* logdet;   // [W] (GREENS mode)
+  int* status;           // [W]
+};
+
+// One workgroup per walker of every problem of the batch.
 template <int TR, int NSR, int NSC>
-__global__ __launch_bounds__(TR * 32) void small_gj_kernel(int mode, int n,
-                                                          const cpx<double>* __restrict__ S_in,
-                                                          cpx<double>* __restrict__ out,
-                                                          cpx<double>* __restrict__ logdet_out,
-                                                          int* __restrict__ status) {
-  const int w = blockIdx.x;
+__global__ __launch_bounds__(TR * 32) void small_gj_kernel(int mode, const Batch<GjArgs> B) {
+  long long wloc;
+  const int pb = batch_find(B, blockIdx.x, wloc);
+  const int n = B.a[pb].n;
+  const cpx<double>* __restrict__ S_in = B.a[pb].S;
+  cpx<double>* __restrict__ out = B.a[pb].out;
+  cpx<double>* __restrict__ logdet_out = B.a[pb].logdet;
+  int* __restrict__ status = B.a[pb].status;
+  const int w = (int)wloc;
   const int tid = threadIdx.x;
   const int tr = tid >> 5, tc = tid & 31;
   const int lane = tid & 63;
@@ -315,24 +328,53 @@ struct OpOverlap {
   }
 };
 
-hipError_t launch_small_gj(const afqmc_kpt_problem& p, int mode, const void* S_in, void* out,
-                           void* logdet_out, hipStream_t s) {
-  const int n = p.nk * p.nocc;
-  const cpx<double>* S = (const cpx<double>*)S_in;
-  cpx<double>* o = (cpx<double>*)out;
-  cpx<double>* ld = (cpx<double>*)logdet_out;
-  dim3 g(p.nwalk);
-  if (n <= 32)
-    hipLaunchKernelGGL((small_gj_kernel<32, 1, 1>), g, dim3(1024), 0, s, mode, n, S, o, ld, p.status);
-  else if (n <= 64)
-    hipLaunchKernelGGL((small_gj_kernel<32, 2, 2>), g, dim3(1024), 0, s, mode, n, S, o, ld, p.status);
-  else if (n <= 96)
-    hipLaunchKernelGGL((small_gj_kernel<16, 6, 3>), g, dim3(512), 0, s, mode, n, S, o, ld, p.status);
-  else if (n <= 128)
-    hipLaunchKernelGGL((small_gj_kernel<16, 8, 4>), g, dim3(512), 0, s, mode, n, S, o, ld, p.status);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+// Size class of the register-resident elimination for n (0..3), -1 if too large.
+static int gj_class(int n) {
+  if (n <= 32) return 0;
+  if (n <= 64) return 1;
+  if (n <= 96) return 2;
+  if (n <= 128) return 3;
+  return -1;
+}
+
+hipError_t launch_small_gj(const Job* jobs, int n, int mode, void* const* S_in,
+                           void* const* out, void* const* logdet_out, hipStream_t s) {
+  return for_groups(
+      n, [&](int i) { return gj_class(jobs[i].p.nk * jobs[i].p.nocc); },
+      [&](const int* ids, int c) -> hipError_t {
+        Batch<GjArgs> B;
+        B.nprob = c;
+        long long cnt[AFQMC_MAXP];
+        for (int q = 0; q < c; ++q) {
+          const afqmc_kpt_problem& p = jobs[ids[q]].p;
+          B.a[q].n = p.nk * p.nocc;
+          B.a[q].S = (const cpx<double>*)S_in[ids[q]];
+          B.a[q].out = (cpx<double>*)out[ids[q]];
+          B.a[q].logdet = logdet_out ? (cpx<double>*)logdet_out[ids[q]] : nullptr;
+          B.a[q].status = p.status;
+          cnt[q] = p.nwalk;
+        }
+        const long long g = batch_close(B, cnt);
+        if (g < 0) return hipErrorInvalidValue;
+        if (g == 0) return hipSuccess;
+        switch (gj_class(B.a[0].n)) {
+          case 0:
+            hipLaunchKernelGGL((small_gj_kernel<32, 1, 1>), dim3((unsigned)g), dim3(1024), 0, s, mode, B);
+            break;
+          case 1:
+            hipLaunchKernelGGL((small_gj_kernel<32, 2, 2>), dim3((unsigned)g), dim3(1024), 0, s, mode, B);
+            break;
+          case 2:
+            hipLaunchKernelGGL((small_gj_kernel<16, 6, 3>), dim3((unsigned)g), dim3(512), 0, s, mode, B);
+            break;
+          case 3:
+            hipLaunchKernelGGL((small_gj_kernel<16, 8, 4>), dim3((unsigned)g), dim3(512), 0, s, mode, B);
+            break;
+          default:
+            return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+      });
 }
 
 // Gh[w][i][R] = sum_j OinvT[w][i][j] U[w][R][j]
@@ -357,18 +399,6 @@ struct OpGreensSolve {
   }
 };
 
-hipError_t launch_greens_solve(const afqmc_kpt_problem& p, const void* oinvT, hipStream_t s) {
-  OpGreensSolve op;
-  op.M = p.nk * p.nocc;
-  op.N = p.nk * p.m;
-  op.K = p.nk * p.nocc;
-  op.nbatch = p.nwalk;
-  op.oinvT = (const cpx<double>*)oinvT;
-  op.U = (const cpx<double>*)p.U;
-  op.Gh = (cpx<double>*)p.Gh;
-  return launch_cgemm<64, 64, 16, 2, 2>(op, s);
-}
-
 size_t carve_greens(Carve& c, const Dims& d, GreensWs& g) {
   g.omat = c.take(sizeof(double) * 2 * d.W * d.n() * d.n());
   g.oinvT = c.take(sizeof(double) * 2 * d.W * d.n() * d.n());
@@ -376,40 +406,78 @@ size_t carve_greens(Carve& c, const Dims& d, GreensWs& g) {
   return c.off;
 }
 
-// Greens for the current U.  With write_logdet_new_only the log determinant goes to the
-// workspace slot (the weight update then moves it into p.logdet), else into p.logdet.
-hipError_t run_greens(const afqmc_kpt_problem& p, void* ws, bool write_logdet_new_only,
-                      hipStream_t s) {
-  Carve c(ws);
-  GreensWs g;
-  carve_greens(c, dims_of(p), g);
+// Greens for the current U of every job.  With write_logdet_new_only the log determinant
+// goes to the workspace slot (the weight update then moves it into p.logdet), else into
+// p.logdet.
+hipError_t run_greens(const Job* jobs, int n, bool write_logdet_new_only, hipStream_t s) {
   TimedScope ts(KC_GREENS, s);
-  OpOverlap op;
-  op.M = p.nocc; op.K = p.m; op.N = p.nk * p.nocc;
-  op.nbatch = p.nwalk * p.nk;
-  op.nk = p.nk;
-  op.A = (const cpx<double>*)p.A;
-  op.U = (const cpx<double>*)p.U;
-  op.O = (cpx<double>*)g.omat;
-  hipError_t e = launch_cgemm<16, 64, 16, 1, 4>(op, s);
-  if (e != hipSuccess) return e;
-  e = launch_small_gj(p, GJ_MODE_GREENS, g.omat, g.oinvT,
-                                 write_logdet_new_only ? g.logdet_new : p.logdet, s);
-  if (e != hipSuccess) return e;
-  return launch_greens_solve(p, g.oinvT, s);
+  void* omat[AFQMC_MAXP];
+  void* oinvT[AFQMC_MAXP];
+  void* ldo[AFQMC_MAXP];
+  for (int c0 = 0; c0 < n; c0 += AFQMC_MAXP) {
+    const int c = (n - c0 < AFQMC_MAXP) ? n - c0 : AFQMC_MAXP;
+    const Job* J = jobs + c0;
+    OpOverlap ov[AFQMC_MAXP];
+    OpGreensSolve sv[AFQMC_MAXP];
+    for (int q = 0; q < c; ++q) {
+      const afqmc_kpt_problem& p = J[q].p;
+      Carve cv(J[q].ws);
+      GreensWs g;
+      carve_greens(cv, dims_of(p), g);
+      omat[q] = g.omat;
+      oinvT[q] = g.oinvT;
+      ldo[q] = write_logdet_new_only ? g.logdet_new : p.logdet;
+      OpOverlap& op = ov[q];
+      op.M = p.nocc; op.K = p.m; op.N = p.nk * p.nocc;
+      op.nbatch = p.nwalk * p.nk;
+      op.nk = p.nk;
+      op.A = (const cpx<double>*)p.A;
+      op.U = (const cpx<double>*)p.U;
+      op.O = (cpx<double>*)g.omat;
+      OpGreensSolve& sl = sv[q];
+      sl.M = p.nk * p.nocc;
+      sl.N = p.nk * p.m;
+      sl.K = p.nk * p.nocc;
+      sl.nbatch = p.nwalk;
+      sl.oinvT = (const cpx<double>*)g.oinvT;
+      sl.U = (const cpx<double>*)p.U;
+      sl.Gh = (cpx<double>*)p.Gh;
+    }
+    hipError_t e = launch_ops<16, 64, 16, 1, 4>(ov, c, s);
+    if (e != hipSuccess) return e;
+    e = launch_small_gj(J, c, GJ_MODE_GREENS, omat, oinvT, ldo, s);
+    if (e != hipSuccess) return e;
+    e = launch_ops<64, 64, 16, 2, 2>(sv, c, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
 // Hybrid phaseless weight update, one workgroup per walker:
 //   log I = 2 (logdet' - logdet) + sum_{Q,g,+/-} (x xbar - xbar^2/2),
 //   dtheta = arg exp(2 (logdet' - logdet)), w <- |I| max(0, cos dtheta) w.
-__global__ __launch_bounds__(256) void weight_kernel(int64_t nf, const double* __restrict__ x,
-                                                     const cpx<double>* __restrict__ xbar,
-                                                     cpx<double>* __restrict__ logdet,
-                                                     const cpx<double>* __restrict__ logdet_new,
-                                                     double* __restrict__ weight,
-                                                     int* __restrict__ status) {
-  const int w = blockIdx.x;
+struct WeightArgs {
+  int64_t nf;                    // nk * nchol * 2 field components per walker
+  const double* x;               // [W][nf]
+  const cpx<double>* xbar;       // [W][nf]
+  cpx<double>* logdet;           // [W]
+  const cpx<double>* logdet_new; // [W]
+  double* weight;                // [W]
+  int* status;                   // [W]
+};
+
+__global__ __launch_bounds__(256) void weight_kernel(const Batch<WeightArgs> B) {
+  long long wloc;
+  const int pb = batch_find(B, blockIdx.x, wloc);
+  const int64_t nf = B.a[pb].nf;
+  const double* __restrict__ x = B.a[pb].x;
+  const cpx<double>* __restrict__ xbar = B.a[pb].xbar;
+  cpx<double>* __restrict__ logdet = B.a[pb].logdet;
+  const cpx<double>* __restrict__ logdet_new = B.a[pb].logdet_new;
+  double* __restrict__ weight = B.a[pb].weight;
+  int* __restrict__ status = B.a[pb].status;
+  const int w = (int)wloc;
   const int tid = threadIdx.x;
   __shared__ double sr[256], si[256];
   double ar = 0.0, ai = 0.0;
@@ -450,14 +518,37 @@ __global__ __launch_bounds__(256) void weight_kernel(int64_t nf, const double* _
   }
 }
 
-hipError_t launch_weights(const afqmc_kpt_problem& p, const double* x, const void* xbar,
-                          const void* logdet_new, hipStream_t s) {
-  const int64_t nf = (int64_t)p.nk * p.nchol * 2;
+hipError_t launch_weights(const Job* jobs, int n, hipStream_t s) {
   TimedScope ts(KC_WEIGHTS, s);
-  hipLaunchKernelGGL(weight_kernel, dim3(p.nwalk), dim3(256), 0, s, nf, x,
-                     (const cpx<double>*)xbar, (cpx<double>*)p.logdet,
-                     (const cpx<double>*)logdet_new, p.weight, p.status);
-  return hipGetLastError();
+  for (int c0 = 0; c0 < n; c0 += AFQMC_MAXP) {
+    const int c = (n - c0 < AFQMC_MAXP) ? n - c0 : AFQMC_MAXP;
+    Batch<WeightArgs> B;
+    B.nprob = c;
+    long long cnt[AFQMC_MAXP];
+    for (int q = 0; q < c; ++q) {
+      const Job& j = jobs[c0 + q];
+      const afqmc_kpt_problem& p = j.p;
+      Carve cv(j.ws);
+      GreensWs g;
+      carve_greens(cv, dims_of(p), g);
+      WeightArgs& a = B.a[q];
+      a.nf = (int64_t)p.nk * p.nchol * 2;
+      a.x = j.x;
+      a.xbar = (const cpx<double>*)j.xbar;
+      a.logdet = (cpx<double>*)p.logdet;
+      a.logdet_new = (const cpx<double>*)g.logdet_new;
+      a.weight = p.weight;
+      a.status = p.status;
+      cnt[q] = p.nwalk;
+    }
+    const long long g = batch_close(B, cnt);
+    if (g < 0) return hipErrorInvalidValue;
+    if (g == 0) continue;
+    hipLaunchKernelGGL(weight_kernel, dim3((unsigned)g), dim3(256), 0, s, B);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace afqmc

@@ -1,12 +1,16 @@
-// Host-side internal interface of the k-point AFQMC library: workspace layout and the
-// per-entry launch sequences (one problem at a time).
+// Host-side internal interface of the k-point AFQMC library: workspace layout, problem
+// batches ("jobs") and the per-entry launch sequences.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
+#include <functional>
+#include <string>
+
 #include "../../include/afqmc_kpt.h"
+#include "batch.h"
 #include "timing.h"
 
 namespace afqmc {
@@ -49,28 +53,93 @@ struct VbiasWs { void* parts; };
 size_t carve_greens(Carve& c, const Dims& d, GreensWs& g);
 size_t carve_vbias(Carve& c, const Dims& d, VbiasWs& v);
 
+// Workspace of one problem for one entry (every entry's layout starts with the Green's
+// function slots).
 size_t ws_bytes_entry(const afqmc_kpt_problem& p, int entry);
 
-// Launch sequences (arguments already validated).
-hipError_t run_prepare(const afqmc_kpt_problem& p, const void* H1, void* ws, hipStream_t s);
-hipError_t run_greens(const afqmc_kpt_problem& p, void* ws, bool write_logdet_new_only,
-                      hipStream_t s);
-hipError_t run_vbias(const afqmc_kpt_problem& p, void* xbar, void* X, void* ws, hipStream_t s);
-hipError_t run_vhs(const afqmc_kpt_problem& p, const double* x, const void* xbar, void* vhs,
-                   void* ws, hipStream_t s);
-hipError_t run_propagate(const afqmc_kpt_problem& p, const void* vhs, const double* x,
-                         const void* xbar, int flags, void* ws, hipStream_t s);
-hipError_t run_ortho(const afqmc_kpt_problem& p, void* ws, hipStream_t s);
-hipError_t run_energy(const afqmc_kpt_problem& p, void* E, void* ws, hipStream_t s);
-hipError_t run_energy_backward(const afqmc_kpt_problem& p, const void* gE, void* gGh, void* ws,
-                               hipStream_t s);
+// One problem of a batch with its workspace region and its slices of the packed per-call
+// buffers (unused ones are null).
+struct Job {
+  afqmc_kpt_problem p;
+  void* ws;
+  const double* x;  // fields of the current step [W][nk][C][2]
+  void* xbar;       // [W][nk][C][2] complex128
+  void* X;          // [W][nk][C] complex128
+  void* vhs;        // [W][nk*m][nk*m] in the contraction precision
+  void* E;          // [W][3] complex128
+  const void* gE;   // [W] complex128
+  void* gGh;        // like Gh
+};
 
-// Kernels shared across translation units.
-hipError_t launch_small_gj(const afqmc_kpt_problem& p, int mode, const void* S_in, void* out,
-                           void* logdet_out, hipStream_t s);
-hipError_t launch_greens_solve(const afqmc_kpt_problem& p, const void* oinvT, hipStream_t s);
-hipError_t launch_cholesky_trace(const afqmc_kpt_problem& p, void* X, void* parts, hipStream_t s);
+// Calls fn(ids, count) for groups of at most AFQMC_MAXP jobs with equal key(job index),
+// in first-seen order; stops at the first error.
+template <class KeyFn, class Fn>
+hipError_t for_groups(int n, KeyFn key, Fn fn) {
+  if (n <= 0) return hipSuccess;
+  char done_small[64];
+  char* done = n <= 64 ? done_small : new char[n];
+  for (int i = 0; i < n; ++i) done[i] = 0;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    if (done[i]) continue;
+    const auto k = key(i);
+    int ids[AFQMC_MAXP];
+    int c = 0;
+    for (int j = i; j < n && c < AFQMC_MAXP; ++j)
+      if (!done[j] && key(j) == k) { ids[c++] = j; done[j] = 1; }
+    e = fn(ids, c);
+  }
+  if (done != done_small) delete[] done;
+  return e;
+}
+
+// Launch sequences over a batch of jobs (arguments already validated).
+hipError_t run_prepare(const afqmc_kpt_problem& p, const void* H1, void* ws, hipStream_t s);
+hipError_t run_greens(const Job* jobs, int n, bool write_logdet_new_only, hipStream_t s);
+hipError_t run_vbias(const Job* jobs, int n, hipStream_t s);
+hipError_t run_vhs(const Job* jobs, int n, hipStream_t s);
+hipError_t run_propagate(const Job* jobs, int n, int flags, hipStream_t s);
+hipError_t run_ortho(const Job* jobs, int n, hipStream_t s);
+hipError_t run_energy(const Job* jobs, int n, hipStream_t s);
+hipError_t run_energy_backward(const Job* jobs, int n, hipStream_t s);
+
+// Kernels shared across translation units.  launch_cholesky_trace writes X (and xbar when
+// requested) of every job; parts are the per-job split-K slices.
+hipError_t launch_small_gj(const Job* jobs, int n, int mode, void* const* S_in,
+                           void* const* out, void* const* logdet_out, hipStream_t s);
+hipError_t launch_cholesky_trace(const Job* jobs, int n, void* const* X, void* const* xbar,
+                                 void* const* parts, hipStream_t s);
 
 enum { GJ_MODE_GREENS = 0, GJ_MODE_CHOL_INV = 1 };
+
+// Autotuned tile shapes of the large contractions.  A stage's candidates are numbered
+// from 0 (the built-in default); the cache maps (stage, precision, shapes of the batch) to
+// the measured fastest candidate.
+enum TuneStage { TS_TAYLOR = 0, TS_VHS = 1, TS_VBIAS = 2, TS_COUNT = 3 };
+std::string tune_key(int stage, const Job* jobs, const int* ids, int c);
+int tune_lookup(const std::string& key);
+void tune_store(const std::string& key, int choice);
+int tune_ncand(int stage, int prec);
+// Times every candidate of a stage for one group (run(choice) launches it) and caches the
+// fastest.  Synchronises the stream.
+hipError_t tune_group(int stage, const Job* jobs, const int* ids, int c,
+                      const std::function<hipError_t(int)>& run, hipStream_t s);
+// Per-stage tuners over a batch, grouped exactly as the entries group their launches.
+hipError_t tune_taylor(const Job* jobs, int n, hipStream_t s);
+hipError_t tune_vhs(const Job* jobs, int n, hipStream_t s);
+hipError_t tune_vbias(const Job* jobs, int n, hipStream_t s);
+
+// One tile candidate of a stage for a group of jobs (the entries call these through the
+// cache; the autotuner times them).
+hipError_t launch_taylor_group(const Job* jobs, const int* ids, int c, int choice,
+                               const void* const* tin, void* const* tout, void* const* acc,
+                               double alpha_scale, hipStream_t s);
+hipError_t launch_vhs_group(const Job* jobs, const int* ids, int c, int choice,
+                            void* const* zeta, hipStream_t s);
+hipError_t launch_vbias_group(const Job* jobs, const int* ids, int c, int choice,
+                              void* const* parts, hipStream_t s);
+
+// Workspace slots of the propagation used by the autotuner.
+void propagate_slots(const Job& j, void** acc, void** t0, void** t1);
 
 }  // namespace afqmc

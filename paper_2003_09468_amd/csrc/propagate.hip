@@ -15,8 +15,7 @@
 
 namespace afqmc {
 
-hipError_t launch_weights(const afqmc_kpt_problem& p, const double* x, const void* xbar,
-                          const void* logdet_new, hipStream_t s);
+hipError_t launch_weights(const Job* jobs, int n, hipStream_t s);
 
 // out[w][(k p)][j] = sum_q bhalf[k][p][q] in[w][(k q)][j]; optionally also acc = out and a
 // copy in the contraction precision T.
@@ -78,49 +77,99 @@ struct OpTaylor {
   }
 };
 
+// One-body half step of every job of a group; in/out/outT give each job's operands.
 template <typename TO>
-static hipError_t launch_bhalf(const afqmc_kpt_problem& p, const void* in, void* out, void* outT,
-                               hipStream_t s) {
-  OpBhalf<TO> op;
-  op.M = p.m; op.K = p.m; op.N = p.nk * p.nocc;
-  op.nbatch = p.nwalk * p.nk;
-  op.nk = p.nk;
-  op.B = (const cpx<double>*)p.bhalf;
-  op.in = (const cpx<double>*)in;
-  op.out = (cpx<double>*)out;
-  op.outT = (cpx<TO>*)outT;
+static hipError_t launch_bhalf(const Job* jobs, const int* ids, int c, void* const* in,
+                               void* const* out, void* const* outT, hipStream_t s) {
+  OpBhalf<TO> ops[AFQMC_MAXP];
+  for (int q = 0; q < c; ++q) {
+    const afqmc_kpt_problem& p = jobs[ids[q]].p;
+    OpBhalf<TO>& op = ops[q];
+    op.M = p.m; op.K = p.m; op.N = p.nk * p.nocc;
+    op.nbatch = p.nwalk * p.nk;
+    op.nk = p.nk;
+    op.B = (const cpx<double>*)p.bhalf;
+    op.in = (const cpx<double>*)in[ids[q]];
+    op.out = out ? (cpx<double>*)out[ids[q]] : nullptr;
+    op.outT = outT ? (cpx<TO>*)outT[ids[q]] : nullptr;
+  }
   TimedScope ts(KC_BHALF, s);
-  if (p.m <= 16) return launch_cgemm<16, 64, 16, 1, 4>(op, s);
-  return launch_cgemm<32, 64, 16, 2, 2>(op, s);
+  int mmax = 0;
+  for (int q = 0; q < c; ++q) mmax = jobs[ids[q]].p.m > mmax ? jobs[ids[q]].p.m : mmax;
+  if (mmax <= 16) return launch_ops<16, 64, 16, 1, 4>(ops, c, s);
+  return launch_ops<32, 64, 16, 2, 2>(ops, c, s);
+}
+
+// Taylor tile class of an FP32 problem: one column tile spans all nk*nocc columns
+// (rounded up to 16), each of the 4 waves owning 16 rows x BN columns.
+static int taylor_class(const afqmc_kpt_problem& p) {
+  if (p.prec != AFQMC_PREC_FP32) return 0;
+  const int c = (p.nk * p.nocc + 15) / 16;
+  return c <= 8 ? c : 9;
 }
 
 template <typename T>
-static hipError_t launch_taylor(const afqmc_kpt_problem& p, const void* vhs, const void* tin,
-                                void* tout, void* acc, double alpha, hipStream_t s) {
-  OpTaylor<T> op;
-  op.M = p.nk * p.m; op.K = p.nk * p.m; op.N = p.nk * p.nocc;
-  op.nbatch = p.nwalk;
-  op.alpha = (T)alpha;
-  op.V = (const cpx<T>*)vhs;
-  op.Tin = (const cpx<T>*)tin;
-  op.Tout = (cpx<T>*)tout;
-  op.acc = (cpx<double>*)acc;
-  TimedScope ts(KC_TAYLOR, s);
-  // FP32: one column tile spans all nk*nocc columns (rounded up to 16), each of the 4 waves
-  // owning 16 rows x BN columns.  FP64: 64 x 32 tiles (measured fastest for the 16x16x4
-  // FP64 MFMA at 702 x 108 x 702).
-  if (sizeof(T) == 8) return launch_cgemm<64, 32, 16, 4, 1>(op, s);
-  switch ((op.N + 15) / 16) {
-    case 1: return launch_cgemm<64, 16, 16, 4, 1>(op, s);
-    case 2: return launch_cgemm<64, 32, 16, 4, 1>(op, s);
-    case 3: return launch_cgemm<64, 48, 16, 4, 1>(op, s);
-    case 4: return launch_cgemm<64, 64, 16, 4, 1>(op, s);
-    case 5: return launch_cgemm<64, 80, 16, 4, 1>(op, s);
-    case 6: return launch_cgemm<64, 96, 16, 4, 1>(op, s);
-    case 7: return launch_cgemm<64, 112, 16, 4, 1>(op, s);
-    case 8: return launch_cgemm<64, 128, 16, 4, 1>(op, s);
-    default: return launch_cgemm<64, 64, 16, 2, 2>(op, s);
+static hipError_t taylor_tiles(const OpTaylor<T>* ops, int c, int cls, int choice,
+                               hipStream_t s) {
+  if (sizeof(T) == 8) {
+    // 64 x 32 tiles: measured fastest for the 16x16x4 FP64 MFMA at 702 x 108 x 702
+    switch (choice) {
+      case 1: return launch_ops<64, 64, 16, 2, 2>(ops, c, s);
+      case 2: return launch_ops<32, 64, 16, 2, 2>(ops, c, s);
+      case 3: return launch_ops<32, 32, 16, 2, 2>(ops, c, s);
+      default: return launch_ops<64, 32, 16, 4, 1>(ops, c, s);
+    }
   }
+  if (choice == 1) return launch_ops<64, 64, 16, 2, 2>(ops, c, s);
+  if (choice == 2) return launch_ops<64, 32, 16, 4, 1>(ops, c, s);
+  switch (cls) {
+    case 1: return launch_ops<64, 16, 16, 4, 1>(ops, c, s);
+    case 2: return launch_ops<64, 32, 16, 4, 1>(ops, c, s);
+    case 3: return launch_ops<64, 48, 16, 4, 1>(ops, c, s);
+    case 4: return launch_ops<64, 64, 16, 4, 1>(ops, c, s);
+    case 5: return launch_ops<64, 80, 16, 4, 1>(ops, c, s);
+    case 6: return launch_ops<64, 96, 16, 4, 1>(ops, c, s);
+    case 7: return launch_ops<64, 112, 16, 4, 1>(ops, c, s);
+    case 8: return launch_ops<64, 128, 16, 4, 1>(ops, c, s);
+    default: return launch_ops<64, 64, 16, 2, 2>(ops, c, s);
+  }
+}
+
+// One Taylor term, T_j = alpha vhs T_{j-1}, acc += T_j, for a group of jobs of one
+// precision and tile class; alpha = -sqrt(dt) * alpha_scale per job.
+hipError_t launch_taylor_group(const Job* jobs, const int* ids, int c, int choice,
+                               const void* const* tin, void* const* tout, void* const* acc,
+                               double alpha_scale, hipStream_t s) {
+  TimedScope ts(KC_TAYLOR, s);
+  const int cls = taylor_class(jobs[ids[0]].p);
+  if (jobs[ids[0]].p.prec == AFQMC_PREC_FP32) {
+    OpTaylor<float> ops[AFQMC_MAXP];
+    for (int q = 0; q < c; ++q) {
+      const Job& j = jobs[ids[q]];
+      OpTaylor<float>& op = ops[q];
+      op.M = j.p.nk * j.p.m; op.K = op.M; op.N = j.p.nk * j.p.nocc;
+      op.nbatch = j.p.nwalk;
+      op.alpha = (float)(-sqrt(j.p.dt) * alpha_scale);
+      op.V = (const cpx<float>*)j.vhs;
+      op.Tin = (const cpx<float>*)tin[ids[q]];
+      op.Tout = tout ? (cpx<float>*)tout[ids[q]] : nullptr;
+      op.acc = (cpx<double>*)acc[ids[q]];
+    }
+    return taylor_tiles<float>(ops, c, cls, choice, s);
+  }
+  OpTaylor<double> ops[AFQMC_MAXP];
+  for (int q = 0; q < c; ++q) {
+    const Job& j = jobs[ids[q]];
+    OpTaylor<double>& op = ops[q];
+    op.M = j.p.nk * j.p.m; op.K = op.M; op.N = j.p.nk * j.p.nocc;
+    op.nbatch = j.p.nwalk;
+    op.alpha = -sqrt(j.p.dt) * alpha_scale;
+    op.V = (const cpx<double>*)j.vhs;
+    op.Tin = (const cpx<double>*)tin[ids[q]];
+    op.Tout = tout ? (cpx<double>*)tout[ids[q]] : nullptr;
+    op.acc = (cpx<double>*)acc[ids[q]];
+  }
+  return taylor_tiles<double>(ops, c, cls, choice, s);
 }
 
 // Layout: the Green's-function slots come first in every entry's workspace, so that
@@ -143,40 +192,73 @@ size_t propagate_ws_bytes(const afqmc_kpt_problem& p) {
   return carve_propagate(c, p, &a, &b, &t, g);
 }
 
-template <typename T>
-static hipError_t propagate_typed(const afqmc_kpt_problem& p, const void* vhs, void* acc, void* t0,
-                                  void* t1, hipStream_t s) {
-  hipError_t e;
-  // T_0 = bhalf U (FP64), acc = T_0, t0 = T_0 in the Taylor precision
-  e = launch_bhalf<T>(p, p.U, acc, t0, s);
-  if (e != hipSuccess) return e;
-  const double sdt = sqrt(p.dt);
-  void* tin = t0;
-  void* tout = t1;
-  for (int j = 1; j <= 6; ++j) {
-    e = launch_taylor<T>(p, vhs, tin, (j < 6) ? tout : nullptr, acc, -sdt / j, s);
-    if (e != hipSuccess) return e;
-    void* t = tin; tin = tout; tout = t;
-  }
-  // U = bhalf acc (FP64)
-  return launch_bhalf<double>(p, acc, p.U, nullptr, s);
+void propagate_slots(const Job& j, void** acc, void** t0, void** t1) {
+  Carve c(j.ws);
+  GreensWs g;
+  carve_propagate(c, j.p, acc, t0, t1, g);
 }
 
-hipError_t run_propagate(const afqmc_kpt_problem& p, const void* vhs, const double* x,
-                         const void* xbar, int flags, void* ws, hipStream_t s) {
-  Carve c(ws);
-  void *acc, *t0, *t1;
-  GreensWs g;
-  carve_propagate(c, p, &acc, &t0, &t1, g);
-  hipError_t e = (p.prec == AFQMC_PREC_FP32) ? propagate_typed<float>(p, vhs, acc, t0, t1, s)
-                                             : propagate_typed<double>(p, vhs, acc, t0, t1, s);
-  if (e != hipSuccess) return e;
+static int taylor_key(const afqmc_kpt_problem& p) { return p.prec * 16 + taylor_class(p); }
+
+// U <- bhalf T6(-sqrt(dt) vhs) bhalf U for every job.
+static hipError_t propagate_jobs(const Job* J, int c, hipStream_t s) {
+  void *acc[AFQMC_MAXP], *t0[AFQMC_MAXP], *t1[AFQMC_MAXP], *U[AFQMC_MAXP];
+  for (int q = 0; q < c; ++q) {
+    propagate_slots(J[q], &acc[q], &t0[q], &t1[q]);
+    U[q] = J[q].p.U;
+  }
+  return for_groups(
+      c, [&](int i) { return taylor_key(J[i].p); },
+      [&](const int* ids, int g) -> hipError_t {
+        const bool f32 = J[ids[0]].p.prec == AFQMC_PREC_FP32;
+        // T_0 = bhalf U (FP64), acc = T_0, t0 = T_0 in the Taylor precision
+        hipError_t e = f32 ? launch_bhalf<float>(J, ids, g, U, acc, t0, s)
+                           : launch_bhalf<double>(J, ids, g, U, acc, t0, s);
+        if (e != hipSuccess) return e;
+        const int choice = tune_lookup(tune_key(TS_TAYLOR, J, ids, g));
+        void** tin = t0;
+        void** tout = t1;
+        for (int j = 1; j <= 6; ++j) {
+          e = launch_taylor_group(J, ids, g, choice, tin, (j < 6) ? tout : nullptr, acc,
+                                  1.0 / j, s);
+          if (e != hipSuccess) return e;
+          void** t = tin; tin = tout; tout = t;
+        }
+        // U = bhalf acc (FP64)
+        return launch_bhalf<double>(J, ids, g, acc, U, nullptr, s);
+      });
+}
+
+hipError_t tune_taylor(const Job* jobs, int n, hipStream_t s) {
+  for (int c0 = 0; c0 < n; c0 += AFQMC_MAXP) {
+    const int c = (n - c0 < AFQMC_MAXP) ? n - c0 : AFQMC_MAXP;
+    const Job* J = jobs + c0;
+    void *acc[AFQMC_MAXP], *t0[AFQMC_MAXP], *t1[AFQMC_MAXP];
+    for (int q = 0; q < c; ++q) propagate_slots(J[q], &acc[q], &t0[q], &t1[q]);
+    const hipError_t e = for_groups(
+        c, [&](int i) { return taylor_key(J[i].p); },
+        [&](const int* ids, int g) -> hipError_t {
+          return tune_group(
+              TS_TAYLOR, J, ids, g,
+              [&](int ch) { return launch_taylor_group(J, ids, g, ch, t0, t1, acc, 1.0, s); }, s);
+        });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t run_propagate(const Job* jobs, int n, int flags, hipStream_t s) {
+  for (int c0 = 0; c0 < n; c0 += AFQMC_MAXP) {
+    const int c = (n - c0 < AFQMC_MAXP) ? n - c0 : AFQMC_MAXP;
+    hipError_t e = propagate_jobs(jobs + c0, c, s);
+    if (e != hipSuccess) return e;
+  }
   // new overlap and Gh; weights from the old and new log overlaps
-  e = run_greens(p, ws, true, s);
+  hipError_t e = run_greens(jobs, n, true, s);
   if (e != hipSuccess) return e;
-  e = launch_weights(p, x, xbar, g.logdet_new, s);
+  e = launch_weights(jobs, n, s);
   if (e != hipSuccess) return e;
-  if (flags & AFQMC_PROPAGATE_ORTHO) return run_ortho(p, ws, s);
+  if (flags & AFQMC_PROPAGATE_ORTHO) return run_ortho(jobs, n, s);
   return hipSuccess;
 }
 
@@ -244,37 +326,44 @@ size_t ortho_ws_bytes(const afqmc_kpt_problem& p) {
   return carve_ortho(c, p, &a, &b, &t, g);
 }
 
-hipError_t run_ortho(const afqmc_kpt_problem& p, void* ws, hipStream_t s) {
-  Carve c(ws);
-  void *S, *R, *Ut;
-  GreensWs g;
-  carve_ortho(c, p, &S, &R, &Ut, g);
-  const int n = p.nk * p.nocc;
-  const int Nn = p.nk * p.m;
-  hipError_t e;
-  // pass 0: U -> Ut, pass 1: Ut -> U
-  for (int pass = 0; pass < 2; ++pass) {
-    TimedScope ts(KC_ORTHO, s);
-    const cpx<double>* src = (const cpx<double>*)(pass == 0 ? p.U : Ut);
-    cpx<double>* dst = (cpx<double>*)(pass == 0 ? Ut : p.U);
-    OpGram gm;
-    gm.M = n; gm.N = n; gm.K = Nn; gm.nbatch = p.nwalk;
-    gm.U = src;
-    gm.S = (cpx<double>*)S;
-    e = launch_cgemm<32, 32, 16, 2, 2>(gm, s);
-    if (e != hipSuccess) return e;
-    e = launch_small_gj(p, GJ_MODE_CHOL_INV, S, R, nullptr, s);
-    if (e != hipSuccess) return e;
-    OpRightMul r;
-    r.M = Nn; r.N = n; r.K = n; r.nbatch = p.nwalk;
-    r.U = src;
-    r.R = (const cpx<double>*)R;
-    r.Uo = dst;
-    e = launch_cgemm<64, 64, 16, 2, 2>(r, s);
-    if (e != hipSuccess) return e;
+hipError_t run_ortho(const Job* jobs, int n, hipStream_t s) {
+  for (int c0 = 0; c0 < n; c0 += AFQMC_MAXP) {
+    const int c = (n - c0 < AFQMC_MAXP) ? n - c0 : AFQMC_MAXP;
+    const Job* J = jobs + c0;
+    void *S[AFQMC_MAXP], *R[AFQMC_MAXP], *Ut[AFQMC_MAXP];
+    for (int q = 0; q < c; ++q) {
+      Carve cv(J[q].ws);
+      GreensWs g;
+      carve_ortho(cv, J[q].p, &S[q], &R[q], &Ut[q], g);
+    }
+    // pass 0: U -> Ut, pass 1: Ut -> U
+    for (int pass = 0; pass < 2; ++pass) {
+      TimedScope ts(KC_ORTHO, s);
+      OpGram gm[AFQMC_MAXP];
+      OpRightMul rm[AFQMC_MAXP];
+      for (int q = 0; q < c; ++q) {
+        const afqmc_kpt_problem& p = J[q].p;
+        const int nn = p.nk * p.nocc, Nn = p.nk * p.m;
+        const cpx<double>* src = (const cpx<double>*)(pass == 0 ? p.U : Ut[q]);
+        cpx<double>* dst = (cpx<double>*)(pass == 0 ? Ut[q] : p.U);
+        gm[q].M = nn; gm[q].N = nn; gm[q].K = Nn; gm[q].nbatch = p.nwalk;
+        gm[q].U = src;
+        gm[q].S = (cpx<double>*)S[q];
+        rm[q].M = Nn; rm[q].N = nn; rm[q].K = nn; rm[q].nbatch = p.nwalk;
+        rm[q].U = src;
+        rm[q].R = (const cpx<double>*)R[q];
+        rm[q].Uo = dst;
+      }
+      hipError_t e = launch_ops<32, 32, 16, 2, 2>(gm, c, s);
+      if (e != hipSuccess) return e;
+      e = launch_small_gj(J, c, GJ_MODE_CHOL_INV, S, R, nullptr, s);
+      if (e != hipSuccess) return e;
+      e = launch_ops<64, 64, 16, 2, 2>(rm, c, s);
+      if (e != hipSuccess) return e;
+    }
   }
   // Gh and the log overlap of the re-orthonormalised walkers
-  return run_greens(p, ws, false, s);
+  return run_greens(jobs, n, false, s);
 }
 
 }  // namespace afqmc

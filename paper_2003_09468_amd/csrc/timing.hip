@@ -28,6 +28,9 @@ bool timing_on() { return g_on; }
 
 TimedScope::TimedScope(int kc, hipStream_t s) : rec_(-1), s_(s) {
   if (!g_on) return;
+  // launches being captured into a graph are not timed
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_used >= g_pool.size()) { ++g_dropped; return; }
   rec_ = (int)g_used++;

@@ -80,12 +80,12 @@ def test_workspace_sizes_positive_and_stable(L):
     p = good_problem()
     out = ctypes.c_size_t()
     sizes = []
-    for e in range(8):
+    for e in range(9):
         assert L.afqmc_kpt_workspace_bytes(ctypes.byref(p), 1, e, ctypes.byref(out)) == 0
         sizes.append(out.value)
         assert out.value % 256 == 0
     assert all(s > 0 for s in sizes)
-    assert L.afqmc_kpt_workspace_bytes(ctypes.byref(p), 1, 8, ctypes.byref(out)) == -1
+    assert L.afqmc_kpt_workspace_bytes(ctypes.byref(p), 1, 9, ctypes.byref(out)) == -1
     assert L.afqmc_kpt_workspace_bytes(ctypes.byref(p), 1, 0, None) == -2
 
 
@@ -178,3 +178,105 @@ def test_product_path_has_no_cpu_fallback():
     for f in os.listdir(os.path.join(ROOT, "paper_2003_09468_amd")):
         if f.endswith(".py"):
             assert "import oracle" not in open(os.path.join(ROOT, "paper_2003_09468_amd", f)).read()
+
+
+# ---------------------------------------------------------------------------
+# batches: packed buffers, the step block, the captured block and the autotuner
+
+def two_problems():
+    a, b = good_problem(), good_problem()
+    b.mesh[0], b.mesh[1], b.mesh[2], b.nk, b.m, b.nchol, b.nwalk = 2, 2, 2, 8, 26, 208, 128
+    b.prec = 1
+    arr = (B.Problem * 2)(a, b)
+    return arr
+
+
+def one_slice(p, buf):
+    W, nk, C = p.nwalk, p.nk, p.nchol
+    N, n = nk * p.m, nk * p.nocc
+    return {0: 8 * W * nk * C * 2, 1: 16 * W * nk * C * 2, 2: 16 * W * nk * C,
+            3: (8 if p.prec == 1 else 16) * W * N * N, 4: 48 * W, 5: 16 * W,
+            6: 16 * W * n * N}[buf]
+
+
+@pytest.mark.parametrize("buf", range(7))
+def test_buffer_layout_packs_problems(L, buf):
+    arr = two_problems()
+    off = (ctypes.c_size_t * 3)()
+    assert L.afqmc_kpt_buffer_layout(arr, 2, buf, off) == 0
+    s0, s1 = one_slice(arr[0], buf), one_slice(arr[1], buf)
+    assert off[0] == 0
+    assert off[1] % 256 == 0 and s0 <= off[1] < s0 + 256
+    assert off[2] == off[1] + s1
+    assert L.afqmc_kpt_buffer_layout(arr, 2, 7, off) == -1
+    assert L.afqmc_kpt_buffer_layout(arr, 2, buf, None) == -2
+
+
+def test_batch_workspace_is_sum_of_parts(L):
+    arr = two_problems()
+    out = ctypes.c_size_t()
+    for e in range(9):
+        parts = []
+        for i in range(2):
+            assert L.afqmc_kpt_workspace_bytes(ctypes.byref(arr[i]), 1, e, ctypes.byref(out)) == 0
+            parts.append(out.value)
+        assert L.afqmc_kpt_workspace_bytes(arr, 2, e, ctypes.byref(out)) == 0
+        assert out.value == sum(parts)
+
+
+def test_batch_validates_every_problem(L):
+    arr = two_problems()
+    arr[1].nocc = 30  # > m
+    ws = ctypes.c_void_p(0x100000)
+    assert L.afqmc_kpt_greens(arr, 2, ws, 1 << 40, None) == -1
+    arr = two_problems()
+    arr[1].Lh32 = None  # FP32 system without its complex64 copy
+    assert L.afqmc_kpt_energy(arr, 2, ctypes.c_void_p(0x2000), ws, 1 << 40, None) == -2
+
+
+def step_args(**kw):
+    a = dict(x=0x2000, nsteps=10, xbar=0x4000, vhs=0x8000, E=0xc000, flags=3, ws=0x100000,
+             nbytes=1 << 40)
+    a.update(kw)
+    return a
+
+
+def call_step(L, arr, n, a):
+    return L.afqmc_kpt_step(arr, n, a["x"], a["nsteps"], a["xbar"], a["vhs"], a["E"], a["flags"],
+                            a["ws"], a["nbytes"], None)
+
+
+def test_step_validation(L):
+    arr = two_problems()
+    assert call_step(L, arr, 2, step_args(nsteps=0)) == -1
+    assert call_step(L, arr, 2, step_args(flags=4)) == -1
+    assert call_step(L, arr, 2, step_args(xbar=None)) == -2
+    assert call_step(L, arr, 2, step_args(vhs=0x8008)) == -3
+    assert call_step(L, arr, 2, step_args(E=None)) == -2           # energy requested
+    assert call_step(L, arr, 2, step_args(ws=None)) == -4
+    assert call_step(L, arr, 2, step_args(nbytes=256)) == -4
+    h = ctypes.c_void_p()
+    a = step_args()
+    assert L.afqmc_kpt_graph_create(arr, 2, a["x"], a["nsteps"], a["xbar"], a["vhs"], a["E"],
+                                    a["flags"], a["ws"], a["nbytes"], None) == -2
+    assert L.afqmc_kpt_graph_create(arr, 2, a["x"], 0, a["xbar"], a["vhs"], a["E"], a["flags"],
+                                    a["ws"], a["nbytes"], ctypes.byref(h)) == -1
+    assert h.value is None
+    assert L.afqmc_kpt_graph_launch(None, None) == -2
+    assert L.afqmc_kpt_graph_destroy(None) == -2
+    assert L.afqmc_kpt_autotune(arr, 2, None, a["ws"], a["nbytes"], None) == -2
+    assert L.afqmc_kpt_autotune(arr, 2, a["vhs"], a["ws"], 256, None) == -4
+
+
+def test_step_reaches_device_check(L):
+    from tests.conftest import gpu_available
+    if gpu_available():
+        pytest.skip("a GPU is present")
+    arr = two_problems()
+    assert call_step(L, arr, 2, step_args()) == -5
+    assert call_step(L, arr, 2, step_args(E=None, flags=1)) == -5  # no energy: E unused
+    h = ctypes.c_void_p()
+    a = step_args()
+    assert L.afqmc_kpt_graph_create(arr, 2, a["x"], a["nsteps"], a["xbar"], a["vhs"], a["E"],
+                                    a["flags"], a["ws"], a["nbytes"], ctypes.byref(h)) == -5
+    assert L.afqmc_kpt_autotune(arr, 2, a["vhs"], a["ws"], a["nbytes"], None) == -5
