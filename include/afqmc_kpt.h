@@ -154,8 +154,8 @@ afqmc_status afqmc_kpt_prepare(const afqmc_kpt_problem* p, int nprob, const void
 /* Overlap and half-rotated Green's function (Green's-function equations of the
  * standard representation; blocked by the trial's k structure):
  *   O = A^H U (nk*nocc square), logdet = log det O, Gh = (U O^{-1})^T,
- * all FP64, via Gauss-Jordan inversion with partial pivoting.
- * Reads U; writes Gh, logdet and ORs status.  Requires nk*nocc <= 128. */
+ * all FP64, via blocked Gauss-Jordan inversion with partial (row) pivoting.
+ * Reads U; writes Gh, logdet and ORs status.  Requires nk*nocc <= 256. */
 afqmc_status afqmc_kpt_greens(const afqmc_kpt_problem* p, int nprob,
                               void* ws, size_t ws_bytes, void* stream);
 
@@ -196,7 +196,8 @@ afqmc_status afqmc_kpt_propagate(const afqmc_kpt_problem* p, int nprob, const vo
 /* Walker re-orthonormalisation (once per block, "Scaling and Performance"):
  * U <- Q of the thin QR factorisation U = Q R with diag(R) real positive
  * (FP64 Cholesky-QR applied twice), then Gh and logdet are recomputed.
- * Gh and the local energy are unchanged by it.  Requires nk*nocc <= 128. */
+ * Gh and the local energy are unchanged by it.  Requires nk*nocc <= 128
+ * (AFQMC_EUNSUPPORTED otherwise, also for AFQMC_PROPAGATE_ORTHO elsewhere). */
 afqmc_status afqmc_kpt_orthonormalize(const afqmc_kpt_problem* p, int nprob,
                                       void* ws, size_t ws_bytes, void* stream);
 

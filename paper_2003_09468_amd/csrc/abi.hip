@@ -102,7 +102,7 @@ afqmc_status check_dims(const afqmc_kpt_problem& p) {
   if (!(p.dt > 0.0) || !isfinite(p.dt)) return AFQMC_EINVAL;
   // sizes the kernels implement
   if (p.m > 64 || p.nocc > 16) return AFQMC_EUNSUPPORTED;
-  if ((int64_t)p.nk * p.nocc > 128) return AFQMC_EUNSUPPORTED;
+  if ((int64_t)p.nk * p.nocc > 256) return AFQMC_EUNSUPPORTED;
   if ((int64_t)p.nk * p.nk * p.nk > (1 << 24)) return AFQMC_EUNSUPPORTED;
   // 32-bit row/column indices inside the GEMM tiles
   if ((int64_t)p.nk * p.m * p.m > 0x7fffffffLL || (int64_t)p.nk * p.m * p.nchol > 0x7fffffffLL)
@@ -134,6 +134,13 @@ afqmc_status check_problems(const afqmc_kpt_problem* p, int nprob, unsigned need
     AFQMC_TRY(check_dims(p[i]));
     AFQMC_TRY(check_fields(p[i], need));
   }
+  return AFQMC_OK;
+}
+
+// The re-orthonormalisation's Cholesky factorisation holds nk*nocc <= 128 in registers.
+afqmc_status check_ortho(const afqmc_kpt_problem* p, int nprob) {
+  for (int i = 0; i < nprob; ++i)
+    if ((int64_t)p[i].nk * p[i].nocc > 128) return AFQMC_EUNSUPPORTED;
   return AFQMC_OK;
 }
 
@@ -235,6 +242,7 @@ afqmc_status check_step_args(const afqmc_kpt_problem* p, int nprob, const double
   AFQMC_TRY(check_problems(p, nprob, need));
   if (nsteps < 1) return AFQMC_EINVAL;
   if (flags & ~(AFQMC_PROPAGATE_ORTHO | AFQMC_STEP_ENERGY)) return AFQMC_EINVAL;
+  if (flags & AFQMC_PROPAGATE_ORTHO) AFQMC_TRY(check_ortho(p, nprob));
   AFQMC_TRY(check_ptr(x, 8));
   AFQMC_TRY(check_ptr(xbar, 16));
   AFQMC_TRY(check_ptr(vhs, 16));
@@ -331,6 +339,7 @@ afqmc_status afqmc_kpt_propagate(const afqmc_kpt_problem* p, int nprob, const vo
   AFQMC_TRY(check_ptr(x, 8));
   AFQMC_TRY(check_ptr(xbar, 16));
   if (flags & ~AFQMC_PROPAGATE_ORTHO) return AFQMC_EINVAL;
+  if (flags & AFQMC_PROPAGATE_ORTHO) AFQMC_TRY(check_ortho(p, nprob));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_PROPAGATE, ws, ws_bytes));
   AFQMC_TRY(check_device());
   Bufs b;
@@ -344,6 +353,7 @@ afqmc_status afqmc_kpt_propagate(const afqmc_kpt_problem* p, int nprob, const vo
 afqmc_status afqmc_kpt_orthonormalize(const afqmc_kpt_problem* p, int nprob, void* ws,
                                       size_t ws_bytes, void* stream) {
   AFQMC_TRY(check_problems(p, nprob, N_A | N_U | N_GH | N_LOGDET | N_STATUS));
+  AFQMC_TRY(check_ortho(p, nprob));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_ORTHO, ws, ws_bytes));
   AFQMC_TRY(check_device());
   std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_ORTHO, ws, Bufs());

@@ -166,27 +166,28 @@ template <class Op, int BM, int BN, int BK, int WM, int WN>
 __global__ __launch_bounds__(WM* WN * 64) void cgemm_kernel(Op op, int tiles_m, int tiles_n) {
   const int ntiles = tiles_m * tiles_n;
   const long long total = (long long)ntiles * op.nbatch;
-  long long bid = blockIdx.x;
-  if ((total & 7) == 0) bid = (bid & 7) * (total >> 3) + (bid >> 3);
+  const long long bid = xcd_remap(blockIdx.x, total);
   const int b = (int)(bid / ntiles);
   const int rem = (int)(bid % ntiles);
   cgemm_tile<Op, BM, BN, BK, WM, WN>(op, b, rem / tiles_n, rem % tiles_n);
 }
 
-// Several problems in one launch: one workgroup per tile of every problem (the hardware
-// dispatcher hands tiles to CUs as they free up), same XCD remap over the global tile index.
+// Several problems in one launch.  Each problem's workgroup range starts at a multiple of
+// 8 and is padded to one (spare workgroups exit), so every XCD receives an equal share of
+// every problem (tiles of different problems differ in K, hence in cost), and inside a
+// problem the same remap as above keeps each XCD on a contiguous range of tiles.
 template <class Op, int BM, int BN, int BK, int WM, int WN>
 __global__ __launch_bounds__(WM* WN * 64) void cgemm_set_kernel(const OpSet<Op> set) {
-  const long long total = set.first[set.nprob];
-  long long lt = blockIdx.x;
-  if ((total & 7) == 0) lt = (lt & 7) * (total >> 3) + (lt >> 3);
+  const long long gid = blockIdx.x;
   int p = 0;
-  while (p + 1 < set.nprob && lt >= set.first[p + 1]) ++p;
+  while (p + 1 < set.nprob && gid >= set.first[p + 1]) ++p;
   p = __builtin_amdgcn_readfirstlane(p);
-  const long long loc = lt - set.first[p];
+  const long long loc = gid - set.first[p];
+  const long long lt = xcd_remap(loc, set.first[p + 1] - set.first[p]);
   const int ntiles = set.tiles_m[p] * set.tiles_n[p];
-  const int b = (int)(loc / ntiles);
-  const int rem = (int)(loc % ntiles);
+  if (lt >= (long long)ntiles * set.op[p].nbatch) return;
+  const int b = (int)(lt / ntiles);
+  const int rem = (int)(lt % ntiles);
   cgemm_tile<Op, BM, BN, BK, WM, WN>(set.op[p], b, rem / set.tiles_n[p], rem % set.tiles_n[p]);
 }
 
@@ -199,11 +200,13 @@ hipError_t launch_cgemm_set(OpSet<Op>& set, hipStream_t s) {
     set.first[p] = total;
     if (op.M <= 0 || op.N <= 0 || op.K <= 0 || op.nbatch <= 0) {
       set.tiles_m[p] = set.tiles_n[p] = 1;
+      set.op[p].nbatch = 0;  // no tiles: every workgroup of the (empty) range exits
       continue;
     }
     set.tiles_m[p] = (op.M + BM - 1) / BM;
     set.tiles_n[p] = (op.N + BN - 1) / BN;
-    total += (long long)set.tiles_m[p] * set.tiles_n[p] * op.nbatch;
+    const long long t = (long long)set.tiles_m[p] * set.tiles_n[p] * op.nbatch;
+    total += (t + 7) & ~7LL;
   }
   set.first[set.nprob] = total;
   if (total == 0) return hipSuccess;

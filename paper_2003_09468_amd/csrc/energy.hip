@@ -22,9 +22,6 @@
 
 namespace afqmc {
 
-__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t total) {
-  return ((total & 7) == 0) ? (bid & 7) * (total >> 3) + (bid >> 3) : bid;
-}
 
 struct ExchArgs {
   int nk, m, nocc, C, W, nchunk_w;
@@ -45,7 +42,9 @@ __global__ __launch_bounds__(256) void exchange_kernel(const Batch<ExchArgs> B) 
   __shared__ double red[2][256];
 
   long long bid;
-  const int pb = batch_find(B, xcd_remap(blockIdx.x, B.first[B.nprob]), bid);
+  // launch order (consecutive workgroups on different XCDs): neighbouring triples, which
+  // share a slab of Lh, run at the same time on all XCDs
+  const int pb = batch_find(B, blockIdx.x, bid);
   const int nk = B.a[pb].nk, m = B.a[pb].m, nocc = B.a[pb].nocc, C = B.a[pb].C, W = B.a[pb].W;
   const int nchunk_w = B.a[pb].nchunk_w;
   const KMesh mesh = B.a[pb].mesh;
@@ -398,7 +397,9 @@ __global__ __launch_bounds__(256) void exchange_bwd_kernel(const Batch<BwdArgs> 
   __shared__ T XB[4][2][16][17];
 
   long long bid;
-  const int pb = batch_find(B, xcd_remap(blockIdx.x, B.first[B.nprob]), bid);
+  // launch order (consecutive workgroups on different XCDs): neighbouring triples, which
+  // share a slab of Lh, run at the same time on all XCDs
+  const int pb = batch_find(B, blockIdx.x, bid);
   const int nk = B.a[pb].nk, m = B.a[pb].m, nocc = B.a[pb].nocc, C = B.a[pb].C, W = B.a[pb].W;
   const int nchunk_w = B.a[pb].nchunk_w;
   const KMesh mesh = B.a[pb].mesh;

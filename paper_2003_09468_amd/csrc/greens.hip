@@ -305,6 +305,257 @@ __global__ __launch_bounds__(TR * 32) void small_gj_kernel(int mode, const Batch
   }
 }
 
+// ---------------------------------------------------------------------------
+// Blocked Gauss-Jordan inversion of the overlap matrix for n <= 256: one 256-thread
+// workgroup per walker, the matrix updated in place in global memory (L2 resident).
+//
+// Pivoting is implicit: the pivot of column j is the unused physical row q_j of largest
+// modulus, and rows are never exchanged.  With T the product of the elimination steps,
+// T O = P where P[:, j] = e_{q_j}; the in-place storage keeps T[:, q_k] in column k, so
+// O^{-1}[j][q_k] = M[q_j][k] at the end, and det O = sign(j -> q_j) prod_j pivot_j.
+//
+// Columns go in panels of 16.  Each thread owns one physical row of the panel in
+// registers and applies the 16 elimination steps to it (pivot row broadcast through LDS,
+// pivot choice by a block-wide max of (|a|^2, row) keys).  The combined effect of the
+// steps on every other column is the rank-16 update
+//   M[:, rest] += Z M[Q, rest],   Z = panel after the steps - E_Q,  E_Q[q_j][j] = 1,
+// computed on FP64 MFMA 16x16x4 tiles with Z and the pivot rows staged in LDS.
+struct GjbArgs {
+  int n;
+  cpx<double>* M;       // [W][n][n] overlap matrix, destroyed
+  cpx<double>* out;     // [W][n][n] O^{-T}
+  cpx<double>* logdet;  // [W]
+  int* status;          // [W]
+};
+
+constexpr int GJB_NMAX = 256;
+
+template <int NR>
+__device__ __forceinline__ double pick16(const double (&a)[NR], int j) {
+  double v = 0.0;
+#pragma unroll
+  for (int c = 0; c < NR; ++c)
+    if (c == j) v = a[c];
+  return v;
+}
+
+__global__ __launch_bounds__(256) void gj_blocked_kernel(const Batch<GjbArgs> B) {
+  long long wloc;
+  const int pb = batch_find(B, blockIdx.x, wloc);
+  const int n = B.a[pb].n;
+  const int w = (int)wloc;
+  cpx<double>* __restrict__ M = B.a[pb].M + (int64_t)w * n * n;
+  cpx<double>* __restrict__ out = B.a[pb].out + (int64_t)w * n * n;
+
+  __shared__ double Zr[GJB_NMAX][17], Zi[GJB_NMAX][17];
+  __shared__ double Rr[16][GJB_NMAX + 1], Ri[16][GJB_NMAX + 1];
+  __shared__ double rowr[2][16], rowi[2][16];
+  __shared__ unsigned long long red[2][4];
+  __shared__ int qs[GJB_NMAX];
+  __shared__ double pvr[GJB_NMAX], pvi[GJB_NMAX];
+  __shared__ unsigned char vis[GJB_NMAX];
+  __shared__ double lsum[2][4];
+  __shared__ int flag_s;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = tid;  // physical row owned in the panel steps
+  const int np = (n + 15) & ~15, ntile = np >> 4;
+  bool used = false;
+  int bad = 0;
+  if (tid == 0) flag_s = 0;
+
+  for (int j0 = 0; j0 < n; j0 += 16) {
+    const int bw = (n - j0 < 16) ? n - j0 : 16;
+    double pr[16], pi[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      cpx<double> v{0.0, 0.0};
+      if (r < n && c < bw) v = M[(int64_t)r * n + j0 + c];
+      pr[c] = v.re;
+      pi[c] = v.im;
+    }
+    int jq = -1;
+    for (int jj = 0; jj < bw; ++jj) {
+      const int buf = jj & 1;
+      unsigned long long key = 0ull;
+      if (r < n && !used) {
+        const double ar = pick16(pr, jj), ai = pick16(pi, jj);
+        const double a2 = ar * ar + ai * ai;
+        key = ((unsigned long long)__double_as_longlong(a2) & ~0xffull) |
+              (unsigned long long)(255 - r);
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(key, off, 64);
+        key = (o > key) ? o : key;
+      }
+      if (lane == 0) red[buf][wave] = key;
+      __syncthreads();
+      key = red[buf][0];
+#pragma unroll
+      for (int v = 1; v < 4; ++v) key = (red[buf][v] > key) ? red[buf][v] : key;
+      const int q = 255 - (int)(key & 0xffull);
+      if (r == q) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) { rowr[buf][c] = pr[c]; rowi[buf][c] = pi[c]; }
+        used = true;
+        jq = jj;
+      }
+      __syncthreads();
+      double vr = rowr[buf][jj], vi = rowi[buf][jj];
+      double den = vr * vr + vi * vi;
+      if (tid == 0) { qs[j0 + jj] = q; pvr[j0 + jj] = vr; pvi[j0 + jj] = vi; }
+      if (!(den > 0.0) || !isfinite(den)) {
+        bad |= isfinite(den) ? 1 : 2;
+        vr = 1.0; vi = 0.0; den = 1.0;
+      }
+      const double ir = vr / den, ii = -vi / den;  // 1 / pivot
+      if (r == q) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const double xr = pr[c], xi = pi[c];
+          pr[c] = (c == jj) ? ir : xr * ir - xi * ii;
+          pi[c] = (c == jj) ? ii : xr * ii + xi * ir;
+        }
+      } else if (r < n) {
+        const double fr = pick16(pr, jj), fi = pick16(pi, jj);
+        const double gr = fr * ir - fi * ii, gi = fr * ii + fi * ir;  // a_rj / pivot
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const double br = rowr[buf][c], bi = rowi[buf][c];
+          const double ur = pr[c] - (gr * br - gi * bi), ui = pi[c] - (gr * bi + gi * br);
+          pr[c] = (c == jj) ? -gr : ur;
+          pi[c] = (c == jj) ? -gi : ui;
+        }
+      }
+    }
+    // the panel's columns of T back to memory; Z = panel - E_Q to LDS
+    if (r < n) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c < bw) M[(int64_t)r * n + j0 + c] = cpx<double>{pr[c], pi[c]};
+    }
+    if (r < np) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const bool on = (r < n) && (c < bw);
+        Zr[r][c] = on ? pr[c] - ((c == jq) ? 1.0 : 0.0) : 0.0;
+        Zi[r][c] = on ? pi[c] : 0.0;
+      }
+    }
+    __syncthreads();
+    // pivot rows M[q_k][:] of this panel (values before the update) to LDS
+    for (int idx = tid; idx < 16 * np; idx += 256) {
+      const int kk = idx / np, c = idx % np;
+      cpx<double> v{0.0, 0.0};
+      if (kk < bw && c < n && (c < j0 || c >= j0 + 16)) v = M[(int64_t)qs[j0 + kk] * n + c];
+      Rr[kk][c] = v.re;
+      Ri[kk][c] = v.im;
+    }
+    __syncthreads();
+    // M[:, rest] += Z M[Q, rest] on 16x16 tiles, K = 16
+    const int Jp = j0 >> 4;
+    for (int t = wave; t < ntile * ntile; t += 4) {
+      const int I = t / ntile, J = t % ntile;
+      if (J == Jp) continue;
+      v4d cr, ci;
+      const int col = J * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = I * 16 + mfma16<double>::drow(lane, v);
+        cpx<double> x{0.0, 0.0};
+        if (row < n && col < n) x = M[(int64_t)row * n + col];
+        cr[v] = x.re;
+        ci[v] = x.im;
+      }
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) {
+        const int k = kb * 4 + (lane >> 4);
+        const int arow = I * 16 + (lane & 15);
+        cmfma<double>(Zr[arow][k], Zi[arow][k], Rr[k][col], Ri[k][col], cr, ci);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = I * 16 + mfma16<double>::drow(lane, v);
+        if (row < n && col < n) M[(int64_t)row * n + col] = cpx<double>{cr[v], ci[v]};
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) atomicOr(&flag_s, bad);
+
+  // log det = sum_j log(pivot_j) + i pi [sign of j -> q_j]
+  double lr = 0.0, li = 0.0;
+  for (int j = tid; j < n; j += 256) {
+    const double pr = pvr[j], pim = pvi[j];
+    lr += 0.5 * log(pr * pr + pim * pim);
+    li += atan2(pim, pr);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    lr += __shfl_xor(lr, off, 64);
+    li += __shfl_xor(li, off, 64);
+  }
+  if (lane == 0) { lsum[0][wave] = lr; lsum[1][wave] = li; }
+  for (int j = tid; j < n; j += 256) vis[j] = 0;
+  __syncthreads();
+  const int fl = flag_s;
+  if (tid == 0) {
+    // parity of the permutation: n minus the number of cycles
+    int cycles = 0;
+    for (int j = 0; j < n; ++j) {
+      if (vis[j]) continue;
+      ++cycles;
+      for (int x = j; !vis[x]; x = qs[x]) vis[x] = 1;
+    }
+    const double ldr = lsum[0][0] + lsum[0][1] + lsum[0][2] + lsum[0][3];
+    double ldi = lsum[1][0] + lsum[1][1] + lsum[1][2] + lsum[1][3];
+    if ((n - cycles) & 1) ldi += AFQMC_PI;
+    double wi = remainder(ldi, 2.0 * AFQMC_PI);
+    if (wi <= -AFQMC_PI) wi += 2.0 * AFQMC_PI;
+    B.a[pb].logdet[w] = fl ? cpx<double>{0.0, 0.0} : cpx<double>{ldr, wi};
+    if (fl) {
+      int bits = 0;
+      if (fl & 1) bits |= AFQMC_WALKER_SINGULAR;
+      if (fl & 2) bits |= AFQMC_WALKER_NONFINITE;
+      B.a[pb].status[w] |= bits;
+    }
+  }
+  // O^{-T}[q_k][j] = O^{-1}[j][q_k] = M[q_j][k]  (0 for a degenerate walker)
+  for (int idx = tid; idx < n * n; idx += 256) {
+    const int j = idx / n, k = idx % n;
+    const cpx<double> v = fl ? cpx<double>{0.0, 0.0} : M[(int64_t)qs[j] * n + k];
+    out[(int64_t)qs[k] * n + j] = v;
+  }
+}
+
+hipError_t launch_gj_blocked(const Job* jobs, int n, void* const* S, void* const* out,
+                             void* const* logdet_out, hipStream_t s) {
+  for (int c0 = 0; c0 < n; c0 += AFQMC_MAXP) {
+    const int c = (n - c0 < AFQMC_MAXP) ? n - c0 : AFQMC_MAXP;
+    Batch<GjbArgs> B;
+    B.nprob = c;
+    long long cnt[AFQMC_MAXP];
+    for (int q = 0; q < c; ++q) {
+      const afqmc_kpt_problem& p = jobs[c0 + q].p;
+      B.a[q].n = p.nk * p.nocc;
+      if (B.a[q].n > GJB_NMAX) return hipErrorInvalidValue;
+      B.a[q].M = (cpx<double>*)S[c0 + q];
+      B.a[q].out = (cpx<double>*)out[c0 + q];
+      B.a[q].logdet = (cpx<double>*)logdet_out[c0 + q];
+      B.a[q].status = p.status;
+      cnt[q] = p.nwalk;
+    }
+    const long long g = batch_close(B, cnt);
+    if (g < 0) return hipErrorInvalidValue;
+    if (g == 0) continue;
+    hipLaunchKernelGGL(gj_blocked_kernel, dim3((unsigned)g), dim3(256), 0, s, B);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // O[w][(k a)][j] = sum_p conj(A[k][p][a]) U[w][(k p)][j], batched over (w, k)
 struct OpOverlap {
   typedef double T;
@@ -445,7 +696,7 @@ hipError_t run_greens(const Job* jobs, int n, bool write_logdet_new_only, hipStr
     }
     hipError_t e = launch_ops<16, 64, 16, 1, 4>(ov, c, s);
     if (e != hipSuccess) return e;
-    e = launch_small_gj(J, c, GJ_MODE_GREENS, omat, oinvT, ldo, s);
+    e = launch_gj_blocked(J, c, omat, oinvT, ldo, s);
     if (e != hipSuccess) return e;
     e = launch_ops<64, 64, 16, 2, 2>(sv, c, s);
     if (e != hipSuccess) return e;

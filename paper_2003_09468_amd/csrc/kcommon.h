@@ -55,6 +55,16 @@ __device__ __forceinline__ void cmfma(T ar, T ai, T br, T bi, typename mfma16<T>
   di = mfma16<T>::mac(ai, br, di);
 }
 
+// Workgroups are dealt round-robin over the 8 XCDs (workgroup i runs on XCD i % 8).  This
+// bijection of [0, total) gives XCD x the contiguous range of work items
+// [x q + min(x, r), ...) with q = total / 8, r = total % 8, so that items sharing an
+// operand stay in one L2.
+__device__ __forceinline__ long long xcd_remap(long long bid, long long total) {
+  const long long q = total >> 3, r = total & 7;
+  const long long x = bid & 7, i = bid >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
 // k-point index algebra on the device (mesh row-major linearisation).
 struct KMesh {
   int m0, m1, m2;

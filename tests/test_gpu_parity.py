@@ -18,6 +18,7 @@ if gpu_available():
     import torch
     from oracle import kpoint as kp
     from tests.gpu_cases import CASES, build, host, rel, phase_err, energy_err
+    from paper_2003_09468_amd import AfqmcError
 
 ALL = list(CASES) if gpu_available() else []
 
@@ -230,3 +231,32 @@ def test_determinism():
     p.greens()
     p.step(torch.from_numpy(x[0]))
     assert np.array_equal(U1, host(p.U))
+
+
+# ---------------------------------------------------------------------------
+# occupied dimension above 128: only the blocked inverse covers it
+
+def test_large_occupied_dimension():
+    """nk*nocc = 160: Green's function, log overlap, energy and one step (no QR)."""
+    s, U, x, p, pre = build(((4, 4, 2), 6, 5, 10, 3, "random", "dense"))
+    Gh, ld = kp.greens(U, s.A)
+    assert rel(host(p.Gh), Gh) < 1e-11
+    assert phase_err(host(p.logdet), ld) < 1e-11
+    E = kp.local_energy(pre["Lh"], pre["h1h"], Gh, s.mesh)
+    assert energy_err(host(p.energy()), E, s.nk) <= 1.0
+    out = kp.step(U, ld, np.ones(U.shape[0]), x[0], pre, s.A, s.L, s.mesh, s.dt)
+    p.step(torch.from_numpy(x[0]))
+    assert rel(host(p.U), out["U"]) < 1e-11
+    assert rel(host(p.Gh), out["Gh"]) < 1e-10
+    assert phase_err(host(p.logdet), out["logdet"]) < 1e-10
+    with pytest.raises(AfqmcError):
+        p.orthonormalize()
+
+
+def test_greens_at_maximum_occupied_dimension():
+    """nk*nocc = 256, the largest the inverse takes (16 panels)."""
+    s, U, x, p, pre = build(((4, 4, 4), 5, 4, 4, 2, "random", "dense"))
+    Gh, ld = kp.greens(U, s.A)
+    assert rel(host(p.Gh), Gh) < 1e-10
+    assert phase_err(host(p.logdet), ld) < 1e-10
+    assert int(host(p.status).max()) == 0
