@@ -25,7 +25,8 @@ import sys
 import time
 
 METRIC = "walker-steps/s at Nk=27 M=26, mixed vs FP64 GPU, |ΔE_loc|≤1e-5 Ha/cell"
-PEAK = {"fp64": 78.6, "fp32": 157.3}  # dense MFMA TFLOP/s, MI355X
+# dense MFMA TFLOP/s, MI355X; BF16-split counts its three BF16 passes per product
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3}
 TOL = 1e-5  # Ha per cell
 
 
@@ -370,13 +371,127 @@ def bench_adjoint(args, torch):
     }
 
 
+def bench_c2(args, torch):
+    """4x4x4 mesh, m=52, nocc=4, nchol=400, 32 walkers (L: 70.9 GB complex128, streamed to
+    the GPU block by block as it is drawn).  The local energy of the initial walkers with
+    every contraction precision on the same Gh, each with its error against FP64, and 10
+    FP64 propagation steps (no QR: the re-orthonormalisation takes nk*nocc <= 128)."""
+    import numpy as np
+    import paper_2003_09468_amd as lib
+    from synth.kpt_inputs import config_shapes, make_system, make_walkers, make_fields
+    cfg = config_shapes("c2")
+    nk, m, C, W = cfg["nk"], cfg["m"], cfg["nchol"], cfg["nwalk"]
+    Ld = torch.empty((nk, nk, m, m, C), dtype=torch.complex128, device="cuda")
+    count = [0]
+    t = time.perf_counter()
+
+    def sink(Q, k, blk):
+        Ld[Q, k].copy_(torch.from_numpy(blk))
+        count[0] += 1
+        if count[0] % (nk * nk // 8) == 0:
+            log(f"  L blocks {count[0]}/{nk * nk} ({time.perf_counter() - t:.0f} s)")
+
+    s, rng = make_system(cfg["mesh"], m, cfg["nocc"], C, seed=cfg["seed"], sink=sink)
+    U0 = make_walkers(s, W, rng)
+    xs = torch.from_numpy(make_fields(s, W, cfg["nsteps"], rng)).cuda()
+    log(f"generated c2 in {time.perf_counter() - t:.1f} s")
+    U0d = torch.from_numpy(U0).cuda()
+
+    def problem(prec):
+        p = lib.KptProblem(s.mesh, m, cfg["nocc"], C, W, s.dt, Ld, torch.from_numpy(s.A),
+                           prec=prec)
+        p.prepare(torch.from_numpy(s.H1))
+        return p
+
+    res = {}
+    p64 = problem(lib.PREC_FP64)
+    reset(p64, U0d)
+    # the precisions are compared on the initial walkers (after 10 steps of this workload
+    # the phaseless cut has removed every walker and the overlaps are ill-conditioned)
+    G = p64.Gh.clone()
+    bufs = {"xbar": torch.empty((W, nk, C, 2), dtype=torch.complex128, device="cuda"),
+            "X": torch.empty((W, nk, C), dtype=torch.complex128, device="cuda"),
+            "vhs": torch.empty((W, nk * m, nk * m), dtype=torch.complex128, device="cuda")}
+    torch.cuda.synchronize()
+    lib.timing_enable(True, 1 << 16)
+    t0 = time.perf_counter()
+    for st in range(cfg["nsteps"]):
+        p64.step(xs[st], bufs=bufs)
+    torch.cuda.synchronize()
+    dt_steps = time.perf_counter() - t0
+    lib.timing_enable(False)
+    kern = {}
+    for kc in lib.KERNEL_CLASSES:
+        ms, n = lib.timing_read(kc)
+        if n:
+            kern[kc] = {"ms_total": round(ms, 3), "launches": n}
+    res["steps_fp64"] = {"walker_steps_per_s": round(W * cfg["nsteps"] / dt_steps, 2),
+                         "ms_per_step": round(dt_steps * 1e3 / cfg["nsteps"], 3),
+                         "kernels": kern}
+    log(f"[fp64] {cfg['nsteps']} steps {dt_steps:.2f} s -> {W * cfg['nsteps'] / dt_steps:.1f} "
+        f"walker-steps/s")
+    del bufs
+    alive = int((p64.status == 0).sum().item())
+    E = {}
+    paths = [("fp64", lib.PREC_FP64), ("fp32", lib.PREC_FP32), ("bf16x3", lib.PREC_BF16X3)]
+    for name, prec in paths:
+        p = p64 if prec == lib.PREC_FP64 else problem(prec)
+        out = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+        p.energy(out=out, Gh=G)
+        torch.cuda.synchronize()
+        E[name] = out.cpu().numpy().copy()
+        reps = 3
+        lib.timing_enable(True, 1 << 16)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            p.energy(out=out, Gh=G)
+        torch.cuda.synchronize()
+        dte = (time.perf_counter() - t0) / reps
+        lib.timing_enable(False)
+        ms_x, n_x = lib.timing_read("exchange")
+        fl = kernel_flops("exchange", cfg)
+        ach = fl / (ms_x / n_x * 1e-3) / 1e12
+        key = name
+        res[name] = {"ms_per_energy": round(dte * 1e3, 3),
+                     "walker_energy_evals_per_s": round(W / dte, 3),
+                     "exchange_ms": round(ms_x / n_x, 3),
+                     "roofline": {"kernel": "exchange", "bound": "mfma",
+                                  "achieved": round(ach, 3), "peak": PEAK[key],
+                                  "unit": "TFLOP/s", "frac": round(ach / PEAK[key], 4),
+                                  "traffic": None, "flops_per_launch": fl}}
+        log(f"[{name}] energy {dte * 1e3:.1f} ms (exchange {ms_x / n_x:.1f} ms, {ach:.1f} TF)")
+        if p is not p64:
+            del p
+            torch.cuda.empty_cache()
+    e64 = E["fp64"]
+    for name in E:
+        d = np.abs(E[name].sum(1) - e64.sum(1)) / nk
+        res[name]["max_abs_dE_per_cell_vs_fp64"] = float(d.max())
+        res[name]["median_abs_dE_per_cell_vs_fp64"] = float(np.median(d))
+    return {
+        "metric": "walker energy evaluations/s at Nk=64 M=52 (exchange-dominated)",
+        "value": res["fp64"]["walker_energy_evals_per_s"], "unit": "walker evals/s",
+        "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": res["fp64"]["ms_per_energy"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "c2: mesh 4x4x4, m=52, nocc=4, nchol=400, 32 walkers; local "
+                               "energies of the initial walkers in FP64, FP32 and BF16x3, then 10 "
+                               "FP64 propagation steps; one step = one local energy of all "
+                               "walkers", "path": "fp64",
+                   "walkers_alive_after_steps": alive},
+        "roofline": res["fp64"]["roofline"], "paths": res,
+        "kernel_source_hash": kernel_source_hash(),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3, help="timed blocks")
     ap.add_argument("--warmup", type=int, default=1, help="untimed blocks")
     ap.add_argument("--config", default="c1",
-                    help="c1 (headline), c0, c3 (uneven batch modes) or c4 (energy adjoint)")
+                    help="c1 (headline), c0, c2 (4x4x4 energy precisions), c3 (uneven batch modes) or "
+                         "c4 (energy adjoint)")
     ap.add_argument("--prec", choices=["both", "fp64", "fp32"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -398,6 +513,9 @@ def main():
         sys.exit(1)
     if args.config == "c3":
         print(json.dumps(bench_batch(args, torch)), flush=True)
+        return
+    if args.config == "c2":
+        print(json.dumps(bench_c2(args, torch)), flush=True)
         return
     if args.config == "c4":
         print(json.dumps(bench_adjoint(args, torch)), flush=True)

@@ -66,10 +66,17 @@ typedef enum {
 
 /* Precision of the large complex contractions (force bias L.G, HS potential,
  * Taylor propagation, exchange).  Overlap, Green's function inverse, QR and
- * all energy sums are FP64 in every mode. */
+ * all energy sums are FP64 in every mode.
+ *   FP64:   complex128 operands, FP64 MFMA.
+ *   FP32:   complex64 operands (L32, Lh32), FP32 MFMA with FP32 accumulation.
+ *   BF16X3: as FP32, except the exchange contraction of the local energy, whose
+ *           operands are split x = hi + lo into two bfloat16 numbers and
+ *           multiplied in three BF16 MFMA passes (hi hi + hi lo + lo hi) with
+ *           FP32 accumulation; the energy adjoint stays FP32. */
 typedef enum {
   AFQMC_PREC_FP64 = 0,
-  AFQMC_PREC_FP32 = 1
+  AFQMC_PREC_FP32 = 1,
+  AFQMC_PREC_BF16X3 = 2
 } afqmc_prec;
 
 /* Per-walker status bits. */
@@ -125,8 +132,8 @@ typedef struct afqmc_kpt_problem {
                         Lh[Q][k][a][r][g] = sum_p conj(A[k][p][a]) L[Q][k][p][r][g] */
   void* h1h;         /* [nk][nocc][m] complex128, written by prepare: A[k]^H H1[k] */
   void* bhalf;       /* [nk][m][m] complex128, written by prepare: exp(-dt/2 (H1 + V0)) */
-  void* L32;         /* [nk][nk][m][m][nchol] complex64 copy of L; prec FP32 only (else NULL) */
-  void* Lh32;        /* [nk][nk][nocc][m][nchol] complex64 copy of Lh; prec FP32 only */
+  void* L32;         /* [nk][nk][m][m][nchol] complex64 copy of L; prec FP32/BF16X3 only */
+  void* Lh32;        /* [nk][nk][nocc][m][nchol] complex64 copy of Lh; prec FP32/BF16X3 only */
   /* walker state */
   void* U;           /* [nwalk][nk*m][nk*nocc] complex128 walker orbitals, in/out */
   void* Gh;          /* [nwalk][nk*nocc][nk*m] complex128 half-rotated Green's function */

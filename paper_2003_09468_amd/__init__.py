@@ -16,6 +16,7 @@ from .binding import (  # noqa: F401
     library_path,
     PREC_FP64,
     PREC_FP32,
+    PREC_BF16X3,
     WALKER_SINGULAR,
     WALKER_NONFINITE,
     WALKER_KILLED,

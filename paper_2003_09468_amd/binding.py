@@ -18,6 +18,7 @@ _LIBNAME = "libafqmc_kpt.so"
 
 PREC_FP64 = 0
 PREC_FP32 = 1
+PREC_BF16X3 = 2
 
 WALKER_SINGULAR = 1
 WALKER_NONFINITE = 2
@@ -201,7 +202,7 @@ class KptProblem:
         self.Lh = torch.empty((nk, nk, nocc, m, nchol), dtype=c128, **kw)
         self.h1h = torch.empty((nk, nocc, m), dtype=c128, **kw)
         self.bhalf = torch.empty((nk, m, m), dtype=c128, **kw)
-        if self.prec == PREC_FP32:
+        if self.prec != PREC_FP64:
             self.L32 = torch.empty(self.L.shape, dtype=torch.complex64, **kw)
             self.Lh32 = torch.empty(self.Lh.shape, dtype=torch.complex64, **kw)
         else:
@@ -279,7 +280,7 @@ class KptProblem:
 
     def vhs(self, x, xbar, out=None):
         N = self.nk * self.m
-        dt = torch.complex64 if self.prec == PREC_FP32 else torch.complex128
+        dt = torch.complex64 if self.prec != PREC_FP64 else torch.complex128
         if out is None:
             out = torch.empty((self.nwalk, N, N), dtype=dt, device=self.device)
         x = x.to(device=self.device, dtype=torch.float64).contiguous()
@@ -405,7 +406,7 @@ class KptBatch:
     def vhs(self, i):
         p = self.problems[i]
         N = p.nk * p.m
-        dt = torch.complex64 if p.prec == PREC_FP32 else torch.complex128
+        dt = torch.complex64 if p.prec != PREC_FP64 else torch.complex128
         return self._view(self._vhs, "vhs", i, dt, (p.nwalk, N, N))
 
     def energy(self, i):

@@ -48,7 +48,7 @@ size_t buf_bytes(const afqmc_kpt_problem& p, int buf) {
     case AFQMC_BUF_FIELDS: return 8 * W * nk * C * 2;
     case AFQMC_BUF_XBAR: return 16 * W * nk * C * 2;
     case AFQMC_BUF_X: return 16 * W * nk * C;
-    case AFQMC_BUF_VHS: return (p.prec == AFQMC_PREC_FP32 ? 8 : 16) * W * N * N;
+    case AFQMC_BUF_VHS: return (low_prec(p.prec) ? 8 : 16) * W * N * N;
     case AFQMC_BUF_ENERGY: return 16 * W * 3;
     case AFQMC_BUF_GE: return 16 * W;
     case AFQMC_BUF_GGH: return 16 * W * n * N;
@@ -98,7 +98,8 @@ afqmc_status check_dims(const afqmc_kpt_problem& p) {
     if (p.mesh[i] < 1 || p.mesh[i] > 64) return AFQMC_EINVAL;
   if ((int64_t)p.mesh[0] * p.mesh[1] * p.mesh[2] != p.nk) return AFQMC_EINVAL;
   if (p.m < 1 || p.nocc < 1 || p.nocc > p.m || p.nchol < 1 || p.nwalk < 1) return AFQMC_EINVAL;
-  if (p.prec != AFQMC_PREC_FP64 && p.prec != AFQMC_PREC_FP32) return AFQMC_EINVAL;
+  if (p.prec != AFQMC_PREC_FP64 && p.prec != AFQMC_PREC_FP32 && p.prec != AFQMC_PREC_BF16X3)
+    return AFQMC_EINVAL;
   if (!(p.dt > 0.0) || !isfinite(p.dt)) return AFQMC_EINVAL;
   // sizes the kernels implement
   if (p.m > 64 || p.nocc > 16) return AFQMC_EUNSUPPORTED;
@@ -111,7 +112,7 @@ afqmc_status check_dims(const afqmc_kpt_problem& p) {
 }
 
 afqmc_status check_fields(const afqmc_kpt_problem& p, unsigned need) {
-  const bool f32 = (p.prec == AFQMC_PREC_FP32);
+  const bool f32 = low_prec(p.prec);
   if (need & N_L) AFQMC_TRY(check_ptr(f32 ? p.L32 : p.L, 16));
   if (need & N_A) AFQMC_TRY(check_ptr(p.A, 16));
   if (need & N_LH) AFQMC_TRY(check_ptr(f32 ? p.Lh32 : p.Lh, 16));
@@ -280,7 +281,7 @@ afqmc_status afqmc_kpt_prepare(const afqmc_kpt_problem* p, int nprob, const void
   AFQMC_TRY(check_problems(p, nprob, 0));
   for (int i = 0; i < nprob; ++i) {
     unsigned need = N_A | N_H1H | N_BHALF | N_LD | N_LHD;  // complex128 L and Lh always
-    if (p[i].prec == AFQMC_PREC_FP32) need |= N_L | N_LH;  // plus the complex64 copies
+    if (low_prec(p[i].prec)) need |= N_L | N_LH;  // plus the complex64 copies
     AFQMC_TRY(check_fields(p[i], need));
   }
   AFQMC_TRY(check_ptr(H1, 16));

@@ -190,6 +190,218 @@ __global__ __launch_bounds__(256) void exchange_kernel(const Batch<ExchArgs> B) 
   }
 }
 
+// ---------------------------------------------------------------------------
+// The exchange with BF16-split operands (three BF16 MFMA passes, FP32 accumulation).
+//
+// Every FP32 operand x is split as x = hi + lo with hi = bf16(x) and lo = bf16(x - hi)
+// (round to nearest even), so x - hi - lo = O(2^-16 |x|); a real product is taken as
+// hi hi' + hi lo' + lo hi' (the lo lo' term, O(2^-16 |x x'|), is dropped) on the
+// 16x16x32 BF16 MFMA.  Same work decomposition as exchange_kernel: rows (g, a), columns
+// (w, b), K = r padded to 32 * KB; the Gh fragments are split once into registers and the
+// Lh slabs are split while staged into LDS (four bf16 planes: re hi, re lo, im hi, im lo).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short bf16_bits_rne(float x) {
+  unsigned int u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ void bf16_split(float x, unsigned short& hi, unsigned short& lo) {
+  hi = bf16_bits_rne(x);
+  lo = bf16_bits_rne(x - __uint_as_float((unsigned int)hi << 16));
+}
+
+__device__ __forceinline__ v4f mfma_bf16(const u16x8& a, const u16x8& b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// d += (ah + al)(bh + bl) without the al bl term
+__device__ __forceinline__ v4f mul3(const u16x8& ah, const u16x8& al, const u16x8& bh,
+                                    const u16x8& bl, v4f d) {
+  d = mfma_bf16(al, bh, d);
+  d = mfma_bf16(ah, bl, d);
+  return mfma_bf16(ah, bh, d);
+}
+
+template <int KB>
+__global__ __launch_bounds__(256) void exchange_bf16x3_kernel(const Batch<ExchArgs> B) {
+  constexpr int KP = 32 * KB;  // r padded to the MFMA K
+  constexpr int RS = KP + 8;   // LDS row stride (bf16): rows start 16-byte aligned
+  constexpr int NLD = (2 * 16 * KP) / 256;
+
+  __shared__ __attribute__((aligned(16))) unsigned short LA[2][2][4][16][RS];  // [buf][slab][plane][(g, a)][r]
+  __shared__ float XB[4][2][16][17];
+  __shared__ double red[2][256];
+
+  long long bid;
+  const int pb = batch_find(B, blockIdx.x, bid);
+  const int nk = B.a[pb].nk, m = B.a[pb].m, nocc = B.a[pb].nocc, C = B.a[pb].C, W = B.a[pb].W;
+  const int nchunk_w = B.a[pb].nchunk_w;
+  const KMesh mesh = B.a[pb].mesh;
+  const cpx<float>* __restrict__ Lh = (const cpx<float>*)B.a[pb].Lh;
+  const cpx<double>* __restrict__ Gh = B.a[pb].Gh;
+  cpx<double>* __restrict__ part = B.a[pb].part;
+  const int chunk = (int)(bid % nchunk_w);
+  const int t = (int)(bid / nchunk_w);
+  const int kp = t % nk, k = (t / nk) % nk, Q = t / (nk * nk);
+  const int mQ = mesh.neg(Q), kpq = mesh.kmq(kp, Q), kq = mesh.kmq(k, Q);
+  const int tp = (mQ * nk + kpq) * nk + kq;
+  if (t > tp) return;
+  const double mult = (t == tp) ? 1.0 : 2.0;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int Gs = 16 / nocc, Ws = 16 / nocc;
+  const int col = lane & 15;
+  const int ws_l = col / nocc, b_l = col % nocc;
+  const int wl = chunk * 4 * Ws + wave * Ws + ws_l;
+  const bool colok = (ws_l < Ws) && (wl < W);
+  const int64_t Nn = (int64_t)nk * m, nn = (int64_t)nk * nocc;
+
+  // Gh fragments (B operand, B[r][(w, b)], r = 32 kb + 8 (lane / 16) + i), split
+  u16x8 g1[KB][4], g2[KB][4];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int r = 32 * kb + 8 * (lane >> 4) + i;
+      float x1r = 0.f, x1i = 0.f, x2r = 0.f, x2i = 0.f;
+      if (r < m && colok) {
+        const cpx<double> v1 = Gh[((int64_t)wl * nn + (int64_t)kpq * nocc + b_l) * Nn + (int64_t)kq * m + r];
+        const cpx<double> v2 = Gh[((int64_t)wl * nn + (int64_t)k * nocc + b_l) * Nn + (int64_t)kp * m + r];
+        x1r = (float)v1.re; x1i = (float)v1.im; x2r = (float)v2.re; x2i = (float)v2.im;
+      }
+      unsigned short h, l;
+      bf16_split(x1r, h, l); g1[kb][0][i] = h; g1[kb][1][i] = l;
+      bf16_split(x1i, h, l); g1[kb][2][i] = h; g1[kb][3][i] = l;
+      bf16_split(x2r, h, l); g2[kb][0][i] = h; g2[kb][1][i] = l;
+      bf16_split(x2i, h, l); g2[kb][2][i] = h; g2[kb][3][i] = l;
+    }
+
+  const cpx<float>* slab0 = Lh + ((int64_t)Q * nk + k) * nocc * m * C;
+  const cpx<float>* slab1 = Lh + ((int64_t)mQ * nk + kpq) * nocc * m * C;
+  const int nch = (C + Gs - 1) / Gs;
+
+  // slab element e of this thread: idx = (sl, r, q), q = a * Gs + g_s (g fastest in memory)
+  float pr[NLD], pim[NLD];
+  auto fetch = [&](int c) {
+    const int g0 = c * Gs;
+#pragma unroll
+    for (int e = 0; e < NLD; ++e) {
+      const int idx = tid + 256 * e;
+      const int sl = idx / (16 * KP), rem = idx % (16 * KP);
+      const int r = rem / 16, q = rem % 16;
+      const int a = q / Gs, g_s = q % Gs;
+      float vr = 0.f, vi = 0.f;
+      if (a < nocc && r < m && g0 + g_s < C) {
+        const cpx<float>* sb = sl ? slab1 : slab0;
+        const cpx<float> v = sb[((int64_t)a * m + r) * C + g0 + g_s];
+        vr = v.re; vi = v.im;
+      }
+      pr[e] = vr; pim[e] = vi;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < NLD; ++e) {
+      const int idx = tid + 256 * e;
+      const int sl = idx / (16 * KP), rem = idx % (16 * KP);
+      const int r = rem / 16, q = rem % 16;
+      const int a = q / Gs, g_s = q % Gs;
+      if (a < nocc) {
+        const int row = g_s * nocc + a;
+        unsigned short h, l;
+        bf16_split(pr[e], h, l);
+        LA[buf][sl][0][row][r] = h;
+        LA[buf][sl][1][row][r] = l;
+        bf16_split(pim[e], h, l);
+        LA[buf][sl][2][row][r] = h;
+        LA[buf][sl][3][row][r] = l;
+      }
+    }
+  };
+  // rows (g, a) beyond Gs * nocc stay zero
+  for (int i = tid; i < 2 * 2 * 4 * 16 * RS; i += 256) (&LA[0][0][0][0][0])[i] = 0;
+  __syncthreads();
+
+  const u16x8 sgn = {0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000};
+  double sr = 0.0, si = 0.0;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) fetch(c + 1);
+    v4f a1r = {0.f, 0.f, 0.f, 0.f}, a1i = a1r, a2r = a1r, a2i = a1r;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const int r0 = 32 * kb + 8 * (lane >> 4);
+      u16x8 x[2][4];
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl)
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl)
+          x[sl][pl] = *reinterpret_cast<const u16x8*>(&LA[buf][sl][pl][col][r0]);
+      // re += Lr Gr - Li Gi,  im += Lr Gi + Li Gr  (-Li: flipped sign bits)
+      a1r = mul3(x[0][0], x[0][1], g1[kb][0], g1[kb][1], a1r);
+      a1r = mul3(x[0][2] ^ sgn, x[0][3] ^ sgn, g1[kb][2], g1[kb][3], a1r);
+      a1i = mul3(x[0][0], x[0][1], g1[kb][2], g1[kb][3], a1i);
+      a1i = mul3(x[0][2], x[0][3], g1[kb][0], g1[kb][1], a1i);
+      a2r = mul3(x[1][0], x[1][1], g2[kb][0], g2[kb][1], a2r);
+      a2r = mul3(x[1][2] ^ sgn, x[1][3] ^ sgn, g2[kb][2], g2[kb][3], a2r);
+      a2i = mul3(x[1][0], x[1][1], g2[kb][2], g2[kb][3], a2i);
+      a2i = mul3(x[1][2], x[1][3], g2[kb][0], g2[kb][1], a2i);
+    }
+    // T1 of the partner triple to the wave-private tile (FP32 MFMA output layout)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = mfma16<float>::drow(lane, v);
+      XB[wave][0][row][col] = a2r[v];
+      XB[wave][1][row][col] = a2i[v];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int g0 = c * Gs;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = mfma16<float>::drow(lane, v);
+      const int g_s = row / nocc, a = row % nocc;
+      if (colok && g_s < Gs && g0 + g_s < C) {
+        const int rp = g_s * nocc + b_l, cp = ws_l * nocc + a;
+        const double pr2 = (double)XB[wave][0][rp][cp], pi2 = (double)XB[wave][1][rp][cp];
+        const double p1r = (double)a1r[v], p1i = (double)a1i[v];
+        sr += p1r * pr2 - p1i * pi2;
+        si += p1r * pi2 + p1i * pr2;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (c + 1 < nch) stash(buf ^ 1);
+    __syncthreads();
+  }
+
+  red[0][tid] = sr;
+  red[1][tid] = si;
+  __syncthreads();
+  if (tid < 4 * Ws) {
+    const int wv = tid / Ws, wsi = tid % Ws;
+    const int w = chunk * 4 * Ws + wv * Ws + wsi;
+    if (w < W) {
+      double ar = 0.0, ai = 0.0;
+      for (int grp = 0; grp < 4; ++grp)
+        for (int b = 0; b < nocc; ++b) {
+          const int l = wv * 64 + grp * 16 + wsi * nocc + b;
+          ar += red[0][l];
+          ai += red[1][l];
+        }
+      part[(int64_t)t * W + w] = cpx<double>{-mult * ar, -mult * ai};
+    }
+  }
+}
+
 // E1B[w] = 2 sum_k sum_{a,r} h1h[k][a][r] Gh[w][(k a),(k r)];  EC[w] = 1/2 sum X_Q X_-Q;
 // EX[w] = sum over canonical triples of the exchange partials.  One workgroup per walker.
 struct EfinArgs {
@@ -286,7 +498,11 @@ static int exch_nchunk(const afqmc_kpt_problem& p) {
 static hipError_t launch_exchange(const Job* jobs, int n, void* const* xpart, hipStream_t s) {
   TimedScope ts(KC_EXCHANGE, s);
   return for_groups(
-      n, [&](int i) { return jobs[i].p.prec * 64 + ks_class(jobs[i].p.m); },
+      n,
+      [&](int i) {
+        const afqmc_kpt_problem& p = jobs[i].p;
+        return p.prec * 64 + (p.prec == AFQMC_PREC_BF16X3 ? (p.m <= 32 ? 1 : 2) : ks_class(p.m));
+      },
       [&](const int* ids, int c) -> hipError_t {
         Batch<ExchArgs> B;
         B.nprob = c;
@@ -297,7 +513,7 @@ static hipError_t launch_exchange(const Job* jobs, int n, void* const* xpart, hi
           a.nk = p.nk; a.m = p.m; a.nocc = p.nocc; a.C = p.nchol; a.W = p.nwalk;
           a.nchunk_w = exch_nchunk(p);
           a.mesh = make_mesh(p);
-          a.Lh = (p.prec == AFQMC_PREC_FP32) ? p.Lh32 : p.Lh;
+          a.Lh = low_prec(p.prec) ? p.Lh32 : p.Lh;
           a.Gh = (const cpx<double>*)p.Gh;
           a.part = (cpx<double>*)xpart[ids[q]];
           cnt[q] = (long long)p.nk * p.nk * p.nk * a.nchunk_w;
@@ -305,8 +521,15 @@ static hipError_t launch_exchange(const Job* jobs, int n, void* const* xpart, hi
         const long long g = batch_close(B, cnt);
         if (g < 0) return hipErrorInvalidValue;
         if (g == 0) return hipSuccess;
-        const bool f32 = jobs[ids[0]].p.prec == AFQMC_PREC_FP32;
+        const bool f32 = low_prec(jobs[ids[0]].p.prec);
         const dim3 grid((unsigned)g), blk(256);
+        if (jobs[ids[0]].p.prec == AFQMC_PREC_BF16X3) {
+          if (jobs[ids[0]].p.m <= 32)
+            hipLaunchKernelGGL((exchange_bf16x3_kernel<1>), grid, blk, 0, s, B);
+          else
+            hipLaunchKernelGGL((exchange_bf16x3_kernel<2>), grid, blk, 0, s, B);
+          return hipGetLastError();
+        }
         switch (ks_class(jobs[ids[0]].p.m)) {
           case 4:
             if (f32) hipLaunchKernelGGL((exchange_kernel<float, 4>), grid, blk, 0, s, B);
@@ -613,7 +836,7 @@ static hipError_t launch_bwd(const Job* jobs, int n, void* const* X, hipStream_t
           a.nk = p.nk; a.m = p.m; a.nocc = p.nocc; a.C = p.nchol; a.W = p.nwalk;
           a.nchunk_w = exch_nchunk(p);
           a.mesh = make_mesh(p);
-          a.Lh = (p.prec == AFQMC_PREC_FP32) ? p.Lh32 : p.Lh;
+          a.Lh = low_prec(p.prec) ? p.Lh32 : p.Lh;
           a.LhD = (const cpx<double>*)p.Lh;
           a.h1h = (const cpx<double>*)p.h1h;
           a.Gh = (const cpx<double>*)p.Gh;
@@ -626,7 +849,7 @@ static hipError_t launch_bwd(const Job* jobs, int n, void* const* X, hipStream_t
         if (g < 0) return hipErrorInvalidValue;
         if (g == 0) return hipSuccess;
         const afqmc_kpt_problem& p0 = jobs[ids[0]].p;
-        const bool f32 = p0.prec == AFQMC_PREC_FP32;
+        const bool f32 = low_prec(p0.prec);
         const int ks = ks_class(p0.m), MT = (p0.m + 15) / 16;
         const dim3 grid((unsigned)g), blk(256);
 #define AFQMC_BWD(KSV, MTV)                                                                \

@@ -130,7 +130,7 @@ static hipError_t vbias_tiles(const OpVbias<T>* ops, int c, int choice, hipStrea
 // Split-K partial traces of a group of jobs of one precision.
 hipError_t launch_vbias_group(const Job* jobs, const int* ids, int c, int choice,
                               void* const* parts, hipStream_t s) {
-  if (jobs[ids[0]].p.prec == AFQMC_PREC_FP32) {
+  if (low_prec(jobs[ids[0]].p.prec)) {
     OpVbias<float> ops[AFQMC_MAXP];
     for (int q = 0; q < c; ++q) ops[q] = vbias_op<float>(jobs[ids[q]].p, parts[ids[q]]);
     return vbias_tiles<float>(ops, c, choice, s);
@@ -323,7 +323,7 @@ static hipError_t vhs_tiles(const OpVhs<T>* ops, int c, int choice, hipStream_t 
 
 hipError_t launch_vhs_group(const Job* jobs, const int* ids, int c, int choice,
                             void* const* zeta, hipStream_t s) {
-  if (jobs[ids[0]].p.prec == AFQMC_PREC_FP32) {
+  if (low_prec(jobs[ids[0]].p.prec)) {
     OpVhs<float> ops[AFQMC_MAXP];
     for (int q = 0; q < c; ++q) ops[q] = vhs_op<float>(jobs[ids[q]], zeta[ids[q]]);
     return vhs_tiles<float>(ops, c, choice, s);
@@ -362,7 +362,7 @@ hipError_t run_vhs(const Job* jobs, int n, hipStream_t s) {
           const long long grid = batch_close(B, cnt);
           if (grid < 0) return hipErrorInvalidValue;
           if (grid > 0) {
-            if (J[ids[0]].p.prec == AFQMC_PREC_FP32)
+            if (low_prec(J[ids[0]].p.prec))
               hipLaunchKernelGGL(field_kernel<float>, dim3((unsigned)grid), dim3(256), 0, s, B);
             else
               hipLaunchKernelGGL(field_kernel<double>, dim3((unsigned)grid), dim3(256), 0, s, B);

@@ -409,7 +409,7 @@ __global__ __launch_bounds__(256) void gj_blocked_kernel(const Batch<GjbArgs> B)
         bad |= isfinite(den) ? 1 : 2;
         vr = 1.0; vi = 0.0; den = 1.0;
       }
-      const double ir = vr / den, ii = -vi / den;  // 1 / pivot
+      const double inv = 1.0 / den, ir = vr * inv, ii = -vi * inv;  // 1 / pivot
       if (r == q) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
@@ -529,6 +529,302 @@ __global__ __launch_bounds__(256) void gj_blocked_kernel(const Batch<GjbArgs> B)
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same elimination for n <= 128 with the matrix resident in registers: 512 threads;
+// waves 1..7 own the 16x16 tiles of the matrix as FP64 MFMA accumulators for the whole
+// elimination, wave 0 eliminates each 16-column panel alone (two rows per lane, no block
+// barrier inside a panel): the pivot is a max over (|a|^2, row) keys by DPP lane
+// exchanges within rows of 16 lanes and readlane across rows, and the pivot row is
+// broadcast by readlane.  Per panel: the owners of the panel's tile column stage it in
+// LDS, wave 0 eliminates it, the owners stage the pivot rows M[Q, :] (values before the
+// update), and every owner applies M += Z M[Q, :] to its tiles (Z = panel - E_Q, formed
+// on the fly from the staged panel).  The inverse is written from the tiles with the
+// pivot permutation undone.
+template <int CTRL>
+__device__ __forceinline__ unsigned long long key_max_dpp(unsigned long long v) {
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)v, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(v >> 32), CTRL, 0xf, 0xf, false);
+  const unsigned long long o = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+  return o > v ? o : v;
+}
+
+__device__ __forceinline__ unsigned long long key_readlane(unsigned long long v, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ double dbl_readlane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int TPW>
+__global__ __launch_bounds__(512) void gj_reg_kernel(const Batch<GjbArgs> B) {
+  constexpr int PW = 8;  // panel width
+  long long wloc;
+  const int pb = batch_find(B, blockIdx.x, wloc);
+  const int n = B.a[pb].n;
+  const int w = (int)wloc;
+  const cpx<double>* __restrict__ S = B.a[pb].M + (int64_t)w * n * n;
+  cpx<double>* __restrict__ out = B.a[pb].out + (int64_t)w * n * n;
+
+  __shared__ double Pr[128][PW + 1], Pi[128][PW + 1];  // staged panel, then its T columns
+  __shared__ double Rr[PW][129], Ri[PW][129];         // pivot rows of the panel
+  __shared__ int qs[128], stamp[128], jpos[128];
+  __shared__ double pvr[128], pvi[128];
+  __shared__ unsigned char vis[128];
+  __shared__ int flag_s;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ntile = (n + 15) >> 4;
+  const int col16 = lane & 15;
+
+  // tiles of this wave: t = (wave - 1) + 7 i
+  double cr[TPW][4], ci[TPW][4];
+  if (wave > 0) {
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int t = (wave - 1) + 7 * i;
+      const int I = t / ntile, J = t % ntile;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = I * 16 + mfma16<double>::drow(lane, v), col = J * 16 + col16;
+        cpx<double> x{0.0, 0.0};
+        if (t < ntile * ntile && row < n && col < n) x = S[(int64_t)row * n + col];
+        cr[i][v] = x.re;
+        ci[i][v] = x.im;
+      }
+    }
+  }
+  for (int i = tid; i < 128; i += 512) { stamp[i] = -1; jpos[i] = 0; }
+  for (int i = tid; i < PW * 129; i += 512) { (&Rr[0][0])[i] = 0.0; (&Ri[0][0])[i] = 0.0; }
+  if (tid == 0) flag_s = 0;
+  bool used0 = false, used1 = false;  // wave 0: rows lane and lane + 64
+  int bad = 0;
+  __syncthreads();
+
+  for (int j0 = 0; j0 < n; j0 += PW) {
+    const int bw = (n - j0 < PW) ? n - j0 : PW;
+    const int Jp = j0 >> 4, c0 = j0 & 15;  // tile column of the panel, first column in it
+    // (1) stage the panel
+    if (wave > 0) {
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        const int t = (wave - 1) + 7 * i;
+        if (t >= ntile * ntile || t % ntile != Jp) continue;
+        const int I = t / ntile;
+        const int c = col16 - c0;
+        if (c < 0 || c >= PW) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = I * 16 + mfma16<double>::drow(lane, v);
+          if (row < n) { Pr[row][c] = cr[i][v]; Pi[row][c] = ci[i][v]; }
+        }
+      }
+    }
+    __syncthreads();
+    // (2) wave 0 eliminates the panel.  Wave 0 owns no tiles, so with TPW >= 4 its two
+    // panel rows live in the registers of the tile arrays.
+    if (wave == 0) {
+      double sar[2][PW], sai[2][PW];
+      auto AR = [&](int sl, int c) -> double& {
+        if constexpr (TPW >= 4) return cr[(sl * PW + c) >> 2][(sl * PW + c) & 3];
+        else return sar[sl][c];
+      };
+      auto AI = [&](int sl, int c) -> double& {
+        if constexpr (TPW >= 4) return ci[(sl * PW + c) >> 2][(sl * PW + c) & 3];
+        else return sai[sl][c];
+      };
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl) {
+        const int r = lane + 64 * sl;
+#pragma unroll
+        for (int c = 0; c < PW; ++c) {
+          AR(sl, c) = (r < n) ? Pr[r][c] : 0.0;
+          AI(sl, c) = (r < n) ? Pi[r][c] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < PW; ++jj) {
+        if (jj < bw) {
+          unsigned long long key = 0ull;
+#pragma unroll
+          for (int sl = 0; sl < 2; ++sl) {
+            const int r = lane + 64 * sl;
+            const bool u = sl ? used1 : used0;
+            if (r < n && !u) {
+              const double a2 = AR(sl, jj) * AR(sl, jj) + AI(sl, jj) * AI(sl, jj);
+              const unsigned long long k2 =
+                  ((unsigned long long)__double_as_longlong(a2) & ~0xffull) |
+                  (unsigned long long)(255 - r);
+              key = (k2 > key) ? k2 : key;
+            }
+          }
+          key = key_max_dpp<0xB1>(key);   // quad_perm [1,0,3,2]
+          key = key_max_dpp<0x4E>(key);   // quad_perm [2,3,0,1]
+          key = key_max_dpp<0x141>(key);  // row_half_mirror
+          key = key_max_dpp<0x140>(key);  // row_mirror
+          unsigned long long kmax = key_readlane(key, 0);
+#pragma unroll
+          for (int rr = 1; rr < 4; ++rr) {
+            const unsigned long long o = key_readlane(key, 16 * rr);
+            kmax = (o > kmax) ? o : kmax;
+          }
+          const int q = 255 - (int)(kmax & 0xffull);
+          const int ql = q & 63, qsl = q >> 6;
+          double br[PW], bi[PW];
+#pragma unroll
+          for (int c = 0; c < PW; ++c) {
+            br[c] = dbl_readlane(qsl ? AR(1, c) : AR(0, c), ql);
+            bi[c] = dbl_readlane(qsl ? AI(1, c) : AI(0, c), ql);
+          }
+          double vr = br[jj], vi = bi[jj];
+          double den = vr * vr + vi * vi;
+          if (lane == 0) {
+            qs[j0 + jj] = q; pvr[j0 + jj] = vr; pvi[j0 + jj] = vi; stamp[q] = j0; jpos[q] = jj;
+          }
+          if (!(den > 0.0) || !isfinite(den)) {
+            bad |= isfinite(den) ? 1 : 2;
+            vr = 1.0; vi = 0.0; den = 1.0;
+          }
+          const double inv = 1.0 / den, ir = vr * inv, ii = -vi * inv;
+#pragma unroll
+          for (int sl = 0; sl < 2; ++sl) {
+            const int r = lane + 64 * sl;
+            if (r >= n) continue;
+            if (r == q) {
+              if (sl) used1 = true; else used0 = true;
+#pragma unroll
+              for (int c = 0; c < PW; ++c) {
+                const double xr = AR(sl, c), xi = AI(sl, c);
+                AR(sl, c) = (c == jj) ? ir : xr * ir - xi * ii;
+                AI(sl, c) = (c == jj) ? ii : xr * ii + xi * ir;
+              }
+            } else {
+              const double fr = AR(sl, jj), fi = AI(sl, jj);
+              const double gr = fr * ir - fi * ii, gi = fr * ii + fi * ir;
+#pragma unroll
+              for (int c = 0; c < PW; ++c) {
+                const double ur = AR(sl, c) - (gr * br[c] - gi * bi[c]);
+                const double ui = AI(sl, c) - (gr * bi[c] + gi * br[c]);
+                AR(sl, c) = (c == jj) ? -gr : ur;
+                AI(sl, c) = (c == jj) ? -gi : ui;
+              }
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl) {
+        const int r = lane + 64 * sl;
+        if (r < n) {
+#pragma unroll
+          for (int c = 0; c < PW; ++c) { Pr[r][c] = AR(sl, c); Pi[r][c] = AI(sl, c); }
+        }
+      }
+    }
+    __syncthreads();
+    // (3) pivot rows M[Q, :] before the update
+    if (wave > 0) {
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        const int t = (wave - 1) + 7 * i;
+        if (t >= ntile * ntile) continue;
+        const int I = t / ntile, J = t % ntile;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = I * 16 + mfma16<double>::drow(lane, v);
+          if (row < n && stamp[row] == j0) {
+            Rr[jpos[row]][J * 16 + col16] = cr[i][v];
+            Ri[jpos[row]][J * 16 + col16] = ci[i][v];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // (4) M += Z M[Q, :] on every tile (K = PW), then the panel's columns take T
+    if (wave > 0) {
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        const int t = (wave - 1) + 7 * i;
+        if (t >= ntile * ntile) continue;
+        const int I = t / ntile, J = t % ntile;
+        v4d ur, ui;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) { ur[v] = cr[i][v]; ui[v] = ci[i][v]; }
+        const int arow = I * 16 + col16;
+#pragma unroll
+        for (int kb = 0; kb < PW / 4; ++kb) {
+          const int k = kb * 4 + (lane >> 4);
+          double zr = 0.0, zi = 0.0;
+          if (arow < n && k < bw) {
+            zr = Pr[arow][k] - ((qs[j0 + k] == arow) ? 1.0 : 0.0);
+            zi = Pi[arow][k];
+          }
+          cmfma<double>(zr, zi, Rr[k][J * 16 + col16], Ri[k][J * 16 + col16], ur, ui);
+        }
+        const int c = col16 - c0;
+        const bool inpanel = (J == Jp) && c >= 0 && c < PW;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = I * 16 + mfma16<double>::drow(lane, v);
+          const bool ok = inpanel && row < n && c < bw;
+          cr[i][v] = inpanel ? (ok ? Pr[row][c] : 0.0) : ur[v];
+          ci[i][v] = inpanel ? (ok ? Pi[row][c] : 0.0) : ui[v];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (wave == 0 && bad) atomicOr(&flag_s, bad);
+  __syncthreads();
+  const int fl = flag_s;
+  // O^{-T}[q_k][j] = M[q_j][k], with j = stamp[q_j] + jpos[q_j]
+  if (wave > 0) {
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int t = (wave - 1) + 7 * i;
+      if (t >= ntile * ntile) continue;
+      const int I = t / ntile, J = t % ntile;
+      const int col = J * 16 + col16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = I * 16 + mfma16<double>::drow(lane, v);
+        if (row < n && col < n) {
+          const int j = stamp[row] + jpos[row];
+          out[(int64_t)qs[col] * n + j] = fl ? cpx<double>{0.0, 0.0} : cpx<double>{cr[i][v], ci[i][v]};
+        }
+      }
+    }
+  } else if (lane == 0) {
+    double lr = 0.0, li = 0.0;
+    for (int j = 0; j < n; ++j) {
+      lr += 0.5 * log(pvr[j] * pvr[j] + pvi[j] * pvi[j]);
+      li += atan2(pvi[j], pvr[j]);
+      vis[j] = 0;
+    }
+    int cycles = 0;
+    for (int j = 0; j < n; ++j) {
+      if (vis[j]) continue;
+      ++cycles;
+      for (int x = j; !vis[x]; x = qs[x]) vis[x] = 1;
+    }
+    if ((n - cycles) & 1) li += AFQMC_PI;
+    double wi = remainder(li, 2.0 * AFQMC_PI);
+    if (wi <= -AFQMC_PI) wi += 2.0 * AFQMC_PI;
+    B.a[pb].logdet[w] = fl ? cpx<double>{0.0, 0.0} : cpx<double>{lr, wi};
+    if (fl) {
+      int bits = 0;
+      if (fl & 1) bits |= AFQMC_WALKER_SINGULAR;
+      if (fl & 2) bits |= AFQMC_WALKER_NONFINITE;
+      B.a[pb].status[w] |= bits;
+    }
+  }
+}
+
 hipError_t launch_gj_blocked(const Job* jobs, int n, void* const* S, void* const* out,
                              void* const* logdet_out, hipStream_t s) {
   for (int c0 = 0; c0 < n; c0 += AFQMC_MAXP) {
@@ -549,7 +845,18 @@ hipError_t launch_gj_blocked(const Job* jobs, int n, void* const* S, void* const
     const long long g = batch_close(B, cnt);
     if (g < 0) return hipErrorInvalidValue;
     if (g == 0) continue;
-    hipLaunchKernelGGL(gj_blocked_kernel, dim3((unsigned)g), dim3(256), 0, s, B);
+    int nmax = 0;
+    for (int q = 0; q < c; ++q) nmax = B.a[q].n > nmax ? B.a[q].n : nmax;
+    // tiles per owner wave: ceil(ntile^2 / 7)
+    const int nt = (nmax + 15) / 16, tpw = (nt * nt + 6) / 7;
+    if (tpw <= 1)
+      hipLaunchKernelGGL((gj_reg_kernel<1>), dim3((unsigned)g), dim3(512), 0, s, B);
+    else if (tpw <= 3)
+      hipLaunchKernelGGL((gj_reg_kernel<3>), dim3((unsigned)g), dim3(512), 0, s, B);
+    else if (tpw <= 7)
+      hipLaunchKernelGGL((gj_reg_kernel<7>), dim3((unsigned)g), dim3(512), 0, s, B);
+    else
+      hipLaunchKernelGGL(gj_blocked_kernel, dim3((unsigned)g), dim3(256), 0, s, B);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

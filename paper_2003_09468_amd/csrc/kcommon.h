@@ -11,6 +11,9 @@ namespace afqmc {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// Contraction precisions other than FP64 keep complex64 copies of L and Lh.
+__host__ __device__ __forceinline__ bool low_prec(int prec) { return prec != AFQMC_PREC_FP64; }
+
 // Complex values as plain (re, im) pairs of the storage type.
 template <typename T>
 struct cpx {

@@ -171,7 +171,7 @@ hipError_t run_prepare(const afqmc_kpt_problem& p, const void* H1, void* ws, hip
   Carve c(ws);
   void* V0 = c.take(16 * (size_t)p.nk * p.m * p.m);
   void* scr = c.take(16 * 4 * (size_t)p.nk * p.m * p.m);
-  const bool f32 = (p.prec == AFQMC_PREC_FP32);
+  const bool f32 = low_prec(p.prec);
   hipError_t e;
   {  // Lh = A^H L, batch (Q, k)
     OpHalfRot op;

@@ -103,7 +103,7 @@ static hipError_t launch_bhalf(const Job* jobs, const int* ids, int c, void* con
 // Taylor tile class of an FP32 problem: one column tile spans all nk*nocc columns
 // (rounded up to 16), each of the 4 waves owning 16 rows x BN columns.
 static int taylor_class(const afqmc_kpt_problem& p) {
-  if (p.prec != AFQMC_PREC_FP32) return 0;
+  if (!low_prec(p.prec)) return 0;
   const int c = (p.nk * p.nocc + 15) / 16;
   return c <= 8 ? c : 9;
 }
@@ -142,7 +142,7 @@ hipError_t launch_taylor_group(const Job* jobs, const int* ids, int c, int choic
                                double alpha_scale, hipStream_t s) {
   TimedScope ts(KC_TAYLOR, s);
   const int cls = taylor_class(jobs[ids[0]].p);
-  if (jobs[ids[0]].p.prec == AFQMC_PREC_FP32) {
+  if (low_prec(jobs[ids[0]].p.prec)) {
     OpTaylor<float> ops[AFQMC_MAXP];
     for (int q = 0; q < c; ++q) {
       const Job& j = jobs[ids[q]];
@@ -177,7 +177,7 @@ hipError_t launch_taylor_group(const Job* jobs, const int* ids, int c, int choic
 static size_t carve_propagate(Carve& c, const afqmc_kpt_problem& p, void** acc, void** t0,
                               void** t1, GreensWs& g) {
   Dims d = dims_of(p);
-  const size_t tsz = (p.prec == AFQMC_PREC_FP32) ? 8 : 16;
+  const size_t tsz = low_prec(p.prec) ? 8 : 16;
   carve_greens(c, d, g);
   *acc = c.take(16 * (size_t)d.W * d.N() * d.n());
   *t0 = c.take(tsz * (size_t)d.W * d.N() * d.n());
@@ -210,7 +210,7 @@ static hipError_t propagate_jobs(const Job* J, int c, hipStream_t s) {
   return for_groups(
       c, [&](int i) { return taylor_key(J[i].p); },
       [&](const int* ids, int g) -> hipError_t {
-        const bool f32 = J[ids[0]].p.prec == AFQMC_PREC_FP32;
+        const bool f32 = low_prec(J[ids[0]].p.prec);
         // T_0 = bhalf U (FP64), acc = T_0, t0 = T_0 in the Taylor precision
         hipError_t e = f32 ? launch_bhalf<float>(J, ids, g, U, acc, t0, s)
                            : launch_bhalf<double>(J, ids, g, U, acc, t0, s);

@@ -97,10 +97,38 @@ def _partner(Q: int, k: int, mesh) -> tuple:
     return mq, kmq
 
 
+def _cholesky_blocks(rng, mesh, m, nchol):
+    """Yield (Q, k, L[Q][k]) in draw order: each block is drawn together with its
+    time-reversal partner (-Q, k-Q), which follows it."""
+    nk = int(np.prod(mesh))
+    done = np.zeros((nk, nk), dtype=bool)
+    scale = np.exp(-np.arange(nchol) / 6.0) / np.sqrt(m)
+    for Q in range(nk):
+        for k in range(nk):
+            if done[Q, k]:
+                continue
+            z = _cn(rng, (m, m, nchol))
+            pQ, pk = _partner(Q, k, mesh)
+            if (pQ, pk) == (Q, k):
+                blk = 0.5 * (z + z.conj().transpose(1, 0, 2))
+                done[Q, k] = True
+                yield Q, k, blk * scale
+            else:
+                blk = z * scale
+                done[Q, k] = True
+                done[pQ, pk] = True
+                yield Q, k, blk
+                yield pQ, pk, blk.conj().transpose(1, 0, 2)
+
+
 def make_system(mesh, m, nocc, nchol, seed=0, dt=DT, trial="identity",
                 rng: np.random.Generator | None = None,
-                ldtype=np.complex128) -> tuple[KptSystem, np.random.Generator]:
-    """Draw H1, L and the trial; return the system and the still-live generator."""
+                ldtype=np.complex128, sink=None) -> tuple[KptSystem, np.random.Generator]:
+    """Draw H1, L and the trial; return the system and the still-live generator.
+
+    With sink, L is not kept: sink(Q, k, block) receives each (m, m, nchol) block in draw
+    order (for workloads whose L exceeds host memory) and the system's L is None.
+    """
     mesh = tuple(int(v) for v in mesh)
     nk = int(np.prod(mesh))
     if nocc > m:
@@ -116,25 +144,16 @@ def make_system(mesh, m, nocc, nchol, seed=0, dt=DT, trial="identity",
         np.fill_diagonal(h, 0.0)
         H1[k] = base + h
 
-    L = np.zeros((nk, nk, m, m, nchol), dtype=ldtype)
-    done = np.zeros((nk, nk), dtype=bool)
-    scale = np.exp(-np.arange(nchol) / 6.0) / np.sqrt(m)
-    for Q in range(nk):
-        for k in range(nk):
-            if done[Q, k]:
-                continue
-            z = _cn(rng, (m, m, nchol))
-            pQ, pk = _partner(Q, k, mesh)
-            if (pQ, pk) == (Q, k):
-                blk = 0.5 * (z + z.conj().transpose(1, 0, 2))
-                L[Q, k] = blk * scale
-                done[Q, k] = True
-            else:
-                blk = z * scale
-                L[Q, k] = blk
-                L[pQ, pk] = blk.conj().transpose(1, 0, 2)
-                done[Q, k] = True
-                done[pQ, pk] = True
+    if sink is None:
+        L = np.zeros((nk, nk, m, m, nchol), dtype=ldtype)
+
+        def store(Q, k, blk):
+            L[Q, k] = blk
+    else:
+        L = None
+        store = sink
+    for Q, k, blk in _cholesky_blocks(rng, mesh, m, nchol):
+        store(Q, k, blk)
 
     if trial == "identity":
         A = np.zeros((nk, m, nocc), dtype=np.complex128)
