@@ -50,31 +50,174 @@ def kernel_flops(name, c):
     return None
 
 
-def kernel_source_hash():
-    """Hash of the HIP sources: counter figures taken for another build are not reused."""
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2003_09468_amd", "csrc")
+COMMON = ["kcommon.h", "batch.h", "cgemm.h"]
+# the sources each kernel class is built from (counter figures are kept while they match)
+KERNEL_FILES = {
+    "taylor": COMMON + ["propagate.hip"], "bhalf": COMMON + ["propagate.hip"],
+    "vhs": COMMON + ["fields.hip"], "vbias": COMMON + ["fields.hip"],
+    "exchange": COMMON + ["energy.hip"], "greens_solve": COMMON + ["greens.hip"],
+    "greens_gj": COMMON + ["greens.hip"],
+}
+# kernel-name patterns of each class in a rocprofv3 trace
+KERNEL_NAMES = {
+    "taylor": "OpTaylor<{t}>", "vhs": "OpVhs<{t}>", "vbias": "OpVbias<{t}>",
+    "exchange": "exchange_kernel<{t}", "greens_solve": "OpGreensSolve",
+    "greens_gj": "gj_", "bhalf": "OpBhalf<{t}>",
+}
+
+
+def kernel_source_hash(files=None):
+    """Hash of HIP sources (all of them, or the given files)."""
     import hashlib
-    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2003_09468_amd", "csrc")
+    names = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".h"))) \
+        if files is None else sorted(set(files))
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
+    for f in names:
+        h.update(f.encode())
+        h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel, prec):
     """HBM bytes per launch of a kernel class from the committed counter summary, if it was
-    taken for the current sources (else None)."""
+    taken for the kernel's current sources (else None)."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                         "traffic_c1.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_hash") != kernel_source_hash():
-        return None
     ent = rec.get("kernels", {}).get(f"{kernel}_{prec}")
-    return None if ent is None else ent.get("bytes_per_launch")
+    if ent is None or kernel not in KERNEL_FILES:
+        return None
+    if ent.get("source_hash") != kernel_source_hash(KERNEL_FILES[kernel]):
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def _pmc_rows(path, counter):
+    import csv
+    out = []
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return out
+
+
+def reduce_pmc(fetch_csv, write_csv):
+    """Per-launch HBM bytes of the c1 FP64 kernels from two counter runs (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch), each scaled by what it reads for the 1 GiB copy; writes
+    profiles/traffic_c1.json and profiles/traffic_c1.md."""
+    from synth.kpt_inputs import config_shapes
+    c = config_shapes("c1")
+    W, nk, m, nocc, C = c["nwalk"], c["nk"], c["m"], c["nocc"], c["nchol"]
+    N, n = nk * m, nk * nocc
+    fetch, write = _pmc_rows(fetch_csv, "FETCH_SIZE"), _pmc_rows(write_csv, "WRITE_SIZE")
+
+    def copy_kib(rows):
+        v = [x for name, x in rows if "copyBuffer" in name]
+        return max(v) if v else None
+    gib = float(1 << 30)
+    fs = gib / (copy_kib(fetch) * 1024.0)
+    ws = gib / (copy_kib(write) * 1024.0)
+    algo = {
+        "taylor": (16.0 * W * (N * N + 2 * N * n), 16.0 * W * N * n * (1 + 5.0 / 6.0)),
+        "vhs": (16.0 * (nk * nk * m * m * C + W * nk * C), 16.0 * W * N * N),
+        "exchange": (16.0 * (nk * nk * nocc * m * C + W * n * N), 16.0 * nk ** 3 * W),
+    }
+    rec = {"workload": "c1: mesh 3x3x3, m=26, nocc=4, nchol=208, 64 walkers (FP64 path)",
+           "fetch_scale": fs, "write_scale": ws, "kernels": {}}
+    for k, pat in KERNEL_NAMES.items():
+        pat = pat.format(t="double")
+        fv = [x for name, x in fetch if pat in name]
+        wv = [x for name, x in write if pat in name]
+        if not fv or not wv:
+            continue
+        fb = sum(fv) / len(fv) * 1024.0 * fs
+        wb = sum(wv) / len(wv) * 1024.0 * ws
+        e = {"launches": len(fv), "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+             "bytes_per_launch": fb + wb, "source_hash": kernel_source_hash(KERNEL_FILES[k])}
+        if k in algo:
+            e["algorithmic_read_bytes"], e["algorithmic_write_bytes"] = algo[k]
+        rec["kernels"][f"{k}_fp64"] = e
+    base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+    json.dump(rec, open(os.path.join(base, "traffic_c1.json"), "w"), indent=1)
+    lines = ["# HBM traffic per launch, c1 FP64 path (rocprofv3 counters)", "",
+             "Commands (repository root on the GPU box; each counter in its own run):", "",
+             "```", "cd /tmp && export TMPDIR=/tmp && cd \"$GRAFT_REPO_ROOT\"",
+             "timeout -s KILL 400 rocprofv3 --pmc FETCH_SIZE --output-format csv "
+             "-d gpurun_out/pmc_fetch -o run -- \\",
+             "    python3 bench.py --steps 1 --warmup 0 --prec fp64 --no-cpu-baseline --calib-copy",
+             "timeout -s KILL 400 rocprofv3 --pmc WRITE_SIZE --output-format csv "
+             "-d gpurun_out/pmc_write -o run -- \\",
+             "    python3 bench.py --steps 1 --warmup 0 --prec fp64 --no-cpu-baseline --calib-copy",
+             "python3 bench.py --reduce-pmc gpurun_out/pmc_fetch/run_counter_collection.csv "
+             "gpurun_out/pmc_write/run_counter_collection.csv", "```", "",
+             f"Scale: the plain 1 GiB device copy (`--calib-copy`) reads as FETCH_SIZE = "
+             f"{gib / fs / 2**20:.1f} MiB and WRITE_SIZE = {gib / ws / 2**20:.1f} MiB, so "
+             f"FETCH_SIZE is multiplied by {fs:.3f} and WRITE_SIZE by {ws:.3f}.", "",
+             "Each row carries the hash of the kernel's own sources; bench.py reports the "
+             "figure only while they hash the same.", "",
+             "| kernel | launches | read MB/launch | write MB/launch | algorithmic read MB | "
+             "algorithmic write MB | source hash |",
+             "|:--|--:|--:|--:|--:|--:|:--|"]
+    for k, e in rec["kernels"].items():
+        ar = e.get("algorithmic_read_bytes")
+        aw = e.get("algorithmic_write_bytes")
+        lines.append(f"| {k} | {e['launches']} | {e['fetch_bytes_per_launch'] / 1e6:.1f} | "
+                     f"{e['write_bytes_per_launch'] / 1e6:.1f} | "
+                     f"{'' if ar is None else f'{ar / 1e6:.1f}'} | "
+                     f"{'' if aw is None else f'{aw / 1e6:.1f}'} | {e['source_hash']} |")
+    lines += ["", "Algorithmic bytes: a Taylor term reads vhs (W (nk m)^2), T_{j-1} and the FP64 "
+              "accumulator and writes T_j (5 of 6 terms) and the accumulator; the HS potential "
+              "reads L once and writes vhs; the exchange reads Lh and Gh once."]
+    open(os.path.join(base, "traffic_c1.md"), "w").write("\n".join(lines) + "\n")
+    print(json.dumps(rec["kernels"], indent=1))
+
+
+def reduce_mfma(csv_path, out_md, title, command):
+    """MFMA utilisation per kernel from one counter run (SQ_VALU_MFMA_BUSY_CYCLES,
+    GRBM_GUI_ACTIVE, SQ_INSTS_VALU_MFMA_MOPS_*): busy cycles / (active cycles x 1024 SIMDs),
+    and the MFMA flops counted by the hardware (MOPS x 512)."""
+    import csv
+    per, dur = {}, {}
+    for r in csv.DictReader(open(csv_path)):
+        key = (r["Kernel_Name"], r["Dispatch_Id"])
+        per.setdefault(key, {})[r["Counter_Name"]] = float(r["Counter_Value"])
+        dur[key] = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+    agg = {}
+    for key, v in per.items():
+        name = key[0]
+        if "afqmc" not in name:
+            continue
+        short = name.replace("void ", "").replace("afqmc::", "").split("(")[0]
+        a = agg.setdefault(short, {"n": 0, "busy": 0.0, "active": 0.0, "mops": 0.0, "ns": 0.0})
+        a["n"] += 1
+        a["busy"] += v.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
+        # GRBM_GUI_ACTIVE arrives summed over the 8 XCDs (8x the dispatch's wall cycles)
+        a["active"] += v.get("GRBM_GUI_ACTIVE", 0.0) / 8.0
+        a["mops"] += sum(x for c, x in v.items() if c.startswith("SQ_INSTS_VALU_MFMA_MOPS"))
+        a["ns"] += dur[key]
+    rows = sorted(agg.items(), key=lambda kv: -kv[1]["active"])
+    lines = [f"# MFMA utilisation: {title}", "", "Command (repository root on the GPU box):", "",
+             "```", "cd /tmp && export TMPDIR=/tmp && cd \"$GRAFT_REPO_ROOT\"", command,
+             f"python3 bench.py --reduce-mfma <run_counter_collection.csv> {out_md}", "```", "",
+             "MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (active cycles x 1024 SIMDs), with the "
+             "active cycles GRBM_GUI_ACTIVE / 8 (the counter arrives summed over the 8 XCDs: "
+             "8x the dispatch's wall time in cycles); MFMA flops = SQ_INSTS_VALU_MFMA_MOPS_* "
+             "x 512 (the hardware count, including zero padding and the three passes of the "
+             "BF16 split), rate = flops / dispatch time (counter runs serialise dispatches).", "",
+             "| kernel | dispatches | us/dispatch | MFMA busy % | MFMA Gflop/dispatch | "
+             "MFMA TFLOP/s |", "|:--|--:|--:|--:|--:|--:|"]
+    for k, a in rows[:24]:
+        util = 100.0 * a["busy"] / (a["active"] * 1024.0) if a["active"] else 0.0
+        gf = a["mops"] * 512 / a["n"] / 1e9
+        us = a["ns"] / a["n"] / 1e3
+        lines.append(f"| `{k}` | {a['n']} | {us:.1f} | {util:.1f} | {gf:.2f} | "
+                     f"{gf / us * 1e3 if us else 0.0:.1f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def run_block(p, xs, bufs, E):
@@ -496,7 +639,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (scale reference for HBM counters)")
+    ap.add_argument("--reduce-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic_c1.{json,md} from two counter runs and exit")
+    ap.add_argument("--reduce-mfma", nargs=2, metavar=("CSV", "OUT_MD"),
+                    help="write an MFMA-utilisation summary from one counter run and exit")
+    ap.add_argument("--title", default="", help="title of the --reduce-mfma summary")
+    ap.add_argument("--command", default="", help="profiling command of the summary")
     args = ap.parse_args()
+    if args.reduce_pmc:
+        reduce_pmc(*args.reduce_pmc)
+        return
+    if args.reduce_mfma:
+        reduce_mfma(args.reduce_mfma[0], args.reduce_mfma[1], args.title, args.command)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(sharding walkers or Q blocks across GPUs is not built).",

@@ -134,6 +134,9 @@ typedef struct afqmc_kpt_problem {
   void* bhalf;       /* [nk][m][m] complex128, written by prepare: exp(-dt/2 (H1 + V0)) */
   void* L32;         /* [nk][nk][m][m][nchol] complex64 copy of L; prec FP32/BF16X3 only */
   void* Lh32;        /* [nk][nk][nocc][m][nchol] complex64 copy of Lh; prec FP32/BF16X3 only */
+  void* Lhs;         /* [nk][nk][nchol][nocc][4][32*ceil(m/32)] bfloat16 (uint16) split planes
+                        of Lh (re hi, re lo, im hi, im lo; r padded with zeros), written by
+                        prepare; prec BF16X3 only (else NULL) */
   /* walker state */
   void* U;           /* [nwalk][nk*m][nk*nocc] complex128 walker orbitals, in/out */
   void* Gh;          /* [nwalk][nk*nocc][nk*m] complex128 half-rotated Green's function */

@@ -76,7 +76,8 @@ namespace {
 enum Need : unsigned {
   N_L = 1u << 0, N_A = 1u << 1, N_LH = 1u << 2, N_H1H = 1u << 3, N_BHALF = 1u << 4,
   N_U = 1u << 5, N_GH = 1u << 6, N_LOGDET = 1u << 7, N_WEIGHT = 1u << 8, N_STATUS = 1u << 9,
-  N_LD = 1u << 10, N_LHD = 1u << 11  // *D: the complex128 arrays in every precision
+  N_LD = 1u << 10, N_LHD = 1u << 11,  // *D: the complex128 arrays in every precision
+  N_LHS = 1u << 12                     // the BF16 split planes (BF16X3 problems only)
 };
 
 inline bool misaligned(const void* p, size_t a) { return ((uintptr_t)p) % a != 0; }
@@ -125,6 +126,7 @@ afqmc_status check_fields(const afqmc_kpt_problem& p, unsigned need) {
   if (need & N_LOGDET) AFQMC_TRY(check_ptr(p.logdet, 16));
   if (need & N_WEIGHT) AFQMC_TRY(check_ptr(p.weight, 8));
   if (need & N_STATUS) AFQMC_TRY(check_ptr(p.status, 4));
+  if ((need & N_LHS) && p.prec == AFQMC_PREC_BF16X3) AFQMC_TRY(check_ptr(p.Lhs, 16));
   return AFQMC_OK;
 }
 
@@ -239,7 +241,7 @@ afqmc_status check_step_args(const afqmc_kpt_problem* p, int nprob, const double
                              void* xbar, void* vhs, void* E, int flags, void* ws,
                              size_t ws_bytes) {
   unsigned need = N_L | N_LH | N_A | N_BHALF | N_U | N_GH | N_LOGDET | N_WEIGHT | N_STATUS;
-  if (flags & AFQMC_STEP_ENERGY) need |= N_H1H;
+  if (flags & AFQMC_STEP_ENERGY) need |= N_H1H | N_LHS;
   AFQMC_TRY(check_problems(p, nprob, need));
   if (nsteps < 1) return AFQMC_EINVAL;
   if (flags & ~(AFQMC_PROPAGATE_ORTHO | AFQMC_STEP_ENERGY)) return AFQMC_EINVAL;
@@ -281,7 +283,7 @@ afqmc_status afqmc_kpt_prepare(const afqmc_kpt_problem* p, int nprob, const void
   AFQMC_TRY(check_problems(p, nprob, 0));
   for (int i = 0; i < nprob; ++i) {
     unsigned need = N_A | N_H1H | N_BHALF | N_LD | N_LHD;  // complex128 L and Lh always
-    if (low_prec(p[i].prec)) need |= N_L | N_LH;  // plus the complex64 copies
+    if (low_prec(p[i].prec)) need |= N_L | N_LH | N_LHS;  // plus the complex64 copies
     AFQMC_TRY(check_fields(p[i], need));
   }
   AFQMC_TRY(check_ptr(H1, 16));
@@ -363,7 +365,7 @@ afqmc_status afqmc_kpt_orthonormalize(const afqmc_kpt_problem* p, int nprob, voi
 
 afqmc_status afqmc_kpt_energy(const afqmc_kpt_problem* p, int nprob, void* E, void* ws,
                               size_t ws_bytes, void* stream) {
-  AFQMC_TRY(check_problems(p, nprob, N_LH | N_H1H | N_GH));
+  AFQMC_TRY(check_problems(p, nprob, N_LH | N_LHS | N_H1H | N_GH));
   AFQMC_TRY(check_ptr(E, 16));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_ENERGY, ws, ws_bytes));
   AFQMC_TRY(check_device());

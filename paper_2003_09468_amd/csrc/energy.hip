@@ -26,7 +26,8 @@ namespace afqmc {
 struct ExchArgs {
   int nk, m, nocc, C, W, nchunk_w;
   KMesh mesh;
-  const void* Lh;           // [nk][nk][nocc][m][C] in the contraction precision
+  const void* Lh;           // [nk][nk][nocc][m][C] in the contraction precision, or for
+                            // BF16X3 the split planes [nk][nk][C][nocc][4][KP] (bf16)
   const cpx<double>* Gh;    // [W][nk*nocc][nk*m]
   cpx<double>* part;        // [nk^3][W]
 };
@@ -197,8 +198,9 @@ __global__ __launch_bounds__(256) void exchange_kernel(const Batch<ExchArgs> B) 
 // (round to nearest even), so x - hi - lo = O(2^-16 |x|); a real product is taken as
 // hi hi' + hi lo' + lo hi' (the lo lo' term, O(2^-16 |x x'|), is dropped) on the
 // 16x16x32 BF16 MFMA.  Same work decomposition as exchange_kernel: rows (g, a), columns
-// (w, b), K = r padded to 32 * KB; the Gh fragments are split once into registers and the
-// Lh slabs are split while staged into LDS (four bf16 planes: re hi, re lo, im hi, im lo).
+// (w, b), K = r padded to 32 * KB; the Gh fragments are split once into registers, and the
+// Lh slabs come pre-split from prepare (four bf16 planes: re hi, re lo, im hi, im lo, r
+// contiguous) and are staged into LDS with 16-byte copies.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
@@ -230,7 +232,6 @@ template <int KB>
 __global__ __launch_bounds__(256) void exchange_bf16x3_kernel(const Batch<ExchArgs> B) {
   constexpr int KP = 32 * KB;  // r padded to the MFMA K
   constexpr int RS = KP + 8;   // LDS row stride (bf16): rows start 16-byte aligned
-  constexpr int NLD = (2 * 16 * KP) / 256;
 
   __shared__ __attribute__((aligned(16))) unsigned short LA[2][2][4][16][RS];  // [buf][slab][plane][(g, a)][r]
   __shared__ float XB[4][2][16][17];
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(256) void exchange_bf16x3_kernel(const Batch<ExchAr
   const int nk = B.a[pb].nk, m = B.a[pb].m, nocc = B.a[pb].nocc, C = B.a[pb].C, W = B.a[pb].W;
   const int nchunk_w = B.a[pb].nchunk_w;
   const KMesh mesh = B.a[pb].mesh;
-  const cpx<float>* __restrict__ Lh = (const cpx<float>*)B.a[pb].Lh;
+  const unsigned short* __restrict__ Lhs = (const unsigned short*)B.a[pb].Lh;
   const cpx<double>* __restrict__ Gh = B.a[pb].Gh;
   cpx<double>* __restrict__ part = B.a[pb].part;
   const int chunk = (int)(bid % nchunk_w);
@@ -280,46 +281,38 @@ __global__ __launch_bounds__(256) void exchange_bf16x3_kernel(const Batch<ExchAr
       bf16_split(x2i, h, l); g2[kb][2][i] = h; g2[kb][3][i] = l;
     }
 
-  const cpx<float>* slab0 = Lh + ((int64_t)Q * nk + k) * nocc * m * C;
-  const cpx<float>* slab1 = Lh + ((int64_t)mQ * nk + kpq) * nocc * m * C;
+  // the pre-split planes: slab (Q, k) is [C][nocc][4][KP] bf16, contiguous per g chunk
+  const unsigned short* slab0 = Lhs + ((int64_t)Q * nk + k) * C * nocc * 4 * KP;
+  const unsigned short* slab1 = Lhs + ((int64_t)mQ * nk + kpq) * C * nocc * 4 * KP;
   const int nch = (C + Gs - 1) / Gs;
 
-  // slab element e of this thread: idx = (sl, r, q), q = a * Gs + g_s (g fastest in memory)
-  float pr[NLD], pim[NLD];
+  // 16-byte units of a chunk: u = ((g_s nocc + a) 4 + plane) (KP / 8) + r8, per slab
+  constexpr int UPR = KP / 8;                 // units per (row, plane)
+  constexpr int NU = (2 * 16 * 4 * UPR) / 256;  // units per thread (both slabs)
+  uint4 pu[NU];
   auto fetch = [&](int c) {
     const int g0 = c * Gs;
 #pragma unroll
-    for (int e = 0; e < NLD; ++e) {
+    for (int e = 0; e < NU; ++e) {
       const int idx = tid + 256 * e;
-      const int sl = idx / (16 * KP), rem = idx % (16 * KP);
-      const int r = rem / 16, q = rem % 16;
-      const int a = q / Gs, g_s = q % Gs;
-      float vr = 0.f, vi = 0.f;
-      if (a < nocc && r < m && g0 + g_s < C) {
-        const cpx<float>* sb = sl ? slab1 : slab0;
-        const cpx<float> v = sb[((int64_t)a * m + r) * C + g0 + g_s];
-        vr = v.re; vi = v.im;
+      const int sl = idx / (16 * 4 * UPR), u = idx % (16 * 4 * UPR);
+      const int row = u / (4 * UPR);           // g_s * nocc + a
+      const int g_s = row / nocc;
+      uint4 v = {0u, 0u, 0u, 0u};
+      if (row < Gs * nocc && g0 + g_s < C) {
+        const unsigned short* sb = sl ? slab1 : slab0;
+        v = *reinterpret_cast<const uint4*>(sb + ((int64_t)g0 * nocc * 4 * UPR + u) * 8);
       }
-      pr[e] = vr; pim[e] = vi;
+      pu[e] = v;
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < NLD; ++e) {
+    for (int e = 0; e < NU; ++e) {
       const int idx = tid + 256 * e;
-      const int sl = idx / (16 * KP), rem = idx % (16 * KP);
-      const int r = rem / 16, q = rem % 16;
-      const int a = q / Gs, g_s = q % Gs;
-      if (a < nocc) {
-        const int row = g_s * nocc + a;
-        unsigned short h, l;
-        bf16_split(pr[e], h, l);
-        LA[buf][sl][0][row][r] = h;
-        LA[buf][sl][1][row][r] = l;
-        bf16_split(pim[e], h, l);
-        LA[buf][sl][2][row][r] = h;
-        LA[buf][sl][3][row][r] = l;
-      }
+      const int sl = idx / (16 * 4 * UPR), u = idx % (16 * 4 * UPR);
+      const int row = u / (4 * UPR), pl = (u / UPR) % 4, r8 = u % UPR;
+      if (row < Gs * nocc) *reinterpret_cast<uint4*>(&LA[buf][sl][pl][row][r8 * 8]) = pu[e];
     }
   };
   // rows (g, a) beyond Gs * nocc stay zero
@@ -513,7 +506,7 @@ static hipError_t launch_exchange(const Job* jobs, int n, void* const* xpart, hi
           a.nk = p.nk; a.m = p.m; a.nocc = p.nocc; a.C = p.nchol; a.W = p.nwalk;
           a.nchunk_w = exch_nchunk(p);
           a.mesh = make_mesh(p);
-          a.Lh = low_prec(p.prec) ? p.Lh32 : p.Lh;
+          a.Lh = (p.prec == AFQMC_PREC_BF16X3) ? p.Lhs : (low_prec(p.prec) ? p.Lh32 : p.Lh);
           a.Gh = (const cpx<double>*)p.Gh;
           a.part = (cpx<double>*)xpart[ids[q]];
           cnt[q] = (long long)p.nk * p.nk * p.nk * a.nchunk_w;

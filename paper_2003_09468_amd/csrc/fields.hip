@@ -307,6 +307,10 @@ static OpVhs<T> vhs_op(const Job& j, void* zeta) {
 // Rows = walkers, (k p r) columns.  Default tiles measured at 27 x 64 x 18252 x 208.
 template <typename T>
 static hipError_t vhs_tiles(const OpVhs<T>* ops, int c, int choice, hipStream_t s) {
+  // the default follows the walker count (the rows): 32-row tiles for W <= 32
+  int mmax = 0;
+  for (int q = 0; q < c; ++q) mmax = ops[q].M > mmax ? ops[q].M : mmax;
+  if (choice == 0 && mmax <= 32) return launch_ops<32, 64, 16, 2, 2>(ops, c, s);
   if (sizeof(T) == 8) {
     switch (choice) {
       case 1: return launch_ops<64, 64, 16, 2, 2>(ops, c, s);
@@ -333,6 +337,10 @@ hipError_t launch_vhs_group(const Job* jobs, const int* ids, int c, int choice,
   return vhs_tiles<double>(ops, c, choice, s);
 }
 
+// Launch groups of the HS potential: precision and walker-count class (the rows of its
+// tiles), so that every problem gets its default tile shape.
+static int vhs_key(const afqmc_kpt_problem& p) { return p.prec * 2 + (p.nwalk <= 32 ? 1 : 0); }
+
 hipError_t run_vhs(const Job* jobs, int n, hipStream_t s) {
   TimedScope ts(KC_VHS, s);
   void* zeta[64];
@@ -344,7 +352,7 @@ hipError_t run_vhs(const Job* jobs, int n, hipStream_t s) {
       zeta[q] = cv.take(sizeof(double) * 2 * (size_t)J[q].p.nwalk * J[q].p.nk * J[q].p.nchol);
     }
     hipError_t e = for_groups(
-        c, [&](int i) { return J[i].p.prec; },
+        c, [&](int i) { return vhs_key(J[i].p); },
         [&](const int* ids, int g) -> hipError_t {
           Batch<FieldArgs> B;
           B.nprob = g;
@@ -387,7 +395,7 @@ hipError_t tune_vhs(const Job* jobs, int n, hipStream_t s) {
       zeta[q] = cv.take(sizeof(double) * 2 * (size_t)J[q].p.nwalk * J[q].p.nk * J[q].p.nchol);
     }
     const hipError_t e = for_groups(
-        c, [&](int i) { return J[i].p.prec; },
+        c, [&](int i) { return vhs_key(J[i].p); },
         [&](const int* ids, int g) -> hipError_t {
           return tune_group(
               TS_VHS, J, ids, g, [&](int ch) { return launch_vhs_group(J, ids, g, ch, zeta, s); },

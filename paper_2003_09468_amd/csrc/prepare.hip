@@ -76,6 +76,42 @@ __global__ void to_c64_kernel(int64_t n, const cpx<double>* __restrict__ x, cpx<
     y[i] = cpx<float>{(float)x[i].re, (float)x[i].im};
 }
 
+// BF16 split planes of Lh for the three-pass exchange:
+//   Lhs[Q][k][g][a][plane][r], planes (re hi, re lo, im hi, im lo) of the FP32-rounded
+//   value, hi = bf16(x), lo = bf16(x - hi) (round to nearest even), r padded to KP with 0.
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  unsigned int u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+__global__ void lh_split_kernel(int nk, int m, int nocc, int C, int KP,
+                                const cpx<double>* __restrict__ Lh,
+                                unsigned short* __restrict__ Lhs) {
+  const int64_t total = (int64_t)nk * nk * C * nocc * KP;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(i % KP);
+    const int a = (int)((i / KP) % nocc);
+    const int g = (int)((i / ((int64_t)KP * nocc)) % C);
+    const int64_t qk = i / ((int64_t)KP * nocc * C);
+    float xr = 0.f, xi = 0.f;
+    if (r < m) {
+      const cpx<double> v = Lh[((qk * nocc + a) * m + r) * C + g];
+      xr = (float)v.re;
+      xi = (float)v.im;
+    }
+    const unsigned short rh = bf16_rne(xr), ih = bf16_rne(xi);
+    const unsigned short rl = bf16_rne(xr - __uint_as_float((unsigned int)rh << 16));
+    const unsigned short il = bf16_rne(xi - __uint_as_float((unsigned int)ih << 16));
+    unsigned short* o = Lhs + ((((qk * C + g) * nocc + a) * 4) * KP + r);
+    o[0] = rh;
+    o[KP] = rl;
+    o[2 * KP] = ih;
+    o[3 * KP] = il;
+  }
+}
+
 // One workgroup per k.  Scratch: [nk][4][m][m] complex128 (X, T, E, tmp).
 __global__ __launch_bounds__(256) void expm_kernel(int m, double scale,
                                                    const cpx<double>* __restrict__ H1,
@@ -218,6 +254,13 @@ hipError_t run_prepare(const afqmc_kpt_problem& p, const void* H1, void* ws, hip
     const int64_t n = (int64_t)p.nk * p.nk * p.m * p.m * p.nchol;
     hipLaunchKernelGGL(to_c64_kernel, dim3(4096), dim3(256), 0, s, n, (const cpx<double>*)p.L,
                        (cpx<float>*)p.L32);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (p.prec == AFQMC_PREC_BF16X3) {
+    const int KP = 32 * ((p.m + 31) / 32);
+    hipLaunchKernelGGL(lh_split_kernel, dim3(4096), dim3(256), 0, s, p.nk, p.m, p.nocc,
+                       p.nchol, KP, (const cpx<double>*)p.Lh, (unsigned short*)p.Lhs);
     e = hipGetLastError();
   }
   return e;
