@@ -227,11 +227,17 @@ def run_block(p, xs, bufs, E):
     return p.energy(out=E)
 
 
-def make_problem(s, U0, prec, torch):
-    from paper_2003_09468_amd import KptProblem
+def make_problem(s, U0, prec, torch, tune=True):
+    """Problem with its static data prepared and, once per shape, the tile autotuner run
+    (setup, outside any timed region, like prepare)."""
+    from paper_2003_09468_amd import KptProblem, KptBatch
     p = KptProblem(s.mesh, s.m, s.nocc, s.nchol, U0.shape[0], s.dt, torch.from_numpy(s.L),
                    torch.from_numpy(s.A), prec=prec)
     p.prepare(torch.from_numpy(s.H1))
+    if tune:
+        p.set_walkers(torch.from_numpy(U0))
+        p.greens()
+        KptBatch([p]).autotune()
     return p
 
 
@@ -355,7 +361,7 @@ def bench_batch(args, torch):
         t = time.perf_counter()
         cfg, s, U0, xs = gen_system(nm, torch)
         log(f"generated {nm} {cfg} in {time.perf_counter() - t:.1f} s")
-        p = make_problem(s, U0, lib.PREC_FP64, torch)
+        p = make_problem(s, U0, lib.PREC_FP64, torch, tune=False)
         sysd.append((cfg, s, torch.from_numpy(U0).cuda(), torch.from_numpy(xs), p))
         del s
     ps = [d[4] for d in sysd]

@@ -311,17 +311,18 @@ static hipError_t vhs_tiles(const OpVhs<T>* ops, int c, int choice, hipStream_t 
   int mmax = 0;
   for (int q = 0; q < c; ++q) mmax = ops[q].M > mmax ? ops[q].M : mmax;
   if (choice == 0 && mmax <= 32) return launch_ops<32, 64, 16, 2, 2>(ops, c, s);
-  if (sizeof(T) == 8) {
+  if constexpr (sizeof(T) == 8) {
     switch (choice) {
       case 1: return launch_ops<64, 64, 16, 2, 2>(ops, c, s);
       case 2: return launch_ops<32, 64, 16, 2, 2>(ops, c, s);
       default: return launch_ops<64, 32, 16, 4, 1>(ops, c, s);
     }
-  }
-  switch (choice) {
-    case 1: return launch_ops<64, 32, 16, 4, 1>(ops, c, s);
-    case 2: return launch_ops<64, 128, 16, 2, 2>(ops, c, s);
-    default: return launch_ops<64, 64, 16, 2, 2>(ops, c, s);
+  } else {
+    switch (choice) {
+      case 1: return launch_ops<64, 32, 16, 4, 1>(ops, c, s);
+      case 2: return launch_ops<64, 128, 16, 2, 2>(ops, c, s);
+      default: return launch_ops<64, 64, 16, 2, 2>(ops, c, s);
+    }
   }
 }
 

@@ -111,27 +111,32 @@ static int taylor_class(const afqmc_kpt_problem& p) {
 template <typename T>
 static hipError_t taylor_tiles(const OpTaylor<T>* ops, int c, int cls, int choice,
                                hipStream_t s) {
-  if (sizeof(T) == 8) {
+  if constexpr (sizeof(T) == 8) {
     // 64 x 32 tiles: measured fastest for the 16x16x4 FP64 MFMA at 702 x 108 x 702
     switch (choice) {
       case 1: return launch_ops<64, 64, 16, 2, 2>(ops, c, s);
       case 2: return launch_ops<32, 64, 16, 2, 2>(ops, c, s);
       case 3: return launch_ops<32, 32, 16, 2, 2>(ops, c, s);
+      // one column tile over nk*nocc <= 112 (less zero padding than 32-column tiles):
+      // seven waves side by side, each 64 (or 2 x 64) rows x 16 columns
+      case 4: return launch_ops<64, 112, 16, 1, 7>(ops, c, s);
+      case 5: return launch_ops<128, 112, 16, 2, 7>(ops, c, s);
       default: return launch_ops<64, 32, 16, 4, 1>(ops, c, s);
     }
-  }
-  if (choice == 1) return launch_ops<64, 64, 16, 2, 2>(ops, c, s);
-  if (choice == 2) return launch_ops<64, 32, 16, 4, 1>(ops, c, s);
-  switch (cls) {
-    case 1: return launch_ops<64, 16, 16, 4, 1>(ops, c, s);
-    case 2: return launch_ops<64, 32, 16, 4, 1>(ops, c, s);
-    case 3: return launch_ops<64, 48, 16, 4, 1>(ops, c, s);
-    case 4: return launch_ops<64, 64, 16, 4, 1>(ops, c, s);
-    case 5: return launch_ops<64, 80, 16, 4, 1>(ops, c, s);
-    case 6: return launch_ops<64, 96, 16, 4, 1>(ops, c, s);
-    case 7: return launch_ops<64, 112, 16, 4, 1>(ops, c, s);
-    case 8: return launch_ops<64, 128, 16, 4, 1>(ops, c, s);
-    default: return launch_ops<64, 64, 16, 2, 2>(ops, c, s);
+  } else {
+    if (choice == 1) return launch_ops<64, 64, 16, 2, 2>(ops, c, s);
+    if (choice == 2) return launch_ops<64, 32, 16, 4, 1>(ops, c, s);
+    switch (cls) {
+      case 1: return launch_ops<64, 16, 16, 4, 1>(ops, c, s);
+      case 2: return launch_ops<64, 32, 16, 4, 1>(ops, c, s);
+      case 3: return launch_ops<64, 48, 16, 4, 1>(ops, c, s);
+      case 4: return launch_ops<64, 64, 16, 4, 1>(ops, c, s);
+      case 5: return launch_ops<64, 80, 16, 4, 1>(ops, c, s);
+      case 6: return launch_ops<64, 96, 16, 4, 1>(ops, c, s);
+      case 7: return launch_ops<64, 112, 16, 4, 1>(ops, c, s);
+      case 8: return launch_ops<64, 128, 16, 4, 1>(ops, c, s);
+      default: return launch_ops<64, 64, 16, 2, 2>(ops, c, s);
+    }
   }
 }
 

@@ -42,7 +42,7 @@ void tune_store(const std::string& key, int choice) {
 
 int tune_ncand(int stage, int prec) {
   switch (stage) {
-    case TS_TAYLOR: return low_prec(prec) ? 3 : 4;
+    case TS_TAYLOR: return low_prec(prec) ? 3 : 6;
     case TS_VHS: return 3;
     case TS_VBIAS: return 3;
     default: return 1;
