@@ -235,6 +235,15 @@ afqmc_status afqmc_kpt_energy(const afqmc_kpt_problem* p, int nprob, void* E,
 afqmc_status afqmc_kpt_energy_backward(const afqmc_kpt_problem* p, int nprob, const void* gE,
                                        void* gGh, void* ws, size_t ws_bytes, void* stream);
 
+/* Mixed estimate of the energy per problem ("Standard Representation": the
+ * weighted average of the walkers' local energies):
+ *   Emix[i] = sum_w weight[w] (E[w][0] + E[w][1] + E[w][2]) / sum_w weight[w]
+ * with E from afqmc_kpt_energy (AFQMC_BUF_ENERGY layout) and the problems' current
+ * weights; walkers with weight 0 (killed, singular) drop out.  Emix: [nprob]
+ * complex128, device; NaN when every weight of a problem is 0.  FP64 sums. */
+afqmc_status afqmc_kpt_mixed_energy(const afqmc_kpt_problem* p, int nprob, const void* E,
+                                    void* Emix, void* stream);
+
 /* Packed layout of one per-call buffer for a batch (host).  offsets: host
  * array of nprob + 1 entries; offsets[i] is the byte offset of problem i's
  * slice (a multiple of 256) and offsets[nprob] the end of the last slice, i.e.

@@ -329,6 +329,15 @@ def local_energy(Lh, h1h, Gh, mesh, walkers=None):
     return np.stack([E1, EC, EX], axis=1)
 
 
+def mixed_energy(E_parts, weight):
+    """Mixed estimate of the energy (the mixed-estimate equation of the standard-
+    representation section): sum_a w_a E_L[phi_a] / sum_a w_a, with E_L the sum of the
+    three parts (one-body, Coulomb, exchange) per walker."""
+    EL = np.asarray(E_parts).sum(axis=1)
+    w = np.asarray(weight, dtype=float)
+    return complex((w * EL).sum() / w.sum())
+
+
 def energy_gradient(Lh, h1h, Gh, mesh, walkers=None):
     """dE/dGh[w][(k1 al), (k2 rho)] of the local energy above (holomorphic derivative).
 

@@ -51,6 +51,7 @@ EXPORTS = [
     "afqmc_kpt_orthonormalize",
     "afqmc_kpt_energy",
     "afqmc_kpt_energy_backward",
+    "afqmc_kpt_mixed_energy",
     "afqmc_kpt_buffer_layout",
     "afqmc_kpt_step",
     "afqmc_kpt_autotune",
@@ -131,6 +132,7 @@ def lib():
         "afqmc_kpt_orthonormalize": [P, i, vp, sz, vp],
         "afqmc_kpt_energy": [P, i, vp, vp, sz, vp],
         "afqmc_kpt_energy_backward": [P, i, vp, vp, vp, sz, vp],
+        "afqmc_kpt_mixed_energy": [P, i, vp, vp, vp],
         "afqmc_kpt_buffer_layout": [P, i, i, ctypes.POINTER(sz)],
         "afqmc_kpt_step": [P, i, vp, i, vp, vp, vp, i, vp, sz, vp],
         "afqmc_kpt_autotune": [P, i, vp, vp, sz, vp],
@@ -329,6 +331,14 @@ class KptProblem:
                                               ws, nb, _stream()))
         return out
 
+    def mixed_energy(self, E):
+        """Weighted average of the walkers' local energies (current weights)."""
+        out = torch.empty(1, dtype=torch.complex128, device=self.device)
+        check("afqmc_kpt_mixed_energy",
+              lib().afqmc_kpt_mixed_energy(ctypes.byref(self.struct), 1, E.data_ptr(),
+                                           out.data_ptr(), _stream()))
+        return out[0]
+
     def step(self, x, ortho=False, bufs=None):
         """force bias -> HS potential -> propagate (new Gh, logdet, weights)."""
         if bufs is None:
@@ -417,6 +427,14 @@ class KptBatch:
     def energy(self, i):
         p = self.problems[i]
         return self._view(self._E, "energy", i, torch.complex128, (p.nwalk, 3))
+
+    def mixed_energy(self):
+        """Mixed estimate per system from the last step's energies (afqmc_kpt_mixed_energy)."""
+        out = torch.empty(self.n, dtype=torch.complex128, device=self.device)
+        check("afqmc_kpt_mixed_energy",
+              lib().afqmc_kpt_mixed_energy(self.arr, self.n, self._E.data_ptr(), out.data_ptr(),
+                                           _stream()))
+        return out
 
     def greens(self):
         ws = self.workspace()

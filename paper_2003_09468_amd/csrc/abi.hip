@@ -389,6 +389,18 @@ afqmc_status afqmc_kpt_energy_backward(const afqmc_kpt_problem* p, int nprob, co
   return hip_status(run_energy_backward(jobs.data(), nprob, (hipStream_t)stream));
 }
 
+afqmc_status afqmc_kpt_mixed_energy(const afqmc_kpt_problem* p, int nprob, const void* E,
+                                    void* Emix, void* stream) {
+  AFQMC_TRY(check_problems(p, nprob, N_WEIGHT));
+  AFQMC_TRY(check_ptr(E, 16));
+  AFQMC_TRY(check_ptr(Emix, 16));
+  AFQMC_TRY(check_device());
+  Bufs b;
+  b.E = (void*)E;
+  std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_ENERGY, nullptr, b);
+  return hip_status(run_mixed_energy(jobs.data(), nprob, Emix, (hipStream_t)stream));
+}
+
 afqmc_status afqmc_kpt_buffer_layout(const afqmc_kpt_problem* p, int nprob, int buf,
                                      size_t* offsets) {
   if (!p || !offsets) return AFQMC_ENULL;

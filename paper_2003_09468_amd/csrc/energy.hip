@@ -583,6 +583,73 @@ hipError_t run_energy(const Job* jobs, int n, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Mixed estimate: one workgroup per problem, FP64 sums of w E_L and w over the walkers.
+struct MixArgs {
+  int W;
+  const cpx<double>* E;  // [W][3]
+  const double* weight;  // [W]
+  cpx<double>* out;      // one value
+};
+
+__global__ __launch_bounds__(256) void mixed_energy_kernel(const Batch<MixArgs> B) {
+  long long loc;
+  const int pb = batch_find(B, blockIdx.x, loc);
+  const MixArgs a = B.a[pb];
+  const int tid = threadIdx.x;
+  __shared__ double red[3][256];
+  double sr = 0.0, si = 0.0, sw = 0.0;
+  for (int w = tid; w < a.W; w += 256) {
+    const double wt = a.weight[w];
+    const cpx<double> e0 = a.E[3 * (int64_t)w], e1 = a.E[3 * (int64_t)w + 1],
+                      e2 = a.E[3 * (int64_t)w + 2];
+    if (wt != 0.0) {  // a zero weight drops the walker even if its energy is not finite
+      sr += wt * (e0.re + e1.re + e2.re);
+      si += wt * (e0.im + e1.im + e2.im);
+      sw += wt;
+    }
+  }
+  red[0][tid] = sr; red[1][tid] = si; red[2][tid] = sw;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (tid < o) {
+      red[0][tid] += red[0][tid + o];
+      red[1][tid] += red[1][tid + o];
+      red[2][tid] += red[2][tid + o];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double s = red[2][0];
+    *a.out = (s != 0.0) ? cpx<double>{red[0][0] / s, red[1][0] / s}
+                        : cpx<double>{__builtin_nan(""), __builtin_nan("")};
+  }
+}
+
+hipError_t run_mixed_energy(const Job* jobs, int n, void* Emix, hipStream_t s) {
+  TimedScope ts(KC_ENERGY_REST, s);
+  for (int c0 = 0; c0 < n; c0 += AFQMC_MAXP) {
+    const int c = (n - c0 < AFQMC_MAXP) ? n - c0 : AFQMC_MAXP;
+    Batch<MixArgs> B;
+    B.nprob = c;
+    long long cnt[AFQMC_MAXP];
+    for (int q = 0; q < c; ++q) {
+      const Job& j = jobs[c0 + q];
+      B.a[q].W = j.p.nwalk;
+      B.a[q].E = (const cpx<double>*)j.E;
+      B.a[q].weight = j.p.weight;
+      B.a[q].out = (cpx<double>*)Emix + c0 + q;
+      cnt[q] = 1;
+    }
+    const long long g = batch_close(B, cnt);
+    if (g <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mixed_energy_kernel, dim3((unsigned)g), dim3(256), 0, s, B);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint.  One workgroup per (k1, k2, walker chunk) accumulates over Q and g
 //   K[(w al), rho] = sum_{b,g} T1_{(Q,k1,k2)}[w][b][al][g] Lh[-Q][k2-Q][b][rho][g]
 // with T1 recomputed per g chunk (GEMM 1, K = m) and fed through a wave-private LDS tile

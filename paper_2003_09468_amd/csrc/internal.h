@@ -102,6 +102,7 @@ hipError_t run_propagate(const Job* jobs, int n, int flags, hipStream_t s);
 hipError_t run_ortho(const Job* jobs, int n, hipStream_t s);
 hipError_t run_energy(const Job* jobs, int n, hipStream_t s);
 hipError_t run_energy_backward(const Job* jobs, int n, hipStream_t s);
+hipError_t run_mixed_energy(const Job* jobs, int n, void* Emix, hipStream_t s);
 
 // Kernels shared across translation units.  launch_cholesky_trace writes X (and xbar when
 // requested) of every job; parts are the per-job split-K slices.

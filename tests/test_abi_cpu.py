@@ -285,3 +285,13 @@ def test_step_reaches_device_check(L):
     assert L.afqmc_kpt_graph_create(arr, 2, a["x"], a["nsteps"], a["xbar"], a["vhs"], a["E"],
                                     a["flags"], a["ws"], a["nbytes"], ctypes.byref(h)) == -5
     assert L.afqmc_kpt_autotune(arr, 2, a["vhs"], a["ws"], a["nbytes"], None) == -5
+
+
+def test_mixed_energy_validation(L):
+    arr = two_problems()
+    assert L.afqmc_kpt_mixed_energy(arr, 2, None, ctypes.c_void_p(0x2000), None) == -2
+    assert L.afqmc_kpt_mixed_energy(arr, 2, ctypes.c_void_p(0x2008), ctypes.c_void_p(0x2000),
+                                    None) == -3
+    arr[1].weight = None
+    assert L.afqmc_kpt_mixed_energy(arr, 2, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x4000),
+                                    None) == -2

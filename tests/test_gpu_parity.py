@@ -260,3 +260,23 @@ def test_greens_at_maximum_occupied_dimension():
     assert rel(host(p.Gh), Gh) < 1e-10
     assert phase_err(host(p.logdet), ld) < 1e-10
     assert int(host(p.status).max()) == 0
+
+
+def test_mixed_energy():
+    """The weighted average of the walkers' energies after a step, on the GPU's own energies
+    and weights, against the oracle's formula; also on every system of a batch."""
+    from paper_2003_09468_amd import KptBatch
+    s, U, x, p, pre = build("line3")
+    p.step(torch.from_numpy(x[0]))
+    E = p.energy()
+    Em = complex(host(p.mixed_energy(E)))
+    ref = kp.mixed_energy(host(E), host(p.weight))
+    assert abs(Em - ref) < 1e-12 * max(1.0, abs(ref))
+    items = [build(c, seed=20 + i) for i, c in enumerate(["aniso", "mixed"])]
+    b = KptBatch([it[3] for it in items])
+    f = b.fields([torch.from_numpy(it[2][:1]) for it in items])
+    b.step(f, energy=True)
+    got = host(b.mixed_energy())
+    for i, it in enumerate(items):
+        ref = kp.mixed_energy(host(b.energy(i)), host(it[3].weight))
+        assert abs(got[i] - ref) < 1e-12 * max(1.0, abs(ref))

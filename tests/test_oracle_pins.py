@@ -380,3 +380,31 @@ def test_weight_update_cases():
     s = 2 * (0.5 * (0.25 + 0.1j) - 0.5 * (0.25 + 0.1j) ** 2)
     np.testing.assert_allclose(logI2[0], s, rtol=1e-15)
     np.testing.assert_allclose(w2[0], math.exp(s.real), rtol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# mixed estimate of the energy
+# ---------------------------------------------------------------------------
+
+def test_mixed_energy_cases():
+    E = np.array([[1.0, 2.0, -0.5], [2.0 + 1.0j, 0.0, 0.0], [10.0, 0.0, 0.0]])
+    EL = E.sum(1)
+    # equal weights: the plain mean; a zero weight drops its walker
+    assert abs(kp.mixed_energy(E, np.ones(3)) - EL.mean()) < 1e-15
+    assert abs(kp.mixed_energy(E, [1.0, 1.0, 0.0]) - EL[:2].mean()) < 1e-15
+    # weights are relative: scaling them changes nothing
+    w = np.array([0.3, 1.7, 2.0])
+    assert abs(kp.mixed_energy(E, w) - kp.mixed_energy(E, 5.0 * w)) < 1e-14
+    assert abs(kp.mixed_energy(E, w) - (w * EL).sum() / w.sum()) < 1e-15
+
+
+def test_mixed_energy_on_trial_walkers_is_slater_condon():
+    """Walkers on the trial determinant: the mixed estimate is the HF energy from explicit
+    4-index integrals, for any weights."""
+    s, _, _ = tiny((2, 2, 2), m=4, nocc=2, nchol=5, trial="random")
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    LL, v, h, Af = supercell_objects(s)
+    Gh, _ = kp.greens(np.stack([Af, Af, Af]), s.A)
+    E = kp.local_energy(pre["Lh"], pre["h1h"], Gh, s.mesh)
+    e_hf = sum(sc.slater_condon_energy(h, v, Af))
+    assert abs(kp.mixed_energy(E, [0.2, 3.0, 1.0]) - e_hf) < 1e-11 * max(1.0, abs(e_hf))
