@@ -69,10 +69,11 @@ typedef enum {
  * all energy sums are FP64 in every mode.
  *   FP64:   complex128 operands, FP64 MFMA.
  *   FP32:   complex64 operands (L32, Lh32), FP32 MFMA with FP32 accumulation.
- *   BF16X3: as FP32, except the exchange contraction of the local energy, whose
- *           operands are split x = hi + lo into two bfloat16 numbers and
- *           multiplied in three BF16 MFMA passes (hi hi + hi lo + lo hi) with
- *           FP32 accumulation; the energy adjoint stays FP32. */
+ *   BF16X3: as FP32, except the HS potential and the exchange contraction of
+ *           the local energy, whose operands are split x = hi + lo into two
+ *           bfloat16 numbers and multiplied in three BF16 MFMA passes
+ *           (hi hi + hi lo + lo hi) with FP32 accumulation; the force bias, the
+ *           Taylor terms (on the FP32 potential) and the energy adjoint are FP32. */
 typedef enum {
   AFQMC_PREC_FP64 = 0,
   AFQMC_PREC_FP32 = 1,
@@ -136,6 +137,9 @@ typedef struct afqmc_kpt_problem {
   void* Lh32;        /* [nk][nk][nocc][m][nchol] complex64 copy of Lh; prec FP32/BF16X3 only */
   void* Lhs;         /* [nk][nk][nchol][nocc][4][32*ceil(m/32)] bfloat16 (uint16) split planes
                         of Lh (re hi, re lo, im hi, im lo; r padded with zeros), written by
+                        prepare; prec BF16X3 only (else NULL) */
+  void* Ls;          /* [nk][nk][m][m][4][32*ceil(nchol/32)] bfloat16 (uint16) split planes
+                        of L (re hi, re lo, im hi, im lo; g padded with zeros), written by
                         prepare; prec BF16X3 only (else NULL) */
   /* walker state */
   void* U;           /* [nwalk][nk*m][nk*nocc] complex128 walker orbitals, in/out */

@@ -94,6 +94,7 @@ class Problem(ctypes.Structure):
         ("L32", ctypes.c_void_p),
         ("Lh32", ctypes.c_void_p),
         ("Lhs", ctypes.c_void_p),
+        ("Ls", ctypes.c_void_p),
         ("U", ctypes.c_void_p),
         ("Gh", ctypes.c_void_p),
         ("logdet", ctypes.c_void_p),
@@ -210,10 +211,12 @@ class KptProblem:
             self.Lh32 = torch.empty(self.Lh.shape, dtype=torch.complex64, **kw)
         else:
             self.L32 = self.Lh32 = None
-        self.Lhs = None
+        self.Lhs = self.Ls = None
         if self.prec == PREC_BF16X3:
             kp = 32 * ((m + 31) // 32)
+            cp = 32 * ((nchol + 31) // 32)
             self.Lhs = torch.empty((nk, nk, nchol, nocc, 4, kp), dtype=torch.int16, **kw)
+            self.Ls = torch.empty((nk, nk, m, m, 4, cp), dtype=torch.int16, **kw)
         N, n = nk * m, nk * nocc
         self.U = torch.zeros((nwalk, N, n), dtype=c128, **kw)
         self.Gh = torch.zeros((nwalk, n, N), dtype=c128, **kw)
@@ -231,7 +234,8 @@ class KptProblem:
         p.prec, p.dt = self.prec, self.dt
         p.L, p.A, p.Lh, p.h1h, p.bhalf = (_ptr(self.L), _ptr(self.A), _ptr(self.Lh),
                                           _ptr(self.h1h), _ptr(self.bhalf))
-        p.L32, p.Lh32, p.Lhs = _ptr(self.L32), _ptr(self.Lh32), _ptr(self.Lhs)
+        p.L32, p.Lh32, p.Lhs, p.Ls = (_ptr(self.L32), _ptr(self.Lh32), _ptr(self.Lhs),
+                                      _ptr(self.Ls))
         p.U = _ptr(self.U)
         p.Gh = _ptr(self.Gh if Gh is None else Gh)
         p.logdet, p.weight, p.status = _ptr(self.logdet), _ptr(self.weight), _ptr(self.status)

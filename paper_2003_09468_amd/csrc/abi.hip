@@ -22,7 +22,11 @@ size_t ws_bytes_entry(const afqmc_kpt_problem& p, int entry) {
     case AFQMC_ENTRY_PREPARE: return prepare_ws_bytes(p);
     case AFQMC_ENTRY_GREENS: { Carve c(nullptr); GreensWs g; return carve_greens(c, d, g); }
     case AFQMC_ENTRY_VBIAS: { Carve c(nullptr); VbiasWs v; return carve_vbias(c, d, v); }
-    case AFQMC_ENTRY_VHS: return align_up(16 * (size_t)d.W * d.nk * d.C);
+    case AFQMC_ENTRY_VHS: {  // the combined field, or its BF16 split planes
+      const size_t cp = 32 * (size_t)((d.C + 31) / 32);
+      const size_t a = 16 * (size_t)d.W * d.nk * d.C, b = 8 * (size_t)d.W * d.nk * cp;
+      return align_up(a > b ? a : b);
+    }
     case AFQMC_ENTRY_PROPAGATE: {
       const size_t a = propagate_ws_bytes(p), b = ortho_ws_bytes(p);
       return a > b ? a : b;
@@ -77,7 +81,7 @@ enum Need : unsigned {
   N_L = 1u << 0, N_A = 1u << 1, N_LH = 1u << 2, N_H1H = 1u << 3, N_BHALF = 1u << 4,
   N_U = 1u << 5, N_GH = 1u << 6, N_LOGDET = 1u << 7, N_WEIGHT = 1u << 8, N_STATUS = 1u << 9,
   N_LD = 1u << 10, N_LHD = 1u << 11,  // *D: the complex128 arrays in every precision
-  N_LHS = 1u << 12                     // the BF16 split planes (BF16X3 problems only)
+  N_LHS = 1u << 12, N_LS = 1u << 13    // the BF16 split planes (BF16X3 problems only)
 };
 
 inline bool misaligned(const void* p, size_t a) { return ((uintptr_t)p) % a != 0; }
@@ -127,6 +131,7 @@ afqmc_status check_fields(const afqmc_kpt_problem& p, unsigned need) {
   if (need & N_WEIGHT) AFQMC_TRY(check_ptr(p.weight, 8));
   if (need & N_STATUS) AFQMC_TRY(check_ptr(p.status, 4));
   if ((need & N_LHS) && p.prec == AFQMC_PREC_BF16X3) AFQMC_TRY(check_ptr(p.Lhs, 16));
+  if ((need & N_LS) && p.prec == AFQMC_PREC_BF16X3) AFQMC_TRY(check_ptr(p.Ls, 16));
   return AFQMC_OK;
 }
 
@@ -240,7 +245,7 @@ hipError_t run_steps(std::vector<Job>& jobs, const double* x, size_t stride, int
 afqmc_status check_step_args(const afqmc_kpt_problem* p, int nprob, const double* x, int nsteps,
                              void* xbar, void* vhs, void* E, int flags, void* ws,
                              size_t ws_bytes) {
-  unsigned need = N_L | N_LH | N_A | N_BHALF | N_U | N_GH | N_LOGDET | N_WEIGHT | N_STATUS;
+  unsigned need = N_L | N_LS | N_LH | N_A | N_BHALF | N_U | N_GH | N_LOGDET | N_WEIGHT | N_STATUS;
   if (flags & AFQMC_STEP_ENERGY) need |= N_H1H | N_LHS;
   AFQMC_TRY(check_problems(p, nprob, need));
   if (nsteps < 1) return AFQMC_EINVAL;
@@ -283,7 +288,7 @@ afqmc_status afqmc_kpt_prepare(const afqmc_kpt_problem* p, int nprob, const void
   AFQMC_TRY(check_problems(p, nprob, 0));
   for (int i = 0; i < nprob; ++i) {
     unsigned need = N_A | N_H1H | N_BHALF | N_LD | N_LHD;  // complex128 L and Lh always
-    if (low_prec(p[i].prec)) need |= N_L | N_LH | N_LHS;  // plus the complex64 copies
+    if (low_prec(p[i].prec)) need |= N_L | N_LH | N_LHS | N_LS;  // plus the lower-precision copies
     AFQMC_TRY(check_fields(p[i], need));
   }
   AFQMC_TRY(check_ptr(H1, 16));
@@ -320,7 +325,7 @@ afqmc_status afqmc_kpt_vbias(const afqmc_kpt_problem* p, int nprob, void* xbar, 
 
 afqmc_status afqmc_kpt_vhs(const afqmc_kpt_problem* p, int nprob, const double* x,
                            const void* xbar, void* vhs, void* ws, size_t ws_bytes, void* stream) {
-  AFQMC_TRY(check_problems(p, nprob, N_L));
+  AFQMC_TRY(check_problems(p, nprob, N_L | N_LS));
   AFQMC_TRY(check_ptr(x, 8));
   AFQMC_TRY(check_ptr(xbar, 16));
   AFQMC_TRY(check_ptr(vhs, 16));

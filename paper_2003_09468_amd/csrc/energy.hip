@@ -201,33 +201,6 @@ __global__ __launch_bounds__(256) void exchange_kernel(const Batch<ExchArgs> B) 
 // (w, b), K = r padded to 32 * KB; the Gh fragments are split once into registers, and the
 // Lh slabs come pre-split from prepare (four bf16 planes: re hi, re lo, im hi, im lo, r
 // contiguous) and are staged into LDS with 16-byte copies.
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ unsigned short bf16_bits_rne(float x) {
-  unsigned int u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-
-__device__ __forceinline__ void bf16_split(float x, unsigned short& hi, unsigned short& lo) {
-  hi = bf16_bits_rne(x);
-  lo = bf16_bits_rne(x - __uint_as_float((unsigned int)hi << 16));
-}
-
-__device__ __forceinline__ v4f mfma_bf16(const u16x8& a, const u16x8& b, v4f c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
-                                                __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
-}
-
-// d += (ah + al)(bh + bl) without the al bl term
-__device__ __forceinline__ v4f mul3(const u16x8& ah, const u16x8& al, const u16x8& bh,
-                                    const u16x8& bl, v4f d) {
-  d = mfma_bf16(al, bh, d);
-  d = mfma_bf16(ah, bl, d);
-  return mfma_bf16(ah, bh, d);
-}
-
 template <int KB>
 __global__ __launch_bounds__(256) void exchange_bf16x3_kernel(const Batch<ExchArgs> B) {
   constexpr int KP = 32 * KB;  // r padded to the MFMA K

@@ -260,6 +260,201 @@ __global__ __launch_bounds__(256) void field_kernel(const Batch<FieldArgs> B) {
   zeta[idx] = cpx<T>{(T)(-xr), (T)(-xi)};
 }
 
+// The combined field as BF16 split planes for the three-pass HS potential:
+//   zs[w][Q][plane][g], planes (re hi, re lo, im hi, im lo) of the FP32-rounded zeta,
+//   g contiguous and zero-padded to CP = 32 ceil(C / 32).
+__global__ __launch_bounds__(256) void field_split_kernel(const Batch<FieldArgs> B) {
+  long long bloc;
+  const int pb = batch_find(B, blockIdx.x, bloc);
+  const int W = B.a[pb].W, nk = B.a[pb].nk, C = B.a[pb].C;
+  const int CP = 32 * ((C + 31) / 32);
+  const KMesh mesh = B.a[pb].mesh;
+  const double* __restrict__ x = B.a[pb].x;
+  const cpx<double>* __restrict__ xbar = B.a[pb].xbar;
+  unsigned short* __restrict__ zs = (unsigned short*)B.a[pb].zeta;
+  const int64_t idx = bloc * 256 + threadIdx.x;
+  const int64_t total = (int64_t)W * nk * CP;
+  if (idx >= total) return;
+  const int g = (int)(idx % CP);
+  const int64_t wq = idx / CP;  // w nk + Q
+  const int Q = (int)(wq % nk), w = (int)(wq / nk);
+  float zr = 0.f, zi = 0.f;
+  if (g < C) {
+    const int64_t i = wq * C + g;
+    const int64_t j = ((int64_t)w * nk + mesh.neg(Q)) * C + g;
+    const double apr = x[2 * i] - xbar[2 * i].re, api = -xbar[2 * i].im;
+    const double amr = x[2 * i + 1] - xbar[2 * i + 1].re, ami = -xbar[2 * i + 1].im;
+    const double bpr = x[2 * j] - xbar[2 * j].re, bpi = -xbar[2 * j].im;
+    const double bmr = x[2 * j + 1] - xbar[2 * j + 1].re, bmi = -xbar[2 * j + 1].im;
+    const double sr = apr + bpr, si = api + bpi, dr = amr - bmr, di = ami - bmi;
+    zr = (float)(-0.5 * (-si + dr));
+    zi = (float)(-0.5 * (sr + di));
+  }
+  unsigned short rh, rl, ih, il;
+  bf16_split(zr, rh, rl);
+  bf16_split(zi, ih, il);
+  unsigned short* o = zs + wq * 4 * CP + g;
+  o[0] = rh;
+  o[CP] = rl;
+  o[2 * CP] = ih;
+  o[3 * CP] = il;
+}
+
+// HS potential on the three-pass BF16 split:
+//   vhs[w][(k p), ((k-Q) r)] = sum_g zeta[w][Q][g] L[Q][k][p][r][g]
+// per Q a (W x nk m m) product with K = nchol, 64 x 64 tiles of four waves (2 x 2, each
+// 32 x 32), K in chunks of 32; both operands come as split planes with g contiguous and
+// are staged into LDS with 16-byte copies; 12 BF16 MFMAs per complex 16 x 16 x 32 block.
+struct VhsBfArgs {
+  int W, nk, m, C, tiles_m, tiles_n;
+  KMesh mesh;
+  const unsigned short* zs;  // [W][nk][4][CP]
+  const unsigned short* Ls;  // [nk][nk m m][4][CP]
+  cpx<float>* vhs;           // [W][nk m][nk m]
+};
+
+__global__ __launch_bounds__(256) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> B) {
+  constexpr int BM = 64, BN = 64, BKC = 32, RS = BKC + 8;
+  __shared__ __attribute__((aligned(16))) unsigned short sA[2][4][BM][RS];
+  __shared__ __attribute__((aligned(16))) unsigned short sB[2][4][BN][RS];
+  long long bloc;
+  const int pb = batch_find(B, blockIdx.x, bloc);
+  const VhsBfArgs& a = B.a[pb];
+  const int W = a.W, nk = a.nk, m = a.m, C = a.C;
+  const int CP = 32 * ((C + 31) / 32);
+  const int ncol = nk * m * m;
+  const int per_q = a.tiles_m * a.tiles_n;
+  const int Q = (int)(bloc / per_q);
+  const int rem = (int)(bloc % per_q);
+  const int row0 = (rem / a.tiles_n) * BM, col0 = (rem % a.tiles_n) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const unsigned short* __restrict__ zs = a.zs;
+  const unsigned short* __restrict__ Ls = a.Ls + (int64_t)Q * ncol * 4 * CP;
+
+  // 16-byte units of a chunk: u = (row 4 + plane) 4 + c8; 64 rows x 4 planes x 4 = 1024
+  uint4 pa[4], pbu[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int u = tid + 256 * e;
+      const int r = u >> 4, pl = (u >> 2) & 3, c8 = u & 3;
+      uint4 va = {0u, 0u, 0u, 0u}, vb = {0u, 0u, 0u, 0u};
+      const int w = row0 + r;
+      if (w < W)
+        va = *reinterpret_cast<const uint4*>(
+            zs + (((int64_t)w * nk + Q) * 4 + pl) * CP + k0 + 8 * c8);
+      const int col = col0 + r;
+      if (col < ncol)
+        vb = *reinterpret_cast<const uint4*>(Ls + ((int64_t)col * 4 + pl) * CP + k0 + 8 * c8);
+      pa[e] = va;
+      pbu[e] = vb;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int u = tid + 256 * e;
+      const int r = u >> 4, pl = (u >> 2) & 3, c8 = u & 3;
+      *reinterpret_cast<uint4*>(&sA[buf][pl][r][8 * c8]) = pa[e];
+      *reinterpret_cast<uint4*>(&sB[buf][pl][r][8 * c8]) = pbu[e];
+    }
+  };
+
+  v4f acr[2][2], aci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acr[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+      aci[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+  const u16x8 sgn = {0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000};
+  const int nch = CP / BKC;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) fetch((c + 1) * BKC);
+    const int kq = 8 * (lane >> 4);
+    u16x8 fa[2][4], fb[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) {
+        fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[buf][pl][wm * 32 + i * 16 + (lane & 15)][kq]);
+        fb[i][pl] = *reinterpret_cast<const u16x8*>(&sB[buf][pl][wn * 32 + i * 16 + (lane & 15)][kq]);
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        // re += Ar Br - Ai Bi,  im += Ar Bi + Ai Br
+        acr[i][j] = mul3(fa[i][0], fa[i][1], fb[j][0], fb[j][1], acr[i][j]);
+        acr[i][j] = mul3(fa[i][2] ^ sgn, fa[i][3] ^ sgn, fb[j][2], fb[j][3], acr[i][j]);
+        aci[i][j] = mul3(fa[i][0], fa[i][1], fb[j][2], fb[j][3], aci[i][j]);
+        aci[i][j] = mul3(fa[i][2], fa[i][3], fb[j][0], fb[j][1], aci[i][j]);
+      }
+    if (c + 1 < nch) stash(buf ^ 1);
+    __syncthreads();
+  }
+  // scatter: column (k p r) of Q to vhs[w][(k p)][((k - Q) r)]
+  const int64_t Nn = (int64_t)nk * m;
+  const int mm = m * m;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int w = row0 + wm * 32 + i * 16 + mfma16<float>::drow(lane, v);
+        const int col = col0 + wn * 32 + j * 16 + (lane & 15);
+        if (w >= W || col >= ncol) continue;
+        const int kp = col / mm, pr = col % mm;
+        const int p = pr / m, r = pr % m;
+        const int k2 = a.mesh.kmq(kp, Q);
+        a.vhs[((int64_t)w * Nn + (int64_t)kp * m + p) * Nn + (int64_t)k2 * m + r] =
+            cpx<float>{acr[i][j][v], aci[i][j][v]};
+      }
+}
+
+static hipError_t launch_vhs_bf16x3(const Job* J, const int* ids, int g, void* const* zeta,
+                                    hipStream_t s) {
+  Batch<FieldArgs> F;
+  Batch<VhsBfArgs> V;
+  F.nprob = V.nprob = g;
+  long long cf[AFQMC_MAXP], cv[AFQMC_MAXP];
+  for (int q = 0; q < g; ++q) {
+    const Job& j = J[ids[q]];
+    const afqmc_kpt_problem& p = j.p;
+    const int CP = 32 * ((p.nchol + 31) / 32);
+    FieldArgs& fa = F.a[q];
+    fa.W = p.nwalk; fa.nk = p.nk; fa.C = p.nchol;
+    fa.mesh = make_mesh(p);
+    fa.x = j.x;
+    fa.xbar = (const cpx<double>*)j.xbar;
+    fa.zeta = zeta[ids[q]];
+    cf[q] = ((int64_t)p.nwalk * p.nk * CP + 255) / 256;
+    VhsBfArgs& va = V.a[q];
+    va.W = p.nwalk; va.nk = p.nk; va.m = p.m; va.C = p.nchol;
+    va.tiles_m = (p.nwalk + 63) / 64;
+    va.tiles_n = (p.nk * p.m * p.m + 63) / 64;
+    va.mesh = make_mesh(p);
+    va.zs = (const unsigned short*)zeta[ids[q]];
+    va.Ls = (const unsigned short*)p.Ls;
+    va.vhs = (cpx<float>*)j.vhs;
+    cv[q] = (long long)p.nk * va.tiles_m * va.tiles_n;
+  }
+  long long gf = batch_close(F, cf), gv = batch_close(V, cv);
+  if (gf < 0 || gv < 0) return hipErrorInvalidValue;
+  if (gf > 0) hipLaunchKernelGGL(field_split_kernel, dim3((unsigned)gf), dim3(256), 0, s, F);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || gv == 0) return e;
+  hipLaunchKernelGGL(vhs_bf16x3_kernel, dim3((unsigned)gv), dim3(256), 0, s, V);
+  return hipGetLastError();
+}
+
 template <typename TT>
 struct OpVhs {
   typedef TT T;
@@ -338,6 +533,13 @@ hipError_t launch_vhs_group(const Job* jobs, const int* ids, int c, int choice,
   return vhs_tiles<double>(ops, c, choice, s);
 }
 
+// Workspace of the combined field: complex values, or the BF16 split planes.
+static size_t zeta_bytes(const afqmc_kpt_problem& p) {
+  const size_t cp = 32 * (size_t)((p.nchol + 31) / 32);
+  const size_t a = 16 * (size_t)p.nwalk * p.nk * p.nchol, b = 8 * (size_t)p.nwalk * p.nk * cp;
+  return a > b ? a : b;
+}
+
 // Launch groups of the HS potential: precision and walker-count class (the rows of its
 // tiles), so that every problem gets its default tile shape.
 static int vhs_key(const afqmc_kpt_problem& p) { return p.prec * 2 + (p.nwalk <= 32 ? 1 : 0); }
@@ -350,11 +552,12 @@ hipError_t run_vhs(const Job* jobs, int n, hipStream_t s) {
     const Job* J = jobs + c0;
     for (int q = 0; q < c; ++q) {
       Carve cv(J[q].ws);
-      zeta[q] = cv.take(sizeof(double) * 2 * (size_t)J[q].p.nwalk * J[q].p.nk * J[q].p.nchol);
+      zeta[q] = cv.take(zeta_bytes(J[q].p));
     }
     hipError_t e = for_groups(
         c, [&](int i) { return vhs_key(J[i].p); },
         [&](const int* ids, int g) -> hipError_t {
+          if (J[ids[0]].p.prec == AFQMC_PREC_BF16X3) return launch_vhs_bf16x3(J, ids, g, zeta, s);
           Batch<FieldArgs> B;
           B.nprob = g;
           long long cnt[AFQMC_MAXP];
@@ -393,7 +596,7 @@ hipError_t tune_vhs(const Job* jobs, int n, hipStream_t s) {
     const Job* J = jobs + c0;
     for (int q = 0; q < c; ++q) {
       Carve cv(J[q].ws);
-      zeta[q] = cv.take(sizeof(double) * 2 * (size_t)J[q].p.nwalk * J[q].p.nk * J[q].p.nchol);
+      zeta[q] = cv.take(zeta_bytes(J[q].p));
     }
     const hipError_t e = for_groups(
         c, [&](int i) { return vhs_key(J[i].p); },

@@ -68,6 +68,36 @@ __device__ __forceinline__ long long xcd_remap(long long bid, long long total) {
   return x * q + (x < r ? x : r) + i;
 }
 
+// bfloat16 bits of x, round to nearest even; and the split x = hi + lo (+ O(2^-16 |x|)).
+__device__ __forceinline__ unsigned short bf16_bits_rne(float x) {
+  unsigned int u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ void bf16_split(float x, unsigned short& hi, unsigned short& lo) {
+  hi = bf16_bits_rne(x);
+  lo = bf16_bits_rne(x - __uint_as_float((unsigned int)hi << 16));
+}
+
+// 16x16x32 BF16 MFMA on raw bf16 bits.  Lane l supplies A[l % 16][8 (l / 16) + i] and
+// B[8 (l / 16) + i][l % 16], i < 8; D as for the FP32 16x16x4 instruction.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ v4f mfma_bf16(const u16x8& a, const u16x8& b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// d += (ah + al)(bh + bl) without the al bl term (three BF16 passes)
+__device__ __forceinline__ v4f mul3(const u16x8& ah, const u16x8& al, const u16x8& bh,
+                                    const u16x8& bl, v4f d) {
+  d = mfma_bf16(al, bh, d);
+  d = mfma_bf16(ah, bl, d);
+  return mfma_bf16(ah, bh, d);
+}
+
 // k-point index algebra on the device (mesh row-major linearisation).
 struct KMesh {
   int m0, m1, m2;

@@ -79,12 +79,6 @@ __global__ void to_c64_kernel(int64_t n, const cpx<double>* __restrict__ x, cpx<
 // BF16 split planes of Lh for the three-pass exchange:
 //   Lhs[Q][k][g][a][plane][r], planes (re hi, re lo, im hi, im lo) of the FP32-rounded
 //   value, hi = bf16(x), lo = bf16(x - hi) (round to nearest even), r padded to KP with 0.
-__device__ __forceinline__ unsigned short bf16_rne(float x) {
-  unsigned int u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-
 __global__ void lh_split_kernel(int nk, int m, int nocc, int C, int KP,
                                 const cpx<double>* __restrict__ Lh,
                                 unsigned short* __restrict__ Lhs) {
@@ -101,14 +95,40 @@ __global__ void lh_split_kernel(int nk, int m, int nocc, int C, int KP,
       xr = (float)v.re;
       xi = (float)v.im;
     }
-    const unsigned short rh = bf16_rne(xr), ih = bf16_rne(xi);
-    const unsigned short rl = bf16_rne(xr - __uint_as_float((unsigned int)rh << 16));
-    const unsigned short il = bf16_rne(xi - __uint_as_float((unsigned int)ih << 16));
+    unsigned short rh, rl, ih, il;
+    bf16_split(xr, rh, rl);
+    bf16_split(xi, ih, il);
     unsigned short* o = Lhs + ((((qk * C + g) * nocc + a) * 4) * KP + r);
     o[0] = rh;
     o[KP] = rl;
     o[2 * KP] = ih;
     o[3 * KP] = il;
+  }
+}
+
+// BF16 split planes of L for the three-pass HS potential:
+//   Ls[Q][k][p][r][plane][g], g contiguous and zero-padded to CP = 32 ceil(C / 32).
+__global__ void l_split_kernel(int64_t ncols, int C, int CP, const cpx<double>* __restrict__ L,
+                               unsigned short* __restrict__ Ls) {
+  const int64_t total = ncols * CP;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int g = (int)(i % CP);
+    const int64_t col = i / CP;  // (Q, k, p, r)
+    float xr = 0.f, xi = 0.f;
+    if (g < C) {
+      const cpx<double> v = L[col * C + g];
+      xr = (float)v.re;
+      xi = (float)v.im;
+    }
+    unsigned short rh, rl, ih, il;
+    bf16_split(xr, rh, rl);
+    bf16_split(xi, ih, il);
+    unsigned short* o = Ls + col * 4 * CP + g;
+    o[0] = rh;
+    o[CP] = rl;
+    o[2 * CP] = ih;
+    o[3 * CP] = il;
   }
 }
 
@@ -261,6 +281,12 @@ hipError_t run_prepare(const afqmc_kpt_problem& p, const void* H1, void* ws, hip
     const int KP = 32 * ((p.m + 31) / 32);
     hipLaunchKernelGGL(lh_split_kernel, dim3(4096), dim3(256), 0, s, p.nk, p.m, p.nocc,
                        p.nchol, KP, (const cpx<double>*)p.Lh, (unsigned short*)p.Lhs);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int CP = 32 * ((p.nchol + 31) / 32);
+    const int64_t ncols = (int64_t)p.nk * p.nk * p.m * p.m;
+    hipLaunchKernelGGL(l_split_kernel, dim3(4096), dim3(256), 0, s, ncols, p.nchol, CP,
+                       (const cpx<double>*)p.L, (unsigned short*)p.Ls);
     e = hipGetLastError();
   }
   return e;

@@ -7,11 +7,12 @@ entry for the force bias, HS potential and propagated walkers, 2e-5 for the ener
 (two chained contractions), and 5e-6 of the summed magnitude of the three energy parts per
 walker for E_L (the parts cancel, so their size, not |E|, sets the rounding scale).
 
-BF16X3 (exchange on the three-pass BF16 split, the rest FP32): each split operand keeps
-16 significant bits plus a rounded remainder and the lo*lo term is dropped, so a product
-carries ~2^-16 relative error (~1.5e-5) before FP32 accumulation; the bar on the exchange
-energy is 1e-4 of its largest magnitude, and 5e-5 of the summed part magnitudes on E_L.
-The measured errors sit 5-20 times below these bars.
+BF16X3 (HS potential and exchange on the three-pass BF16 split, the rest FP32): each
+split operand keeps 16 significant bits plus a rounded remainder and the lo*lo term is
+dropped, so a product carries ~2^-16 relative error (~1.5e-5) before FP32 accumulation;
+the bars are 1e-4 of the largest entry for the HS potential and of the largest magnitude
+for the exchange energy, 5e-5 of the summed part magnitudes on E_L, and 5e-5 for one
+propagated step (the potential enters the propagator multiplied by sqrt(dt)).
 """
 
 import numpy as np
@@ -40,11 +41,11 @@ def test_contractions_and_step(case, prec):
     zeta = kp.combined_field(x[0], xbar, s.mesh)
     vref = kp.hs_potential(s.L, zeta, s.mesh)
     v = p.vhs(torch.from_numpy(x[0]), xb)
-    assert rel(host(v), vref) < 5e-6
+    assert rel(host(v), vref) < (5e-6 if prec == 1 else 1e-4)
     out = kp.step(U, ld, np.ones(U.shape[0]), x[0], pre, s.A, s.L, s.mesh, s.dt)
     p.propagate(v, torch.from_numpy(x[0]), xb)
     torch.cuda.synchronize()
-    assert rel(host(p.U), out["U"]) < 5e-6
+    assert rel(host(p.U), out["U"]) < (5e-6 if prec == 1 else 5e-5)
 
 
 @pytest.mark.parametrize("case", ALL)
