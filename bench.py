@@ -527,7 +527,7 @@ def bench_c2(args, torch):
     """4x4x4 mesh, m=52, nocc=4, nchol=400, 32 walkers (L: 70.9 GB complex128, streamed to
     the GPU block by block as it is drawn).  The local energy of the initial walkers with
     every contraction precision on the same Gh, each with its error against FP64, and 10
-    FP64 propagation steps (no QR: the re-orthonormalisation takes nk*nocc <= 128)."""
+    FP64 propagation steps, the walkers re-orthonormalised after the last."""
     import numpy as np
     import paper_2003_09468_amd as lib
     from synth.kpt_inputs import config_shapes, make_system, make_walkers, make_fields
@@ -568,7 +568,7 @@ def bench_c2(args, torch):
     lib.timing_enable(True, 1 << 16)
     t0 = time.perf_counter()
     for st in range(cfg["nsteps"]):
-        p64.step(xs[st], bufs=bufs)
+        p64.step(xs[st], ortho=(st == cfg["nsteps"] - 1), bufs=bufs)
     torch.cuda.synchronize()
     dt_steps = time.perf_counter() - t0
     lib.timing_enable(False)

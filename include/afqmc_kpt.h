@@ -210,7 +210,7 @@ afqmc_status afqmc_kpt_propagate(const afqmc_kpt_problem* p, int nprob, const vo
 /* Walker re-orthonormalisation (once per block, "Scaling and Performance"):
  * U <- Q of the thin QR factorisation U = Q R with diag(R) real positive
  * (FP64 Cholesky-QR applied twice), then Gh and logdet are recomputed.
- * Gh and the local energy are unchanged by it.  Requires nk*nocc <= 128
+ * Gh and the local energy are unchanged by it.  Requires nk*nocc <= 256
  * (AFQMC_EUNSUPPORTED otherwise, also for AFQMC_PROPAGATE_ORTHO elsewhere). */
 afqmc_status afqmc_kpt_orthonormalize(const afqmc_kpt_problem* p, int nprob,
                                       void* ws, size_t ws_bytes, void* stream);

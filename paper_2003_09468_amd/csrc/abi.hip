@@ -145,10 +145,10 @@ afqmc_status check_problems(const afqmc_kpt_problem* p, int nprob, unsigned need
   return AFQMC_OK;
 }
 
-// The re-orthonormalisation's Cholesky factorisation holds nk*nocc <= 128 in registers.
+// The re-orthonormalisation handles nk*nocc <= 256 (registers up to 128, L2 above).
 afqmc_status check_ortho(const afqmc_kpt_problem* p, int nprob) {
   for (int i = 0; i < nprob; ++i)
-    if ((int64_t)p[i].nk * p[i].nocc > 128) return AFQMC_EUNSUPPORTED;
+    if ((int64_t)p[i].nk * p[i].nocc > 256) return AFQMC_EUNSUPPORTED;
   return AFQMC_OK;
 }
 

@@ -886,6 +886,124 @@ struct OpOverlap {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Cholesky factor and its inverse for 128 < n <= 256 (re-orthonormalisation of large
+// walkers), one 256-thread workgroup per walker, in global memory (L2 resident).
+// Column j of the factor S = L L^H (left-looking): row j of L (final for k < j) is staged
+// in LDS, and thread r >= j forms t_r = S[r][j] - sum_{k<j} L[r][k] conj(L[j][k]);
+// L[j][j] = sqrt(t_j), L[r][j] = t_r / L[j][j].  Then thread c solves L x = e_c by forward
+// substitution (x = column c of L^{-1}) and writes out[c][i] = conj(x_i), the row c of
+// R^{-1} = (L^{-1})^H.  A non-positive or non-finite pivot marks the walker and leaves
+// R^{-1} = identity.
+struct CholArgs {
+  int n;
+  cpx<double>* S;    // [W][n][n], lower triangle overwritten by L
+  cpx<double>* out;  // [W][n][n] R^{-1}
+  int* status;       // [W]
+};
+
+__global__ __launch_bounds__(256) void chol_inv_kernel(const Batch<CholArgs> B) {
+  long long wloc;
+  const int pb = batch_find(B, blockIdx.x, wloc);
+  const int n = B.a[pb].n;
+  const int w = (int)wloc;
+  cpx<double>* __restrict__ L = B.a[pb].S + (int64_t)w * n * n;
+  cpx<double>* __restrict__ out = B.a[pb].out + (int64_t)w * n * n;
+  const int r = threadIdx.x;
+  __shared__ double rjr[256], rji[256];
+  __shared__ double diag[256];
+  __shared__ int flag_s;
+  if (r == 0) flag_s = 0;
+  int bad = 0;  // 1: non-positive pivot, 2: non-finite
+  for (int j = 0; j < n; ++j) {
+    if (r < j) {
+      const cpx<double> v = L[(int64_t)j * n + r];
+      rjr[r] = v.re;
+      rji[r] = v.im;
+    }
+    __syncthreads();
+    double tr = 0.0, ti = 0.0;
+    if (r >= j && r < n) {
+      const cpx<double>* __restrict__ Lr = L + (int64_t)r * n;
+      tr = Lr[j].re;
+      ti = Lr[j].im;
+#pragma unroll 4
+      for (int k = 0; k < j; ++k) {
+        const cpx<double> a = Lr[k];
+        // a conj(b), b = L[j][k]
+        tr -= a.re * rjr[k] + a.im * rji[k];
+        ti -= a.im * rjr[k] - a.re * rji[k];
+      }
+    }
+    if (r == j) {
+      double d = tr;
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad |= isfinite(d) ? 1 : 2;
+        d = 1.0;
+      }
+      diag[j] = sqrt(d);
+    }
+    __syncthreads();
+    if (r >= j && r < n) {
+      const double sd = diag[j];
+      L[(int64_t)r * n + j] = (r == j) ? cpx<double>{sd, 0.0} : cpx<double>{tr / sd, ti / sd};
+    }
+    __syncthreads();
+  }
+  if (bad) atomicOr(&flag_s, bad);
+  __syncthreads();
+  const int fl = flag_s;
+  if (r < n) {
+    cpx<double>* __restrict__ Or = out + (int64_t)r * n;
+    for (int i = 0; i < r; ++i) Or[i] = cpx<double>{0.0, 0.0};
+    if (fl) {
+      for (int i = r; i < n; ++i) Or[i] = cpx<double>{i == r ? 1.0 : 0.0, 0.0};
+    } else {
+      Or[r] = cpx<double>{1.0 / diag[r], 0.0};
+      for (int i = r + 1; i < n; ++i) {
+        const cpx<double>* __restrict__ Li = L + (int64_t)i * n;
+        double sr = 0.0, si = 0.0;
+#pragma unroll 4
+        for (int k = r; k < i; ++k) {
+          // L[i][k] x_k with x_k = conj(Or[k])
+          const cpx<double> a = Li[k], x = Or[k];
+          sr += a.re * x.re + a.im * x.im;
+          si += a.im * x.re - a.re * x.im;
+        }
+        const double id = 1.0 / diag[i];
+        Or[i] = cpx<double>{-sr * id, si * id};  // conj(x_i), x_i = -s / L[i][i]
+      }
+    }
+  }
+  if (r == 0 && fl) {
+    int bits = 0;
+    if (fl & 1) bits |= AFQMC_WALKER_SINGULAR;
+    if (fl & 2) bits |= AFQMC_WALKER_NONFINITE;
+    B.a[pb].status[w] |= bits;
+  }
+}
+
+static hipError_t launch_chol_inv(const Job* jobs, const int* ids, int c, void* const* S,
+                                  void* const* out, hipStream_t s) {
+  Batch<CholArgs> B;
+  B.nprob = c;
+  long long cnt[AFQMC_MAXP];
+  for (int q = 0; q < c; ++q) {
+    const afqmc_kpt_problem& p = jobs[ids[q]].p;
+    B.a[q].n = p.nk * p.nocc;
+    if (B.a[q].n > 256) return hipErrorInvalidValue;
+    B.a[q].S = (cpx<double>*)S[ids[q]];
+    B.a[q].out = (cpx<double>*)out[ids[q]];
+    B.a[q].status = p.status;
+    cnt[q] = p.nwalk;
+  }
+  const long long g = batch_close(B, cnt);
+  if (g < 0) return hipErrorInvalidValue;
+  if (g == 0) return hipSuccess;
+  hipLaunchKernelGGL(chol_inv_kernel, dim3((unsigned)g), dim3(256), 0, s, B);
+  return hipGetLastError();
+}
+
 // Size class of the register-resident elimination for n (0..3), -1 if too large.
 static int gj_class(int n) {
   if (n <= 32) return 0;
@@ -915,6 +1033,8 @@ hipError_t launch_small_gj(const Job* jobs, int n, int mode, void* const* S_in,
         const long long g = batch_close(B, cnt);
         if (g < 0) return hipErrorInvalidValue;
         if (g == 0) return hipSuccess;
+        if (gj_class(B.a[0].n) < 0 && mode == GJ_MODE_CHOL_INV)
+          return launch_chol_inv(jobs, ids, c, S_in, out, s);
         switch (gj_class(B.a[0].n)) {
           case 0:
             hipLaunchKernelGGL((small_gj_kernel<32, 1, 1>), dim3((unsigned)g), dim3(1024), 0, s, mode, B);

@@ -114,7 +114,6 @@ def test_unsupported_sizes(L):
     p = good_problem()
     p.mesh[0], p.mesh[1], p.mesh[2], p.nk, p.m, p.nocc = 4, 4, 4, 64, 52, 5  # nk*nocc > 256
     assert call(L, "afqmc_kpt_greens", p, ctypes.c_void_p(0x100000), 1 << 40, None) == -7
-    p.nocc = 4  # nk*nocc = 256: Green's function yes, re-orthonormalisation no
     assert call(L, "afqmc_kpt_orthonormalize", p, ctypes.c_void_p(0x100000), 1 << 40,
                 None) == -7
     assert call(L, "afqmc_kpt_propagate", p, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000),

@@ -18,7 +18,6 @@ if gpu_available():
     import torch
     from oracle import kpoint as kp
     from tests.gpu_cases import CASES, build, host, rel, phase_err, energy_err
-    from paper_2003_09468_amd import AfqmcError
 
 ALL = list(CASES) if gpu_available() else []
 
@@ -234,10 +233,10 @@ def test_determinism():
 
 
 # ---------------------------------------------------------------------------
-# occupied dimension above 128: only the blocked inverse covers it
+# occupied dimension above 128: the blocked inverse and the L2-resident Cholesky
 
 def test_large_occupied_dimension():
-    """nk*nocc = 160: Green's function, log overlap, energy and one step (no QR)."""
+    """nk*nocc = 160: Green's function, log overlap, energy, one step and the QR."""
     s, U, x, p, pre = build(((4, 4, 2), 6, 5, 10, 3, "random", "dense"))
     Gh, ld = kp.greens(U, s.A)
     assert rel(host(p.Gh), Gh) < 1e-11
@@ -249,17 +248,51 @@ def test_large_occupied_dimension():
     assert rel(host(p.U), out["U"]) < 1e-11
     assert rel(host(p.Gh), out["Gh"]) < 1e-10
     assert phase_err(host(p.logdet), out["logdet"]) < 1e-10
-    with pytest.raises(AfqmcError):
-        p.orthonormalize()
+    check_ortho(p, s, host(p.U))
+
+
+def check_ortho(p, s, Ub):
+    """Re-orthonormalise the GPU's walkers and compare with the oracle's QR of them; the
+    QR adds no status bits."""
+    st0 = host(p.status).copy()
+    p.orthonormalize()
+    torch.cuda.synchronize()
+    Q = kp.orthonormalize(Ub)
+    Gh, ld = kp.greens(Q, s.A)
+    assert rel(host(p.U), Q) < 1e-11
+    assert rel(host(p.Gh), Gh) < 1e-10
+    assert phase_err(host(p.logdet), ld) < 1e-10
+    assert np.array_equal(host(p.status), st0)
 
 
 def test_greens_at_maximum_occupied_dimension():
-    """nk*nocc = 256, the largest the inverse takes (16 panels)."""
+    """nk*nocc = 256, the largest the inverse and the Cholesky take."""
     s, U, x, p, pre = build(((4, 4, 4), 5, 4, 4, 2, "random", "dense"))
     Gh, ld = kp.greens(U, s.A)
     assert rel(host(p.Gh), Gh) < 1e-10
     assert phase_err(host(p.logdet), ld) < 1e-10
     assert int(host(p.status).max()) == 0
+    Ub = U * 2.0 + 0.3 * np.roll(U, 1, axis=2)
+    p.set_walkers(torch.from_numpy(Ub))
+    check_ortho(p, s, Ub)
+
+
+def test_large_ortho_rank_deficient_walker():
+    """nk*nocc = 160: a walker with a zero orbital has a singular overlap matrix S = U^H U;
+    it is flagged and left unchanged, the others are re-orthonormalised."""
+    s, U, x, p, pre = build(((4, 4, 2), 6, 5, 10, 3, "random", "dense"))
+    Ub = U.copy()
+    Ub[1][:, 7] = 0.0
+    p.set_walkers(torch.from_numpy(Ub))
+    p.orthonormalize()
+    torch.cuda.synchronize()
+    st = host(p.status)
+    assert st[1] & 1
+    assert st[0] == 0 and st[2] == 0
+    Uo = host(p.U)
+    assert np.array_equal(Uo[1], Ub[1])
+    Q = kp.orthonormalize(Ub[[0, 2]])
+    assert rel(Uo[[0, 2]], Q) < 1e-11
 
 
 def test_mixed_energy():
