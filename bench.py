@@ -295,8 +295,9 @@ def roofline(path_res, prec_key, cfg):
         return {"kernel": dom, "bound": "alu", "achieved": None, "peak": None, "unit": None,
                 "frac": None, "traffic": None}
     ach = fl / (kern[dom]["ms_per_launch"] * 1e-3) / 1e12
-    # in the BF16X3 mode only the HS potential and the exchange run on the BF16 split
-    pk = "fp32" if prec_key == "bf16x3" and dom not in ("vhs", "exchange") else prec_key
+    # in the BF16X3 mode the HS potential, the Taylor terms and the exchange run on the
+    # BF16 split, the rest in FP32
+    pk = "fp32" if prec_key == "bf16x3" and dom not in ("vhs", "taylor", "exchange") else prec_key
     return {"kernel": dom, "bound": "mfma", "achieved": round(ach, 3), "peak": PEAK[pk],
             "unit": "TFLOP/s", "frac": round(ach / PEAK[pk], 4),
             "traffic": measured_traffic(dom, prec_key), "flops_per_launch": fl}

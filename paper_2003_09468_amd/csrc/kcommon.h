@@ -80,6 +80,21 @@ __device__ __forceinline__ void bf16_split(float x, unsigned short& hi, unsigned
   lo = bf16_bits_rne(x - __uint_as_float((unsigned int)hi << 16));
 }
 
+// Split of two floats into packed (hi, lo) BF16 pairs, element 0 in the low half:
+// hi = bf16_rne(x), lo = bf16_rne(x - hi) (the difference is exact in FP32).  The
+// conversions compile to the packed round-to-nearest-even conversion of gfx950.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void bf16_split2(float x0, float x1, unsigned int& hi,
+                                            unsigned int& lo) {
+  const bf16x2_t h = {(__bf16)x0, (__bf16)x1};
+  hi = __builtin_bit_cast(unsigned int, h);
+  const float r0 = x0 - __uint_as_float(hi << 16);
+  const float r1 = x1 - __uint_as_float(hi & 0xffff0000u);
+  const bf16x2_t l = {(__bf16)r0, (__bf16)r1};
+  lo = __builtin_bit_cast(unsigned int, l);
+}
+
 // 16x16x32 BF16 MFMA on raw bf16 bits.  Lane l supplies A[l % 16][8 (l / 16) + i] and
 // B[8 (l / 16) + i][l % 16], i < 8; D as for the FP32 16x16x4 instruction.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));

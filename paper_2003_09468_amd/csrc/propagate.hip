@@ -7,7 +7,8 @@
 // writes T_j and adds it into an FP64 accumulator; the one-body half steps are batched over
 // (walker, k) blocks and always run in FP64.  With FP32 contractions the Taylor terms are
 // computed from complex64 vhs and T_{j-1} with FP32 MFMA accumulation, while the walker
-// accumulator stays complex128.
+// accumulator stays complex128.  In the BF16X3 mode the Taylor terms run on the three-pass
+// BF16 split of the same complex64 operands.
 #include <math.h>
 
 #include "cgemm.h"
@@ -140,6 +141,373 @@ static hipError_t taylor_tiles(const OpTaylor<T>* ops, int c, int cls, int choic
   }
 }
 
+// ---------------------------------------------------------------------------
+// Taylor terms on the three-pass BF16 split (BF16X3 mode).  The walker-side operand
+// T_{j-1} is kept as BF16 planes Tp[w][n][plane][k] (planes re hi, re lo, im hi, im lo;
+// k = row of T, contiguous, zero for M <= k < KP = 32 ceil(M / 32)), the layout the MFMA
+// B operand reads: T_0's planes come from a transposing split of the complex64 T_0, and
+// each term's epilogue writes the next planes directly.
+
+__host__ __device__ __forceinline__ int kpad32(int m) { return 32 * ((m + 31) / 32); }
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Tp[w][n][pl][k] from T[w][k][n] (complex64), 64 k x 64 n tiles transposed through LDS.
+struct TSplitArgs {
+  int W, M, N, KP, tk, tn;  // tk = ceil(KP / 64), tn = ceil(N / 64)
+  const cpx<float>* T;
+  unsigned short* Tp;
+};
+
+__global__ __launch_bounds__(256) void t_split_kernel(const Batch<TSplitArgs> B) {
+  __shared__ float2 tile[64][65];
+  long long loc;
+  const int pb = batch_find(B, blockIdx.x, loc);
+  const TSplitArgs& a = B.a[pb];
+  const int per_w = a.tk * a.tn;
+  const int w = (int)(loc / per_w), rem = (int)(loc % per_w);
+  const int k0 = (rem / a.tn) * 64, n0 = (rem % a.tn) * 64;
+  const int tid = threadIdx.x;
+  const cpx<float>* __restrict__ T = a.T + (int64_t)w * a.M * a.N;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int u = tid + 256 * e, kk = u >> 6, nn = u & 63;
+    const int k = k0 + kk, n = n0 + nn;
+    float2 v = {0.f, 0.f};
+    if (k < a.M && n < a.N) {
+      const cpx<float> t = T[(int64_t)k * a.N + n];
+      v = float2{t.re, t.im};
+    }
+    tile[kk][nn] = v;
+  }
+  __syncthreads();
+  unsigned short* __restrict__ Tp = a.Tp + (int64_t)w * a.N * 4 * a.KP;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int u = tid + 256 * e, nn = u >> 4, kq = 4 * (u & 15);
+    const int n = n0 + nn, k = k0 + kq;
+    if (n >= a.N || k >= a.KP) continue;
+    unsigned int h0[4], h1[4];
+    bf16_split2(tile[kq][nn].x, tile[kq + 1][nn].x, h0[0], h0[1]);
+    bf16_split2(tile[kq][nn].y, tile[kq + 1][nn].y, h0[2], h0[3]);
+    bf16_split2(tile[kq + 2][nn].x, tile[kq + 3][nn].x, h1[0], h1[1]);
+    bf16_split2(tile[kq + 2][nn].y, tile[kq + 3][nn].y, h1[2], h1[3]);
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl)
+      *reinterpret_cast<uint2*>(Tp + ((int64_t)n * 4 + pl) * a.KP + k) = uint2{h0[pl], h1[pl]};
+  }
+}
+
+static hipError_t launch_t_split(const Job* jobs, const int* ids, int c, void* const* T,
+                                 void* const* Tp, hipStream_t s) {
+  Batch<TSplitArgs> Bs;
+  Bs.nprob = c;
+  long long cnt[AFQMC_MAXP];
+  for (int q = 0; q < c; ++q) {
+    const afqmc_kpt_problem& p = jobs[ids[q]].p;
+    TSplitArgs& t = Bs.a[q];
+    t.W = p.nwalk; t.M = p.nk * p.m; t.N = p.nk * p.nocc; t.KP = kpad32(t.M);
+    t.tk = (t.KP + 63) / 64; t.tn = (t.N + 63) / 64;
+    t.T = (const cpx<float>*)T[ids[q]];
+    t.Tp = (unsigned short*)Tp[ids[q]];
+    cnt[q] = (long long)t.W * t.tk * t.tn;
+  }
+  const long long g = batch_close(Bs, cnt);
+  if (g < 0) return hipErrorInvalidValue;
+  if (g == 0) return hipSuccess;
+  hipLaunchKernelGGL(t_split_kernel, dim3((unsigned)g), dim3(256), 0, s, Bs);
+  return hipGetLastError();
+}
+
+// One term, T_j = alpha vhs T_{j-1}, acc += T_j, one 512-thread workgroup per (walker,
+// 64-row tile, column tile of 16 NB columns).  Waves 4-7 produce: they stream the
+// complex64 rows of vhs (from HBM) with DEPTH chunks of K in flight in registers and split
+// them into BF16 planes, and copy the chunk's T_{j-1} planes (from L2), into two LDS
+// stages.  Waves 0-3 consume, in 2 x 2: wave (wm, wn) owns rows 32 wm .. 32 wm + 31 and
+// the first ceil(NB / 2) (wn = 0) or the remaining (wn = 1) 16-column blocks, with 12 BF16
+// MFMAs per complex 16 x 16 x 32 block and FP32 accumulation.  One block barrier per K
+// chunk.  In the epilogue the consumers leave alpha T in LDS (over the stages) and all
+// eight waves add it into the FP64 accumulator (every load issued before the first
+// store) and write the planes of T_j.  Workgroups of one walker are placed on one XCD,
+// where its planes stay in L2.
+// Producer loads are unconditional (clamped addresses, zeros selected afterwards) so that
+// each wait covers exactly the oldest chunk.
+struct TaylorBfArgs {
+  int W, M, N, KP, tiles_m, tiles_n;  // M = K = nk*m, N = nk*nocc
+  float alpha;
+  const cpx<float>* V;        // [W][M][M]
+  const unsigned short* Tin;  // [W][N][4][KP] planes of T_{j-1}
+  unsigned short* Tout;       // [W][N][4][KP] planes of T_j, null for the last term
+  cpx<double>* acc;           // [W][M][N]
+};
+
+template <int NB, bool VEC>
+__global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBfArgs> B) {
+  constexpr int BM = 64, BN = 16 * NB, BKC = 32, RS = BKC + 8;
+  constexpr int DEPTH = NB >= 6 ? 2 : 3;  // chunks in flight (register budget)
+  constexpr int CB = (NB + 1) / 2;
+  constexpr int SA_BYTES = 2 * 4 * BM * RS * 2, SB_BYTES = 2 * 4 * BN * RS * 2;
+  constexpr int RST = BN + 1;  // row stride of the result tile (float2)
+  constexpr int RES_BYTES = BM * RST * 8;
+  constexpr int LDS_BYTES =
+      SA_BYTES + SB_BYTES > RES_BYTES ? SA_BYTES + SB_BYTES : RES_BYTES;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LDS_BYTES];
+  auto sA = reinterpret_cast<unsigned short (*)[4][BM][RS]>(lds);
+  auto sB = reinterpret_cast<unsigned short (*)[4][BN][RS]>(lds + SA_BYTES);
+  auto res = reinterpret_cast<float2 (*)[RST]>(lds);  // after the K loop
+  long long loc;
+  const int pb = batch_find(B, blockIdx.x, loc);
+  const TaylorBfArgs& a = B.a[pb];
+  const long long per_w = (long long)a.tiles_m * a.tiles_n;
+  const long long total = per_w * a.W;
+  const long long lt = xcd_remap(loc, (total + 7) & ~7LL);
+  if (lt >= total) return;
+  const int w = (int)(lt / per_w);
+  const int rem = (int)(lt % per_w);
+  const int row0 = (rem / a.tiles_n) * BM, col0 = (rem % a.tiles_n) * BN;
+  const int M = a.M, N = a.N, K = a.M, KP = a.KP;
+  const int nch = KP / BKC;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+
+  if (wave >= 4) {
+    // ---------------- producers
+    const int pt = threadIdx.x - 256;
+    const cpx<float>* __restrict__ V = a.V + (int64_t)w * M * K;
+    const unsigned short* __restrict__ Tp = a.Tin + (int64_t)w * N * 4 * KP;
+    float4 ra[DEPTH][4];  // A unit e: row pt / 16 + 16 e, k pair pt % 16
+    u32x4 rb[DEPTH][NB];  // B unit e: u = pt + 256 e: column u / 16, plane (u / 4) % 4,
+                          // 8 k at 8 (u % 4)
+    auto issue = [&](int q, float4 (&xa)[4], u32x4 (&xb)[NB]) {
+      const int k0 = (q < nch ? q : nch - 1) * BKC;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = min(row0 + (pt >> 4) + 16 * e, M - 1);
+        const int k = k0 + 2 * (pt & 15);
+        if constexpr (VEC) {
+          xa[e] = *reinterpret_cast<const float4*>(V + (int64_t)row * K + min(k, K - 2));
+        } else {
+          const cpx<float> v0 = V[(int64_t)row * K + min(k, K - 1)];
+          const cpx<float> v1 = V[(int64_t)row * K + min(k + 1, K - 1)];
+          xa[e] = float4{v0.re, v0.im, v1.re, v1.im};
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < NB; ++e) {
+        const int u = pt + 256 * e;
+        const int col = min(col0 + (u >> 4), N - 1);
+        xb[e] = *reinterpret_cast<const u32x4*>(
+            Tp + ((int64_t)col * 4 + ((u >> 2) & 3)) * KP + k0 + 8 * (u & 3));
+      }
+    };
+    auto stash = [&](int q, int st, const float4 (&xa)[4], const u32x4 (&xb)[NB]) {
+      const int k0 = q * BKC;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = (pt >> 4) + 16 * e, kk = 2 * (pt & 15);
+        const bool rok = row0 + r < M;
+        const float4 v = xa[e];
+        const bool ok0 = rok && k0 + kk < K, ok1 = rok && k0 + kk + 1 < K;
+        unsigned int h[4];
+        bf16_split2(ok0 ? v.x : 0.f, ok1 ? v.z : 0.f, h[0], h[1]);
+        bf16_split2(ok0 ? v.y : 0.f, ok1 ? v.w : 0.f, h[2], h[3]);
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl)
+          *reinterpret_cast<unsigned int*>(&sA[st][pl][r][kk]) = h[pl];
+      }
+#pragma unroll
+      for (int e = 0; e < NB; ++e) {
+        const int u = pt + 256 * e;
+        *reinterpret_cast<u32x4*>(&sB[st][(u >> 2) & 3][u >> 4][8 * (u & 3)]) = xb[e];
+      }
+    };
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) issue(d, ra[d], rb[d]);
+    stash(0, 0, ra[0], rb[0]);
+    issue(DEPTH, ra[0], rb[0]);
+    __syncthreads();
+    // iteration c: the consumers work on chunk c; chunk c + 1 (slot (c + 1) % DEPTH) goes
+    // to stage (c + 1) & 1 and chunk c + 1 + DEPTH is requested into the freed slot.  The
+    // body has no branches (past the last chunk it stores into the stage nobody reads), so
+    // the compiler's wait before each store covers only the oldest chunk.
+    for (int c0 = 0; c0 < nch; c0 += DEPTH) {
+#pragma unroll
+      for (int d = 0; d < DEPTH; ++d) {
+        const int c = c0 + d;
+        const int sl = (d + 1) % DEPTH;
+        stash(c + 1, (c + 1) & 1, ra[sl], rb[sl]);
+        issue(c + 1 + DEPTH, ra[sl], rb[sl]);
+        __syncthreads();
+      }
+    }
+  } else {
+    // ---------------- consumers
+    const int wm = wave >> 1, wn = wave & 1;
+    v4f acr[2][CB], aci[2][CB];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        acr[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+        aci[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+      }
+    const int cb0 = wn ? CB : 0, ncb = wn ? NB - CB : CB;
+    const u16x8 sgn = {0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000};
+    __syncthreads();
+    // as many barriers as the producers: ceil(nch / DEPTH) DEPTH iterations
+    for (int c0 = 0; c0 < nch; c0 += DEPTH) {
+#pragma unroll
+      for (int d = 0; d < DEPTH; ++d) {
+        const int c = c0 + d;
+        if (c < nch) {
+          const int st = c & 1;
+          const int kq = 8 * (lane >> 4);
+          u16x8 fa[2][4];
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl)
+              fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][pl][wm * 32 + i * 16 + (lane & 15)][kq]);
+#pragma unroll
+          for (int j = 0; j < CB; ++j) {
+            if (j < ncb) {
+              u16x8 fb[4];
+#pragma unroll
+              for (int pl = 0; pl < 4; ++pl)
+                fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][16 * (cb0 + j) + (lane & 15)][kq]);
+#pragma unroll
+              for (int i = 0; i < 2; ++i) {
+                // re += Vr Tr - Vi Ti,  im += Vr Ti + Vi Tr
+                acr[i][j] = mul3(fa[i][0], fa[i][1], fb[0], fb[1], acr[i][j]);
+                acr[i][j] = mul3(fa[i][2] ^ sgn, fa[i][3] ^ sgn, fb[2], fb[3], acr[i][j]);
+                aci[i][j] = mul3(fa[i][0], fa[i][1], fb[2], fb[3], aci[i][j]);
+                aci[i][j] = mul3(fa[i][2], fa[i][3], fb[0], fb[1], aci[i][j]);
+              }
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // the stages are free: alpha T to the result tile (lane: rows 4 (lane / 16) + v of
+    // column lane % 16 of each 16 x 16 block)
+    const float alpha = a.alpha;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        if (j >= ncb) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          res[wm * 32 + i * 16 + 4 * (lane >> 4) + v][16 * (cb0 + j) + (lane & 15)] =
+              float2{alpha * acr[i][j][v], alpha * aci[i][j][v]};
+      }
+  }
+  __syncthreads();
+
+  // ---------------- epilogue, all eight waves
+  const int tid = threadIdx.x;
+  // acc += T (FP64), in two halves: every load of a half first, then its stores
+  constexpr int NE = BM * BN / 1024;
+  cpx<double>* __restrict__ acc = a.acc + (int64_t)w * M * N;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    cpx<double> av[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int u = tid + 512 * (2 * e + h), row = row0 + u / BN, col = col0 + u % BN;
+      const bool ok = row < M && col < N;
+      av[e] = acc[ok ? (int64_t)row * N + col : 0];
+    }
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int u = tid + 512 * (2 * e + h), row = row0 + u / BN, col = col0 + u % BN;
+      if (row < M && col < N) {
+        const float2 t = res[u / BN][u % BN];
+        acc[(int64_t)row * N + col] =
+            cpx<double>{av[e].re + (double)t.x, av[e].im + (double)t.y};
+      }
+    }
+  }
+  // planes of T_j for the next term: four consecutive rows of one column per unit (rows
+  // M <= k < KP hold zeros: the A rows past M were staged as zeros)
+  if (a.Tout) {
+    unsigned short* __restrict__ To = a.Tout + (int64_t)w * N * 4 * KP;
+    constexpr int NQ = (16 * BN + 511) / 512;
+#pragma unroll
+    for (int e = 0; e < NQ; ++e) {
+      const int u = tid + 512 * e;
+      const int cl = u >> 4, rq = 4 * (u & 15);
+      const int col = col0 + cl, rb = row0 + rq;
+      if (u >= 16 * BN || col >= N || rb >= KP) continue;
+      const float2 t0 = res[rq][cl], t1 = res[rq + 1][cl], t2 = res[rq + 2][cl],
+                   t3 = res[rq + 3][cl];
+      unsigned int h0[4], h1[4];
+      bf16_split2(t0.x, t1.x, h0[0], h0[1]);
+      bf16_split2(t0.y, t1.y, h0[2], h0[3]);
+      bf16_split2(t2.x, t3.x, h1[0], h1[1]);
+      bf16_split2(t2.y, t3.y, h1[2], h1[3]);
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl)
+        *reinterpret_cast<uint2*>(To + ((int64_t)col * 4 + pl) * KP + rb) = uint2{h0[pl], h1[pl]};
+    }
+  }
+}
+
+static hipError_t launch_taylor_bf16x3(const Job* jobs, const int* ids, int c,
+                                       const void* const* tin, void* const* tout,
+                                       void* const* acc, double alpha_scale, hipStream_t s) {
+  Batch<TaylorBfArgs> Bt;
+  Bt.nprob = c;
+  long long cnt[AFQMC_MAXP];
+  int nb = 0;
+  bool vec = true;
+  for (int q = 0; q < c; ++q) {
+    const Job& j = jobs[ids[q]];
+    TaylorBfArgs& t = Bt.a[q];
+    t.W = j.p.nwalk;
+    t.M = j.p.nk * j.p.m;
+    t.N = j.p.nk * j.p.nocc;
+    t.KP = kpad32(t.M);
+    const int nbq = (t.N + 15) / 16 < 8 ? (t.N + 15) / 16 : 8;
+    if (q == 0) nb = nbq;
+    if (nbq != nb) return hipErrorInvalidValue;  // one column-tile width per group
+    t.tiles_m = (t.M + 63) / 64;
+    t.tiles_n = (t.N + 16 * nb - 1) / (16 * nb);
+    vec = vec && (t.M % 2 == 0) && (((uintptr_t)j.vhs & 15) == 0);
+    t.alpha = (float)(-sqrt(j.p.dt) * alpha_scale);
+    t.V = (const cpx<float>*)j.vhs;
+    t.Tin = (const unsigned short*)tin[ids[q]];
+    t.Tout = tout ? (unsigned short*)tout[ids[q]] : nullptr;
+    t.acc = (cpx<double>*)acc[ids[q]];
+    cnt[q] = ((long long)t.W * t.tiles_m * t.tiles_n + 7) & ~7LL;
+  }
+  const long long g = batch_close(Bt, cnt);
+  if (g < 0) return hipErrorInvalidValue;
+  if (g == 0) return hipSuccess;
+  const dim3 grid((unsigned)g), block(512);
+#define AFQMC_TBF(NBV)                                                                  \
+  case NBV:                                                                             \
+    if (vec) hipLaunchKernelGGL((taylor_bf16x3_kernel<NBV, true>), grid, block, 0, s, Bt); \
+    else hipLaunchKernelGGL((taylor_bf16x3_kernel<NBV, false>), grid, block, 0, s, Bt);    \
+    break;
+  switch (nb) {
+    AFQMC_TBF(1)
+    AFQMC_TBF(2)
+    AFQMC_TBF(3)
+    AFQMC_TBF(4)
+    AFQMC_TBF(5)
+    AFQMC_TBF(6)
+    AFQMC_TBF(7)
+    default:
+      if (vec) hipLaunchKernelGGL((taylor_bf16x3_kernel<8, true>), grid, block, 0, s, Bt);
+      else hipLaunchKernelGGL((taylor_bf16x3_kernel<8, false>), grid, block, 0, s, Bt);
+      break;
+  }
+#undef AFQMC_TBF
+  return hipGetLastError();
+}
+
 // One Taylor term, T_j = alpha vhs T_{j-1}, acc += T_j, for a group of jobs of one
 // precision and tile class; alpha = -sqrt(dt) * alpha_scale per job.
 hipError_t launch_taylor_group(const Job* jobs, const int* ids, int c, int choice,
@@ -147,6 +515,8 @@ hipError_t launch_taylor_group(const Job* jobs, const int* ids, int c, int choic
                                double alpha_scale, hipStream_t s) {
   TimedScope ts(KC_TAYLOR, s);
   const int cls = taylor_class(jobs[ids[0]].p);
+  if (jobs[ids[0]].p.prec == AFQMC_PREC_BF16X3)
+    return launch_taylor_bf16x3(jobs, ids, c, tin, tout, acc, alpha_scale, s);
   if (low_prec(jobs[ids[0]].p.prec)) {
     OpTaylor<float> ops[AFQMC_MAXP];
     for (int q = 0; q < c; ++q) {
@@ -182,11 +552,14 @@ hipError_t launch_taylor_group(const Job* jobs, const int* ids, int c, int choic
 static size_t carve_propagate(Carve& c, const afqmc_kpt_problem& p, void** acc, void** t0,
                               void** t1, GreensWs& g) {
   Dims d = dims_of(p);
-  const size_t tsz = low_prec(p.prec) ? 8 : 16;
+  // Taylor operands: complex128 or complex64 [W][N][n]; in the BF16X3 mode they hold
+  // BF16 planes [W][n][4][KP] (t1 first receives the complex64 T_0)
+  size_t tbytes = (low_prec(p.prec) ? 8 : 16) * (size_t)d.W * d.N() * d.n();
+  if (p.prec == AFQMC_PREC_BF16X3) tbytes = 8 * (size_t)d.W * d.n() * kpad32(d.N());
   carve_greens(c, d, g);
   *acc = c.take(16 * (size_t)d.W * d.N() * d.n());
-  *t0 = c.take(tsz * (size_t)d.W * d.N() * d.n());
-  *t1 = c.take(tsz * (size_t)d.W * d.N() * d.n());
+  *t0 = c.take(tbytes);
+  *t1 = c.take(tbytes);
   return c.off;
 }
 
@@ -216,9 +589,16 @@ static hipError_t propagate_jobs(const Job* J, int c, hipStream_t s) {
       c, [&](int i) { return taylor_key(J[i].p); },
       [&](const int* ids, int g) -> hipError_t {
         const bool f32 = low_prec(J[ids[0]].p.prec);
-        // T_0 = bhalf U (FP64), acc = T_0, t0 = T_0 in the Taylor precision
-        hipError_t e = f32 ? launch_bhalf<float>(J, ids, g, U, acc, t0, s)
-                           : launch_bhalf<double>(J, ids, g, U, acc, t0, s);
+        // T_0 = bhalf U (FP64), acc = T_0, t0 = T_0 in the Taylor precision (BF16X3: t1 =
+        // T_0 as complex64, then t0 = its BF16 planes)
+        hipError_t e;
+        if (J[ids[0]].p.prec == AFQMC_PREC_BF16X3) {
+          e = launch_bhalf<float>(J, ids, g, U, acc, t1, s);
+          if (e == hipSuccess) e = launch_t_split(J, ids, g, t1, t0, s);
+        } else {
+          e = f32 ? launch_bhalf<float>(J, ids, g, U, acc, t0, s)
+                  : launch_bhalf<double>(J, ids, g, U, acc, t0, s);
+        }
         if (e != hipSuccess) return e;
         const int choice = tune_lookup(tune_key(TS_TAYLOR, J, ids, g));
         void** tin = t0;

@@ -42,7 +42,7 @@ void tune_store(const std::string& key, int choice) {
 
 int tune_ncand(int stage, int prec) {
   switch (stage) {
-    case TS_TAYLOR: return low_prec(prec) ? 3 : 6;
+    case TS_TAYLOR: return prec == AFQMC_PREC_BF16X3 ? 1 : low_prec(prec) ? 3 : 6;
     case TS_VHS: return 3;
     case TS_VBIAS: return 3;
     default: return 1;
@@ -52,6 +52,10 @@ int tune_ncand(int stage, int prec) {
 hipError_t tune_group(int stage, const Job* jobs, const int* ids, int c,
                       const std::function<hipError_t(int)>& run, hipStream_t s) {
   const int nc = tune_ncand(stage, jobs[ids[0]].p.prec);
+  if (nc <= 1) {  // a single variant: nothing to time
+    tune_store(tune_key(stage, jobs, ids, c), 0);
+    return hipSuccess;
+  }
   hipEvent_t a, b;
   hipError_t e = hipEventCreate(&a);
   if (e != hipSuccess) return e;

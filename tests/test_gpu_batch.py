@@ -1,6 +1,7 @@
 """Batches of uneven systems in one call, the captured step block and the autotuner.
 
-A batch mixes meshes, band counts, Cholesky ranks, walker counts and one FP32 system.
+A batch mixes meshes, band counts, Cholesky ranks, walker counts, one FP32 and one BF16X3
+system.
 Every system's result must equal what the same system gives when run alone through the
 single-problem entry points (same kernels, same reduction order: agreement to rounding
 noise), and the FP64 systems must match the oracle to the FP64 bar.  The captured block
@@ -18,11 +19,11 @@ pytestmark = pytest.mark.gpu
 if gpu_available():
     import torch
     from oracle import kpoint as kp
-    from paper_2003_09468_amd import KptBatch, PREC_FP32
+    from paper_2003_09468_amd import KptBatch
     from tests.gpu_cases import build, host, rel, phase_err, energy_err
 
-# (case, precision): uneven sizes; one FP32 system shares the batch
-BATCH = [("aniso", 0), ("line3", 0), ("wide", 0), ("mixed", 1), ("c0", 0)]
+# (case, precision): uneven sizes; one FP32 and one BF16X3 system share the batch
+BATCH = [("aniso", 0), ("line3", 0), ("wide", 0), ("mixed", 1), ("c0", 0), ("mol", 2)]
 NSTEPS = 2  # the fields drawn by build() cover two steps
 
 
@@ -73,7 +74,7 @@ def test_batch_fp64_systems_match_oracle():
     items = make()
     _, _, got = run_batch(items)
     for (case, prec), (s, U, x, p, pre), g in zip(BATCH, items, got):
-        if prec == PREC_FP32:
+        if prec != 0:
             continue
         Gh, ld = kp.greens(U, s.A)
         w = np.ones(U.shape[0])

@@ -62,3 +62,17 @@ def test_energy_and_adjoint(case, prec):
         assert np.abs(Eg[:, 2] - E[:, 2]).max() / np.abs(E[:, 2]).max() < 1e-4
     D = kp.energy_gradient(pre["Lh"], pre["h1h"], Gh, s.mesh)
     assert rel(host(p.energy_backward()), D) < 2e-5
+
+
+@pytest.mark.parametrize("shape", [((3, 3, 1), 14, 12, 12, 5, "random", "dense"),
+                                   ((4, 4, 2), 6, 5, 10, 3, "random", "dense")],
+                         ids=["n108", "n160"])
+def test_bf16x3_step_wide_column_tiles(shape):
+    """BF16X3 Taylor terms with 108 walker columns (seven 16-column blocks, the 3x3x3
+    workload's width) and with 160 (two column tiles); one step against the oracle."""
+    s, U, x, p, pre = build(shape, prec=2)
+    Gh, ld = kp.greens(U, s.A)
+    out = kp.step(U, ld, np.ones(U.shape[0]), x[0], pre, s.A, s.L, s.mesh, s.dt)
+    p.step(torch.from_numpy(x[0]))
+    torch.cuda.synchronize()
+    assert rel(host(p.U), out["U"]) < 5e-5
