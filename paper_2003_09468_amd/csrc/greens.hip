@@ -1033,7 +1033,7 @@ hipError_t launch_small_gj(const Job* jobs, int n, int mode, void* const* S_in,
         const long long g = batch_close(B, cnt);
         if (g < 0) return hipErrorInvalidValue;
         if (g == 0) return hipSuccess;
-        if (gj_class(B.a[0].n) < 0 && mode == GJ_MODE_CHOL_INV)
+        if (mode == GJ_MODE_CHOL_INV)
           return launch_chol_inv(jobs, ids, c, S_in, out, s);
         switch (gj_class(B.a[0].n)) {
           case 0:

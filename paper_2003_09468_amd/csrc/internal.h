@@ -141,6 +141,6 @@ hipError_t launch_vbias_group(const Job* jobs, const int* ids, int c, int choice
                               void* const* parts, hipStream_t s);
 
 // Workspace slots of the propagation used by the autotuner.
-void propagate_slots(const Job& j, void** acc, void** t0, void** t1);
+void propagate_slots(const Job& j, void** acc, void** t0, void** t1, void** tc);
 
 }  // namespace afqmc

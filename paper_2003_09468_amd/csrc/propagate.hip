@@ -142,11 +142,15 @@ static hipError_t taylor_tiles(const OpTaylor<T>* ops, int c, int cls, int choic
 }
 
 // ---------------------------------------------------------------------------
-// Taylor terms on the three-pass BF16 split (BF16X3 mode).  The walker-side operand
-// T_{j-1} is kept as BF16 planes Tp[w][n][plane][k] (planes re hi, re lo, im hi, im lo;
-// k = row of T, contiguous, zero for M <= k < KP = 32 ceil(M / 32)), the layout the MFMA
-// B operand reads: T_0's planes come from a transposing split of the complex64 T_0, and
-// each term's epilogue writes the next planes directly.
+// The Taylor polynomial on the three-pass BF16 split (BF16X3 mode), in nested (Horner)
+// form: with X = -sqrt(dt) vhs,
+//   R_6 = T_0,  R_{j-1} = T_0 + (X / j) R_j  (j = 6 .. 1),  T6(X) T_0 = R_0,
+// the same polynomial as the sum of the terms X^j T_0 / j!.  Each step is one batched
+// product whose epilogue forms R_{j-1} directly: the intermediate R are only ever read as
+// BF16 operands, so they are formed in FP32 from the complex64 T_0 and stored as planes;
+// the last step adds X R_1 to the FP64 T_0.  The walker-side operand is kept as BF16
+// planes Rp[w][n][plane][k] (planes re hi, re lo, im hi, im lo; k = row of R, contiguous,
+// zero for M <= k < KP = 32 ceil(M / 32)), the layout the MFMA B operand reads.
 
 __host__ __device__ __forceinline__ int kpad32(int m) { return 32 * ((m + 31) / 32); }
 
@@ -219,26 +223,29 @@ static hipError_t launch_t_split(const Job* jobs, const int* ids, int c, void* c
   return hipGetLastError();
 }
 
-// One term, T_j = alpha vhs T_{j-1}, acc += T_j, one 512-thread workgroup per (walker,
+// One step, R_{j-1} = T_0 + alpha vhs R_j, one 512-thread workgroup per (walker,
 // 64-row tile, column tile of 16 NB columns).  Waves 4-7 produce: they stream the
 // complex64 rows of vhs (from HBM) with DEPTH chunks of K in flight in registers and split
-// them into BF16 planes, and copy the chunk's T_{j-1} planes (from L2), into two LDS
+// them into BF16 planes, and copy the chunk's R_j planes (from L2), into two LDS
 // stages.  Waves 0-3 consume, in 2 x 2: wave (wm, wn) owns rows 32 wm .. 32 wm + 31 and
 // the first ceil(NB / 2) (wn = 0) or the remaining (wn = 1) 16-column blocks, with 12 BF16
 // MFMAs per complex 16 x 16 x 32 block and FP32 accumulation.  One block barrier per K
-// chunk.  In the epilogue the consumers leave alpha T in LDS (over the stages) and all
-// eight waves add it into the FP64 accumulator (every load issued before the first
-// store) and write the planes of T_j.  Workgroups of one walker are placed on one XCD,
-// where its planes stay in L2.
+// chunk.  In the epilogue the consumers leave alpha (vhs R_j) in LDS (over the stages)
+// and all eight waves add T_0 to it: from complex64 into the planes of R_{j-1}, or, in
+// the last step, into the FP64 accumulator that holds T_0 (every load issued before the
+// first store).  Workgroups of one walker are placed on one XCD, where its planes stay in
+// L2.
 // Producer loads are unconditional (clamped addresses, zeros selected afterwards) so that
 // each wait covers exactly the oldest chunk.
 struct TaylorBfArgs {
   int W, M, N, KP, tiles_m, tiles_n;  // M = K = nk*m, N = nk*nocc
-  float alpha;
+  int last;                           // 1: R_0 into acc (FP64), else planes of R_{j-1}
+  float alpha;                        // -sqrt(dt) / j
   const cpx<float>* V;        // [W][M][M]
-  const unsigned short* Tin;  // [W][N][4][KP] planes of T_{j-1}
-  unsigned short* Tout;       // [W][N][4][KP] planes of T_j, null for the last term
-  cpx<double>* acc;           // [W][M][N]
+  const unsigned short* Tin;  // [W][N][4][KP] planes of R_j
+  unsigned short* Tout;       // [W][N][4][KP] planes of R_{j-1} (not last)
+  const cpx<float>* T0;       // [W][M][N] T_0 as complex64 (not last)
+  cpx<double>* acc;           // [W][M][N] T_0 in FP64; R_0 after the last step
 };
 
 template <int NB, bool VEC>
@@ -407,78 +414,106 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
 
   // ---------------- epilogue, all eight waves
   const int tid = threadIdx.x;
-  // acc += T (FP64), in two halves: every load of a half first, then its stores
   constexpr int NE = BM * BN / 1024;
-  cpx<double>* __restrict__ acc = a.acc + (int64_t)w * M * N;
+  if (a.last) {
+    // acc = T_0 + X R_1 (FP64), in two halves: every load of a half first, then its stores
+    cpx<double>* __restrict__ acc = a.acc + (int64_t)w * M * N;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    cpx<double> av[NE];
+    for (int h = 0; h < 2; ++h) {
+      cpx<double> av[NE];
 #pragma unroll
-    for (int e = 0; e < NE; ++e) {
-      const int u = tid + 512 * (2 * e + h), row = row0 + u / BN, col = col0 + u % BN;
-      const bool ok = row < M && col < N;
-      av[e] = acc[ok ? (int64_t)row * N + col : 0];
+      for (int e = 0; e < NE; ++e) {
+        const int u = tid + 512 * (2 * e + h), row = row0 + u / BN, col = col0 + u % BN;
+        const bool ok = row < M && col < N;
+        av[e] = acc[ok ? (int64_t)row * N + col : 0];
+      }
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int u = tid + 512 * (2 * e + h), row = row0 + u / BN, col = col0 + u % BN;
+        if (row < M && col < N) {
+          const float2 t = res[u / BN][u % BN];
+          acc[(int64_t)row * N + col] =
+              cpx<double>{av[e].re + (double)t.x, av[e].im + (double)t.y};
+        }
+      }
     }
+    return;
+  }
+  // R_{j-1} = T_0 + X R_j in the tile (rows past M stay zero), then its planes: four
+  // consecutive rows of one column per unit
+  {
+    const cpx<float>* __restrict__ T0 = a.T0 + (int64_t)w * M * N;
 #pragma unroll
-    for (int e = 0; e < NE; ++e) {
-      const int u = tid + 512 * (2 * e + h), row = row0 + u / BN, col = col0 + u % BN;
-      if (row < M && col < N) {
-        const float2 t = res[u / BN][u % BN];
-        acc[(int64_t)row * N + col] =
-            cpx<double>{av[e].re + (double)t.x, av[e].im + (double)t.y};
+    for (int h = 0; h < 2; ++h) {
+      float2 tv[NE];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int u = tid + 512 * (2 * e + h), row = row0 + u / BN, col = col0 + u % BN;
+        const bool ok = row < M && col < N;
+        const cpx<float> t = T0[ok ? (int64_t)row * N + col : 0];
+        tv[e] = ok ? float2{t.re, t.im} : float2{0.f, 0.f};
+      }
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int u = tid + 512 * (2 * e + h);
+        float2& r = res[u / BN][u % BN];
+        r = float2{r.x + tv[e].x, r.y + tv[e].y};
       }
     }
   }
-  // planes of T_j for the next term: four consecutive rows of one column per unit (rows
-  // M <= k < KP hold zeros: the A rows past M were staged as zeros)
-  if (a.Tout) {
-    unsigned short* __restrict__ To = a.Tout + (int64_t)w * N * 4 * KP;
-    constexpr int NQ = (16 * BN + 511) / 512;
+  __syncthreads();
+  unsigned short* __restrict__ To = a.Tout + (int64_t)w * N * 4 * KP;
+  constexpr int NQ = (16 * BN + 511) / 512;
 #pragma unroll
-    for (int e = 0; e < NQ; ++e) {
-      const int u = tid + 512 * e;
-      const int cl = u >> 4, rq = 4 * (u & 15);
-      const int col = col0 + cl, rb = row0 + rq;
-      if (u >= 16 * BN || col >= N || rb >= KP) continue;
-      const float2 t0 = res[rq][cl], t1 = res[rq + 1][cl], t2 = res[rq + 2][cl],
-                   t3 = res[rq + 3][cl];
-      unsigned int h0[4], h1[4];
-      bf16_split2(t0.x, t1.x, h0[0], h0[1]);
-      bf16_split2(t0.y, t1.y, h0[2], h0[3]);
-      bf16_split2(t2.x, t3.x, h1[0], h1[1]);
-      bf16_split2(t2.y, t3.y, h1[2], h1[3]);
+  for (int e = 0; e < NQ; ++e) {
+    const int u = tid + 512 * e;
+    const int cl = u >> 4, rq = 4 * (u & 15);
+    const int col = col0 + cl, rb = row0 + rq;
+    if (u >= 16 * BN || col >= N || rb >= KP) continue;
+    const float2 t0 = res[rq][cl], t1 = res[rq + 1][cl], t2 = res[rq + 2][cl],
+                 t3 = res[rq + 3][cl];
+    unsigned int h0[4], h1[4];
+    bf16_split2(t0.x, t1.x, h0[0], h0[1]);
+    bf16_split2(t0.y, t1.y, h0[2], h0[3]);
+    bf16_split2(t2.x, t3.x, h1[0], h1[1]);
+    bf16_split2(t2.y, t3.y, h1[2], h1[3]);
 #pragma unroll
-      for (int pl = 0; pl < 4; ++pl)
-        *reinterpret_cast<uint2*>(To + ((int64_t)col * 4 + pl) * KP + rb) = uint2{h0[pl], h1[pl]};
-    }
+    for (int pl = 0; pl < 4; ++pl)
+      *reinterpret_cast<uint2*>(To + ((int64_t)col * 4 + pl) * KP + rb) = uint2{h0[pl], h1[pl]};
   }
 }
 
-static hipError_t launch_taylor_bf16x3(const Job* jobs, const int* ids, int c,
+// One Horner step for a group of BF16X3 jobs: R_{j-1} = T_0 + (-sqrt(dt) / j) vhs R_j
+// (planes tin -> planes tout, T_0 from t0c), or with tout null the last step into acc.
+static hipError_t launch_taylor_bf16x3(const Job* jobs, const int* ids, int c, int j,
                                        const void* const* tin, void* const* tout,
-                                       void* const* acc, double alpha_scale, hipStream_t s) {
+                                       const void* const* t0c, void* const* acc,
+                                       hipStream_t s) {
+  TimedScope ts(KC_TAYLOR, s);
   Batch<TaylorBfArgs> Bt;
   Bt.nprob = c;
   long long cnt[AFQMC_MAXP];
   int nb = 0;
   bool vec = true;
   for (int q = 0; q < c; ++q) {
-    const Job& j = jobs[ids[q]];
+    const Job& jb = jobs[ids[q]];
     TaylorBfArgs& t = Bt.a[q];
-    t.W = j.p.nwalk;
-    t.M = j.p.nk * j.p.m;
-    t.N = j.p.nk * j.p.nocc;
+    t.W = jb.p.nwalk;
+    t.M = jb.p.nk * jb.p.m;
+    t.N = jb.p.nk * jb.p.nocc;
     t.KP = kpad32(t.M);
     const int nbq = (t.N + 15) / 16 < 8 ? (t.N + 15) / 16 : 8;
     if (q == 0) nb = nbq;
     if (nbq != nb) return hipErrorInvalidValue;  // one column-tile width per group
     t.tiles_m = (t.M + 63) / 64;
     t.tiles_n = (t.N + 16 * nb - 1) / (16 * nb);
-    vec = vec && (t.M % 2 == 0) && (((uintptr_t)j.vhs & 15) == 0);
-    t.alpha = (float)(-sqrt(j.p.dt) * alpha_scale);
-    t.V = (const cpx<float>*)j.vhs;
+    vec = vec && (t.M % 2 == 0) && (((uintptr_t)jb.vhs & 15) == 0);
+    t.last = tout ? 0 : 1;
+    t.alpha = (float)(-sqrt(jb.p.dt) / j);
+    t.V = (const cpx<float>*)jb.vhs;
     t.Tin = (const unsigned short*)tin[ids[q]];
     t.Tout = tout ? (unsigned short*)tout[ids[q]] : nullptr;
+    t.T0 = (const cpx<float>*)t0c[ids[q]];
     t.acc = (cpx<double>*)acc[ids[q]];
     cnt[q] = ((long long)t.W * t.tiles_m * t.tiles_n + 7) & ~7LL;
   }
@@ -508,15 +543,13 @@ static hipError_t launch_taylor_bf16x3(const Job* jobs, const int* ids, int c,
   return hipGetLastError();
 }
 
-// One Taylor term, T_j = alpha vhs T_{j-1}, acc += T_j, for a group of jobs of one
-// precision and tile class; alpha = -sqrt(dt) * alpha_scale per job.
+// One Taylor term, T_j = alpha vhs T_{j-1}, acc += T_j, for a group of FP64 or FP32 jobs
+// of one tile class; alpha = -sqrt(dt) * alpha_scale per job.
 hipError_t launch_taylor_group(const Job* jobs, const int* ids, int c, int choice,
                                const void* const* tin, void* const* tout, void* const* acc,
                                double alpha_scale, hipStream_t s) {
   TimedScope ts(KC_TAYLOR, s);
   const int cls = taylor_class(jobs[ids[0]].p);
-  if (jobs[ids[0]].p.prec == AFQMC_PREC_BF16X3)
-    return launch_taylor_bf16x3(jobs, ids, c, tin, tout, acc, alpha_scale, s);
   if (low_prec(jobs[ids[0]].p.prec)) {
     OpTaylor<float> ops[AFQMC_MAXP];
     for (int q = 0; q < c; ++q) {
@@ -550,55 +583,65 @@ hipError_t launch_taylor_group(const Job* jobs, const int* ids, int c, int choic
 // Layout: the Green's-function slots come first in every entry's workspace, so that
 // run_greens (which carves from the start) and the weight update agree on them.
 static size_t carve_propagate(Carve& c, const afqmc_kpt_problem& p, void** acc, void** t0,
-                              void** t1, GreensWs& g) {
+                              void** t1, void** tc, GreensWs& g) {
   Dims d = dims_of(p);
   // Taylor operands: complex128 or complex64 [W][N][n]; in the BF16X3 mode they hold
-  // BF16 planes [W][n][4][KP] (t1 first receives the complex64 T_0)
-  size_t tbytes = (low_prec(p.prec) ? 8 : 16) * (size_t)d.W * d.N() * d.n();
-  if (p.prec == AFQMC_PREC_BF16X3) tbytes = 8 * (size_t)d.W * d.n() * kpad32(d.N());
+  // BF16 planes [W][n][4][KP] and tc the complex64 T_0
+  const bool bf = p.prec == AFQMC_PREC_BF16X3;
+  const size_t tbytes = bf ? 8 * (size_t)d.W * d.n() * kpad32(d.N())
+                           : (low_prec(p.prec) ? 8 : 16) * (size_t)d.W * d.N() * d.n();
   carve_greens(c, d, g);
   *acc = c.take(16 * (size_t)d.W * d.N() * d.n());
   *t0 = c.take(tbytes);
   *t1 = c.take(tbytes);
+  *tc = c.take(bf ? 8 * (size_t)d.W * d.N() * d.n() : 0);
   return c.off;
 }
 
 size_t propagate_ws_bytes(const afqmc_kpt_problem& p) {
   Carve c(nullptr);
-  void *a, *b, *t;
+  void *a, *b, *t, *tc;
   GreensWs g;
-  return carve_propagate(c, p, &a, &b, &t, g);
+  return carve_propagate(c, p, &a, &b, &t, &tc, g);
 }
 
-void propagate_slots(const Job& j, void** acc, void** t0, void** t1) {
+void propagate_slots(const Job& j, void** acc, void** t0, void** t1, void** tc) {
   Carve c(j.ws);
   GreensWs g;
-  carve_propagate(c, j.p, acc, t0, t1, g);
+  carve_propagate(c, j.p, acc, t0, t1, tc, g);
 }
 
 static int taylor_key(const afqmc_kpt_problem& p) { return p.prec * 16 + taylor_class(p); }
 
 // U <- bhalf T6(-sqrt(dt) vhs) bhalf U for every job.
 static hipError_t propagate_jobs(const Job* J, int c, hipStream_t s) {
-  void *acc[AFQMC_MAXP], *t0[AFQMC_MAXP], *t1[AFQMC_MAXP], *U[AFQMC_MAXP];
+  void *acc[AFQMC_MAXP], *t0[AFQMC_MAXP], *t1[AFQMC_MAXP], *tc[AFQMC_MAXP], *U[AFQMC_MAXP];
   for (int q = 0; q < c; ++q) {
-    propagate_slots(J[q], &acc[q], &t0[q], &t1[q]);
+    propagate_slots(J[q], &acc[q], &t0[q], &t1[q], &tc[q]);
     U[q] = J[q].p.U;
   }
   return for_groups(
       c, [&](int i) { return taylor_key(J[i].p); },
       [&](const int* ids, int g) -> hipError_t {
         const bool f32 = low_prec(J[ids[0]].p.prec);
-        // T_0 = bhalf U (FP64), acc = T_0, t0 = T_0 in the Taylor precision (BF16X3: t1 =
-        // T_0 as complex64, then t0 = its BF16 planes)
         hipError_t e;
         if (J[ids[0]].p.prec == AFQMC_PREC_BF16X3) {
-          e = launch_bhalf<float>(J, ids, g, U, acc, t1, s);
-          if (e == hipSuccess) e = launch_t_split(J, ids, g, t1, t0, s);
-        } else {
-          e = f32 ? launch_bhalf<float>(J, ids, g, U, acc, t0, s)
-                  : launch_bhalf<double>(J, ids, g, U, acc, t0, s);
+          // T_0 = bhalf U: acc (FP64) and tc (complex64), R_6 = T_0 as planes in t0;
+          // Horner steps j = 6 .. 1 alternate between the plane buffers
+          e = launch_bhalf<float>(J, ids, g, U, acc, tc, s);
+          if (e == hipSuccess) e = launch_t_split(J, ids, g, tc, t0, s);
+          void** rin = t0;
+          void** rout = t1;
+          for (int j = 6; j >= 1 && e == hipSuccess; --j) {
+            e = launch_taylor_bf16x3(J, ids, g, j, rin, (j > 1) ? rout : nullptr, tc, acc, s);
+            void** t = rin; rin = rout; rout = t;
+          }
+          if (e != hipSuccess) return e;
+          return launch_bhalf<double>(J, ids, g, acc, U, nullptr, s);
         }
+        // T_0 = bhalf U (FP64), acc = T_0, t0 = T_0 in the Taylor precision
+        e = f32 ? launch_bhalf<float>(J, ids, g, U, acc, t0, s)
+                : launch_bhalf<double>(J, ids, g, U, acc, t0, s);
         if (e != hipSuccess) return e;
         const int choice = tune_lookup(tune_key(TS_TAYLOR, J, ids, g));
         void** tin = t0;
@@ -618,11 +661,13 @@ hipError_t tune_taylor(const Job* jobs, int n, hipStream_t s) {
   for (int c0 = 0; c0 < n; c0 += AFQMC_MAXP) {
     const int c = (n - c0 < AFQMC_MAXP) ? n - c0 : AFQMC_MAXP;
     const Job* J = jobs + c0;
-    void *acc[AFQMC_MAXP], *t0[AFQMC_MAXP], *t1[AFQMC_MAXP];
-    for (int q = 0; q < c; ++q) propagate_slots(J[q], &acc[q], &t0[q], &t1[q]);
+    void *acc[AFQMC_MAXP], *t0[AFQMC_MAXP], *t1[AFQMC_MAXP], *tc[AFQMC_MAXP];
+    for (int q = 0; q < c; ++q) propagate_slots(J[q], &acc[q], &t0[q], &t1[q], &tc[q]);
     const hipError_t e = for_groups(
         c, [&](int i) { return taylor_key(J[i].p); },
         [&](const int* ids, int g) -> hipError_t {
+          // the BF16X3 steps have a single variant
+          if (J[ids[0]].p.prec == AFQMC_PREC_BF16X3) return hipSuccess;
           return tune_group(
               TS_TAYLOR, J, ids, g,
               [&](int ch) { return launch_taylor_group(J, ids, g, ch, t0, t1, acc, 1.0, s); }, s);
