@@ -127,9 +127,188 @@ static hipError_t vbias_tiles(const OpVbias<T>* ops, int c, int choice, hipStrea
   }
 }
 
+// Split-K partial traces on the three-pass BF16 split (BF16X3 mode):
+//   part[s][w][Q][g] = sum over the k of slice s of sum_{a,r} Lh[Q][k][a][r][g] Gh[w][(k a)][(k-Q) r]
+// one 256-thread workgroup per (Q, slice, 64 g, 64 walkers); the K stream runs over
+// (k, a, 32 r) chunks.  Lh comes as split planes Lhs[Q][k][g][a][plane][r] (r padded to
+// KP with zeros); the FP64 Gh rows are rounded to FP32 and split while staged.  Two chunks
+// in flight in registers (unconditional, clamped loads), two LDS stages, four waves in
+// 2 x 2 (32 g x 32 walkers each, 12 BF16 MFMAs per complex 16 x 16 x 32 block).
+struct VbBfArgs {
+  int W, nk, m, nocc, C, KP, S, kper, tiles_g, tiles_w;
+  KMesh mesh;
+  const unsigned short* Lhs;  // [nk][nk][C][nocc][4][KP]
+  const cpx<double>* Gh;      // [W][nk nocc][nk m]
+  cpx<double>* part;          // [S][W][nk][C]
+};
+
+__global__ __launch_bounds__(256) void vbias_bf16x3_kernel(const Batch<VbBfArgs> B) {
+  constexpr int BG = 64, BW = 64, RS = 40;
+  __shared__ __attribute__((aligned(16))) unsigned short sA[2][4][BG][RS];
+  __shared__ __attribute__((aligned(16))) unsigned short sB[2][4][BW][RS];
+  long long loc;
+  const int pb = batch_find(B, blockIdx.x, loc);
+  const VbBfArgs& a = B.a[pb];
+  const int tw = (int)(loc % a.tiles_w);
+  long long rest = loc / a.tiles_w;
+  const int tg = (int)(rest % a.tiles_g);
+  rest /= a.tiles_g;
+  const int sl = (int)(rest % a.S), Q = (int)(rest / a.S);
+  const int g0 = tg * BG, w0 = tw * BW;
+  const int W = a.W, nk = a.nk, m = a.m, nocc = a.nocc, C = a.C, KP = a.KP;
+  const int kb = sl * a.kper, ke = min(nk, kb + a.kper);
+  const int nrc = KP / 32;
+  const int nch = ke > kb ? (ke - kb) * nocc * nrc : 0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t n = (int64_t)nk * nocc, Nn = (int64_t)nk * m;
+  cpx<double>* __restrict__ part = a.part + (int64_t)sl * W * nk * C;
+  if (nch == 0) {  // empty slice: zero partial
+    for (int u = tid; u < BG * BW; u += 256) {
+      const int g = g0 + (u & 63), w = w0 + (u >> 6);
+      if (g < C && w < W) part[((int64_t)w * nk + Q) * C + g] = cpx<double>{0.0, 0.0};
+    }
+    return;
+  }
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  u4 ra[2][4];
+  cpx<double> rb[2][4][2];
+  // unit u = tid + 256 e: A: g = u >> 4, plane (u >> 2) & 3, 8 r at 8 (u & 3);
+  // B: walker u >> 4, r pair u & 15
+  auto issue = [&](int c, u4 (&xa)[4], cpx<double> (&xb)[4][2]) {
+    c = c < nch ? c : nch - 1;
+    const int kk = kb + c / (nocc * nrc), aa = (c / nrc) % nocc, r0 = 32 * (c % nrc);
+    const int k2 = a.mesh.kmq(kk, Q);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int u = tid + 256 * e;
+      const int g = min(g0 + (u >> 4), C - 1);
+      xa[e] = *reinterpret_cast<const u4*>(
+          a.Lhs + (((((int64_t)Q * nk + kk) * C + g) * nocc + aa) * 4 + ((u >> 2) & 3)) * KP +
+          r0 + 8 * (u & 3));
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int u = tid + 256 * e;
+      const int w = min(w0 + (u >> 4), W - 1);
+      const int r = r0 + 2 * (u & 15);
+      const cpx<double>* row = a.Gh + ((int64_t)w * n + (int64_t)kk * nocc + aa) * Nn + (int64_t)k2 * m;
+      xb[e][0] = row[min(r, m - 1)];
+      xb[e][1] = row[min(r + 1, m - 1)];
+    }
+  };
+  auto stash = [&](int c, int st, const u4 (&xa)[4], const cpx<double> (&xb)[4][2]) {
+    const int r0 = 32 * ((c < nch ? c : nch - 1) % nrc);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int u = tid + 256 * e;
+      *reinterpret_cast<u4*>(&sA[st][(u >> 2) & 3][u >> 4][8 * (u & 3)]) = xa[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int u = tid + 256 * e;
+      const int r = r0 + 2 * (u & 15);
+      const bool ok0 = r < m, ok1 = r + 1 < m;
+      unsigned int h[4];
+      bf16_split2(ok0 ? (float)xb[e][0].re : 0.f, ok1 ? (float)xb[e][1].re : 0.f, h[0], h[1]);
+      bf16_split2(ok0 ? (float)xb[e][0].im : 0.f, ok1 ? (float)xb[e][1].im : 0.f, h[2], h[3]);
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl)
+        *reinterpret_cast<unsigned int*>(&sB[st][pl][u >> 4][2 * (u & 15)]) = h[pl];
+    }
+  };
+  v4f acr[2][2], aci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acr[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+      aci[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+  const u16x8 sgn = {0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000};
+  issue(0, ra[0], rb[0]);
+  issue(1, ra[1], rb[1]);
+  stash(0, 0, ra[0], rb[0]);
+  issue(2, ra[0], rb[0]);
+  __syncthreads();
+  // iteration c: chunk c from stage c & 1; chunk c + 1 (slot (c + 1) & 1) to the other
+  // stage; chunk c + 3 requested into the freed slot
+  for (int c0 = 0; c0 < nch; c0 += 2) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int c = c0 + d;
+      if (c < nch) {
+        const int st = c & 1;
+        const int kq = 8 * (lane >> 4);
+        u16x8 fa[2][4], fb[2][4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int pl = 0; pl < 4; ++pl) {
+            fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][pl][wm * 32 + i * 16 + (lane & 15)][kq]);
+            fb[i][pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][wn * 32 + i * 16 + (lane & 15)][kq]);
+          }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            // re += Lr Gr - Li Gi,  im += Lr Gi + Li Gr
+            acr[i][j] = mul3(fa[i][0], fa[i][1], fb[j][0], fb[j][1], acr[i][j]);
+            acr[i][j] = mul3(fa[i][2] ^ sgn, fa[i][3] ^ sgn, fb[j][2], fb[j][3], acr[i][j]);
+            aci[i][j] = mul3(fa[i][0], fa[i][1], fb[j][2], fb[j][3], aci[i][j]);
+            aci[i][j] = mul3(fa[i][2], fa[i][3], fb[j][0], fb[j][1], aci[i][j]);
+          }
+      }
+      stash(c + 1, (c + 1) & 1, ra[(d + 1) & 1], rb[(d + 1) & 1]);
+      issue(c + 3, ra[(d + 1) & 1], rb[(d + 1) & 1]);
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int g = g0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
+        const int w = w0 + wn * 32 + j * 16 + (lane & 15);
+        if (g < C && w < W)
+          part[((int64_t)w * nk + Q) * C + g] = cpx<double>{(double)acr[i][j][v], (double)aci[i][j][v]};
+      }
+}
+
+static hipError_t launch_vbias_bf16x3(const Job* jobs, const int* ids, int c, void* const* parts,
+                                      hipStream_t s) {
+  Batch<VbBfArgs> Bv;
+  Bv.nprob = c;
+  long long cnt[AFQMC_MAXP];
+  for (int q = 0; q < c; ++q) {
+    const afqmc_kpt_problem& p = jobs[ids[q]].p;
+    VbBfArgs& v = Bv.a[q];
+    v.W = p.nwalk; v.nk = p.nk; v.m = p.m; v.nocc = p.nocc; v.C = p.nchol;
+    v.KP = 32 * ((p.m + 31) / 32);
+    v.S = vbias_splits(dims_of(p));
+    v.kper = (p.nk + v.S - 1) / v.S;
+    v.tiles_g = (p.nchol + 63) / 64;
+    v.tiles_w = (p.nwalk + 63) / 64;
+    v.mesh = make_mesh(p);
+    v.Lhs = (const unsigned short*)p.Lhs;
+    v.Gh = (const cpx<double>*)p.Gh;
+    v.part = (cpx<double>*)parts[ids[q]];
+    cnt[q] = (long long)p.nk * v.S * v.tiles_g * v.tiles_w;
+  }
+  const long long g = batch_close(Bv, cnt);
+  if (g < 0) return hipErrorInvalidValue;
+  if (g == 0) return hipSuccess;
+  hipLaunchKernelGGL(vbias_bf16x3_kernel, dim3((unsigned)g), dim3(256), 0, s, Bv);
+  return hipGetLastError();
+}
+
 // Split-K partial traces of a group of jobs of one precision.
 hipError_t launch_vbias_group(const Job* jobs, const int* ids, int c, int choice,
                               void* const* parts, hipStream_t s) {
+  if (jobs[ids[0]].p.prec == AFQMC_PREC_BF16X3)
+    return launch_vbias_bf16x3(jobs, ids, c, parts, s);
   if (low_prec(jobs[ids[0]].p.prec)) {
     OpVbias<float> ops[AFQMC_MAXP];
     for (int q = 0; q < c; ++q) ops[q] = vbias_op<float>(jobs[ids[q]].p, parts[ids[q]]);
@@ -302,121 +481,207 @@ __global__ __launch_bounds__(256) void field_split_kernel(const Batch<FieldArgs>
 
 // HS potential on the three-pass BF16 split:
 //   vhs[w][(k p), ((k-Q) r)] = sum_g zeta[w][Q][g] L[Q][k][p][r][g]
-// per Q a (W x nk m m) product with K = nchol, 64 x 64 tiles of four waves (2 x 2, each
-// 32 x 32), K in chunks of 32; both operands come as split planes with g contiguous and
-// are staged into LDS with 16-byte copies; 12 BF16 MFMAs per complex 16 x 16 x 32 block.
+// per Q a (W x nk m m) product with K = nchol; both operands come as split planes with g
+// contiguous.  The product streams L once from HBM, so the kernel is persistent and
+// pipelined: each 512-thread workgroup walks its tiles (64 walkers x 128 columns, tile
+// index blockIdx.x + i gridDim.x over every problem of the batch) as one stream of K
+// chunks of 32.  Waves 4-7 produce: they keep DEPTH chunks of both operands in flight in
+// registers and copy the oldest into one of two LDS stages; waves 0-3 consume, in 2 x 2
+// (each 32 walkers x 64 columns, 12 BF16 MFMAs per complex 16 x 16 x 32 block, FP32
+// accumulation) and scatter a finished tile straight from registers.  One block barrier
+// per chunk; loads are unconditional (clamped addresses, zeros selected afterwards).
 struct VhsBfArgs {
-  int W, nk, m, C, tiles_m, tiles_n;
+  int W, nk, m, C, CP, tiles_m, tiles_n;
   KMesh mesh;
   const unsigned short* zs;  // [W][nk][4][CP]
   const unsigned short* Ls;  // [nk][nk m m][4][CP]
   cpx<float>* vhs;           // [W][nk m][nk m]
 };
 
-__global__ __launch_bounds__(256) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> B) {
-  constexpr int BM = 64, BN = 64, BKC = 32, RS = BKC + 8;
+// Position of a workgroup in its stream of (tile, chunk) pairs.
+struct VhsPos {
+  long long tile;  // global tile index
+  int chunk;
+};
+
+__global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> B) {
+  constexpr int BM = 64, BN = 128, BKC = 32, RS = BKC + 8, DEPTH = 2;
   __shared__ __attribute__((aligned(16))) unsigned short sA[2][4][BM][RS];
   __shared__ __attribute__((aligned(16))) unsigned short sB[2][4][BN][RS];
-  long long bloc;
-  const int pb = batch_find(B, blockIdx.x, bloc);
-  const VhsBfArgs& a = B.a[pb];
-  const int W = a.W, nk = a.nk, m = a.m, C = a.C;
-  const int CP = 32 * ((C + 31) / 32);
-  const int ncol = nk * m * m;
-  const int per_q = a.tiles_m * a.tiles_n;
-  const int Q = (int)(bloc / per_q);
-  const int rem = (int)(bloc % per_q);
-  const int row0 = (rem / a.tiles_n) * BM, col0 = (rem % a.tiles_n) * BN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const unsigned short* __restrict__ zs = a.zs;
-  const unsigned short* __restrict__ Ls = a.Ls + (int64_t)Q * ncol * 4 * CP;
-
-  // 16-byte units of a chunk: u = (row 4 + plane) 4 + c8; 64 rows x 4 planes x 4 = 1024
-  uint4 pa[4], pbu[4];
-  auto fetch = [&](int k0) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int u = tid + 256 * e;
-      const int r = u >> 4, pl = (u >> 2) & 3, c8 = u & 3;
-      uint4 va = {0u, 0u, 0u, 0u}, vb = {0u, 0u, 0u, 0u};
-      const int w = row0 + r;
-      if (w < W)
-        va = *reinterpret_cast<const uint4*>(
-            zs + (((int64_t)w * nk + Q) * 4 + pl) * CP + k0 + 8 * c8);
-      const int col = col0 + r;
-      if (col < ncol)
-        vb = *reinterpret_cast<const uint4*>(Ls + ((int64_t)col * 4 + pl) * CP + k0 + 8 * c8);
-      pa[e] = va;
-      pbu[e] = vb;
-    }
+  const long long ntiles = B.first[B.nprob];
+  const long long G = gridDim.x;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if ((long long)blockIdx.x >= ntiles) return;
+  // number of chunks of a tile, and the stream length of this workgroup
+  auto nchunks = [&](long long t) {
+    long long loc;
+    const int p = batch_find(B, t, loc);
+    return B.a[p].CP / BKC;
   };
-  auto stash = [&](int buf) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int u = tid + 256 * e;
-      const int r = u >> 4, pl = (u >> 2) & 3, c8 = u & 3;
-      *reinterpret_cast<uint4*>(&sA[buf][pl][r][8 * c8]) = pa[e];
-      *reinterpret_cast<uint4*>(&sB[buf][pl][r][8 * c8]) = pbu[e];
+  long long total = 0;
+  for (long long t = blockIdx.x; t < ntiles; t += G) total += nchunks(t);
+  auto advance = [&](VhsPos& ps) {
+    if (++ps.chunk == nchunks(ps.tile)) {
+      ps.chunk = 0;
+      ps.tile += G;
     }
   };
 
-  v4f acr[2][2], aci[2][2];
+  if (wave >= 4) {
+    // ---------------- producers: unit u = pt + 256 e: row / column u >> 4, plane
+    // (u >> 2) & 3, 8 k at 8 (u & 3); A: 4 units, B: 8 units per thread
+    const int pt = threadIdx.x - 256;
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    u4 ra[DEPTH][4], rb[DEPTH][8];
+    VhsPos ip{(long long)blockIdx.x, 0}, sp{(long long)blockIdx.x, 0};
+    long long issued = 0;
+    auto issue = [&](u4 (&xa)[4], u4 (&xb)[8]) {
+      // past the end of the stream: reload the last chunk (never stored)
+      const VhsPos q = issued < total ? ip : VhsPos{ip.tile - G, 0};
+      long long loc;
+      const int p = batch_find(B, q.tile < ntiles ? q.tile : ntiles - 1, loc);
+      const VhsBfArgs& a = B.a[p];
+      const int per_q = a.tiles_m * a.tiles_n;
+      const int Q = (int)(loc / per_q), rem = (int)(loc % per_q);
+      const int row0 = (rem / a.tiles_n) * BM, col0 = (rem % a.tiles_n) * BN;
+      const int ncol = a.nk * a.m * a.m, CP = a.CP;
+      const int k0 = (issued < total ? q.chunk : 0) * BKC;
+      const unsigned short* __restrict__ Lq = a.Ls + (int64_t)Q * ncol * 4 * CP;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      acr[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-      aci[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-    }
-  const u16x8 sgn = {0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000};
-  const int nch = CP / BKC;
-  fetch(0);
-  stash(0);
-  __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < nch) fetch((c + 1) * BKC);
-    const int kq = 8 * (lane >> 4);
-    u16x8 fa[2][4], fb[2][4];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int pl = 0; pl < 4; ++pl) {
-        fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[buf][pl][wm * 32 + i * 16 + (lane & 15)][kq]);
-        fb[i][pl] = *reinterpret_cast<const u16x8*>(&sB[buf][pl][wn * 32 + i * 16 + (lane & 15)][kq]);
+      for (int e = 0; e < 4; ++e) {
+        const int u = pt + 256 * e;
+        const int w = min(row0 + (u >> 4), a.W - 1);
+        xa[e] = *reinterpret_cast<const u4*>(
+            a.zs + (((int64_t)w * a.nk + Q) * 4 + ((u >> 2) & 3)) * CP + k0 + 8 * (u & 3));
       }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        // re += Ar Br - Ai Bi,  im += Ar Bi + Ai Br
-        acr[i][j] = mul3(fa[i][0], fa[i][1], fb[j][0], fb[j][1], acr[i][j]);
-        acr[i][j] = mul3(fa[i][2] ^ sgn, fa[i][3] ^ sgn, fb[j][2], fb[j][3], acr[i][j]);
-        aci[i][j] = mul3(fa[i][0], fa[i][1], fb[j][2], fb[j][3], aci[i][j]);
-        aci[i][j] = mul3(fa[i][2], fa[i][3], fb[j][0], fb[j][1], aci[i][j]);
+      for (int e = 0; e < 8; ++e) {
+        const int u = pt + 256 * e;
+        const int col = min(col0 + (u >> 4), ncol - 1);
+        xb[e] = *reinterpret_cast<const u4*>(
+            Lq + ((int64_t)col * 4 + ((u >> 2) & 3)) * CP + k0 + 8 * (u & 3));
       }
-    if (c + 1 < nch) stash(buf ^ 1);
+      if (issued < total) advance(ip);
+      ++issued;
+    };
+    auto stash = [&](int st, const u4 (&xa)[4], const u4 (&xb)[8]) {
+      // rows past W: zeros (their loads were clamped); columns past ncol are not stored
+      long long loc;
+      const int p = batch_find(B, sp.tile < ntiles ? sp.tile : ntiles - 1, loc);
+      const VhsBfArgs& a = B.a[p];
+      const int rem = (int)(loc % (a.tiles_m * a.tiles_n));
+      const int row0 = (rem / a.tiles_n) * BM;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int u = pt + 256 * e;
+        const u4 z = {0u, 0u, 0u, 0u};
+        *reinterpret_cast<u4*>(&sA[st][(u >> 2) & 3][u >> 4][8 * (u & 3)]) =
+            row0 + (u >> 4) < a.W ? xa[e] : z;
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int u = pt + 256 * e;
+        *reinterpret_cast<u4*>(&sB[st][(u >> 2) & 3][u >> 4][8 * (u & 3)]) = xb[e];
+      }
+    };
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) issue(ra[d], rb[d]);
+    stash(0, ra[0], rb[0]);
+    advance(sp);
+    issue(ra[0], rb[0]);
     __syncthreads();
-  }
-  // scatter: column (k p r) of Q to vhs[w][(k p)][((k - Q) r)]
-  const int64_t Nn = (int64_t)nk * m;
-  const int mm = m * m;
+    // iteration s: the consumers work on chunk s; chunk s + 1 (slot (s + 1) % DEPTH) goes
+    // to stage (s + 1) & 1 and the next chunk is requested into the freed slot
+    for (long long s0 = 0; s0 < total; s0 += DEPTH) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int w = row0 + wm * 32 + i * 16 + mfma16<float>::drow(lane, v);
-        const int col = col0 + wn * 32 + j * 16 + (lane & 15);
-        if (w >= W || col >= ncol) continue;
-        const int kp = col / mm, pr = col % mm;
-        const int p = pr / m, r = pr % m;
-        const int k2 = a.mesh.kmq(kp, Q);
-        a.vhs[((int64_t)w * Nn + (int64_t)kp * m + p) * Nn + (int64_t)k2 * m + r] =
-            cpx<float>{acr[i][j][v], aci[i][j][v]};
+      for (int d = 0; d < DEPTH; ++d) {
+        const int sl = (d + 1) % DEPTH;
+        stash((int)((s0 + d + 1) & 1), ra[sl], rb[sl]);
+        if (sp.tile < ntiles) advance(sp);
+        issue(ra[sl], rb[sl]);
+        __syncthreads();
       }
+    }
+    return;
+  }
+
+  // ---------------- consumers
+  const int wm = wave >> 1, wn = wave & 1;
+  v4f acr[2][4], aci[2][4];
+  auto zero = [&]() {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acr[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+        aci[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+      }
+  };
+  zero();
+  const u16x8 sgn = {0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000};
+  VhsPos cp{(long long)blockIdx.x, 0};
+  __syncthreads();
+  for (long long s0 = 0; s0 < total; s0 += DEPTH) {
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) {
+      if (s0 + d < total) {
+        const int st = (int)((s0 + d) & 1);
+        const int kq = 8 * (lane >> 4);
+        u16x8 fa[2][4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int pl = 0; pl < 4; ++pl)
+            fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][pl][wm * 32 + i * 16 + (lane & 15)][kq]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          u16x8 fb[4];
+#pragma unroll
+          for (int pl = 0; pl < 4; ++pl)
+            fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][wn * 64 + j * 16 + (lane & 15)][kq]);
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            // re += Zr Lr - Zi Li,  im += Zr Li + Zi Lr
+            acr[i][j] = mul3(fa[i][0], fa[i][1], fb[0], fb[1], acr[i][j]);
+            acr[i][j] = mul3(fa[i][2] ^ sgn, fa[i][3] ^ sgn, fb[2], fb[3], acr[i][j]);
+            aci[i][j] = mul3(fa[i][0], fa[i][1], fb[2], fb[3], aci[i][j]);
+            aci[i][j] = mul3(fa[i][2], fa[i][3], fb[0], fb[1], aci[i][j]);
+          }
+        }
+        long long loc;
+        const int p = batch_find(B, cp.tile, loc);
+        const VhsBfArgs& a = B.a[p];
+        if (cp.chunk + 1 == a.CP / BKC) {
+          // tile done: column (k p r) of Q to vhs[w][(k p)][((k - Q) r)]
+          const int per_q = a.tiles_m * a.tiles_n;
+          const int Q = (int)(loc / per_q), rem = (int)(loc % per_q);
+          const int row0 = (rem / a.tiles_n) * BM, col0 = (rem % a.tiles_n) * BN;
+          const int m = a.m, mm = m * m, ncol = a.nk * mm;
+          const int64_t Nn = (int64_t)a.nk * m;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int col = col0 + wn * 64 + j * 16 + (lane & 15);
+            if (col >= ncol) continue;
+            const int kp = col / mm, pr = col % mm;
+            const int pp = pr / m, r = pr % m;
+            const int64_t off = ((int64_t)kp * m + pp) * Nn + (int64_t)a.mesh.kmq(kp, Q) * m + r;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int w = row0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
+                if (w < a.W)
+                  a.vhs[(int64_t)w * Nn * Nn + off] = cpx<float>{acr[i][j][v], aci[i][j][v]};
+              }
+          }
+          zero();
+        }
+        advance(cp);
+      }
+      __syncthreads();
+    }
+  }
 }
 
 static hipError_t launch_vhs_bf16x3(const Job* J, const int* ids, int g, void* const* zeta,
@@ -437,21 +702,27 @@ static hipError_t launch_vhs_bf16x3(const Job* J, const int* ids, int g, void* c
     fa.zeta = zeta[ids[q]];
     cf[q] = ((int64_t)p.nwalk * p.nk * CP + 255) / 256;
     VhsBfArgs& va = V.a[q];
-    va.W = p.nwalk; va.nk = p.nk; va.m = p.m; va.C = p.nchol;
+    va.W = p.nwalk; va.nk = p.nk; va.m = p.m; va.C = p.nchol; va.CP = CP;
     va.tiles_m = (p.nwalk + 63) / 64;
-    va.tiles_n = (p.nk * p.m * p.m + 63) / 64;
+    va.tiles_n = (p.nk * p.m * p.m + 127) / 128;
     va.mesh = make_mesh(p);
     va.zs = (const unsigned short*)zeta[ids[q]];
     va.Ls = (const unsigned short*)p.Ls;
     va.vhs = (cpx<float>*)j.vhs;
-    cv[q] = (long long)p.nk * va.tiles_m * va.tiles_n;
+    cv[q] = (long long)p.nk * va.tiles_m * va.tiles_n;  // tiles
   }
   long long gf = batch_close(F, cf), gv = batch_close(V, cv);
   if (gf < 0 || gv < 0) return hipErrorInvalidValue;
   if (gf > 0) hipLaunchKernelGGL(field_split_kernel, dim3((unsigned)gf), dim3(256), 0, s, F);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || gv == 0) return e;
-  hipLaunchKernelGGL(vhs_bf16x3_kernel, dim3((unsigned)gv), dim3(256), 0, s, V);
+  // persistent: one workgroup per CU (the LDS stages take 120 KB), at most one per tile
+  int dev = 0, ncu = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const long long grid = gv < ncu ? gv : ncu;
+  hipLaunchKernelGGL(vhs_bf16x3_kernel, dim3((unsigned)grid), dim3(512), 0, s, V);
   return hipGetLastError();
 }
 

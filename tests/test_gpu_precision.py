@@ -7,12 +7,13 @@ entry for the force bias, HS potential and propagated walkers, 2e-5 for the ener
 (two chained contractions), and 5e-6 of the summed magnitude of the three energy parts per
 walker for E_L (the parts cancel, so their size, not |E|, sets the rounding scale).
 
-BF16X3 (HS potential and exchange on the three-pass BF16 split, the rest FP32): each
-split operand keeps 16 significant bits plus a rounded remainder and the lo*lo term is
-dropped, so a product carries ~2^-16 relative error (~1.5e-5) before FP32 accumulation;
-the bars are 1e-4 of the largest entry for the HS potential and of the largest magnitude
-for the exchange energy, 5e-5 of the summed part magnitudes on E_L, and 5e-5 for one
-propagated step (the potential enters the propagator multiplied by sqrt(dt)).
+BF16X3 (force bias, HS potential, Taylor terms and exchange on the three-pass BF16 split,
+the rest FP32): each split operand keeps 16 significant bits plus a rounded remainder and
+the lo*lo term is dropped, so a product carries ~2^-16 relative error (~1.5e-5) before
+FP32 accumulation; the bars are 1e-4 of the largest entry for the force bias and the HS
+potential and of the largest magnitude for the exchange energy, 5e-5 of the summed part
+magnitudes on E_L, and 5e-5 for one propagated step (the potential enters the propagator
+multiplied by sqrt(dt)).
 """
 
 import numpy as np
@@ -37,7 +38,7 @@ def test_contractions_and_step(case, prec):
     Gh, ld = kp.greens(U, s.A)
     xbar, X = kp.force_bias(pre["Lh"], Gh, s.mesh, s.dt)
     xb, Xg = p.vbias()
-    assert rel(host(Xg), X) < 5e-6
+    assert rel(host(Xg), X) < (5e-6 if prec == 1 else 1e-4)
     zeta = kp.combined_field(x[0], xbar, s.mesh)
     vref = kp.hs_potential(s.L, zeta, s.mesh)
     v = p.vhs(torch.from_numpy(x[0]), xb)
