@@ -201,7 +201,30 @@ __global__ __launch_bounds__(256) void exchange_kernel(const Batch<ExchArgs> B) 
 // (w, b), K = r padded to 32 * KB; the Gh fragments are split once into registers, and the
 // Lh slabs come pre-split from prepare (four bf16 planes: re hi, re lo, im hi, im lo, r
 // contiguous) and are staged into LDS with 16-byte copies.
-template <int KB>
+// 4 x 4 transpose inside each lane quad: on return register v of quad lane j holds what
+// register j of quad lane v held.  Two butterfly steps (lane bit 0 with register bit 0,
+// then bit 1); in each, the register whose index bit differs from the lane's bit is
+// exchanged with the partner lane by a DPP quad permutation.
+template <int CTRL>
+__device__ __forceinline__ void quad_swap_pair(float& x0, float& x1, bool hi) {
+  const float send = hi ? x0 : x1;
+  const float recv =
+      __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(send), CTRL, 0xf, 0xf, false));
+  x0 = hi ? recv : x0;
+  x1 = hi ? x1 : recv;
+}
+
+__device__ __forceinline__ v4f quad_transpose(v4f x, int lane) {
+  float x0 = x[0], x1 = x[1], x2 = x[2], x3 = x[3];
+  const bool b0 = lane & 1, b1 = (lane >> 1) & 1;
+  quad_swap_pair<0xB1>(x0, x1, b0);  // quad_perm [1,0,3,2]
+  quad_swap_pair<0xB1>(x2, x3, b0);
+  quad_swap_pair<0x4E>(x0, x2, b1);  // quad_perm [2,3,0,1]
+  quad_swap_pair<0x4E>(x1, x3, b1);
+  return v4f{x0, x1, x2, x3};
+}
+
+template <int KB, int WT>
 __global__ __launch_bounds__(256) void exchange_bf16x3_kernel(const Batch<ExchArgs> B) {
   constexpr int KP = 32 * KB;  // r padded to the MFMA K
   constexpr int RS = KP + 8;   // LDS row stride (bf16): rows start 16-byte aligned
@@ -230,141 +253,206 @@ __global__ __launch_bounds__(256) void exchange_bf16x3_kernel(const Batch<ExchAr
   const int Gs = 16 / nocc, Ws = 16 / nocc;
   const int col = lane & 15;
   const int ws_l = col / nocc, b_l = col % nocc;
-  const int wl = chunk * 4 * Ws + wave * Ws + ws_l;
-  const bool colok = (ws_l < Ws) && (wl < W);
   const int64_t Nn = (int64_t)nk * m, nn = (int64_t)nk * nocc;
+  // column tile ct of this wave: walkers chunk 4 WT Ws + (wave WT + ct) Ws + (0 .. Ws-1)
+  auto walker = [&](int ct) { return chunk * 4 * WT * Ws + (wave * WT + ct) * Ws + ws_l; };
 
-  // Gh fragments (B operand, B[r][(w, b)], r = 32 kb + 8 (lane / 16) + i), split
-  u16x8 g1[KB][4], g2[KB][4];
+  // Gh fragments (B operand, B[r][(w, b)], r = 32 kb + 8 (lane / 16) + i), split; the
+  // Lh fragments of a g chunk serve all WT column tiles
+  u16x8 g1[WT][KB][4], g2[WT][KB][4];
 #pragma unroll
-  for (int kb = 0; kb < KB; ++kb)
+  for (int ct = 0; ct < WT; ++ct) {
+    const int wl = walker(ct);
+    const bool colok = (ws_l < Ws) && (wl < W);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int r = 32 * kb + 8 * (lane >> 4) + i;
-      float x1r = 0.f, x1i = 0.f, x2r = 0.f, x2i = 0.f;
-      if (r < m && colok) {
-        const cpx<double> v1 = Gh[((int64_t)wl * nn + (int64_t)kpq * nocc + b_l) * Nn + (int64_t)kq * m + r];
-        const cpx<double> v2 = Gh[((int64_t)wl * nn + (int64_t)k * nocc + b_l) * Nn + (int64_t)kp * m + r];
-        x1r = (float)v1.re; x1i = (float)v1.im; x2r = (float)v2.re; x2i = (float)v2.im;
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int r = 32 * kb + 8 * (lane >> 4) + i;
+        float x1r = 0.f, x1i = 0.f, x2r = 0.f, x2i = 0.f;
+        if (r < m && colok) {
+          const cpx<double> v1 = Gh[((int64_t)wl * nn + (int64_t)kpq * nocc + b_l) * Nn + (int64_t)kq * m + r];
+          const cpx<double> v2 = Gh[((int64_t)wl * nn + (int64_t)k * nocc + b_l) * Nn + (int64_t)kp * m + r];
+          x1r = (float)v1.re; x1i = (float)v1.im; x2r = (float)v2.re; x2i = (float)v2.im;
+        }
+        unsigned short h, l;
+        bf16_split(x1r, h, l); g1[ct][kb][0][i] = h; g1[ct][kb][1][i] = l;
+        bf16_split(x1i, h, l); g1[ct][kb][2][i] = h; g1[ct][kb][3][i] = l;
+        bf16_split(x2r, h, l); g2[ct][kb][0][i] = h; g2[ct][kb][1][i] = l;
+        bf16_split(x2i, h, l); g2[ct][kb][2][i] = h; g2[ct][kb][3][i] = l;
       }
-      unsigned short h, l;
-      bf16_split(x1r, h, l); g1[kb][0][i] = h; g1[kb][1][i] = l;
-      bf16_split(x1i, h, l); g1[kb][2][i] = h; g1[kb][3][i] = l;
-      bf16_split(x2r, h, l); g2[kb][0][i] = h; g2[kb][1][i] = l;
-      bf16_split(x2i, h, l); g2[kb][2][i] = h; g2[kb][3][i] = l;
-    }
+  }
 
   // the pre-split planes: slab (Q, k) is [C][nocc][4][KP] bf16, contiguous per g chunk
   const unsigned short* slab0 = Lhs + ((int64_t)Q * nk + k) * C * nocc * 4 * KP;
   const unsigned short* slab1 = Lhs + ((int64_t)mQ * nk + kpq) * C * nocc * 4 * KP;
   const int nch = (C + Gs - 1) / Gs;
 
-  // 16-byte units of a chunk: u = ((g_s nocc + a) 4 + plane) (KP / 8) + r8, per slab
+  // 16-byte units of a chunk: u = ((g_s nocc + a) 4 + plane) (KP / 8) + r8, per slab.
+  // DEPTH chunks are in flight in registers (the slabs mostly come from beyond L2); the
+  // loads are unconditional (clamped addresses, zeros selected when staged) so that each
+  // wait covers only the oldest chunk.
   constexpr int UPR = KP / 8;                 // units per (row, plane)
   constexpr int NU = (2 * 16 * 4 * UPR) / 256;  // units per thread (both slabs)
-  uint4 pu[NU];
-  auto fetch = [&](int c) {
+  constexpr int DEPTH = KB == 1 ? 4 : 3;
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  u4 pu[DEPTH][NU];
+  auto fetch = [&](int c, u4 (&xu)[NU]) {
+    const int g0 = (c < nch ? c : nch - 1) * Gs;
+#pragma unroll
+    for (int e = 0; e < NU; ++e) {
+      const int idx = tid + 256 * e;
+      const int sl = idx / (16 * 4 * UPR), u = idx % (16 * 4 * UPR);
+      const int row = min(u / (4 * UPR), Gs * nocc - 1);  // g_s * nocc + a
+      const int gg = min(g0 + row / nocc, C - 1);
+      const unsigned short* sb = sl ? slab1 : slab0;
+      xu[e] = *reinterpret_cast<const u4*>(
+          sb + (((int64_t)gg * nocc + row % nocc) * 4 * UPR + u % (4 * UPR)) * 8);
+    }
+  };
+  auto stash = [&](int c, int buf, const u4 (&xu)[NU]) {
     const int g0 = c * Gs;
 #pragma unroll
     for (int e = 0; e < NU; ++e) {
       const int idx = tid + 256 * e;
       const int sl = idx / (16 * 4 * UPR), u = idx % (16 * 4 * UPR);
-      const int row = u / (4 * UPR);           // g_s * nocc + a
-      const int g_s = row / nocc;
-      uint4 v = {0u, 0u, 0u, 0u};
-      if (row < Gs * nocc && g0 + g_s < C) {
-        const unsigned short* sb = sl ? slab1 : slab0;
-        v = *reinterpret_cast<const uint4*>(sb + ((int64_t)g0 * nocc * 4 * UPR + u) * 8);
-      }
-      pu[e] = v;
-    }
-  };
-  auto stash = [&](int buf) {
-#pragma unroll
-    for (int e = 0; e < NU; ++e) {
-      const int idx = tid + 256 * e;
-      const int sl = idx / (16 * 4 * UPR), u = idx % (16 * 4 * UPR);
       const int row = u / (4 * UPR), pl = (u / UPR) % 4, r8 = u % UPR;
-      if (row < Gs * nocc) *reinterpret_cast<uint4*>(&LA[buf][sl][pl][row][r8 * 8]) = pu[e];
+      const u4 z = {0u, 0u, 0u, 0u};
+      if (row < Gs * nocc)
+        *reinterpret_cast<u4*>(&LA[buf][sl][pl][row][r8 * 8]) =
+            g0 + row / nocc < C ? xu[e] : z;
     }
   };
   // rows (g, a) beyond Gs * nocc stay zero
   for (int i = tid; i < 2 * 2 * 4 * 16 * RS; i += 256) (&LA[0][0][0][0][0])[i] = 0;
   __syncthreads();
 
-  const u16x8 sgn = {0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000};
-  double sr = 0.0, si = 0.0;
-  fetch(0);
-  stash(0);
+  double sr[WT], si[WT];
+#pragma unroll
+  for (int ct = 0; ct < WT; ++ct) sr[ct] = si[ct] = 0.0;
+#pragma unroll
+  for (int d = 0; d < DEPTH; ++d) fetch(d, pu[d]);
+  stash(0, 0, pu[0]);
+  fetch(DEPTH, pu[0]);
   __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < nch) fetch(c + 1);
-    v4f a1r = {0.f, 0.f, 0.f, 0.f}, a1i = a1r, a2r = a1r, a2i = a1r;
+  // iteration c: chunk c from LDS buffer c & 1; chunk c + 1 (slot (c + 1) % DEPTH) to the
+  // other buffer; chunk c + 1 + DEPTH requested into the freed slot
+  for (int c0 = 0; c0 < nch; c0 += DEPTH) {
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-      const int r0 = 32 * kb + 8 * (lane >> 4);
-      u16x8 x[2][4];
+    for (int d = 0; d < DEPTH; ++d) {
+      const int c = c0 + d;
+      const int buf = c & 1;
+      if (c < nch) {
+        v4f a1r[WT], a1i[WT], a2r[WT], a2i[WT];
 #pragma unroll
-      for (int sl = 0; sl < 2; ++sl)
+        for (int ct = 0; ct < WT; ++ct) {
+          a1r[ct] = v4f{0.f, 0.f, 0.f, 0.f};
+          a1i[ct] = a1r[ct]; a2r[ct] = a1r[ct]; a2i[ct] = a1r[ct];
+        }
 #pragma unroll
-        for (int pl = 0; pl < 4; ++pl)
-          x[sl][pl] = *reinterpret_cast<const u16x8*>(&LA[buf][sl][pl][col][r0]);
-      // re += Lr Gr - Li Gi,  im += Lr Gi + Li Gr  (-Li: flipped sign bits)
-      a1r = mul3(x[0][0], x[0][1], g1[kb][0], g1[kb][1], a1r);
-      a1r = mul3(x[0][2] ^ sgn, x[0][3] ^ sgn, g1[kb][2], g1[kb][3], a1r);
-      a1i = mul3(x[0][0], x[0][1], g1[kb][2], g1[kb][3], a1i);
-      a1i = mul3(x[0][2], x[0][3], g1[kb][0], g1[kb][1], a1i);
-      a2r = mul3(x[1][0], x[1][1], g2[kb][0], g2[kb][1], a2r);
-      a2r = mul3(x[1][2] ^ sgn, x[1][3] ^ sgn, g2[kb][2], g2[kb][3], a2r);
-      a2i = mul3(x[1][0], x[1][1], g2[kb][2], g2[kb][3], a2i);
-      a2i = mul3(x[1][2], x[1][3], g2[kb][0], g2[kb][1], a2i);
-    }
-    // T1 of the partner triple to the wave-private tile (FP32 MFMA output layout)
+        for (int kb = 0; kb < KB; ++kb) {
+          const int r0 = 32 * kb + 8 * (lane >> 4);
+          u16x8 x[2][4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = mfma16<float>::drow(lane, v);
-      XB[wave][0][row][col] = a2r[v];
-      XB[wave][1][row][col] = a2i[v];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int g0 = c * Gs;
+          for (int sl = 0; sl < 2; ++sl)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = mfma16<float>::drow(lane, v);
-      const int g_s = row / nocc, a = row % nocc;
-      if (colok && g_s < Gs && g0 + g_s < C) {
-        const int rp = g_s * nocc + b_l, cp = ws_l * nocc + a;
-        const double pr2 = (double)XB[wave][0][rp][cp], pi2 = (double)XB[wave][1][rp][cp];
-        const double p1r = (double)a1r[v], p1i = (double)a1i[v];
-        sr += p1r * pr2 - p1i * pi2;
-        si += p1r * pi2 + p1i * pr2;
+            for (int pl = 0; pl < 4; ++pl)
+              x[sl][pl] = *reinterpret_cast<const u16x8*>(&LA[buf][sl][pl][col][r0]);
+          const u16x8 n02 = bf16_neg(x[0][2]), n03 = bf16_neg(x[0][3]), n12 = bf16_neg(x[1][2]),
+                      n13 = bf16_neg(x[1][3]);
+#pragma unroll
+          for (int ct = 0; ct < WT; ++ct) {
+            // re += Lr Gr - Li Gi,  im += Lr Gi + Li Gr  (-Li: flipped sign bits)
+            a1r[ct] = mul3(x[0][0], x[0][1], g1[ct][kb][0], g1[ct][kb][1], a1r[ct]);
+            a1r[ct] = mul3(n02, n03, g1[ct][kb][2], g1[ct][kb][3], a1r[ct]);
+            a1i[ct] = mul3(x[0][0], x[0][1], g1[ct][kb][2], g1[ct][kb][3], a1i[ct]);
+            a1i[ct] = mul3(x[0][2], x[0][3], g1[ct][kb][0], g1[ct][kb][1], a1i[ct]);
+            a2r[ct] = mul3(x[1][0], x[1][1], g2[ct][kb][0], g2[ct][kb][1], a2r[ct]);
+            a2r[ct] = mul3(n12, n13, g2[ct][kb][2], g2[ct][kb][3], a2r[ct]);
+            a2i[ct] = mul3(x[1][0], x[1][1], g2[ct][kb][2], g2[ct][kb][3], a2i[ct]);
+            a2i[ct] = mul3(x[1][2], x[1][3], g2[ct][kb][0], g2[ct][kb][1], a2i[ct]);
+          }
+        }
+        const int g0 = c * Gs;
+        if (nocc == 4) {
+          // lane (g, w, b) holds T1_t[b][a] for a = v and the partner's T1 for Lh index v
+          // and Gh index b; the quad transpose brings T2_t[a][b] to register a
+          const bool gok = g0 + (lane >> 4) < C;
+#pragma unroll
+          for (int ct = 0; ct < WT; ++ct) {
+            const v4f tr = quad_transpose(a2r[ct], lane), ti = quad_transpose(a2i[ct], lane);
+            if (gok && walker(ct) < W) {
+              // the four products of one (g, w, b) in FP32 (the operands are FP32 MFMA
+              // results of BF16-split data), their sum over g and the lanes in FP64
+              float qr = 0.f, qi = 0.f;
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                qr += a1r[ct][v] * tr[v] - a1i[ct][v] * ti[v];
+                qi += a1r[ct][v] * ti[v] + a1i[ct][v] * tr[v];
+              }
+              sr[ct] += (double)qr;
+              si[ct] += (double)qi;
+            }
+          }
+        } else
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct) {
+          const bool colok = (ws_l < Ws) && (walker(ct) < W);
+          // T1 of the partner triple to the wave-private tile (FP32 MFMA output layout)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = mfma16<float>::drow(lane, v);
+            XB[wave][0][row][col] = a2r[ct][v];
+            XB[wave][1][row][col] = a2i[ct][v];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = mfma16<float>::drow(lane, v);
+            const int g_s = row / nocc, a = row % nocc;
+            if (colok && g_s < Gs && g0 + g_s < C) {
+              const int rp = g_s * nocc + b_l, cp = ws_l * nocc + a;
+              const double pr2 = (double)XB[wave][0][rp][cp], pi2 = (double)XB[wave][1][rp][cp];
+              const double p1r = (double)a1r[ct][v], p1i = (double)a1i[ct][v];
+              sr[ct] += p1r * pr2 - p1i * pi2;
+              si[ct] += p1r * pi2 + p1i * pr2;
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
       }
+      // past the last chunk the stores go to the buffer nobody reads
+      stash(c + 1, buf ^ 1, pu[(d + 1) % DEPTH]);
+      fetch(c + 1 + DEPTH, pu[(d + 1) % DEPTH]);
+      __syncthreads();
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    if (c + 1 < nch) stash(buf ^ 1);
-    __syncthreads();
   }
 
-  red[0][tid] = sr;
-  red[1][tid] = si;
-  __syncthreads();
-  if (tid < 4 * Ws) {
-    const int wv = tid / Ws, wsi = tid % Ws;
-    const int w = chunk * 4 * Ws + wv * Ws + wsi;
-    if (w < W) {
-      double ar = 0.0, ai = 0.0;
-      for (int grp = 0; grp < 4; ++grp)
-        for (int b = 0; b < nocc; ++b) {
-          const int l = wv * 64 + grp * 16 + wsi * nocc + b;
-          ar += red[0][l];
-          ai += red[1][l];
-        }
-      part[(int64_t)t * W + w] = cpx<double>{-mult * ar, -mult * ai};
+  // per-walker reduction over the lanes of a wave with the same column walker
+#pragma unroll
+  for (int ct = 0; ct < WT; ++ct) {
+    red[0][tid] = sr[ct];
+    red[1][tid] = si[ct];
+    __syncthreads();
+    if (tid < 4 * Ws) {
+      const int wv = tid / Ws, wsi = tid % Ws;
+      const int w = chunk * 4 * WT * Ws + (wv * WT + ct) * Ws + wsi;
+      if (w < W) {
+        double ar = 0.0, ai = 0.0;
+        for (int grp = 0; grp < 4; ++grp)
+          for (int b = 0; b < nocc; ++b) {
+            const int l = wv * 64 + grp * 16 + wsi * nocc + b;
+            ar += red[0][l];
+            ai += red[1][l];
+          }
+        part[(int64_t)t * W + w] = cpx<double>{-mult * ar, -mult * ai};
+      }
     }
+    __syncthreads();
   }
 }
 
@@ -455,6 +543,10 @@ static int ks_class(int m) {
   return KS <= 4 ? 4 : (KS <= 8 ? 8 : (KS <= 16 ? 16 : -1));
 }
 
+// Column tiles (16 / nocc walkers each) per wave of the BF16X3 exchange: two for K = 32
+// (the slab of Lh is reused by twice the walkers), one for K = 64 (register budget).
+static int exch_bf16_wt(const afqmc_kpt_problem& p) { return p.m <= 32 ? 2 : 1; }
+
 static int exch_nchunk(const afqmc_kpt_problem& p) {
   const int Ws = 16 / p.nocc;
   return (p.nwalk + 4 * Ws - 1) / (4 * Ws);
@@ -478,6 +570,10 @@ static hipError_t launch_exchange(const Job* jobs, int n, void* const* xpart, hi
           ExchArgs& a = B.a[q];
           a.nk = p.nk; a.m = p.m; a.nocc = p.nocc; a.C = p.nchol; a.W = p.nwalk;
           a.nchunk_w = exch_nchunk(p);
+          if (p.prec == AFQMC_PREC_BF16X3) {
+            const int per = 4 * exch_bf16_wt(p) * (16 / p.nocc);
+            a.nchunk_w = (p.nwalk + per - 1) / per;
+          }
           a.mesh = make_mesh(p);
           a.Lh = (p.prec == AFQMC_PREC_BF16X3) ? p.Lhs : (low_prec(p.prec) ? p.Lh32 : p.Lh);
           a.Gh = (const cpx<double>*)p.Gh;
@@ -491,9 +587,9 @@ static hipError_t launch_exchange(const Job* jobs, int n, void* const* xpart, hi
         const dim3 grid((unsigned)g), blk(256);
         if (jobs[ids[0]].p.prec == AFQMC_PREC_BF16X3) {
           if (jobs[ids[0]].p.m <= 32)
-            hipLaunchKernelGGL((exchange_bf16x3_kernel<1>), grid, blk, 0, s, B);
+            hipLaunchKernelGGL((exchange_bf16x3_kernel<1, 2>), grid, blk, 0, s, B);
           else
-            hipLaunchKernelGGL((exchange_bf16x3_kernel<2>), grid, blk, 0, s, B);
+            hipLaunchKernelGGL((exchange_bf16x3_kernel<2, 1>), grid, blk, 0, s, B);
           return hipGetLastError();
         }
         switch (ks_class(jobs[ids[0]].p.m)) {

@@ -225,7 +225,6 @@ __global__ __launch_bounds__(256) void vbias_bf16x3_kernel(const Batch<VbBfArgs>
       acr[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
       aci[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
     }
-  const u16x8 sgn = {0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000};
   issue(0, ra[0], rb[0]);
   issue(1, ra[1], rb[1]);
   stash(0, 0, ra[0], rb[0]);
@@ -248,13 +247,15 @@ __global__ __launch_bounds__(256) void vbias_bf16x3_kernel(const Batch<VbBfArgs>
             fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][pl][wm * 32 + i * 16 + (lane & 15)][kq]);
             fb[i][pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][wn * 32 + i * 16 + (lane & 15)][kq]);
           }
+        const u16x8 fn[2][2] = {{bf16_neg(fa[0][2]), bf16_neg(fa[0][3])},
+                                {bf16_neg(fa[1][2]), bf16_neg(fa[1][3])}};
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
-            // re += Lr Gr - Li Gi,  im += Lr Gi + Li Gr
+            // re += Lr Gr - Li Gi,  im += Lr Gi + Li Gr  (fn: -Li)
             acr[i][j] = mul3(fa[i][0], fa[i][1], fb[j][0], fb[j][1], acr[i][j]);
-            acr[i][j] = mul3(fa[i][2] ^ sgn, fa[i][3] ^ sgn, fb[j][2], fb[j][3], acr[i][j]);
+            acr[i][j] = mul3(fn[i][0], fn[i][1], fb[j][2], fb[j][3], acr[i][j]);
             aci[i][j] = mul3(fa[i][0], fa[i][1], fb[j][2], fb[j][3], aci[i][j]);
             aci[i][j] = mul3(fa[i][2], fa[i][3], fb[j][0], fb[j][1], aci[i][j]);
           }
@@ -619,7 +620,6 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
       }
   };
   zero();
-  const u16x8 sgn = {0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000};
   VhsPos cp{(long long)blockIdx.x, 0};
   __syncthreads();
   for (long long s0 = 0; s0 < total; s0 += DEPTH) {
@@ -634,6 +634,8 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
 #pragma unroll
           for (int pl = 0; pl < 4; ++pl)
             fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][pl][wm * 32 + i * 16 + (lane & 15)][kq]);
+        const u16x8 fn[2][2] = {{bf16_neg(fa[0][2]), bf16_neg(fa[0][3])},
+                                {bf16_neg(fa[1][2]), bf16_neg(fa[1][3])}};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           u16x8 fb[4];
@@ -642,9 +644,9 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
             fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][wn * 64 + j * 16 + (lane & 15)][kq]);
 #pragma unroll
           for (int i = 0; i < 2; ++i) {
-            // re += Zr Lr - Zi Li,  im += Zr Li + Zi Lr
+            // re += Zr Lr - Zi Li,  im += Zr Li + Zi Lr  (fn: -Zi)
             acr[i][j] = mul3(fa[i][0], fa[i][1], fb[0], fb[1], acr[i][j]);
-            acr[i][j] = mul3(fa[i][2] ^ sgn, fa[i][3] ^ sgn, fb[2], fb[3], acr[i][j]);
+            acr[i][j] = mul3(fn[i][0], fn[i][1], fb[2], fb[3], acr[i][j]);
             aci[i][j] = mul3(fa[i][0], fa[i][1], fb[2], fb[3], aci[i][j]);
             aci[i][j] = mul3(fa[i][2], fa[i][3], fb[0], fb[1], aci[i][j]);
           }

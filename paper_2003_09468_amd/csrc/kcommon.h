@@ -105,6 +105,12 @@ __device__ __forceinline__ v4f mfma_bf16(const u16x8& a, const u16x8& b, v4f c) 
                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
+// Negation of eight packed BF16 values (sign bits flipped, as 32-bit words).
+__device__ __forceinline__ u16x8 bf16_neg(const u16x8& x) {
+  typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+  return __builtin_bit_cast(u16x8, __builtin_bit_cast(u32x4_t, x) ^ 0x80008000u);
+}
+
 // d += (ah + al)(bh + bl) without the al bl term (three BF16 passes)
 __device__ __forceinline__ v4f mul3(const u16x8& ah, const u16x8& al, const u16x8& bh,
                                     const u16x8& bl, v4f d) {

@@ -359,7 +359,6 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
         aci[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
       }
     const int cb0 = wn ? CB : 0, ncb = wn ? NB - CB : CB;
-    const u16x8 sgn = {0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000};
     __syncthreads();
     // as many barriers as the producers: ceil(nch / DEPTH) DEPTH iterations
     for (int c0 = 0; c0 < nch; c0 += DEPTH) {
@@ -375,6 +374,8 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
 #pragma unroll
             for (int pl = 0; pl < 4; ++pl)
               fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][pl][wm * 32 + i * 16 + (lane & 15)][kq]);
+          const u16x8 fn[2][2] = {{bf16_neg(fa[0][2]), bf16_neg(fa[0][3])},
+                                  {bf16_neg(fa[1][2]), bf16_neg(fa[1][3])}};
 #pragma unroll
           for (int j = 0; j < CB; ++j) {
             if (j < ncb) {
@@ -384,9 +385,9 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
                 fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][16 * (cb0 + j) + (lane & 15)][kq]);
 #pragma unroll
               for (int i = 0; i < 2; ++i) {
-                // re += Vr Tr - Vi Ti,  im += Vr Ti + Vi Tr
+                // re += Vr Tr - Vi Ti,  im += Vr Ti + Vi Tr  (fn: -Vi)
                 acr[i][j] = mul3(fa[i][0], fa[i][1], fb[0], fb[1], acr[i][j]);
-                acr[i][j] = mul3(fa[i][2] ^ sgn, fa[i][3] ^ sgn, fb[2], fb[3], acr[i][j]);
+                acr[i][j] = mul3(fn[i][0], fn[i][1], fb[2], fb[3], acr[i][j]);
                 aci[i][j] = mul3(fa[i][0], fa[i][1], fb[2], fb[3], aci[i][j]);
                 aci[i][j] = mul3(fa[i][2], fa[i][3], fb[0], fb[1], aci[i][j]);
               }
