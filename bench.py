@@ -264,13 +264,22 @@ def bench_path(name, p, U0d, xs, args, torch, cfg):
     for _ in range(args.warmup):
         run_block(p, xs, bufs, E)
     torch.cuda.synchronize()
-    lib.timing_enable(True, 1 << 16)
-    torch.cuda.synchronize()
+    # throughput: no per-kernel events in the timed blocks (two event records per launch
+    # cost about 2 ms per block)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         run_block(p, xs, bufs, E)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # per-kernel durations: the same blocks again, each launch bracketed by HIP events on
+    # its stream
+    lib.timing_enable(True, 1 << 16)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        run_block(p, xs, bufs, E)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
     lib.timing_enable(False)
     kern = {}
     for kc in lib.KERNEL_CLASSES:
@@ -280,11 +289,13 @@ def bench_path(name, p, U0d, xs, args, torch, cfg):
                         "ms_per_launch": ms / n}
     dt = (t1 - t0) / args.steps
     ws = W * xs.shape[0] / dt
-    log(f"[{name}] block {dt * 1e3:.2f} ms  -> {ws:.1f} walker-steps/s")
+    log(f"[{name}] block {dt * 1e3:.2f} ms  -> {ws:.1f} walker-steps/s "
+        f"(with per-kernel events {(t3 - t2) / args.steps * 1e3:.2f} ms)")
     for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms_total"]):
         log(f"    {k:13s} {v['ms_total']:9.3f} ms/block  {v['launches']:4d} launches  "
             f"{v['ms_per_launch']:.4f} ms/launch")
-    return {"ms_per_block": dt * 1e3, "walker_steps_per_s": ws, "kernels": kern}, E0, w0
+    return {"ms_per_block": dt * 1e3, "walker_steps_per_s": ws, "kernels": kern,
+            "ms_per_block_with_kernel_events": (t3 - t2) / args.steps * 1e3}, E0, w0
 
 
 def roofline(path_res, prec_key, cfg):
@@ -765,6 +776,8 @@ def main():
         "roofline": roofline(main_res, use, cfg),
         "paths": {k: {"walker_steps_per_s": round(v["walker_steps_per_s"], 2),
                       "ms_per_block": round(v["ms_per_block"], 3),
+                      "ms_per_block_with_kernel_events":
+                          round(v["ms_per_block_with_kernel_events"], 3),
                       "energy_evals_per_s": energy_evals(v, cfg),
                       "kernels": {kk: {"ms_per_block": round(vv["ms_total"], 4),
                                        "launches": vv["launches"],

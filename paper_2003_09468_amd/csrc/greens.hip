@@ -3,14 +3,12 @@
 // Green's-function equations of the standard representation, blocked by the trial's
 // k structure: O = A^H U (nk*nocc square), log det O, Gh = (U O^{-1})^T.
 //
-// The (nk*nocc)^2 overlap matrix (108^2 complex128 = 187 KB for a 3x3x3 mesh with
-// 4 occupied bands) does not fit the 160 KB LDS, so one 1024-thread workgroup per walker
-// keeps it in registers: thread (tr, tc) of a 32 x 32 grid owns rows tr + 32 i and
-// columns tc + 32 j.  Gauss-Jordan elimination with partial (row) pivoting inverts it in
-// place, exchanging only the pivot column and two rows per step through LDS; the log
-// determinant is the sum of the pivot logarithms plus i*pi per row swap.  The same engine
-// factorises the Gram matrix of the re-orthonormalisation (Cholesky, then inversion of
-// the triangular factor).  The solve Gh = O^{-T} U^T is a batched MFMA GEMM.
+// The overlap O is a batched MFMA GEMM over (walker, k); its inverse and log determinant
+// come from a Gauss-Jordan elimination with implicit row pivoting, one workgroup per
+// walker: register-resident on FP64 MFMA tiles for nk*nocc <= 112, L2-resident in panels
+// of 16 up to 256.  The solve Gh = O^{-T} U^T is a batched MFMA GEMM.  The Cholesky factor
+// of the re-orthonormalisation's Gram matrix and the inverse of that factor are formed
+// in LDS (nk*nocc <= 128) or L2-resident, one workgroup per walker.
 #include <math.h>
 
 #include "cgemm.h"
@@ -19,291 +17,6 @@
 namespace afqmc {
 
 #define AFQMC_PI 3.14159265358979323846
-
-// Thread (tr, tc) of a TR x 32 grid owns rows tr + TR*si (si < NSR) and columns
-// tc + 32*sj (sj < NSC); n <= min(TR*NSR, 32*NSC).
-template <int NSR, int NSC>
-__device__ __forceinline__ double pick_col(const double (&a)[NSR][NSC], int si, int sj) {
-  double v = 0.0;
-#pragma unroll
-  for (int y = 0; y < NSC; ++y)
-    if (y == sj) v = a[si][y];
-  return v;
-}
-
-// Arguments of one problem: n x n matrices of nwalk walkers.
-struct GjArgs {
-  int n;
-  const cpx<double>* S;  // [W][n][n]
-  cpx<double>* out;      // [W][n][n]
-  cpx<double>* logdet;   // [W] (GREENS mode)
-  int* status;           // [W]
-};
-
-// One workgroup per walker of every problem of the batch.
-template <int TR, int NSR, int NSC>
-__global__ __launch_bounds__(TR * 32) void small_gj_kernel(int mode, const Batch<GjArgs> B) {
-  long long wloc;
-  const int pb = batch_find(B, blockIdx.x, wloc);
-  const int n = B.a[pb].n;
-  const cpx<double>* __restrict__ S_in = B.a[pb].S;
-  cpx<double>* __restrict__ out = B.a[pb].out;
-  cpx<double>* __restrict__ logdet_out = B.a[pb].logdet;
-  int* __restrict__ status = B.a[pb].status;
-  const int w = (int)wloc;
-  const int tid = threadIdx.x;
-  const int tr = tid >> 5, tc = tid & 31;
-  const int lane = tid & 63;
-
-  __shared__ double colr[2][128], coli[2][128];
-  __shared__ double rowr[2][128], rowi[2][128];
-  __shared__ double rjr[2][128], rji[2][128];
-  __shared__ int perm[128];
-  __shared__ int cols[128], pos[128];
-  __shared__ double pivr_s[128], pivi_s[128];
-  __shared__ double red_s[2][16];
-  __shared__ int flag_s;
-
-  double re[NSR][NSC], im[NSR][NSC];
-
-  if (tid == 0) flag_s = 0;
-  {
-    const cpx<double>* Sw = S_in + (int64_t)w * n * n;
-#pragma unroll
-    for (int si = 0; si < NSR; ++si)
-#pragma unroll
-      for (int sj = 0; sj < NSC; ++sj) {
-        const int row = tr + TR * si, col = tc + 32 * sj;
-        cpx<double> v{0.0, 0.0};
-        if (row < n && col < n) v = Sw[(int64_t)row * n + col];
-        re[si][sj] = v.re;
-        im[si][sj] = v.im;
-      }
-  }
-  __syncthreads();
-
-  int bad = 0;  // 1: zero pivot, 2: non-finite
-
-  // ---- Cholesky S = L L^H (lower), in place, for the re-orthonormalisation
-  if (mode == GJ_MODE_CHOL_INV) {
-    for (int j = 0; j < n; ++j) {
-      const int buf = j & 1, js = j >> 5, jl = j & 31;
-      if (tc == jl) {
-#pragma unroll
-        for (int si = 0; si < NSR; ++si) {
-          const int row = tr + TR * si;
-          if (row < n) {
-            colr[buf][row] = pick_col<NSR, NSC>(re, si, js);
-            coli[buf][row] = pick_col<NSR, NSC>(im, si, js);
-          }
-        }
-      }
-      __syncthreads();
-      double d = colr[buf][j];
-      if (!(d > 0.0) || !isfinite(d)) {
-        bad |= isfinite(d) ? 1 : 2;
-        d = 1.0;
-      }
-      const double sd = sqrt(d), isd = 1.0 / sd;
-#pragma unroll
-      for (int si = 0; si < NSR; ++si)
-#pragma unroll
-        for (int sj = 0; sj < NSC; ++sj) {
-          const int row = tr + TR * si, col = tc + 32 * sj;
-          if (row >= n || col >= n || row < j || col < j) continue;
-          if (col == j) {
-            if (row == j) { re[si][sj] = sd; im[si][sj] = 0.0; }
-            else { re[si][sj] = colr[buf][row] * isd; im[si][sj] = coli[buf][row] * isd; }
-          } else if (row == j) {
-            re[si][sj] = 0.0; im[si][sj] = 0.0;  // upper part of the factor
-          } else {
-            // S[row][col] -= l_row conj(l_col), l = S[:, j] / sqrt(S[j][j])
-            const double ar = colr[buf][row] * isd, ai = coli[buf][row] * isd;
-            const double br = colr[buf][col] * isd, bi = coli[buf][col] * isd;
-            re[si][sj] -= ar * br + ai * bi;
-            im[si][sj] -= ai * br - ar * bi;
-          }
-        }
-    }
-    __syncthreads();
-  }
-
-  // ---- Gauss-Jordan inversion with partial pivoting, in place.
-  // Step j: the pivot column goes to LDS; every wave finds the pivot row p (largest
-  // modulus among rows >= j, lowest index on ties) with one 64-bit max-reduction of
-  // (|a|^2 bits, 127 - row); rows j and p go to LDS; then every owned entry takes the
-  // rank-1 update  a' = a~ - g(row) b(col)  with
-  //   b(col) = (col == j) ? 1 : a_pj,  g(row) = a_rowj / pivot  (row != j),  -1/pivot (row j),
-  //   a~ = 0 in column j and in row j, the old row j in row p, else a.
-  // Pivots are kept in LDS; their logarithms are summed after the loop.
-  for (int j = 0; j < n; ++j) {
-    const int buf = j & 1, js = j >> 5, jl = j & 31;
-    if (tc == jl) {
-#pragma unroll
-      for (int si = 0; si < NSR; ++si) {
-        const int row = tr + TR * si;
-        if (row < n) {
-          colr[buf][row] = pick_col<NSR, NSC>(re, si, js);
-          coli[buf][row] = pick_col<NSR, NSC>(im, si, js);
-        }
-      }
-    }
-    __syncthreads();
-    unsigned long long key = 0ull;
-    for (int i = j + lane; i < n; i += 64) {
-      const double v = colr[buf][i] * colr[buf][i] + coli[buf][i] * coli[buf][i];
-      const unsigned long long k2 =
-          ((unsigned long long)__double_as_longlong(v) & ~0x7full) | (unsigned long long)(127 - i);
-      key = (k2 > key) ? k2 : key;
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const unsigned long long o = __shfl_xor(key, off, 64);
-      key = (o > key) ? o : key;
-    }
-    const int p = (key == 0ull) ? j : 127 - (int)(key & 0x7full);
-    if (tr == p % TR) {
-      const int ps = p / TR;
-#pragma unroll
-      for (int sj = 0; sj < NSC; ++sj) {
-        const int col = tc + 32 * sj;
-        if (col < n) {
-          double vr = 0.0, vi = 0.0;
-#pragma unroll
-          for (int si = 0; si < NSR; ++si)
-            if (si == ps) { vr = re[si][sj]; vi = im[si][sj]; }
-          rowr[buf][col] = vr;
-          rowi[buf][col] = vi;
-        }
-      }
-    }
-    if (tr == j % TR && p != j) {
-      const int jsr = j / TR;
-#pragma unroll
-      for (int sj = 0; sj < NSC; ++sj) {
-        const int col = tc + 32 * sj;
-        if (col < n) {
-          double vr = 0.0, vi = 0.0;
-#pragma unroll
-          for (int si = 0; si < NSR; ++si)
-            if (si == jsr) { vr = re[si][sj]; vi = im[si][sj]; }
-          rjr[buf][col] = vr;
-          rji[buf][col] = vi;
-        }
-      }
-    }
-    __syncthreads();
-    double pr = rowr[buf][j], pim = rowi[buf][j];
-    double den = pr * pr + pim * pim;
-    if (!(den > 0.0) || !isfinite(den)) {
-      bad |= isfinite(den) ? 1 : 2;
-      pr = 1.0; pim = 0.0; den = 1.0;
-    }
-    const double ivr = pr / den, ivi = -pim / den;  // 1 / pivot
-    if (tid == 0) {
-      perm[j] = p;
-      pivr_s[j] = pr;
-      pivi_s[j] = pim;
-    }
-    // per-column factor b(col)
-    double br_[NSC], bi_[NSC];
-#pragma unroll
-    for (int sj = 0; sj < NSC; ++sj) {
-      const int col = tc + 32 * sj;
-      const bool cj = (col == j);
-      br_[sj] = cj ? 1.0 : ((col < n) ? rowr[buf][col] : 0.0);
-      bi_[sj] = cj ? 0.0 : ((col < n) ? rowi[buf][col] : 0.0);
-    }
-#pragma unroll
-    for (int si = 0; si < NSR; ++si) {
-      const int row = tr + TR * si;
-      if (row >= n) continue;
-      const bool isj = (row == j);
-      const bool swapped = (row == p) && (p != j);
-      double gr, gi;
-      if (isj) {
-        gr = -ivr; gi = -ivi;
-      } else {
-        const double fr = swapped ? colr[buf][j] : colr[buf][row];
-        const double fi = swapped ? coli[buf][j] : coli[buf][row];
-        gr = fr * ivr - fi * ivi;
-        gi = fr * ivi + fi * ivr;
-      }
-#pragma unroll
-      for (int sj = 0; sj < NSC; ++sj) {
-        const int col = tc + 32 * sj;
-        double ar = swapped ? ((col < n) ? rjr[buf][col] : 0.0) : re[si][sj];
-        double ai = swapped ? ((col < n) ? rji[buf][col] : 0.0) : im[si][sj];
-        if (isj || col == j) { ar = 0.0; ai = 0.0; }
-        re[si][sj] = ar - (gr * br_[sj] - gi * bi_[sj]);
-        im[si][sj] = ai - (gr * bi_[sj] + gi * br_[sj]);
-      }
-    }
-  }
-  if (bad) atomicOr(&flag_s, bad);
-  __syncthreads();
-  // log det = sum log(pivot) + i pi (number of row swaps)
-  {
-    double lr = 0.0, li = 0.0;
-    for (int j = tid; j < n; j += TR * 32) {
-      const double pr = pivr_s[j], pim = pivi_s[j];
-      lr += 0.5 * log(pr * pr + pim * pim);
-      li += atan2(pim, pr) + ((perm[j] != j) ? AFQMC_PI : 0.0);
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      lr += __shfl_xor(lr, off, 64);
-      li += __shfl_xor(li, off, 64);
-    }
-    if (lane == 0) { red_s[0][tid >> 6] = lr; red_s[1][tid >> 6] = li; }
-  }
-  __syncthreads();
-  if (tid == 0) {
-    for (int c = 0; c < n; ++c) cols[c] = c;
-    for (int j = n - 1; j >= 0; --j) {
-      const int p = perm[j];
-      const int t = cols[j]; cols[j] = cols[p]; cols[p] = t;
-    }
-    for (int c = 0; c < n; ++c) pos[cols[c]] = c;
-  }
-  __syncthreads();
-  const int fl = flag_s;
-  double ldr = 0.0, ldi = 0.0;
-  for (int wv = 0; wv < TR / 2; ++wv) { ldr += red_s[0][wv]; ldi += red_s[1][wv]; }
-
-  // ---- write out: the inverse's column c sits in working column cols[c]
-  cpx<double>* Ow = out + (int64_t)w * n * n;
-#pragma unroll
-  for (int si = 0; si < NSR; ++si)
-#pragma unroll
-    for (int sj = 0; sj < NSC; ++sj) {
-      const int row = tr + TR * si, col = tc + 32 * sj;
-      if (row >= n || col >= n) continue;
-      const int c = pos[col];
-      double vr = re[si][sj], vi = im[si][sj];
-      if (mode == GJ_MODE_CHOL_INV) vi = -vi;  // R^{-1} = (L^{-1})^H
-      if (fl) {
-        // degenerate walker: Gh = 0 / leave U unchanged (identity R^{-1})
-        vr = (mode == GJ_MODE_CHOL_INV && c == row) ? 1.0 : 0.0;
-        vi = 0.0;
-      }
-      // GREENS: out[c][row] = Oinv[row][c] (O^{-T});  CHOL_INV: out[c][row] = Rinv[c][row]
-      Ow[(int64_t)c * n + row] = cpx<double>{vr, vi};
-    }
-  if (tid == 0) {
-    if (mode == GJ_MODE_GREENS) {
-      double wi = remainder(ldi, 2.0 * AFQMC_PI);
-      if (wi <= -AFQMC_PI) wi += 2.0 * AFQMC_PI;
-      logdet_out[w] = fl ? cpx<double>{0.0, 0.0} : cpx<double>{ldr, wi};
-    }
-    if (fl) {
-      int bits = 0;
-      if (fl & 1) bits |= AFQMC_WALKER_SINGULAR;
-      if (fl & 2) bits |= AFQMC_WALKER_NONFINITE;
-      status[w] |= bits;
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Blocked Gauss-Jordan inversion of the overlap matrix for n <= 256: one 256-thread
@@ -983,6 +696,110 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const Batch<CholArgs> B) 
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same for n <= 128 with the lower triangle in LDS (n (n + 1) / 2 complex entries,
+// 132 KB at n = 128), one 256-thread workgroup per walker.  Cholesky column j
+// (left-looking): thread r >= j forms t_r = S[r][j] - sum_{k<j} L[r][k] conj(L[j][k]) from
+// LDS.  Then the factor is inverted in place, column by column from the last: with
+// X = L^{-1}, X L = I gives X[i][j] = -(sum_{k=j+1}^{i} X[i][k] L[k][j]) / L[j][j] (i > j),
+// which needs only the columns of X to the right of j and column j of L.  Output as the
+// L2 version: out[c][i] = conj(X[i][c]), the rows of R^{-1} = X^H.
+__device__ __forceinline__ int tri(int r, int k) { return r * (r + 1) / 2 + k; }
+
+__global__ __launch_bounds__(256) void chol_inv_lds_kernel(const Batch<CholArgs> B) {
+  constexpr int NMAX = 128;
+  __shared__ cpx<double> T[NMAX * (NMAX + 1) / 2];
+  __shared__ double diag[NMAX];
+  __shared__ int flag_s;
+  long long wloc;
+  const int pb = batch_find(B, blockIdx.x, wloc);
+  const int n = B.a[pb].n;
+  const int w = (int)wloc;
+  const cpx<double>* __restrict__ S = B.a[pb].S + (int64_t)w * n * n;
+  cpx<double>* __restrict__ out = B.a[pb].out + (int64_t)w * n * n;
+  const int tid = threadIdx.x;
+  if (tid == 0) flag_s = 0;
+  for (int e = tid; e < n * n; e += 256) {
+    const int r = e / n, k = e % n;
+    if (k <= r) T[tri(r, k)] = S[e];
+  }
+  __syncthreads();
+  int bad = 0;  // 1: non-positive pivot, 2: non-finite
+  for (int j = 0; j < n; ++j) {
+    const int r = tid;
+    double tr = 0.0, ti = 0.0;
+    if (r >= j && r < n) {
+      const cpx<double>* Lr = T + tri(r, 0);
+      const cpx<double>* Lj = T + tri(j, 0);
+      tr = Lr[j].re;
+      ti = Lr[j].im;
+#pragma unroll 4
+      for (int k = 0; k < j; ++k) {
+        const cpx<double> a = Lr[k], b = Lj[k];
+        tr -= a.re * b.re + a.im * b.im;
+        ti -= a.im * b.re - a.re * b.im;
+      }
+    }
+    if (r == j) {
+      double d = tr;
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad |= isfinite(d) ? 1 : 2;
+        d = 1.0;
+      }
+      diag[j] = sqrt(d);
+    }
+    __syncthreads();
+    if (r >= j && r < n) {
+      const double sd = diag[j];
+      T[tri(r, j)] = (r == j) ? cpx<double>{sd, 0.0} : cpx<double>{tr / sd, ti / sd};
+    }
+    __syncthreads();
+  }
+  if (bad) atomicOr(&flag_s, bad);
+  __syncthreads();
+  const int fl = flag_s;
+  if (!fl) {
+    for (int j = n - 1; j >= 0; --j) {
+      const int i = tid;
+      double xr = 0.0, xi = 0.0;
+      if (i > j && i < n) {
+        const cpx<double>* Xi = T + tri(i, 0);
+#pragma unroll 4
+        for (int k = j + 1; k <= i; ++k) {
+          const cpx<double> x = Xi[k], l = T[tri(k, j)];  // X[i][k] L[k][j]
+          xr += x.re * l.re - x.im * l.im;
+          xi += x.re * l.im + x.im * l.re;
+        }
+        const double id = 1.0 / diag[j];
+        xr *= -id;
+        xi *= -id;
+      }
+      __syncthreads();
+      if (i > j && i < n) T[tri(i, j)] = cpx<double>{xr, xi};
+      if (i == j) T[tri(j, j)] = cpx<double>{1.0 / diag[j], 0.0};
+      __syncthreads();
+    }
+  }
+  // out[c][i] = conj(X[i][c]) for i >= c, 0 below; identity for a flagged walker
+  for (int e = tid; e < n * n; e += 256) {
+    const int c = e / n, i = e % n;
+    cpx<double> v{0.0, 0.0};
+    if (fl) {
+      v.re = (i == c) ? 1.0 : 0.0;
+    } else if (i >= c) {
+      const cpx<double> x = T[tri(i, c)];
+      v = cpx<double>{x.re, -x.im};
+    }
+    out[e] = v;
+  }
+  if (tid == 0 && fl) {
+    int bits = 0;
+    if (fl & 1) bits |= AFQMC_WALKER_SINGULAR;
+    if (fl & 2) bits |= AFQMC_WALKER_NONFINITE;
+    B.a[pb].status[w] |= bits;
+  }
+}
+
 static hipError_t launch_chol_inv(const Job* jobs, const int* ids, int c, void* const* S,
                                   void* const* out, hipStream_t s) {
   Batch<CholArgs> B;
@@ -1000,59 +817,20 @@ static hipError_t launch_chol_inv(const Job* jobs, const int* ids, int c, void* 
   const long long g = batch_close(B, cnt);
   if (g < 0) return hipErrorInvalidValue;
   if (g == 0) return hipSuccess;
-  hipLaunchKernelGGL(chol_inv_kernel, dim3((unsigned)g), dim3(256), 0, s, B);
+  if (B.a[0].n <= 128)
+    hipLaunchKernelGGL(chol_inv_lds_kernel, dim3((unsigned)g), dim3(256), 0, s, B);
+  else
+    hipLaunchKernelGGL(chol_inv_kernel, dim3((unsigned)g), dim3(256), 0, s, B);
   return hipGetLastError();
 }
 
-// Size class of the register-resident elimination for n (0..3), -1 if too large.
-static int gj_class(int n) {
-  if (n <= 32) return 0;
-  if (n <= 64) return 1;
-  if (n <= 96) return 2;
-  if (n <= 128) return 3;
-  return -1;
-}
-
-hipError_t launch_small_gj(const Job* jobs, int n, int mode, void* const* S_in,
-                           void* const* out, void* const* logdet_out, hipStream_t s) {
+// Cholesky factor and R^{-1} of the Gram matrices S[j] of every job (out[j]), the
+// LDS-resident kernel for nk*nocc <= 128, the L2-resident one above.
+hipError_t launch_ortho_factor(const Job* jobs, int n, void* const* S, void* const* out,
+                               hipStream_t s) {
   return for_groups(
-      n, [&](int i) { return gj_class(jobs[i].p.nk * jobs[i].p.nocc); },
-      [&](const int* ids, int c) -> hipError_t {
-        Batch<GjArgs> B;
-        B.nprob = c;
-        long long cnt[AFQMC_MAXP];
-        for (int q = 0; q < c; ++q) {
-          const afqmc_kpt_problem& p = jobs[ids[q]].p;
-          B.a[q].n = p.nk * p.nocc;
-          B.a[q].S = (const cpx<double>*)S_in[ids[q]];
-          B.a[q].out = (cpx<double>*)out[ids[q]];
-          B.a[q].logdet = logdet_out ? (cpx<double>*)logdet_out[ids[q]] : nullptr;
-          B.a[q].status = p.status;
-          cnt[q] = p.nwalk;
-        }
-        const long long g = batch_close(B, cnt);
-        if (g < 0) return hipErrorInvalidValue;
-        if (g == 0) return hipSuccess;
-        if (mode == GJ_MODE_CHOL_INV)
-          return launch_chol_inv(jobs, ids, c, S_in, out, s);
-        switch (gj_class(B.a[0].n)) {
-          case 0:
-            hipLaunchKernelGGL((small_gj_kernel<32, 1, 1>), dim3((unsigned)g), dim3(1024), 0, s, mode, B);
-            break;
-          case 1:
-            hipLaunchKernelGGL((small_gj_kernel<32, 2, 2>), dim3((unsigned)g), dim3(1024), 0, s, mode, B);
-            break;
-          case 2:
-            hipLaunchKernelGGL((small_gj_kernel<16, 6, 3>), dim3((unsigned)g), dim3(512), 0, s, mode, B);
-            break;
-          case 3:
-            hipLaunchKernelGGL((small_gj_kernel<16, 8, 4>), dim3((unsigned)g), dim3(512), 0, s, mode, B);
-            break;
-          default:
-            return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-      });
+      n, [&](int i) { return jobs[i].p.nk * jobs[i].p.nocc <= 128 ? 0 : 1; },
+      [&](const int* ids, int c) { return launch_chol_inv(jobs, ids, c, S, out, s); });
 }
 
 // Gh[w][i][R] = sum_j OinvT[w][i][j] U[w][R][j]

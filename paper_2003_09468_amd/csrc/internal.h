@@ -106,12 +106,10 @@ hipError_t run_mixed_energy(const Job* jobs, int n, void* Emix, hipStream_t s);
 
 // Kernels shared across translation units.  launch_cholesky_trace writes X (and xbar when
 // requested) of every job; parts are the per-job split-K slices.
-hipError_t launch_small_gj(const Job* jobs, int n, int mode, void* const* S_in,
-                           void* const* out, void* const* logdet_out, hipStream_t s);
+hipError_t launch_ortho_factor(const Job* jobs, int n, void* const* S, void* const* out,
+                               hipStream_t s);
 hipError_t launch_cholesky_trace(const Job* jobs, int n, void* const* X, void* const* xbar,
                                  void* const* parts, hipStream_t s);
-
-enum { GJ_MODE_GREENS = 0, GJ_MODE_CHOL_INV = 1 };
 
 // Autotuned tile shapes of the large contractions.  A stage's candidates are numbered
 // from 0 (the built-in default); the cache maps (stage, precision, shapes of the batch) to

@@ -787,7 +787,7 @@ hipError_t run_ortho(const Job* jobs, int n, hipStream_t s) {
       }
       hipError_t e = launch_ops<32, 32, 16, 2, 2>(gm, c, s);
       if (e != hipSuccess) return e;
-      e = launch_small_gj(J, c, GJ_MODE_CHOL_INV, S, R, nullptr, s);
+      e = launch_ortho_factor(J, c, S, R, s);
       if (e != hipSuccess) return e;
       e = launch_ops<64, 64, 16, 2, 2>(rm, c, s);
       if (e != hipSuccess) return e;
