@@ -512,28 +512,37 @@ __global__ __launch_bounds__(512) void gj_reg_kernel(const Batch<GjbArgs> B) {
         }
       }
     }
-  } else if (lane == 0) {
+  } else {
+    // log det = sum_j log(pivot_j) + i pi [sign of j -> q_j]: the logarithms by the lanes
+    // of wave 0, the permutation's cycles by lane 0
     double lr = 0.0, li = 0.0;
-    for (int j = 0; j < n; ++j) {
+    for (int j = lane; j < n; j += 64) {
       lr += 0.5 * log(pvr[j] * pvr[j] + pvi[j] * pvi[j]);
       li += atan2(pvi[j], pvr[j]);
       vis[j] = 0;
     }
-    int cycles = 0;
-    for (int j = 0; j < n; ++j) {
-      if (vis[j]) continue;
-      ++cycles;
-      for (int x = j; !vis[x]; x = qs[x]) vis[x] = 1;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      lr += __shfl_xor(lr, off, 64);
+      li += __shfl_xor(li, off, 64);
     }
-    if ((n - cycles) & 1) li += AFQMC_PI;
-    double wi = remainder(li, 2.0 * AFQMC_PI);
-    if (wi <= -AFQMC_PI) wi += 2.0 * AFQMC_PI;
-    B.a[pb].logdet[w] = fl ? cpx<double>{0.0, 0.0} : cpx<double>{lr, wi};
-    if (fl) {
-      int bits = 0;
-      if (fl & 1) bits |= AFQMC_WALKER_SINGULAR;
-      if (fl & 2) bits |= AFQMC_WALKER_NONFINITE;
-      B.a[pb].status[w] |= bits;
+    if (lane == 0) {
+      int cycles = 0;
+      for (int j = 0; j < n; ++j) {
+        if (vis[j]) continue;
+        ++cycles;
+        for (int x = j; !vis[x]; x = qs[x]) vis[x] = 1;
+      }
+      if ((n - cycles) & 1) li += AFQMC_PI;
+      double wi = remainder(li, 2.0 * AFQMC_PI);
+      if (wi <= -AFQMC_PI) wi += 2.0 * AFQMC_PI;
+      B.a[pb].logdet[w] = fl ? cpx<double>{0.0, 0.0} : cpx<double>{lr, wi};
+      if (fl) {
+        int bits = 0;
+        if (fl & 1) bits |= AFQMC_WALKER_SINGULAR;
+        if (fl & 2) bits |= AFQMC_WALKER_NONFINITE;
+        B.a[pb].status[w] |= bits;
+      }
     }
   }
 }
