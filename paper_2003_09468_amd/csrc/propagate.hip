@@ -224,11 +224,11 @@ static hipError_t launch_t_split(const Job* jobs, const int* ids, int c, void* c
 }
 
 // One step, R_{j-1} = T_0 + alpha vhs R_j, one 512-thread workgroup per (walker,
-// 64-row tile, column tile of 16 NB columns).  Waves 4-7 produce: they stream the
+// BM-row tile (64 or 96), column tile of 16 NB columns).  Waves 4-7 produce: they stream the
 // complex64 rows of vhs (from HBM) with DEPTH chunks of K in flight in registers and split
 // them into BF16 planes, and copy the chunk's R_j planes (from L2), into two LDS
-// stages.  Waves 0-3 consume, in 2 x 2: wave (wm, wn) owns rows 32 wm .. 32 wm + 31 and
-// the first ceil(NB / 2) (wn = 0) or the remaining (wn = 1) 16-column blocks, with 12 BF16
+// stages.  Waves 0-3 consume, in 2 x 2: wave (wm, wn) owns rows BM/2 wm .. BM/2 (wm + 1) - 1
+// and the first ceil(NB / 2) (wn = 0) or the remaining (wn = 1) 16-column blocks, with 12 BF16
 // MFMAs per complex 16 x 16 x 32 block and FP32 accumulation.  One block barrier per K
 // chunk.  In the epilogue the consumers leave alpha (vhs R_j) in LDS (over the stages)
 // and all eight waves add T_0 to it: from complex64 into the planes of R_{j-1}, or, in
@@ -248,10 +248,13 @@ struct TaylorBfArgs {
   cpx<double>* acc;           // [W][M][N] T_0 in FP64; R_0 after the last step
 };
 
-template <int NB, bool VEC>
+template <int BM, int NB, bool VEC>
 __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBfArgs> B) {
-  constexpr int BM = 64, BN = 16 * NB, BKC = 32, RS = BKC + 8;
-  constexpr int DEPTH = NB >= 6 ? 2 : 3;  // chunks in flight (register budget)
+  constexpr int BN = 16 * NB, BKC = 32, RS = BKC + 8;
+  constexpr int NCW = 4, NT = 512;  // 4 consumer waves (2 x 2), then 4 producer waves
+  constexpr int RB = BM / 32;       // 16-row blocks per consumer wave
+  constexpr int NUA = BM / 16;      // A units per producer thread
+  constexpr int DEPTH = (NB >= 6 || BM > 64) ? 2 : 3;  // chunks in flight (register budget)
   constexpr int CB = (NB + 1) / 2;
   constexpr int SA_BYTES = 2 * 4 * BM * RS * 2, SB_BYTES = 2 * 4 * BN * RS * 2;
   constexpr int RST = BN + 1;  // row stride of the result tile (float2)
@@ -277,18 +280,18 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
 
-  if (wave >= 4) {
+  if (wave >= NCW) {
     // ---------------- producers
-    const int pt = threadIdx.x - 256;
+    const int pt = threadIdx.x - 64 * NCW;
     const cpx<float>* __restrict__ V = a.V + (int64_t)w * M * K;
     const unsigned short* __restrict__ Tp = a.Tin + (int64_t)w * N * 4 * KP;
-    float4 ra[DEPTH][4];  // A unit e: row pt / 16 + 16 e, k pair pt % 16
+    float4 ra[DEPTH][NUA];  // A unit e: row pt / 16 + 16 e, k pair pt % 16
     u32x4 rb[DEPTH][NB];  // B unit e: u = pt + 256 e: column u / 16, plane (u / 4) % 4,
                           // 8 k at 8 (u % 4)
-    auto issue = [&](int q, float4 (&xa)[4], u32x4 (&xb)[NB]) {
+    auto issue = [&](int q, float4 (&xa)[NUA], u32x4 (&xb)[NB]) {
       const int k0 = (q < nch ? q : nch - 1) * BKC;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < NUA; ++e) {
         const int row = min(row0 + (pt >> 4) + 16 * e, M - 1);
         const int k = k0 + 2 * (pt & 15);
         if constexpr (VEC) {
@@ -307,10 +310,10 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
             Tp + ((int64_t)col * 4 + ((u >> 2) & 3)) * KP + k0 + 8 * (u & 3));
       }
     };
-    auto stash = [&](int q, int st, const float4 (&xa)[4], const u32x4 (&xb)[NB]) {
+    auto stash = [&](int q, int st, const float4 (&xa)[NUA], const u32x4 (&xb)[NB]) {
       const int k0 = q * BKC;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < NUA; ++e) {
         const int r = (pt >> 4) + 16 * e, kk = 2 * (pt & 15);
         const bool rok = row0 + r < M;
         const float4 v = xa[e];
@@ -350,9 +353,9 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
   } else {
     // ---------------- consumers
     const int wm = wave >> 1, wn = wave & 1;
-    v4f acr[2][CB], aci[2][CB];
+    v4f acr[RB][CB], aci[RB][CB];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < RB; ++i)
 #pragma unroll
       for (int j = 0; j < CB; ++j) {
         acr[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -368,14 +371,15 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
         if (c < nch) {
           const int st = c & 1;
           const int kq = 8 * (lane >> 4);
-          u16x8 fa[2][4];
+          u16x8 fa[RB][4], fn[RB][2];
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < RB; ++i) {
 #pragma unroll
             for (int pl = 0; pl < 4; ++pl)
-              fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][pl][wm * 32 + i * 16 + (lane & 15)][kq]);
-          const u16x8 fn[2][2] = {{bf16_neg(fa[0][2]), bf16_neg(fa[0][3])},
-                                  {bf16_neg(fa[1][2]), bf16_neg(fa[1][3])}};
+              fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][pl][wm * 16 * RB + i * 16 + (lane & 15)][kq]);
+            fn[i][0] = bf16_neg(fa[i][2]);
+            fn[i][1] = bf16_neg(fa[i][3]);
+          }
 #pragma unroll
           for (int j = 0; j < CB; ++j) {
             if (j < ncb) {
@@ -384,7 +388,7 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
               for (int pl = 0; pl < 4; ++pl)
                 fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][16 * (cb0 + j) + (lane & 15)][kq]);
 #pragma unroll
-              for (int i = 0; i < 2; ++i) {
+              for (int i = 0; i < RB; ++i) {
                 // re += Vr Tr - Vi Ti,  im += Vr Ti + Vi Tr  (fn: -Vi)
                 acr[i][j] = mul3(fa[i][0], fa[i][1], fb[0], fb[1], acr[i][j]);
                 acr[i][j] = mul3(fn[i][0], fn[i][1], fb[2], fb[3], acr[i][j]);
@@ -401,21 +405,21 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
     // column lane % 16 of each 16 x 16 block)
     const float alpha = a.alpha;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < RB; ++i)
 #pragma unroll
       for (int j = 0; j < CB; ++j) {
         if (j >= ncb) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          res[wm * 32 + i * 16 + 4 * (lane >> 4) + v][16 * (cb0 + j) + (lane & 15)] =
+          res[wm * 16 * RB + i * 16 + 4 * (lane >> 4) + v][16 * (cb0 + j) + (lane & 15)] =
               float2{alpha * acr[i][j][v], alpha * aci[i][j][v]};
       }
   }
   __syncthreads();
 
-  // ---------------- epilogue, all eight waves
+  // ---------------- epilogue, all waves
   const int tid = threadIdx.x;
-  constexpr int NE = BM * BN / 1024;
+  constexpr int NE = (BM * BN + 2 * NT - 1) / (2 * NT);  // tile entries per thread and half
   if (a.last) {
     // acc = T_0 + X R_1 (FP64), in two halves: every load of a half first, then its stores
     cpx<double>* __restrict__ acc = a.acc + (int64_t)w * M * N;
@@ -424,14 +428,14 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
       cpx<double> av[NE];
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
-        const int u = tid + 512 * (2 * e + h), row = row0 + u / BN, col = col0 + u % BN;
-        const bool ok = row < M && col < N;
+        const int u = tid + NT * (2 * e + h), row = row0 + u / BN, col = col0 + u % BN;
+        const bool ok = u < BM * BN && row < M && col < N;
         av[e] = acc[ok ? (int64_t)row * N + col : 0];
       }
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
-        const int u = tid + 512 * (2 * e + h), row = row0 + u / BN, col = col0 + u % BN;
-        if (row < M && col < N) {
+        const int u = tid + NT * (2 * e + h), row = row0 + u / BN, col = col0 + u % BN;
+        if (u < BM * BN && row < M && col < N) {
           const float2 t = res[u / BN][u % BN];
           acc[(int64_t)row * N + col] =
               cpx<double>{av[e].re + (double)t.x, av[e].im + (double)t.y};
@@ -449,28 +453,31 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
       float2 tv[NE];
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
-        const int u = tid + 512 * (2 * e + h), row = row0 + u / BN, col = col0 + u % BN;
-        const bool ok = row < M && col < N;
+        const int u = tid + NT * (2 * e + h), row = row0 + u / BN, col = col0 + u % BN;
+        const bool ok = u < BM * BN && row < M && col < N;
         const cpx<float> t = T0[ok ? (int64_t)row * N + col : 0];
         tv[e] = ok ? float2{t.re, t.im} : float2{0.f, 0.f};
       }
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
-        const int u = tid + 512 * (2 * e + h);
-        float2& r = res[u / BN][u % BN];
-        r = float2{r.x + tv[e].x, r.y + tv[e].y};
+        const int u = tid + NT * (2 * e + h);
+        if (u < BM * BN) {
+          float2& r = res[u / BN][u % BN];
+          r = float2{r.x + tv[e].x, r.y + tv[e].y};
+        }
       }
     }
   }
   __syncthreads();
   unsigned short* __restrict__ To = a.Tout + (int64_t)w * N * 4 * KP;
-  constexpr int NQ = (16 * BN + 511) / 512;
+  constexpr int QPC = BM / 4;                        // row quads per column
+  constexpr int NQ = (QPC * BN + NT - 1) / NT;
 #pragma unroll
   for (int e = 0; e < NQ; ++e) {
-    const int u = tid + 512 * e;
-    const int cl = u >> 4, rq = 4 * (u & 15);
+    const int u = tid + NT * e;
+    const int cl = u / QPC, rq = 4 * (u % QPC);
     const int col = col0 + cl, rb = row0 + rq;
-    if (u >= 16 * BN || col >= N || rb >= KP) continue;
+    if (u >= QPC * BN || col >= N || rb >= KP) continue;
     const float2 t0 = res[rq][cl], t1 = res[rq + 1][cl], t2 = res[rq + 2][cl],
                  t3 = res[rq + 3][cl];
     unsigned int h0[4], h1[4];
@@ -493,7 +500,6 @@ static hipError_t launch_taylor_bf16x3(const Job* jobs, const int* ids, int c, i
   TimedScope ts(KC_TAYLOR, s);
   Batch<TaylorBfArgs> Bt;
   Bt.nprob = c;
-  long long cnt[AFQMC_MAXP];
   int nb = 0;
   bool vec = true;
   for (int q = 0; q < c; ++q) {
@@ -506,7 +512,6 @@ static hipError_t launch_taylor_bf16x3(const Job* jobs, const int* ids, int c, i
     const int nbq = (t.N + 15) / 16 < 8 ? (t.N + 15) / 16 : 8;
     if (q == 0) nb = nbq;
     if (nbq != nb) return hipErrorInvalidValue;  // one column-tile width per group
-    t.tiles_m = (t.M + 63) / 64;
     t.tiles_n = (t.N + 16 * nb - 1) / (16 * nb);
     vec = vec && (t.M % 2 == 0) && (((uintptr_t)jb.vhs & 15) == 0);
     t.last = tout ? 0 : 1;
@@ -516,30 +521,52 @@ static hipError_t launch_taylor_bf16x3(const Job* jobs, const int* ids, int c, i
     t.Tout = tout ? (unsigned short*)tout[ids[q]] : nullptr;
     t.T0 = (const cpx<float>*)t0c[ids[q]];
     t.acc = (cpx<double>*)acc[ids[q]];
+  }
+  // row-tile height: 64 or 96, whichever costs less over the rounds of workgroups (one
+  // workgroup per CU at a time: the LDS stages take 50-145 KB), a round costing its rows
+  // plus a fixed share equal to 64 rows (the per-chunk latencies do not grow with BM)
+  int dev = 0, ncu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  if (ncu < 1) ncu = 1;
+  auto cost = [&](int bm) {
+    long long tiles = 0;
+    for (int q = 0; q < c; ++q)
+      tiles += (long long)Bt.a[q].W * ((Bt.a[q].M + bm - 1) / bm) * Bt.a[q].tiles_n;
+    return ((tiles + ncu - 1) / ncu) * (bm + 64);
+  };
+  const int bm = cost(96) < cost(64) ? 96 : 64;
+  long long cnt[AFQMC_MAXP];
+  for (int q = 0; q < c; ++q) {
+    TaylorBfArgs& t = Bt.a[q];
+    t.tiles_m = (t.M + bm - 1) / bm;
     cnt[q] = ((long long)t.W * t.tiles_m * t.tiles_n + 7) & ~7LL;
   }
   const long long g = batch_close(Bt, cnt);
   if (g < 0) return hipErrorInvalidValue;
   if (g == 0) return hipSuccess;
   const dim3 grid((unsigned)g), block(512);
-#define AFQMC_TBF(NBV)                                                                  \
-  case NBV:                                                                             \
-    if (vec) hipLaunchKernelGGL((taylor_bf16x3_kernel<NBV, true>), grid, block, 0, s, Bt); \
-    else hipLaunchKernelGGL((taylor_bf16x3_kernel<NBV, false>), grid, block, 0, s, Bt);    \
-    break;
-  switch (nb) {
-    AFQMC_TBF(1)
-    AFQMC_TBF(2)
-    AFQMC_TBF(3)
-    AFQMC_TBF(4)
-    AFQMC_TBF(5)
-    AFQMC_TBF(6)
-    AFQMC_TBF(7)
-    default:
-      if (vec) hipLaunchKernelGGL((taylor_bf16x3_kernel<8, true>), grid, block, 0, s, Bt);
-      else hipLaunchKernelGGL((taylor_bf16x3_kernel<8, false>), grid, block, 0, s, Bt);
-      break;
+#define AFQMC_TBF(BMV, NBV)                                                              \
+  if (vec) hipLaunchKernelGGL((taylor_bf16x3_kernel<BMV, NBV, true>), grid, block, 0, s, Bt); \
+  else hipLaunchKernelGGL((taylor_bf16x3_kernel<BMV, NBV, false>), grid, block, 0, s, Bt);
+#define AFQMC_TBF_NB(BMV)     \
+  switch (nb) {               \
+    case 1: AFQMC_TBF(BMV, 1) break; \
+    case 2: AFQMC_TBF(BMV, 2) break; \
+    case 3: AFQMC_TBF(BMV, 3) break; \
+    case 4: AFQMC_TBF(BMV, 4) break; \
+    case 5: AFQMC_TBF(BMV, 5) break; \
+    case 6: AFQMC_TBF(BMV, 6) break; \
+    case 7: AFQMC_TBF(BMV, 7) break; \
+    default: AFQMC_TBF(BMV, 8) break; \
   }
+  if (bm == 96) {
+    AFQMC_TBF_NB(96)
+  } else {
+    AFQMC_TBF_NB(64)
+  }
+#undef AFQMC_TBF_NB
 #undef AFQMC_TBF
   return hipGetLastError();
 }

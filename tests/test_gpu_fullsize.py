@@ -5,7 +5,7 @@
   of each are recomputed by the oracle (FP64 bars as in the other parity tests).
 * The 3x3x3, m=26 system with FP32 and BF16X3 contractions: energies of sampled initial
   walkers against the oracle, with the bars of test_gpu_precision (relative to the summed
-  magnitude of the energy parts).
+  magnitude of the energy parts), and one BF16X3 propagation step.
 """
 
 import numpy as np
@@ -84,3 +84,20 @@ def test_reduced_precision_energy_c1(prec, bar):
     Er = kp.local_energy(pre["Lh"], pre["h1h"], Gh, s.mesh)
     scale = np.abs(Er).sum(1)
     assert (np.abs(E[sample].sum(1) - Er.sum(1)) / scale).max() < bar
+
+
+def test_bf16x3_step_full_size():
+    """One BF16X3 step of the 3x3x3, m=26, 64-walker system (702 x 702 potential, 108 walker
+    columns: the launch uses the 96-row Taylor tiles) against the oracle on sampled walkers,
+    with the one-step bar of test_gpu_precision."""
+    s, U, x, p = system("c3B", prec=2)
+    p.step(torch.from_numpy(x[0]))
+    torch.cuda.synchronize()
+    Ug = host(p.U)
+    del p
+    torch.cuda.empty_cache()
+    sample = [0, 33, 63]
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    _, ld = kp.greens(U[sample], s.A)
+    out = kp.step(U[sample], ld, np.ones(len(sample)), x[0][sample], pre, s.A, s.L, s.mesh, s.dt)
+    assert rel(Ug[sample], out["U"]) < 5e-5
