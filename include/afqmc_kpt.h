@@ -138,9 +138,10 @@ typedef struct afqmc_kpt_problem {
   void* Lhs;         /* [nk][nk][nchol][nocc][4][32*ceil(m/32)] bfloat16 (uint16) split planes
                         of Lh (re hi, re lo, im hi, im lo; r padded with zeros), written by
                         prepare; prec BF16X3 only (else NULL) */
-  void* Ls;          /* [nk][nk][m][m][4][32*ceil(nchol/32)] bfloat16 (uint16) split planes
-                        of L (re hi, re lo, im hi, im lo; g padded with zeros), written by
-                        prepare; prec BF16X3 only (else NULL) */
+  void* Ls;          /* [nk(Q)][ceil(nchol/32)][nk*m*m (k p r)][4][32] bfloat16 (uint16)
+                        split planes of L (re hi, re lo, im hi, im lo) in chunks of 32
+                        Cholesky indices, g padded with zeros, written by prepare; prec
+                        BF16X3 only (else NULL) */
   /* walker state */
   void* U;           /* [nwalk][nk*m][nk*nocc] complex128 walker orbitals, in/out */
   void* Gh;          /* [nwalk][nk*nocc][nk*m] complex128 half-rotated Green's function */

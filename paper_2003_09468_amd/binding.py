@@ -216,7 +216,7 @@ class KptProblem:
             kp = 32 * ((m + 31) // 32)
             cp = 32 * ((nchol + 31) // 32)
             self.Lhs = torch.empty((nk, nk, nchol, nocc, 4, kp), dtype=torch.int16, **kw)
-            self.Ls = torch.empty((nk, nk, m, m, 4, cp), dtype=torch.int16, **kw)
+            self.Ls = torch.empty((nk, cp // 32, nk * m * m, 4, 32), dtype=torch.int16, **kw)
         N, n = nk * m, nk * nocc
         self.U = torch.zeros((nwalk, N, n), dtype=c128, **kw)
         self.Gh = torch.zeros((nwalk, n, N), dtype=c128, **kw)

@@ -495,7 +495,7 @@ struct VhsBfArgs {
   int W, nk, m, C, CP, tiles_m, tiles_n;
   KMesh mesh;
   const unsigned short* zs;  // [W][nk][4][CP]
-  const unsigned short* Ls;  // [nk][nk m m][4][CP]
+  const unsigned short* Ls;  // [nk][CP / 32][nk m m][4][32]
   cpx<float>* vhs;           // [W][nk m][nk m]
 };
 
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
         const int u = pt + 256 * e;
         const int col = min(col0 + (u >> 4), ncol - 1);
         xb[e] = *reinterpret_cast<const u4*>(
-            Lq + ((int64_t)col * 4 + ((u >> 2) & 3)) * CP + k0 + 8 * (u & 3));
+            Lq + (((int64_t)(k0 / BKC) * ncol + col) * 4 + ((u >> 2) & 3)) * BKC + 8 * (u & 3));
       }
       if (issued < total) advance(ip);
       ++issued;

@@ -106,29 +106,32 @@ __global__ void lh_split_kernel(int nk, int m, int nocc, int C, int KP,
   }
 }
 
-// BF16 split planes of L for the three-pass HS potential:
-//   Ls[Q][k][p][r][plane][g], g contiguous and zero-padded to CP = 32 ceil(C / 32).
-__global__ void l_split_kernel(int64_t ncols, int C, int CP, const cpx<double>* __restrict__ L,
+// BF16 split planes of L for the three-pass HS potential, by chunks of 32 g:
+//   Ls[Q][g / 32][(k p r)][plane][g % 32], g zero-padded to CP = 32 ceil(C / 32), so that
+//   one chunk of consecutive columns is one contiguous block.
+__global__ void l_split_kernel(int64_t ncols, int64_t ncq, int C, int CP,
+                               const cpx<double>* __restrict__ L,
                                unsigned short* __restrict__ Ls) {
   const int64_t total = ncols * CP;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int g = (int)(i % CP);
-    const int64_t col = i / CP;  // (Q, k, p, r)
+    const int64_t cg = i / CP;  // (Q, k, p, r)
+    const int64_t Q = cg / ncq, col = cg % ncq;
     float xr = 0.f, xi = 0.f;
     if (g < C) {
-      const cpx<double> v = L[col * C + g];
+      const cpx<double> v = L[cg * C + g];
       xr = (float)v.re;
       xi = (float)v.im;
     }
     unsigned short rh, rl, ih, il;
     bf16_split(xr, rh, rl);
     bf16_split(xi, ih, il);
-    unsigned short* o = Ls + col * 4 * CP + g;
+    unsigned short* o = Ls + ((((Q * (CP / 32) + g / 32) * ncq + col) * 4) * 32 + (g % 32));
     o[0] = rh;
-    o[CP] = rl;
-    o[2 * CP] = ih;
-    o[3 * CP] = il;
+    o[32] = rl;
+    o[64] = ih;
+    o[96] = il;
   }
 }
 
@@ -284,8 +287,8 @@ hipError_t run_prepare(const afqmc_kpt_problem& p, const void* H1, void* ws, hip
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int CP = 32 * ((p.nchol + 31) / 32);
-    const int64_t ncols = (int64_t)p.nk * p.nk * p.m * p.m;
-    hipLaunchKernelGGL(l_split_kernel, dim3(4096), dim3(256), 0, s, ncols, p.nchol, CP,
+    const int64_t ncq = (int64_t)p.nk * p.m * p.m, ncols = p.nk * ncq;
+    hipLaunchKernelGGL(l_split_kernel, dim3(4096), dim3(256), 0, s, ncols, ncq, p.nchol, CP,
                        (const cpx<double>*)p.L, (unsigned short*)p.Ls);
     e = hipGetLastError();
   }
