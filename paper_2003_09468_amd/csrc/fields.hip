@@ -473,11 +473,12 @@ __global__ __launch_bounds__(256) void field_split_kernel(const Batch<FieldArgs>
   unsigned short rh, rl, ih, il;
   bf16_split(zr, rh, rl);
   bf16_split(zi, ih, il);
-  unsigned short* o = zs + wq * 4 * CP + g;
+  // zs[Q][g / 32][w][plane][g % 32]: one chunk of the walkers is one contiguous block
+  unsigned short* o = zs + ((((int64_t)Q * (CP / 32) + g / 32) * W + w) * 4) * 32 + (g % 32);
   o[0] = rh;
-  o[CP] = rl;
-  o[2 * CP] = ih;
-  o[3 * CP] = il;
+  o[32] = rl;
+  o[64] = ih;
+  o[96] = il;
 }
 
 // HS potential on the three-pass BF16 split:
@@ -494,7 +495,7 @@ __global__ __launch_bounds__(256) void field_split_kernel(const Batch<FieldArgs>
 struct VhsBfArgs {
   int W, nk, m, C, CP, tiles_m, tiles_n;
   KMesh mesh;
-  const unsigned short* zs;  // [W][nk][4][CP]
+  const unsigned short* zs;  // [nk][CP / 32][W][4][32]
   const unsigned short* Ls;  // [nk][CP / 32][nk m m][4][32]
   cpx<float>* vhs;           // [W][nk m][nk m]
 };
@@ -554,7 +555,8 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
         const int u = pt + 256 * e;
         const int w = min(row0 + (u >> 4), a.W - 1);
         xa[e] = *reinterpret_cast<const u4*>(
-            a.zs + (((int64_t)w * a.nk + Q) * 4 + ((u >> 2) & 3)) * CP + k0 + 8 * (u & 3));
+            a.zs + ((((int64_t)Q * (CP / BKC) + k0 / BKC) * a.W + w) * 4 + ((u >> 2) & 3)) * BKC +
+            8 * (u & 3));
       }
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
