@@ -149,14 +149,16 @@ static hipError_t taylor_tiles(const OpTaylor<T>* ops, int c, int cls, int choic
 // product whose epilogue forms R_{j-1} directly: the intermediate R are only ever read as
 // BF16 operands, so they are formed in FP32 from the complex64 T_0 and stored as planes;
 // the last step adds X R_1 to the FP64 T_0.  The walker-side operand is kept as BF16
-// planes Rp[w][n][plane][k] (planes re hi, re lo, im hi, im lo; k = row of R, contiguous,
-// zero for M <= k < KP = 32 ceil(M / 32)), the layout the MFMA B operand reads.
+// planes Rp[w][k / 32][n][plane][k % 32] (planes re hi, re lo, im hi, im lo; k = row of R,
+// zero for M <= k < KP = 32 ceil(M / 32)): K-contiguous for the MFMA B operand, and one
+// K chunk of all columns is one contiguous block.
 
 __host__ __device__ __forceinline__ int kpad32(int m) { return 32 * ((m + 31) / 32); }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// Tp[w][n][pl][k] from T[w][k][n] (complex64), 64 k x 64 n tiles transposed through LDS.
+// Tp[w][k / 32][n][pl][k % 32] from T[w][k][n] (complex64), 64 k x 64 n tiles transposed
+// through LDS.
 struct TSplitArgs {
   int W, M, N, KP, tk, tn;  // tk = ceil(KP / 64), tn = ceil(N / 64)
   const cpx<float>* T;
@@ -198,7 +200,8 @@ __global__ __launch_bounds__(256) void t_split_kernel(const Batch<TSplitArgs> B)
     bf16_split2(tile[kq + 2][nn].y, tile[kq + 3][nn].y, h1[2], h1[3]);
 #pragma unroll
     for (int pl = 0; pl < 4; ++pl)
-      *reinterpret_cast<uint2*>(Tp + ((int64_t)n * 4 + pl) * a.KP + k) = uint2{h0[pl], h1[pl]};
+      *reinterpret_cast<uint2*>(Tp + ((((int64_t)(k >> 5) * a.N + n) * 4 + pl) << 5) + (k & 31)) =
+          uint2{h0[pl], h1[pl]};
   }
 }
 
@@ -242,8 +245,8 @@ struct TaylorBfArgs {
   int last;                           // 1: R_0 into acc (FP64), else planes of R_{j-1}
   float alpha;                        // -sqrt(dt) / j
   const cpx<float>* V;        // [W][M][M]
-  const unsigned short* Tin;  // [W][N][4][KP] planes of R_j
-  unsigned short* Tout;       // [W][N][4][KP] planes of R_{j-1} (not last)
+  const unsigned short* Tin;  // [W][KP / 32][N][4][32] planes of R_j
+  unsigned short* Tout;       // [W][KP / 32][N][4][32] planes of R_{j-1} (not last)
   const cpx<float>* T0;       // [W][M][N] T_0 as complex64 (not last)
   cpx<double>* acc;           // [W][M][N] T_0 in FP64; R_0 after the last step
 };
@@ -307,7 +310,7 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
         const int u = pt + 256 * e;
         const int col = min(col0 + (u >> 4), N - 1);
         xb[e] = *reinterpret_cast<const u32x4*>(
-            Tp + ((int64_t)col * 4 + ((u >> 2) & 3)) * KP + k0 + 8 * (u & 3));
+            Tp + ((((int64_t)(k0 >> 5) * N + col) * 4 + ((u >> 2) & 3)) << 5) + 8 * (u & 3));
       }
     };
     auto stash = [&](int q, int st, const float4 (&xa)[NUA], const u32x4 (&xb)[NB]) {
@@ -487,7 +490,8 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
     bf16_split2(t2.y, t3.y, h1[2], h1[3]);
 #pragma unroll
     for (int pl = 0; pl < 4; ++pl)
-      *reinterpret_cast<uint2*>(To + ((int64_t)col * 4 + pl) * KP + rb) = uint2{h0[pl], h1[pl]};
+      *reinterpret_cast<uint2*>(To + ((((int64_t)(rb >> 5) * N + col) * 4 + pl) << 5) + (rb & 31)) =
+          uint2{h0[pl], h1[pl]};
   }
 }
 
