@@ -1,7 +1,7 @@
 """Batches of uneven systems in one call, the captured step block and the autotuner.
 
-A batch mixes meshes, band counts, Cholesky ranks, walker counts, one FP32 and one BF16X3
-system.
+A batch mixes meshes, band counts, Cholesky ranks, walker counts, one FP32 and two BF16X3
+systems.
 Every system's result must equal what the same system gives when run alone through the
 single-problem entry points (same kernels, same reduction order: agreement to rounding
 noise), and the FP64 systems must match the oracle to the FP64 bar.  The captured block
@@ -22,8 +22,10 @@ if gpu_available():
     from paper_2003_09468_amd import KptBatch
     from tests.gpu_cases import build, host, rel, phase_err, energy_err
 
-# (case, precision): uneven sizes; one FP32 and one BF16X3 system share the batch
-BATCH = [("aniso", 0), ("line3", 0), ("wide", 0), ("mixed", 1), ("c0", 0), ("mol", 2)]
+# (case, precision): uneven sizes; one FP32 and two BF16X3 systems share the batch (the two
+# BF16X3 systems differ in mesh and Cholesky padding but share each BF16X3 launch)
+BATCH = [("aniso", 0), ("line3", 0), ("wide", 0), ("mixed", 1), ("c0", 0), ("mol", 2),
+         (((2, 2, 1), 9, 3, 40, 7, "random", "dense"), 2)]
 NSTEPS = 2  # the fields drawn by build() cover two steps
 
 
