@@ -69,11 +69,13 @@ typedef enum {
  * all energy sums are FP64 in every mode.
  *   FP64:   complex128 operands, FP64 MFMA.
  *   FP32:   complex64 operands (L32, Lh32), FP32 MFMA with FP32 accumulation.
- *   BF16X3: as FP32, except the HS potential and the exchange contraction of
- *           the local energy, whose operands are split x = hi + lo into two
- *           bfloat16 numbers and multiplied in three BF16 MFMA passes
- *           (hi hi + hi lo + lo hi) with FP32 accumulation; the force bias, the
- *           Taylor terms (on the FP32 potential) and the energy adjoint are FP32. */
+ *   BF16X3: the force bias, the HS potential, the Taylor products and the exchange
+ *           contraction of the local energy take their operands split x = hi + lo
+ *           into two bfloat16 numbers (from the FP32-rounded value) and multiply them
+ *           in three BF16 MFMA passes (hi hi + hi lo + lo hi) with FP32
+ *           accumulation; the Taylor polynomial is evaluated in nested form,
+ *           T0 + X/1 (T0 + X/2 (... (T0 + X/6 T0))), X = -sqrt(dt) vhs; the energy
+ *           adjoint is FP32. */
 typedef enum {
   AFQMC_PREC_FP64 = 0,
   AFQMC_PREC_FP32 = 1,
@@ -133,7 +135,7 @@ typedef struct afqmc_kpt_problem {
                         Lh[Q][k][a][r][g] = sum_p conj(A[k][p][a]) L[Q][k][p][r][g] */
   void* h1h;         /* [nk][nocc][m] complex128, written by prepare: A[k]^H H1[k] */
   void* bhalf;       /* [nk][m][m] complex128, written by prepare: exp(-dt/2 (H1 + V0)) */
-  void* L32;         /* [nk][nk][m][m][nchol] complex64 copy of L; prec FP32/BF16X3 only */
+  void* L32;         /* [nk][nk][m][m][nchol] complex64 copy of L; prec FP32 only */
   void* Lh32;        /* [nk][nk][nocc][m][nchol] complex64 copy of Lh; prec FP32/BF16X3 only */
   void* Lhs;         /* [nk][nk][nchol][nocc][4][32*ceil(m/32)] bfloat16 (uint16) split planes
                         of Lh (re hi, re lo, im hi, im lo; r padded with zeros), written by

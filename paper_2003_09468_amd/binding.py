@@ -206,11 +206,12 @@ class KptProblem:
         self.Lh = torch.empty((nk, nk, nocc, m, nchol), dtype=c128, **kw)
         self.h1h = torch.empty((nk, nocc, m), dtype=c128, **kw)
         self.bhalf = torch.empty((nk, m, m), dtype=c128, **kw)
-        if self.prec != PREC_FP64:
-            self.L32 = torch.empty(self.L.shape, dtype=torch.complex64, **kw)
-            self.Lh32 = torch.empty(self.Lh.shape, dtype=torch.complex64, **kw)
-        else:
-            self.L32 = self.Lh32 = None
+        # complex64 copies: L for the FP32 HS potential, Lh for the FP32 force bias and
+        # exchange and for the adjoint of both reduced modes (BF16X3 reads split planes of L)
+        self.L32 = (torch.empty(self.L.shape, dtype=torch.complex64, **kw)
+                    if self.prec == PREC_FP32 else None)
+        self.Lh32 = (torch.empty(self.Lh.shape, dtype=torch.complex64, **kw)
+                     if self.prec != PREC_FP64 else None)
         self.Lhs = self.Ls = None
         if self.prec == PREC_BF16X3:
             kp = 32 * ((m + 31) // 32)

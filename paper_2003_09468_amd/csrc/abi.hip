@@ -118,7 +118,7 @@ afqmc_status check_dims(const afqmc_kpt_problem& p) {
 
 afqmc_status check_fields(const afqmc_kpt_problem& p, unsigned need) {
   const bool f32 = low_prec(p.prec);
-  if (need & N_L) AFQMC_TRY(check_ptr(f32 ? p.L32 : p.L, 16));
+  if ((need & N_L) && p.prec != AFQMC_PREC_BF16X3) AFQMC_TRY(check_ptr(f32 ? p.L32 : p.L, 16));
   if (need & N_A) AFQMC_TRY(check_ptr(p.A, 16));
   if (need & N_LH) AFQMC_TRY(check_ptr(f32 ? p.Lh32 : p.Lh, 16));
   if (need & N_LD) AFQMC_TRY(check_ptr(p.L, 16));

@@ -876,6 +876,8 @@ hipError_t tune_vhs(const Job* jobs, int n, hipStream_t s) {
     const hipError_t e = for_groups(
         c, [&](int i) { return vhs_key(J[i].p); },
         [&](const int* ids, int g) -> hipError_t {
+          // the BF16X3 HS potential has a single variant
+          if (J[ids[0]].p.prec == AFQMC_PREC_BF16X3) return hipSuccess;
           return tune_group(
               TS_VHS, J, ids, g, [&](int ch) { return launch_vhs_group(J, ids, g, ch, zeta, s); },
               s);

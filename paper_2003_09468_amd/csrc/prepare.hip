@@ -273,7 +273,7 @@ hipError_t run_prepare(const afqmc_kpt_problem& p, const void* H1, void* ws, hip
                      (cpx<double>*)p.bhalf);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (f32) {
+  if (p.prec == AFQMC_PREC_FP32) {  // BF16X3 reads the split planes of L instead
     const int64_t n = (int64_t)p.nk * p.nk * p.m * p.m * p.nchol;
     hipLaunchKernelGGL(to_c64_kernel, dim3(4096), dim3(256), 0, s, n, (const cpx<double>*)p.L,
                        (cpx<float>*)p.L32);

@@ -43,7 +43,7 @@ void tune_store(const std::string& key, int choice) {
 int tune_ncand(int stage, int prec) {
   switch (stage) {
     case TS_TAYLOR: return prec == AFQMC_PREC_BF16X3 ? 1 : low_prec(prec) ? 3 : 6;
-    case TS_VHS: return 3;
+    case TS_VHS: return prec == AFQMC_PREC_BF16X3 ? 1 : 3;
     case TS_VBIAS: return prec == AFQMC_PREC_BF16X3 ? 1 : 3;
     default: return 1;
   }
