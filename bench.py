@@ -710,10 +710,13 @@ def main():
     paths = ["fp64", "fp32", "bf16x3"] if args.prec == "all" else [args.prec]
     precs = {"fp64": lib.PREC_FP64, "fp32": lib.PREC_FP32, "bf16x3": lib.PREC_BF16X3}
     G64 = None
-    same_state = {}
+    same_state, initial = {}, {}
     for name in paths:
         p = make_problem(s, U0, precs[name], torch)
         res[name], E0[name], W0[name] = bench_path(name, p, U0d, xs, args, torch, cfg)
+        # every path's energies on the initial walkers (the same Gh: FP64 greens)
+        reset(p, U0d)
+        initial[name] = p.energy().sum(1).cpu().numpy() / cfg["nk"]
         if name == "fp64":
             G64 = bench_path.G_end
         elif G64 is not None:
@@ -729,7 +732,8 @@ def main():
                "compared": "E_L per walker after one block from the same start, against the "
                            "FP64 GPU path (which matches the FP64 oracle to 1e-10)",
                "same_state_compared": "the path's energies evaluated on the FP64 path's Green's "
-                                      "functions after that block"}
+                                      "functions after that block",
+               "initial_walkers_compared": "the path's energies of the initial walkers"}
         for name in res:
             if name == "fp64":
                 continue
@@ -740,10 +744,14 @@ def main():
                 d2 = np.abs(same_state[name] - e64)
                 ent["same_state_max_abs_dE_per_cell"] = float(d2.max())
                 ent["same_state_median_abs_dE_per_cell"] = float(np.median(d2))
+            d3 = np.abs(initial[name] - initial["fp64"])
+            ent["initial_walkers_max_abs_dE_per_cell"] = float(d3.max())
+            ent["initial_walkers_median_abs_dE_per_cell"] = float(np.median(d3))
             acc[name] = ent
             log(f"accuracy {name}: max |dE_L| = {d.max():.3e} Ha/cell (median "
                 f"{np.median(d):.3e}); same state max "
-                f"{ent.get('same_state_max_abs_dE_per_cell', float('nan')):.3e}")
+                f"{ent.get('same_state_max_abs_dE_per_cell', float('nan')):.3e}; initial "
+                f"walkers max {d3.max():.3e}")
 
     # the fastest path whose block-level energies meet the tolerance; FP64 otherwise
     use = "fp64" if "fp64" in res else paths[0]
