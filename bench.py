@@ -65,6 +65,11 @@ KERNEL_NAMES = {
     "exchange": "exchange_kernel<{t}", "greens_solve": "OpGreensSolve",
     "greens_gj": "gj_", "bhalf": "OpBhalf<{t}>",
 }
+# the BF16X3 kernels of the same classes
+KERNEL_NAMES_BF16X3 = {
+    "taylor": "taylor_bf16x3_kernel", "vhs": "vhs_bf16x3_kernel",
+    "vbias": "vbias_bf16x3_kernel", "exchange": "exchange_bf16x3_kernel",
+}
 
 
 def kernel_source_hash(files=None):
@@ -106,9 +111,9 @@ def _pmc_rows(path, counter):
 
 
 def reduce_pmc(fetch_csv, write_csv):
-    """Per-launch HBM bytes of the c1 FP64 kernels from two counter runs (FETCH_SIZE, then
-    WRITE_SIZE, KiB per dispatch), each scaled by what it reads for the 1 GiB copy; writes
-    profiles/traffic_c1.json and profiles/traffic_c1.md."""
+    """Per-launch HBM bytes of the c1 FP64 and BF16X3 kernels from two counter runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what it reads for the
+    1 GiB copy; writes profiles/traffic_c1.json and profiles/traffic_c1.md."""
     from synth.kpt_inputs import config_shapes
     c = config_shapes("c1")
     W, nk, m, nocc, C = c["nwalk"], c["nk"], c["m"], c["nocc"], c["nchol"]
@@ -126,32 +131,46 @@ def reduce_pmc(fetch_csv, write_csv):
         "vhs": (16.0 * (nk * nk * m * m * C + W * nk * C), 16.0 * W * N * N),
         "exchange": (16.0 * (nk * nk * nocc * m * C + W * n * N), 16.0 * nk ** 3 * W),
     }
-    rec = {"workload": "c1: mesh 3x3x3, m=26, nocc=4, nchol=208, 64 walkers (FP64 path)",
+    # BF16X3: planes are 8 bytes per complex entry (four bf16), complex64 8, complex128 16;
+    # the Taylor launches are the six nested steps (five write planes, the last the FP64
+    # result), L and Lh planes are padded to 32 along g and r
+    KP, CP, KPm = 32 * ((N + 31) // 32), 32 * ((C + 31) // 32), 32 * ((m + 31) // 32)
+    algo_bf = {
+        "taylor": (8.0 * W * N * N + 8.0 * W * n * KP + (5 * 8.0 + 16.0) / 6 * W * N * n,
+                   (5 * 8.0 * W * n * KP + 16.0 * W * N * n) / 6),
+        "vhs": (8.0 * (nk * nk * m * m * CP + W * nk * CP), 8.0 * W * N * N),
+        "exchange": (8.0 * nk * nk * C * nocc * KPm + 16.0 * W * n * N, 16.0 * nk ** 3 * W),
+    }
+    rec = {"workload": "c1: mesh 3x3x3, m=26, nocc=4, nchol=208, 64 walkers (FP64 and "
+                       "BF16X3 paths)",
            "fetch_scale": fs, "write_scale": ws, "kernels": {}}
-    for k, pat in KERNEL_NAMES.items():
-        pat = pat.format(t="double")
-        fv = [x for name, x in fetch if pat in name]
-        wv = [x for name, x in write if pat in name]
-        if not fv or not wv:
-            continue
-        fb = sum(fv) / len(fv) * 1024.0 * fs
-        wb = sum(wv) / len(wv) * 1024.0 * ws
-        e = {"launches": len(fv), "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
-             "bytes_per_launch": fb + wb, "source_hash": kernel_source_hash(KERNEL_FILES[k])}
-        if k in algo:
-            e["algorithmic_read_bytes"], e["algorithmic_write_bytes"] = algo[k]
-        rec["kernels"][f"{k}_fp64"] = e
+    for prec, names, alg in (("fp64", {k: v.format(t="double") for k, v in KERNEL_NAMES.items()},
+                              algo),
+                             ("bf16x3", KERNEL_NAMES_BF16X3, algo_bf)):
+        for k, pat in names.items():
+            fv = [x for name, x in fetch if pat in name]
+            wv = [x for name, x in write if pat in name]
+            if not fv or not wv:
+                continue
+            fb = sum(fv) / len(fv) * 1024.0 * fs
+            wb = sum(wv) / len(wv) * 1024.0 * ws
+            e = {"launches": len(fv), "fetch_bytes_per_launch": fb,
+                 "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb,
+                 "source_hash": kernel_source_hash(KERNEL_FILES[k])}
+            if k in alg:
+                e["algorithmic_read_bytes"], e["algorithmic_write_bytes"] = alg[k]
+            rec["kernels"][f"{k}_{prec}"] = e
     base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
     json.dump(rec, open(os.path.join(base, "traffic_c1.json"), "w"), indent=1)
-    lines = ["# HBM traffic per launch, c1 FP64 path (rocprofv3 counters)", "",
+    lines = ["# HBM traffic per launch, c1 FP64 and BF16X3 paths (rocprofv3 counters)", "",
              "Commands (repository root on the GPU box; each counter in its own run):", "",
              "```", "cd /tmp && export TMPDIR=/tmp && cd \"$GRAFT_REPO_ROOT\"",
              "timeout -s KILL 400 rocprofv3 --pmc FETCH_SIZE --output-format csv "
              "-d gpurun_out/pmc_fetch -o run -- \\",
-             "    python3 bench.py --steps 1 --warmup 0 --prec fp64 --no-cpu-baseline --calib-copy",
+             "    python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --calib-copy",
              "timeout -s KILL 400 rocprofv3 --pmc WRITE_SIZE --output-format csv "
              "-d gpurun_out/pmc_write -o run -- \\",
-             "    python3 bench.py --steps 1 --warmup 0 --prec fp64 --no-cpu-baseline --calib-copy",
+             "    python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --calib-copy",
              "python3 bench.py --reduce-pmc gpurun_out/pmc_fetch/run_counter_collection.csv "
              "gpurun_out/pmc_write/run_counter_collection.csv", "```", "",
              f"Scale: the plain 1 GiB device copy (`--calib-copy`) reads as FETCH_SIZE = "
@@ -171,7 +190,11 @@ def reduce_pmc(fetch_csv, write_csv):
                      f"{'' if aw is None else f'{aw / 1e6:.1f}'} | {e['source_hash']} |")
     lines += ["", "Algorithmic bytes: a Taylor term reads vhs (W (nk m)^2), T_{j-1} and the FP64 "
               "accumulator and writes T_j (5 of 6 terms) and the accumulator; the HS potential "
-              "reads L once and writes vhs; the exchange reads Lh and Gh once."]
+              "reads L once and writes vhs; the exchange reads Lh and Gh once.  BF16X3 (8 bytes "
+              "per split complex entry): a nested Taylor step reads the complex64 potential, "
+              "the walker planes and T_0 (the last step the FP64 T_0) and writes the next "
+              "planes (the last step the FP64 result); the HS potential reads the L planes "
+              "and writes the complex64 potential; the exchange reads the Lh planes and Gh."]
     open(os.path.join(base, "traffic_c1.md"), "w").write("\n".join(lines) + "\n")
     print(json.dumps(rec["kernels"], indent=1))
 
