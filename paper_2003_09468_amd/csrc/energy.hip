@@ -201,29 +201,6 @@ __global__ __launch_bounds__(256) void exchange_kernel(const Batch<ExchArgs> B) 
 // (w, b), K = r padded to 32 * KB; the Gh fragments are split once into registers, and the
 // Lh slabs come pre-split from prepare (four bf16 planes: re hi, re lo, im hi, im lo, r
 // contiguous) and are staged into LDS with 16-byte copies.
-// 4 x 4 transpose inside each lane quad: on return register v of quad lane j holds what
-// register j of quad lane v held.  Two butterfly steps (lane bit 0 with register bit 0,
-// then bit 1); in each, the register whose index bit differs from the lane's bit is
-// exchanged with the partner lane by a DPP quad permutation.
-template <int CTRL>
-__device__ __forceinline__ void quad_swap_pair(float& x0, float& x1, bool hi) {
-  const float send = hi ? x0 : x1;
-  const float recv =
-      __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(send), CTRL, 0xf, 0xf, false));
-  x0 = hi ? recv : x0;
-  x1 = hi ? x1 : recv;
-}
-
-__device__ __forceinline__ v4f quad_transpose(v4f x, int lane) {
-  float x0 = x[0], x1 = x[1], x2 = x[2], x3 = x[3];
-  const bool b0 = lane & 1, b1 = (lane >> 1) & 1;
-  quad_swap_pair<0xB1>(x0, x1, b0);  // quad_perm [1,0,3,2]
-  quad_swap_pair<0xB1>(x2, x3, b0);
-  quad_swap_pair<0x4E>(x0, x2, b1);  // quad_perm [2,3,0,1]
-  quad_swap_pair<0x4E>(x1, x3, b1);
-  return v4f{x0, x1, x2, x3};
-}
-
 template <int KB, int WT>
 __global__ __launch_bounds__(256) void exchange_bf16x3_kernel(const Batch<ExchArgs> B) {
   constexpr int KP = 32 * KB;  // r padded to the MFMA K
@@ -374,27 +351,6 @@ __global__ __launch_bounds__(256) void exchange_bf16x3_kernel(const Batch<ExchAr
           }
         }
         const int g0 = c * Gs;
-        if (nocc == 4) {
-          // lane (g, w, b) holds T1_t[b][a] for a = v and the partner's T1 for Lh index v
-          // and Gh index b; the quad transpose brings T2_t[a][b] to register a
-          const bool gok = g0 + (lane >> 4) < C;
-#pragma unroll
-          for (int ct = 0; ct < WT; ++ct) {
-            const v4f tr = quad_transpose(a2r[ct], lane), ti = quad_transpose(a2i[ct], lane);
-            if (gok && walker(ct) < W) {
-              // the four products of one (g, w, b) in FP32 (the operands are FP32 MFMA
-              // results of BF16-split data), their sum over g and the lanes in FP64
-              float qr = 0.f, qi = 0.f;
-#pragma unroll
-              for (int v = 0; v < 4; ++v) {
-                qr += a1r[ct][v] * tr[v] - a1i[ct][v] * ti[v];
-                qi += a1r[ct][v] * ti[v] + a1i[ct][v] * tr[v];
-              }
-              sr[ct] += (double)qr;
-              si[ct] += (double)qi;
-            }
-          }
-        } else
 #pragma unroll
         for (int ct = 0; ct < WT; ++ct) {
           const bool colok = (ws_l < Ws) && (walker(ct) < W);
@@ -446,6 +402,212 @@ __global__ __launch_bounds__(256) void exchange_bf16x3_kernel(const Batch<ExchAr
         for (int grp = 0; grp < 4; ++grp)
           for (int b = 0; b < nocc; ++b) {
             const int l = wv * 64 + grp * 16 + wsi * nocc + b;
+            ar += red[0][l];
+            ai += red[1][l];
+          }
+        part[(int64_t)t * W + w] = cpx<double>{-mult * ar, -mult * ai};
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// The same for nocc = 4 (four occupied bands per k-point, as in the diamond workloads),
+// with the occupied dimension fixed: a 16-row tile holds 4 values of g and a 16-column
+// tile 4 walkers.  Lane (g_s, w_s, b) of a wave holds T1_t[b][a] of its (g, w) in
+// register a, and the partner's T1_pi(t)[a][b] sits in lane (g_s, w_s, a), register b:
+// the partner tile is transposed inside each lane quad through a wave-private LDS tile
+// (row stride 20 words, so the 32-bit scatter of 64 lanes hits 64 distinct banks), and
+// the four products of one (g, w, b) are summed in FP32 before the FP64 sum over g.
+// Rows of g >= C and columns of walkers >= W hold zeros, so their products vanish.
+template <int KB, int WT>
+__global__ __launch_bounds__(256) void exchange_bf16x3_q4_kernel(const Batch<ExchArgs> B) {
+  constexpr int KP = 32 * KB;        // r padded to the MFMA K
+  constexpr int RS = KP + 8;         // LDS row stride (bf16): rows start 16-byte aligned
+  constexpr int UPR = KP / 8;        // 16-byte units per (row, plane)
+  constexpr int CU = 16 * 4 * UPR;   // units of one slab chunk: rows (g, a) x planes x r
+  constexpr int NU = 2 * CU / 256;   // units per thread (both slabs)
+  constexpr int DEPTH = 2;          // chunks in flight (3 waves per SIMD at K = 32)
+  constexpr int TS = 20;             // transpose tile row stride (words)
+
+  __shared__ __attribute__((aligned(16))) unsigned short LA[2][2][4][16][RS];  // [buf][slab][plane][(g, a)][r]
+  __shared__ __attribute__((aligned(16))) float XT[4][WT][2][16 * TS];         // [wave][ct][re/im][quad][.]
+  __shared__ double red[2][256];
+
+  long long bid;
+  const int pb = batch_find(B, blockIdx.x, bid);
+  const int nk = B.a[pb].nk, m = B.a[pb].m, C = B.a[pb].C, W = B.a[pb].W;
+  const int nchunk_w = B.a[pb].nchunk_w;
+  const KMesh mesh = B.a[pb].mesh;
+  const unsigned short* __restrict__ Lhs = (const unsigned short*)B.a[pb].Lh;
+  const cpx<double>* __restrict__ Gh = B.a[pb].Gh;
+  cpx<double>* __restrict__ part = B.a[pb].part;
+  const int chunk = (int)(bid % nchunk_w);
+  const int t = (int)(bid / nchunk_w);
+  const int kp = t % nk, k = (t / nk) % nk, Q = t / (nk * nk);
+  const int mQ = mesh.neg(Q), kpq = mesh.kmq(kp, Q), kq = mesh.kmq(k, Q);
+  const int tp = (mQ * nk + kpq) * nk + kq;
+  if (t > tp) return;
+  const double mult = (t == tp) ? 1.0 : 2.0;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, ws_l = col >> 2, b_l = col & 3;
+  const int64_t Nn = (int64_t)nk * m, nn = (int64_t)nk * 4;
+  // column tile ct of this wave: walkers 16 WT chunk + 4 (wave WT + ct) + (0 .. 3)
+  auto walker = [&](int ct) { return chunk * 16 * WT + (wave * WT + ct) * 4 + ws_l; };
+
+  // Gh fragments (B operand, B[r][(w, b)], r = 32 kb + 8 (lane / 16) + i), split
+  u16x8 g1[WT][KB][4], g2[WT][KB][4];
+#pragma unroll
+  for (int ct = 0; ct < WT; ++ct) {
+    const int wl = walker(ct);
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int r = 32 * kb + 8 * (lane >> 4) + i;
+        float x1r = 0.f, x1i = 0.f, x2r = 0.f, x2i = 0.f;
+        if (r < m && wl < W) {
+          const cpx<double> v1 = Gh[((int64_t)wl * nn + (int64_t)kpq * 4 + b_l) * Nn + (int64_t)kq * m + r];
+          const cpx<double> v2 = Gh[((int64_t)wl * nn + (int64_t)k * 4 + b_l) * Nn + (int64_t)kp * m + r];
+          x1r = (float)v1.re; x1i = (float)v1.im; x2r = (float)v2.re; x2i = (float)v2.im;
+        }
+        unsigned short h, l;
+        bf16_split(x1r, h, l); g1[ct][kb][0][i] = h; g1[ct][kb][1][i] = l;
+        bf16_split(x1i, h, l); g1[ct][kb][2][i] = h; g1[ct][kb][3][i] = l;
+        bf16_split(x2r, h, l); g2[ct][kb][0][i] = h; g2[ct][kb][1][i] = l;
+        bf16_split(x2i, h, l); g2[ct][kb][2][i] = h; g2[ct][kb][3][i] = l;
+      }
+  }
+
+  // slab (Q, k) is [C][4][4][KP] bf16: chunk c (g = 4c .. 4c + 3) is units [c CU, (c + 1) CU)
+  const unsigned short* slab0 = Lhs + ((int64_t)Q * nk + k) * C * 16 * KP;
+  const unsigned short* slab1 = Lhs + ((int64_t)mQ * nk + kpq) * C * 16 * KP;
+  const int nch = (C + 3) / 4;
+  const int64_t ulast = (int64_t)C * 16 * UPR - 1;  // last unit of a slab
+
+  // DEPTH chunks in flight in registers; the loads are unconditional (clamped into the
+  // slab; rows of g >= C are zeroed when staged) so that each wait covers only the oldest
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  u4 pu[DEPTH][NU];
+  auto fetch = [&](int c, u4 (&xu)[NU]) {
+#pragma unroll
+    for (int e = 0; e < NU; ++e) {
+      const int idx = tid + 256 * e;
+      const int sl = idx / CU, u = idx % CU;
+      const int64_t un = min((int64_t)c * CU + u, ulast);
+      xu[e] = *reinterpret_cast<const u4*>((sl ? slab1 : slab0) + un * 8);
+    }
+  };
+  auto stash = [&](int c, int buf, const u4 (&xu)[NU]) {
+    const bool full = 4 * c + 4 <= C;  // uniform: every row of the chunk is a valid g
+#pragma unroll
+    for (int e = 0; e < NU; ++e) {
+      const int idx = tid + 256 * e;
+      const int sl = idx / CU, u = idx % CU;
+      const int row = u / (4 * UPR), pl = (u / UPR) % 4, r8 = u % UPR;
+      u4 v = xu[e];
+      if (!full && 4 * c + row / 4 >= C) v = u4{0u, 0u, 0u, 0u};
+      *reinterpret_cast<u4*>(&LA[buf][sl][pl][row][r8 * 8]) = v;
+    }
+  };
+
+  double sr[WT], si[WT];
+#pragma unroll
+  for (int ct = 0; ct < WT; ++ct) sr[ct] = si[ct] = 0.0;
+#pragma unroll
+  for (int d = 0; d < DEPTH; ++d) fetch(d, pu[d]);
+  stash(0, 0, pu[0]);
+  fetch(DEPTH, pu[0]);
+  __syncthreads();
+  const int quad = lane >> 2, bq = lane & 3;
+  // iteration c: chunk c from LDS buffer c & 1; chunk c + 1 (slot (c + 1) % DEPTH) to the
+  // other buffer; chunk c + 1 + DEPTH requested into the freed slot
+  for (int c0 = 0; c0 < nch; c0 += DEPTH) {
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) {
+      const int c = c0 + d;
+      const int buf = c & 1;
+      if (c < nch) {
+        v4f a1r[WT], a1i[WT], a2r[WT], a2i[WT];
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct) {
+          a1r[ct] = v4f{0.f, 0.f, 0.f, 0.f};
+          a1i[ct] = a1r[ct]; a2r[ct] = a1r[ct]; a2i[ct] = a1r[ct];
+        }
+        // one slab at a time (register budget): re += Lr Gr - Li Gi, im += Lr Gi + Li Gr
+        // (-Li: flipped sign bits)
+        auto slab_mfma = [&](int sl, const u16x8 (&g)[WT][KB][4], v4f (&ar)[WT], v4f (&ai)[WT]) {
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb) {
+            const int r0 = 32 * kb + 8 * (lane >> 4);
+            u16x8 x[4];
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl)
+              x[pl] = *reinterpret_cast<const u16x8*>(&LA[buf][sl][pl][col][r0]);
+            const u16x8 n2 = bf16_neg(x[2]), n3 = bf16_neg(x[3]);
+#pragma unroll
+            for (int ct = 0; ct < WT; ++ct) {
+              ar[ct] = mul3(x[0], x[1], g[ct][kb][0], g[ct][kb][1], ar[ct]);
+              ar[ct] = mul3(n2, n3, g[ct][kb][2], g[ct][kb][3], ar[ct]);
+              ai[ct] = mul3(x[0], x[1], g[ct][kb][2], g[ct][kb][3], ai[ct]);
+              ai[ct] = mul3(x[2], x[3], g[ct][kb][0], g[ct][kb][1], ai[ct]);
+            }
+          }
+        };
+        slab_mfma(1, g2, a2r, a2i);  // the partner tile first: its transpose overlaps slab 0
+        slab_mfma(0, g1, a1r, a1i);
+        // register v of lane (quad, bq) to word v TS-row quad, column 4 v + bq; read back
+        // as the 4 words 4 bq .. 4 bq + 3: register v of lane bq then holds register bq of
+        // lane v
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            XT[wave][ct][0][quad * TS + 4 * v + bq] = a2r[ct][v];
+            XT[wave][ct][1][quad * TS + 4 * v + bq] = a2i[ct][v];
+          }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct) {
+          const v4f tr = *reinterpret_cast<const v4f*>(&XT[wave][ct][0][quad * TS + 4 * bq]);
+          const v4f ti = *reinterpret_cast<const v4f*>(&XT[wave][ct][1][quad * TS + 4 * bq]);
+          float qr = 0.f, qi = 0.f;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            qr = fmaf(a1r[ct][v], tr[v], qr);
+            qr = fmaf(-a1i[ct][v], ti[v], qr);
+            qi = fmaf(a1r[ct][v], ti[v], qi);
+            qi = fmaf(a1i[ct][v], tr[v], qi);
+          }
+          sr[ct] += (double)qr;
+          si[ct] += (double)qi;
+        }
+      }
+      // past the last chunk the stores go to the buffer nobody reads (the barrier below
+      // also orders this chunk's transpose reads before the next chunk's writes)
+      stash(c + 1, buf ^ 1, pu[(d + 1) % DEPTH]);
+      fetch(c + 1 + DEPTH, pu[(d + 1) % DEPTH]);
+      __syncthreads();
+    }
+  }
+
+  // per-walker reduction over the 16 lanes (g_s, b) of a wave with the same walker
+#pragma unroll
+  for (int ct = 0; ct < WT; ++ct) {
+    red[0][tid] = sr[ct];
+    red[1][tid] = si[ct];
+    __syncthreads();
+    if (tid < 16) {
+      const int wv = tid >> 2, wsi = tid & 3;
+      const int w = chunk * 16 * WT + (wv * WT + ct) * 4 + wsi;
+      if (w < W) {
+        double ar = 0.0, ai = 0.0;
+        for (int gs = 0; gs < 4; ++gs)
+          for (int b = 0; b < 4; ++b) {
+            const int l = wv * 64 + gs * 16 + wsi * 4 + b;
             ar += red[0][l];
             ai += red[1][l];
           }
@@ -559,7 +721,9 @@ static hipError_t launch_exchange(const Job* jobs, int n, void* const* xpart, hi
       n,
       [&](int i) {
         const afqmc_kpt_problem& p = jobs[i].p;
-        return p.prec * 64 + (p.prec == AFQMC_PREC_BF16X3 ? (p.m <= 32 ? 1 : 2) : ks_class(p.m));
+        return p.prec * 64 + (p.prec == AFQMC_PREC_BF16X3
+                                  ? (p.m <= 32 ? 1 : 2) + (p.nocc == 4 ? 4 : 0)
+                                  : ks_class(p.m));
       },
       [&](const int* ids, int c) -> hipError_t {
         Batch<ExchArgs> B;
@@ -586,10 +750,14 @@ static hipError_t launch_exchange(const Job* jobs, int n, void* const* xpart, hi
         const bool f32 = low_prec(jobs[ids[0]].p.prec);
         const dim3 grid((unsigned)g), blk(256);
         if (jobs[ids[0]].p.prec == AFQMC_PREC_BF16X3) {
-          if (jobs[ids[0]].p.m <= 32)
-            hipLaunchKernelGGL((exchange_bf16x3_kernel<1, 2>), grid, blk, 0, s, B);
-          else
-            hipLaunchKernelGGL((exchange_bf16x3_kernel<2, 1>), grid, blk, 0, s, B);
+          const bool k1 = jobs[ids[0]].p.m <= 32;
+          if (jobs[ids[0]].p.nocc == 4) {
+            if (k1) hipLaunchKernelGGL((exchange_bf16x3_q4_kernel<1, 2>), grid, blk, 0, s, B);
+            else hipLaunchKernelGGL((exchange_bf16x3_q4_kernel<2, 1>), grid, blk, 0, s, B);
+          } else {
+            if (k1) hipLaunchKernelGGL((exchange_bf16x3_kernel<1, 2>), grid, blk, 0, s, B);
+            else hipLaunchKernelGGL((exchange_bf16x3_kernel<2, 1>), grid, blk, 0, s, B);
+          }
           return hipGetLastError();
         }
         switch (ks_class(jobs[ids[0]].p.m)) {

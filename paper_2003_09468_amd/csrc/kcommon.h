@@ -105,10 +105,19 @@ __device__ __forceinline__ v4f mfma_bf16(const u16x8& a, const u16x8& b, v4f c) 
                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-// Negation of eight packed BF16 values (sign bits flipped, as 32-bit words).
+// Negation of eight packed BF16 values: one 32-bit XOR of the two sign bits per register.
+// (Written as a vector XOR, the combiner narrows it to 16-bit lanes, which cost three
+// instructions per register.)
 __device__ __forceinline__ u16x8 bf16_neg(const u16x8& x) {
   typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
-  return __builtin_bit_cast(u16x8, __builtin_bit_cast(u32x4_t, x) ^ 0x80008000u);
+  u32x4_t v = __builtin_bit_cast(u32x4_t, x);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    unsigned int r;
+    asm("v_xor_b32 %0, 0x80008000, %1" : "=v"(r) : "v"(v[i]));
+    v[i] = r;
+  }
+  return __builtin_bit_cast(u16x8, v);
 }
 
 // d += (ah + al)(bh + bl) without the al bl term (three BF16 passes)
