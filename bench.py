@@ -310,15 +310,26 @@ def bench_path(name, p, U0d, xs, args, torch, cfg):
         if n:
             kern[kc] = {"ms_total": ms / args.steps, "launches": n // args.steps,
                         "ms_per_launch": ms / n}
+    # comb population control, the step between blocks (not part of the timed block)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    p.population_control(0.5)
+    ev[0].record()
+    for r in range(5):
+        p.population_control((r + 0.5) / 5)
+    ev[1].record()
+    torch.cuda.synchronize()
+    pc_ms = ev[0].elapsed_time(ev[1]) / 5
     dt = (t1 - t0) / args.steps
     ws = W * xs.shape[0] / dt
     log(f"[{name}] block {dt * 1e3:.2f} ms  -> {ws:.1f} walker-steps/s "
-        f"(with per-kernel events {(t3 - t2) / args.steps * 1e3:.2f} ms)")
+        f"(with per-kernel events {(t3 - t2) / args.steps * 1e3:.2f} ms); "
+        f"population control {pc_ms:.3f} ms")
     for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms_total"]):
         log(f"    {k:13s} {v['ms_total']:9.3f} ms/block  {v['launches']:4d} launches  "
             f"{v['ms_per_launch']:.4f} ms/launch")
     return {"ms_per_block": dt * 1e3, "walker_steps_per_s": ws, "kernels": kern,
-            "ms_per_block_with_kernel_events": (t3 - t2) / args.steps * 1e3}, E0, w0
+            "ms_per_block_with_kernel_events": (t3 - t2) / args.steps * 1e3,
+            "population_control_ms": round(pc_ms, 4)}, E0, w0
 
 
 def roofline(path_res, prec_key, cfg):

@@ -100,7 +100,8 @@ typedef enum {
   AFQMC_ENTRY_ORTHO = 5,
   AFQMC_ENTRY_ENERGY = 6,
   AFQMC_ENTRY_ENERGY_BACKWARD = 7,
-  AFQMC_ENTRY_STEP = 8            /* afqmc_kpt_step, graphs and afqmc_kpt_autotune */
+  AFQMC_ENTRY_STEP = 8,           /* afqmc_kpt_step, graphs and afqmc_kpt_autotune */
+  AFQMC_ENTRY_POPULATION = 9      /* afqmc_kpt_population_control */
 } afqmc_entry;
 
 /* Flags of afqmc_kpt_step and afqmc_kpt_graph_create (AFQMC_PROPAGATE_ORTHO
@@ -250,6 +251,25 @@ afqmc_status afqmc_kpt_energy_backward(const afqmc_kpt_problem* p, int nprob, co
  * complex128, device; NaN when every weight of a problem is 0.  FP64 sums. */
 afqmc_status afqmc_kpt_mixed_energy(const afqmc_kpt_problem* p, int nprob, const void* E,
                                     void* Emix, void* stream);
+
+/* Population control between blocks by the comb (the paper's blocks imply a branching
+ * step that it does not spell out; this is the standard comb, a stochastic
+ * reconfiguration driven by one uniform number per problem).  With the cumulative
+ * weights c_i = w_0 + ... + w_i, summed in FP64 in walker order, and c = c_{nwalk-1},
+ * copy j (0 <= j < nwalk) of the new population is the walker i with
+ *   c_{i-1} <= (j + xi) (c / nwalk) < c_i        (c_{-1} = 0),
+ * taken no later than the last walker of positive weight; so a walker of weight w_i
+ * gets floor or ceil of nwalk w_i / c copies, and one of weight 0 none.  U, Gh, logdet
+ * and status of the chosen walkers are copied in place and every weight becomes
+ * c / nwalk.  A problem with a negative or non-finite weight, or a total that is not
+ * positive, is left unchanged (parent[j] = j).
+ *   xi:     [nprob] host array, each in [0, 1)
+ *   parent: NULL, or [nprob] host array whose entries are NULL or device [nwalk] int32
+ *           outputs (the walker each copy came from)
+ * Workspace: AFQMC_ENTRY_POPULATION (a copy of U and Gh).  FP64 arithmetic. */
+afqmc_status afqmc_kpt_population_control(const afqmc_kpt_problem* p, int nprob,
+                                          const double* xi, int32_t* const* parent, void* ws,
+                                          size_t ws_bytes, void* stream);
 
 /* Packed layout of one per-call buffer for a batch (host).  offsets: host
  * array of nprob + 1 entries; offsets[i] is the byte offset of problem i's

@@ -37,6 +37,7 @@ ENTRIES = {
     "energy": 6,
     "energy_backward": 7,
     "step": 8,
+    "population": 9,
 }
 
 BUFFERS = {"fields": 0, "xbar": 1, "X": 2, "vhs": 3, "energy": 4, "gE": 5, "gGh": 6}
@@ -52,6 +53,7 @@ EXPORTS = [
     "afqmc_kpt_energy",
     "afqmc_kpt_energy_backward",
     "afqmc_kpt_mixed_energy",
+    "afqmc_kpt_population_control",
     "afqmc_kpt_buffer_layout",
     "afqmc_kpt_step",
     "afqmc_kpt_autotune",
@@ -134,6 +136,7 @@ def lib():
         "afqmc_kpt_energy": [P, i, vp, vp, sz, vp],
         "afqmc_kpt_energy_backward": [P, i, vp, vp, vp, sz, vp],
         "afqmc_kpt_mixed_energy": [P, i, vp, vp, vp],
+        "afqmc_kpt_population_control": [P, i, vp, vp, vp, sz, vp],
         "afqmc_kpt_buffer_layout": [P, i, i, ctypes.POINTER(sz)],
         "afqmc_kpt_step": [P, i, vp, i, vp, vp, vp, i, vp, sz, vp],
         "afqmc_kpt_autotune": [P, i, vp, vp, sz, vp],
@@ -344,6 +347,19 @@ class KptProblem:
                                            out.data_ptr(), _stream()))
         return out[0]
 
+    def population_control(self, xi):
+        """Comb population control with the uniform number xi in [0, 1): resamples U, Gh,
+        logdet and status in place, sets every weight to the mean weight; returns the
+        parent index of each new walker (int32, device)."""
+        parent = torch.empty(self.nwalk, dtype=torch.int32, device=self.device)
+        xs = (ctypes.c_double * 1)(float(xi))
+        pp = (ctypes.c_void_p * 1)(parent.data_ptr())
+        ws, nb = self._ws_args()
+        check("afqmc_kpt_population_control",
+              lib().afqmc_kpt_population_control(ctypes.byref(self.struct), 1, xs, pp, ws, nb,
+                                                 _stream()))
+        return parent
+
     def step(self, x, ortho=False, bufs=None):
         """force bias -> HS potential -> propagate (new Gh, logdet, weights)."""
         if bufs is None:
@@ -440,6 +456,19 @@ class KptBatch:
               lib().afqmc_kpt_mixed_energy(self.arr, self.n, self._E.data_ptr(), out.data_ptr(),
                                            _stream()))
         return out
+
+    def population_control(self, xis):
+        """Comb population control of every system (one uniform number per system); returns
+        the parent indices per system."""
+        parents = [torch.empty(p.nwalk, dtype=torch.int32, device=self.device)
+                   for p in self.problems]
+        xs = (ctypes.c_double * self.n)(*[float(x) for x in xis])
+        pp = (ctypes.c_void_p * self.n)(*[t.data_ptr() for t in parents])
+        ws = self.workspace()
+        check("afqmc_kpt_population_control",
+              lib().afqmc_kpt_population_control(self.arr, self.n, xs, pp, ws.data_ptr(),
+                                                 ws.numel(), _stream()))
+        return parents
 
     def greens(self):
         ws = self.workspace()

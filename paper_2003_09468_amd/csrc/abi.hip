@@ -15,6 +15,9 @@ size_t propagate_ws_bytes(const afqmc_kpt_problem& p);
 size_t ortho_ws_bytes(const afqmc_kpt_problem& p);
 size_t energy_ws_bytes(const afqmc_kpt_problem& p);
 size_t backward_ws_bytes(const afqmc_kpt_problem& p);
+size_t population_ws_bytes(const afqmc_kpt_problem& p);
+hipError_t run_population(const afqmc_kpt_problem* p, int nprob, const double* xi,
+                          int32_t* const* parent, void* ws, hipStream_t s);
 
 size_t ws_bytes_entry(const afqmc_kpt_problem& p, int entry) {
   Dims d = dims_of(p);
@@ -34,6 +37,7 @@ size_t ws_bytes_entry(const afqmc_kpt_problem& p, int entry) {
     case AFQMC_ENTRY_ORTHO: return ortho_ws_bytes(p);
     case AFQMC_ENTRY_ENERGY: return energy_ws_bytes(p);
     case AFQMC_ENTRY_ENERGY_BACKWARD: return backward_ws_bytes(p);
+    case AFQMC_ENTRY_POPULATION: return population_ws_bytes(p);
     case AFQMC_ENTRY_STEP: {
       size_t b = ws_bytes_entry(p, AFQMC_ENTRY_VBIAS);
       const size_t e[3] = {ws_bytes_entry(p, AFQMC_ENTRY_VHS), ws_bytes_entry(p, AFQMC_ENTRY_PROPAGATE),
@@ -272,7 +276,7 @@ afqmc_status afqmc_kpt_workspace_bytes(const afqmc_kpt_problem* p, int nprob, in
                                        size_t* bytes) {
   if (!bytes) return AFQMC_ENULL;
   if (!p) return AFQMC_ENULL;
-  if (nprob < 1 || entry < AFQMC_ENTRY_PREPARE || entry > AFQMC_ENTRY_STEP)
+  if (nprob < 1 || entry < AFQMC_ENTRY_PREPARE || entry > AFQMC_ENTRY_POPULATION)
     return AFQMC_EINVAL;
   size_t need = 0;
   for (int i = 0; i < nprob; ++i) {
@@ -404,6 +408,20 @@ afqmc_status afqmc_kpt_mixed_energy(const afqmc_kpt_problem* p, int nprob, const
   b.E = (void*)E;
   std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_ENERGY, nullptr, b);
   return hip_status(run_mixed_energy(jobs.data(), nprob, Emix, (hipStream_t)stream));
+}
+
+afqmc_status afqmc_kpt_population_control(const afqmc_kpt_problem* p, int nprob,
+                                          const double* xi, int32_t* const* parent, void* ws,
+                                          size_t ws_bytes, void* stream) {
+  AFQMC_TRY(check_problems(p, nprob, N_U | N_GH | N_LOGDET | N_WEIGHT | N_STATUS));
+  if (!xi) return AFQMC_ENULL;
+  for (int i = 0; i < nprob; ++i) {
+    if (!(xi[i] >= 0.0 && xi[i] < 1.0)) return AFQMC_EINVAL;
+    if (parent && parent[i] && misaligned(parent[i], 4)) return AFQMC_EALIGN;
+  }
+  AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_POPULATION, ws, ws_bytes));
+  AFQMC_TRY(check_device());
+  return hip_status(run_population(p, nprob, xi, parent, ws, (hipStream_t)stream));
 }
 
 afqmc_status afqmc_kpt_buffer_layout(const afqmc_kpt_problem* p, int nprob, int buf,

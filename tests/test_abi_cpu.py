@@ -80,12 +80,14 @@ def test_workspace_sizes_positive_and_stable(L):
     p = good_problem()
     out = ctypes.c_size_t()
     sizes = []
-    for e in range(9):
+    for e in range(10):
         assert L.afqmc_kpt_workspace_bytes(ctypes.byref(p), 1, e, ctypes.byref(out)) == 0
         sizes.append(out.value)
         assert out.value % 256 == 0
     assert all(s > 0 for s in sizes)
-    assert L.afqmc_kpt_workspace_bytes(ctypes.byref(p), 1, 9, ctypes.byref(out)) == -1
+    # population control holds a copy of U and Gh
+    assert sizes[9] >= 2 * 16 * 64 * (27 * 26) * (27 * 4)
+    assert L.afqmc_kpt_workspace_bytes(ctypes.byref(p), 1, 10, ctypes.byref(out)) == -1
     assert L.afqmc_kpt_workspace_bytes(ctypes.byref(p), 1, 0, None) == -2
 
 
@@ -294,3 +296,34 @@ def test_mixed_energy_validation(L):
     arr[1].weight = None
     assert L.afqmc_kpt_mixed_energy(arr, 2, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x4000),
                                     None) == -2
+
+
+def test_population_control_validation(L):
+    p = good_problem()
+    out = ctypes.c_size_t()
+    assert L.afqmc_kpt_workspace_bytes(ctypes.byref(p), 1, 9, ctypes.byref(out)) == 0
+    need = out.value
+    ws = ctypes.c_void_p(0x1000000)
+    f = L.afqmc_kpt_population_control
+
+    def xs(v):
+        return (ctypes.c_double * 1)(v)
+
+    assert f(ctypes.byref(p), 1, None, None, ws, need, None) == -2
+    for bad in (1.0, -0.25, float("nan"), float("inf")):
+        assert f(ctypes.byref(p), 1, xs(bad), None, ws, need, None) == -1
+    misaligned = (ctypes.c_void_p * 1)(0x2002)
+    assert f(ctypes.byref(p), 1, xs(0.5), misaligned, ws, need, None) == -3
+    assert f(ctypes.byref(p), 1, xs(0.5), None, ws, need - 1, None) == -4
+    assert f(ctypes.byref(p), 1, xs(0.5), None, None, need, None) == -4
+    q = good_problem()
+    q.status = None
+    assert f(ctypes.byref(q), 1, xs(0.5), None, ws, need, None) == -2
+    assert f(ctypes.byref(p), 0, xs(0.5), None, ws, need, None) == -1
+    # valid arguments: the device check comes first (only without a GPU: the pointers
+    # here are fake)
+    from tests.conftest import gpu_available
+    if not gpu_available():
+        aligned = (ctypes.c_void_p * 1)(0x2000)
+        assert f(ctypes.byref(p), 1, xs(0.0), aligned, ws, need, None) == -5
+        assert f(ctypes.byref(p), 1, xs(0.999), None, ws, need, None) == -5

@@ -408,3 +408,76 @@ def test_mixed_energy_on_trial_walkers_is_slater_condon():
     E = kp.local_energy(pre["Lh"], pre["h1h"], Gh, s.mesh)
     e_hf = sum(sc.slater_condon_energy(h, v, Af))
     assert abs(kp.mixed_energy(E, [0.2, 3.0, 1.0]) - e_hf) < 1e-11 * max(1.0, abs(e_hf))
+
+
+# ---------------------------------------------------------------------------
+# population control (comb): properties any correct comb has
+# ---------------------------------------------------------------------------
+
+from oracle import walkers as wk
+
+
+def test_comb_worked_example():
+    # cumulative weights 0.5, 2.0, 2.0, 4.0; points 0.25, 1.25, 2.25, 3.25 (spacing 1)
+    par = wk.comb_parents([0.5, 1.5, 0.0, 2.0], 0.25)
+    assert par.tolist() == [0, 1, 3, 3]
+    # the point 2.0 lies on the boundary after the empty interval of walker 2
+    assert wk.comb_parents([0.5, 1.5, 0.0, 2.0], 0.0).tolist() == [0, 1, 3, 3]
+    assert wk.comb_parents([1.0, 0.0, 0.0, 3.0], 0.5).tolist() == [0, 3, 3, 3]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_comb_copy_counts_are_floor_or_ceiling(seed):
+    rng = np.random.default_rng(seed)
+    W = 64
+    w = rng.exponential(size=W)
+    w[rng.choice(W, 9, replace=False)] = 0.0
+    for xi in rng.random(20):
+        par = wk.comb_parents(w, xi)
+        n = np.bincount(par, minlength=W)
+        expect = W * w / w.sum()
+        assert n.sum() == W
+        assert np.all(n >= np.floor(expect) - 1e-12) and np.all(n <= np.ceil(expect) + 1e-12)
+        assert np.all(n[w == 0] == 0)
+        assert np.all(np.diff(par) >= 0)  # copies come out in walker order
+
+
+def test_comb_unbiased_over_xi():
+    rng = np.random.default_rng(7)
+    W = 16
+    w = rng.exponential(size=W)
+    S = 4000
+    n = np.zeros(W)
+    for s in range(S):
+        n += np.bincount(wk.comb_parents(w, (s + 0.5) / S), minlength=W)
+    # the midpoint rule in xi is exact up to one point per interval boundary crossing
+    assert np.allclose(n / S, W * w / w.sum(), atol=2.0 / S)
+
+
+def test_comb_identity_and_degenerate_cases():
+    W = 10
+    for xi in (0.0, 0.3, 0.999):
+        assert wk.comb_parents(np.full(W, 2.5), xi).tolist() == list(range(W))
+    assert wk.comb_parents(np.zeros(W), 0.4).tolist() == list(range(W))
+    bad = np.ones(W)
+    bad[3] = -1.0
+    assert wk.comb_parents(bad, 0.4).tolist() == list(range(W))
+    bad[3] = np.nan
+    assert wk.comb_parents(bad, 0.4).tolist() == list(range(W))
+    one = np.zeros(W)
+    one[6] = 1e-300
+    assert wk.comb_parents(one, 0.999999).tolist() == [6] * W
+
+
+def test_population_control_state():
+    rng = np.random.default_rng(3)
+    W = 8
+    U = rng.normal(size=(W, 5, 2)) + 1j * rng.normal(size=(W, 5, 2))
+    G = rng.normal(size=(W, 2, 5)) + 0j
+    ld = rng.normal(size=W) + 1j * rng.normal(size=W)
+    st = np.arange(W, dtype=np.int32)
+    w = rng.exponential(size=W)
+    U2, G2, ld2, st2, w2, par = wk.population_control(U, G, ld, st, w, 0.6)
+    assert np.array_equal(U2, U[par]) and np.array_equal(G2, G[par])
+    assert np.array_equal(ld2, ld[par]) and np.array_equal(st2, st[par])
+    assert np.allclose(w2, w.sum() / W) and np.isclose(w2.sum(), w.sum())
