@@ -821,6 +821,7 @@ def main():
                       "ms_per_block_with_kernel_events":
                           round(v["ms_per_block_with_kernel_events"], 3),
                       "energy_evals_per_s": energy_evals(v, cfg),
+                      "population_control_ms": v.get("population_control_ms"),
                       "kernels": {kk: {"ms_per_block": round(vv["ms_total"], 4),
                                        "launches": vv["launches"],
                                        "ms_per_launch": round(vv["ms_per_launch"], 5)}

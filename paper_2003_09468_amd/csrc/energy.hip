@@ -430,7 +430,11 @@ __global__ __launch_bounds__(256) void exchange_bf16x3_q4_kernel(const Batch<Exc
   constexpr int DEPTH = 2;          // chunks in flight (3 waves per SIMD at K = 32)
   constexpr int TS = 20;             // transpose tile row stride (words)
 
-  __shared__ __attribute__((aligned(16))) unsigned short LA[2][2][4][16][RS];  // [buf][slab][plane][(g, a)][r]
+  // [buf][slab][plane][(g, a) r]: rows of RS (80 bytes: the 16 rows of one fragment read hit
+  // distinct banks), planes padded by 64 bytes (the staging stores of 4 planes x 4 units
+  // hit distinct banks)
+  constexpr int PS = 16 * RS + 32;
+  __shared__ __attribute__((aligned(16))) unsigned short LA[2][2][4][PS];
   __shared__ __attribute__((aligned(16))) float XT[4][WT][2][16 * TS];         // [wave][ct][re/im][quad][.]
   __shared__ double red[2][256];
 
@@ -508,7 +512,7 @@ __global__ __launch_bounds__(256) void exchange_bf16x3_q4_kernel(const Batch<Exc
       const int row = u / (4 * UPR), pl = (u / UPR) % 4, r8 = u % UPR;
       u4 v = xu[e];
       if (!full && 4 * c + row / 4 >= C) v = u4{0u, 0u, 0u, 0u};
-      *reinterpret_cast<u4*>(&LA[buf][sl][pl][row][r8 * 8]) = v;
+      *reinterpret_cast<u4*>(&LA[buf][sl][pl][row * RS + r8 * 8]) = v;
     }
   };
 
@@ -544,7 +548,7 @@ __global__ __launch_bounds__(256) void exchange_bf16x3_q4_kernel(const Batch<Exc
             u16x8 x[4];
 #pragma unroll
             for (int pl = 0; pl < 4; ++pl)
-              x[pl] = *reinterpret_cast<const u16x8*>(&LA[buf][sl][pl][col][r0]);
+              x[pl] = *reinterpret_cast<const u16x8*>(&LA[buf][sl][pl][col * RS + r0]);
             const u16x8 n2 = bf16_neg(x[2]), n3 = bf16_neg(x[3]);
 #pragma unroll
             for (int ct = 0; ct < WT; ++ct) {

@@ -144,6 +144,7 @@ struct VbBfArgs {
 
 __global__ __launch_bounds__(256) void vbias_bf16x3_kernel(const Batch<VbBfArgs> B) {
   constexpr int BG = 64, BW = 64, RS = 40;
+  // (no plane padding: the two stages fill exactly half of the LDS, two workgroups per CU)
   __shared__ __attribute__((aligned(16))) unsigned short sA[2][4][BG][RS];
   __shared__ __attribute__((aligned(16))) unsigned short sB[2][4][BW][RS];
   long long loc;
@@ -508,8 +509,11 @@ struct VhsPos {
 
 __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> B) {
   constexpr int BM = 64, BN = 128, BKC = 32, RS = BKC + 8, DEPTH = 2;
-  __shared__ __attribute__((aligned(16))) unsigned short sA[2][4][BM][RS];
-  __shared__ __attribute__((aligned(16))) unsigned short sB[2][4][BN][RS];
+  // planes padded by 64 bytes: a 16-byte staging store of 16 lanes covers 4 planes x 4
+  // units, which unpadded plane strides (multiples of 256 bytes) put in one bank group
+  constexpr int PSA = BM * RS + 32, PSB = BN * RS + 32;
+  __shared__ __attribute__((aligned(16))) unsigned short sA[2][4][PSA];
+  __shared__ __attribute__((aligned(16))) unsigned short sB[2][4][PSB];
   const long long ntiles = B.first[B.nprob];
   const long long G = gridDim.x;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -579,13 +583,13 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
       for (int e = 0; e < 4; ++e) {
         const int u = pt + 256 * e;
         const u4 z = {0u, 0u, 0u, 0u};
-        *reinterpret_cast<u4*>(&sA[st][(u >> 2) & 3][u >> 4][8 * (u & 3)]) =
+        *reinterpret_cast<u4*>(&sA[st][(u >> 2) & 3][(u >> 4) * RS + 8 * (u & 3)]) =
             row0 + (u >> 4) < a.W ? xa[e] : z;
       }
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int u = pt + 256 * e;
-        *reinterpret_cast<u4*>(&sB[st][(u >> 2) & 3][u >> 4][8 * (u & 3)]) = xb[e];
+        *reinterpret_cast<u4*>(&sB[st][(u >> 2) & 3][(u >> 4) * RS + 8 * (u & 3)]) = xb[e];
       }
     };
 #pragma unroll
@@ -635,7 +639,7 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
         for (int i = 0; i < 2; ++i)
 #pragma unroll
           for (int pl = 0; pl < 4; ++pl)
-            fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][pl][wm * 32 + i * 16 + (lane & 15)][kq]);
+            fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][pl][(wm * 32 + i * 16 + (lane & 15)) * RS + kq]);
         const u16x8 fn[2][2] = {{bf16_neg(fa[0][2]), bf16_neg(fa[0][3])},
                                 {bf16_neg(fa[1][2]), bf16_neg(fa[1][3])}};
 #pragma unroll
@@ -643,7 +647,7 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
           u16x8 fb[4];
 #pragma unroll
           for (int pl = 0; pl < 4; ++pl)
-            fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][wn * 64 + j * 16 + (lane & 15)][kq]);
+            fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][(wn * 64 + j * 16 + (lane & 15)) * RS + kq]);
 #pragma unroll
           for (int i = 0; i < 2; ++i) {
             // re += Zr Lr - Zi Li,  im += Zr Li + Zi Lr  (fn: -Zi)

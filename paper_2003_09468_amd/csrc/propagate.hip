@@ -259,14 +259,18 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
   constexpr int NUA = BM / 16;      // A units per producer thread
   constexpr int DEPTH = (NB >= 6 || BM > 64) ? 2 : 3;  // chunks in flight (register budget)
   constexpr int CB = (NB + 1) / 2;
-  constexpr int SA_BYTES = 2 * 4 * BM * RS * 2, SB_BYTES = 2 * 4 * BN * RS * 2;
+  // B planes padded by 64 bytes: a 16-byte staging store of 16 lanes covers 4 planes x 4
+  // units, and unpadded plane strides (a multiple of 256 bytes) would put them in one bank
+  // group
+  constexpr int PSB = BN * RS + 32;
+  constexpr int SA_BYTES = 2 * 4 * BM * RS * 2, SB_BYTES = 2 * 4 * PSB * 2;
   constexpr int RST = BN + 1;  // row stride of the result tile (float2)
   constexpr int RES_BYTES = BM * RST * 8;
   constexpr int LDS_BYTES =
       SA_BYTES + SB_BYTES > RES_BYTES ? SA_BYTES + SB_BYTES : RES_BYTES;
   __shared__ __attribute__((aligned(16))) unsigned char lds[LDS_BYTES];
   auto sA = reinterpret_cast<unsigned short (*)[4][BM][RS]>(lds);
-  auto sB = reinterpret_cast<unsigned short (*)[4][BN][RS]>(lds + SA_BYTES);
+  auto sB = reinterpret_cast<unsigned short (*)[4][PSB]>(lds + SA_BYTES);
   auto res = reinterpret_cast<float2 (*)[RST]>(lds);  // after the K loop
   long long loc;
   const int pb = batch_find(B, blockIdx.x, loc);
@@ -331,7 +335,7 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
 #pragma unroll
       for (int e = 0; e < NB; ++e) {
         const int u = pt + 256 * e;
-        *reinterpret_cast<u32x4*>(&sB[st][(u >> 2) & 3][u >> 4][8 * (u & 3)]) = xb[e];
+        *reinterpret_cast<u32x4*>(&sB[st][(u >> 2) & 3][(u >> 4) * RS + 8 * (u & 3)]) = xb[e];
       }
     };
 #pragma unroll
@@ -389,7 +393,7 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
               u16x8 fb[4];
 #pragma unroll
               for (int pl = 0; pl < 4; ++pl)
-                fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][16 * (cb0 + j) + (lane & 15)][kq]);
+                fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][(16 * (cb0 + j) + (lane & 15)) * RS + kq]);
 #pragma unroll
               for (int i = 0; i < RB; ++i) {
                 // re += Vr Tr - Vi Ti,  im += Vr Ti + Vi Tr  (fn: -Vi)
