@@ -68,7 +68,7 @@ KERNEL_NAMES = {
 # the BF16X3 kernels of the same classes
 KERNEL_NAMES_BF16X3 = {
     "taylor": "taylor_bf16x3_kernel", "vhs": "vhs_bf16x3_kernel",
-    "vbias": "vbias_bf16x3_kernel", "exchange": "exchange_bf16x3_kernel",
+    "vbias": "vbias_bf16x3_kernel", "exchange": "exchange_bf16x3",
 }
 
 
