@@ -332,9 +332,13 @@ def bench_path(name, p, U0d, xs, args, torch, cfg):
             "population_control_ms": round(pc_ms, 4)}, E0, w0
 
 
-def roofline(path_res, prec_key, cfg):
+def roofline(path_res, prec_key, cfg, kernel=None):
+    """Roofline of one kernel class of a path (default: the one with the most time per
+    block)."""
     kern = path_res["kernels"]
-    dom = max(kern, key=lambda k: kern[k]["ms_total"])
+    dom = kernel if kernel is not None else max(kern, key=lambda k: kern[k]["ms_total"])
+    if dom not in kern:
+        return None
     fl = kernel_flops(dom, cfg)
     if fl is None:
         return {"kernel": dom, "bound": "alu", "achieved": None, "peak": None, "unit": None,
@@ -826,7 +830,8 @@ def main():
                                        "launches": vv["launches"],
                                        "ms_per_launch": round(vv["ms_per_launch"], 5)}
                                   for kk, vv in v["kernels"].items()},
-                      "roofline_dominant": roofline(v, k, cfg)}
+                      "roofline_dominant": roofline(v, k, cfg),
+                      "roofline_exchange": roofline(v, k, cfg, "exchange")}
                   for k, v in res.items()},
         "accuracy": acc,
     }

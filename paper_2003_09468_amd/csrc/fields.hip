@@ -501,10 +501,13 @@ struct VhsBfArgs {
   cpx<float>* vhs;           // [W][nk m][nk m]
 };
 
-// Position of a workgroup in its stream of (tile, chunk) pairs.
+// Position of a workgroup in its stream of (tile, chunk) pairs, with the tile decoded
+// once when the stream reaches it (the decode takes a batch lookup and 64-bit divisions,
+// too slow to repeat for every chunk).
 struct VhsPos {
-  long long tile;  // global tile index
+  long long tile;  // global tile index (past the end: decoded as the last tile)
   int chunk;
+  int p, nchk, Q, row0, col0;
 };
 
 __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> B) {
@@ -519,19 +522,27 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if ((long long)blockIdx.x >= ntiles) return;
-  // number of chunks of a tile, and the stream length of this workgroup
-  auto nchunks = [&](long long t) {
+  auto decode = [&](long long t, VhsPos& ps) {
+    ps.tile = t;
+    ps.chunk = 0;
     long long loc;
-    const int p = batch_find(B, t, loc);
-    return B.a[p].CP / BKC;
+    ps.p = batch_find(B, t < ntiles ? t : ntiles - 1, loc);
+    const VhsBfArgs& a = B.a[ps.p];
+    const int per_q = a.tiles_m * a.tiles_n;
+    ps.Q = (int)(loc / per_q);
+    const int rem = (int)(loc % per_q);
+    ps.row0 = (rem / a.tiles_n) * BM;
+    ps.col0 = (rem % a.tiles_n) * BN;
+    ps.nchk = a.CP / BKC;
   };
+  // the stream length of this workgroup
   long long total = 0;
-  for (long long t = blockIdx.x; t < ntiles; t += G) total += nchunks(t);
+  for (long long t = blockIdx.x; t < ntiles; t += G) {
+    long long loc;
+    total += B.a[batch_find(B, t, loc)].CP / BKC;
+  }
   auto advance = [&](VhsPos& ps) {
-    if (++ps.chunk == nchunks(ps.tile)) {
-      ps.chunk = 0;
-      ps.tile += G;
-    }
+    if (++ps.chunk == ps.nchk) decode(ps.tile + G, ps);
   };
 
   if (wave >= 4) {
@@ -540,19 +551,16 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
     const int pt = threadIdx.x - 256;
     typedef unsigned int u4 __attribute__((ext_vector_type(4)));
     u4 ra[DEPTH][4], rb[DEPTH][8];
-    VhsPos ip{(long long)blockIdx.x, 0}, sp{(long long)blockIdx.x, 0};
+    VhsPos ip, sp;
+    decode(blockIdx.x, ip);
+    sp = ip;
     long long issued = 0;
     auto issue = [&](u4 (&xa)[4], u4 (&xb)[8]) {
-      // past the end of the stream: reload the last chunk (never stored)
-      const VhsPos q = issued < total ? ip : VhsPos{ip.tile - G, 0};
-      long long loc;
-      const int p = batch_find(B, q.tile < ntiles ? q.tile : ntiles - 1, loc);
-      const VhsBfArgs& a = B.a[p];
-      const int per_q = a.tiles_m * a.tiles_n;
-      const int Q = (int)(loc / per_q), rem = (int)(loc % per_q);
-      const int row0 = (rem / a.tiles_n) * BM, col0 = (rem % a.tiles_n) * BN;
+      // past the end of the stream: chunk 0 of the last tile again (never stored)
+      const VhsBfArgs& a = B.a[ip.p];
+      const int Q = ip.Q, row0 = ip.row0, col0 = ip.col0;
       const int ncol = a.nk * a.m * a.m, CP = a.CP;
-      const int k0 = (issued < total ? q.chunk : 0) * BKC;
+      const int k0 = (issued < total ? ip.chunk : 0) * BKC;
       const unsigned short* __restrict__ Lq = a.Ls + (int64_t)Q * ncol * 4 * CP;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -574,11 +582,8 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
     };
     auto stash = [&](int st, const u4 (&xa)[4], const u4 (&xb)[8]) {
       // rows past W: zeros (their loads were clamped); columns past ncol are not stored
-      long long loc;
-      const int p = batch_find(B, sp.tile < ntiles ? sp.tile : ntiles - 1, loc);
-      const VhsBfArgs& a = B.a[p];
-      const int rem = (int)(loc % (a.tiles_m * a.tiles_n));
-      const int row0 = (rem / a.tiles_n) * BM;
+      const VhsBfArgs& a = B.a[sp.p];
+      const int row0 = sp.row0;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int u = pt + 256 * e;
@@ -626,7 +631,8 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
       }
   };
   zero();
-  VhsPos cp{(long long)blockIdx.x, 0};
+  VhsPos cp;
+  decode(blockIdx.x, cp);
   __syncthreads();
   for (long long s0 = 0; s0 < total; s0 += DEPTH) {
 #pragma unroll
@@ -657,14 +663,10 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
             aci[i][j] = mul3(fa[i][2], fa[i][3], fb[0], fb[1], aci[i][j]);
           }
         }
-        long long loc;
-        const int p = batch_find(B, cp.tile, loc);
-        const VhsBfArgs& a = B.a[p];
-        if (cp.chunk + 1 == a.CP / BKC) {
+        if (cp.chunk + 1 == cp.nchk) {
           // tile done: column (k p r) of Q to vhs[w][(k p)][((k - Q) r)]
-          const int per_q = a.tiles_m * a.tiles_n;
-          const int Q = (int)(loc / per_q), rem = (int)(loc % per_q);
-          const int row0 = (rem / a.tiles_n) * BM, col0 = (rem % a.tiles_n) * BN;
+          const VhsBfArgs& a = B.a[cp.p];
+          const int Q = cp.Q, row0 = cp.row0, col0 = cp.col0;
           const int m = a.m, mm = m * m, ncol = a.nk * mm;
           const int64_t Nn = (int64_t)a.nk * m;
 #pragma unroll
