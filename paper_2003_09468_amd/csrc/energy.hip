@@ -427,7 +427,7 @@ __global__ __launch_bounds__(256) void exchange_bf16x3_q4_kernel(const Batch<Exc
   constexpr int UPR = KP / 8;        // 16-byte units per (row, plane)
   constexpr int CU = 16 * 4 * UPR;   // units of one slab chunk: rows (g, a) x planes x r
   constexpr int NU = 2 * CU / 256;   // units per thread (both slabs)
-  constexpr int DEPTH = 2;          // chunks in flight (3 waves per SIMD at K = 32)
+  constexpr int DEPTH = 2;           // chunks in flight (3 waves per SIMD at K = 32)
   constexpr int TS = 20;             // transpose tile row stride (words)
 
   // [buf][slab][plane][(g, a) r]: rows of RS (80 bytes: the 16 rows of one fragment read hit

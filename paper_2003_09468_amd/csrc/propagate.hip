@@ -226,18 +226,18 @@ static hipError_t launch_t_split(const Job* jobs, const int* ids, int c, void* c
   return hipGetLastError();
 }
 
-// One step, R_{j-1} = T_0 + alpha vhs R_j, one 512-thread workgroup per (walker,
-// BM-row tile (64 or 96), column tile of 16 NB columns).  Waves 4-7 produce: they stream the
-// complex64 rows of vhs (from HBM) with DEPTH chunks of K in flight in registers and split
-// them into BF16 planes, and copy the chunk's R_j planes (from L2), into two LDS
-// stages.  Waves 0-3 consume, in 2 x 2: wave (wm, wn) owns rows BM/2 wm .. BM/2 (wm + 1) - 1
-// and the first ceil(NB / 2) (wn = 0) or the remaining (wn = 1) 16-column blocks, with 12 BF16
-// MFMAs per complex 16 x 16 x 32 block and FP32 accumulation.  One block barrier per K
-// chunk.  In the epilogue the consumers leave alpha (vhs R_j) in LDS (over the stages)
-// and all eight waves add T_0 to it: from complex64 into the planes of R_{j-1}, or, in
-// the last step, into the FP64 accumulator that holds T_0 (every load issued before the
-// first store).  Workgroups of one walker are placed on one XCD, where its planes stay in
-// L2.
+// One step, R_{j-1} = T_0 + alpha vhs R_j, one workgroup per (walker, BM-row tile (64 or
+// 96), column tile of 16 NB columns) with NCW consumer waves and 4 producer waves.  The
+// producers (the last four waves) stream the complex64 rows of vhs (from HBM) with DEPTH
+// chunks of K in flight in registers and split them into BF16 planes, and copy the chunk's
+// R_j planes (from L2), into two LDS stages.  The consumers sit in a 2 x NCW/2 grid: wave
+// (wm, wn) owns rows BM/2 wm .. BM/2 (wm + 1) - 1 and 16-column blocks CB wn .. CB (wn + 1)
+// - 1 (CB = ceil(NB / (NCW / 2))), with 12 BF16 MFMAs per complex 16 x 16 x 32 block and
+// FP32 accumulation.  One block barrier per K chunk.  In the epilogue the consumers leave
+// alpha (vhs R_j) in LDS (over the stages) and all waves add T_0 to it: from complex64 into
+// the planes of R_{j-1}, or, in the last step, into the FP64 accumulator that holds T_0
+// (every load issued before the first store).  Workgroups of one walker are placed on one
+// XCD, where its planes stay in L2.
 // Producer loads are unconditional (clamped addresses, zeros selected afterwards) so that
 // each wait covers exactly the oldest chunk.
 struct TaylorBfArgs {
@@ -251,14 +251,18 @@ struct TaylorBfArgs {
   cpx<double>* acc;           // [W][M][N] T_0 in FP64; R_0 after the last step
 };
 
-template <int BM, int NB, bool VEC>
-__global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBfArgs> B) {
+template <int BM, int NB, bool VEC, int NCW>
+__global__ __launch_bounds__(64 * NCW + 256) void taylor_bf16x3_kernel(const Batch<TaylorBfArgs> B) {
   constexpr int BN = 16 * NB, BKC = 32, RS = BKC + 8;
-  constexpr int NCW = 4, NT = 512;  // 4 consumer waves (2 x 2), then 4 producer waves
-  constexpr int RB = BM / 32;       // 16-row blocks per consumer wave
+  // NCW consumer waves in a 2 x NCW / 2 grid, then 4 producer waves
+  constexpr int NT = 64 * NCW + 256, GM = 2, GN = NCW / GM;
+  constexpr int RB = BM / (16 * GM);  // 16-row blocks per consumer wave
+  static_assert(RB * 16 * GM == BM, "row tile must split evenly over the consumer rows");
   constexpr int NUA = BM / 16;      // A units per producer thread
-  constexpr int DEPTH = (NB >= 6 || BM > 64) ? 2 : 3;  // chunks in flight (register budget)
-  constexpr int CB = (NB + 1) / 2;
+  // chunks in flight in the producers' registers: the register budget of 3 waves per SIMD
+  // leaves room for one with 8 consumer waves
+  constexpr int DEPTH = NCW > 4 ? 1 : ((NB >= 6 || BM > 64) ? 2 : 3);
+  constexpr int CB = (NB + GN - 1) / GN;  // 16-column blocks per consumer wave
   // B planes padded by 64 bytes: a 16-byte staging store of 16 lanes covers 4 planes x 4
   // units, and unpadded plane strides (a multiple of 256 bytes) would put them in one bank
   // group
@@ -359,7 +363,7 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
     }
   } else {
     // ---------------- consumers
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / GN, wn = wave % GN;
     v4f acr[RB][CB], aci[RB][CB];
 #pragma unroll
     for (int i = 0; i < RB; ++i)
@@ -368,7 +372,7 @@ __global__ __launch_bounds__(512) void taylor_bf16x3_kernel(const Batch<TaylorBf
         acr[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
         aci[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
       }
-    const int cb0 = wn ? CB : 0, ncb = wn ? NB - CB : CB;
+    const int cb0 = wn * CB, ncb = NB - cb0 < CB ? NB - cb0 : CB;
     __syncthreads();
     // as many barriers as the producers: ceil(nch / DEPTH) DEPTH iterations
     for (int c0 = 0; c0 < nch; c0 += DEPTH) {
@@ -554,10 +558,13 @@ static hipError_t launch_taylor_bf16x3(const Job* jobs, const int* ids, int c, i
   const long long g = batch_close(Bt, cnt);
   if (g < 0) return hipErrorInvalidValue;
   if (g == 0) return hipSuccess;
-  const dim3 grid((unsigned)g), block(512);
+  // 8 consumer waves (2 x 4): two per SIMD, so one wave's LDS reads and barrier waits
+  // overlap the other's MFMAs (with 4 consumers the MFMA pipe idled two thirds of the time)
+  constexpr int NCWL = 8;
+  const dim3 grid((unsigned)g), block(64 * NCWL + 256);
 #define AFQMC_TBF(BMV, NBV)                                                              \
-  if (vec) hipLaunchKernelGGL((taylor_bf16x3_kernel<BMV, NBV, true>), grid, block, 0, s, Bt); \
-  else hipLaunchKernelGGL((taylor_bf16x3_kernel<BMV, NBV, false>), grid, block, 0, s, Bt);
+  if (vec) hipLaunchKernelGGL((taylor_bf16x3_kernel<BMV, NBV, true, NCWL>), grid, block, 0, s, Bt); \
+  else hipLaunchKernelGGL((taylor_bf16x3_kernel<BMV, NBV, false, NCWL>), grid, block, 0, s, Bt);
 #define AFQMC_TBF_NB(BMV)     \
   switch (nb) {               \
     case 1: AFQMC_TBF(BMV, 1) break; \
