@@ -163,7 +163,7 @@ def reduce_pmc(fetch_csv, write_csv):
     base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
     json.dump(rec, open(os.path.join(base, "traffic_c1.json"), "w"), indent=1)
     lines = ["# HBM traffic per launch, c1 FP64 and BF16X3 paths (rocprofv3 counters)", "",
-             "Commands (repository root on the GPU box; each counter in its own run):", "",
+             "Commands (repository root, on the MI355X; each counter in its own run):", "",
              "```", "cd /tmp && export TMPDIR=/tmp && cd \"$GRAFT_REPO_ROOT\"",
              "timeout -s KILL 400 rocprofv3 --pmc FETCH_SIZE --output-format csv "
              "-d gpurun_out/pmc_fetch -o run -- \\",
@@ -223,7 +223,7 @@ def reduce_mfma(csv_path, out_md, title, command):
         a["mops"] += sum(x for c, x in v.items() if c.startswith("SQ_INSTS_VALU_MFMA_MOPS"))
         a["ns"] += dur[key]
     rows = sorted(agg.items(), key=lambda kv: -kv[1]["active"])
-    lines = [f"# MFMA utilisation: {title}", "", "Command (repository root on the GPU box):", "",
+    lines = [f"# MFMA utilisation: {title}", "", "Command (repository root, on the MI355X):", "",
              "```", "cd /tmp && export TMPDIR=/tmp && cd \"$GRAFT_REPO_ROOT\"", command,
              f"python3 bench.py --reduce-mfma <run_counter_collection.csv> {out_md}", "```", "",
              "MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (active cycles x 1024 SIMDs), with the "
@@ -712,7 +712,7 @@ def main():
         reduce_mfma(args.reduce_mfma[0], args.reduce_mfma[1], args.title, args.command)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
               "(sharding walkers or Q blocks across GPUs is not built).",
               file=sys.stderr)
         sys.exit(2)
