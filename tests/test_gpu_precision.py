@@ -77,3 +77,18 @@ def test_bf16x3_step_wide_column_tiles(shape):
     p.step(torch.from_numpy(x[0]))
     torch.cuda.synchronize()
     assert rel(host(p.U), out["U"]) < 5e-5
+
+
+@pytest.mark.parametrize("shape", [((2, 1, 1), 40, 4, 30, 21, "random", "dense"),
+                                   ((1, 2, 1), 36, 3, 22, 9, "random", "dense")],
+                         ids=["m40_nocc4", "m36_nocc3"])
+def test_bf16x3_energy_two_k_blocks(shape):
+    """BF16X3 exchange with m > 32 (two 32-wide K blocks per MFMA chain, one column tile
+    per wave): the nocc = 4 kernel and the general one, ragged walker chunks."""
+    s, U, x, p, pre = build(shape, prec=2)
+    Gh, _ = kp.greens(U, s.A)
+    E = kp.local_energy(pre["Lh"], pre["h1h"], Gh, s.mesh)
+    Eg = host(p.energy())
+    scale = np.abs(E).sum(1)
+    assert (np.abs(Eg.sum(1) - E.sum(1)) / scale).max() < 5e-5
+    assert np.abs(Eg[:, 2] - E[:, 2]).max() / np.abs(E[:, 2]).max() < 1e-4
