@@ -100,12 +100,20 @@ size_t carve_vbias(Carve& c, const Dims& d, VbiasWs& v) {
   return c.off;
 }
 
+// K slices of the force bias of one problem: at most 4.  At c1 the BF16X3 kernel's 432
+// workgroups then fill the chip in one round, where 8 slices take 864 in 1.7 rounds (0.108
+// instead of 0.135 ms); the FP64 GEMM gains 5% (0.29 instead of 0.31 ms).  The workspace
+// is sized for the uncapped count, which is not smaller.
+static int vbias_slices(const afqmc_kpt_problem& p) {
+  const int s = vbias_splits(dims_of(p));
+  return s > 4 ? 4 : s;
+}
+
 template <typename T>
 static OpVbias<T> vbias_op(const afqmc_kpt_problem& p, void* parts) {
-  Dims d = dims_of(p);
   OpVbias<T> op;
   op.nk = p.nk; op.m = p.m; op.nocc = p.nocc; op.C = p.nchol;
-  op.S = vbias_splits(d);
+  op.S = vbias_slices(p);
   op.kper = (p.nk + op.S - 1) / op.S;
   op.mesh = make_mesh(p);
   op.M = p.nchol;
@@ -125,15 +133,6 @@ static hipError_t vbias_tiles(const OpVbias<T>* ops, int c, int choice, hipStrea
     case 2: return launch_ops<64, 32, 16, 4, 1>(ops, c, s);
     default: return launch_ops<64, 64, 16, 2, 2>(ops, c, s);
   }
-}
-
-// K slices of the force bias of one problem: the BF16X3 kernel takes at most 4 (at c1
-// its 432 workgroups then fill the chip in one round, where 8 slices take 864 in 1.7
-// rounds: 0.108 instead of 0.135 ms); the GEMM path keeps the general count.  The
-// workspace is sized for the general count, which is not smaller.
-static int vbias_slices(const afqmc_kpt_problem& p) {
-  const int s = vbias_splits(dims_of(p));
-  return (p.prec == AFQMC_PREC_BF16X3 && s > 4) ? 4 : s;
 }
 
 // Split-K partial traces on the three-pass BF16 split (BF16X3 mode):
