@@ -249,8 +249,10 @@ hipError_t run_steps(std::vector<Job>& jobs, const double* x, size_t stride, int
 afqmc_status check_step_args(const afqmc_kpt_problem* p, int nprob, const double* x, int nsteps,
                              void* xbar, void* vhs, void* E, int flags, void* ws,
                              size_t ws_bytes) {
-  unsigned need = N_L | N_LS | N_LH | N_A | N_BHALF | N_U | N_GH | N_LOGDET | N_WEIGHT | N_STATUS;
-  if (flags & AFQMC_STEP_ENERGY) need |= N_H1H | N_LHS;
+  // every step runs the force bias, whose BF16X3 kernel reads the split planes Lhs
+  unsigned need = N_L | N_LS | N_LH | N_LHS | N_A | N_BHALF | N_U | N_GH | N_LOGDET | N_WEIGHT |
+                  N_STATUS;
+  if (flags & AFQMC_STEP_ENERGY) need |= N_H1H;
   AFQMC_TRY(check_problems(p, nprob, need));
   if (nsteps < 1) return AFQMC_EINVAL;
   if (flags & ~(AFQMC_PROPAGATE_ORTHO | AFQMC_STEP_ENERGY)) return AFQMC_EINVAL;
@@ -315,7 +317,7 @@ afqmc_status afqmc_kpt_greens(const afqmc_kpt_problem* p, int nprob, void* ws, s
 
 afqmc_status afqmc_kpt_vbias(const afqmc_kpt_problem* p, int nprob, void* xbar, void* X, void* ws,
                              size_t ws_bytes, void* stream) {
-  AFQMC_TRY(check_problems(p, nprob, N_LH | N_GH));
+  AFQMC_TRY(check_problems(p, nprob, N_LH | N_LHS | N_GH));
   AFQMC_TRY(check_ptr(xbar, 16));
   if (X) AFQMC_TRY(check_ptr(X, 16));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_VBIAS, ws, ws_bytes));
@@ -386,7 +388,8 @@ afqmc_status afqmc_kpt_energy(const afqmc_kpt_problem* p, int nprob, void* E, vo
 
 afqmc_status afqmc_kpt_energy_backward(const afqmc_kpt_problem* p, int nprob, const void* gE,
                                        void* gGh, void* ws, size_t ws_bytes, void* stream) {
-  AFQMC_TRY(check_problems(p, nprob, N_LH | N_LHD | N_H1H | N_GH));
+  // the Coulomb part of the adjoint needs X, whose BF16X3 trace reads Lhs
+  AFQMC_TRY(check_problems(p, nprob, N_LH | N_LHD | N_LHS | N_H1H | N_GH));
   if (gE) AFQMC_TRY(check_ptr(gE, 16));
   AFQMC_TRY(check_ptr(gGh, 16));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_ENERGY_BACKWARD, ws, ws_bytes));
@@ -451,7 +454,7 @@ afqmc_status afqmc_kpt_step(const afqmc_kpt_problem* p, int nprob, const double*
 
 afqmc_status afqmc_kpt_autotune(const afqmc_kpt_problem* p, int nprob, void* vhs, void* ws,
                                 size_t ws_bytes, void* stream) {
-  AFQMC_TRY(check_problems(p, nprob, N_L | N_LH | N_GH | N_U));
+  AFQMC_TRY(check_problems(p, nprob, N_L | N_LS | N_LH | N_LHS | N_GH | N_U));
   AFQMC_TRY(check_ptr(vhs, 16));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_STEP, ws, ws_bytes));
   AFQMC_TRY(check_device());

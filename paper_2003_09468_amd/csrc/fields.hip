@@ -102,12 +102,8 @@ size_t carve_vbias(Carve& c, const Dims& d, VbiasWs& v) {
 
 // K slices of the force bias of one problem: at most 4.  At c1 the BF16X3 kernel's 432
 // workgroups then fill the chip in one round, where 8 slices take 864 in 1.7 rounds (0.108
-// instead of 0.135 ms); the FP64 GEMM gains 5% (0.29 instead of 0.31 ms).  The workspace
-// is sized for the uncapped count, which is not smaller.
-static int vbias_slices(const afqmc_kpt_problem& p) {
-  const int s = vbias_splits(dims_of(p));
-  return s > 4 ? 4 : s;
-}
+// instead of 0.135 ms); the FP64 GEMM gains 5% (0.29 instead of 0.31 ms).
+static int vbias_slices(const afqmc_kpt_problem& p) { return vbias_splits(dims_of(p)); }
 
 template <typename T>
 static OpVbias<T> vbias_op(const afqmc_kpt_problem& p, void* parts) {

@@ -27,10 +27,11 @@ inline Dims dims_of(const afqmc_kpt_problem& p) {
   return Dims{p.nk, p.m, p.nocc, p.nchol, p.nwalk};
 }
 
-// Number of K slices of the split-K force-bias contraction.
+// Number of K slices of the split-K force-bias contraction: at most 4, and at least two
+// k-points per slice.
 inline int vbias_splits(const Dims& d) {
   int s = 1;
-  while (s * 2 <= d.nk && d.nk / (s * 2) >= 2 && s < 8) s *= 2;
+  while (s * 2 <= d.nk && d.nk / (s * 2) >= 2 && s < 4) s *= 2;
   return s;
 }
 

@@ -17,6 +17,12 @@ CASES = {
     "line3": ((3, 1, 1), 9, 4, 20, 7, "random", "dense"),
     "mixed": ((1, 2, 3), 6, 2, 17, 3, "random", "dense"),
     "wide": ((2, 2, 1), 26, 4, 40, 33, "random", "dense"),
+    # band counts past 32 (the exchange and its adjoint with 16 K steps, 3 and 4 column
+    # tiles), the largest band count, and nocc > 8 (one g and one walker per 16-wide tile)
+    "m40": ((2, 1, 1), 40, 4, 37, 5, "random", "dense"),
+    "m52": ((1, 2, 1), 52, 4, 45, 6, "random", "dense"),
+    "m64": ((1, 1, 2), 64, 5, 30, 3, "random", "dense"),
+    "occ10": ((2, 1, 1), 14, 10, 19, 3, "random", "dense"),
 }
 
 
@@ -50,15 +56,30 @@ def phase_err(ld_gpu, ld_ref):
     return np.abs(np.exp(np.asarray(ld_gpu) - np.asarray(ld_ref)) - 1.0).max()
 
 
-def energy_err(Eg, E, nk):
-    """Max over walkers of |dE| per cell divided by the FP64 bar for that walker.
+def overlap_cond(U, A):
+    """2-norm condition number of each walker's overlap matrix A^H U (A block diagonal)."""
+    nk, m, nocc = A.shape
+    U = np.asarray(U).reshape(U.shape[0], nk, m, -1)
+    O = np.einsum("kpa,wkpj->wkaj", A.conj(), U).reshape(U.shape[0], nk * nocc, -1)
+    return np.linalg.cond(O)
 
-    The bar is 1e-10 Ha/cell; for walkers with |E| > 1000 Ha/cell (near-singular overlaps,
-    where FP64 rounding of the overlap inverse alone exceeds the absolute bar) it is 1e-13
-    relative.  A value <= 1 passes.
+
+def energy_bar(E, nk, cond):
+    """FP64 energy bar per walker, Ha per cell: 1e-10, or the rounding floor of the walker's
+    overlap inverse where that is larger.
+
+    Gh = (U O^-1)^T computed in FP64 carries a relative error up to about eps cond(O); every
+    part of E_L is a sum of products of two Gh entries, so the parts move by up to
+    2 eps cond(O) times their magnitude.  Where that floor exceeds 1e-10 Ha/cell no FP64
+    evaluation can meet the absolute bar, and the bar becomes the floor itself.
     """
+    S = np.abs(np.asarray(E)).sum(axis=-1) / nk
+    floor = 2.0 * np.finfo(np.float64).eps * np.asarray(cond) * S
+    return np.maximum(1e-10, floor)
+
+
+def energy_err(Eg, E, nk, cond):
+    """Max over walkers and parts of |dE| per cell divided by energy_bar; <= 1 passes."""
     Eg, E = np.asarray(Eg), np.asarray(E)
-    d = np.abs(Eg - E) / nk
-    mag = np.abs(E) / nk
-    bar = np.maximum(1e-10, 1e-13 * mag)
-    return float((d / bar).max())
+    d = np.abs(Eg - E).max(axis=-1) / nk
+    return float((d / energy_bar(E, nk, cond)).max())

@@ -163,6 +163,7 @@ def test_workspace_checks(L):
 def test_strerror_and_version(L):
     for code in range(-7, 1):
         assert isinstance(L.afqmc_kpt_strerror(code), bytes)
+        assert L.afqmc_kpt_strerror(code) != b"unknown status"
     assert L.afqmc_kpt_strerror(-99) == b"unknown status"
     assert b"gfx950" in L.afqmc_kpt_version()
 
@@ -327,3 +328,45 @@ def test_population_control_validation(L):
         aligned = (ctypes.c_void_p * 1)(0x2000)
         assert f(ctypes.byref(p), 1, xs(0.0), aligned, ws, need, None) == -5
         assert f(ctypes.byref(p), 1, xs(0.999), None, ws, need, None) == -5
+
+
+def bf16x3_problem():
+    p = good_problem()
+    p.prec = 2
+    p.Lhs, p.Ls = 0xd00000, 0xe00000
+    return p
+
+
+def test_bf16x3_split_planes_required(L):
+    """Every entry whose BF16X3 kernels read the split planes rejects NULL planes before any
+    HIP call: the force bias (every step) and the Coulomb trace of the energy and its adjoint
+    read Lhs, the HS potential reads Ls."""
+    ws = ctypes.c_void_p(0x1000000)
+    buf = [ctypes.c_void_p(0x2000 * (i + 1)) for i in range(4)]
+    for missing in ("Lhs", "Ls"):
+        p = bf16x3_problem()
+        setattr(p, missing, None)
+        if missing == "Lhs":
+            assert call(L, "afqmc_kpt_vbias", p, buf[0], buf[1], ws, 1 << 40, None) == -2
+            assert call(L, "afqmc_kpt_energy", p, buf[0], ws, 1 << 40, None) == -2
+            assert call(L, "afqmc_kpt_energy_backward", p, None, buf[0], ws, 1 << 40,
+                        None) == -2
+        else:
+            assert call(L, "afqmc_kpt_vhs", p, buf[0], buf[1], buf[2], ws, 1 << 40, None) == -2
+        arr = (B.Problem * 1)(p)
+        # a step block without the energy still runs the force bias and the HS potential
+        assert call_step(L, arr, 1, step_args(E=None, flags=1)) == -2
+        h = ctypes.c_void_p()
+        a = step_args(E=None, flags=1)
+        assert L.afqmc_kpt_graph_create(arr, 1, a["x"], a["nsteps"], a["xbar"], a["vhs"],
+                                        a["E"], a["flags"], a["ws"], a["nbytes"],
+                                        ctypes.byref(h)) == -2
+        assert L.afqmc_kpt_autotune(arr, 1, a["vhs"], a["ws"], a["nbytes"], None) == -2
+    # an FP64 problem never reads the planes: NULL is fine up to the device check
+    from tests.conftest import gpu_available
+    if not gpu_available():
+        p = good_problem()
+        assert call(L, "afqmc_kpt_vbias", p, buf[0], buf[1], ws, 1 << 40, None) == -5
+        p = bf16x3_problem()
+        assert call(L, "afqmc_kpt_vbias", p, buf[0], buf[1], ws, 1 << 40, None) == -5
+

@@ -2,7 +2,9 @@
 
 * Systems A (2x2x2, m=26, 128 walkers) and B (3x3x3, m=26, 64 walkers) of the uneven
   batch run as one batch for two steps (QR after the last) and the energy; sampled walkers
-  of each are recomputed by the oracle (FP64 bars as in the other parity tests).
+  of each are recomputed by the oracle (FP64 bars as in the other parity tests).  System C
+  (3x3x3, m=52, nchol=416, 32 walkers: the 16-step exchange kernel) runs batched with A
+  and is checked the same way.
 * The 3x3x3, m=26 system with FP32 and BF16X3 contractions: energies of sampled initial
   walkers against the oracle, with the bars of test_gpu_precision (relative to the summed
   magnitude of the energy parts), and one BF16X3 propagation step.
@@ -52,10 +54,28 @@ def batch_ab():
     return out
 
 
-@pytest.mark.parametrize("which,sample", [(0, [0, 127]), (1, [5, 60])], ids=["A", "B"])
-def test_batch_sampled_walkers(batch_ab, which, sample):
-    s, U, x, res = batch_ab[which]
+@pytest.fixture(scope="module")
+def batch_ac():
+    """Systems A and C as one batch (different band counts: every stage groups them into
+    separate kernel variants of one call)."""
+    from paper_2003_09468_amd import KptBatch
+    sysd = [system("c3A"), system("c3C")]
+    print("batch A+C: systems prepared", flush=True)
+    b = KptBatch([d[3] for d in sysd])
+    b.step(b.fields([torch.from_numpy(d[2]) for d in sysd]), ortho=True, energy=True)
+    torch.cuda.synchronize()
+    s, U, x, p = sysd[1]
+    out = (s, U, x, dict(U=host(p.U), logdet=host(p.logdet), weight=host(p.weight),
+                         E=host(b.energy(1)).copy()))
+    del b, sysd, p
+    torch.cuda.empty_cache()
+    return out
+
+
+def check_sampled(sysres, sample):
+    s, U, x, res = sysres
     pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    print(f"oracle prepared (mesh {s.mesh}, m={s.m}); walkers {sample}", flush=True)
     Us = U[sample]
     _, ld = kp.greens(Us, s.A)
     w = np.ones(len(sample))
@@ -70,6 +90,15 @@ def test_batch_sampled_walkers(batch_ab, which, sample):
     E = kp.local_energy(pre["Lh"], pre["h1h"], Gr, s.mesh)
     scale = np.abs(E).sum(1)
     assert (np.abs(res["E"][sample] - E).sum(1) / scale).max() < 1e-11
+
+
+@pytest.mark.parametrize("which,sample", [(0, [0, 127]), (1, [5, 60])], ids=["A", "B"])
+def test_batch_sampled_walkers(batch_ab, which, sample):
+    check_sampled(batch_ab[which], sample)
+
+
+def test_batch_c3C_sampled_walkers(batch_ac):
+    check_sampled(batch_ac, [0, 31])
 
 
 @pytest.mark.parametrize("prec,bar", [(1, 5e-6), (2, 5e-5)], ids=["fp32", "bf16x3"])

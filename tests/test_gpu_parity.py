@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 if gpu_available():
     import torch
     from oracle import kpoint as kp
-    from tests.gpu_cases import CASES, build, host, rel, phase_err, energy_err
+    from tests.gpu_cases import CASES, build, host, rel, phase_err, energy_err, overlap_cond
 
 ALL = list(CASES) if gpu_available() else []
 
@@ -98,8 +98,8 @@ def test_energy(case):
     Gh, _ = kp.greens(U, s.A)
     E = kp.local_energy(pre["Lh"], pre["h1h"], Gh, s.mesh)
     Eg = host(p.energy())
-    # every part: 1e-10 Ha per cell (1e-13 relative beyond 1000 Ha/cell)
-    assert energy_err(Eg, E, s.nk) <= 1.0
+    # every part: 1e-10 Ha per cell, or the FP64 floor 2 eps cond(O) |parts| where larger
+    assert energy_err(Eg, E, s.nk, overlap_cond(U, s.A)) <= 1.0
 
 
 @pytest.mark.parametrize("case", ALL)
@@ -112,7 +112,7 @@ def test_energy_at_trial_is_real_hf(case):
     Eg = host(p.energy())
     Gh, _ = kp.greens(Af[None], s.A)
     E = kp.local_energy(pre["Lh"], pre["h1h"], Gh, s.mesh)[0]
-    assert energy_err(Eg, np.broadcast_to(E[None], Eg.shape), s.nk) <= 1.0
+    assert energy_err(Eg, np.broadcast_to(E[None], Eg.shape), s.nk, np.ones(len(Eg))) <= 1.0
     assert np.abs(Eg.imag).max() < 1e-10
 
 
@@ -144,7 +144,7 @@ def test_autograd_convention():
     expect = np.conj(host(c)[:, None, None] * D)
     assert rel(host(G.grad), expect) < 1e-11
     Eref = kp.local_energy(pre["Lh"], pre["h1h"], Gh, s.mesh).sum(1)
-    assert energy_err(host(E), Eref, s.nk) <= 1.0
+    assert energy_err(host(E)[:, None], Eref[:, None], s.nk, overlap_cond(U, s.A)) <= 1.0
 
 
 def test_two_steps_then_energy_c0():
@@ -161,7 +161,7 @@ def test_two_steps_then_energy_c0():
     Gh, ld = kp.greens(Ur, s.A)
     E = kp.local_energy(pre["Lh"], pre["h1h"], Gh, s.mesh)
     Eg = host(p.energy())
-    assert energy_err(Eg, E, s.nk) <= 1.0
+    assert energy_err(Eg, E, s.nk, overlap_cond(Ur, s.A)) <= 1.0
     np.testing.assert_allclose(host(p.weight), w, rtol=1e-10)
     assert rel(host(p.U), Ur) < 1e-10
 
@@ -242,7 +242,7 @@ def test_large_occupied_dimension():
     assert rel(host(p.Gh), Gh) < 1e-11
     assert phase_err(host(p.logdet), ld) < 1e-11
     E = kp.local_energy(pre["Lh"], pre["h1h"], Gh, s.mesh)
-    assert energy_err(host(p.energy()), E, s.nk) <= 1.0
+    assert energy_err(host(p.energy()), E, s.nk, overlap_cond(U, s.A)) <= 1.0
     out = kp.step(U, ld, np.ones(U.shape[0]), x[0], pre, s.A, s.L, s.mesh, s.dt)
     p.step(torch.from_numpy(x[0]))
     assert rel(host(p.U), out["U"]) < 1e-11

@@ -296,6 +296,39 @@ def test_blocked_equals_supercell(mesh):
         assert np.abs(E1 - E[w]).max() < 1e-12 * max(1.0, np.abs(E1).max())
         F = sc.fock(h, v, G)
         assert np.abs(2.0 * Af.conj().T @ F - D[w]).max() < 1e-12 * max(1.0, np.abs(D[w]).max())
+    # weights (importance function and phaseless cut) against routes that share nothing with
+    # the oracle's LU log determinants: the overlap ratio (det O'/det O)^2 from the
+    # eigenvalues of the supercell overlap matrices, and the Gaussian factor as the ratio of
+    # normal densities p(x - xbar) / p(x), continued to complex xbar
+    w0 = np.array([1.0, 0.5])[: U.shape[0]]
+    _, logdet2 = kp.greens(U2, s.A)
+    w_or, log_I, dth = kp.weight_update(logdet, logdet2, x, xbar, w0)
+    for w in range(U.shape[0]):
+        ev0 = np.linalg.eigvals(Af.conj().T @ U[w])
+        ev1 = np.linalg.eigvals(Af.conj().T @ U2[w])
+        ratio = np.prod(ev1 / ev0) ** 2
+        dens = np.exp(-0.5 * (x[w] - xbar[w]) ** 2) / np.exp(-0.5 * x[w] ** 2)
+        imp = ratio * np.prod(dens)
+        assert abs(np.exp(log_I[w]) / imp - 1.0) < 1e-11
+        assert abs(dth[w] - np.angle(ratio)) < 1e-11
+        assert abs(w_or[w] - abs(imp) * max(0.0, math.cos(np.angle(ratio))) * w0[w]) \
+            < 1e-11 * w_or[w] + 1e-300
+
+
+def test_importance_factor_is_density_ratio():
+    """For real force biases the Gaussian part of the importance function,
+    exp(sum x xbar - xbar^2/2), is the ratio of standard normal densities p(x - xbar)/p(x):
+    the shifted sampling density over the unshifted one."""
+    from scipy.stats import norm
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((3, 2, 4, 2))
+    xbar = 0.3 * rng.standard_normal(x.shape)
+    zero = np.zeros(3, dtype=complex)
+    w, log_I, dth = kp.weight_update(zero, zero, x, xbar.astype(complex), np.ones(3))
+    ref = np.prod(norm.pdf(x - xbar) / norm.pdf(x), axis=(1, 2, 3))
+    np.testing.assert_allclose(w, ref, rtol=1e-12)
+    np.testing.assert_allclose(log_I.real, np.log(ref), rtol=1e-12)
+    assert np.all(dth == 0.0)
 
 
 # ---------------------------------------------------------------------------
