@@ -273,7 +273,7 @@ def reset(p, U0d):
 def bench_path(name, p, U0d, xs, args, torch, cfg):
     import paper_2003_09468_amd as lib
     W, N = p.nwalk, p.nk * p.m
-    vdt = torch.complex64 if p.prec != lib.PREC_FP64 else torch.complex128
+    vdt = torch.complex64 if lib.step_prec(p.prec) != lib.PREC_FP64 else torch.complex128
     bufs = {
         "xbar": torch.empty((W, p.nk, p.nchol, 2), dtype=torch.complex128, device="cuda"),
         "X": torch.empty((W, p.nk, p.nchol), dtype=torch.complex128, device="cuda"),

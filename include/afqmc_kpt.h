@@ -82,6 +82,19 @@ typedef enum {
   AFQMC_PREC_BF16X3 = 2
 } afqmc_prec;
 
+/* Precision placement ("GPU Implementation": the paper runs the whole method in single
+ * precision; here each group of contractions has its own).  The prec field of a problem is
+ * either an afqmc_prec value, which applies to every contraction, or
+ *   AFQMC_PREC_PLACE(step, energy)
+ * with step the precision of the force bias, HS potential and Taylor products (every
+ * entry but the two below) and energy the precision of afqmc_kpt_energy and
+ * afqmc_kpt_energy_backward (also when afqmc_kpt_step evaluates the energy).  Example:
+ * AFQMC_PREC_PLACE(AFQMC_PREC_BF16X3, AFQMC_PREC_FP64) propagates with BF16X3 and
+ * evaluates the local energy and its adjoint in FP64.  The arrays each stage reads must be
+ * present (e.g. Lhs and Ls for a BF16X3 step, Lh32 for a reduced energy); prepare writes
+ * all of them. */
+#define AFQMC_PREC_PLACE(step, energy) ((step) | (((energy) + 1) << 4))
+
 /* Per-walker status bits. */
 #define AFQMC_WALKER_SINGULAR 1  /* overlap matrix A^H U had a zero pivot */
 #define AFQMC_WALKER_NONFINITE 2 /* a non-finite overlap or weight */
@@ -127,7 +140,7 @@ typedef struct afqmc_kpt_problem {
   int32_t nocc;      /* occupied orbitals per spin per k-point, nocc <= m */
   int32_t nchol;     /* Cholesky vectors per Q */
   int32_t nwalk;     /* walkers in the batch */
-  int32_t prec;      /* afqmc_prec */
+  int32_t prec;      /* afqmc_prec, or AFQMC_PREC_PLACE(step, energy) */
   double dt;         /* imaginary time step, > 0 */
   /* static data */
   const void* L;     /* [nk][nk][m][m][nchol] complex128, input */
@@ -136,15 +149,16 @@ typedef struct afqmc_kpt_problem {
                         Lh[Q][k][a][r][g] = sum_p conj(A[k][p][a]) L[Q][k][p][r][g] */
   void* h1h;         /* [nk][nocc][m] complex128, written by prepare: A[k]^H H1[k] */
   void* bhalf;       /* [nk][m][m] complex128, written by prepare: exp(-dt/2 (H1 + V0)) */
-  void* L32;         /* [nk][nk][m][m][nchol] complex64 copy of L; prec FP32 only */
-  void* Lh32;        /* [nk][nk][nocc][m][nchol] complex64 copy of Lh; prec FP32/BF16X3 only */
+  void* L32;         /* [nk][nk][m][m][nchol] complex64 copy of L; step prec FP32 only */
+  void* Lh32;        /* [nk][nk][nocc][m][nchol] complex64 copy of Lh; needed when the step
+                        or the energy precision is FP32 or BF16X3 (else NULL) */
   void* Lhs;         /* [nk][nk][nchol][nocc][4][32*ceil(m/32)] bfloat16 (uint16) split planes
                         of Lh (re hi, re lo, im hi, im lo; r padded with zeros), written by
-                        prepare; prec BF16X3 only (else NULL) */
+                        prepare; needed when the step or the energy precision is BF16X3 */
   void* Ls;          /* [nk(Q)][ceil(nchol/32)][nk*m*m (k p r)][4][32] bfloat16 (uint16)
                         split planes of L (re hi, re lo, im hi, im lo) in chunks of 32
-                        Cholesky indices, g padded with zeros, written by prepare; prec
-                        BF16X3 only (else NULL) */
+                        Cholesky indices, g padded with zeros, written by prepare; step
+                        prec BF16X3 only (else NULL) */
   /* walker state */
   void* U;           /* [nwalk][nk*m][nk*nocc] complex128 walker orbitals, in/out */
   void* Gh;          /* [nwalk][nk*nocc][nk*m] complex128 half-rotated Green's function */

@@ -17,6 +17,9 @@ from .binding import (  # noqa: F401
     PREC_FP64,
     PREC_FP32,
     PREC_BF16X3,
+    prec_place,
+    step_prec,
+    energy_prec,
     WALKER_SINGULAR,
     WALKER_NONFINITE,
     WALKER_KILLED,

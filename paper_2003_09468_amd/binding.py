@@ -20,6 +20,21 @@ PREC_FP64 = 0
 PREC_FP32 = 1
 PREC_BF16X3 = 2
 
+
+def prec_place(step: int, energy: int) -> int:
+    """AFQMC_PREC_PLACE: the step contractions in one precision, the local energy and its
+    adjoint in another."""
+    return int(step) | ((int(energy) + 1) << 4)
+
+
+def step_prec(prec: int) -> int:
+    return int(prec) & 15
+
+
+def energy_prec(prec: int) -> int:
+    prec = int(prec)
+    return (prec >> 4) - 1 if prec >> 4 else prec & 15
+
 WALKER_SINGULAR = 1
 WALKER_NONFINITE = 2
 WALKER_KILLED = 4
@@ -211,15 +226,17 @@ class KptProblem:
         self.bhalf = torch.empty((nk, m, m), dtype=c128, **kw)
         # complex64 copies: L for the FP32 HS potential, Lh for the FP32 force bias and
         # exchange and for the adjoint of both reduced modes (BF16X3 reads split planes of L)
+        sp, ep = step_prec(self.prec), energy_prec(self.prec)
         self.L32 = (torch.empty(self.L.shape, dtype=torch.complex64, **kw)
-                    if self.prec == PREC_FP32 else None)
+                    if sp == PREC_FP32 else None)
         self.Lh32 = (torch.empty(self.Lh.shape, dtype=torch.complex64, **kw)
-                     if self.prec != PREC_FP64 else None)
+                     if sp != PREC_FP64 or ep != PREC_FP64 else None)
         self.Lhs = self.Ls = None
-        if self.prec == PREC_BF16X3:
+        if PREC_BF16X3 in (sp, ep):
             kp = 32 * ((m + 31) // 32)
-            cp = 32 * ((nchol + 31) // 32)
             self.Lhs = torch.empty((nk, nk, nchol, nocc, 4, kp), dtype=torch.int16, **kw)
+        if sp == PREC_BF16X3:
+            cp = 32 * ((nchol + 31) // 32)
             self.Ls = torch.empty((nk, cp // 32, nk * m * m, 4, 32), dtype=torch.int16, **kw)
         N, n = nk * m, nk * nocc
         self.U = torch.zeros((nwalk, N, n), dtype=c128, **kw)
@@ -295,7 +312,7 @@ class KptProblem:
 
     def vhs(self, x, xbar, out=None):
         N = self.nk * self.m
-        dt = torch.complex64 if self.prec != PREC_FP64 else torch.complex128
+        dt = torch.complex64 if step_prec(self.prec) != PREC_FP64 else torch.complex128
         if out is None:
             out = torch.empty((self.nwalk, N, N), dtype=dt, device=self.device)
         x = x.to(device=self.device, dtype=torch.float64).contiguous()
@@ -442,7 +459,7 @@ class KptBatch:
     def vhs(self, i):
         p = self.problems[i]
         N = p.nk * p.m
-        dt = torch.complex64 if p.prec != PREC_FP64 else torch.complex128
+        dt = torch.complex64 if step_prec(p.prec) != PREC_FP64 else torch.complex128
         return self._view(self._vhs, "vhs", i, dt, (p.nwalk, N, N))
 
     def energy(self, i):

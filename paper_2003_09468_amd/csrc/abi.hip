@@ -19,7 +19,9 @@ size_t population_ws_bytes(const afqmc_kpt_problem& p);
 hipError_t run_population(const afqmc_kpt_problem* p, int nprob, const double* xi,
                           int32_t* const* parent, void* ws, hipStream_t s);
 
-size_t ws_bytes_entry(const afqmc_kpt_problem& p, int entry) {
+size_t ws_bytes_entry(const afqmc_kpt_problem& p0, int entry) {
+  // the step entry sizes each of its stages in that stage's precision
+  const afqmc_kpt_problem p = stage_view(p0, energy_entry(entry));
   Dims d = dims_of(p);
   switch (entry) {
     case AFQMC_ENTRY_PREPARE: return prepare_ws_bytes(p);
@@ -39,9 +41,9 @@ size_t ws_bytes_entry(const afqmc_kpt_problem& p, int entry) {
     case AFQMC_ENTRY_ENERGY_BACKWARD: return backward_ws_bytes(p);
     case AFQMC_ENTRY_POPULATION: return population_ws_bytes(p);
     case AFQMC_ENTRY_STEP: {
-      size_t b = ws_bytes_entry(p, AFQMC_ENTRY_VBIAS);
-      const size_t e[3] = {ws_bytes_entry(p, AFQMC_ENTRY_VHS), ws_bytes_entry(p, AFQMC_ENTRY_PROPAGATE),
-                           ws_bytes_entry(p, AFQMC_ENTRY_ENERGY)};
+      size_t b = ws_bytes_entry(p0, AFQMC_ENTRY_VBIAS);
+      const size_t e[3] = {ws_bytes_entry(p0, AFQMC_ENTRY_VHS), ws_bytes_entry(p0, AFQMC_ENTRY_PROPAGATE),
+                           ws_bytes_entry(p0, AFQMC_ENTRY_ENERGY)};
       for (size_t v : e) b = v > b ? v : b;
       return b;
     }
@@ -56,7 +58,7 @@ size_t buf_bytes(const afqmc_kpt_problem& p, int buf) {
     case AFQMC_BUF_FIELDS: return 8 * W * nk * C * 2;
     case AFQMC_BUF_XBAR: return 16 * W * nk * C * 2;
     case AFQMC_BUF_X: return 16 * W * nk * C;
-    case AFQMC_BUF_VHS: return (low_prec(p.prec) ? 8 : 16) * W * N * N;
+    case AFQMC_BUF_VHS: return (low_prec(step_prec(p.prec)) ? 8 : 16) * W * N * N;
     case AFQMC_BUF_ENERGY: return 16 * W * 3;
     case AFQMC_BUF_GE: return 16 * W;
     case AFQMC_BUF_GGH: return 16 * W * n * N;
@@ -107,7 +109,9 @@ afqmc_status check_dims(const afqmc_kpt_problem& p) {
     if (p.mesh[i] < 1 || p.mesh[i] > 64) return AFQMC_EINVAL;
   if ((int64_t)p.mesh[0] * p.mesh[1] * p.mesh[2] != p.nk) return AFQMC_EINVAL;
   if (p.m < 1 || p.nocc < 1 || p.nocc > p.m || p.nchol < 1 || p.nwalk < 1) return AFQMC_EINVAL;
-  if (p.prec != AFQMC_PREC_FP64 && p.prec != AFQMC_PREC_FP32 && p.prec != AFQMC_PREC_BF16X3)
+  // an afqmc_prec value, or AFQMC_PREC_PLACE(step, energy)
+  if ((p.prec & ~0x3f) != 0 || (p.prec & 15) > AFQMC_PREC_BF16X3 ||
+      (p.prec >> 4) > AFQMC_PREC_BF16X3 + 1)
     return AFQMC_EINVAL;
   if (!(p.dt > 0.0) || !isfinite(p.dt)) return AFQMC_EINVAL;
   // sizes the kernels implement
@@ -139,12 +143,15 @@ afqmc_status check_fields(const afqmc_kpt_problem& p, unsigned need) {
   return AFQMC_OK;
 }
 
-afqmc_status check_problems(const afqmc_kpt_problem* p, int nprob, unsigned need) {
+// need: the arrays the entry's stages read, checked in the precision of the step (energy =
+// false) or of the local energy (energy = true).
+afqmc_status check_problems(const afqmc_kpt_problem* p, int nprob, unsigned need,
+                            bool energy = false) {
   if (!p) return AFQMC_ENULL;
   if (nprob < 1) return AFQMC_EINVAL;
   for (int i = 0; i < nprob; ++i) {
     AFQMC_TRY(check_dims(p[i]));
-    AFQMC_TRY(check_fields(p[i], need));
+    AFQMC_TRY(check_fields(stage_view(p[i], energy), need));
   }
   return AFQMC_OK;
 }
@@ -212,7 +219,7 @@ std::vector<Job> make_jobs(const afqmc_kpt_problem* p, int nprob, int entry, voi
   size_t wo = 0;
   for (int i = 0; i < nprob; ++i) {
     Job& j = jobs[i];
-    j.p = p[i];
+    j.p = stage_view(p[i], energy_entry(entry));
     j.ws = ws ? (char*)ws + wo : nullptr;
     wo += align_up(ws_bytes_entry(p[i], entry));
     j.x = slice(b.x, p, nprob, AFQMC_BUF_FIELDS, i, off);
@@ -227,8 +234,8 @@ std::vector<Job> make_jobs(const afqmc_kpt_problem* p, int nprob, int entry, voi
 }
 
 // The step sequence; fields of step s at x + s * stride bytes.
-hipError_t run_steps(std::vector<Job>& jobs, const double* x, size_t stride, int nsteps,
-                     int flags, hipStream_t s) {
+hipError_t run_steps(std::vector<Job>& jobs, const int* orig_prec, const double* x,
+                     size_t stride, int nsteps, int flags, hipStream_t s) {
   const int n = (int)jobs.size();
   std::vector<const double*> x0(n);
   for (int i = 0; i < n; ++i) x0[i] = jobs[i].x;
@@ -242,7 +249,12 @@ hipError_t run_steps(std::vector<Job>& jobs, const double* x, size_t stride, int
     if (e == hipSuccess) e = run_propagate(jobs.data(), n, pf, s);
   }
   for (int i = 0; i < n; ++i) jobs[i].x = x0[i];
-  if (e == hipSuccess && (flags & AFQMC_STEP_ENERGY)) e = run_energy(jobs.data(), n, s);
+  if (e == hipSuccess && (flags & AFQMC_STEP_ENERGY)) {
+    // the same workspace and buffers, with the problems in their energy precision
+    std::vector<Job> ej(jobs);
+    for (int i = 0; i < n; ++i) ej[i].p.prec = energy_prec(orig_prec[i]);
+    e = run_energy(ej.data(), n, s);
+  }
   return e;
 }
 
@@ -252,8 +264,9 @@ afqmc_status check_step_args(const afqmc_kpt_problem* p, int nprob, const double
   // every step runs the force bias, whose BF16X3 kernel reads the split planes Lhs
   unsigned need = N_L | N_LS | N_LH | N_LHS | N_A | N_BHALF | N_U | N_GH | N_LOGDET | N_WEIGHT |
                   N_STATUS;
-  if (flags & AFQMC_STEP_ENERGY) need |= N_H1H;
   AFQMC_TRY(check_problems(p, nprob, need));
+  if (flags & AFQMC_STEP_ENERGY)
+    AFQMC_TRY(check_problems(p, nprob, N_LH | N_LHS | N_H1H | N_GH, true));
   if (nsteps < 1) return AFQMC_EINVAL;
   if (flags & ~(AFQMC_PROPAGATE_ORTHO | AFQMC_STEP_ENERGY)) return AFQMC_EINVAL;
   if (flags & AFQMC_PROPAGATE_ORTHO) AFQMC_TRY(check_ortho(p, nprob));
@@ -293,9 +306,11 @@ afqmc_status afqmc_kpt_prepare(const afqmc_kpt_problem* p, int nprob, const void
                                size_t ws_bytes, void* stream) {
   AFQMC_TRY(check_problems(p, nprob, 0));
   for (int i = 0; i < nprob; ++i) {
-    unsigned need = N_A | N_H1H | N_BHALF | N_LD | N_LHD;  // complex128 L and Lh always
-    if (low_prec(p[i].prec)) need |= N_L | N_LH | N_LHS | N_LS;  // plus the lower-precision copies
+    // complex128 L and Lh always, plus the lower-precision copies each stage reads
+    const unsigned need = N_A | N_H1H | N_BHALF | N_LD | N_LHD;
     AFQMC_TRY(check_fields(p[i], need));
+    AFQMC_TRY(check_fields(stage_view(p[i], false), N_L | N_LH | N_LHS | N_LS));
+    AFQMC_TRY(check_fields(stage_view(p[i], true), N_LH | N_LHS));
   }
   AFQMC_TRY(check_ptr(H1, 16));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_PREPARE, ws, ws_bytes));
@@ -376,7 +391,7 @@ afqmc_status afqmc_kpt_orthonormalize(const afqmc_kpt_problem* p, int nprob, voi
 
 afqmc_status afqmc_kpt_energy(const afqmc_kpt_problem* p, int nprob, void* E, void* ws,
                               size_t ws_bytes, void* stream) {
-  AFQMC_TRY(check_problems(p, nprob, N_LH | N_LHS | N_H1H | N_GH));
+  AFQMC_TRY(check_problems(p, nprob, N_LH | N_LHS | N_H1H | N_GH, true));
   AFQMC_TRY(check_ptr(E, 16));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_ENERGY, ws, ws_bytes));
   AFQMC_TRY(check_device());
@@ -389,7 +404,7 @@ afqmc_status afqmc_kpt_energy(const afqmc_kpt_problem* p, int nprob, void* E, vo
 afqmc_status afqmc_kpt_energy_backward(const afqmc_kpt_problem* p, int nprob, const void* gE,
                                        void* gGh, void* ws, size_t ws_bytes, void* stream) {
   // the Coulomb part of the adjoint needs X, whose BF16X3 trace reads Lhs
-  AFQMC_TRY(check_problems(p, nprob, N_LH | N_LHD | N_LHS | N_H1H | N_GH));
+  AFQMC_TRY(check_problems(p, nprob, N_LH | N_LHD | N_LHS | N_H1H | N_GH, true));
   if (gE) AFQMC_TRY(check_ptr(gE, 16));
   AFQMC_TRY(check_ptr(gGh, 16));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_ENERGY_BACKWARD, ws, ws_bytes));
@@ -449,7 +464,10 @@ afqmc_status afqmc_kpt_step(const afqmc_kpt_problem* p, int nprob, const double*
   std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_STEP, ws, b);
   std::vector<size_t> off(nprob + 1);
   buf_offsets(p, nprob, AFQMC_BUF_FIELDS, off.data());
-  return hip_status(run_steps(jobs, x, off[nprob], nsteps, flags, (hipStream_t)stream));
+  std::vector<int> prec(nprob);
+  for (int i = 0; i < nprob; ++i) prec[i] = p[i].prec;
+  return hip_status(
+      run_steps(jobs, prec.data(), x, off[nprob], nsteps, flags, (hipStream_t)stream));
 }
 
 afqmc_status afqmc_kpt_autotune(const afqmc_kpt_problem* p, int nprob, void* vhs, void* ws,
@@ -486,13 +504,15 @@ afqmc_status afqmc_kpt_graph_create(const afqmc_kpt_problem* p, int nprob, const
   std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_STEP, ws, b);
   std::vector<size_t> off(nprob + 1);
   buf_offsets(p, nprob, AFQMC_BUF_FIELDS, off.data());
+  std::vector<int> prec(nprob);
+  for (int i = 0; i < nprob; ++i) prec[i] = p[i].prec;
   // record on a private stream (a capture cannot use the legacy default stream)
   hipStream_t cs;
   AFQMC_TRY(hip_status(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)));
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    const hipError_t er = run_steps(jobs, x, off[nprob], nsteps, flags, cs);
+    const hipError_t er = run_steps(jobs, prec.data(), x, off[nprob], nsteps, flags, cs);
     e = hipStreamEndCapture(cs, &g);
     if (er != hipSuccess) e = er;
   }

@@ -11,6 +11,7 @@
 
 #include "../../include/afqmc_kpt.h"
 #include "batch.h"
+#include "kcommon.h"
 #include "timing.h"
 
 namespace afqmc {
@@ -55,8 +56,19 @@ size_t carve_greens(Carve& c, const Dims& d, GreensWs& g);
 size_t carve_vbias(Carve& c, const Dims& d, VbiasWs& v);
 
 // Workspace of one problem for one entry (every entry's layout starts with the Green's
-// function slots).
+// function slots).  A placed precision sizes each stage in its own precision.
 size_t ws_bytes_entry(const afqmc_kpt_problem& p, int entry);
+
+// The problem as a stage sees it: prec resolved to the energy precision for the local
+// energy and its adjoint, to the step precision otherwise.
+inline afqmc_kpt_problem stage_view(const afqmc_kpt_problem& p, bool energy) {
+  afqmc_kpt_problem q = p;
+  q.prec = energy ? energy_prec(p.prec) : step_prec(p.prec);
+  return q;
+}
+inline bool energy_entry(int entry) {
+  return entry == AFQMC_ENTRY_ENERGY || entry == AFQMC_ENTRY_ENERGY_BACKWARD;
+}
 
 // One problem of a batch with its workspace region and its slices of the packed per-call
 // buffers (unused ones are null).

@@ -14,6 +14,14 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // Contraction precisions other than FP64 keep complex64 copies of L and Lh.
 __host__ __device__ __forceinline__ bool low_prec(int prec) { return prec != AFQMC_PREC_FP64; }
 
+// A placed precision (AFQMC_PREC_PLACE) resolves to the precision of the step contractions
+// (force bias, HS potential, Taylor products) and to that of the local energy and its
+// adjoint; a plain afqmc_prec value is both.
+__host__ __device__ __forceinline__ int step_prec(int prec) { return prec & 15; }
+__host__ __device__ __forceinline__ int energy_prec(int prec) {
+  return (prec >> 4) ? (prec >> 4) - 1 : (prec & 15);
+}
+
 // Complex values as plain (re, im) pairs of the storage type.
 template <typename T>
 struct cpx {

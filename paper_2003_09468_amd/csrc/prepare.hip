@@ -230,7 +230,9 @@ hipError_t run_prepare(const afqmc_kpt_problem& p, const void* H1, void* ws, hip
   Carve c(ws);
   void* V0 = c.take(16 * (size_t)p.nk * p.m * p.m);
   void* scr = c.take(16 * 4 * (size_t)p.nk * p.m * p.m);
-  const bool f32 = low_prec(p.prec);
+  // the reduced copies that the step and the energy precision read
+  const int sp = step_prec(p.prec), ep = energy_prec(p.prec);
+  const bool f32 = low_prec(sp) || low_prec(ep);
   hipError_t e;
   {  // Lh = A^H L, batch (Q, k)
     OpHalfRot op;
@@ -273,19 +275,21 @@ hipError_t run_prepare(const afqmc_kpt_problem& p, const void* H1, void* ws, hip
                      (cpx<double>*)p.bhalf);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (p.prec == AFQMC_PREC_FP32) {  // BF16X3 reads the split planes of L instead
+  if (sp == AFQMC_PREC_FP32) {  // BF16X3 reads the split planes of L instead
     const int64_t n = (int64_t)p.nk * p.nk * p.m * p.m * p.nchol;
     hipLaunchKernelGGL(to_c64_kernel, dim3(4096), dim3(256), 0, s, n, (const cpx<double>*)p.L,
                        (cpx<float>*)p.L32);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (p.prec == AFQMC_PREC_BF16X3) {
+  if (sp == AFQMC_PREC_BF16X3 || ep == AFQMC_PREC_BF16X3) {
     const int KP = 32 * ((p.m + 31) / 32);
     hipLaunchKernelGGL(lh_split_kernel, dim3(4096), dim3(256), 0, s, p.nk, p.m, p.nocc,
                        p.nchol, KP, (const cpx<double>*)p.Lh, (unsigned short*)p.Lhs);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+  }
+  if (sp == AFQMC_PREC_BF16X3) {
     const int CP = 32 * ((p.nchol + 31) / 32);
     const int64_t ncq = (int64_t)p.nk * p.m * p.m, ncols = p.nk * ncq;
     hipLaunchKernelGGL(l_split_kernel, dim3(4096), dim3(256), 0, s, ncols, ncq, p.nchol, CP,

@@ -370,3 +370,85 @@ def test_bf16x3_split_planes_required(L):
         p = bf16x3_problem()
         assert call(L, "afqmc_kpt_vbias", p, buf[0], buf[1], ws, 1 << 40, None) == -5
 
+
+
+def test_placed_precision_encoding(L):
+    """AFQMC_PREC_PLACE(step, energy) is accepted for every pair of precisions; other bits,
+    step values above BF16X3 and energy codes above BF16X3 + 1 are rejected."""
+    ws = ctypes.c_void_p(0x1000000)
+    out = ctypes.c_size_t()
+    for sp in range(3):
+        for ep in range(3):
+            p = good_problem()
+            p.prec = B.prec_place(sp, ep)
+            assert B.step_prec(p.prec) == sp and B.energy_prec(p.prec) == ep
+            assert L.afqmc_kpt_workspace_bytes(ctypes.byref(p), 1, 8, ctypes.byref(out)) == 0
+    for bad in (3, 15, B.prec_place(0, 3), 0x40, 0x100, -1):
+        p = good_problem()
+        p.prec = bad
+        assert call(L, "afqmc_kpt_greens", p, ws, 1 << 40, None) == -1, bad
+    # a plain value is its own step and energy precision
+    assert B.step_prec(2) == 2 and B.energy_prec(2) == 2
+
+
+def test_placed_precision_workspaces(L):
+    """Each stage is sized in its own precision: the step workspace of BF16X3 propagation
+    with an FP64 energy is the larger of the BF16X3 step stages and the FP64 energy; the
+    energy and adjoint entries are sized as FP64, the propagation as BF16X3; the HS
+    potential buffer is complex64 (BF16X3 step)."""
+    def ws(prec, entry):
+        p = good_problem()
+        p.prec = prec
+        out = ctypes.c_size_t()
+        assert L.afqmc_kpt_workspace_bytes(ctypes.byref(p), 1, entry, ctypes.byref(out)) == 0
+        return out.value
+    pl = B.prec_place(2, 0)
+    for e in (B.ENTRIES["energy"], B.ENTRIES["energy_backward"]):
+        assert ws(pl, e) == ws(0, e)
+    for e in (B.ENTRIES["propagate"], B.ENTRIES["vhs"], B.ENTRIES["vbias"]):
+        assert ws(pl, e) == ws(2, e)
+    step = B.ENTRIES["step"]
+    assert ws(pl, step) == max([ws(2, B.ENTRIES[e]) for e in ("vbias", "vhs", "propagate")]
+                               + [ws(0, B.ENTRIES["energy"])])
+    for prec, nb in ((pl, 8), (B.prec_place(0, 2), 16), (0, 16), (2, 8)):
+        p = good_problem()
+        p.prec = prec
+        off = (ctypes.c_size_t * 2)()
+        assert L.afqmc_kpt_buffer_layout(ctypes.byref(p), 1, 3, off) == 0
+        assert off[1] == nb * 64 * (27 * 26) ** 2
+
+
+def test_placed_precision_checks_each_stage(L):
+    """With BF16X3 propagation and an FP64 energy the energy entries need neither split
+    planes nor complex64 copies, the step entries need the BF16X3 planes; with an FP64 step
+    and a BF16X3 energy it is the other way round."""
+    from tests.conftest import gpu_available
+    if gpu_available():
+        pytest.skip("the device check would pass and launch")
+    ws = ctypes.c_void_p(0x1000000)
+    buf = [ctypes.c_void_p(0x2000 * (i + 1)) for i in range(4)]
+    p = good_problem()
+    p.prec = B.prec_place(2, 0)
+    p.Lh32 = p.Lhs = p.Ls = None
+    assert call(L, "afqmc_kpt_energy", p, buf[0], ws, 1 << 40, None) == -5
+    assert call(L, "afqmc_kpt_energy_backward", p, None, buf[0], ws, 1 << 40, None) == -5
+    assert call(L, "afqmc_kpt_vbias", p, buf[0], buf[1], ws, 1 << 40, None) == -2
+    assert call(L, "afqmc_kpt_vhs", p, buf[0], buf[1], buf[2], ws, 1 << 40, None) == -2
+    p.Lh32, p.Lhs, p.Ls = 0xc00000, 0xd00000, 0xe00000
+    assert call(L, "afqmc_kpt_vbias", p, buf[0], buf[1], ws, 1 << 40, None) == -5
+    arr = (B.Problem * 1)(p)
+    assert call_step(L, arr, 1, step_args(E=buf[3], flags=3)) == -5
+    # FP64 step, BF16X3 energy: the energy needs Lhs, the step does not
+    p = good_problem()
+    p.prec = B.prec_place(0, 2)
+    p.Lhs = p.Ls = None
+    assert call(L, "afqmc_kpt_vbias", p, buf[0], buf[1], ws, 1 << 40, None) == -5
+    assert call(L, "afqmc_kpt_energy", p, buf[0], ws, 1 << 40, None) == -2
+    arr = (B.Problem * 1)(p)
+    assert call_step(L, arr, 1, step_args(E=None, flags=1)) == -5
+    assert call_step(L, arr, 1, step_args(E=buf[3], flags=3)) == -2
+    # prepare needs the union of both stages' arrays
+    H1 = buf[3]
+    assert call(L, "afqmc_kpt_prepare", p, H1, ws, 1 << 40, None) == -2
+    p.Lhs = 0xd00000
+    assert call(L, "afqmc_kpt_prepare", p, H1, ws, 1 << 40, None) == -5
