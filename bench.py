@@ -7,11 +7,16 @@ a GTH-DZVP basis.  One timed step is one block as the paper times it: 20 propaga
 steps (force bias, HS potential, 6th-order Taylor propagation, new Green's function and
 phaseless weights), one walker re-orthonormalisation, one local-energy evaluation.
 
-Two precisions of the large contractions run on the same inputs: FP64 and FP32 MFMA
-(overlap, inverse, QR and energy sums stay FP64).  The reported value is the FP32
-path's walker-steps/s when its local energies stay within 1e-5 Ha/cell of the FP64
-path after the same block, else the FP64 path's.  The FP64 path itself matches the
-FP64 CPU oracle to 1e-10 Ha/cell (GPU parity tests).
+Paths on the same inputs, named by the precision of the step contractions (force bias,
+HS potential, Taylor products) and of the local energy: FP64 throughout, FP32
+throughout, BF16X3 throughout, and BF16X3 steps with an FP64 or an FP32 energy
+(overlap, inverse, QR and energy sums are FP64 in every path).  The reported value is
+the walker-steps/s of the fastest path whose local energies, evaluated on the FP64
+path's walkers after a block, differ from the FP64 energies by at most 1e-5 Ha/cell on
+every walker that carries weight and in the weighted (mixed) estimate; the FP64 path
+itself matches the FP64 CPU oracle to 1e-10 Ha/cell (GPU parity tests).  Every path
+also reports how far its own trajectory ends from the FP64 one and the error of one
+of its steps from the common state.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -28,6 +33,15 @@ METRIC = "walker-steps/s at Nk=27 M=26, mixed vs FP64 GPU, |ΔE_loc|≤1e-5 Ha/c
 # dense MFMA TFLOP/s, MI355X; BF16-split counts its three BF16 passes per product
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3}
 TOL = 1e-5  # Ha per cell
+# path -> (precision of the step contractions, precision of the local energy)
+PATHS = {
+    "fp64": ("fp64", "fp64"),
+    "fp32": ("fp32", "fp32"),
+    "bf16x3": ("bf16x3", "bf16x3"),
+    "bf16x3+fp64E": ("bf16x3", "fp64"),
+    "bf16x3+fp32E": ("bf16x3", "fp32"),
+}
+ENERGY_CLASSES = ("exchange", "energy_rest", "exchange_bwd")
 
 
 def log(*a):
@@ -281,9 +295,10 @@ def bench_path(name, p, U0d, xs, args, torch, cfg):
     }
     E = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
     reset(p, U0d)
-    E0 = run_block(p, xs, bufs, E).clone()  # first block from the common start: accuracy
-    w0 = p.weight.clone()
-    bench_path.G_end = p.Gh.clone()  # walker state after that block
+    # first block from the common start: the path's own trajectory and its end state
+    first = {"E": run_block(p, xs, bufs, E).clone()}
+    for k in ("U", "Gh", "logdet", "weight", "status"):
+        first[k] = getattr(p, k).clone()
     for _ in range(args.warmup):
         run_block(p, xs, bufs, E)
     torch.cuda.synchronize()
@@ -329,10 +344,22 @@ def bench_path(name, p, U0d, xs, args, torch, cfg):
             f"{v['ms_per_launch']:.4f} ms/launch")
     return {"ms_per_block": dt * 1e3, "walker_steps_per_s": ws, "kernels": kern,
             "ms_per_block_with_kernel_events": (t3 - t2) / args.steps * 1e3,
-            "population_control_ms": round(pc_ms, 4)}, E0, w0
+            "population_control_ms": round(pc_ms, 4)}, first
 
 
-def roofline(path_res, prec_key, cfg, kernel=None):
+def kernel_prec(path, kernel):
+    """Precision a kernel class of a path runs in (the key of PEAK and of the traffic
+    summary)."""
+    sp, ep = PATHS[path]
+    pk = ep if kernel in ENERGY_CLASSES else sp
+    # in a BF16X3 stage the force bias, HS potential, Taylor terms and exchange run on the
+    # BF16 split; the adjoint is FP32
+    if pk == "bf16x3" and kernel not in ("vhs", "taylor", "exchange", "vbias"):
+        pk = "fp32"
+    return pk
+
+
+def roofline(path_res, path, cfg, kernel=None):
     """Roofline of one kernel class of a path (default: the one with the most time per
     block)."""
     kern = path_res["kernels"]
@@ -344,20 +371,18 @@ def roofline(path_res, prec_key, cfg, kernel=None):
         return {"kernel": dom, "bound": "alu", "achieved": None, "peak": None, "unit": None,
                 "frac": None, "traffic": None}
     ach = fl / (kern[dom]["ms_per_launch"] * 1e-3) / 1e12
-    # in the BF16X3 mode the HS potential, the Taylor terms and the exchange run on the
-    # BF16 split, the rest in FP32
-    pk = "fp32" if prec_key == "bf16x3" and dom not in ("vhs", "taylor", "exchange") else prec_key
-    return {"kernel": dom, "bound": "mfma", "achieved": round(ach, 3), "peak": PEAK[pk],
-            "unit": "TFLOP/s", "frac": round(ach / PEAK[pk], 4),
-            "traffic": measured_traffic(dom, prec_key), "flops_per_launch": fl}
+    pk = kernel_prec(path, dom)
+    return {"kernel": dom, "precision": pk, "bound": "mfma", "achieved": round(ach, 3),
+            "peak": PEAK[pk], "unit": "TFLOP/s", "frac": round(ach / PEAK[pk], 4),
+            "traffic": measured_traffic(dom, pk), "flops_per_launch": fl}
 
 
-def exchange_roofline(path_res, prec_key, cfg):
+def exchange_roofline(path_res, path, cfg):
     """Roofline of the exchange; in the BF16X3 mode also the MFMA work the hardware executes
     (three BF16 passes, the contraction index r padded to a multiple of 32) against the
     dense BF16 peak."""
-    r = roofline(path_res, prec_key, cfg, "exchange")
-    if r is None or prec_key != "bf16x3":
+    r = roofline(path_res, path, cfg, "exchange")
+    if r is None or r["precision"] != "bf16x3":
         return r
     kp = 32 * ((cfg["m"] + 31) // 32)
     ex = 3.0 * r["flops_per_launch"] * kp / cfg["m"]
@@ -369,24 +394,129 @@ def exchange_roofline(path_res, prec_key, cfg):
 
 
 def energy_evals(v, cfg):
-    """Walker energy evaluations per second: walkers / (exchange + one-body/Coulomb/reduction time)."""
+    """Walker energy evaluations per second: walkers / time of the energy's launches (its
+    Cholesky-vector traces X for the Coulomb term, which run as one more force-bias launch,
+    the exchange, and the one-body/Coulomb/reduction kernels)."""
     k = v["kernels"]
     ms = sum(k[c]["ms_total"] for c in ("exchange", "energy_rest") if c in k)
+    vb = k.get("vbias")
+    if vb and vb["launches"] > cfg["nsteps"]:
+        ms += vb["ms_per_launch"] * (vb["launches"] - cfg["nsteps"])
     return round(cfg["nwalk"] * 1e3 / ms, 2) if ms > 0 else None
 
 
-def cpu_baseline(s, U0, xs_host):
-    """The FP64 oracle on the host cores, on a bounded sample of the same block."""
+DTYPE = {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f32+f64",
+         "bf16x3+fp64E": "bf16x3+f64", "bf16x3+fp32E": "bf16x3+f32+f64"}
+
+
+def step_from(p, st, x0):
+    """One step of p from a saved walker state (U, Gh, logdet, weight, status); returns the
+    new U, Gh and weights (device copies)."""
+    for k in ("U", "Gh", "logdet", "weight", "status"):
+        getattr(p, k).copy_(st[k])
+    p.step(x0)
+    return {"U": p.U.clone(), "Gh": p.Gh.clone(), "weight": p.weight.clone()}
+
+
+def overlap_cond(U, A):
+    """2-norm condition number of each walker's overlap matrix A^H U (A block diagonal)."""
     import numpy as np
-    from oracle import kpoint as kp
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        threads = None
-    cores = len(os.sched_getaffinity(0))
-    nw = 4
-    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    nk, m, nocc = A.shape
+    U = np.asarray(U).reshape(U.shape[0], nk, m, -1)
+    O = np.einsum("kpa,wkpj->wkaj", A.conj(), U).reshape(U.shape[0], nk * nocc, -1)
+    return np.linalg.cond(O)
+
+
+def _stats(d, mask=None):
+    import numpy as np
+    d = np.asarray(d, dtype=float)
+    out = {"max": float(d.max()), "median": float(np.median(d))}
+    if mask is not None:
+        out["live_walkers"] = int(mask.sum())
+        out["live_max"] = float(d[mask].max()) if mask.any() else None
+    return out
+
+
+def accuracy_report(p64, first, st64, initial, s, cfg):
+    """Errors of every path against the FP64 path, |dE_L| in Ha per cell.
+
+    trajectory: each path propagated on its own from the same start for one block
+      (measures the chaos of the walk as much as the precision: an FP64 run with 1e-13
+      relative noise on the fields ends about 1e-6 away);
+    energy_at_fp64_state: the path's local-energy stage on the FP64 path's walkers after
+      that block (the tolerance applies here: on the walkers that carry weight and to the
+      weighted mixed estimate);
+    step_at_fp64_state: one step of the path from that state, its energies evaluated in
+      FP64 (the error one step of its propagation adds);
+    initial_walkers: the energy stage on the initial walkers.
+    A walker is live when its weight is positive."""
+    import numpy as np
+    nk = cfg["nk"]
+
+    def tot(E):
+        return np.asarray(E).sum(1) / nk
+
+    def mixed(e, w):
+        return complex((w * e).sum() / w.sum()) if w.sum() > 0 else complex("nan")
+
+    f64 = first["fp64"]
+    e64 = tot(f64["E"].cpu().numpy())
+    w64 = f64["weight"].cpu().numpy()
+    live = w64 > 0
+    cond = overlap_cond(f64["U"].cpu().numpy(), s.A)
+    st = st64["step"]
+    e64s = tot(p64.energy(Gh=st["Gh"]).cpu().numpy())
+    w64s = st["weight"].cpu().numpy()
+    acc = {"tolerance": TOL, "unit": "Ha/cell",
+           "reading": "the tolerance applies to the local energy at a common walker state "
+                      "(the FP64 path's walkers after one block): max |dE_L| over the live "
+                      "walkers and |dE| of the weighted mixed estimate; the other figures "
+                      "are reported beside it",
+           "fp64_state": {"walkers": int(len(w64)), "live_walkers": int(live.sum()),
+                          "mixed_energy_per_cell": [float(mixed(e64, w64).real),
+                                                    float(mixed(e64, w64).imag)],
+                          "cond_overlap": _stats(cond, live),
+                          "cond_overlap_min": float(cond.min())}}
+    for name in first:
+        if name == "fp64":
+            continue
+        f = first[name]
+        ent = {}
+        e = tot(f["E"].cpu().numpy())
+        w = f["weight"].cpu().numpy()
+        both = live & (w > 0)
+        ent["trajectory"] = _stats(np.abs(e - e64), both)
+        ent["trajectory"]["mixed_abs_dE"] = abs(mixed(e, w) - mixed(e64, w64))
+        o = st64["others"][name]
+        e2 = tot(o["E"])
+        ent["energy_at_fp64_state"] = _stats(np.abs(e2 - e64), live)
+        ent["energy_at_fp64_state"]["mixed_abs_dE"] = abs(mixed(e2, w64) - mixed(e64, w64))
+        so = o["step"]
+        e3 = tot(p64.energy(Gh=so["Gh"]).cpu().numpy())
+        w3 = so["weight"].cpu().numpy()
+        both3 = (w3 > 0) & (w64s > 0)
+        ent["step_at_fp64_state"] = _stats(np.abs(e3 - e64s), both3)
+        dU = ((so["U"] - st["U"]).abs().pow(2).sum((1, 2)).sqrt() /
+              st["U"].abs().pow(2).sum((1, 2)).sqrt()).cpu().numpy()
+        ent["step_at_fp64_state"]["rel_dU"] = _stats(dU)
+        ent["initial_walkers"] = _stats(np.abs(initial[name] - initial["fp64"]))
+        es = ent["energy_at_fp64_state"]
+        ent["meets_tolerance"] = bool(es["live_max"] is not None and es["live_max"] <= TOL
+                                      and es["mixed_abs_dE"] <= TOL)
+        acc[name] = ent
+        log(f"accuracy {name}: energy at the FP64 state: live max {es['live_max']:.3e}, "
+            f"mixed {es['mixed_abs_dE']:.3e}, all-walker max {es['max']:.3e} Ha/cell; "
+            f"one step from it: live max {ent['step_at_fp64_state']['live_max']} Ha/cell; "
+            f"own trajectory: live max {ent['trajectory']['live_max']}, mixed "
+            f"{ent['trajectory']['mixed_abs_dE']:.3e}; initial walkers max "
+            f"{ent['initial_walkers']['max']:.3e}")
+    return acc
+
+
+def _oracle_rate(kp, s, pre, U0, xs_host, nw, ne):
+    """Oracle walker-steps/s from one step of nw walkers, QR + G of nw walkers and the
+    local energy of ne walkers; returns (rate, description)."""
+    import numpy as np
     U = U0[:nw]
     Gh, ld = kp.greens(U, s.A)
     t = time.perf_counter()
@@ -397,15 +527,36 @@ def cpu_baseline(s, U0, xs_host):
     kp.greens(Q, s.A)
     t_qr = time.perf_counter() - t
     t = time.perf_counter()
-    kp.local_energy(pre["Lh"], pre["h1h"], out["Gh"], s.mesh, walkers=[0])
+    kp.local_energy(pre["Lh"], pre["h1h"], out["Gh"], s.mesh, walkers=list(range(ne)))
     t_e = time.perf_counter() - t
     nsteps = xs_host.shape[0]
-    per_ws = t_step / nw + (t_qr / nw + t_e) / nsteps
-    return {"value": round(1.0 / per_ws, 3), "unit": "walker-steps/s",
-            "cores": threads if threads else cores, "host_cores": cores, "kind": "oracle",
-            "sample": (f"1 propagation step of {nw} walkers ({t_step:.2f} s), QR+G of {nw} "
-                       f"walkers ({t_qr:.2f} s), local energy of 1 walker ({t_e:.2f} s); "
-                       f"walker-steps/s = 1/(t_step/{nw} + (t_qr/{nw} + t_E)/{nsteps})")}
+    per_ws = t_step / nw + (t_qr / nw + t_e / ne) / nsteps
+    return 1.0 / per_ws, (f"1 propagation step of {nw} walkers ({t_step:.2f} s), QR+G of "
+                          f"{nw} walkers ({t_qr:.2f} s), local energy of {ne} walkers "
+                          f"({t_e:.2f} s)")
+
+
+def cpu_baseline(s, U0, xs_host):
+    """The FP64 oracle on the host cores, on a bounded sample of the same block, with the
+    BLAS threads of this process and with one thread."""
+    from oracle import kpoint as kp
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threadpool_limits, threads = None, None
+    cores = len(os.sched_getaffinity(0))
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    rate, desc = _oracle_rate(kp, s, pre, U0, xs_host, 8, 2)
+    out = {"value": round(rate, 3), "unit": "walker-steps/s",
+           "cores": threads if threads else cores, "host_cores": cores, "kind": "oracle",
+           "sample": (desc + "; walker-steps/s = 1/(t_step/nw + (t_QR/nw + t_E/ne)/"
+                      f"{xs_host.shape[0]}) for the {xs_host.shape[0]}-step block")}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            r1, d1 = _oracle_rate(kp, s, pre, U0, xs_host, 2, 1)
+        out["single_thread"] = {"value": round(r1, 3), "cores": 1, "sample": d1}
+    return out
 
 
 def gen_system(name, torch):
@@ -710,7 +861,8 @@ def main():
     ap.add_argument("--config", default="c1",
                     help="c1 (headline), c0, c2 (4x4x4 energy precisions), c3 (uneven batch modes) or "
                          "c4 (energy adjoint)")
-    ap.add_argument("--prec", choices=["all", "fp64", "fp32", "bf16x3"], default="all")
+    ap.add_argument("--prec", default="all",
+                    help="all, or a comma-separated list of paths: " + ", ".join(PATHS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (scale reference for HBM counters)")
@@ -760,58 +912,51 @@ def main():
     U0d = torch.from_numpy(U0).cuda()
     xs = torch.from_numpy(xs_host).cuda()
 
-    res, E0, W0 = {}, {}, {}
-    paths = ["fp64", "fp32", "bf16x3"] if args.prec == "all" else [args.prec]
-    precs = {"fp64": lib.PREC_FP64, "fp32": lib.PREC_FP32, "bf16x3": lib.PREC_BF16X3}
-    G64 = None
-    same_state, initial = {}, {}
+    res, first, acc = {}, {}, None
+    paths = list(PATHS) if args.prec == "all" else args.prec.split(",")
     for name in paths:
-        p = make_problem(s, U0, precs[name], torch)
-        res[name], E0[name], W0[name] = bench_path(name, p, U0d, xs, args, torch, cfg)
+        if name not in PATHS:
+            sys.exit(f"bench.py: unknown path {name!r} (known: {', '.join(PATHS)})")
+    if "fp64" in paths:  # the reference path first: every other path is compared with it
+        paths.remove("fp64")
+        paths.insert(0, "fp64")
+    code = {"fp64": lib.PREC_FP64, "fp32": lib.PREC_FP32, "bf16x3": lib.PREC_BF16X3}
+    p64, initial, state64 = None, {}, {}
+    for name in paths:
+        sp, ep = PATHS[name]
+        prec = code[sp] if sp == ep else lib.prec_place(code[sp], code[ep])
+        p = make_problem(s, U0, prec, torch)
+        res[name], first[name] = bench_path(name, p, U0d, xs, args, torch, cfg)
         # every path's energies on the initial walkers (the same Gh: FP64 greens)
         reset(p, U0d)
         initial[name] = p.energy().sum(1).cpu().numpy() / cfg["nk"]
         if name == "fp64":
-            G64 = bench_path.G_end
-        elif G64 is not None:
-            # the reduced-precision contractions on the FP64 path's state after the block
-            same_state[name] = p.energy(Gh=G64).sum(1).cpu().numpy() / cfg["nk"]
+            p64 = p
+            state64 = first[name]
+            # one FP64 step from the FP64 path's state after the block
+            state64["step"] = step_from(p64, state64, xs[0])
+            continue
+        if p64 is not None:
+            # the path's stages at the FP64 path's state after the block: its local energy
+            # there, and one of its steps from there (evaluated with the FP64 energy)
+            state64.setdefault("others", {})[name] = {
+                "E": p.energy(Gh=state64["Gh"]).cpu().numpy(),
+                "step": step_from(p, state64, xs[0]),
+            }
         del p
         torch.cuda.empty_cache()
 
-    acc = None
-    if "fp64" in res and len(res) > 1:
-        e64 = E0["fp64"].sum(1).cpu().numpy() / cfg["nk"]
-        acc = {"tolerance": TOL,
-               "compared": "E_L per walker after one block from the same start, against the "
-                           "FP64 GPU path (which matches the FP64 oracle to 1e-10)",
-               "same_state_compared": "the path's energies evaluated on the FP64 path's Green's "
-                                      "functions after that block",
-               "initial_walkers_compared": "the path's energies of the initial walkers"}
-        for name in res:
-            if name == "fp64":
-                continue
-            d = np.abs(E0[name].sum(1).cpu().numpy() / cfg["nk"] - e64)
-            ent = {"max_abs_dE_per_cell": float(d.max()),
-                   "median_abs_dE_per_cell": float(np.median(d))}
-            if name in same_state:
-                d2 = np.abs(same_state[name] - e64)
-                ent["same_state_max_abs_dE_per_cell"] = float(d2.max())
-                ent["same_state_median_abs_dE_per_cell"] = float(np.median(d2))
-            d3 = np.abs(initial[name] - initial["fp64"])
-            ent["initial_walkers_max_abs_dE_per_cell"] = float(d3.max())
-            ent["initial_walkers_median_abs_dE_per_cell"] = float(np.median(d3))
-            acc[name] = ent
-            log(f"accuracy {name}: max |dE_L| = {d.max():.3e} Ha/cell (median "
-                f"{np.median(d):.3e}); same state max "
-                f"{ent.get('same_state_max_abs_dE_per_cell', float('nan')):.3e}; initial "
-                f"walkers max {d3.max():.3e}")
+    if p64 is not None and len(res) > 1:
+        acc = accuracy_report(p64, first, state64, initial, s, cfg)
+        del p64
+        torch.cuda.empty_cache()
 
-    # the fastest path whose block-level energies meet the tolerance; FP64 otherwise
+    # the fastest path whose local energy meets the tolerance at the common state; FP64
+    # otherwise
     use = "fp64" if "fp64" in res else paths[0]
     if acc is not None:
         for name in sorted(res, key=lambda k: -res[k]["walker_steps_per_s"]):
-            if name == "fp64" or acc[name]["max_abs_dE_per_cell"] <= TOL:
+            if name == "fp64" or acc[name]["meets_tolerance"]:
                 use = name
                 break
     main_res = res[use]
@@ -826,7 +971,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f32+f64"}[use],
+        "dtype": DTYPE[use],
         "data": "synthetic",
         "config": {"workload": f"{args.config}: mesh {'x'.join(map(str, cfg['mesh']))}, "
                                f"m={cfg['m']}, nocc={cfg['nocc']}, nchol={cfg['nchol']}, "
