@@ -79,8 +79,21 @@ typedef enum {
 typedef enum {
   AFQMC_PREC_FP64 = 0,
   AFQMC_PREC_FP32 = 1,
-  AFQMC_PREC_BF16X3 = 2
+  AFQMC_PREC_BF16X3 = 2,
+  AFQMC_PREC_INT8X5 = 3   /* local energy only, see AFQMC_PREC_PLACE */
 } afqmc_prec;
+
+/* AFQMC_PREC_INT8X5, an energy precision: the exchange contraction of afqmc_kpt_energy on
+ * int8 MFMA with exact int32 accumulation (an Ozaki-type split).  Every row of the real
+ * operands [Re | Im] of Lh (per Q, k, a, g, over r) and of Gh (per walker, row and column
+ * block, over r) is scaled by a power of two s with |x| < s / 2 and cut into five signed
+ * 7-bit digits, x = s (d1 / 128 + d2 / 128^2 + ... + d5 / 128^5) + rest, |d| <= 64; the
+ * digit products of levels i + j <= 6 are summed exactly in int32 per level, the levels
+ * combined exactly in FP64 and scaled by the two powers of two.  Each product of the
+ * contraction is then exact up to 1.5 * 2^-35 s s' (truncated digits and dropped levels),
+ * 2^-35 = 2.9e-11.  The one-body and Coulomb parts, the pairing and all sums are FP64; the
+ * adjoint (afqmc_kpt_energy_backward) runs in FP64.  Needs Lh8 (written by prepare) and
+ * m <= 64. */
 
 /* Precision placement ("GPU Implementation": the paper runs the whole method in single
  * precision; here each group of contractions has its own).  The prec field of a problem is
@@ -94,6 +107,7 @@ typedef enum {
  * present (e.g. Lhs and Ls for a BF16X3 step, Lh32 for a reduced energy); prepare writes
  * all of them. */
 #define AFQMC_PREC_PLACE(step, energy) ((step) | (((energy) + 1) << 4))
+/* (step: FP64, FP32 or BF16X3; energy: any afqmc_prec) */
 
 /* Per-walker status bits. */
 #define AFQMC_WALKER_SINGULAR 1  /* overlap matrix A^H U had a zero pivot */
@@ -165,6 +179,18 @@ typedef struct afqmc_kpt_problem {
   void* logdet;      /* [nwalk] complex128, log det(A^H U) (imaginary part in (-pi, pi]) */
   double* weight;    /* [nwalk] walker weights */
   int32_t* status;   /* [nwalk] AFQMC_WALKER_* bits (sticky: OR-ed in, never cleared) */
+  /* energy shift of the projector exp(-dt (H - E_T)) */
+  double* etrial;    /* [1] float64 E_T per supercell (Ha), device, or NULL for no shift:
+                        every step multiplies each weight by exp(dt E_T), a common factor
+                        that keeps the weights of long runs finite; read by the weight
+                        update, written by afqmc_kpt_update_etrial */
+  /* energy precision AFQMC_PREC_INT8X5 only (else NULL), written by prepare */
+  void* Lh8;         /* int8 digits of Lh: [nk][nk][nchol][nocc] rows of 5 x KP8 digits
+                        (digit d1 .. d5, each over kk = 0 .. KP8-1: Re Lh[Q][k][a][kk][g]
+                        for kk < m, Im Lh[..][kk - m][g] for m <= kk < 2m, 0 beyond;
+                        KP8 = 64 ceil(2m / 64)), followed by the rows' int32 exponents
+                        e ([nk][nk][nchol][nocc], s = 2^e); bytes:
+                        nk^2 nchol nocc (5 KP8 + 4) */
 } afqmc_kpt_problem;
 
 /* Workspace (device bytes) the given entry point needs for these problems.
@@ -218,7 +244,7 @@ afqmc_status afqmc_kpt_vhs(const afqmc_kpt_problem* p, int nprob, const double* 
  * computed term by term (T_j = V T_{j-1} / j); then the new Gh and logdet, and
  *   log I = 2 (logdet' - logdet) + sum_{Q,g,+/-} (x xbar - xbar^2 / 2),
  *   dtheta = arg exp(2 (logdet' - logdet)),
- *   weight <- |I| max(0, cos dtheta) weight.
+ *   weight <- |I| max(0, cos dtheta) exp(dt E_T) weight   (E_T = *etrial, or 0 if NULL).
  * With AFQMC_PROPAGATE_ORTHO the walkers are re-orthonormalised afterwards
  * (see afqmc_kpt_orthonormalize).  vhs, x, xbar as in afqmc_kpt_vhs. */
 afqmc_status afqmc_kpt_propagate(const afqmc_kpt_problem* p, int nprob, const void* vhs,
@@ -284,6 +310,31 @@ afqmc_status afqmc_kpt_mixed_energy(const afqmc_kpt_problem* p, int nprob, const
 afqmc_status afqmc_kpt_population_control(const afqmc_kpt_problem* p, int nprob,
                                           const double* xi, int32_t* const* parent, void* ws,
                                           size_t ws_bytes, void* stream);
+
+/* Energy shift between blocks: E_T <- (1 - blend) E_T + blend Re(Emix[i]) for every problem
+ * i whose mixed estimate Emix[i] (from afqmc_kpt_mixed_energy, device [nprob] complex128)
+ * is finite; E_T is left as it is otherwise.  Requires etrial in every problem; blend in
+ * (0, 1].  Device-side, so a captured block can include it.  FP64. */
+afqmc_status afqmc_kpt_update_etrial(const afqmc_kpt_problem* p, int nprob, const void* Emix,
+                                     double blend, void* stream);
+
+/* One level of a blocking analysis. */
+typedef struct afqmc_reblock_level {
+  int64_t n;       /* blocks at this level */
+  double mean;     /* their mean (the same at every level up to the dropped tail) */
+  double err;      /* standard error of the mean, sqrt(s^2 / n), s^2 with n - 1 */
+  double err_err;  /* its uncertainty, err / sqrt(2 (n - 1)) */
+} afqmc_reblock_level;
+
+/* Blocking analysis of a serially correlated series, e.g. the mixed energies of successive
+ * blocks (the error bars of the paper's results): level 0 is the series x[0..n-1], level
+ * l + 1 the means of neighbouring pairs of level l (an odd last element dropped), down to
+ * two blocks.  *optimal is the first level whose block size B = 2^l satisfies
+ * B^3 > 2 n (err_l / err_0)^4 (Lee, Needs and Towler, Phys. Rev. E 83, 066706 (2011)),
+ * or -1.  Host arrays: x [n]; levels [max_levels] out (the first min(*nlevels,
+ * max_levels) written).  Sums in FP64 in series order.  Needs no device. */
+afqmc_status afqmc_kpt_reblock(const double* x, int64_t n, afqmc_reblock_level* levels,
+                               int max_levels, int* nlevels, int* optimal);
 
 /* Packed layout of one per-call buffer for a batch (host).  offsets: host
  * array of nprob + 1 entries; offsets[i] is the byte offset of problem i's

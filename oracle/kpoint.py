@@ -243,18 +243,19 @@ def propagate(U, vhs, bhalf, dt, order=6):
     return apply_block_diag(bhalf, T)
 
 
-def weight_update(logdet_old, logdet_new, x, xbar, w_old):
+def weight_update(logdet_old, logdet_new, x, xbar, w_old, shift=0.0):
     """Hybrid phaseless weight update.
 
     r = (det O'/det O)^2; I = r exp(sum (x xbar - xbar^2/2)) (bilinear, summed
-    over Q, g and +/-); dtheta = arg r; w' = |I| max(0, cos dtheta) w.
+    over Q, g and +/-); dtheta = arg r; w' = |I| max(0, cos dtheta) e^shift w, where
+    shift = dt E_T is the energy shift of the projector exp(-dt (H - E_T)) (0: none).
     Returns (w_new, log_I, dtheta).
     """
     log_r = 2.0 * (logdet_new - logdet_old)
     s = np.sum(x * xbar - 0.5 * xbar * xbar, axis=(1, 2, 3))
     log_I = log_r + s
     dtheta = np.angle(np.exp(1j * log_r.imag))
-    w_new = np.exp(log_I.real) * np.maximum(0.0, np.cos(dtheta)) * w_old
+    w_new = np.exp(log_I.real + shift) * np.maximum(0.0, np.cos(dtheta)) * w_old
     return w_new, log_I, dtheta
 
 
@@ -269,15 +270,16 @@ def orthonormalize(U):
     return out
 
 
-def step(U, logdet, weight, x, pre, A, L, mesh, dt, order=6):
-    """One walker-batch step: force bias -> HS potential -> propagate -> G, weights."""
+def step(U, logdet, weight, x, pre, A, L, mesh, dt, order=6, etrial=0.0):
+    """One walker-batch step: force bias -> HS potential -> propagate -> G, weights (with
+    the energy shift E_T = etrial per supercell)."""
     Gh, _ = greens(U, A)
     xbar, X = force_bias(pre["Lh"], Gh, mesh, dt)
     zeta = combined_field(x, xbar, mesh)
     vhs = hs_potential(L, zeta, mesh)
     U2 = propagate(U, vhs, pre["bhalf"], dt, order)
     Gh2, logdet2 = greens(U2, A)
-    w2, log_I, dth = weight_update(logdet, logdet2, x, xbar, weight)
+    w2, log_I, dth = weight_update(logdet, logdet2, x, xbar, weight, shift=dt * etrial)
     return dict(U=U2, Gh=Gh2, logdet=logdet2, weight=w2, xbar=xbar, X=X, vhs=vhs,
                 log_I=log_I, dtheta=dth)
 

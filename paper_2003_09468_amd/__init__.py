@@ -17,6 +17,7 @@ from .binding import (  # noqa: F401
     PREC_FP64,
     PREC_FP32,
     PREC_BF16X3,
+    PREC_INT8X5,
     prec_place,
     step_prec,
     energy_prec,
@@ -25,6 +26,7 @@ from .binding import (  # noqa: F401
     WALKER_KILLED,
     ENTRIES,
     local_energy,
+    reblock,
     timing_enable,
     timing_read,
     KERNEL_CLASSES,

@@ -19,6 +19,7 @@ _LIBNAME = "libafqmc_kpt.so"
 PREC_FP64 = 0
 PREC_FP32 = 1
 PREC_BF16X3 = 2
+PREC_INT8X5 = 3  # energy precision only (prec_place(step, PREC_INT8X5))
 
 
 def prec_place(step: int, energy: int) -> int:
@@ -69,6 +70,8 @@ EXPORTS = [
     "afqmc_kpt_energy_backward",
     "afqmc_kpt_mixed_energy",
     "afqmc_kpt_population_control",
+    "afqmc_kpt_update_etrial",
+    "afqmc_kpt_reblock",
     "afqmc_kpt_buffer_layout",
     "afqmc_kpt_step",
     "afqmc_kpt_autotune",
@@ -117,6 +120,8 @@ class Problem(ctypes.Structure):
         ("logdet", ctypes.c_void_p),
         ("weight", ctypes.c_void_p),
         ("status", ctypes.c_void_p),
+        ("etrial", ctypes.c_void_p),
+        ("Lh8", ctypes.c_void_p),
     ]
 
 
@@ -152,6 +157,9 @@ def lib():
         "afqmc_kpt_energy_backward": [P, i, vp, vp, vp, sz, vp],
         "afqmc_kpt_mixed_energy": [P, i, vp, vp, vp],
         "afqmc_kpt_population_control": [P, i, vp, vp, vp, sz, vp],
+        "afqmc_kpt_update_etrial": [P, i, vp, ctypes.c_double, vp],
+        "afqmc_kpt_reblock": [vp, ctypes.c_int64, vp, i, ctypes.POINTER(i),
+                              ctypes.POINTER(i)],
         "afqmc_kpt_buffer_layout": [P, i, i, ctypes.POINTER(sz)],
         "afqmc_kpt_step": [P, i, vp, i, vp, vp, vp, i, vp, sz, vp],
         "afqmc_kpt_autotune": [P, i, vp, vp, sz, vp],
@@ -204,6 +212,27 @@ def _stream() -> int:
     return torch.cuda.current_stream().cuda_stream
 
 
+class ReblockLevel(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("mean", ctypes.c_double), ("err", ctypes.c_double),
+                ("err_err", ctypes.c_double)]
+
+
+def reblock(x):
+    """Blocking analysis of a host series (afqmc_kpt_reblock): a list of levels
+    (n, mean, err, err_err) and the index of the level to quote (-1: none)."""
+    vals = [float(v) for v in x]
+    xs = (ctypes.c_double * max(len(vals), 1))(*vals)
+    cap = 64
+    lv = (ReblockLevel * cap)()
+    nl, opt = ctypes.c_int(0), ctypes.c_int(0)
+    check("afqmc_kpt_reblock",
+          lib().afqmc_kpt_reblock(ctypes.addressof(xs), len(vals), lv, cap, ctypes.byref(nl),
+                                  ctypes.byref(opt)))
+    out = [(int(l.n), float(l.mean), float(l.err), float(l.err_err))
+           for l in lv[:min(nl.value, cap)]]
+    return out, int(opt.value)
+
+
 class KptProblem:
     """One k-point system and its walker batch, with device buffers owned by torch.
 
@@ -229,9 +258,15 @@ class KptProblem:
         sp, ep = step_prec(self.prec), energy_prec(self.prec)
         self.L32 = (torch.empty(self.L.shape, dtype=torch.complex64, **kw)
                     if sp == PREC_FP32 else None)
+        low = (PREC_FP32, PREC_BF16X3)
         self.Lh32 = (torch.empty(self.Lh.shape, dtype=torch.complex64, **kw)
-                     if sp != PREC_FP64 or ep != PREC_FP64 else None)
-        self.Lhs = self.Ls = None
+                     if sp in low or ep in low else None)
+        self.Lhs = self.Ls = self.Lh8 = None
+        if ep == PREC_INT8X5:
+            # five int8 digits per element of [Re | Im] rows padded to 64, then int32 exponents
+            kp8 = 64 * ((2 * m + 63) // 64)
+            rows = nk * nk * nchol * nocc
+            self.Lh8 = torch.empty(rows * (5 * kp8 + 4), dtype=torch.int8, **kw)
         if PREC_BF16X3 in (sp, ep):
             kp = 32 * ((m + 31) // 32)
             self.Lhs = torch.empty((nk, nk, nchol, nocc, 4, kp), dtype=torch.int16, **kw)
@@ -244,6 +279,7 @@ class KptProblem:
         self.logdet = torch.zeros(nwalk, dtype=c128, **kw)
         self.weight = torch.ones(nwalk, dtype=torch.float64, **kw)
         self.status = torch.zeros(nwalk, dtype=torch.int32, **kw)
+        self.etrial = torch.zeros(1, dtype=torch.float64, **kw)  # E_T per supercell
         self._ws = None
         self.struct = self._make_struct()
 
@@ -255,11 +291,13 @@ class KptProblem:
         p.prec, p.dt = self.prec, self.dt
         p.L, p.A, p.Lh, p.h1h, p.bhalf = (_ptr(self.L), _ptr(self.A), _ptr(self.Lh),
                                           _ptr(self.h1h), _ptr(self.bhalf))
+        p.Lh8 = _ptr(self.Lh8)
         p.L32, p.Lh32, p.Lhs, p.Ls = (_ptr(self.L32), _ptr(self.Lh32), _ptr(self.Lhs),
                                       _ptr(self.Ls))
         p.U = _ptr(self.U)
         p.Gh = _ptr(self.Gh if Gh is None else Gh)
         p.logdet, p.weight, p.status = _ptr(self.logdet), _ptr(self.weight), _ptr(self.status)
+        p.etrial = _ptr(self.etrial)
         return p
 
     def workspace_bytes(self, entry: str) -> int:
@@ -363,6 +401,18 @@ class KptProblem:
               lib().afqmc_kpt_mixed_energy(ctypes.byref(self.struct), 1, E.data_ptr(),
                                            out.data_ptr(), _stream()))
         return out[0]
+
+    def set_etrial(self, value):
+        """Energy shift E_T (per supercell) of the projector exp(-dt (H - E_T))."""
+        self.etrial.fill_(float(value))
+
+    def update_etrial(self, Emix, blend=1.0):
+        """E_T <- (1 - blend) E_T + blend Re(Emix) on the device (Emix: [1] complex128 from
+        mixed_energy, e.g. a view of its result); a non-finite Emix leaves E_T."""
+        Emix = Emix.reshape(1).to(dtype=torch.complex128)
+        check("afqmc_kpt_update_etrial",
+              lib().afqmc_kpt_update_etrial(ctypes.byref(self.struct), 1, Emix.data_ptr(),
+                                            float(blend), _stream()))
 
     def population_control(self, xi):
         """Comb population control with the uniform number xi in [0, 1): resamples U, Gh,

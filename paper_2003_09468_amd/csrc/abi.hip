@@ -18,6 +18,10 @@ size_t backward_ws_bytes(const afqmc_kpt_problem& p);
 size_t population_ws_bytes(const afqmc_kpt_problem& p);
 hipError_t run_population(const afqmc_kpt_problem* p, int nprob, const double* xi,
                           int32_t* const* parent, void* ws, hipStream_t s);
+hipError_t run_update_etrial(const afqmc_kpt_problem* p, int nprob, const void* Emix,
+                             double blend, hipStream_t s);
+int reblock_host(const double* x, int64_t n, afqmc_reblock_level* levels, int max_levels,
+                 int* optimal);
 
 size_t ws_bytes_entry(const afqmc_kpt_problem& p0, int entry) {
   // the step entry sizes each of its stages in that stage's precision
@@ -87,7 +91,8 @@ enum Need : unsigned {
   N_L = 1u << 0, N_A = 1u << 1, N_LH = 1u << 2, N_H1H = 1u << 3, N_BHALF = 1u << 4,
   N_U = 1u << 5, N_GH = 1u << 6, N_LOGDET = 1u << 7, N_WEIGHT = 1u << 8, N_STATUS = 1u << 9,
   N_LD = 1u << 10, N_LHD = 1u << 11,  // *D: the complex128 arrays in every precision
-  N_LHS = 1u << 12, N_LS = 1u << 13    // the BF16 split planes (BF16X3 problems only)
+  N_LHS = 1u << 12, N_LS = 1u << 13,   // the BF16 split planes (BF16X3 problems only)
+  N_ETRIAL = 1u << 14                  // the energy shift: optional, 8-byte aligned if set
 };
 
 inline bool misaligned(const void* p, size_t a) { return ((uintptr_t)p) % a != 0; }
@@ -110,8 +115,8 @@ afqmc_status check_dims(const afqmc_kpt_problem& p) {
   if ((int64_t)p.mesh[0] * p.mesh[1] * p.mesh[2] != p.nk) return AFQMC_EINVAL;
   if (p.m < 1 || p.nocc < 1 || p.nocc > p.m || p.nchol < 1 || p.nwalk < 1) return AFQMC_EINVAL;
   // an afqmc_prec value, or AFQMC_PREC_PLACE(step, energy)
-  if ((p.prec & ~0x3f) != 0 || (p.prec & 15) > AFQMC_PREC_BF16X3 ||
-      (p.prec >> 4) > AFQMC_PREC_BF16X3 + 1)
+  if ((p.prec & ~0x7f) != 0 || (p.prec & 15) > AFQMC_PREC_BF16X3 ||
+      (p.prec >> 4) > AFQMC_PREC_INT8X5 + 1)
     return AFQMC_EINVAL;
   if (!(p.dt > 0.0) || !isfinite(p.dt)) return AFQMC_EINVAL;
   // sizes the kernels implement
@@ -138,6 +143,7 @@ afqmc_status check_fields(const afqmc_kpt_problem& p, unsigned need) {
   if (need & N_LOGDET) AFQMC_TRY(check_ptr(p.logdet, 16));
   if (need & N_WEIGHT) AFQMC_TRY(check_ptr(p.weight, 8));
   if (need & N_STATUS) AFQMC_TRY(check_ptr(p.status, 4));
+  if ((need & N_ETRIAL) && p.etrial && misaligned(p.etrial, 8)) return AFQMC_EALIGN;
   if ((need & N_LHS) && p.prec == AFQMC_PREC_BF16X3) AFQMC_TRY(check_ptr(p.Lhs, 16));
   if ((need & N_LS) && p.prec == AFQMC_PREC_BF16X3) AFQMC_TRY(check_ptr(p.Ls, 16));
   return AFQMC_OK;
@@ -153,6 +159,13 @@ afqmc_status check_problems(const afqmc_kpt_problem* p, int nprob, unsigned need
     AFQMC_TRY(check_dims(p[i]));
     AFQMC_TRY(check_fields(stage_view(p[i], energy), need));
   }
+  return AFQMC_OK;
+}
+
+// The int8-split energy reads the digits of Lh.
+afqmc_status check_int8x5(const afqmc_kpt_problem* p, int nprob) {
+  for (int i = 0; i < nprob; ++i)
+    if (energy_prec(p[i].prec) == AFQMC_PREC_INT8X5) AFQMC_TRY(check_ptr(p[i].Lh8, 16));
   return AFQMC_OK;
 }
 
@@ -220,6 +233,7 @@ std::vector<Job> make_jobs(const afqmc_kpt_problem* p, int nprob, int entry, voi
   for (int i = 0; i < nprob; ++i) {
     Job& j = jobs[i];
     j.p = stage_view(p[i], energy_entry(entry));
+    j.int8x5 = entry == AFQMC_ENTRY_ENERGY && energy_prec(p[i].prec) == AFQMC_PREC_INT8X5;
     j.ws = ws ? (char*)ws + wo : nullptr;
     wo += align_up(ws_bytes_entry(p[i], entry));
     j.x = slice(b.x, p, nprob, AFQMC_BUF_FIELDS, i, off);
@@ -252,7 +266,11 @@ hipError_t run_steps(std::vector<Job>& jobs, const int* orig_prec, const double*
   if (e == hipSuccess && (flags & AFQMC_STEP_ENERGY)) {
     // the same workspace and buffers, with the problems in their energy precision
     std::vector<Job> ej(jobs);
-    for (int i = 0; i < n; ++i) ej[i].p.prec = energy_prec(orig_prec[i]);
+    for (int i = 0; i < n; ++i) {
+      const int ep = energy_prec(orig_prec[i]);
+      ej[i].int8x5 = ep == AFQMC_PREC_INT8X5;
+      ej[i].p.prec = ej[i].int8x5 ? AFQMC_PREC_FP64 : ep;
+    }
     e = run_energy(ej.data(), n, s);
   }
   return e;
@@ -263,10 +281,12 @@ afqmc_status check_step_args(const afqmc_kpt_problem* p, int nprob, const double
                              size_t ws_bytes) {
   // every step runs the force bias, whose BF16X3 kernel reads the split planes Lhs
   unsigned need = N_L | N_LS | N_LH | N_LHS | N_A | N_BHALF | N_U | N_GH | N_LOGDET | N_WEIGHT |
-                  N_STATUS;
+                  N_STATUS | N_ETRIAL;
   AFQMC_TRY(check_problems(p, nprob, need));
-  if (flags & AFQMC_STEP_ENERGY)
+  if (flags & AFQMC_STEP_ENERGY) {
     AFQMC_TRY(check_problems(p, nprob, N_LH | N_LHS | N_H1H | N_GH, true));
+    AFQMC_TRY(check_int8x5(p, nprob));
+  }
   if (nsteps < 1) return AFQMC_EINVAL;
   if (flags & ~(AFQMC_PROPAGATE_ORTHO | AFQMC_STEP_ENERGY)) return AFQMC_EINVAL;
   if (flags & AFQMC_PROPAGATE_ORTHO) AFQMC_TRY(check_ortho(p, nprob));
@@ -312,6 +332,7 @@ afqmc_status afqmc_kpt_prepare(const afqmc_kpt_problem* p, int nprob, const void
     AFQMC_TRY(check_fields(stage_view(p[i], false), N_L | N_LH | N_LHS | N_LS));
     AFQMC_TRY(check_fields(stage_view(p[i], true), N_LH | N_LHS));
   }
+  AFQMC_TRY(check_int8x5(p, nprob));
   AFQMC_TRY(check_ptr(H1, 16));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_PREPARE, ws, ws_bytes));
   AFQMC_TRY(check_device());
@@ -363,7 +384,8 @@ afqmc_status afqmc_kpt_vhs(const afqmc_kpt_problem* p, int nprob, const double* 
 afqmc_status afqmc_kpt_propagate(const afqmc_kpt_problem* p, int nprob, const void* vhs,
                                  const double* x, const void* xbar, int flags, void* ws,
                                  size_t ws_bytes, void* stream) {
-  AFQMC_TRY(check_problems(p, nprob, N_A | N_BHALF | N_U | N_GH | N_LOGDET | N_WEIGHT | N_STATUS));
+  AFQMC_TRY(check_problems(p, nprob, N_A | N_BHALF | N_U | N_GH | N_LOGDET | N_WEIGHT | N_STATUS |
+                                         N_ETRIAL));
   AFQMC_TRY(check_ptr(vhs, 16));
   AFQMC_TRY(check_ptr(x, 8));
   AFQMC_TRY(check_ptr(xbar, 16));
@@ -392,6 +414,7 @@ afqmc_status afqmc_kpt_orthonormalize(const afqmc_kpt_problem* p, int nprob, voi
 afqmc_status afqmc_kpt_energy(const afqmc_kpt_problem* p, int nprob, void* E, void* ws,
                               size_t ws_bytes, void* stream) {
   AFQMC_TRY(check_problems(p, nprob, N_LH | N_LHS | N_H1H | N_GH, true));
+  AFQMC_TRY(check_int8x5(p, nprob));
   AFQMC_TRY(check_ptr(E, 16));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_ENERGY, ws, ws_bytes));
   AFQMC_TRY(check_device());
@@ -440,6 +463,27 @@ afqmc_status afqmc_kpt_population_control(const afqmc_kpt_problem* p, int nprob,
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_POPULATION, ws, ws_bytes));
   AFQMC_TRY(check_device());
   return hip_status(run_population(p, nprob, xi, parent, ws, (hipStream_t)stream));
+}
+
+afqmc_status afqmc_kpt_update_etrial(const afqmc_kpt_problem* p, int nprob, const void* Emix,
+                                     double blend, void* stream) {
+  AFQMC_TRY(check_problems(p, nprob, 0));
+  for (int i = 0; i < nprob; ++i) AFQMC_TRY(check_ptr(p[i].etrial, 8));
+  AFQMC_TRY(check_ptr(Emix, 16));
+  if (!(blend > 0.0 && blend <= 1.0)) return AFQMC_EINVAL;
+  AFQMC_TRY(check_device());
+  return hip_status(run_update_etrial(p, nprob, Emix, blend, (hipStream_t)stream));
+}
+
+afqmc_status afqmc_kpt_reblock(const double* x, int64_t n, afqmc_reblock_level* levels,
+                               int max_levels, int* nlevels, int* optimal) {
+  if (!x || !nlevels || !optimal) return AFQMC_ENULL;
+  if (n < 1 || max_levels < 0) return AFQMC_EINVAL;
+  if (max_levels > 0 && !levels) return AFQMC_ENULL;
+  for (int64_t i = 0; i < n; ++i)
+    if (!isfinite(x[i])) return AFQMC_EINVAL;
+  *nlevels = reblock_host(x, n, levels, max_levels, optimal);
+  return AFQMC_OK;
 }
 
 afqmc_status afqmc_kpt_buffer_layout(const afqmc_kpt_problem* p, int nprob, int buf,

@@ -687,6 +687,278 @@ __global__ __launch_bounds__(256) void energy_final_kernel(const Batch<EfinArgs>
   }
 }
 
+// ---------------------------------------------------------------------------
+// The exchange on int8 MFMA with exact integer accumulation (energy precision INT8X5).
+//
+// The complex contraction T1 = sum_r Lh[a][r][g] G[b][r] is taken as two real products
+// over kk < 2m: Re T1 = [Re Lh | Im Lh] . [Re G ; -Im G], Im T1 = [Re Lh | Im Lh] .
+// [Im G ; Re G].  Every real row is scaled by a power of two s (|x| < s / 2) and written as
+// five signed 7-bit digits, x / s = d1 / 128 + ... + d5 / 128^5 + rest (|d| <= 64, |rest|
+// <= 128^-5 / 2): the rows of Lh by prepare, the Gh rows of a workgroup's columns here, in
+// registers.  The digit products d_i d'_j with i + j <= 6 run on the 16x16x64 int8 MFMA and
+// are summed exactly in int32 per level i + j (at most five pairs of at most 2 x 64 products
+// of |d d'| <= 4096 each: |sum| < 2^22); the levels are combined exactly in FP64 (Horner
+// in 128: |D| < 2^49) and scaled by the two powers of two and 128^-6.  What is lost per
+// real product is the truncation of both operands and the levels 7 .. 10, at most
+// 1.5 * 2^-35 s s'.  Work decomposition, pairing and FP64 sums as in exchange_kernel.
+typedef int v4i __attribute__((ext_vector_type(4)));
+constexpr int I8_ND = 5;  // digits per value
+
+__device__ __forceinline__ v4i mfma_i8(const v4i& a, const v4i& b, v4i c) {
+  return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
+}
+
+// Digits of x (|x| < 2^(e-1)): x 2^-e = sum_i d_i 128^-(i+1) + rest; each step is exact.
+__device__ __forceinline__ void i8_digits(double x, int e, int (&d)[I8_ND]) {
+  double r = ldexp(x, -e);
+#pragma unroll
+  for (int i = 0; i < I8_ND; ++i) {
+    r *= 128.0;
+    const double q = rint(r);
+    r -= q;
+    d[i] = (int)q;
+  }
+}
+
+// Exponent e of a row whose largest magnitude is amax: 2^(e-2) <= amax < 2^(e-1), or 0 for
+// a zero row.
+__device__ __forceinline__ int i8_exponent(double amax) {
+  return amax > 0.0 ? ilogb(amax) + 2 : 0;
+}
+
+template <int KB>
+__global__ __launch_bounds__(256) void exchange_int8x5_kernel(const Batch<ExchArgs> B) {
+  constexpr int KP8 = 64 * KB;           // kk padded to the MFMA K
+  constexpr int ROWB = I8_ND * KP8;      // digit bytes of one (g, a) row
+  constexpr int RSB = ROWB + 16;         // LDS row stride (bytes)
+  constexpr int UNITS = 2 * 16 * ROWB / 16;         // 16-byte units of one chunk, both slabs
+  constexpr int NU = (UNITS + 255) / 256;
+
+  __shared__ __attribute__((aligned(16))) signed char LA[2][2][16][RSB];  // [buf][slab][(g, a)][digit][kk]
+  __shared__ int LE[2][2][16];                                        // row exponents
+  __shared__ double XB[4][2][16][17];                                 // per-wave exchange tile
+  __shared__ double red[2][256];
+
+  long long bid;
+  const int pb = batch_find(B, blockIdx.x, bid);
+  const int nk = B.a[pb].nk, m = B.a[pb].m, nocc = B.a[pb].nocc, C = B.a[pb].C, W = B.a[pb].W;
+  const int nchunk_w = B.a[pb].nchunk_w;
+  const KMesh mesh = B.a[pb].mesh;
+  const signed char* __restrict__ L8 = (const signed char*)B.a[pb].Lh;
+  const int64_t nrows = (int64_t)nk * nk * C * nocc;
+  const int* __restrict__ L8e = (const int*)(L8 + nrows * ROWB);
+  const cpx<double>* __restrict__ Gh = B.a[pb].Gh;
+  cpx<double>* __restrict__ part = B.a[pb].part;
+  const int chunk = (int)(bid % nchunk_w);
+  const int t = (int)(bid / nchunk_w);
+  const int kp = t % nk, k = (t / nk) % nk, Q = t / (nk * nk);
+  const int mQ = mesh.neg(Q), kpq = mesh.kmq(kp, Q), kq = mesh.kmq(k, Q);
+  const int tp = (mQ * nk + kpq) * nk + kq;  // partner triple (-Q, k'-Q, k-Q)
+  if (t > tp) return;
+  const double mult = (t == tp) ? 1.0 : 2.0;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int Gs = 16 / nocc, Ws = 16 / nocc;
+  const int col = lane & 15;
+  const int ws_l = col / nocc, b_l = col % nocc;
+  const int wl = chunk * 4 * Ws + wave * Ws + ws_l;
+  const bool colok = (ws_l < Ws) && (wl < W);
+  const int64_t Nn = (int64_t)nk * m, nn = (int64_t)nk * nocc;
+
+  // B operands of both GEMMs for this lane's column: positions kk = 64 kb + 16 (lane / 16)
+  // + i; the value there is Re/-Im G (first real product) and Im/Re G (second)
+  v4i b1r[KB][I8_ND], b1i[KB][I8_ND], b2r[KB][I8_ND], b2i[KB][I8_ND];
+  int e1 = 0, e2 = 0;
+  bool bad = false;
+  {
+    double v1r[KB][16], v1i[KB][16], v2r[KB][16], v2i[KB][16];
+    double a1 = 0.0, a2 = 0.0;
+    int nf = 0;  // a non-finite entry (fmax would drop a NaN)
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int pos = 64 * kb + 16 * (lane >> 4) + i;
+        const bool re = pos < m;
+        const int r = re ? pos : pos - m;
+        double x1r = 0.0, x1i = 0.0, x2r = 0.0, x2i = 0.0;
+        if (colok && pos < 2 * m) {
+          const cpx<double> g1 = Gh[((int64_t)wl * nn + (int64_t)kpq * nocc + b_l) * Nn + (int64_t)kq * m + r];
+          const cpx<double> g2 = Gh[((int64_t)wl * nn + (int64_t)k * nocc + b_l) * Nn + (int64_t)kp * m + r];
+          x1r = re ? g1.re : -g1.im; x1i = re ? g1.im : g1.re;
+          x2r = re ? g2.re : -g2.im; x2i = re ? g2.im : g2.re;
+        }
+        v1r[kb][i] = x1r; v1i[kb][i] = x1i; v2r[kb][i] = x2r; v2i[kb][i] = x2i;
+        a1 = fmax(a1, fmax(fabs(x1r), fabs(x1i)));
+        a2 = fmax(a2, fmax(fabs(x2r), fabs(x2i)));
+        nf |= !(isfinite(x1r) && isfinite(x1i) && isfinite(x2r) && isfinite(x2i));
+      }
+    // row maxima over the four lane groups holding the same column
+    a1 = fmax(a1, __shfl_xor(a1, 16, 64));
+    a1 = fmax(a1, __shfl_xor(a1, 32, 64));
+    a2 = fmax(a2, __shfl_xor(a2, 16, 64));
+    a2 = fmax(a2, __shfl_xor(a2, 32, 64));
+    nf |= __shfl_xor(nf, 16, 64);
+    nf |= __shfl_xor(nf, 32, 64);
+    bad = nf || !isfinite(a1) || !isfinite(a2);
+    e1 = bad ? 0 : i8_exponent(a1);
+    e2 = bad ? 0 : i8_exponent(a2);
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int w1r[I8_ND] = {}, w1i[I8_ND] = {}, w2r[I8_ND] = {}, w2i[I8_ND] = {};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = 4 * q + u;
+          int d[I8_ND];
+          i8_digits(bad ? 0.0 : v1r[kb][i], e1, d);
+#pragma unroll
+          for (int j = 0; j < I8_ND; ++j) w1r[j] |= (d[j] & 0xff) << (8 * u);
+          i8_digits(bad ? 0.0 : v1i[kb][i], e1, d);
+#pragma unroll
+          for (int j = 0; j < I8_ND; ++j) w1i[j] |= (d[j] & 0xff) << (8 * u);
+          i8_digits(bad ? 0.0 : v2r[kb][i], e2, d);
+#pragma unroll
+          for (int j = 0; j < I8_ND; ++j) w2r[j] |= (d[j] & 0xff) << (8 * u);
+          i8_digits(bad ? 0.0 : v2i[kb][i], e2, d);
+#pragma unroll
+          for (int j = 0; j < I8_ND; ++j) w2i[j] |= (d[j] & 0xff) << (8 * u);
+        }
+#pragma unroll
+        for (int j = 0; j < I8_ND; ++j) {
+          b1r[kb][j][q] = w1r[j]; b1i[kb][j][q] = w1i[j];
+          b2r[kb][j][q] = w2r[j]; b2i[kb][j][q] = w2i[j];
+        }
+      }
+  }
+
+  // slab rows (g, a) of chunk c: rows [(slab C + c Gs) nocc, + Gs nocc) of the digit array
+  const int64_t srow0 = ((int64_t)Q * nk + k) * C * nocc;
+  const int64_t srow1 = ((int64_t)mQ * nk + kpq) * C * nocc;
+  const int nch = (C + Gs - 1) / Gs;
+  const int rows = Gs * nocc;
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  u4 pu[NU];
+  int pe = 0;
+  auto fetch = [&](int c) {
+#pragma unroll
+    for (int e = 0; e < NU; ++e) {
+      const int u = tid + 256 * e;
+      const int sl = u / (16 * ROWB / 16), rem = u % (16 * ROWB / 16);
+      const int row = rem / (ROWB / 16), off = (rem % (ROWB / 16)) * 16;
+      u4 v = {0u, 0u, 0u, 0u};
+      if (u < UNITS && row < rows && c * Gs + row / nocc < C)
+        v = *reinterpret_cast<const u4*>(L8 + ((sl ? srow1 : srow0) + (int64_t)c * rows + row) * ROWB + off);
+      pu[e] = v;
+    }
+    if (tid < 32) {
+      const int sl = tid >> 4, row = tid & 15;
+      pe = (row < rows && c * Gs + row / nocc < C) ? L8e[(sl ? srow1 : srow0) + (int64_t)c * rows + row] : 0;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < NU; ++e) {
+      const int u = tid + 256 * e;
+      const int sl = u / (16 * ROWB / 16), rem = u % (16 * ROWB / 16);
+      const int row = rem / (ROWB / 16), off = (rem % (ROWB / 16)) * 16;
+      if (u < UNITS) *reinterpret_cast<u4*>(&LA[buf][sl][row][off]) = pu[e];
+    }
+    if (tid < 32) LE[buf][tid >> 4][tid & 15] = pe;
+  };
+
+  // T1 of one slab on this wave's 16 x 16 tile: rows 4 (lane / 16) + v, column lane % 16
+  auto tile = [&](int buf, int sl, const v4i (&br)[KB][I8_ND], const v4i (&bi)[KB][I8_ND],
+                  int eb, double (&tr)[4], double (&ti)[4]) {
+    v4i cr[I8_ND], ci[I8_ND];
+#pragma unroll
+    for (int l = 0; l < I8_ND; ++l) { cr[l] = v4i{0, 0, 0, 0}; ci[l] = cr[l]; }
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int i = 0; i < I8_ND; ++i) {
+        const v4i a = *reinterpret_cast<const v4i*>(&LA[buf][sl][col][i * KP8 + 64 * kb + 16 * (lane >> 4)]);
+#pragma unroll
+        for (int j = 0; j + i < I8_ND; ++j) {
+          cr[i + j] = mfma_i8(a, br[kb][j], cr[i + j]);
+          ci[i + j] = mfma_i8(a, bi[kb][j], ci[i + j]);
+        }
+      }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double dr = (double)cr[0][v], di = (double)ci[0][v];
+#pragma unroll
+      for (int l = 1; l < I8_ND; ++l) {
+        dr = fma(dr, 128.0, (double)cr[l][v]);
+        di = fma(di, 128.0, (double)ci[l][v]);
+      }
+      const int ex = LE[buf][sl][4 * (lane >> 4) + v] + eb - 7 * (I8_ND + 1);
+      tr[v] = ldexp(dr, ex);
+      ti[v] = ldexp(di, ex);
+    }
+  };
+
+  double sr = 0.0, si = 0.0;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) fetch(c + 1);
+    double t2r[4], t2i[4], t1r[4], t1i[4];
+    tile(buf, 1, b2r, b2i, e2, t2r, t2i);
+    // T1 of the partner triple to the wave-private tile
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * (lane >> 4) + v;
+      XB[wave][0][row][col] = t2r[v];
+      XB[wave][1][row][col] = t2i[v];
+    }
+    tile(buf, 0, b1r, b1i, e1, t1r, t1i);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int g0 = c * Gs;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * (lane >> 4) + v;
+      const int g_s = row / nocc, a = row % nocc;
+      if (colok && g_s < Gs && g0 + g_s < C) {
+        const int rp = g_s * nocc + b_l, cp = ws_l * nocc + a;
+        const double pr2 = XB[wave][0][rp][cp], pi2 = XB[wave][1][rp][cp];
+        sr += t1r[v] * pr2 - t1i[v] * pi2;
+        si += t1r[v] * pi2 + t1i[v] * pr2;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (c + 1 < nch) stash(buf ^ 1);
+    __syncthreads();
+  }
+  // a column with a non-finite Green's function entry: a non-finite energy, as in FP64
+  if (bad) { sr = __builtin_nan(""); si = sr; }
+
+  // per-walker reduction: lanes of a wave with the same column walker
+  red[0][tid] = sr;
+  red[1][tid] = si;
+  __syncthreads();
+  if (tid < 4 * Ws) {
+    const int wv = tid / Ws, wsi = tid % Ws;
+    const int w = chunk * 4 * Ws + wv * Ws + wsi;
+    if (w < W) {
+      double ar = 0.0, ai = 0.0;
+      for (int grp = 0; grp < 4; ++grp)
+        for (int b = 0; b < nocc; ++b) {
+          const int l = wv * 64 + grp * 16 + wsi * nocc + b;
+          ar += red[0][l];
+          ai += red[1][l];
+        }
+      part[(int64_t)t * W + w] = cpx<double>{-mult * ar, -mult * ai};
+    }
+  }
+}
+
 static size_t carve_energy(Carve& c, const afqmc_kpt_problem& p, void** X, void** parts,
                            void** xpart) {
   Dims d = dims_of(p);
@@ -725,6 +997,7 @@ static hipError_t launch_exchange(const Job* jobs, int n, void* const* xpart, hi
       n,
       [&](int i) {
         const afqmc_kpt_problem& p = jobs[i].p;
+        if (jobs[i].int8x5) return 1024 + (p.m <= 32 ? 1 : 2);
         return p.prec * 64 + (p.prec == AFQMC_PREC_BF16X3
                                   ? (p.m <= 32 ? 1 : 2) + (p.nocc == 4 ? 4 : 0)
                                   : ks_class(p.m));
@@ -744,6 +1017,7 @@ static hipError_t launch_exchange(const Job* jobs, int n, void* const* xpart, hi
           }
           a.mesh = make_mesh(p);
           a.Lh = (p.prec == AFQMC_PREC_BF16X3) ? p.Lhs : (low_prec(p.prec) ? p.Lh32 : p.Lh);
+          if (jobs[ids[q]].int8x5) a.Lh = p.Lh8;
           a.Gh = (const cpx<double>*)p.Gh;
           a.part = (cpx<double>*)xpart[ids[q]];
           cnt[q] = (long long)p.nk * p.nk * p.nk * a.nchunk_w;
@@ -753,6 +1027,11 @@ static hipError_t launch_exchange(const Job* jobs, int n, void* const* xpart, hi
         if (g == 0) return hipSuccess;
         const bool f32 = low_prec(jobs[ids[0]].p.prec);
         const dim3 grid((unsigned)g), blk(256);
+        if (jobs[ids[0]].int8x5) {
+          if (jobs[ids[0]].p.m <= 32) hipLaunchKernelGGL((exchange_int8x5_kernel<1>), grid, blk, 0, s, B);
+          else hipLaunchKernelGGL((exchange_int8x5_kernel<2>), grid, blk, 0, s, B);
+          return hipGetLastError();
+        }
         if (jobs[ids[0]].p.prec == AFQMC_PREC_BF16X3) {
           const bool k1 = jobs[ids[0]].p.m <= 32;
           if (jobs[ids[0]].p.nocc == 4) {

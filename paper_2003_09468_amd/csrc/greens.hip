@@ -930,6 +930,8 @@ struct WeightArgs {
   const cpx<double>* logdet_new; // [W]
   double* weight;                // [W]
   int* status;                   // [W]
+  const double* etrial;          // [1] E_T per supercell, or null (no shift)
+  double dt;
 };
 
 __global__ __launch_bounds__(256) void weight_kernel(const Batch<WeightArgs> B) {
@@ -965,7 +967,9 @@ __global__ __launch_bounds__(256) void weight_kernel(const Batch<WeightArgs> B) 
   if (tid == 0) {
     const cpx<double> l0 = logdet[w], l1 = logdet_new[w];
     const double lrr = 2.0 * (l1.re - l0.re), lri = 2.0 * (l1.im - l0.im);
-    const double lIr = lrr + sr[0];
+    // the projector's energy shift exp(dt E_T) joins the modulus of I
+    const double* et = B.a[pb].etrial;
+    const double lIr = lrr + sr[0] + (et ? B.a[pb].dt * et[0] : 0.0);
     const double dth = atan2(sin(lri), cos(lri));
     const double c = cos(dth);
     int st = status[w];
@@ -1004,6 +1008,8 @@ hipError_t launch_weights(const Job* jobs, int n, hipStream_t s) {
       a.logdet_new = (const cpx<double>*)g.logdet_new;
       a.weight = p.weight;
       a.status = p.status;
+      a.etrial = p.etrial;
+      a.dt = p.dt;
       cnt[q] = p.nwalk;
     }
     const long long g = batch_close(B, cnt);

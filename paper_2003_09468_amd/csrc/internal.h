@@ -61,9 +61,11 @@ size_t ws_bytes_entry(const afqmc_kpt_problem& p, int entry);
 
 // The problem as a stage sees it: prec resolved to the energy precision for the local
 // energy and its adjoint, to the step precision otherwise.
+// The int8-split energy runs as FP64 except for its exchange kernel (Job::int8x5).
 inline afqmc_kpt_problem stage_view(const afqmc_kpt_problem& p, bool energy) {
   afqmc_kpt_problem q = p;
   q.prec = energy ? energy_prec(p.prec) : step_prec(p.prec);
+  if (q.prec == AFQMC_PREC_INT8X5) q.prec = AFQMC_PREC_FP64;
   return q;
 }
 inline bool energy_entry(int entry) {
@@ -74,6 +76,7 @@ inline bool energy_entry(int entry) {
 // buffers (unused ones are null).
 struct Job {
   afqmc_kpt_problem p;
+  bool int8x5;      // energy stage whose exchange runs on the int8 split (p.prec is FP64)
   void* ws;
   const double* x;  // fields of the current step [W][nk][C][2]
   void* xbar;       // [W][nk][C][2] complex128

@@ -11,8 +11,10 @@ namespace afqmc {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// Contraction precisions other than FP64 keep complex64 copies of L and Lh.
-__host__ __device__ __forceinline__ bool low_prec(int prec) { return prec != AFQMC_PREC_FP64; }
+// The FP32 and BF16X3 contractions keep complex64 copies of L and Lh.
+__host__ __device__ __forceinline__ bool low_prec(int prec) {
+  return prec == AFQMC_PREC_FP32 || prec == AFQMC_PREC_BF16X3;
+}
 
 // A placed precision (AFQMC_PREC_PLACE) resolves to the precision of the step contractions
 // (force bias, HS potential, Taylor products) and to that of the local energy and its

@@ -109,6 +109,44 @@ __global__ void lh_split_kernel(int nk, int m, int nocc, int C, int KP,
 // BF16 split planes of L for the three-pass HS potential, by chunks of 32 g:
 //   Ls[Q][g / 32][(k p r)][plane][g % 32], g zero-padded to CP = 32 ceil(C / 32), so that
 //   one chunk of consecutive columns is one contiguous block.
+// Int8 digits of Lh for the INT8X5 exchange: row (Q, k, g, a) over kk < KP8 of
+// [Re Lh[Q][k][a][:][g] | Im Lh[Q][k][a][:][g] | 0], scaled by 2^e (2^(e-2) <= max |x| <
+// 2^(e-1)) and cut into five signed 7-bit digits x 2^-e = sum_i d_i 128^-(i+1) + rest (each
+// step exact: multiply by 128, round to nearest, subtract).  One thread per row.
+__global__ void lh_int8_kernel(int nk, int m, int nocc, int C, int KP8,
+                               const cpx<double>* __restrict__ Lh, signed char* __restrict__ L8) {
+  constexpr int ND = 5;
+  const int64_t nrows = (int64_t)nk * nk * C * nocc;
+  int* __restrict__ ex = (int*)(L8 + nrows * ND * KP8);
+  for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < nrows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(row % nocc);
+    const int g = (int)((row / nocc) % C);
+    const int64_t qk = row / ((int64_t)nocc * C);
+    const cpx<double>* src = Lh + (qk * nocc + a) * m * C + g;  // element r at src[r * C]
+    double amax = 0.0;
+    for (int r = 0; r < m; ++r) {
+      const cpx<double> v = src[(int64_t)r * C];
+      amax = fmax(amax, fmax(fabs(v.re), fabs(v.im)));
+    }
+    const int e = amax > 0.0 ? ilogb(amax) + 2 : 0;
+    ex[row] = e;
+    signed char* o = L8 + row * ND * KP8;
+    for (int kk = 0; kk < KP8; ++kk) {
+      double x = 0.0;
+      if (kk < m) x = src[(int64_t)kk * C].re;
+      else if (kk < 2 * m) x = src[(int64_t)(kk - m) * C].im;
+      double r = ldexp(x, -e);
+      for (int i = 0; i < ND; ++i) {
+        r *= 128.0;
+        const double q = rint(r);
+        r -= q;
+        o[i * KP8 + kk] = (signed char)(int)q;
+      }
+    }
+  }
+}
+
 __global__ void l_split_kernel(int64_t ncols, int64_t ncq, int C, int CP,
                                const cpx<double>* __restrict__ L,
                                unsigned short* __restrict__ Ls) {
@@ -286,6 +324,13 @@ hipError_t run_prepare(const afqmc_kpt_problem& p, const void* H1, void* ws, hip
     const int KP = 32 * ((p.m + 31) / 32);
     hipLaunchKernelGGL(lh_split_kernel, dim3(4096), dim3(256), 0, s, p.nk, p.m, p.nocc,
                        p.nchol, KP, (const cpx<double>*)p.Lh, (unsigned short*)p.Lhs);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (ep == AFQMC_PREC_INT8X5) {
+    const int KP8 = 64 * ((2 * p.m + 63) / 64);
+    hipLaunchKernelGGL(lh_int8_kernel, dim3(2048), dim3(256), 0, s, p.nk, p.m, p.nocc, p.nchol,
+                       KP8, (const cpx<double>*)p.Lh, (signed char*)p.Lh8);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

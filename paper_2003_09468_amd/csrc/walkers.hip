@@ -3,6 +3,8 @@
 // interval holds it (stochastic reconfiguration; every new weight is the mean weight).
 #include <math.h>
 
+#include <vector>
+
 #include "internal.h"
 #include "kcommon.h"
 
@@ -193,6 +195,83 @@ hipError_t run_population(const afqmc_kpt_problem* p, int nprob, const double* x
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Energy shift between blocks: E_T <- (1 - blend) E_T + blend Re(Emix), per system, when the
+// system's mixed estimate is finite.  One thread per system.
+struct EtrialArgs {
+  double* et;               // [1]
+  const cpx<double>* emix;  // [1]
+  double blend;
+};
+
+__global__ __launch_bounds__(64) void etrial_kernel(const Batch<EtrialArgs> B) {
+  if (threadIdx.x != 0) return;
+  long long loc;
+  const int pb = batch_find(B, blockIdx.x, loc);
+  const EtrialArgs a = B.a[pb];
+  const cpx<double> e = a.emix[0];
+  if (__builtin_isfinite(e.re) && __builtin_isfinite(e.im))
+    a.et[0] = (1.0 - a.blend) * a.et[0] + a.blend * e.re;
+}
+
+hipError_t run_update_etrial(const afqmc_kpt_problem* p, int nprob, const void* Emix,
+                             double blend, hipStream_t s) {
+  for (int c0 = 0; c0 < nprob; c0 += AFQMC_MAXP) {
+    const int c = (nprob - c0 < AFQMC_MAXP) ? nprob - c0 : AFQMC_MAXP;
+    Batch<EtrialArgs> B;
+    B.nprob = c;
+    long long cnt[AFQMC_MAXP];
+    for (int q = 0; q < c; ++q) {
+      B.a[q].et = p[c0 + q].etrial;
+      B.a[q].emix = (const cpx<double>*)Emix + c0 + q;
+      B.a[q].blend = blend;
+      cnt[q] = 1;
+    }
+    const long long g = batch_close(B, cnt);
+    if (g <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(etrial_kernel, dim3((unsigned)g), dim3(64), 0, s, B);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Blocking analysis on the host (error bars of a serially correlated series): level 0 is
+// the series, level l + 1 the means of neighbouring pairs of level l; sample variance with
+// the n - 1 denominator; the first level with B^3 > 2 n (err_l / err_0)^4 is the one to
+// quote (Lee, Needs and Towler).
+int reblock_host(const double* x, int64_t n, afqmc_reblock_level* levels, int max_levels,
+                 int* optimal) {
+  std::vector<double> cur(x, x + n), nxt;
+  int nl = 0, opt = -1;
+  double err0 = 0.0;
+  while ((int64_t)cur.size() >= 2) {
+    const int64_t m = (int64_t)cur.size();
+    double sum = 0.0;
+    for (int64_t i = 0; i < m; ++i) sum += cur[i];
+    const double mean = sum / (double)m;
+    double ss = 0.0;
+    for (int64_t i = 0; i < m; ++i) ss += (cur[i] - mean) * (cur[i] - mean);
+    const double err = sqrt(ss / (double)(m - 1) / (double)m);
+    if (nl == 0) err0 = err;
+    if (nl < max_levels)
+      levels[nl] = afqmc_reblock_level{m, mean, err, err / sqrt(2.0 * (double)(m - 1))};
+    if (opt < 0) {
+      const double r = err0 > 0.0 ? err / err0 : 1.0;
+      const double B = ldexp(1.0, nl);
+      if (B * B * B > 2.0 * (double)n * r * r * r * r) opt = nl;
+    }
+    ++nl;
+    const int64_t h = m / 2;
+    nxt.resize(h);
+    for (int64_t i = 0; i < h; ++i) nxt[i] = 0.5 * (cur[2 * i] + cur[2 * i + 1]);
+    cur.swap(nxt);
+  }
+  *optimal = opt;
+  return nl;
 }
 
 }  // namespace afqmc

@@ -383,7 +383,7 @@ def test_placed_precision_encoding(L):
             p.prec = B.prec_place(sp, ep)
             assert B.step_prec(p.prec) == sp and B.energy_prec(p.prec) == ep
             assert L.afqmc_kpt_workspace_bytes(ctypes.byref(p), 1, 8, ctypes.byref(out)) == 0
-    for bad in (3, 15, B.prec_place(0, 3), 0x40, 0x100, -1):
+    for bad in (3, 15, B.prec_place(0, 4), B.prec_place(3, 0), 0x80, 0x100, -1):
         p = good_problem()
         p.prec = bad
         assert call(L, "afqmc_kpt_greens", p, ws, 1 << 40, None) == -1, bad
@@ -452,3 +452,98 @@ def test_placed_precision_checks_each_stage(L):
     assert call(L, "afqmc_kpt_prepare", p, H1, ws, 1 << 40, None) == -2
     p.Lhs = 0xd00000
     assert call(L, "afqmc_kpt_prepare", p, H1, ws, 1 << 40, None) == -5
+
+
+def test_reblock_matches_oracle(L):
+    """The library's host blocking analysis against the oracle's: same levels and the same
+    chosen level (sums in a different order: 1e-12 relative)."""
+    import numpy as np
+    from oracle import blocking as blk
+    import paper_2003_09468_amd as lib
+    rng = np.random.default_rng(2)
+    for n in (2, 3, 17, 1000, 4097):
+        e = rng.standard_normal(n)
+        x = np.empty(n)
+        x[0] = e[0]
+        for t in range(1, n):
+            x[t] = 0.7 * x[t - 1] + e[t]
+        x = 5.0 + 0.01 * x
+        got, opt = lib.reblock(x)
+        ref = blk.reblock(x)
+        assert len(got) == len(ref)
+        for (n1, m1, e1, ee1), (n2, m2, e2, ee2) in zip(got, ref):
+            assert n1 == n2
+            assert m1 == pytest.approx(m2, rel=1e-12)
+            assert e1 == pytest.approx(e2, rel=1e-9, abs=1e-300)
+            assert ee1 == pytest.approx(ee2, rel=1e-9, abs=1e-300)
+        assert opt == blk.optimal_level(ref)
+    got, opt = lib.reblock([4.0])
+    assert got == [] and opt == -1
+
+
+def test_reblock_and_etrial_validation(L):
+    import numpy as np
+    lv = (B.ReblockLevel * 4)()
+    nl, opt = ctypes.c_int(0), ctypes.c_int(0)
+    x = np.array([1.0, float("nan"), 2.0])
+    assert L.afqmc_kpt_reblock(x.ctypes.data, 3, lv, 4, ctypes.byref(nl), ctypes.byref(opt)) == -1
+    x = np.array([1.0, 2.0, 3.0, 4.0])
+    assert L.afqmc_kpt_reblock(None, 4, lv, 4, ctypes.byref(nl), ctypes.byref(opt)) == -2
+    assert L.afqmc_kpt_reblock(x.ctypes.data, 0, lv, 4, ctypes.byref(nl), ctypes.byref(opt)) == -1
+    assert L.afqmc_kpt_reblock(x.ctypes.data, 4, None, 4, ctypes.byref(nl), ctypes.byref(opt)) == -2
+    # a short output array: only the first levels are written, the count is complete
+    assert L.afqmc_kpt_reblock(x.ctypes.data, 4, lv, 1, ctypes.byref(nl), ctypes.byref(opt)) == 0
+    assert nl.value == 2 and lv[0].n == 4 and lv[1].n == 0
+    # the energy shift: needs etrial and Emix, blend in (0, 1]
+    p = good_problem()
+    Em = ctypes.c_void_p(0x2000)
+    assert call(L, "afqmc_kpt_update_etrial", p, Em, 1.0, None) == -2
+    p.etrial = 0x3008
+    assert call(L, "afqmc_kpt_update_etrial", p, None, 1.0, None) == -2
+    for bad in (0.0, 1.5, float("nan")):
+        assert call(L, "afqmc_kpt_update_etrial", p, Em, bad, None) == -1
+    p.etrial = 0x3004  # not 8-byte aligned
+    assert call(L, "afqmc_kpt_update_etrial", p, Em, 1.0, None) == -3
+    assert call(L, "afqmc_kpt_propagate", p, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000),
+                ctypes.c_void_p(0x4000), 0, ctypes.c_void_p(0x100000), 1 << 40, None) == -3
+
+
+def test_int8x5_energy_precision(L):
+    """INT8X5 is an energy precision only: PLACE(step, INT8X5) is valid, as a plain value or
+    a step precision it is not; the energy needs the digit array Lh8 (the adjoint, FP64,
+    does not); workspaces are those of FP64."""
+    ws = ctypes.c_void_p(0x1000000)
+    E = ctypes.c_void_p(0x2000)
+    out = ctypes.c_size_t()
+    for sp in range(3):
+        p = good_problem()
+        p.prec = B.prec_place(sp, B.PREC_INT8X5)
+        assert B.energy_prec(p.prec) == B.PREC_INT8X5
+        for e in range(10):
+            assert L.afqmc_kpt_workspace_bytes(ctypes.byref(p), 1, e, ctypes.byref(out)) == 0
+        q = good_problem()
+        q.prec = sp
+        for e in (B.ENTRIES["energy"], B.ENTRIES["energy_backward"]):
+            L.afqmc_kpt_workspace_bytes(ctypes.byref(q), 1, e, ctypes.byref(out))
+            want = out.value
+            L.afqmc_kpt_workspace_bytes(ctypes.byref(p), 1, e, ctypes.byref(out))
+            if sp == 0:
+                assert out.value == want
+        # Lh8 missing
+        assert call(L, "afqmc_kpt_energy", p, E, ws, 1 << 40, None) == -2
+        p.Lh8 = 0x5008  # misaligned
+        assert call(L, "afqmc_kpt_energy", p, E, ws, 1 << 40, None) == -3
+        p.Lh8 = 0x5000
+        p.Lhs = p.Ls = 0x6000
+        from tests.conftest import gpu_available
+        if not gpu_available():
+            assert call(L, "afqmc_kpt_energy", p, E, ws, 1 << 40, None) == -5
+        # the adjoint does not read Lh8
+        p.Lh8 = None
+        if not gpu_available():
+            assert call(L, "afqmc_kpt_energy_backward", p, None, ctypes.c_void_p(0x3000), ws,
+                        1 << 40, None) == -5
+    for bad in (B.PREC_INT8X5, B.prec_place(B.PREC_INT8X5, 0)):
+        p = good_problem()
+        p.prec = bad
+        assert call(L, "afqmc_kpt_energy", p, E, ws, 1 << 40, None) == -1

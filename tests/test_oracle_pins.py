@@ -514,3 +514,98 @@ def test_population_control_state():
     assert np.array_equal(U2, U[par]) and np.array_equal(G2, G[par])
     assert np.array_equal(ld2, ld[par]) and np.array_equal(st2, st[par])
     assert np.allclose(w2, w.sum() / W) and np.isclose(w2.sum(), w.sum())
+
+
+# ---------------------------------------------------------------------------
+# Blocking analysis of block energies (oracle/blocking.py)
+from oracle import blocking as blk  # noqa: E402
+
+
+def test_reblock_worked_example():
+    """x = 1, 2, 3, 4 by hand: level 0 mean 5/2, s^2 = 5/3, err = sqrt(5/12); level 1 the
+    pair means 3/2 and 7/2, s^2 = 2, err = 1; no level 2 (one block)."""
+    lv = blk.reblock([1.0, 2.0, 3.0, 4.0])
+    assert len(lv) == 2
+    n, mean, err, ee = lv[0]
+    assert n == 4 and mean == 2.5
+    assert err == pytest.approx(math.sqrt(5.0 / 12.0), rel=1e-15)
+    assert ee == pytest.approx(math.sqrt(5.0 / 12.0) / math.sqrt(6.0), rel=1e-15)
+    n, mean, err, ee = lv[1]
+    assert n == 2 and mean == 2.5 and err == pytest.approx(1.0, rel=1e-15)
+    # odd length: the last element is dropped when pairing
+    lv = blk.reblock([1.0, 2.0, 3.0, 4.0, 100.0])
+    assert lv[1][0] == 2 and lv[1][1] == 2.5
+
+
+def test_reblock_iid_standard_error():
+    """iid N(0, 1): every level estimates 1/sqrt(N), and the chosen level's error is within
+    its statistical uncertainty of it."""
+    rng = np.random.default_rng(7)
+    N = 1 << 16
+    lv = blk.reblock(rng.standard_normal(N))
+    opt = blk.optimal_level(lv)
+    assert opt >= 0
+    _, _, err, ee = lv[opt]
+    assert abs(err - 1.0 / math.sqrt(N)) < 4.0 * ee
+    # B^3 > 2N with err ratio about 1: B = 2^opt is the first power of two past (2N)^(1/3)
+    assert 2 ** (opt - 1) <= (2.0 * N) ** (1.0 / 3.0) * 1.5
+
+
+def test_reblock_ar1_standard_error():
+    """AR(1) x_t = phi x_{t-1} + e_t, e ~ N(0, 1): the variance of the mean of N terms is
+    (1 / (1 - phi^2)) (1 + phi) / (1 - phi) / N for large N (the integrated autocorrelation
+    time (1 + phi) / (1 - phi)); the chosen level recovers it, level 0 underestimates it by
+    the factor sqrt((1 - phi) / (1 + phi))."""
+    rng = np.random.default_rng(11)
+    N, phi = 1 << 17, 0.8
+    e = rng.standard_normal(N)
+    x = np.empty(N)
+    x[0] = e[0] / math.sqrt(1.0 - phi * phi)
+    for t in range(1, N):
+        x[t] = phi * x[t - 1] + e[t]
+    true = math.sqrt((1.0 / (1.0 - phi * phi)) * (1.0 + phi) / (1.0 - phi) / N)
+    lv = blk.reblock(x)
+    opt = blk.optimal_level(lv)
+    assert opt > 0
+    _, _, err, ee = lv[opt]
+    assert abs(err - true) < 4.0 * ee + 0.05 * true
+    assert lv[0][2] < 0.5 * true
+
+
+def test_reblock_shift_and_scale():
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(1000)
+    a, b = blk.reblock(x), blk.reblock(-3.0 * x + 17.0)
+    assert len(a) == len(b)
+    for (n1, m1, e1, _), (n2, m2, e2, _) in zip(a, b):
+        assert n1 == n2
+        assert m2 == pytest.approx(-3.0 * m1 + 17.0, abs=1e-12)
+        assert e2 == pytest.approx(3.0 * e1, rel=1e-10)
+    assert blk.optimal_level(a) == blk.optimal_level(b)
+    assert blk.optimal_level([]) == -1
+    assert blk.reblock([1.0]) == []
+
+
+# ---------------------------------------------------------------------------
+# Energy shift E_T of the projector exp(-dt (H - E_T))
+# ---------------------------------------------------------------------------
+
+def test_energy_shift_is_a_common_factor():
+    """The shift multiplies every walker's new weight by exp(dt E_T) and changes nothing
+    else: the walkers, the mixed estimate and the comb's parents are those without it."""
+    s, _, _ = tiny((2, 1, 1), m=5, nocc=2, nchol=7, trial="random")
+    rng = np.random.default_rng(5)
+    U = make_walkers(s, 6, rng, kind="dense")
+    x = make_fields(s, 6, 1, rng)[0]
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    _, ld = kp.greens(U, s.A)
+    w0 = rng.uniform(0.5, 2.0, 6)
+    a = kp.step(U, ld, w0, x, pre, s.A, s.L, s.mesh, s.dt)
+    ET = -3.7
+    b = kp.step(U, ld, w0, x, pre, s.A, s.L, s.mesh, s.dt, etrial=ET)
+    assert np.array_equal(a["U"], b["U"]) and np.array_equal(a["Gh"], b["Gh"])
+    np.testing.assert_allclose(b["weight"], a["weight"] * math.exp(s.dt * ET), rtol=1e-14)
+    E = kp.local_energy(pre["Lh"], pre["h1h"], a["Gh"], s.mesh)
+    assert abs(kp.mixed_energy(E, a["weight"]) - kp.mixed_energy(E, b["weight"])) < 1e-12
+    for xi in (0.1, 0.6):
+        assert np.array_equal(wk.comb_parents(a["weight"], xi), wk.comb_parents(b["weight"], xi))
