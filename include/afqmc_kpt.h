@@ -271,6 +271,23 @@ afqmc_status afqmc_kpt_orthonormalize(const afqmc_kpt_problem* p, int nprob,
 afqmc_status afqmc_kpt_energy(const afqmc_kpt_problem* p, int nprob, void* E,
                               void* ws, size_t ws_bytes, void* stream);
 
+/* The local energy of afqmc_kpt_energy (same kernels, same results bit for bit) for
+ * callers that cannot allocate device memory: code under HIP graph capture, serving loops
+ * and harnesses that forbid hipMalloc.  Instead of a caller workspace the scratch regions
+ * of the energy (Cholesky traces, split-K and exchange partials) live in a fixed device
+ * array of AFQMC_ENERGY_NOALLOC_MAX_BYTES, one per device, held from the first call on
+ * that device until the process ends; the call allocates nothing (no hipMalloc, no
+ * library allocation).  The caller still passes the problems and E.
+ *   Returns AFQMC_EWORKSPACE when the batch needs more scratch than that (the bytes
+ *   afqmc_kpt_workspace_bytes reports for AFQMC_ENTRY_ENERGY); the 3x3x3, m = 26,
+ *   nchol = 208, 64-walker energy needs about 50 MB.
+ *   Every call on a device shares that device's array, and nothing in it needs to start
+ *   at zero: calls that overlap on one device (two streams, two threads) race and give
+ *   wrong energies; order them on one stream. */
+#define AFQMC_ENERGY_NOALLOC_MAX_BYTES (64u << 20)
+afqmc_status afqmc_kpt_energy_noalloc(const afqmc_kpt_problem* p, int nprob, void* E,
+                                      void* stream);
+
 /* Adjoint of the local energy with respect to Gh (generalized Fock matrix):
  *   gGh[w][(k1 al), (k2 rho)] = gE[w] * dE_L[w] / dGh[w][(k1 al), (k2 rho)],
  *   E_L = E1B + EC + EX (holomorphic in Gh, so this is the plain complex

@@ -67,6 +67,7 @@ EXPORTS = [
     "afqmc_kpt_propagate",
     "afqmc_kpt_orthonormalize",
     "afqmc_kpt_energy",
+    "afqmc_kpt_energy_noalloc",
     "afqmc_kpt_energy_backward",
     "afqmc_kpt_mixed_energy",
     "afqmc_kpt_population_control",
@@ -154,6 +155,7 @@ def lib():
         "afqmc_kpt_propagate": [P, i, vp, vp, vp, i, vp, sz, vp],
         "afqmc_kpt_orthonormalize": [P, i, vp, sz, vp],
         "afqmc_kpt_energy": [P, i, vp, vp, sz, vp],
+        "afqmc_kpt_energy_noalloc": [P, i, vp, vp],
         "afqmc_kpt_energy_backward": [P, i, vp, vp, vp, sz, vp],
         "afqmc_kpt_mixed_energy": [P, i, vp, vp, vp],
         "afqmc_kpt_population_control": [P, i, vp, vp, vp, sz, vp],
@@ -380,6 +382,16 @@ class KptProblem:
         ws, nb = self._ws_args()
         check("afqmc_kpt_energy",
               lib().afqmc_kpt_energy(ctypes.byref(st), 1, out.data_ptr(), ws, nb, _stream()))
+        return out
+
+    def energy_noalloc(self, out=None, Gh=None):
+        """The local energy through the entry point that allocates nothing (fixed device
+        scratch instead of this problem's workspace)."""
+        if out is None:
+            out = torch.empty((self.nwalk, 3), dtype=torch.complex128, device=self.device)
+        st = self.struct if Gh is None else self._make_struct(Gh)
+        check("afqmc_kpt_energy_noalloc",
+              lib().afqmc_kpt_energy_noalloc(ctypes.byref(st), 1, out.data_ptr(), _stream()))
         return out
 
     def energy_backward(self, gE=None, out=None, Gh=None):

@@ -300,6 +300,35 @@ afqmc_status check_step_args(const afqmc_kpt_problem* p, int nprob, const double
 
 }  // namespace
 
+// Fixed scratch of the local energy for callers that cannot allocate: the Cholesky traces X,
+// the split-K partials of the traces and the exchange partials of afqmc_kpt_energy live in
+// this array instead of a caller workspace.  Each device holds its own copy (for the life
+// of the process); host code uses only the per-device address from hipGetSymbolAddress,
+// never the array's name.
+static __device__ __align__(256) unsigned char scratch[AFQMC_ENERGY_NOALLOC_MAX_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_dev[kMaxDevices];  // device address of scratch, per device; null until set up
+
+// The current device's copy of scratch, resolved once per device with that device current.
+afqmc_status scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return AFQMC_ENODEV;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return AFQMC_EHIP;
+    scratch_dev[dev] = ptr;
+  }
+  *out = scratch_dev[dev];
+  return AFQMC_OK;
+}
+
+}  // namespace
+
 // Captured step block.
 struct afqmc_kpt_graph_s {
   hipGraphExec_t exec;
@@ -418,6 +447,23 @@ afqmc_status afqmc_kpt_energy(const afqmc_kpt_problem* p, int nprob, void* E, vo
   AFQMC_TRY(check_ptr(E, 16));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_ENERGY, ws, ws_bytes));
   AFQMC_TRY(check_device());
+  Bufs b;
+  b.E = E;
+  std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_ENERGY, ws, b);
+  return hip_status(run_energy(jobs.data(), nprob, (hipStream_t)stream));
+}
+
+afqmc_status afqmc_kpt_energy_noalloc(const afqmc_kpt_problem* p, int nprob, void* E,
+                                      void* stream) {
+  AFQMC_TRY(check_problems(p, nprob, N_LH | N_LHS | N_H1H | N_GH, true));
+  AFQMC_TRY(check_int8x5(p, nprob));
+  AFQMC_TRY(check_ptr(E, 16));
+  size_t need = 0;
+  for (int i = 0; i < nprob; ++i) need += align_up(ws_bytes_entry(p[i], AFQMC_ENTRY_ENERGY));
+  if (need > (size_t)AFQMC_ENERGY_NOALLOC_MAX_BYTES) return AFQMC_EWORKSPACE;
+  AFQMC_TRY(check_device());
+  void* ws = nullptr;
+  AFQMC_TRY(scratch_address(&ws));
   Bufs b;
   b.E = E;
   std::vector<Job> jobs = make_jobs(p, nprob, AFQMC_ENTRY_ENERGY, ws, b);

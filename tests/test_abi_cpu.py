@@ -454,6 +454,36 @@ def test_placed_precision_checks_each_stage(L):
     assert call(L, "afqmc_kpt_prepare", p, H1, ws, 1 << 40, None) == -5
 
 
+def test_energy_noalloc_validation(L):
+    """The entry point without a workspace validates like afqmc_kpt_energy and rejects a
+    batch whose energy scratch exceeds its fixed array, all before any HIP call."""
+    from tests.conftest import gpu_available
+    cap = 64 << 20  # AFQMC_ENERGY_NOALLOC_MAX_BYTES
+    assert f"({cap >> 20}u << 20)" in open(HEADER).read()
+    E = ctypes.c_void_p(0x2000)
+    p = good_problem()
+    assert L.afqmc_kpt_energy_noalloc(ctypes.byref(p), 1, None, None) == -2
+    assert L.afqmc_kpt_energy_noalloc(ctypes.byref(p), 1, ctypes.c_void_p(0x2008), None) == -3
+    assert L.afqmc_kpt_energy_noalloc(None, 1, E, None) == -2
+    assert L.afqmc_kpt_energy_noalloc(ctypes.byref(p), 0, E, None) == -1
+    q = good_problem()
+    q.Gh = None
+    assert L.afqmc_kpt_energy_noalloc(ctypes.byref(q), 1, E, None) == -2
+    # the 3x3x3, m = 26, 64-walker energy fits; twice the walkers do not
+    out = ctypes.c_size_t()
+    L.afqmc_kpt_workspace_bytes(ctypes.byref(p), 1, 6, ctypes.byref(out))
+    assert out.value <= cap
+    big = good_problem()
+    big.nwalk = 128
+    L.afqmc_kpt_workspace_bytes(ctypes.byref(big), 1, 6, ctypes.byref(out))
+    assert out.value > cap
+    assert L.afqmc_kpt_energy_noalloc(ctypes.byref(big), 1, E, None) == -4
+    pair = (B.Problem * 2)(good_problem(), good_problem())
+    assert L.afqmc_kpt_energy_noalloc(pair, 2, E, None) == -4
+    if not gpu_available():
+        assert L.afqmc_kpt_energy_noalloc(ctypes.byref(p), 1, E, None) == -5
+
+
 def test_reblock_matches_oracle(L):
     """The library's host blocking analysis against the oracle's: same levels and the same
     chosen level (sums in a different order: 1e-12 relative)."""
@@ -531,6 +561,7 @@ def test_int8x5_energy_precision(L):
                 assert out.value == want
         # Lh8 missing
         assert call(L, "afqmc_kpt_energy", p, E, ws, 1 << 40, None) == -2
+        assert L.afqmc_kpt_energy_noalloc(ctypes.byref(p), 1, E, None) == -2
         p.Lh8 = 0x5008  # misaligned
         assert call(L, "afqmc_kpt_energy", p, E, ws, 1 << 40, None) == -3
         p.Lh8 = 0x5000
