@@ -259,9 +259,12 @@ def reduce_mfma(csv_path, out_md, title, command):
 
 
 def run_block(p, xs, bufs, E):
+    """One block: the steps (each Gh feeds only the next force bias, so reduced precisions
+    form it by the FP32 product; the last step's re-orthonormalisation forms it in FP64),
+    then the local energy."""
     nsteps = xs.shape[0]
     for s in range(nsteps):
-        p.step(xs[s], ortho=(s == nsteps - 1), bufs=bufs)
+        p.step(xs[s], ortho=(s == nsteps - 1), bufs=bufs, reduced_gh=True)
     return p.energy(out=E)
 
 
@@ -429,7 +432,7 @@ def step_from(p, st, x0):
     new U, Gh and weights (device copies)."""
     for k in ("U", "Gh", "logdet", "weight", "status"):
         getattr(p, k).copy_(st[k])
-    p.step(x0)
+    p.step(x0, reduced_gh=True)
     return {"U": p.U.clone(), "Gh": p.Gh.clone(), "weight": p.weight.clone()}
 
 

@@ -116,6 +116,13 @@ typedef enum {
 
 /* Flags of afqmc_kpt_propagate. */
 #define AFQMC_PROPAGATE_ORTHO 1  /* re-orthonormalise the walkers after the step */
+#define AFQMC_PROPAGATE_REDUCED_GH 4 /* in the FP32 and BF16X3 step precisions, form the new
+                                        Gh = (U O^-1)^T by an FP32 product (the overlap, its
+                                        inverse, the log determinant and the weights stay
+                                        FP64), for a Gh that only feeds the next force bias,
+                                        which reads it at that precision anyway; ignored in
+                                        FP64 and overridden by AFQMC_PROPAGATE_ORTHO, which
+                                        forms Gh in FP64 */
 
 /* Entry-point ids for afqmc_kpt_workspace_bytes. */
 typedef enum {
@@ -246,7 +253,9 @@ afqmc_status afqmc_kpt_vhs(const afqmc_kpt_problem* p, int nprob, const double* 
  *   dtheta = arg exp(2 (logdet' - logdet)),
  *   weight <- |I| max(0, cos dtheta) exp(dt E_T) weight   (E_T = *etrial, or 0 if NULL).
  * With AFQMC_PROPAGATE_ORTHO the walkers are re-orthonormalised afterwards
- * (see afqmc_kpt_orthonormalize).  vhs, x, xbar as in afqmc_kpt_vhs. */
+ * (see afqmc_kpt_orthonormalize).  vhs, x, xbar as in afqmc_kpt_vhs.  afqmc_kpt_step sets
+ * AFQMC_PROPAGATE_REDUCED_GH for every step whose Gh feeds only the next force bias (all
+ * but a last step without AFQMC_PROPAGATE_ORTHO). */
 afqmc_status afqmc_kpt_propagate(const afqmc_kpt_problem* p, int nprob, const void* vhs,
                                  const double* x, const void* xbar, int flags,
                                  void* ws, size_t ws_bytes, void* stream);

@@ -41,6 +41,7 @@ WALKER_NONFINITE = 2
 WALKER_KILLED = 4
 
 PROPAGATE_ORTHO = 1
+PROPAGATE_REDUCED_GH = 4
 STEP_ENERGY = 2
 
 ENTRIES = {
@@ -362,13 +363,15 @@ class KptProblem:
                                   out.data_ptr(), ws, nb, _stream()))
         return out
 
-    def propagate(self, vhs, x, xbar, ortho=False):
+    def propagate(self, vhs, x, xbar, ortho=False, reduced_gh=False):
         x = x.to(device=self.device, dtype=torch.float64).contiguous()
         ws, nb = self._ws_args()
         check("afqmc_kpt_propagate",
               lib().afqmc_kpt_propagate(ctypes.byref(self.struct), 1, vhs.data_ptr(),
                                         x.data_ptr(), xbar.data_ptr(),
-                                        PROPAGATE_ORTHO if ortho else 0, ws, nb, _stream()))
+                                        (PROPAGATE_ORTHO if ortho else 0) |
+                                        (PROPAGATE_REDUCED_GH if reduced_gh else 0),
+                                        ws, nb, _stream()))
 
     def orthonormalize(self):
         ws, nb = self._ws_args()
@@ -439,13 +442,15 @@ class KptProblem:
                                                  _stream()))
         return parent
 
-    def step(self, x, ortho=False, bufs=None):
-        """force bias -> HS potential -> propagate (new Gh, logdet, weights)."""
+    def step(self, x, ortho=False, bufs=None, reduced_gh=False):
+        """force bias -> HS potential -> propagate (new Gh, logdet, weights); reduced_gh:
+        the new Gh by the FP32 product in the FP32 and BF16X3 modes (for a Gh that only
+        feeds the next force bias; with ortho the re-orthonormalisation forms it in FP64)."""
         if bufs is None:
             bufs = {}
         xbar, _ = self.vbias(bufs.get("xbar"), bufs.get("X"))
         v = self.vhs(x, xbar, bufs.get("vhs"))
-        self.propagate(v, x, xbar, ortho=ortho)
+        self.propagate(v, x, xbar, ortho=ortho, reduced_gh=reduced_gh)
         return xbar, v
 
 

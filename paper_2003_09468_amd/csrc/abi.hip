@@ -259,8 +259,12 @@ hipError_t run_steps(std::vector<Job>& jobs, const int* orig_prec, const double*
       jobs[i].x = (const double*)((const char*)x0[i] + (size_t)st * stride);
     e = run_vbias(jobs.data(), n, s);
     if (e == hipSuccess) e = run_vhs(jobs.data(), n, s);
-    const int pf = (st == nsteps - 1) ? (flags & AFQMC_PROPAGATE_ORTHO) : 0;
-    if (e == hipSuccess) e = run_propagate(jobs.data(), n, pf, s);
+    // every Gh but that of a last step without re-orthonormalisation only feeds the next
+    // force bias
+    const bool last = st == nsteps - 1;
+    const int pf = last ? (flags & AFQMC_PROPAGATE_ORTHO) : 0;
+    const int rg = (!last || (flags & AFQMC_PROPAGATE_ORTHO)) ? AFQMC_PROPAGATE_REDUCED_GH : 0;
+    if (e == hipSuccess) e = run_propagate(jobs.data(), n, pf | rg, s);
   }
   for (int i = 0; i < n; ++i) jobs[i].x = x0[i];
   if (e == hipSuccess && (flags & AFQMC_STEP_ENERGY)) {
@@ -418,7 +422,7 @@ afqmc_status afqmc_kpt_propagate(const afqmc_kpt_problem* p, int nprob, const vo
   AFQMC_TRY(check_ptr(vhs, 16));
   AFQMC_TRY(check_ptr(x, 8));
   AFQMC_TRY(check_ptr(xbar, 16));
-  if (flags & ~AFQMC_PROPAGATE_ORTHO) return AFQMC_EINVAL;
+  if (flags & ~(AFQMC_PROPAGATE_ORTHO | AFQMC_PROPAGATE_REDUCED_GH)) return AFQMC_EINVAL;
   if (flags & AFQMC_PROPAGATE_ORTHO) AFQMC_TRY(check_ortho(p, nprob));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_PROPAGATE, ws, ws_bytes));
   AFQMC_TRY(check_device());

@@ -885,14 +885,16 @@ __global__ __launch_bounds__(256) void exchange_int8x5_kernel(const Batch<ExchAr
           ci[i + j] = mfma_i8(a, bi[kb][j], ci[i + j]);
         }
       }
+    // D = sum_l acc_l 128^(4-l): levels (0, 1) and (2, 3) pair up exactly in int32
+    // (levels 0 and 2 stay below 2^21, every level below 2^21.4: |acc 128 + acc'| < 2^29),
+    // the rest is exact in FP64 (|D| < 2^49)
+    static_assert(I8_ND == 5, "level grouping assumes five digits");
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      double dr = (double)cr[0][v], di = (double)ci[0][v];
-#pragma unroll
-      for (int l = 1; l < I8_ND; ++l) {
-        dr = fma(dr, 128.0, (double)cr[l][v]);
-        di = fma(di, 128.0, (double)ci[l][v]);
-      }
+      const int r01 = cr[0][v] * 128 + cr[1][v], r23 = cr[2][v] * 128 + cr[3][v];
+      const int i01 = ci[0][v] * 128 + ci[1][v], i23 = ci[2][v] * 128 + ci[3][v];
+      const double dr = fma(fma((double)r01, 16384.0, (double)r23), 128.0, (double)cr[4][v]);
+      const double di = fma(fma((double)i01, 16384.0, (double)i23), 128.0, (double)ci[4][v]);
       const int ex = LE[buf][sl][4 * (lane >> 4) + v] + eb - 7 * (I8_ND + 1);
       tr[v] = ldexp(dr, ex);
       ti[v] = ldexp(di, ex);

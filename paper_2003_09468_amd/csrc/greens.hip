@@ -842,25 +842,27 @@ hipError_t launch_ortho_factor(const Job* jobs, int n, void* const* S, void* con
       [&](const int* ids, int c) { return launch_chol_inv(jobs, ids, c, S, out, s); });
 }
 
-// Gh[w][i][R] = sum_j OinvT[w][i][j] U[w][R][j]
+// Gh[w][i][R] = sum_j OinvT[w][i][j] U[w][R][j]; FP64, or (T = float) with the operands
+// rounded to FP32 and FP32 accumulation
+template <typename TT>
 struct OpGreensSolve {
-  typedef double T;
+  typedef TT T;
   static constexpr bool A_KCONTIG = true;
   static constexpr bool B_NCONTIG = false;
   int M, N, K, nbatch;
   const cpx<double>* oinvT;
   const cpx<double>* U;
   cpx<double>* Gh;
-  __device__ void load_a(int b, int row, int k, double& re, double& im) const {
+  __device__ void load_a(int b, int row, int k, T& re, T& im) const {
     const cpx<double> v = oinvT[((int64_t)b * M + row) * K + k];
-    re = v.re; im = v.im;
+    re = (T)v.re; im = (T)v.im;
   }
-  __device__ void load_b(int b, int k, int col, double& re, double& im) const {
+  __device__ void load_b(int b, int k, int col, T& re, T& im) const {
     const cpx<double> v = U[((int64_t)b * N + col) * K + k];
-    re = v.re; im = v.im;
+    re = (T)v.re; im = (T)v.im;
   }
-  __device__ void store(int b, int row, int col, double re, double im) const {
-    Gh[((int64_t)b * M + row) * N + col] = cpx<double>{re, im};
+  __device__ void store(int b, int row, int col, T re, T im) const {
+    Gh[((int64_t)b * M + row) * N + col] = cpx<double>{(double)re, (double)im};
   }
 };
 
@@ -873,8 +875,10 @@ size_t carve_greens(Carve& c, const Dims& d, GreensWs& g) {
 
 // Greens for the current U of every job.  With write_logdet_new_only the log determinant
 // goes to the workspace slot (the weight update then moves it into p.logdet), else into
-// p.logdet.
-hipError_t run_greens(const Job* jobs, int n, bool write_logdet_new_only, hipStream_t s) {
+// p.logdet.  With reduced_gh, jobs whose contraction precision is FP32 or BF16X3 form Gh by
+// the FP32 product (the overlap, its inverse and log det stay FP64).
+hipError_t run_greens(const Job* jobs, int n, bool write_logdet_new_only, hipStream_t s,
+                      bool reduced_gh) {
   TimedScope ts(KC_GREENS, s);
   void* omat[AFQMC_MAXP];
   void* oinvT[AFQMC_MAXP];
@@ -883,7 +887,9 @@ hipError_t run_greens(const Job* jobs, int n, bool write_logdet_new_only, hipStr
     const int c = (n - c0 < AFQMC_MAXP) ? n - c0 : AFQMC_MAXP;
     const Job* J = jobs + c0;
     OpOverlap ov[AFQMC_MAXP];
-    OpGreensSolve sv[AFQMC_MAXP];
+    OpGreensSolve<double> sv[AFQMC_MAXP];
+    OpGreensSolve<float> sf[AFQMC_MAXP];
+    int nd = 0, nf = 0;
     for (int q = 0; q < c; ++q) {
       const afqmc_kpt_problem& p = J[q].p;
       Carve cv(J[q].ws);
@@ -899,20 +905,26 @@ hipError_t run_greens(const Job* jobs, int n, bool write_logdet_new_only, hipStr
       op.A = (const cpx<double>*)p.A;
       op.U = (const cpx<double>*)p.U;
       op.O = (cpx<double>*)g.omat;
-      OpGreensSolve& sl = sv[q];
-      sl.M = p.nk * p.nocc;
-      sl.N = p.nk * p.m;
-      sl.K = p.nk * p.nocc;
-      sl.nbatch = p.nwalk;
-      sl.oinvT = (const cpx<double>*)g.oinvT;
-      sl.U = (const cpx<double>*)p.U;
-      sl.Gh = (cpx<double>*)p.Gh;
+      const bool f32 = reduced_gh && low_prec(p.prec);
+      auto fill = [&](auto& sl) {
+        sl.M = p.nk * p.nocc;
+        sl.N = p.nk * p.m;
+        sl.K = p.nk * p.nocc;
+        sl.nbatch = p.nwalk;
+        sl.oinvT = (const cpx<double>*)g.oinvT;
+        sl.U = (const cpx<double>*)p.U;
+        sl.Gh = (cpx<double>*)p.Gh;
+      };
+      if (f32) fill(sf[nf++]);
+      else fill(sv[nd++]);
     }
     hipError_t e = launch_ops<16, 64, 16, 1, 4>(ov, c, s);
     if (e != hipSuccess) return e;
     e = launch_gj_blocked(J, c, omat, oinvT, ldo, s);
     if (e != hipSuccess) return e;
-    e = launch_ops<64, 64, 16, 2, 2>(sv, c, s);
+    if (nd) e = launch_ops<64, 64, 16, 2, 2>(sv, nd, s);
+    if (e != hipSuccess) return e;
+    if (nf) e = launch_ops<64, 64, 16, 2, 2>(sf, nf, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -950,12 +962,24 @@ __global__ __launch_bounds__(256) void weight_kernel(const Batch<WeightArgs> B) 
   double ar = 0.0, ai = 0.0;
   const double* xw = x + (int64_t)w * nf;
   const cpx<double>* bw = xbar + (int64_t)w * nf;
-  for (int64_t i = tid; i < nf; i += 256) {
-    const double xv = xw[i];
-    const cpx<double> b = bw[i];
-    // x b - b^2 / 2
-    ar += xv * b.re - 0.5 * (b.re * b.re - b.im * b.im);
-    ai += xv * b.im - b.re * b.im;
+  // eight elements per thread and pass, all loads issued before the sums (one workgroup per
+  // walker: the latency of the loads, not their bytes, bounds this loop)
+  constexpr int U = 8;
+  for (int64_t i0 = tid; i0 < nf; i0 += 256 * U) {
+    double xv[U];
+    cpx<double> b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + 256 * u;
+      xv[u] = i < nf ? xw[i] : 0.0;
+      b[u] = i < nf ? bw[i] : cpx<double>{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      // x b - b^2 / 2
+      ar += xv[u] * b[u].re - 0.5 * (b[u].re * b[u].re - b[u].im * b[u].im);
+      ai += xv[u] * b[u].im - b[u].re * b[u].im;
+    }
   }
   sr[tid] = ar;
   si[tid] = ai;

@@ -111,7 +111,8 @@ hipError_t for_groups(int n, KeyFn key, Fn fn) {
 
 // Launch sequences over a batch of jobs (arguments already validated).
 hipError_t run_prepare(const afqmc_kpt_problem& p, const void* H1, void* ws, hipStream_t s);
-hipError_t run_greens(const Job* jobs, int n, bool write_logdet_new_only, hipStream_t s);
+hipError_t run_greens(const Job* jobs, int n, bool write_logdet_new_only, hipStream_t s,
+                      bool reduced_gh = false);
 hipError_t run_vbias(const Job* jobs, int n, hipStream_t s);
 hipError_t run_vhs(const Job* jobs, int n, hipStream_t s);
 hipError_t run_propagate(const Job* jobs, int n, int flags, hipStream_t s);

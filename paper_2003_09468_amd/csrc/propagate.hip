@@ -727,7 +727,7 @@ hipError_t run_propagate(const Job* jobs, int n, int flags, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   // new overlap and Gh; weights from the old and new log overlaps
-  hipError_t e = run_greens(jobs, n, true, s);
+  hipError_t e = run_greens(jobs, n, true, s, (flags & AFQMC_PROPAGATE_REDUCED_GH) != 0);
   if (e != hipSuccess) return e;
   e = launch_weights(jobs, n, s);
   if (e != hipSuccess) return e;

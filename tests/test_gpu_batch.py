@@ -38,11 +38,12 @@ def state(p):
 
 
 def run_single(items):
-    """Each system alone: two steps (re-orthonormalise after the last) and the energy."""
+    """Each system alone: two steps (re-orthonormalise after the last) and the energy; as in
+    the block entry, the reduced precisions form each step's Gh by the FP32 product."""
     out = []
     for s, U, x, p, pre in items:
         for it in range(NSTEPS):
-            p.step(torch.from_numpy(x[it]), ortho=(it == NSTEPS - 1))
+            p.step(torch.from_numpy(x[it]), ortho=(it == NSTEPS - 1), reduced_gh=True)
         E = p.energy()
         torch.cuda.synchronize()
         out.append(state(p) + [host(E)])

@@ -84,3 +84,34 @@ def test_placed_step_block_energy(case):
     E = host(b.energy(0)).copy()
     pd.Gh.copy_(p.Gh)
     assert np.array_equal(E, host(pd.energy()))
+
+
+@pytest.mark.parametrize("case", ["wide", "m40"] if gpu_available() else [])
+def test_reduced_green_function_product(case):
+    """AFQMC_PROPAGATE_REDUCED_GH: in a reduced step precision the new Gh comes from the FP32
+    product; the walkers, log overlaps, weights and status are those of the FP64 product bit
+    for bit, Gh agrees to FP32 rounding; FP64 problems ignore the flag; afqmc_kpt_step uses it
+    for every step whose Gh only feeds the next force bias."""
+    for prec in (lib.PREC_BF16X3, lib.PREC_FP32, lib.PREC_FP64):
+        s, U, x, p, pre = build(case, prec=prec)
+        _, _, _, q, _ = build(case, prec=prec)
+        xt = torch.from_numpy(x[0])
+        p.step(xt, reduced_gh=True)
+        q.step(xt)
+        torch.cuda.synchronize()
+        for k in ("U", "logdet", "weight", "status"):
+            assert torch.equal(getattr(p, k), getattr(q, k)), (prec, k)
+        if prec == lib.PREC_FP64:
+            assert torch.equal(p.Gh, q.Gh)
+        else:
+            assert rel(host(p.Gh), host(q.Gh)) < 2e-6
+    # the block entry: reduced Gh for the first step, FP64 after the re-orthonormalisation
+    s, U, x, p, pre = build(case, prec=lib.PREC_BF16X3)
+    _, _, _, q, _ = build(case, prec=lib.PREC_BF16X3)
+    b = lib.KptBatch([p])
+    b.step(b.fields([torch.from_numpy(x)]), ortho=True, energy=False)
+    for it in range(x.shape[0]):
+        q.step(torch.from_numpy(x[it]), ortho=(it == x.shape[0] - 1), reduced_gh=True)
+    torch.cuda.synchronize()
+    for k in ("U", "Gh", "logdet", "weight", "status"):
+        assert torch.equal(getattr(p, k), getattr(q, k)), k
