@@ -31,7 +31,7 @@ import time
 
 METRIC = "walker-steps/s at Nk=27 M=26, mixed vs FP64 GPU, |ΔE_loc|≤1e-5 Ha/cell"
 # dense MFMA TFLOP/s, MI355X; BF16-split counts its three BF16 passes per product
-PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3, "int8": 5000.0}
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3, "int8x5": 5000.0, "int8x4": 5000.0}
 TOL = 1e-5  # Ha per cell
 # path -> (precision of the step contractions, precision of the local energy)
 PATHS = {
@@ -41,6 +41,7 @@ PATHS = {
     "bf16x3+fp64E": ("bf16x3", "fp64"),
     "bf16x3+fp32E": ("bf16x3", "fp32"),
     "bf16x3+int8x5E": ("bf16x3", "int8x5"),
+    "bf16x3+int8x4E": ("bf16x3", "int8x4"),
 }
 ENERGY_CLASSES = ("exchange", "energy_rest", "exchange_bwd")
 
@@ -361,8 +362,8 @@ def kernel_prec(path, kernel):
     if pk == "bf16x3" and kernel not in ("vhs", "taylor", "exchange", "vbias"):
         pk = "fp32"
     # the int8 split replaces only the exchange contraction; the rest of that energy is FP64
-    if pk == "int8x5":
-        pk = "int8" if kernel == "exchange" else "fp64"
+    if pk in ("int8x5", "int8x4"):
+        pk = pk if kernel == "exchange" else "fp64"
     return pk
 
 
@@ -389,10 +390,11 @@ def exchange_roofline(path_res, path, cfg):
     (three BF16 passes, the contraction index r padded to a multiple of 32) against the
     dense BF16 peak."""
     r = roofline(path_res, path, cfg, "exchange")
-    if r is not None and r["precision"] == "int8":
-        # per complex T1 entry: two real products, 15 digit pairs, K = 2m padded to 64
+    if r is not None and r["precision"] in ("int8x5", "int8x4"):
+        # per complex T1 entry: two real products, 15 (10) digit pairs, K = 2m padded to 64
         kp8 = 64 * ((2 * cfg["m"] + 63) // 64)
-        ex = r["flops_per_launch"] / (8.0 * cfg["m"]) * 2 * 15 * kp8 * 2
+        pairs = 15 if r["precision"] == "int8x5" else 10
+        ex = r["flops_per_launch"] / (8.0 * cfg["m"]) * 2 * pairs * kp8 * 2
         ms = path_res["kernels"]["exchange"]["ms_per_launch"]
         r["executed_int8_ops_per_launch"] = ex
         r["executed_int8_tops"] = round(ex / (ms * 1e-3) / 1e12, 1)
@@ -424,7 +426,7 @@ def energy_evals(v, cfg):
 
 DTYPE = {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f32+f64",
          "bf16x3+fp64E": "bf16x3+f64", "bf16x3+fp32E": "bf16x3+f32+f64",
-         "bf16x3+int8x5E": "bf16x3+int8x5+f64"}
+         "bf16x3+int8x5E": "bf16x3+int8x5+f64", "bf16x3+int8x4E": "bf16x3+int8x4+f64"}
 
 
 def step_from(p, st, x0):
@@ -939,7 +941,7 @@ def main():
         paths.remove("fp64")
         paths.insert(0, "fp64")
     code = {"fp64": lib.PREC_FP64, "fp32": lib.PREC_FP32, "bf16x3": lib.PREC_BF16X3,
-            "int8x5": lib.PREC_INT8X5}
+            "int8x5": lib.PREC_INT8X5, "int8x4": lib.PREC_INT8X4}
     p64, initial, state64 = None, {}, {}
     for name in paths:
         sp, ep = PATHS[name]

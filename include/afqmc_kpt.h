@@ -80,7 +80,8 @@ typedef enum {
   AFQMC_PREC_FP64 = 0,
   AFQMC_PREC_FP32 = 1,
   AFQMC_PREC_BF16X3 = 2,
-  AFQMC_PREC_INT8X5 = 3   /* local energy only, see AFQMC_PREC_PLACE */
+  AFQMC_PREC_INT8X5 = 3,  /* local energy only, see AFQMC_PREC_PLACE */
+  AFQMC_PREC_INT8X4 = 4   /* local energy only, see AFQMC_PREC_PLACE */
 } afqmc_prec;
 
 /* AFQMC_PREC_INT8X5, an energy precision: the exchange contraction of afqmc_kpt_energy on
@@ -93,7 +94,9 @@ typedef enum {
  * contraction is then exact up to 1.5 * 2^-35 s s' (truncated digits and dropped levels),
  * 2^-35 = 2.9e-11.  The one-body and Coulomb parts, the pairing and all sums are FP64; the
  * adjoint (afqmc_kpt_energy_backward) runs in FP64.  Needs Lh8 (written by prepare) and
- * m <= 64. */
+ * m <= 64.
+ * AFQMC_PREC_INT8X4: the same with four digits per operand (levels i + j <= 5, two thirds
+ * of the int8 MFMA work), each product exact up to 1.25 * 2^-28 s s' (2^-28 = 3.7e-9). */
 
 /* Precision placement ("GPU Implementation": the paper runs the whole method in single
  * precision; here each group of contractions has its own).  The prec field of a problem is
@@ -176,10 +179,14 @@ typedef struct afqmc_kpt_problem {
   void* Lhs;         /* [nk][nk][nchol][nocc][4][32*ceil(m/32)] bfloat16 (uint16) split planes
                         of Lh (re hi, re lo, im hi, im lo; r padded with zeros), written by
                         prepare; needed when the step or the energy precision is BF16X3 */
-  void* Ls;          /* [nk(Q)][ceil(nchol/32)][nk*m*m (k p r)][4][32] bfloat16 (uint16)
-                        split planes of L (re hi, re lo, im hi, im lo) in chunks of 32
-                        Cholesky indices, g padded with zeros, written by prepare; step
-                        prec BF16X3 only (else NULL) */
+  void* Ls;          /* half store of L ("k-Point Representation": L^{-Q,k-Q} is the
+                        conjugate transpose of L^{Q,k}): for the nq momentum transfers Q whose
+                        index does not exceed that of -Q, in increasing Q,
+                        [nq][ceil(nchol/32)][nk*m*m (k p r)][4][32] bfloat16 (uint16) split
+                        planes of L[Q] (re hi, re lo, im hi, im lo) in chunks of 32 Cholesky
+                        indices, g padded with zeros, followed by int32 Q[nq]; written by
+                        prepare; step prec BF16X3 only (else NULL).  nq = (nk + s) / 2,
+                        s = prod_d (2 if mesh[d] is even else 1) the number of Q = -Q */
   /* walker state */
   void* U;           /* [nwalk][nk*m][nk*nocc] complex128 walker orbitals, in/out */
   void* Gh;          /* [nwalk][nk*nocc][nk*m] complex128 half-rotated Green's function */
@@ -191,7 +198,8 @@ typedef struct afqmc_kpt_problem {
                         every step multiplies each weight by exp(dt E_T), a common factor
                         that keeps the weights of long runs finite; read by the weight
                         update, written by afqmc_kpt_update_etrial */
-  /* energy precision AFQMC_PREC_INT8X5 only (else NULL), written by prepare */
+  /* energy precision AFQMC_PREC_INT8X5 or AFQMC_PREC_INT8X4 only (else NULL), written by
+     prepare (five digits in both) */
   void* Lh8;         /* int8 digits of Lh: [nk][nk][nchol][nocc] rows of 5 x KP8 digits
                         (digit d1 .. d5, each over kk = 0 .. KP8-1: Re Lh[Q][k][a][kk][g]
                         for kk < m, Im Lh[..][kk - m][g] for m <= kk < 2m, 0 beyond;

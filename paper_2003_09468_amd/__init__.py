@@ -18,6 +18,7 @@ from .binding import (  # noqa: F401
     PREC_FP32,
     PREC_BF16X3,
     PREC_INT8X5,
+    PREC_INT8X4,
     prec_place,
     step_prec,
     energy_prec,

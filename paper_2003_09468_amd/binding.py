@@ -20,12 +20,22 @@ PREC_FP64 = 0
 PREC_FP32 = 1
 PREC_BF16X3 = 2
 PREC_INT8X5 = 3  # energy precision only (prec_place(step, PREC_INT8X5))
+PREC_INT8X4 = 4  # energy precision only
 
 
 def prec_place(step: int, energy: int) -> int:
     """AFQMC_PREC_PLACE: the step contractions in one precision, the local energy and its
     adjoint in another."""
     return int(step) | ((int(energy) + 1) << 4)
+
+
+def ls_slots(mesh) -> int:
+    """Slots of the half store of L: (nk + number of Q with -Q = Q) / 2."""
+    nk, self_inv = 1, 1
+    for d in mesh:
+        nk *= int(d)
+        self_inv *= 2 if int(d) % 2 == 0 else 1
+    return (nk + self_inv) // 2
 
 
 def step_prec(prec: int) -> int:
@@ -265,7 +275,7 @@ class KptProblem:
         self.Lh32 = (torch.empty(self.Lh.shape, dtype=torch.complex64, **kw)
                      if sp in low or ep in low else None)
         self.Lhs = self.Ls = self.Lh8 = None
-        if ep == PREC_INT8X5:
+        if ep in (PREC_INT8X5, PREC_INT8X4):
             # five int8 digits per element of [Re | Im] rows padded to 64, then int32 exponents
             kp8 = 64 * ((2 * m + 63) // 64)
             rows = nk * nk * nchol * nocc
@@ -275,7 +285,10 @@ class KptProblem:
             self.Lhs = torch.empty((nk, nk, nchol, nocc, 4, kp), dtype=torch.int16, **kw)
         if sp == PREC_BF16X3:
             cp = 32 * ((nchol + 31) // 32)
-            self.Ls = torch.empty((nk, cp // 32, nk * m * m, 4, 32), dtype=torch.int16, **kw)
+            # half store: one slot per time-reversal pair (Q <= -Q), then int32 Q per slot
+            nq = ls_slots(self.mesh)
+            self.Ls = torch.empty(nq * (cp // 32) * nk * m * m * 4 * 32 + 2 * nq,
+                                  dtype=torch.int16, **kw)
         N, n = nk * m, nk * nocc
         self.U = torch.zeros((nwalk, N, n), dtype=c128, **kw)
         self.Gh = torch.zeros((nwalk, n, N), dtype=c128, **kw)

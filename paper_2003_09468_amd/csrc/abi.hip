@@ -116,7 +116,7 @@ afqmc_status check_dims(const afqmc_kpt_problem& p) {
   if (p.m < 1 || p.nocc < 1 || p.nocc > p.m || p.nchol < 1 || p.nwalk < 1) return AFQMC_EINVAL;
   // an afqmc_prec value, or AFQMC_PREC_PLACE(step, energy)
   if ((p.prec & ~0x7f) != 0 || (p.prec & 15) > AFQMC_PREC_BF16X3 ||
-      (p.prec >> 4) > AFQMC_PREC_INT8X5 + 1)
+      (p.prec >> 4) > AFQMC_PREC_INT8X4 + 1)
     return AFQMC_EINVAL;
   if (!(p.dt > 0.0) || !isfinite(p.dt)) return AFQMC_EINVAL;
   // sizes the kernels implement
@@ -162,10 +162,10 @@ afqmc_status check_problems(const afqmc_kpt_problem* p, int nprob, unsigned need
   return AFQMC_OK;
 }
 
-// The int8-split energy reads the digits of Lh.
-afqmc_status check_int8x5(const afqmc_kpt_problem* p, int nprob) {
+// The int8-split energies read the digits of Lh.
+afqmc_status check_int8(const afqmc_kpt_problem* p, int nprob) {
   for (int i = 0; i < nprob; ++i)
-    if (energy_prec(p[i].prec) == AFQMC_PREC_INT8X5) AFQMC_TRY(check_ptr(p[i].Lh8, 16));
+    if (int8_digits(energy_prec(p[i].prec))) AFQMC_TRY(check_ptr(p[i].Lh8, 16));
   return AFQMC_OK;
 }
 
@@ -233,7 +233,7 @@ std::vector<Job> make_jobs(const afqmc_kpt_problem* p, int nprob, int entry, voi
   for (int i = 0; i < nprob; ++i) {
     Job& j = jobs[i];
     j.p = stage_view(p[i], energy_entry(entry));
-    j.int8x5 = entry == AFQMC_ENTRY_ENERGY && energy_prec(p[i].prec) == AFQMC_PREC_INT8X5;
+    j.int8 = entry == AFQMC_ENTRY_ENERGY ? int8_digits(energy_prec(p[i].prec)) : 0;
     j.ws = ws ? (char*)ws + wo : nullptr;
     wo += align_up(ws_bytes_entry(p[i], entry));
     j.x = slice(b.x, p, nprob, AFQMC_BUF_FIELDS, i, off);
@@ -272,8 +272,8 @@ hipError_t run_steps(std::vector<Job>& jobs, const int* orig_prec, const double*
     std::vector<Job> ej(jobs);
     for (int i = 0; i < n; ++i) {
       const int ep = energy_prec(orig_prec[i]);
-      ej[i].int8x5 = ep == AFQMC_PREC_INT8X5;
-      ej[i].p.prec = ej[i].int8x5 ? AFQMC_PREC_FP64 : ep;
+      ej[i].int8 = int8_digits(ep);
+      ej[i].p.prec = ej[i].int8 ? AFQMC_PREC_FP64 : ep;
     }
     e = run_energy(ej.data(), n, s);
   }
@@ -289,7 +289,7 @@ afqmc_status check_step_args(const afqmc_kpt_problem* p, int nprob, const double
   AFQMC_TRY(check_problems(p, nprob, need));
   if (flags & AFQMC_STEP_ENERGY) {
     AFQMC_TRY(check_problems(p, nprob, N_LH | N_LHS | N_H1H | N_GH, true));
-    AFQMC_TRY(check_int8x5(p, nprob));
+    AFQMC_TRY(check_int8(p, nprob));
   }
   if (nsteps < 1) return AFQMC_EINVAL;
   if (flags & ~(AFQMC_PROPAGATE_ORTHO | AFQMC_STEP_ENERGY)) return AFQMC_EINVAL;
@@ -365,7 +365,7 @@ afqmc_status afqmc_kpt_prepare(const afqmc_kpt_problem* p, int nprob, const void
     AFQMC_TRY(check_fields(stage_view(p[i], false), N_L | N_LH | N_LHS | N_LS));
     AFQMC_TRY(check_fields(stage_view(p[i], true), N_LH | N_LHS));
   }
-  AFQMC_TRY(check_int8x5(p, nprob));
+  AFQMC_TRY(check_int8(p, nprob));
   AFQMC_TRY(check_ptr(H1, 16));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_PREPARE, ws, ws_bytes));
   AFQMC_TRY(check_device());
@@ -447,7 +447,7 @@ afqmc_status afqmc_kpt_orthonormalize(const afqmc_kpt_problem* p, int nprob, voi
 afqmc_status afqmc_kpt_energy(const afqmc_kpt_problem* p, int nprob, void* E, void* ws,
                               size_t ws_bytes, void* stream) {
   AFQMC_TRY(check_problems(p, nprob, N_LH | N_LHS | N_H1H | N_GH, true));
-  AFQMC_TRY(check_int8x5(p, nprob));
+  AFQMC_TRY(check_int8(p, nprob));
   AFQMC_TRY(check_ptr(E, 16));
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_ENERGY, ws, ws_bytes));
   AFQMC_TRY(check_device());
@@ -460,7 +460,7 @@ afqmc_status afqmc_kpt_energy(const afqmc_kpt_problem* p, int nprob, void* E, vo
 afqmc_status afqmc_kpt_energy_noalloc(const afqmc_kpt_problem* p, int nprob, void* E,
                                       void* stream) {
   AFQMC_TRY(check_problems(p, nprob, N_LH | N_LHS | N_H1H | N_GH, true));
-  AFQMC_TRY(check_int8x5(p, nprob));
+  AFQMC_TRY(check_int8(p, nprob));
   AFQMC_TRY(check_ptr(E, 16));
   size_t need = 0;
   for (int i = 0; i < nprob; ++i) need += align_up(ws_bytes_entry(p[i], AFQMC_ENTRY_ENERGY));

@@ -688,31 +688,35 @@ __global__ __launch_bounds__(256) void energy_final_kernel(const Batch<EfinArgs>
 }
 
 // ---------------------------------------------------------------------------
-// The exchange on int8 MFMA with exact integer accumulation (energy precision INT8X5).
+// The exchange on int8 MFMA with exact integer accumulation (energy precisions INT8X5 and
+// INT8X4: five or four digits per operand).
 //
 // The complex contraction T1 = sum_r Lh[a][r][g] G[b][r] is taken as two real products
 // over kk < 2m: Re T1 = [Re Lh | Im Lh] . [Re G ; -Im G], Im T1 = [Re Lh | Im Lh] .
 // [Im G ; Re G].  Every real row is scaled by a power of two s (|x| < s / 2) and written as
 // five signed 7-bit digits, x / s = d1 / 128 + ... + d5 / 128^5 + rest (|d| <= 64, |rest|
 // <= 128^-5 / 2): the rows of Lh by prepare, the Gh rows of a workgroup's columns here, in
-// registers.  The digit products d_i d'_j with i + j <= 6 run on the 16x16x64 int8 MFMA and
+// registers (INT8X4 keeps four).  The digit products d_i d'_j with i + j <= 6 (5) run on
+// the 16x16x64 int8 MFMA and
 // are summed exactly in int32 per level i + j (at most five pairs of at most 2 x 64 products
 // of |d d'| <= 4096 each: |sum| < 2^22); the levels are combined exactly in FP64 (Horner
 // in 128: |D| < 2^49) and scaled by the two powers of two and 128^-6.  What is lost per
 // real product is the truncation of both operands and the levels 7 .. 10, at most
-// 1.5 * 2^-35 s s'.  Work decomposition, pairing and FP64 sums as in exchange_kernel.
+// 1.5 * 2^-35 s s' (INT8X4: levels 6 .. 8, 1.25 * 2^-28 s s').  Work decomposition,
+// pairing and FP64 sums as in exchange_kernel.
 typedef int v4i __attribute__((ext_vector_type(4)));
-constexpr int I8_ND = 5;  // digits per value
+constexpr int I8_STORE = 5;  // digits per value of the Lh digit rows written by prepare
 
 __device__ __forceinline__ v4i mfma_i8(const v4i& a, const v4i& b, v4i c) {
   return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
 }
 
 // Digits of x (|x| < 2^(e-1)): x 2^-e = sum_i d_i 128^-(i+1) + rest; each step is exact.
-__device__ __forceinline__ void i8_digits(double x, int e, int (&d)[I8_ND]) {
+template <int ND>
+__device__ __forceinline__ void i8_digits(double x, int e, int (&d)[ND]) {
   double r = ldexp(x, -e);
 #pragma unroll
-  for (int i = 0; i < I8_ND; ++i) {
+  for (int i = 0; i < ND; ++i) {
     r *= 128.0;
     const double q = rint(r);
     r -= q;
@@ -726,10 +730,14 @@ __device__ __forceinline__ int i8_exponent(double amax) {
   return amax > 0.0 ? ilogb(amax) + 2 : 0;
 }
 
-template <int KB>
-__global__ __launch_bounds__(256) void exchange_int8x5_kernel(const Batch<ExchArgs> B) {
+// ND digits per operand (5: INT8X5, 4: INT8X4, which reads the first four of the five
+// stored Lh digits); the digit products of levels i + j <= ND + 1 are formed.
+template <int KB, int ND>
+__global__ __launch_bounds__(256) void exchange_int8_kernel(const Batch<ExchArgs> B) {
+  constexpr int I8_ND = ND;
   constexpr int KP8 = 64 * KB;           // kk padded to the MFMA K
-  constexpr int ROWB = I8_ND * KP8;      // digit bytes of one (g, a) row
+  constexpr int ROWG = I8_STORE * KP8;   // bytes of one stored (g, a) row
+  constexpr int ROWB = I8_ND * KP8;      // digit bytes of one row that the kernel reads
   constexpr int RSB = ROWB + 16;         // LDS row stride (bytes)
   constexpr int UNITS = 2 * 16 * ROWB / 16;         // 16-byte units of one chunk, both slabs
   constexpr int NU = (UNITS + 255) / 256;
@@ -746,7 +754,7 @@ __global__ __launch_bounds__(256) void exchange_int8x5_kernel(const Batch<ExchAr
   const KMesh mesh = B.a[pb].mesh;
   const signed char* __restrict__ L8 = (const signed char*)B.a[pb].Lh;
   const int64_t nrows = (int64_t)nk * nk * C * nocc;
-  const int* __restrict__ L8e = (const int*)(L8 + nrows * ROWB);
+  const int* __restrict__ L8e = (const int*)(L8 + nrows * ROWG);
   const cpx<double>* __restrict__ Gh = B.a[pb].Gh;
   cpx<double>* __restrict__ part = B.a[pb].part;
   const int chunk = (int)(bid % nchunk_w);
@@ -812,6 +820,7 @@ __global__ __launch_bounds__(256) void exchange_int8x5_kernel(const Batch<ExchAr
         for (int u = 0; u < 4; ++u) {
           const int i = 4 * q + u;
           int d[I8_ND];
+          static_assert(sizeof(d) == I8_ND * sizeof(int), "");
           i8_digits(bad ? 0.0 : v1r[kb][i], e1, d);
 #pragma unroll
           for (int j = 0; j < I8_ND; ++j) w1r[j] |= (d[j] & 0xff) << (8 * u);
@@ -849,7 +858,7 @@ __global__ __launch_bounds__(256) void exchange_int8x5_kernel(const Batch<ExchAr
       const int row = rem / (ROWB / 16), off = (rem % (ROWB / 16)) * 16;
       u4 v = {0u, 0u, 0u, 0u};
       if (u < UNITS && row < rows && c * Gs + row / nocc < C)
-        v = *reinterpret_cast<const u4*>(L8 + ((sl ? srow1 : srow0) + (int64_t)c * rows + row) * ROWB + off);
+        v = *reinterpret_cast<const u4*>(L8 + ((sl ? srow1 : srow0) + (int64_t)c * rows + row) * ROWG + off);
       pu[e] = v;
     }
     if (tid < 32) {
@@ -885,16 +894,20 @@ __global__ __launch_bounds__(256) void exchange_int8x5_kernel(const Batch<ExchAr
           ci[i + j] = mfma_i8(a, bi[kb][j], ci[i + j]);
         }
       }
-    // D = sum_l acc_l 128^(4-l): levels (0, 1) and (2, 3) pair up exactly in int32
+    // D = sum_l acc_l 128^(ND-1-l): levels (0, 1) and (2, 3) pair up exactly in int32
     // (levels 0 and 2 stay below 2^21, every level below 2^21.4: |acc 128 + acc'| < 2^29),
     // the rest is exact in FP64 (|D| < 2^49)
-    static_assert(I8_ND == 5, "level grouping assumes five digits");
+    static_assert(I8_ND == 4 || I8_ND == 5, "level grouping for four or five digits");
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r01 = cr[0][v] * 128 + cr[1][v], r23 = cr[2][v] * 128 + cr[3][v];
       const int i01 = ci[0][v] * 128 + ci[1][v], i23 = ci[2][v] * 128 + ci[3][v];
-      const double dr = fma(fma((double)r01, 16384.0, (double)r23), 128.0, (double)cr[4][v]);
-      const double di = fma(fma((double)i01, 16384.0, (double)i23), 128.0, (double)ci[4][v]);
+      double dr = fma((double)r01, 16384.0, (double)r23);
+      double di = fma((double)i01, 16384.0, (double)i23);
+      if constexpr (I8_ND == 5) {
+        dr = fma(dr, 128.0, (double)cr[4][v]);
+        di = fma(di, 128.0, (double)ci[4][v]);
+      }
       const int ex = LE[buf][sl][4 * (lane >> 4) + v] + eb - 7 * (I8_ND + 1);
       tr[v] = ldexp(dr, ex);
       ti[v] = ldexp(di, ex);
@@ -999,7 +1012,7 @@ static hipError_t launch_exchange(const Job* jobs, int n, void* const* xpart, hi
       n,
       [&](int i) {
         const afqmc_kpt_problem& p = jobs[i].p;
-        if (jobs[i].int8x5) return 1024 + (p.m <= 32 ? 1 : 2);
+        if (jobs[i].int8) return 1024 + 8 * jobs[i].int8 + (p.m <= 32 ? 1 : 2);
         return p.prec * 64 + (p.prec == AFQMC_PREC_BF16X3
                                   ? (p.m <= 32 ? 1 : 2) + (p.nocc == 4 ? 4 : 0)
                                   : ks_class(p.m));
@@ -1019,7 +1032,7 @@ static hipError_t launch_exchange(const Job* jobs, int n, void* const* xpart, hi
           }
           a.mesh = make_mesh(p);
           a.Lh = (p.prec == AFQMC_PREC_BF16X3) ? p.Lhs : (low_prec(p.prec) ? p.Lh32 : p.Lh);
-          if (jobs[ids[q]].int8x5) a.Lh = p.Lh8;
+          if (jobs[ids[q]].int8) a.Lh = p.Lh8;
           a.Gh = (const cpx<double>*)p.Gh;
           a.part = (cpx<double>*)xpart[ids[q]];
           cnt[q] = (long long)p.nk * p.nk * p.nk * a.nchunk_w;
@@ -1029,9 +1042,15 @@ static hipError_t launch_exchange(const Job* jobs, int n, void* const* xpart, hi
         if (g == 0) return hipSuccess;
         const bool f32 = low_prec(jobs[ids[0]].p.prec);
         const dim3 grid((unsigned)g), blk(256);
-        if (jobs[ids[0]].int8x5) {
-          if (jobs[ids[0]].p.m <= 32) hipLaunchKernelGGL((exchange_int8x5_kernel<1>), grid, blk, 0, s, B);
-          else hipLaunchKernelGGL((exchange_int8x5_kernel<2>), grid, blk, 0, s, B);
+        if (jobs[ids[0]].int8) {
+          const bool k1 = jobs[ids[0]].p.m <= 32;
+          if (jobs[ids[0]].int8 == 5) {
+            if (k1) hipLaunchKernelGGL((exchange_int8_kernel<1, 5>), grid, blk, 0, s, B);
+            else hipLaunchKernelGGL((exchange_int8_kernel<2, 5>), grid, blk, 0, s, B);
+          } else {
+            if (k1) hipLaunchKernelGGL((exchange_int8_kernel<1, 4>), grid, blk, 0, s, B);
+            else hipLaunchKernelGGL((exchange_int8_kernel<2, 4>), grid, blk, 0, s, B);
+          }
           return hipGetLastError();
         }
         if (jobs[ids[0]].p.prec == AFQMC_PREC_BF16X3) {

@@ -486,22 +486,29 @@ __global__ __launch_bounds__(256) void field_split_kernel(const Batch<FieldArgs>
   o[96] = il;
 }
 
-// HS potential on the three-pass BF16 split:
+// HS potential on the three-pass BF16 split, from the half store of L:
 //   vhs[w][(k p), ((k-Q) r)] = sum_g zeta[w][Q][g] L[Q][k][p][r][g]
 // per Q a (W x nk m m) product with K = nchol; both operands come as split planes with g
-// contiguous.  The product streams L once from HBM, so the kernel is persistent and
-// pipelined: each 512-thread workgroup walks its tiles (64 walkers x 128 columns, tile
-// index blockIdx.x + i gridDim.x over every problem of the batch) as one stream of K
-// chunks of 32.  Waves 4-7 produce: they keep DEPTH chunks of both operands in flight in
+// contiguous.  L holds one member of each time-reversal pair: the Q whose index does not
+// exceed that of -Q (slots in increasing Q).  For a slot with Q != -Q the same L tile also
+// gives the partner blocks, L[-Q][k-Q][r][p] = conj(L[Q][k][p][r]):
+//   vhs[w][((k-Q) r), (k p)] = sum_g zeta[w][-Q][g] conj(L[Q][k][p][r][g]),
+// a second product on the same B operand.  The product streams the half store once from
+// HBM, so the kernel is persistent and pipelined: each 512-thread workgroup walks its tiles
+// (64 walkers x 96 columns of a slot, tile index blockIdx.x + i gridDim.x over every
+// problem of the batch) as one stream of K chunks of 32.  Waves 4-7 produce: they keep
+// DEPTH chunks of the operands (zeta of Q, of -Q for a paired slot, and L) in flight in
 // registers and copy the oldest into one of two LDS stages; waves 0-3 consume, in 2 x 2
-// (each 32 walkers x 64 columns, 12 BF16 MFMAs per complex 16 x 16 x 32 block, FP32
-// accumulation) and scatter a finished tile straight from registers.  One block barrier
-// per chunk; loads are unconditional (clamped addresses, zeros selected afterwards).
+// (each 32 walkers x 48 columns, 12 BF16 MFMAs per complex 16 x 16 x 32 block and product,
+// FP32 accumulation) and scatter a finished tile straight from registers (the partner
+// block transposed).  One block barrier per chunk; loads are unconditional (clamped
+// addresses, zeros selected afterwards).
 struct VhsBfArgs {
   int W, nk, m, C, CP, tiles_m, tiles_n;
   KMesh mesh;
   const unsigned short* zs;  // [nk][CP / 32][W][4][32]
-  const unsigned short* Ls;  // [nk][CP / 32][nk m m][4][32]
+  const unsigned short* Ls;  // [nq][CP / 32][nk m m][4][32], then int32 Q of each slot
+  const int* slotq;          // [nq]: the Q of each slot (the tail of Ls)
   cpx<float>* vhs;           // [W][nk m][nk m]
 };
 
@@ -511,15 +518,18 @@ struct VhsBfArgs {
 struct VhsPos {
   long long tile;  // global tile index (past the end: decoded as the last tile)
   int chunk;
-  int p, nchk, Q, row0, col0;
+  int p, nchk, slot, Q, nQ, row0, col0;  // nQ = -Q, or -1 for a self-paired slot
 };
 
 __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> B) {
-  constexpr int BM = 64, BN = 128, BKC = 32, RS = BKC + 8, DEPTH = 2;
+  // 96 columns per tile: the stages of both fields and of L then fit the 160 KB of LDS
+  constexpr int BM = 64, BN = 96, BKC = 32, RS = BKC + 8, DEPTH = 2;
+  constexpr int NUB = BN / 16;   // B units per producer thread
+  constexpr int NJ = BN / 32;    // 16-column blocks per consumer wave
   // planes padded by 64 bytes: a 16-byte staging store of 16 lanes covers 4 planes x 4
   // units, which unpadded plane strides (multiples of 256 bytes) put in one bank group
   constexpr int PSA = BM * RS + 32, PSB = BN * RS + 32;
-  __shared__ __attribute__((aligned(16))) unsigned short sA[2][4][PSA];
+  __shared__ __attribute__((aligned(16))) unsigned short sA[2][2][4][PSA];  // [stage][Q / -Q]
   __shared__ __attribute__((aligned(16))) unsigned short sB[2][4][PSB];
   const long long ntiles = B.first[B.nprob];
   const long long G = gridDim.x;
@@ -533,7 +543,10 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
     ps.p = batch_find(B, t < ntiles ? t : ntiles - 1, loc);
     const VhsBfArgs& a = B.a[ps.p];
     const int per_q = a.tiles_m * a.tiles_n;
-    ps.Q = (int)(loc / per_q);
+    ps.slot = (int)(loc / per_q);
+    ps.Q = a.slotq[ps.slot];
+    const int nq = a.mesh.neg(ps.Q);
+    ps.nQ = nq == ps.Q ? -1 : nq;
     const int rem = (int)(loc % per_q);
     ps.row0 = (rem / a.tiles_n) * BM;
     ps.col0 = (rem % a.tiles_n) * BN;
@@ -551,31 +564,33 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
 
   if (wave >= 4) {
     // ---------------- producers: unit u = pt + 256 e: row / column u >> 4, plane
-    // (u >> 2) & 3, 8 k at 8 (u & 3); A: 4 units, B: 8 units per thread
+    // (u >> 2) & 3, 8 k at 8 (u & 3); A: 4 units per field (Q and -Q), B: NUB units
     const int pt = threadIdx.x - 256;
     typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-    u4 ra[DEPTH][4], rb[DEPTH][8];
+    u4 ra[DEPTH][8], rb[DEPTH][NUB];
     VhsPos ip, sp;
     decode(blockIdx.x, ip);
     sp = ip;
     long long issued = 0;
-    auto issue = [&](u4 (&xa)[4], u4 (&xb)[8]) {
+    auto issue = [&](u4 (&xa)[8], u4 (&xb)[NUB]) {
       // past the end of the stream: chunk 0 of the last tile again (never stored)
       const VhsBfArgs& a = B.a[ip.p];
-      const int Q = ip.Q, row0 = ip.row0, col0 = ip.col0;
+      const int row0 = ip.row0, col0 = ip.col0;
       const int ncol = a.nk * a.m * a.m, CP = a.CP;
       const int k0 = (issued < total ? ip.chunk : 0) * BKC;
-      const unsigned short* __restrict__ Lq = a.Ls + (int64_t)Q * ncol * 4 * CP;
+      const unsigned short* __restrict__ Lq = a.Ls + (int64_t)ip.slot * ncol * 4 * CP;
+      const int q2 = ip.nQ >= 0 ? ip.nQ : ip.Q;  // a self-paired slot loads Q twice (unused)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int u = pt + 256 * e;
+      for (int e = 0; e < 8; ++e) {
+        const int u = pt + 256 * (e & 3);
+        const int Qf = e < 4 ? ip.Q : q2;
         const int w = min(row0 + (u >> 4), a.W - 1);
         xa[e] = *reinterpret_cast<const u4*>(
-            a.zs + ((((int64_t)Q * (CP / BKC) + k0 / BKC) * a.W + w) * 4 + ((u >> 2) & 3)) * BKC +
+            a.zs + ((((int64_t)Qf * (CP / BKC) + k0 / BKC) * a.W + w) * 4 + ((u >> 2) & 3)) * BKC +
             8 * (u & 3));
       }
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
+      for (int e = 0; e < NUB; ++e) {
         const int u = pt + 256 * e;
         const int col = min(col0 + (u >> 4), ncol - 1);
         xb[e] = *reinterpret_cast<const u4*>(
@@ -584,19 +599,19 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
       if (issued < total) advance(ip);
       ++issued;
     };
-    auto stash = [&](int st, const u4 (&xa)[4], const u4 (&xb)[8]) {
+    auto stash = [&](int st, const u4 (&xa)[8], const u4 (&xb)[NUB]) {
       // rows past W: zeros (their loads were clamped); columns past ncol are not stored
       const VhsBfArgs& a = B.a[sp.p];
       const int row0 = sp.row0;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int u = pt + 256 * e;
+      for (int e = 0; e < 8; ++e) {
+        const int u = pt + 256 * (e & 3);
         const u4 z = {0u, 0u, 0u, 0u};
-        *reinterpret_cast<u4*>(&sA[st][(u >> 2) & 3][(u >> 4) * RS + 8 * (u & 3)]) =
+        *reinterpret_cast<u4*>(&sA[st][e >> 2][(u >> 2) & 3][(u >> 4) * RS + 8 * (u & 3)]) =
             row0 + (u >> 4) < a.W ? xa[e] : z;
       }
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
+      for (int e = 0; e < NUB; ++e) {
         const int u = pt + 256 * e;
         *reinterpret_cast<u4*>(&sB[st][(u >> 2) & 3][(u >> 4) * RS + 8 * (u & 3)]) = xb[e];
       }
@@ -624,14 +639,14 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
 
   // ---------------- consumers
   const int wm = wave >> 1, wn = wave & 1;
-  v4f acr[2][4], aci[2][4];
+  v4f acr[2][NJ], aci[2][NJ], bcr[2][NJ], bci[2][NJ];  // products with zeta of Q and of -Q
   auto zero = [&]() {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < NJ; ++j) {
         acr[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-        aci[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+        aci[i][j] = acr[i][j]; bcr[i][j] = acr[i][j]; bci[i][j] = acr[i][j];
       }
   };
   zero();
@@ -644,20 +659,21 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
       if (s0 + d < total) {
         const int st = (int)((s0 + d) & 1);
         const int kq = 8 * (lane >> 4);
+        const bool paired = cp.nQ >= 0;
         u16x8 fa[2][4];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
           for (int pl = 0; pl < 4; ++pl)
-            fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][pl][(wm * 32 + i * 16 + (lane & 15)) * RS + kq]);
+            fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][0][pl][(wm * 32 + i * 16 + (lane & 15)) * RS + kq]);
         const u16x8 fn[2][2] = {{bf16_neg(fa[0][2]), bf16_neg(fa[0][3])},
                                 {bf16_neg(fa[1][2]), bf16_neg(fa[1][3])}};
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NJ; ++j) {
           u16x8 fb[4];
 #pragma unroll
           for (int pl = 0; pl < 4; ++pl)
-            fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][(wn * 64 + j * 16 + (lane & 15)) * RS + kq]);
+            fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][(wn * (BN / 2) + j * 16 + (lane & 15)) * RS + kq]);
 #pragma unroll
           for (int i = 0; i < 2; ++i) {
             // re += Zr Lr - Zi Li,  im += Zr Li + Zi Lr  (fn: -Zi)
@@ -667,26 +683,57 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
             aci[i][j] = mul3(fa[i][2], fa[i][3], fb[0], fb[1], aci[i][j]);
           }
         }
+        if (paired) {
+          // with conj(L): re += Zr Lr + Zi Li,  im += Zi Lr - Zr Li
+          u16x8 ga[2][4];
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl)
+              ga[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][1][pl][(wm * 32 + i * 16 + (lane & 15)) * RS + kq]);
+          const u16x8 gn[2][2] = {{bf16_neg(ga[0][0]), bf16_neg(ga[0][1])},
+                                  {bf16_neg(ga[1][0]), bf16_neg(ga[1][1])}};
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            u16x8 fb[4];
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl)
+              fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][(wn * (BN / 2) + j * 16 + (lane & 15)) * RS + kq]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+              bcr[i][j] = mul3(ga[i][0], ga[i][1], fb[0], fb[1], bcr[i][j]);
+              bcr[i][j] = mul3(ga[i][2], ga[i][3], fb[2], fb[3], bcr[i][j]);
+              bci[i][j] = mul3(ga[i][2], ga[i][3], fb[0], fb[1], bci[i][j]);
+              bci[i][j] = mul3(gn[i][0], gn[i][1], fb[2], fb[3], bci[i][j]);
+            }
+          }
+        }
         if (cp.chunk + 1 == cp.nchk) {
-          // tile done: column (k p r) of Q to vhs[w][(k p)][((k - Q) r)]
+          // tile done: column (k p r) of Q to vhs[w][(k p)][((k - Q) r)], and for a paired
+          // slot the partner product to vhs[w][((k - Q) r)][(k p)]
           const VhsBfArgs& a = B.a[cp.p];
           const int Q = cp.Q, row0 = cp.row0, col0 = cp.col0;
           const int m = a.m, mm = m * m, ncol = a.nk * mm;
           const int64_t Nn = (int64_t)a.nk * m;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int col = col0 + wn * 64 + j * 16 + (lane & 15);
+          for (int j = 0; j < NJ; ++j) {
+            const int col = col0 + wn * (BN / 2) + j * 16 + (lane & 15);
             if (col >= ncol) continue;
             const int kp = col / mm, pr = col % mm;
             const int pp = pr / m, r = pr % m;
-            const int64_t off = ((int64_t)kp * m + pp) * Nn + (int64_t)a.mesh.kmq(kp, Q) * m + r;
+            const int kq = a.mesh.kmq(kp, Q);
+            const int64_t off = ((int64_t)kp * m + pp) * Nn + (int64_t)kq * m + r;
+            const int64_t offt = ((int64_t)kq * m + r) * Nn + (int64_t)kp * m + pp;
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
               for (int v = 0; v < 4; ++v) {
                 const int w = row0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
-                if (w < a.W)
+                if (w < a.W) {
                   a.vhs[(int64_t)w * Nn * Nn + off] = cpx<float>{acr[i][j][v], aci[i][j][v]};
+                  if (paired)
+                    a.vhs[(int64_t)w * Nn * Nn + offt] = cpx<float>{bcr[i][j][v], bci[i][j][v]};
+                }
               }
           }
           zero();
@@ -718,19 +765,20 @@ static hipError_t launch_vhs_bf16x3(const Job* J, const int* ids, int g, void* c
     VhsBfArgs& va = V.a[q];
     va.W = p.nwalk; va.nk = p.nk; va.m = p.m; va.C = p.nchol; va.CP = CP;
     va.tiles_m = (p.nwalk + 63) / 64;
-    va.tiles_n = (p.nk * p.m * p.m + 127) / 128;
+    va.tiles_n = (p.nk * p.m * p.m + 95) / 96;
     va.mesh = make_mesh(p);
     va.zs = (const unsigned short*)zeta[ids[q]];
     va.Ls = (const unsigned short*)p.Ls;
+    va.slotq = (const int*)((const char*)p.Ls + ls_plane_bytes(p));
     va.vhs = (cpx<float>*)j.vhs;
-    cv[q] = (long long)p.nk * va.tiles_m * va.tiles_n;  // tiles
+    cv[q] = (long long)ls_slots(p) * va.tiles_m * va.tiles_n;  // tiles
   }
   long long gf = batch_close(F, cf), gv = batch_close(V, cv);
   if (gf < 0 || gv < 0) return hipErrorInvalidValue;
   if (gf > 0) hipLaunchKernelGGL(field_split_kernel, dim3((unsigned)gf), dim3(256), 0, s, F);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || gv == 0) return e;
-  // persistent: one workgroup per CU (the LDS stages take 120 KB), at most one per tile
+  // persistent: one workgroup per CU (the LDS stages take 145 KB), at most one per tile
   int dev = 0, ncu = 0;
   e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);

@@ -59,13 +59,29 @@ size_t carve_vbias(Carve& c, const Dims& d, VbiasWs& v);
 // function slots).  A placed precision sizes each stage in its own precision.
 size_t ws_bytes_entry(const afqmc_kpt_problem& p, int entry);
 
+// The half store of L's split planes (BF16X3 step): one slot per time-reversal pair, the Q
+// whose index does not exceed that of -Q, in increasing Q.  -Q = Q exactly when every
+// component of Q is 0 or half an even mesh dimension, so the slots number
+// (nk + prod_d (1 + [mesh_d even])) / 2.
+inline int ls_slots(const afqmc_kpt_problem& p) {
+  int self = 1;
+  for (int d = 0; d < 3; ++d) self *= (p.mesh[d] % 2 == 0) ? 2 : 1;
+  return (p.nk + self) / 2;
+}
+// Bytes of the planes [slots][CP / 32][nk m m][4][32] (bf16); the int32 Q of each slot
+// follows them.
+inline size_t ls_plane_bytes(const afqmc_kpt_problem& p) {
+  const size_t CP = 32 * (size_t)((p.nchol + 31) / 32);
+  return (size_t)ls_slots(p) * CP * (size_t)p.nk * p.m * p.m * 4 * 2;
+}
+
 // The problem as a stage sees it: prec resolved to the energy precision for the local
 // energy and its adjoint, to the step precision otherwise.
-// The int8-split energy runs as FP64 except for its exchange kernel (Job::int8x5).
+// The int8-split energies run as FP64 except for their exchange kernel (Job::int8).
 inline afqmc_kpt_problem stage_view(const afqmc_kpt_problem& p, bool energy) {
   afqmc_kpt_problem q = p;
   q.prec = energy ? energy_prec(p.prec) : step_prec(p.prec);
-  if (q.prec == AFQMC_PREC_INT8X5) q.prec = AFQMC_PREC_FP64;
+  if (int8_digits(q.prec)) q.prec = AFQMC_PREC_FP64;
   return q;
 }
 inline bool energy_entry(int entry) {
@@ -76,7 +92,8 @@ inline bool energy_entry(int entry) {
 // buffers (unused ones are null).
 struct Job {
   afqmc_kpt_problem p;
-  bool int8x5;      // energy stage whose exchange runs on the int8 split (p.prec is FP64)
+  int int8;         // energy stage whose exchange runs on the int8 split: its digits per
+                    // operand (4 or 5; p.prec is FP64), else 0
   void* ws;
   const double* x;  // fields of the current step [W][nk][C][2]
   void* xbar;       // [W][nk][C][2] complex128

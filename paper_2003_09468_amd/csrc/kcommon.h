@@ -16,6 +16,11 @@ __host__ __device__ __forceinline__ bool low_prec(int prec) {
   return prec == AFQMC_PREC_FP32 || prec == AFQMC_PREC_BF16X3;
 }
 
+// Digits per operand of an int8-split energy precision (0 for the others).
+__host__ __device__ __forceinline__ int int8_digits(int prec) {
+  return prec == AFQMC_PREC_INT8X5 ? 5 : (prec == AFQMC_PREC_INT8X4 ? 4 : 0);
+}
+
 // A placed precision (AFQMC_PREC_PLACE) resolves to the precision of the step contractions
 // (force bias, HS potential, Taylor products) and to that of the local energy and its
 // adjoint; a plain afqmc_prec value is both.

@@ -106,9 +106,6 @@ __global__ void lh_split_kernel(int nk, int m, int nocc, int C, int KP,
   }
 }
 
-// BF16 split planes of L for the three-pass HS potential, by chunks of 32 g:
-//   Ls[Q][g / 32][(k p r)][plane][g % 32], g zero-padded to CP = 32 ceil(C / 32), so that
-//   one chunk of consecutive columns is one contiguous block.
 // Int8 digits of Lh for the INT8X5 exchange: row (Q, k, g, a) over kk < KP8 of
 // [Re Lh[Q][k][a][:][g] | Im Lh[Q][k][a][:][g] | 0], scaled by 2^e (2^(e-2) <= max |x| <
 // 2^(e-1)) and cut into five signed 7-bit digits x 2^-e = sum_i d_i 128^-(i+1) + rest (each
@@ -147,18 +144,31 @@ __global__ void lh_int8_kernel(int nk, int m, int nocc, int C, int KP8,
   }
 }
 
+// The Q of each slot of the half store (the Q with index <= that of -Q, increasing); one
+// thread.
+__global__ void ls_slot_kernel(int nk, KMesh mesh, int* __restrict__ slotq) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int s = 0;
+  for (int Q = 0; Q < nk; ++Q)
+    if (Q <= mesh.neg(Q)) slotq[s++] = Q;
+}
+
+// BF16 split planes of L for the three-pass HS potential, half store, by chunks of 32 g:
+//   Ls[slot][g / 32][(k p r)][plane][g % 32] = split of L[Q(slot)][k][p][r][g], g
+//   zero-padded to CP = 32 ceil(C / 32), so that one chunk of consecutive columns is one
+//   contiguous block.
 __global__ void l_split_kernel(int64_t ncols, int64_t ncq, int C, int CP,
-                               const cpx<double>* __restrict__ L,
+                               const cpx<double>* __restrict__ L, const int* __restrict__ slotq,
                                unsigned short* __restrict__ Ls) {
   const int64_t total = ncols * CP;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int g = (int)(i % CP);
-    const int64_t cg = i / CP;  // (Q, k, p, r)
+    const int64_t cg = i / CP;  // (slot, k, p, r)
     const int64_t Q = cg / ncq, col = cg % ncq;
     float xr = 0.f, xi = 0.f;
     if (g < C) {
-      const cpx<double> v = L[cg * C + g];
+      const cpx<double> v = L[((int64_t)slotq[Q] * ncq + col) * C + g];
       xr = (float)v.re;
       xi = (float)v.im;
     }
@@ -327,7 +337,7 @@ hipError_t run_prepare(const afqmc_kpt_problem& p, const void* H1, void* ws, hip
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (ep == AFQMC_PREC_INT8X5) {
+  if (int8_digits(ep)) {  // five digits stored; INT8X4 reads the first four
     const int KP8 = 64 * ((2 * p.m + 63) / 64);
     hipLaunchKernelGGL(lh_int8_kernel, dim3(2048), dim3(256), 0, s, p.nk, p.m, p.nocc, p.nchol,
                        KP8, (const cpx<double>*)p.Lh, (signed char*)p.Lh8);
@@ -336,9 +346,13 @@ hipError_t run_prepare(const afqmc_kpt_problem& p, const void* H1, void* ws, hip
   }
   if (sp == AFQMC_PREC_BF16X3) {
     const int CP = 32 * ((p.nchol + 31) / 32);
-    const int64_t ncq = (int64_t)p.nk * p.m * p.m, ncols = p.nk * ncq;
+    const int64_t ncq = (int64_t)p.nk * p.m * p.m, ncols = ls_slots(p) * ncq;
+    int* slotq = (int*)((char*)p.Ls + ls_plane_bytes(p));
+    hipLaunchKernelGGL(ls_slot_kernel, dim3(1), dim3(64), 0, s, p.nk, make_mesh(p), slotq);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(l_split_kernel, dim3(4096), dim3(256), 0, s, ncols, ncq, p.nchol, CP,
-                       (const cpx<double>*)p.L, (unsigned short*)p.Ls);
+                       (const cpx<double>*)p.L, (const int*)slotq, (unsigned short*)p.Ls);
     e = hipGetLastError();
   }
   return e;

@@ -383,7 +383,7 @@ def test_placed_precision_encoding(L):
             p.prec = B.prec_place(sp, ep)
             assert B.step_prec(p.prec) == sp and B.energy_prec(p.prec) == ep
             assert L.afqmc_kpt_workspace_bytes(ctypes.byref(p), 1, 8, ctypes.byref(out)) == 0
-    for bad in (3, 15, B.prec_place(0, 4), B.prec_place(3, 0), 0x80, 0x100, -1):
+    for bad in (3, 4, 15, B.prec_place(0, 5), B.prec_place(3, 0), 0x80, 0x100, -1):
         p = good_problem()
         p.prec = bad
         assert call(L, "afqmc_kpt_greens", p, ws, 1 << 40, None) == -1, bad
@@ -538,17 +538,18 @@ def test_reblock_and_etrial_validation(L):
                 ctypes.c_void_p(0x4000), 0, ctypes.c_void_p(0x100000), 1 << 40, None) == -3
 
 
-def test_int8x5_energy_precision(L):
-    """INT8X5 is an energy precision only: PLACE(step, INT8X5) is valid, as a plain value or
-    a step precision it is not; the energy needs the digit array Lh8 (the adjoint, FP64,
-    does not); workspaces are those of FP64."""
+@pytest.mark.parametrize("ep", [3, 4], ids=["int8x5", "int8x4"])
+def test_int8_energy_precision(L, ep):
+    """INT8X5 and INT8X4 are energy precisions only: PLACE(step, INT8Xn) is valid, as a plain
+    value or a step precision they are not; the energy needs the digit array Lh8 (the
+    adjoint, FP64, does not); workspaces are those of FP64."""
     ws = ctypes.c_void_p(0x1000000)
     E = ctypes.c_void_p(0x2000)
     out = ctypes.c_size_t()
     for sp in range(3):
         p = good_problem()
-        p.prec = B.prec_place(sp, B.PREC_INT8X5)
-        assert B.energy_prec(p.prec) == B.PREC_INT8X5
+        p.prec = B.prec_place(sp, ep)
+        assert B.energy_prec(p.prec) == ep
         for e in range(10):
             assert L.afqmc_kpt_workspace_bytes(ctypes.byref(p), 1, e, ctypes.byref(out)) == 0
         q = good_problem()
@@ -574,7 +575,21 @@ def test_int8x5_energy_precision(L):
         if not gpu_available():
             assert call(L, "afqmc_kpt_energy_backward", p, None, ctypes.c_void_p(0x3000), ws,
                         1 << 40, None) == -5
-    for bad in (B.PREC_INT8X5, B.prec_place(B.PREC_INT8X5, 0)):
+    for bad in (ep, B.prec_place(ep, 0)):
         p = good_problem()
         p.prec = bad
         assert call(L, "afqmc_kpt_energy", p, E, ws, 1 << 40, None) == -1
+
+
+@pytest.mark.parametrize("mesh", [(1, 1, 1), (2, 2, 2), (3, 3, 3), (4, 4, 4), (2, 3, 1),
+                                  (1, 2, 3), (3, 1, 1), (2, 1, 1), (4, 3, 2)])
+def test_half_store_slots(mesh):
+    """The half store of L keeps one block per time-reversal pair: its slot count equals the
+    number of Q whose index does not exceed that of -Q (brute force over the oracle's -Q
+    table), i.e. (nk + #{Q = -Q}) / 2."""
+    from oracle import kpoint as kp
+    _, negq = kp.kpoint_tables(mesh)
+    brute = sum(1 for Q in range(len(negq)) if Q <= negq[Q])
+    assert B.ls_slots(mesh) == brute
+    pairs = sum(1 for Q in range(len(negq)) if Q < negq[Q])
+    assert brute == pairs + sum(1 for Q in range(len(negq)) if Q == negq[Q])

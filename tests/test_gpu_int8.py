@@ -1,13 +1,15 @@
-"""The local energy with its exchange on the int8 split (energy precision INT8X5) against the
-FP64 oracle, with a bar derived from the split's truncation bound; the rest of the energy
-and the adjoint are the FP64 kernels, bit for bit.
+"""The local energy with its exchange on the int8 split (energy precisions INT8X5 and
+INT8X4) against the FP64 oracle, with a bar derived from the split's truncation bound; the
+rest of the energy and the adjoint are the FP64 kernels, bit for bit.
 
 Bound.  Every real row x of [Re Lh | Im Lh] (per Q, k, a, g) and of [Re G | Im G] (per
 walker, row and column block of Gh) is scaled by s = 2^e with 2^(e-2) <= max|x| < 2^(e-1)
-and kept to five 7-bit digits; a real product of two rows over kk < 2m then loses at most
-2m * 1.5 * 2^-35 * s s' (the truncated operands and the dropped digit levels 7 .. 10), so
-each complex T1 entry is off by at most delta = sqrt(2) * 2m * 1.5 * 2^-35 * s s'.  The
-exchange sums T1_t[b,a,g] T2_t[a,b,g] over the triples t, so
+and kept to S 7-bit digits (S = 5 or 4).  The two truncated operands cost at most
+2 * (128^-S / 2) * (1/2) s s' per real product and the dropped digit levels S+2 .. 2S at
+most (S-1) 4096 128^-(S+2) (128/127) s s', together (1/2 + (S-1)/4 * 128/127) 2^-7S s s'
+(about 1.5 * 2^-35 for S = 5, 1.25 * 2^-28 for S = 4); over kk < 2m each complex T1 entry
+is off by at most delta = sqrt(2) * 2m * (that factor) * s s'.  The exchange sums
+T1_t[b,a,g] T2_t[a,b,g] over the triples t, so
   |dEX| <= sum_t sum_{g,a,b} delta_t |T2_t| + |T1_t| delta'_t + delta_t delta'_t,
 with |T1|, |T2| bounded by the sums of |Lh| |G| over r.  The test takes twice that.
 """
@@ -38,14 +40,14 @@ def _scale(x, axis):
     return np.where(amax > 0, np.ldexp(1.0, E + 1), 1.0)
 
 
-def exchange_bound(Lh, Gh, mesh):
+def exchange_bound(Lh, Gh, mesh, S=5):
     nk, _, nocc, m, nchol = Lh.shape
     kmq, negq = kp.kpoint_tables(mesh)
     nw = Gh.shape[0]
     G = kp.blocked(Gh, nk, nocc, m).transpose(1, 3, 0, 2, 4)  # [k1, k2, w, a, r]
     sL = _scale(Lh, 3)                                         # [Q, k, a, g]
     sG = _scale(G, 4)                                          # [k1, k2, w, b]
-    eps = math.sqrt(2.0) * 2 * m * 1.5 * 2.0 ** -35
+    eps = math.sqrt(2.0) * 2 * m * (0.5 + (S - 1) / 4.0 * 128.0 / 127.0) * 2.0 ** (-7 * S)
     aL, aG = np.abs(Lh), np.abs(G)
     out = np.zeros(nw)
     for Q in range(nk):
@@ -65,9 +67,11 @@ def exchange_bound(Lh, Gh, mesh):
 
 
 @pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
+@pytest.mark.parametrize("digits", [5, 4])
 @pytest.mark.parametrize("case", CASESEL)
-def test_int8x5_energy_against_oracle(case):
-    pl = lib.prec_place(lib.PREC_FP64, lib.PREC_INT8X5)
+def test_int8_energy_against_oracle(case, digits):
+    ep = lib.PREC_INT8X5 if digits == 5 else lib.PREC_INT8X4
+    pl = lib.prec_place(lib.PREC_FP64, ep)
     s, U, x, p, pre = build(case, prec=pl)
     _, _, _, pd, _ = build(case, prec=lib.PREC_FP64)
     assert p.Lh8 is not None and p.Lh32 is None and p.Lhs is None
@@ -83,14 +87,15 @@ def test_int8x5_energy_against_oracle(case):
         # one-body and Coulomb parts: the FP64 kernels
         assert np.array_equal(E[:, :2], Ed[:, :2])
         Eref = kp.local_energy(pre["Lh"], pre["h1h"], Gh, s.mesh)
-        bound = exchange_bound(pre["Lh"], Gh, s.mesh)
+        bound = exchange_bound(pre["Lh"], Gh, s.mesh, S=digits)
         dEX = np.abs(E[:, 2] - Eref[:, 2])
         # twice the derived bound, plus the FP64 evaluation's own rounding
         bar = 2.0 * bound + 1e-12 * np.abs(Eref).sum(axis=1)
         assert np.all(dEX <= bar), (case, it, dEX, bar)
-        # the split is far closer than the bar suggests on these inputs, and far closer
-        # than an FP32 contraction (relative 6e-8 per product)
-        assert np.all(dEX <= 1e-9 * np.abs(Eref).sum(axis=1) + 1e-12), (case, it, dEX)
+        # the split is far closer than the bar suggests on these inputs, and (five digits)
+        # far closer than an FP32 contraction (relative 6e-8 per product)
+        rel_bar = 1e-9 if digits == 5 else 1e-7
+        assert np.all(dEX <= rel_bar * np.abs(Eref).sum(axis=1) + 1e-12), (case, it, dEX)
         # the adjoint stays FP64
         assert np.array_equal(host(p.energy_backward()), host(pd.energy_backward()))
 
