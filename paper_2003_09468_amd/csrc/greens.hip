@@ -284,29 +284,41 @@ __global__ __launch_bounds__(512) void gj_reg_kernel(const Batch<GjbArgs> B) {
   const cpx<double>* __restrict__ S = B.a[pb].M + (int64_t)w * n * n;
   cpx<double>* __restrict__ out = B.a[pb].out + (int64_t)w * n * n;
 
-  __shared__ double Pr[128][PW + 1], Pi[128][PW + 1];  // staged panel, then its T columns
-  __shared__ double Rr[PW][129], Ri[PW][129];         // pivot rows of the panel
+  // two panel buffers: the panel being applied (its T columns) and the next one, which
+  // wave 0 eliminates while the owners finish applying the current one
+  __shared__ double Pr[2][128][PW + 1], Pi[2][128][PW + 1];
+  __shared__ double Rr[PW][129], Ri[PW][129];  // pivot rows of the panel being applied
   __shared__ int qs[128], stamp[128], jpos[128];
   __shared__ double pvr[128], pvi[128];
   __shared__ unsigned char vis[128];
   __shared__ int flag_s;
+  __shared__ int staged;  // owners that have staged the next panel (monotone count)
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ntile = (n + 15) >> 4;
   const int col16 = lane & 15;
+  // tile i of owner wave (1..7): linear index t = (wave - 1) + 7 i over the ntile^2 tiles;
+  // row I = t / ntile, column J = t % ntile, skewed by I when ntile = 7 so that the tiles
+  // of one column belong to different owners
+  auto tile_ij = [&](int i, int& I, int& J) {
+    const int t = (wave - 1) + 7 * i;
+    I = t / ntile;
+    const int jj = t % ntile;
+    J = (ntile == 7) ? (jj - I + 7) % 7 : jj;
+    return t < ntile * ntile;
+  };
 
-  // tiles of this wave: t = (wave - 1) + 7 i
   double cr[TPW][4], ci[TPW][4];
   if (wave > 0) {
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
-      const int t = (wave - 1) + 7 * i;
-      const int I = t / ntile, J = t % ntile;
+      int I, J;
+      const bool ok = tile_ij(i, I, J);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = I * 16 + mfma16<double>::drow(lane, v), col = J * 16 + col16;
         cpx<double> x{0.0, 0.0};
-        if (t < ntile * ntile && row < n && col < n) x = S[(int64_t)row * n + col];
+        if (ok && row < n && col < n) x = S[(int64_t)row * n + col];
         cr[i][v] = x.re;
         ci[i][v] = x.im;
       }
@@ -314,139 +326,179 @@ __global__ __launch_bounds__(512) void gj_reg_kernel(const Batch<GjbArgs> B) {
   }
   for (int i = tid; i < 128; i += 512) { stamp[i] = -1; jpos[i] = 0; }
   for (int i = tid; i < PW * 129; i += 512) { (&Rr[0][0])[i] = 0.0; (&Ri[0][0])[i] = 0.0; }
-  if (tid == 0) flag_s = 0;
+  if (tid == 0) { flag_s = 0; staged = 0; }
   bool used0 = false, used1 = false;  // wave 0: rows lane and lane + 64
   int bad = 0;
-  __syncthreads();
 
-  for (int j0 = 0; j0 < n; j0 += PW) {
-    const int bw = (n - j0 < PW) ? n - j0 : PW;
-    const int Jp = j0 >> 4, c0 = j0 & 15;  // tile column of the panel, first column in it
-    // (1) stage the panel
-    if (wave > 0) {
+  // owners: the columns j1 .. j1 + PW - 1 of their tiles to panel buffer pbuf
+  auto stage_panel = [&](int j1, int pbuf) {
+    const int Jq = j1 >> 4, cq = j1 & 15;
 #pragma unroll
-      for (int i = 0; i < TPW; ++i) {
-        const int t = (wave - 1) + 7 * i;
-        if (t >= ntile * ntile || t % ntile != Jp) continue;
-        const int I = t / ntile;
-        const int c = col16 - c0;
-        if (c < 0 || c >= PW) continue;
+    for (int i = 0; i < TPW; ++i) {
+      int I, J;
+      if (!tile_ij(i, I, J) || J != Jq) continue;
+      const int c = col16 - cq;
+      if (c < 0 || c >= PW) continue;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = I * 16 + mfma16<double>::drow(lane, v);
-          if (row < n) { Pr[row][c] = cr[i][v]; Pi[row][c] = ci[i][v]; }
-        }
+      for (int v = 0; v < 4; ++v) {
+        const int row = I * 16 + mfma16<double>::drow(lane, v);
+        if (row < n) { Pr[pbuf][row][c] = cr[i][v]; Pi[pbuf][row][c] = ci[i][v]; }
       }
     }
-    __syncthreads();
-    // (2) wave 0 eliminates the panel.  Wave 0 owns no tiles, so with TPW >= 4 its two
-    // panel rows live in the registers of the tile arrays.
-    if (wave == 0) {
-      double sar[2][PW], sai[2][PW];
-      auto AR = [&](int sl, int c) -> double& {
-        if constexpr (TPW >= 4) return cr[(sl * PW + c) >> 2][(sl * PW + c) & 3];
-        else return sar[sl][c];
-      };
-      auto AI = [&](int sl, int c) -> double& {
-        if constexpr (TPW >= 4) return ci[(sl * PW + c) >> 2][(sl * PW + c) & 3];
-        else return sai[sl][c];
-      };
+  };
+
+  // wave 0: eliminates the panel at j1 in buffer pbuf (two rows per lane in the registers of
+  // its unused tile arrays), writes its T columns back and records the pivots
+  auto factor = [&](int j1, int pbuf) {
+    const int bw = (n - j1 < PW) ? n - j1 : PW;
+    double sar[2][PW], sai[2][PW];
+    auto AR = [&](int sl, int c) -> double& {
+      if constexpr (TPW >= 4) return cr[(sl * PW + c) >> 2][(sl * PW + c) & 3];
+      else return sar[sl][c];
+    };
+    auto AI = [&](int sl, int c) -> double& {
+      if constexpr (TPW >= 4) return ci[(sl * PW + c) >> 2][(sl * PW + c) & 3];
+      else return sai[sl][c];
+    };
 #pragma unroll
-      for (int sl = 0; sl < 2; ++sl) {
-        const int r = lane + 64 * sl;
+    for (int sl = 0; sl < 2; ++sl) {
+      const int r = lane + 64 * sl;
+#pragma unroll
+      for (int c = 0; c < PW; ++c) {
+        AR(sl, c) = (r < n) ? Pr[pbuf][r][c] : 0.0;
+        AI(sl, c) = (r < n) ? Pi[pbuf][r][c] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < PW; ++jj) {
+      if (jj < bw) {
+        unsigned long long key = 0ull;
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+          const int r = lane + 64 * sl;
+          const bool u = sl ? used1 : used0;
+          if (r < n && !u) {
+            const double a2 = AR(sl, jj) * AR(sl, jj) + AI(sl, jj) * AI(sl, jj);
+            const unsigned long long k2 =
+                ((unsigned long long)__double_as_longlong(a2) & ~0xffull) |
+                (unsigned long long)(255 - r);
+            key = (k2 > key) ? k2 : key;
+          }
+        }
+        key = key_max_dpp<0xB1>(key);   // quad_perm [1,0,3,2]
+        key = key_max_dpp<0x4E>(key);   // quad_perm [2,3,0,1]
+        key = key_max_dpp<0x141>(key);  // row_half_mirror
+        key = key_max_dpp<0x140>(key);  // row_mirror
+        unsigned long long kmax = key_readlane(key, 0);
+#pragma unroll
+        for (int rr = 1; rr < 4; ++rr) {
+          const unsigned long long o = key_readlane(key, 16 * rr);
+          kmax = (o > kmax) ? o : kmax;
+        }
+        const int q = 255 - (int)(kmax & 0xffull);
+        const int ql = q & 63, qsl = q >> 6;
+        double br[PW], bi[PW];
 #pragma unroll
         for (int c = 0; c < PW; ++c) {
-          AR(sl, c) = (r < n) ? Pr[r][c] : 0.0;
-          AI(sl, c) = (r < n) ? Pi[r][c] : 0.0;
+          br[c] = dbl_readlane(qsl ? AR(1, c) : AR(0, c), ql);
+          bi[c] = dbl_readlane(qsl ? AI(1, c) : AI(0, c), ql);
         }
-      }
+        double vr = br[jj], vi = bi[jj];
+        double den = vr * vr + vi * vi;
+        if (lane == 0) {
+          qs[j1 + jj] = q; pvr[j1 + jj] = vr; pvi[j1 + jj] = vi; stamp[q] = j1; jpos[q] = jj;
+        }
+        if (!(den > 0.0) || !isfinite(den)) {
+          bad |= isfinite(den) ? 1 : 2;
+          vr = 1.0; vi = 0.0; den = 1.0;
+        }
+        const double inv = 1.0 / den, ir = vr * inv, ii = -vi * inv;
 #pragma unroll
-      for (int jj = 0; jj < PW; ++jj) {
-        if (jj < bw) {
-          unsigned long long key = 0ull;
+        for (int sl = 0; sl < 2; ++sl) {
+          const int r = lane + 64 * sl;
+          if (r >= n) continue;
+          if (r == q) {
+            if (sl) used1 = true; else used0 = true;
 #pragma unroll
-          for (int sl = 0; sl < 2; ++sl) {
-            const int r = lane + 64 * sl;
-            const bool u = sl ? used1 : used0;
-            if (r < n && !u) {
-              const double a2 = AR(sl, jj) * AR(sl, jj) + AI(sl, jj) * AI(sl, jj);
-              const unsigned long long k2 =
-                  ((unsigned long long)__double_as_longlong(a2) & ~0xffull) |
-                  (unsigned long long)(255 - r);
-              key = (k2 > key) ? k2 : key;
+            for (int c = 0; c < PW; ++c) {
+              const double xr = AR(sl, c), xi = AI(sl, c);
+              AR(sl, c) = (c == jj) ? ir : xr * ir - xi * ii;
+              AI(sl, c) = (c == jj) ? ii : xr * ii + xi * ir;
+            }
+          } else {
+            const double fr = AR(sl, jj), fi = AI(sl, jj);
+            const double gr = fr * ir - fi * ii, gi = fr * ii + fi * ir;
+#pragma unroll
+            for (int c = 0; c < PW; ++c) {
+              const double ur = AR(sl, c) - (gr * br[c] - gi * bi[c]);
+              const double ui = AI(sl, c) - (gr * bi[c] + gi * br[c]);
+              AR(sl, c) = (c == jj) ? -gr : ur;
+              AI(sl, c) = (c == jj) ? -gi : ui;
             }
           }
-          key = key_max_dpp<0xB1>(key);   // quad_perm [1,0,3,2]
-          key = key_max_dpp<0x4E>(key);   // quad_perm [2,3,0,1]
-          key = key_max_dpp<0x141>(key);  // row_half_mirror
-          key = key_max_dpp<0x140>(key);  // row_mirror
-          unsigned long long kmax = key_readlane(key, 0);
-#pragma unroll
-          for (int rr = 1; rr < 4; ++rr) {
-            const unsigned long long o = key_readlane(key, 16 * rr);
-            kmax = (o > kmax) ? o : kmax;
-          }
-          const int q = 255 - (int)(kmax & 0xffull);
-          const int ql = q & 63, qsl = q >> 6;
-          double br[PW], bi[PW];
-#pragma unroll
-          for (int c = 0; c < PW; ++c) {
-            br[c] = dbl_readlane(qsl ? AR(1, c) : AR(0, c), ql);
-            bi[c] = dbl_readlane(qsl ? AI(1, c) : AI(0, c), ql);
-          }
-          double vr = br[jj], vi = bi[jj];
-          double den = vr * vr + vi * vi;
-          if (lane == 0) {
-            qs[j0 + jj] = q; pvr[j0 + jj] = vr; pvi[j0 + jj] = vi; stamp[q] = j0; jpos[q] = jj;
-          }
-          if (!(den > 0.0) || !isfinite(den)) {
-            bad |= isfinite(den) ? 1 : 2;
-            vr = 1.0; vi = 0.0; den = 1.0;
-          }
-          const double inv = 1.0 / den, ir = vr * inv, ii = -vi * inv;
-#pragma unroll
-          for (int sl = 0; sl < 2; ++sl) {
-            const int r = lane + 64 * sl;
-            if (r >= n) continue;
-            if (r == q) {
-              if (sl) used1 = true; else used0 = true;
-#pragma unroll
-              for (int c = 0; c < PW; ++c) {
-                const double xr = AR(sl, c), xi = AI(sl, c);
-                AR(sl, c) = (c == jj) ? ir : xr * ir - xi * ii;
-                AI(sl, c) = (c == jj) ? ii : xr * ii + xi * ir;
-              }
-            } else {
-              const double fr = AR(sl, jj), fi = AI(sl, jj);
-              const double gr = fr * ir - fi * ii, gi = fr * ii + fi * ir;
-#pragma unroll
-              for (int c = 0; c < PW; ++c) {
-                const double ur = AR(sl, c) - (gr * br[c] - gi * bi[c]);
-                const double ui = AI(sl, c) - (gr * bi[c] + gi * br[c]);
-                AR(sl, c) = (c == jj) ? -gr : ur;
-                AI(sl, c) = (c == jj) ? -gi : ui;
-              }
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int sl = 0; sl < 2; ++sl) {
-        const int r = lane + 64 * sl;
-        if (r < n) {
-#pragma unroll
-          for (int c = 0; c < PW; ++c) { Pr[r][c] = AR(sl, c); Pi[r][c] = AI(sl, c); }
         }
       }
     }
-    __syncthreads();
-    // (3) pivot rows M[Q, :] before the update
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int r = lane + 64 * sl;
+      if (r < n) {
+#pragma unroll
+        for (int c = 0; c < PW; ++c) { Pr[pbuf][r][c] = AR(sl, c); Pi[pbuf][r][c] = AI(sl, c); }
+      }
+    }
+  };
+
+  // owners: M += Z M[Q, :] on tile i (K = PW) for the panel at j0 (buffer pbuf); the
+  // panel's own columns take T
+  auto update = [&](int i, int j0, int pbuf) {
+    const int bw = (n - j0 < PW) ? n - j0 : PW;
+    const int Jp = j0 >> 4, c0 = j0 & 15;
+    int I, J;
+    if (!tile_ij(i, I, J)) return;
+    v4d ur, ui;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) { ur[v] = cr[i][v]; ui[v] = ci[i][v]; }
+    const int arow = I * 16 + col16;
+#pragma unroll
+    for (int kb = 0; kb < PW / 4; ++kb) {
+      const int k = kb * 4 + (lane >> 4);
+      double zr = 0.0, zi = 0.0;
+      if (arow < n && k < bw) {
+        zr = Pr[pbuf][arow][k] - ((qs[j0 + k] == arow) ? 1.0 : 0.0);
+        zi = Pi[pbuf][arow][k];
+      }
+      cmfma<double>(zr, zi, Rr[k][J * 16 + col16], Ri[k][J * 16 + col16], ur, ui);
+    }
+    const int c = col16 - c0;
+    const bool inpanel = (J == Jp) && c >= 0 && c < PW;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = I * 16 + mfma16<double>::drow(lane, v);
+      const bool ok = inpanel && row < n && c < bw;
+      cr[i][v] = inpanel ? (ok ? Pr[pbuf][row][c] : 0.0) : ur[v];
+      ci[i][v] = inpanel ? (ok ? Pi[pbuf][row][c] : 0.0) : ui[v];
+    }
+  };
+
+  __syncthreads();
+  // the first panel: staged by its owners, eliminated by wave 0
+  if (wave > 0) stage_panel(0, 0);
+  __syncthreads();
+  if (wave == 0) factor(0, 0);
+  __syncthreads();
+
+  int np = 0;
+  for (int j0 = 0; j0 < n; j0 += PW, ++np) {
+    const int pbuf = np & 1;
+    const bool next = j0 + PW < n;
+    const int Jn = (j0 + PW) >> 4;
+    // (1) pivot rows M[Q, :] of this panel, before its update
     if (wave > 0) {
 #pragma unroll
       for (int i = 0; i < TPW; ++i) {
-        const int t = (wave - 1) + 7 * i;
-        if (t >= ntile * ntile) continue;
-        const int I = t / ntile, J = t % ntile;
+        int I, J;
+        if (!tile_ij(i, I, J)) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = I * 16 + mfma16<double>::drow(lane, v);
@@ -458,37 +510,35 @@ __global__ __launch_bounds__(512) void gj_reg_kernel(const Batch<GjbArgs> B) {
       }
     }
     __syncthreads();
-    // (4) M += Z M[Q, :] on every tile (K = PW), then the panel's columns take T
     if (wave > 0) {
+      // (2) the tiles that hold the next panel first, then that panel to the other buffer
+      if (next) {
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+          int I, J;
+          if (tile_ij(i, I, J) && J == Jn) update(i, j0, pbuf);
+        }
+        stage_panel(j0 + PW, pbuf ^ 1);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (lane == 0) __hip_atomic_fetch_add(&staged, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      // (3) every other tile, while wave 0 eliminates the next panel
 #pragma unroll
       for (int i = 0; i < TPW; ++i) {
-        const int t = (wave - 1) + 7 * i;
-        if (t >= ntile * ntile) continue;
-        const int I = t / ntile, J = t % ntile;
-        v4d ur, ui;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) { ur[v] = cr[i][v]; ui[v] = ci[i][v]; }
-        const int arow = I * 16 + col16;
-#pragma unroll
-        for (int kb = 0; kb < PW / 4; ++kb) {
-          const int k = kb * 4 + (lane >> 4);
-          double zr = 0.0, zi = 0.0;
-          if (arow < n && k < bw) {
-            zr = Pr[arow][k] - ((qs[j0 + k] == arow) ? 1.0 : 0.0);
-            zi = Pi[arow][k];
-          }
-          cmfma<double>(zr, zi, Rr[k][J * 16 + col16], Ri[k][J * 16 + col16], ur, ui);
-        }
-        const int c = col16 - c0;
-        const bool inpanel = (J == Jp) && c >= 0 && c < PW;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = I * 16 + mfma16<double>::drow(lane, v);
-          const bool ok = inpanel && row < n && c < bw;
-          cr[i][v] = inpanel ? (ok ? Pr[row][c] : 0.0) : ur[v];
-          ci[i][v] = inpanel ? (ok ? Pi[row][c] : 0.0) : ui[v];
-        }
+        int I, J;
+        if (tile_ij(i, I, J) && (!next || J != Jn)) update(i, j0, pbuf);
       }
+    } else if (next) {
+      // wait for the seven owners (a bounded wait: past the bound the walker is flagged and
+      // the elimination goes on, so the workgroup always finishes)
+      const int target = 7 * (np + 1);
+      int it = 0;
+      while (__hip_atomic_load(&staged, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+        if (++it > (1 << 22)) { bad |= 2; break; }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      factor(j0 + PW, pbuf ^ 1);
     }
     __syncthreads();
   }
@@ -499,9 +549,8 @@ __global__ __launch_bounds__(512) void gj_reg_kernel(const Batch<GjbArgs> B) {
   if (wave > 0) {
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
-      const int t = (wave - 1) + 7 * i;
-      if (t >= ntile * ntile) continue;
-      const int I = t / ntile, J = t % ntile;
+      int I, J;
+      if (!tile_ij(i, I, J)) continue;
       const int col = J * 16 + col16;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
