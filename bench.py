@@ -33,6 +33,8 @@ METRIC = "walker-steps/s at Nk=27 M=26, mixed vs FP64 GPU, |ΔE_loc|≤1e-5 Ha/c
 # dense MFMA TFLOP/s, MI355X; BF16-split counts its three BF16 passes per product
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3, "int8x5": 5000.0, "int8x4": 5000.0}
 TOL = 1e-5  # Ha per cell
+# the paths of the counter runs (every kernel class of the FP64, BF16X3 and int8 paths)
+PMC_PATHS = "fp64,bf16x3,bf16x3+int8x4E,bf16x3+int8x5E"
 # path -> (precision of the step contractions, precision of the local energy)
 PATHS = {
     "fp64": ("fp64", "fp64"),
@@ -151,18 +153,28 @@ def reduce_pmc(fetch_csv, write_csv):
     # the Taylor launches are the six nested steps (five write planes, the last the FP64
     # result), L and Lh planes are padded to 32 along g and r
     KP, CP, KPm = 32 * ((N + 31) // 32), 32 * ((C + 31) // 32), 32 * ((m + 31) // 32)
+    # the HS potential reads the half store of L (one slot per (Q, -Q) pair)
+    from paper_2003_09468_amd.binding import ls_slots
+    nq = ls_slots(c["mesh"])
     algo_bf = {
         "taylor": (8.0 * W * N * N + 8.0 * W * n * KP + (5 * 8.0 + 16.0) / 6 * W * N * n,
                    (5 * 8.0 * W * n * KP + 16.0 * W * N * n) / 6),
-        "vhs": (8.0 * (nk * nk * m * m * CP + W * nk * CP), 8.0 * W * N * N),
+        "vhs": (8.0 * (nq * nk * m * m * CP + W * nk * CP), 8.0 * W * N * N),
         "exchange": (8.0 * nk * nk * C * nocc * KPm + 16.0 * W * n * N, 16.0 * nk ** 3 * W),
     }
-    rec = {"workload": "c1: mesh 3x3x3, m=26, nocc=4, nchol=208, 64 walkers (FP64 and "
-                       "BF16X3 paths)",
+    # the int8 exchanges read ND of the five stored digits per element of the [Re | Im] rows
+    # (2m padded to 64) and the row exponents, and Gh
+    KP8 = 64 * ((2 * m + 63) // 64)
+    algo_i8 = {nd: {"exchange": (nk * nk * C * nocc * (nd * KP8 + 4.0) + 16.0 * W * n * N,
+                                 16.0 * nk ** 3 * W)} for nd in (4, 5)}
+    rec = {"workload": "c1: mesh 3x3x3, m=26, nocc=4, nchol=208, 64 walkers (FP64, BF16X3 "
+                       "and int8-split energy paths)",
            "fetch_scale": fs, "write_scale": ws, "kernels": {}}
     for prec, names, alg in (("fp64", {k: v.format(t="double") for k, v in KERNEL_NAMES.items()},
                               algo),
-                             ("bf16x3", KERNEL_NAMES_BF16X3, algo_bf)):
+                             ("bf16x3", KERNEL_NAMES_BF16X3, algo_bf),
+                             ("int8x4", {"exchange": "exchange_int8_kernel<1, 4>"}, algo_i8[4]),
+                             ("int8x5", {"exchange": "exchange_int8_kernel<1, 5>"}, algo_i8[5])):
         for k, pat in names.items():
             fv = [x for name, x in fetch if pat in name]
             wv = [x for name, x in write if pat in name]
@@ -178,15 +190,18 @@ def reduce_pmc(fetch_csv, write_csv):
             rec["kernels"][f"{k}_{prec}"] = e
     base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
     json.dump(rec, open(os.path.join(base, "traffic_c1.json"), "w"), indent=1)
-    lines = ["# HBM traffic per launch, c1 FP64 and BF16X3 paths (rocprofv3 counters)", "",
+    lines = ["# HBM traffic per launch, c1 FP64, BF16X3 and int8-split energy paths "
+             "(rocprofv3 counters)", "",
              "Commands (repository root, on the MI355X; each counter in its own run):", "",
              "```", "cd /tmp && export TMPDIR=/tmp && cd \"$GRAFT_REPO_ROOT\"",
              "timeout -s KILL 400 rocprofv3 --pmc FETCH_SIZE --output-format csv "
              "-d gpurun_out/pmc_fetch -o run -- \\",
-             "    python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --calib-copy",
+             f"    python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --calib-copy "
+             f"--prec {PMC_PATHS}",
              "timeout -s KILL 400 rocprofv3 --pmc WRITE_SIZE --output-format csv "
              "-d gpurun_out/pmc_write -o run -- \\",
-             "    python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --calib-copy",
+             f"    python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --calib-copy "
+             f"--prec {PMC_PATHS}",
              "python3 bench.py --reduce-pmc gpurun_out/pmc_fetch/run_counter_collection.csv "
              "gpurun_out/pmc_write/run_counter_collection.csv", "```", "",
              f"Scale: the plain 1 GiB device copy (`--calib-copy`) reads as FETCH_SIZE = "
@@ -209,8 +224,11 @@ def reduce_pmc(fetch_csv, write_csv):
               "reads L once and writes vhs; the exchange reads Lh and Gh once.  BF16X3 (8 bytes "
               "per split complex entry): a nested Taylor step reads the complex64 potential, "
               "the walker planes and T_0 (the last step the FP64 T_0) and writes the next "
-              "planes (the last step the FP64 result); the HS potential reads the L planes "
-              "and writes the complex64 potential; the exchange reads the Lh planes and Gh."]
+              "planes (the last step the FP64 result); the HS potential reads the half store of "
+              "the L planes and the combined-field planes and writes the complex64 potential; "
+              "the exchange reads the Lh planes and Gh.  Int8 split: the exchange reads four "
+              "(INT8X4) or five (INT8X5) int8 digits per element of the [Re | Im] rows of Lh "
+              "(2m padded to 64) with their exponents, and Gh."]
     open(os.path.join(base, "traffic_c1.md"), "w").write("\n".join(lines) + "\n")
     print(json.dumps(rec["kernels"], indent=1))
 
@@ -760,6 +778,69 @@ def bench_adjoint(args, torch):
     }
 
 
+def bench_dense(args, torch):
+    """The k-point against the standard (dense) representation of the same system (the
+    comparison of the paper's timing figure, at supercell sizes the dense kernels take:
+    nk m <= 64): meshes 1x1x2, 2x2x1 and 2x2x2 with m = 8, nocc = 2, nchol = 24 per Q and 64
+    walkers.  Both run FP64 blocks of 20 steps + QR + local energy on the same walkers, the
+    dense system with the mapped fields, so both end on the same state."""
+    import numpy as np
+    from synth.kpt_inputs import make_system, make_walkers, make_fields
+    import paper_2003_09468_amd as lib
+    W, nsteps = 64, 20
+    res = {}
+    for mesh in ((1, 1, 2), (2, 2, 1), (2, 2, 2)):
+        s, rng = make_system(mesh, 8, 2, 24, seed=0)
+        U0 = make_walkers(s, W, rng)
+        xs = torch.from_numpy(make_fields(s, W, nsteps, rng)).cuda()
+        p = make_problem(s, U0, lib.PREC_FP64, torch)
+        d = p.dense(torch.from_numpy(s.H1))
+        xds = torch.stack([p.dense_fields(xs[t]) for t in range(nsteps)])
+        U0d = torch.from_numpy(U0).cuda()
+        times, E = {}, {}
+        for name, q, fields in (("kpoint", p, xs), ("dense", d, xds)):
+            Eo = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+            reset(q, U0d)
+            run_block(q, fields, {}, Eo)
+            E[name] = Eo.sum(1).cpu().numpy() / s.nk
+            for _ in range(args.warmup):
+                reset(q, U0d)
+                run_block(q, fields, {}, Eo)
+            torch.cuda.synchronize()
+            t = 0.0
+            for _ in range(max(args.steps, 1)):
+                reset(q, U0d)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                run_block(q, fields, {}, Eo)
+                torch.cuda.synchronize()
+                t += time.perf_counter() - t0
+            times[name] = t / max(args.steps, 1) * 1e3
+        key = "x".join(map(str, mesh))
+        res[key] = {"nk": s.nk, "supercell_orbitals": s.nk * s.m,
+                    "dense_cholesky_vectors": s.nk * s.nchol,
+                    "kpoint_ms_per_block": round(times["kpoint"], 3),
+                    "dense_ms_per_block": round(times["dense"], 3),
+                    "dense_over_kpoint": round(times["dense"] / times["kpoint"], 3),
+                    "max_abs_dE_per_cell": float(np.abs(E["dense"] - E["kpoint"]).max())}
+        log(f"[{key}] k-point {times['kpoint']:.2f} ms, dense {times['dense']:.2f} ms per block; "
+            f"energies after the block differ by {res[key]['max_abs_dE_per_cell']:.2e} Ha/cell")
+        del p, d
+        torch.cuda.empty_cache()
+    last = res["2x2x2"]
+    return {
+        "metric": "block time, k-point vs standard (dense) representation, mesh 2x2x2, m=8",
+        "value": last["dense_over_kpoint"], "unit": "dense/k-point time ratio", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": last["kpoint_ms_per_block"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "meshes 1x1x2, 2x2x1, 2x2x2; m=8, nocc=2, nchol=24 per Q, 64 "
+                               "walkers; one step = one FP64 block of 20 steps + QR + energy "
+                               "in each representation", "path": "fp64"},
+        "paths": res, "kernel_source_hash": kernel_source_hash(),
+    }
+
+
 def bench_c2(args, torch):
     """4x4x4 mesh, m=52, nocc=4, nchol=400, 32 walkers (L: 70.9 GB complex128, streamed to
     the GPU block by block as it is drawn).  The local energy of the initial walkers with
@@ -879,8 +960,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3, help="timed blocks")
     ap.add_argument("--warmup", type=int, default=1, help="untimed blocks")
     ap.add_argument("--config", default="c1",
-                    help="c1 (headline), c0, c2 (4x4x4 energy precisions), c3 (uneven batch modes) or "
-                         "c4 (energy adjoint)")
+                    help="c1 (headline), c0, c2 (4x4x4 energy precisions), c3 (uneven batch modes), "
+                         "c4 (energy adjoint) or dense (k-point vs standard representation)")
     ap.add_argument("--prec", default="all",
                     help="all, or a comma-separated list of paths: " + ", ".join(PATHS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -921,6 +1002,9 @@ def main():
         return
     if args.config == "c4":
         print(json.dumps(bench_adjoint(args, torch)), flush=True)
+        return
+    if args.config == "dense":
+        print(json.dumps(bench_dense(args, torch)), flush=True)
         return
     cfg = config_shapes(args.config)
     log(f"generating {args.config}: {cfg}")

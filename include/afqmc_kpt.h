@@ -206,7 +206,40 @@ typedef struct afqmc_kpt_problem {
                         KP8 = 64 ceil(2m / 64)), followed by the rows' int32 exponents
                         e ([nk][nk][nchol][nocc], s = 2^e); bytes:
                         nk^2 nchol nocc (5 KP8 + 4) */
+  /* spins of the walkers (AFQMC_SPIN_*); 0 for the closed shell */
+  int32_t spin;
 } afqmc_kpt_problem;
+
+/* Spins ("Introduction to AFQMC": the Hamiltonian sums over the spins of both electrons).
+ * AFQMC_SPIN_CLOSED: one determinant serves both spins (the closed shell; nocc electrons
+ * of each spin per k-point).  AFQMC_SPIN_UP / AFQMC_SPIN_DOWN: a collinear walker set with
+ * one determinant per spin, each against its own block-diagonal trial, held as two
+ * problems: the up half at index i of the problem array, the down half at i + 1, in every
+ * call that takes either.  The halves describe one system: equal mesh, m, nchol, nwalk,
+ * prec and dt, the same L pointer, and the same H1 in afqmc_kpt_prepare (the static arrays
+ * derived from L alone, bhalf, L32 and Ls, may be shared or separate); nocc (electrons of
+ * that spin per k-point) and A may differ.  Each half has its own U, Gh, logdet, weight and
+ * status (distinct pointers; the Lh arrays and h1h come from its own trial).  Semantics:
+ *   fields: the down half uses the up half's fields x (its own slot is not read);
+ *   force bias: X = sum over both spins of tr(Lh^s Gh^s) (half the sum of the two
+ *     halves' closed-shell traces), xbar from it; both halves' xbar and X slots hold them;
+ *   propagation: both determinants take the same one- and two-body operators;
+ *   weights: the overlap is det(O_up) det(O_down); the update multiplies both halves'
+ *     weights by the same factor (the phaseless angle of the product's ratio, the up half's
+ *     etrial), writes each half's own logdet and ORs the status bits of either half into
+ *     both, so that weights started equal stay equal;
+ *   energy: E1 and EX summed over the spins, EC = 1/2 sum_{Q,g} X_Q X_-Q of the pair's X;
+ *     both halves' E rows hold the pair's energy;
+ *   adjoint: gGh of each half is dE/dGh of that spin; the down half uses the up half's gE;
+ *   population control: the down half uses the up half's xi, so that the two halves'
+ *     (equal) weights give the same copies.
+ * A problem with an invalid spin value or an unmatched half makes the call return
+ * AFQMC_EINVAL before any HIP call. */
+typedef enum {
+  AFQMC_SPIN_CLOSED = 0,
+  AFQMC_SPIN_UP = 1,
+  AFQMC_SPIN_DOWN = 2
+} afqmc_spin;
 
 /* Workspace (device bytes) the given entry point needs for these problems.
  * bytes: host pointer.  The same workspace may be reused across calls that
@@ -369,6 +402,62 @@ typedef struct afqmc_reblock_level {
  * max_levels) written).  Sums in FP64 in series order.  Needs no device. */
 afqmc_status afqmc_kpt_reblock(const double* x, int64_t n, afqmc_reblock_level* levels,
                                int max_levels, int* nlevels, int* optimal);
+
+/* The standard (dense) representation of the system ("Standard Representation"): one
+ * set of Cholesky vectors of the whole supercell basis, N = nk m orbitals, n = nk nocc
+ * occupied, nk nchol Hermitian vectors.  For every Q whose index does not exceed that of
+ * -Q (increasing Q): Q = -Q gives the nchol supercell operators LL_Q; a pair (Q, -Q) the
+ * 2 nchol vectors (LL_Q + LL_Q^H)/sqrt 2, then i (LL_Q - LL_Q^H)/sqrt 2, which carry the
+ * same two-body integrals and the same V0.  Writes, for a 1x1x1-mesh problem with m = N,
+ * nocc = n, nchol = nk nchol (run through the same entry points):
+ *   Ld:  [1][1][N][N][nk nchol] complex128, Hermitian per vector
+ *   H1d: [1][N][N] complex128, block diagonal of H1 ([nk][m][m] complex128, device)
+ *   Ad:  [1][N][n] complex128, block diagonal of the trial A
+ * Reads L and A of the first problem of p (nprob = 1).  The dense walkers are the k-point
+ * ones unchanged ([nwalk][N][n]). */
+afqmc_status afqmc_kpt_dense_system(const afqmc_kpt_problem* p, int nprob, const void* H1,
+                                    void* Ld, void* H1d, void* Ad, void* stream);
+
+/* The fields of the dense system that give the same HS exponent as the k-point fields x
+ * ([nwalk][nk][nchol][2] float64): for a pair, x_A = (x+_Q + x+_-Q)/sqrt 2 and
+ * x_B = (x-_-Q - x-_Q)/sqrt 2 (an orthogonal change of the Gaussian fields; the other two
+ * directions neither enter the exponent nor carry a force bias); for Q = -Q, x+_Q.
+ *   xd: [nwalk][1][nk nchol][2] float64 out (the minus fields 0: a Hermitian vector has no
+ *   minus potential). */
+afqmc_status afqmc_kpt_dense_fields(const afqmc_kpt_problem* p, int nprob, const double* x,
+                                    double* xd, void* stream);
+
+/* Non-uniform band counts ("k-Point Representation": m is the average number of bands per
+ * k-point).  A system with mk[k] bands at k-point k is the uniform system with m >= max mk
+ * bands per k-point whose extra bands are zero rows and columns of L, H1 and the trial and
+ * zero rows of the walkers: those bands carry no matrix element, the propagator keeps the
+ * walkers' zero rows zero (the identity block of exp(-dt/2 (H1 + V0)), a zero block of the
+ * HS potential), and every overlap, trace and contraction is that of the ragged system.
+ * afqmc_kpt_pad_bands writes the padded arrays from packed ragged ones; every entry point
+ * then runs on the padded problem unchanged.
+ *   p:    one padded problem (nprob = 1); mesh, nk, m, nocc, nchol and nwalk are read, its
+ *         pointers are not; nk <= AFQMC_PAD_MAX_NK
+ *   mk:   [nk] host int32, nocc <= mk[k] <= m
+ *   L_r:  blocks (Q, k), Q-major then k, each [mk[k]][mk[k-Q]][nchol] complex128
+ *   H1_r: blocks k, each [mk[k]][mk[k]] complex128
+ *   A_r:  blocks k, each [mk[k]][nocc] complex128
+ *   U_r:  [nwalk][sum_k mk[k]][nk*nocc] complex128 (rows of k-point k after those of k - 1)
+ *   L, H1, A, U: the padded [nk][nk][m][m][nchol], [nk][m][m], [nk][m][nocc] and
+ *         [nwalk][nk*m][nk*nocc] complex128 outputs, zero beyond the ragged blocks.
+ * All device pointers; an input may be NULL, and its output is then not written. */
+#define AFQMC_PAD_MAX_NK 128
+afqmc_status afqmc_kpt_pad_bands(const afqmc_kpt_problem* p, int nprob, const int32_t* mk,
+                                 const void* L_r, const void* H1_r, const void* A_r,
+                                 const void* U_r, void* L, void* H1, void* A, void* U,
+                                 void* stream);
+
+/* The ragged walkers and half-rotated Green's functions of a padded problem (the inverse of
+ * the walker padding above): U [nwalk][nk*m][nk*nocc] -> U_r [nwalk][sum mk][nk*nocc] and
+ * Gh [nwalk][nk*nocc][nk*m] -> Gh_r [nwalk][nk*nocc][sum mk], complex128 device arrays
+ * (either pair may be NULL).  Same p, nprob and mk rules as afqmc_kpt_pad_bands. */
+afqmc_status afqmc_kpt_unpad_bands(const afqmc_kpt_problem* p, int nprob, const int32_t* mk,
+                                   const void* U, const void* Gh, void* U_r, void* Gh_r,
+                                   void* stream);
 
 /* Packed layout of one per-call buffer for a batch (host).  offsets: host
  * array of nprob + 1 entries; offsets[i] is the byte offset of problem i's

@@ -12,6 +12,10 @@ from .binding import (  # noqa: F401
     KptProblem,
     KptBatch,
     KptGraph,
+    KptSpinPair,
+    SPIN_CLOSED,
+    SPIN_UP,
+    SPIN_DOWN,
     lib,
     library_path,
     PREC_FP64,
@@ -28,6 +32,8 @@ from .binding import (  # noqa: F401
     ENTRIES,
     local_energy,
     reblock,
+    pad_bands,
+    unpad_bands,
     timing_enable,
     timing_read,
     KERNEL_CLASSES,

@@ -50,6 +50,12 @@ WALKER_SINGULAR = 1
 WALKER_NONFINITE = 2
 WALKER_KILLED = 4
 
+# spins of a problem's walkers (afqmc_spin): one determinant for both spins, or the up and
+# down halves of a two-determinant (collinear) walker set, held as consecutive problems
+SPIN_CLOSED = 0
+SPIN_UP = 1
+SPIN_DOWN = 2
+
 PROPAGATE_ORTHO = 1
 PROPAGATE_REDUCED_GH = 4
 STEP_ENERGY = 2
@@ -84,6 +90,10 @@ EXPORTS = [
     "afqmc_kpt_population_control",
     "afqmc_kpt_update_etrial",
     "afqmc_kpt_reblock",
+    "afqmc_kpt_dense_system",
+    "afqmc_kpt_dense_fields",
+    "afqmc_kpt_pad_bands",
+    "afqmc_kpt_unpad_bands",
     "afqmc_kpt_buffer_layout",
     "afqmc_kpt_step",
     "afqmc_kpt_autotune",
@@ -134,6 +144,7 @@ class Problem(ctypes.Structure):
         ("status", ctypes.c_void_p),
         ("etrial", ctypes.c_void_p),
         ("Lh8", ctypes.c_void_p),
+        ("spin", ctypes.c_int32),
     ]
 
 
@@ -171,6 +182,10 @@ def lib():
         "afqmc_kpt_mixed_energy": [P, i, vp, vp, vp],
         "afqmc_kpt_population_control": [P, i, vp, vp, vp, sz, vp],
         "afqmc_kpt_update_etrial": [P, i, vp, ctypes.c_double, vp],
+        "afqmc_kpt_dense_system": [P, i, vp, vp, vp, vp, vp],
+        "afqmc_kpt_dense_fields": [P, i, vp, vp, vp],
+        "afqmc_kpt_pad_bands": [P, i, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+        "afqmc_kpt_unpad_bands": [P, i, vp, vp, vp, vp, vp, vp],
         "afqmc_kpt_reblock": [vp, ctypes.c_int64, vp, i, ctypes.POINTER(i),
                               ctypes.POINTER(i)],
         "afqmc_kpt_buffer_layout": [P, i, i, ctypes.POINTER(sz)],
@@ -252,7 +267,12 @@ class KptProblem:
     L: [nk][nk][m][m][nchol] complex128, A: [nk][m][nocc] complex128 (device tensors).
     """
 
-    def __init__(self, mesh, m, nocc, nchol, nwalk, dt, L, A, prec=PREC_FP64, device="cuda"):
+    def __init__(self, mesh, m, nocc, nchol, nwalk, dt, L, A, prec=PREC_FP64, device="cuda",
+                 spin=SPIN_CLOSED, share=None):
+        """spin: SPIN_CLOSED, or SPIN_UP / SPIN_DOWN for a half of a two-determinant walker
+        set (see KptSpinPair); share: another problem of the same system whose arrays
+        derived from L and H1 alone (L, bhalf, L32, Ls) this one uses instead of its own."""
+        self.spin = int(spin)
         self.mesh = tuple(int(v) for v in mesh)
         self.nk = self.mesh[0] * self.mesh[1] * self.mesh[2]
         self.m, self.nocc, self.nchol, self.nwalk = int(m), int(nocc), int(nchol), int(nwalk)
@@ -261,16 +281,18 @@ class KptProblem:
         self.device = torch.device(device)
         nk, c128 = self.nk, torch.complex128
         kw = dict(device=self.device)
-        self.L = L.to(**kw, dtype=c128).contiguous()
+        self.L = share.L if share is not None else L.to(**kw, dtype=c128).contiguous()
         self.A = A.to(**kw, dtype=c128).contiguous()
         self.Lh = torch.empty((nk, nk, nocc, m, nchol), dtype=c128, **kw)
         self.h1h = torch.empty((nk, nocc, m), dtype=c128, **kw)
-        self.bhalf = torch.empty((nk, m, m), dtype=c128, **kw)
+        self.bhalf = (share.bhalf if share is not None
+                      else torch.empty((nk, m, m), dtype=c128, **kw))
         # complex64 copies: L for the FP32 HS potential, Lh for the FP32 force bias and
         # exchange and for the adjoint of both reduced modes (BF16X3 reads split planes of L)
         sp, ep = step_prec(self.prec), energy_prec(self.prec)
         self.L32 = (torch.empty(self.L.shape, dtype=torch.complex64, **kw)
-                    if sp == PREC_FP32 else None)
+                    if sp == PREC_FP32 and share is None else
+                    (share.L32 if share is not None else None))
         low = (PREC_FP32, PREC_BF16X3)
         self.Lh32 = (torch.empty(self.Lh.shape, dtype=torch.complex64, **kw)
                      if sp in low or ep in low else None)
@@ -283,7 +305,9 @@ class KptProblem:
         if PREC_BF16X3 in (sp, ep):
             kp = 32 * ((m + 31) // 32)
             self.Lhs = torch.empty((nk, nk, nchol, nocc, 4, kp), dtype=torch.int16, **kw)
-        if sp == PREC_BF16X3:
+        if sp == PREC_BF16X3 and share is not None:
+            self.Ls = share.Ls
+        elif sp == PREC_BF16X3:
             cp = 32 * ((nchol + 31) // 32)
             # half store: one slot per time-reversal pair (Q <= -Q), then int32 Q per slot
             nq = ls_slots(self.mesh)
@@ -314,6 +338,7 @@ class KptProblem:
         p.Gh = _ptr(self.Gh if Gh is None else Gh)
         p.logdet, p.weight, p.status = _ptr(self.logdet), _ptr(self.weight), _ptr(self.status)
         p.etrial = _ptr(self.etrial)
+        p.spin = self.spin
         return p
 
     def workspace_bytes(self, entry: str) -> int:
@@ -430,6 +455,36 @@ class KptProblem:
                                            out.data_ptr(), _stream()))
         return out[0]
 
+    def dense(self, H1, prec=None):
+        """The standard (dense) representation of this system as a 1x1x1-mesh problem (same
+        walkers, same Hamiltonian): Cholesky vectors, one-body matrix and trial from
+        afqmc_kpt_dense_system, prepared; the walkers of this problem are copied in."""
+        N, n = self.nk * self.m, self.nk * self.nocc
+        kw = dict(device=self.device, dtype=torch.complex128)
+        Ld = torch.empty((1, 1, N, N, self.nk * self.nchol), **kw)
+        H1d = torch.empty((1, N, N), **kw)
+        Ad = torch.empty((1, N, n), **kw)
+        H1 = H1.to(**kw).contiguous()
+        check("afqmc_kpt_dense_system",
+              lib().afqmc_kpt_dense_system(ctypes.byref(self.struct), 1, H1.data_ptr(),
+                                           Ld.data_ptr(), H1d.data_ptr(), Ad.data_ptr(),
+                                           _stream()))
+        d = KptProblem((1, 1, 1), N, n, self.nk * self.nchol, self.nwalk, self.dt, Ld, Ad,
+                       prec=self.prec if prec is None else prec, device=self.device)
+        d.prepare(H1d)
+        d.set_walkers(self.U, self.weight)
+        return d
+
+    def dense_fields(self, x):
+        """The dense system's fields for the k-point fields x ([nwalk][nk][nchol][2])."""
+        x = x.to(device=self.device, dtype=torch.float64).contiguous()
+        xd = torch.empty((self.nwalk, 1, self.nk * self.nchol, 2), dtype=torch.float64,
+                         device=self.device)
+        check("afqmc_kpt_dense_fields",
+              lib().afqmc_kpt_dense_fields(ctypes.byref(self.struct), 1, x.data_ptr(),
+                                           xd.data_ptr(), _stream()))
+        return xd
+
     def set_etrial(self, value):
         """Energy shift E_T (per supercell) of the projector exp(-dt (H - E_T))."""
         self.etrial.fill_(float(value))
@@ -465,6 +520,54 @@ class KptProblem:
         v = self.vhs(x, xbar, bufs.get("vhs"))
         self.propagate(v, x, xbar, ortho=ortho, reduced_gh=reduced_gh)
         return xbar, v
+
+
+def _band_problem(mesh, m, nocc, nchol, nwalk):
+    p = Problem()
+    p.mesh[0], p.mesh[1], p.mesh[2] = (int(v) for v in mesh)
+    p.nk = p.mesh[0] * p.mesh[1] * p.mesh[2]
+    p.m, p.nocc, p.nchol, p.nwalk = int(m), int(nocc), int(nchol), max(int(nwalk), 1)
+    p.prec, p.dt = 0, 1.0
+    return p
+
+
+def _band_counts(mk):
+    return (ctypes.c_int32 * len(mk))(*[int(v) for v in mk])
+
+
+def pad_bands(mesh, mk, m, nocc, nchol, L_r=None, H1_r=None, A_r=None, U_r=None,
+              device="cuda"):
+    """Uniform arrays with m bands per k-point from packed ragged ones (afqmc_kpt_pad_bands):
+    returns (L, H1, A, U), None for each input not given.  L_r, H1_r, A_r: the flat packed
+    blocks; U_r: [nwalk][sum mk][nk*nocc]."""
+    dev = torch.device(device)
+    nk = int(mesh[0]) * int(mesh[1]) * int(mesh[2])
+    c128 = dict(dtype=torch.complex128, device=dev)
+    ins = [None if t is None else t.to(**c128).contiguous() for t in (L_r, H1_r, A_r, U_r)]
+    nwalk = 1 if ins[3] is None else int(ins[3].shape[0])
+    shapes = [(nk, nk, m, m, nchol), (nk, m, m), (nk, m, nocc), (nwalk, nk * m, nk * nocc)]
+    outs = [None if t is None else torch.empty(sh, **c128) for t, sh in zip(ins, shapes)]
+    p = _band_problem(mesh, m, nocc, nchol, nwalk)
+    check("afqmc_kpt_pad_bands",
+          lib().afqmc_kpt_pad_bands(ctypes.byref(p), 1, _band_counts(mk),
+                                    *[_ptr(t) for t in ins], *[_ptr(t) for t in outs],
+                                    _stream()))
+    return tuple(outs)
+
+
+def unpad_bands(problem, mk, U=None, Gh=None):
+    """Ragged walkers [nwalk][sum mk][n] and half-rotated Green's functions
+    [nwalk][n][sum mk] of a padded problem (afqmc_kpt_unpad_bands)."""
+    M = sum(int(v) for v in mk)
+    n = problem.nk * problem.nocc
+    c128 = dict(dtype=torch.complex128, device=problem.device)
+    Ur = None if U is None else torch.empty((problem.nwalk, M, n), **c128)
+    Gr = None if Gh is None else torch.empty((problem.nwalk, n, M), **c128)
+    p = _band_problem(problem.mesh, problem.m, problem.nocc, problem.nchol, problem.nwalk)
+    check("afqmc_kpt_unpad_bands",
+          lib().afqmc_kpt_unpad_bands(ctypes.byref(p), 1, _band_counts(mk), _ptr(U), _ptr(Gh),
+                                      _ptr(Ur), _ptr(Gr), _stream()))
+    return Ur, Gr
 
 
 class KptBatch:
@@ -572,6 +675,53 @@ class KptBatch:
         check("afqmc_kpt_greens",
               lib().afqmc_kpt_greens(self.arr, self.n, ws.data_ptr(), ws.numel(), _stream()))
 
+    def prepare(self, H1):
+        """afqmc_kpt_prepare of every system with the one-body blocks H1 (equal shapes)."""
+        H1 = H1.to(device=self.device, dtype=torch.complex128).contiguous()
+        ws = self.workspace()
+        check("afqmc_kpt_prepare",
+              lib().afqmc_kpt_prepare(self.arr, self.n, H1.data_ptr(), ws.data_ptr(),
+                                      ws.numel(), _stream()))
+
+    def vbias(self):
+        """Force bias of every system (afqmc_kpt_vbias) into the batch's xbar and X slices."""
+        if getattr(self, "_X", None) is None:
+            self._X = self._alloc("X")
+        ws = self.workspace()
+        check("afqmc_kpt_vbias",
+              lib().afqmc_kpt_vbias(self.arr, self.n, self._xbar.data_ptr(), self._X.data_ptr(),
+                                    ws.data_ptr(), ws.numel(), _stream()))
+
+    def X(self, i):
+        p = self.problems[i]
+        return self._view(self._X, "X", i, torch.complex128, (p.nwalk, p.nk, p.nchol))
+
+    def local_energy(self):
+        """Local energy of every system (afqmc_kpt_energy) into the batch's energy slices."""
+        ws = self.workspace()
+        check("afqmc_kpt_energy",
+              lib().afqmc_kpt_energy(self.arr, self.n, self._E.data_ptr(), ws.data_ptr(),
+                                     ws.numel(), _stream()))
+
+    def energy_backward(self, gEs):
+        """dE/dGh of every system (afqmc_kpt_energy_backward) for the per-walker cotangents
+        gEs[i] ([nwalk] complex128, None for ones); returns one gradient view per system."""
+        gE = self._alloc("gE")
+        for i, g in enumerate(gEs):
+            p = self.problems[i]
+            v = self._view(gE, "gE", i, torch.complex128, (p.nwalk,))
+            if g is None:
+                v.fill_(1.0)
+            else:
+                v.copy_(g.resolve_conj().to(device=self.device, dtype=torch.complex128))
+        out = self._alloc("gGh")
+        ws = self.workspace()
+        check("afqmc_kpt_energy_backward",
+              lib().afqmc_kpt_energy_backward(self.arr, self.n, gE.data_ptr(), out.data_ptr(),
+                                              ws.data_ptr(), ws.numel(), _stream()))
+        return [self._view(out, "gGh", i, torch.complex128, tuple(p.Gh.shape))
+                for i, p in enumerate(self.problems)]
+
     def step(self, fields, ortho=False, energy=False):
         """Run the packed fields' nsteps steps of every system (afqmc_kpt_step)."""
         raw, nsteps = fields
@@ -591,6 +741,32 @@ class KptBatch:
     def graph(self, fields, ortho=False, energy=False):
         """Capture the step block over these packed fields (refresh them between launches)."""
         return KptGraph(self, fields, ortho, energy)
+
+
+class KptSpinPair(KptBatch):
+    """Collinear walkers with one determinant per spin (afqmc_spin): one system, held as
+    the up half (nocc_up electrons of spin up per k-point, trial A_up) followed by the down
+    half (nocc_dn, A_dn), which shares L and the arrays derived from L and H1.  Every entry
+    of the batch couples the halves: one field per walker, the force bias and the energy of
+    both spins, one weight per walker (kept equal in both halves)."""
+
+    def __init__(self, mesh, m, nocc_up, nocc_dn, nchol, nwalk, dt, L, A_up, A_dn,
+                 prec=PREC_FP64, device="cuda"):
+        up = KptProblem(mesh, m, nocc_up, nchol, nwalk, dt, L, A_up, prec=prec, device=device,
+                        spin=SPIN_UP)
+        dn = KptProblem(mesh, m, nocc_dn, nchol, nwalk, dt, None, A_dn, prec=prec,
+                        device=device, spin=SPIN_DOWN, share=up)
+        super().__init__([up, dn])
+        self.up, self.dn = up, dn
+
+    def set_walkers(self, U_up, U_dn, weight=None):
+        self.up.set_walkers(U_up, weight)
+        self.dn.set_walkers(U_dn, weight)
+
+    def step_fields(self, x):
+        """Packed fields of one walker set ([nsteps][W][nk][C][2]) for step()/graph(); the
+        down half's slot is not read, so it is left as a copy."""
+        return self.fields([x, x])
 
 
 class KptGraph:

@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libafqmc_kpt.so")
 SOURCES = ["abi.hip", "greens.hip", "fields.hip", "propagate.hip", "energy.hip", "prepare.hip",
-           "timing.hip", "tune.hip", "walkers.hip"]
+           "timing.hip", "tune.hip", "walkers.hip", "dense.hip", "spin.hip",
+           "bands.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

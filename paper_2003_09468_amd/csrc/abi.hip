@@ -22,6 +22,10 @@ hipError_t run_update_etrial(const afqmc_kpt_problem* p, int nprob, const void* 
                              double blend, hipStream_t s);
 int reblock_host(const double* x, int64_t n, afqmc_reblock_level* levels, int max_levels,
                  int* optimal);
+hipError_t run_dense_system(const afqmc_kpt_problem& p, const void* H1, void* Ld, void* H1d,
+                            void* Ad, hipStream_t s);
+hipError_t run_dense_fields(const afqmc_kpt_problem& p, const double* x, double* xd,
+                            hipStream_t s);
 
 size_t ws_bytes_entry(const afqmc_kpt_problem& p0, int entry) {
   // the step entry sizes each of its stages in that stage's precision
@@ -149,6 +153,31 @@ afqmc_status check_fields(const afqmc_kpt_problem& p, unsigned need) {
   return AFQMC_OK;
 }
 
+// Two-determinant walkers: every up half directly followed by its down half, the two
+// describing one system (sizes but nocc, precision, time step, the L pointer), with walker
+// arrays of their own.
+afqmc_status check_spins(const afqmc_kpt_problem* p, int nprob) {
+  auto same = [](const void* a, const void* b) { return a && a == b; };
+  for (int i = 0; i < nprob; ++i) {
+    const int sp = p[i].spin;
+    if (sp < AFQMC_SPIN_CLOSED || sp > AFQMC_SPIN_DOWN) return AFQMC_EINVAL;
+    if (sp == AFQMC_SPIN_DOWN && (i == 0 || p[i - 1].spin != AFQMC_SPIN_UP)) return AFQMC_EINVAL;
+    if (sp != AFQMC_SPIN_UP) continue;
+    if (i + 1 >= nprob || p[i + 1].spin != AFQMC_SPIN_DOWN) return AFQMC_EINVAL;
+    const afqmc_kpt_problem &a = p[i], &b = p[i + 1];
+    for (int d = 0; d < 3; ++d)
+      if (a.mesh[d] != b.mesh[d]) return AFQMC_EINVAL;
+    if (a.m != b.m || a.nchol != b.nchol || a.nwalk != b.nwalk || a.prec != b.prec ||
+        a.dt != b.dt || a.L != b.L)
+      return AFQMC_EINVAL;
+    if (same(a.U, b.U) || same(a.Gh, b.Gh) || same(a.logdet, b.logdet) ||
+        same(a.weight, b.weight) || same(a.status, b.status) || same(a.Lh, b.Lh) ||
+        same(a.h1h, b.h1h))
+      return AFQMC_EINVAL;
+  }
+  return AFQMC_OK;
+}
+
 // need: the arrays the entry's stages read, checked in the precision of the step (energy =
 // false) or of the local energy (energy = true).
 afqmc_status check_problems(const afqmc_kpt_problem* p, int nprob, unsigned need,
@@ -159,7 +188,7 @@ afqmc_status check_problems(const afqmc_kpt_problem* p, int nprob, unsigned need
     AFQMC_TRY(check_dims(p[i]));
     AFQMC_TRY(check_fields(stage_view(p[i], energy), need));
   }
-  return AFQMC_OK;
+  return check_spins(p, nprob);
 }
 
 // The int8-split energies read the digits of Lh.
@@ -243,6 +272,11 @@ std::vector<Job> make_jobs(const afqmc_kpt_problem* p, int nprob, int entry, voi
     j.E = slice(b.E, p, nprob, AFQMC_BUF_ENERGY, i, off);
     j.gE = slice(b.gE, p, nprob, AFQMC_BUF_GE, i, off);
     j.gGh = slice(b.gGh, p, nprob, AFQMC_BUF_GGH, i, off);
+    // the down half of a two-determinant pair takes the up half's fields and cotangents
+    if (p[i].spin == AFQMC_SPIN_DOWN) {
+      j.x = jobs[i - 1].x;
+      j.gE = jobs[i - 1].gE;
+    }
   }
   return jobs;
 }
@@ -506,13 +540,17 @@ afqmc_status afqmc_kpt_population_control(const afqmc_kpt_problem* p, int nprob,
                                           size_t ws_bytes, void* stream) {
   AFQMC_TRY(check_problems(p, nprob, N_U | N_GH | N_LOGDET | N_WEIGHT | N_STATUS));
   if (!xi) return AFQMC_ENULL;
+  // the down half of a two-determinant pair draws with the up half's xi (equal weights and
+  // equal xi give both halves the same copies)
+  std::vector<double> xs(xi, xi + nprob);
   for (int i = 0; i < nprob; ++i) {
-    if (!(xi[i] >= 0.0 && xi[i] < 1.0)) return AFQMC_EINVAL;
+    if (p[i].spin == AFQMC_SPIN_DOWN) xs[i] = xs[i - 1];
+    if (!(xs[i] >= 0.0 && xs[i] < 1.0)) return AFQMC_EINVAL;
     if (parent && parent[i] && misaligned(parent[i], 4)) return AFQMC_EALIGN;
   }
   AFQMC_TRY(check_ws(p, nprob, AFQMC_ENTRY_POPULATION, ws, ws_bytes));
   AFQMC_TRY(check_device());
-  return hip_status(run_population(p, nprob, xi, parent, ws, (hipStream_t)stream));
+  return hip_status(run_population(p, nprob, xs.data(), parent, ws, (hipStream_t)stream));
 }
 
 afqmc_status afqmc_kpt_update_etrial(const afqmc_kpt_problem* p, int nprob, const void* Emix,
@@ -534,6 +572,78 @@ afqmc_status afqmc_kpt_reblock(const double* x, int64_t n, afqmc_reblock_level* 
     if (!isfinite(x[i])) return AFQMC_EINVAL;
   *nlevels = reblock_host(x, n, levels, max_levels, optimal);
   return AFQMC_OK;
+}
+
+afqmc_status afqmc_kpt_dense_system(const afqmc_kpt_problem* p, int nprob, const void* H1,
+                                    void* Ld, void* H1d, void* Ad, void* stream) {
+  AFQMC_TRY(check_problems(p, nprob, N_LD | N_A));
+  if (nprob != 1) return AFQMC_EINVAL;
+  AFQMC_TRY(check_ptr(H1, 16));
+  AFQMC_TRY(check_ptr(Ld, 16));
+  AFQMC_TRY(check_ptr(H1d, 16));
+  AFQMC_TRY(check_ptr(Ad, 16));
+  AFQMC_TRY(check_device());
+  return hip_status(run_dense_system(p[0], H1, Ld, H1d, Ad, (hipStream_t)stream));
+}
+
+afqmc_status afqmc_kpt_dense_fields(const afqmc_kpt_problem* p, int nprob, const double* x,
+                                    double* xd, void* stream) {
+  AFQMC_TRY(check_problems(p, nprob, 0));
+  if (nprob != 1) return AFQMC_EINVAL;
+  AFQMC_TRY(check_ptr(x, 8));
+  AFQMC_TRY(check_ptr(xd, 8));
+  AFQMC_TRY(check_device());
+  return hip_status(run_dense_fields(p[0], x, xd, (hipStream_t)stream));
+}
+
+}  // extern "C"
+
+namespace {
+
+// The padded problem and band counts of afqmc_kpt_pad_bands / afqmc_kpt_unpad_bands.
+afqmc_status check_bands(const afqmc_kpt_problem* p, int nprob, const int32_t* mk) {
+  if (!p || !mk) return AFQMC_ENULL;
+  if (nprob != 1) return AFQMC_EINVAL;
+  AFQMC_TRY(check_dims(p[0]));
+  if (p[0].nk > AFQMC_PAD_MAX_NK) return AFQMC_EUNSUPPORTED;
+  for (int k = 0; k < p[0].nk; ++k)
+    if (mk[k] < p[0].nocc || mk[k] > p[0].m) return AFQMC_EINVAL;
+  return AFQMC_OK;
+}
+
+// An input given requires its output.
+afqmc_status check_pair_ptr(const void* in, const void* out) {
+  if (!in) return AFQMC_OK;
+  AFQMC_TRY(check_ptr(in, 16));
+  return check_ptr(out, 16);
+}
+
+}  // namespace
+
+extern "C" {
+
+afqmc_status afqmc_kpt_pad_bands(const afqmc_kpt_problem* p, int nprob, const int32_t* mk,
+                                 const void* L_r, const void* H1_r, const void* A_r,
+                                 const void* U_r, void* L, void* H1, void* A, void* U,
+                                 void* stream) {
+  AFQMC_TRY(check_bands(p, nprob, mk));
+  AFQMC_TRY(check_pair_ptr(L_r, L));
+  AFQMC_TRY(check_pair_ptr(H1_r, H1));
+  AFQMC_TRY(check_pair_ptr(A_r, A));
+  AFQMC_TRY(check_pair_ptr(U_r, U));
+  AFQMC_TRY(check_device());
+  return hip_status(run_pad_bands(p[0], mk, L_r, H1_r, A_r, U_r, L, H1, A, U,
+                                  (hipStream_t)stream));
+}
+
+afqmc_status afqmc_kpt_unpad_bands(const afqmc_kpt_problem* p, int nprob, const int32_t* mk,
+                                   const void* U, const void* Gh, void* U_r, void* Gh_r,
+                                   void* stream) {
+  AFQMC_TRY(check_bands(p, nprob, mk));
+  AFQMC_TRY(check_pair_ptr(U, U_r));
+  AFQMC_TRY(check_pair_ptr(Gh, Gh_r));
+  AFQMC_TRY(check_device());
+  return hip_status(run_unpad_bands(p[0], mk, U, Gh, U_r, Gh_r, (hipStream_t)stream));
 }
 
 afqmc_status afqmc_kpt_buffer_layout(const afqmc_kpt_problem* p, int nprob, int buf,

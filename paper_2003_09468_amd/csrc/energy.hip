@@ -1120,7 +1120,15 @@ hipError_t run_energy(const Job* jobs, int n, hipStream_t s) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  if (!has_pairs(jobs, n)) return hipSuccess;
+  // two-determinant walkers: the pair's energy from both halves' closed-shell parts
+  std::vector<void*> X(n);
+  for (int q = 0; q < n; ++q) {
+    Carve cv(jobs[q].ws);
+    void *parts, *xpart;
+    carve_energy(cv, jobs[q].p, &X[q], &parts, &xpart);
+  }
+  return run_spin_energy(jobs, n, X.data(), s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1469,20 +1477,39 @@ static hipError_t launch_bwd(const Job* jobs, int n, void* const* X, hipStream_t
 }
 
 hipError_t run_energy_backward(const Job* jobs, int n, hipStream_t s) {
+  std::vector<void*> X(n), parts(n);
+  for (int q = 0; q < n; ++q) {
+    Carve cv(jobs[q].ws);
+    carve_backward(cv, jobs[q].p, &X[q], &parts[q]);
+  }
+  // the traces of every problem first: a two-determinant pair's Coulomb term needs both
+  // halves' (the pair's X, the mean of the two closed-shell traces, in both halves' slots)
   for (int c0 = 0; c0 < n; c0 += AFQMC_MAXP) {
     const int c = (n - c0 < AFQMC_MAXP) ? n - c0 : AFQMC_MAXP;
-    const Job* J = jobs + c0;
-    void *X[AFQMC_MAXP], *parts[AFQMC_MAXP];
-    for (int q = 0; q < c; ++q) {
-      Carve cv(J[q].ws);
-      carve_backward(cv, J[q].p, &X[q], &parts[q]);
-    }
-    hipError_t e = launch_cholesky_trace(J, c, X, nullptr, parts, s);
-    if (e != hipSuccess) return e;
-    e = launch_bwd(J, c, X, s);
+    const hipError_t e = launch_cholesky_trace(jobs + c0, c, X.data() + c0, nullptr,
+                                               parts.data() + c0, s);
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  const bool pairs = has_pairs(jobs, n);
+  if (pairs) {
+    std::vector<double*> a, b;
+    std::vector<int64_t> cnt;
+    for (int i = 0; i + 1 < n; ++i) {
+      if (jobs[i].p.spin != AFQMC_SPIN_UP) continue;
+      a.push_back((double*)X[i]);
+      b.push_back((double*)X[i + 1]);
+      cnt.push_back(2 * (int64_t)jobs[i].p.nwalk * jobs[i].p.nk * jobs[i].p.nchol);
+    }
+    const hipError_t e = run_pair_mean(a.data(), b.data(), cnt.data(), (int)a.size(), s);
+    if (e != hipSuccess) return e;
+  }
+  for (int c0 = 0; c0 < n; c0 += AFQMC_MAXP) {
+    const int c = (n - c0 < AFQMC_MAXP) ? n - c0 : AFQMC_MAXP;
+    const hipError_t e = launch_bwd(jobs + c0, c, X.data() + c0, s);
+    if (e != hipSuccess) return e;
+  }
+  // each half's closed-shell adjoint with the pair's X is twice that spin's derivative
+  return pairs ? run_spin_adjoint_scale(jobs, n, s) : hipSuccess;
 }
 
 }  // namespace afqmc

@@ -381,7 +381,8 @@ hipError_t run_vbias(const Job* jobs, int n, hipStream_t s) {
     hipError_t e = launch_cholesky_trace(jobs + c0, c, X, xb, parts, s);
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  // two-determinant walkers: the pair's force bias from both halves' traces
+  return run_spin_fields(jobs, n, s);
 }
 
 hipError_t tune_vbias(const Job* jobs, int n, hipStream_t s) {

@@ -983,6 +983,8 @@ hipError_t run_greens(const Job* jobs, int n, bool write_logdet_new_only, hipStr
 // Hybrid phaseless weight update, one workgroup per walker:
 //   log I = 2 (logdet' - logdet) + sum_{Q,g,+/-} (x xbar - xbar^2/2),
 //   dtheta = arg exp(2 (logdet' - logdet)), w <- |I| max(0, cos dtheta) w.
+// A two-determinant walker (one per spin) takes the sum of the two spins' log-overlap
+// changes in place of twice one, and writes the same weight and status to both halves.
 struct WeightArgs {
   int64_t nf;                    // nk * nchol * 2 field components per walker
   const double* x;               // [W][nf]
@@ -993,6 +995,11 @@ struct WeightArgs {
   int* status;                   // [W]
   const double* etrial;          // [1] E_T per supercell, or null (no shift)
   double dt;
+  // the down half of a two-determinant walker set (null for one determinant)
+  cpx<double>* logdet2;
+  const cpx<double>* logdet2_new;
+  double* weight2;
+  int* status2;
 };
 
 __global__ __launch_bounds__(256) void weight_kernel(const Batch<WeightArgs> B) {
@@ -1039,13 +1046,24 @@ __global__ __launch_bounds__(256) void weight_kernel(const Batch<WeightArgs> B) 
   }
   if (tid == 0) {
     const cpx<double> l0 = logdet[w], l1 = logdet_new[w];
-    const double lrr = 2.0 * (l1.re - l0.re), lri = 2.0 * (l1.im - l0.im);
+    cpx<double>* const ld2 = B.a[pb].logdet2;
+    cpx<double> m1{0.0, 0.0};
+    double lrr, lri;
+    if (ld2) {
+      const cpx<double> m0 = ld2[w];
+      m1 = B.a[pb].logdet2_new[w];
+      lrr = (l1.re - l0.re) + (m1.re - m0.re);
+      lri = (l1.im - l0.im) + (m1.im - m0.im);
+    } else {
+      lrr = 2.0 * (l1.re - l0.re);
+      lri = 2.0 * (l1.im - l0.im);
+    }
     // the projector's energy shift exp(dt E_T) joins the modulus of I
     const double* et = B.a[pb].etrial;
     const double lIr = lrr + sr[0] + (et ? B.a[pb].dt * et[0] : 0.0);
     const double dth = atan2(sin(lri), cos(lri));
     const double c = cos(dth);
-    int st = status[w];
+    int st = status[w] | (ld2 ? B.a[pb].status2[w] : 0);
     double wn = weight[w];
     if (st & (AFQMC_WALKER_SINGULAR | AFQMC_WALKER_NONFINITE)) {
       wn = 0.0;
@@ -1057,23 +1075,48 @@ __global__ __launch_bounds__(256) void weight_kernel(const Batch<WeightArgs> B) 
     weight[w] = wn;
     status[w] = st;
     logdet[w] = l1;
+    if (ld2) {
+      B.a[pb].weight2[w] = wn;
+      B.a[pb].status2[w] = st;
+      ld2[w] = m1;
+    }
   }
 }
 
 hipError_t launch_weights(const Job* jobs, int n, hipStream_t s) {
   TimedScope ts(KC_WEIGHTS, s);
-  for (int c0 = 0; c0 < n; c0 += AFQMC_MAXP) {
-    const int c = (n - c0 < AFQMC_MAXP) ? n - c0 : AFQMC_MAXP;
+  // one entry per closed-shell problem and per two-determinant pair (its up half)
+  std::vector<int> ids;
+  for (int i = 0; i < n; ++i)
+    if (jobs[i].p.spin != AFQMC_SPIN_DOWN) ids.push_back(i);
+  const int ne = (int)ids.size();
+  for (int c0 = 0; c0 < ne; c0 += AFQMC_MAXP) {
+    const int c = (ne - c0 < AFQMC_MAXP) ? ne - c0 : AFQMC_MAXP;
     Batch<WeightArgs> B;
     B.nprob = c;
     long long cnt[AFQMC_MAXP];
     for (int q = 0; q < c; ++q) {
-      const Job& j = jobs[c0 + q];
+      const int i = ids[c0 + q];
+      const Job& j = jobs[i];
       const afqmc_kpt_problem& p = j.p;
       Carve cv(j.ws);
       GreensWs g;
       carve_greens(cv, dims_of(p), g);
       WeightArgs& a = B.a[q];
+      a.logdet2 = nullptr;
+      a.logdet2_new = nullptr;
+      a.weight2 = nullptr;
+      a.status2 = nullptr;
+      if (p.spin == AFQMC_SPIN_UP) {
+        const Job& d = jobs[i + 1];
+        Carve cd(d.ws);
+        GreensWs gd;
+        carve_greens(cd, dims_of(d.p), gd);
+        a.logdet2 = (cpx<double>*)d.p.logdet;
+        a.logdet2_new = (const cpx<double>*)gd.logdet_new;
+        a.weight2 = d.p.weight;
+        a.status2 = d.p.status;
+      }
       a.nf = (int64_t)p.nk * p.nchol * 2;
       a.x = j.x;
       a.xbar = (const cpx<double>*)j.xbar;

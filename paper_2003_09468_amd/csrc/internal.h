@@ -8,6 +8,7 @@
 
 #include <functional>
 #include <string>
+#include <vector>
 
 #include "../../include/afqmc_kpt.h"
 #include "batch.h"
@@ -137,6 +138,25 @@ hipError_t run_ortho(const Job* jobs, int n, hipStream_t s);
 hipError_t run_energy(const Job* jobs, int n, hipStream_t s);
 hipError_t run_energy_backward(const Job* jobs, int n, hipStream_t s);
 hipError_t run_mixed_energy(const Job* jobs, int n, void* Emix, hipStream_t s);
+
+// Two-determinant walkers (AFQMC_SPIN_UP at job i, AFQMC_SPIN_DOWN at i + 1): the couplings
+// between the halves' closed-shell stages.  run_spin_fields: xbar and X of each pair to the
+// mean of the halves' (after the force bias); run_spin_energy: the pair's energy into both
+// halves' rows from their closed-shell energies and traces X[job]; run_pair_mean: a = b =
+// (a + b) / 2 over n[i] doubles; run_spin_adjoint_scale: gGh of every half times 1/2.
+// Band padding (bands.hip): padded uniform arrays from packed ragged ones, and back.
+hipError_t run_pad_bands(const afqmc_kpt_problem& p, const int32_t* mk, const void* Lr,
+                         const void* H1r, const void* Ar, const void* Ur, void* L, void* H1,
+                         void* A, void* U, hipStream_t s);
+hipError_t run_unpad_bands(const afqmc_kpt_problem& p, const int32_t* mk, const void* U,
+                           const void* Gh, void* Ur, void* Ghr, hipStream_t s);
+
+bool has_pairs(const Job* jobs, int n);
+hipError_t run_pair_mean(double* const* a, double* const* b, const int64_t* n, int cnt,
+                         hipStream_t s);
+hipError_t run_spin_fields(const Job* jobs, int n, hipStream_t s);
+hipError_t run_spin_energy(const Job* jobs, int n, void* const* X, hipStream_t s);
+hipError_t run_spin_adjoint_scale(const Job* jobs, int n, hipStream_t s);
 
 // Kernels shared across translation units.  launch_cholesky_trace writes X (and xbar when
 // requested) of every job; parts are the per-job split-K slices.

@@ -13,4 +13,10 @@ from .kpt_inputs import (  # noqa: F401
     make_walkers,
     make_fields,
     config_shapes,
+    make_spin_trial,
+    spin_view,
+    RaggedSystem,
+    make_ragged_system,
+    make_ragged_walkers,
+    pack_ragged,
 )

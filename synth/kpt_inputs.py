@@ -204,3 +204,110 @@ def make_config(name: str, walkers: str = "blockdiag", trial: str = "identity"):
     U = make_walkers(s, c["nwalk"], rng, kind=walkers)
     x = make_fields(s, c["nwalk"], max(c["nsteps"], 1), rng)
     return s, U, x
+
+
+def make_spin_trial(sysobj: KptSystem, n_dn: int, rng: np.random.Generator,
+                    mix: float = 0.3) -> np.ndarray:
+    """Down-spin trial orbitals A_dn[k] (m x n_dn) of a collinear spin-polarised trial whose
+    up-spin orbitals are sysobj.A: per k, the Q factor of the first min(n_dn, nocc) up-spin
+    columns (zero columns beyond) plus mix * CN(0, 1) of shape (m, n_dn)."""
+    nk, m, nocc = sysobj.nk, sysobj.m, sysobj.nocc
+    if n_dn > m:
+        raise ValueError("n_dn must not exceed m")
+    A = np.empty((nk, m, n_dn), dtype=np.complex128)
+    c = min(n_dn, nocc)
+    for k in range(nk):
+        B = np.zeros((m, n_dn), dtype=np.complex128)
+        B[:, :c] = sysobj.A[k][:, :c]
+        q, _ = np.linalg.qr(B + mix * _cn(rng, (m, n_dn)))
+        A[k] = q
+    return A
+
+
+def spin_view(sysobj: KptSystem, A_spin: np.ndarray) -> KptSystem:
+    """The same system with another spin's trial orbitals (for make_walkers)."""
+    return KptSystem(mesh=sysobj.mesh, m=sysobj.m, nocc=A_spin.shape[2], nchol=sysobj.nchol,
+                     dt=sysobj.dt, H1=sysobj.H1, L=sysobj.L, A=A_spin, seed=sysobj.seed,
+                     extra=sysobj.extra)
+
+
+@dataclass
+class RaggedSystem:
+    """A k-point system with mk[k] bands at k (non-uniform band counts).
+
+    H1[k]: (mk[k], mk[k]); L[Q][k]: (mk[k], mk[k-Q], nchol); A[k]: (mk[k], nocc)."""
+    mesh: tuple
+    mk: tuple
+    nocc: int
+    nchol: int
+    dt: float
+    H1: list
+    L: list
+    A: list
+    seed: int = 0
+
+    @property
+    def nk(self) -> int:
+        return int(np.prod(self.mesh))
+
+
+def make_ragged_system(mesh, mk, nocc, nchol, seed=0, dt=DT,
+                       rng: np.random.Generator | None = None):
+    """The generator of make_system with mk[k] bands at k: H1[k] diag(linspace(-1, 2,
+    mk[k])) plus the off-diagonal part of (C + C^H)/2; L blocks of shape
+    (mk[k], mk[k-Q], nchol) drawn with their time-reversal partners as in make_system
+    (scale exp(-g/6)/sqrt(max mk)); random trial orbitals (Q factor of CN(0,1) (mk[k], nocc))."""
+    mesh = tuple(int(v) for v in mesh)
+    nk = int(np.prod(mesh))
+    mk = tuple(int(v) for v in mk)
+    if len(mk) != nk or min(mk) < nocc:
+        raise ValueError("need nk band counts, each at least nocc")
+    if rng is None:
+        rng = np.random.Generator(np.random.PCG64(seed))
+    H1 = []
+    for k in range(nk):
+        m = mk[k]
+        c = 0.05 * _cn(rng, (m, m))
+        h = 0.5 * (c + c.conj().T)
+        np.fill_diagonal(h, 0.0)
+        H1.append(np.diag(np.linspace(-1.0, 2.0, m)) + h)
+    scale = np.exp(-np.arange(nchol) / 6.0) / np.sqrt(max(mk))
+    L = [[None] * nk for _ in range(nk)]
+    for Q in range(nk):
+        for k in range(nk):
+            if L[Q][k] is not None:
+                continue
+            pQ, pk = _partner(Q, k, mesh)  # pk = k - Q
+            z = _cn(rng, (mk[k], mk[pk], nchol))
+            if (pQ, pk) == (Q, k):
+                L[Q][k] = 0.5 * (z + z.conj().transpose(1, 0, 2)) * scale
+            else:
+                L[Q][k] = z * scale
+                L[pQ][pk] = L[Q][k].conj().transpose(1, 0, 2)
+    A = []
+    for k in range(nk):
+        q, _ = np.linalg.qr(_cn(rng, (mk[k], nocc)))
+        A.append(q)
+    return RaggedSystem(mesh=mesh, mk=mk, nocc=nocc, nchol=nchol, dt=dt, H1=H1, L=L, A=A,
+                        seed=seed), rng
+
+
+def make_ragged_walkers(rs: RaggedSystem, nwalk: int, rng: np.random.Generator):
+    """Dense walkers U[w] of shape (sum mk, nk*nocc): QR of a CN(0,1) matrix."""
+    M, n = sum(rs.mk), rs.nk * rs.nocc
+    U = np.empty((nwalk, M, n), dtype=np.complex128)
+    for w in range(nwalk):
+        q, _ = np.linalg.qr(_cn(rng, (M, n)))
+        U[w] = q
+    return U
+
+
+def pack_ragged(rs: RaggedSystem, U=None):
+    """The packed layouts of the band-padding entry: L blocks (Q-major, then k) of
+    (mk[k], mk[k-Q], nchol), H1 blocks (mk[k], mk[k]), A blocks (mk[k], nocc), each flat
+    and concatenated; U as given ([nwalk][sum mk][nk*nocc])."""
+    nk = rs.nk
+    Lr = np.concatenate([rs.L[Q][k].reshape(-1) for Q in range(nk) for k in range(nk)])
+    Hr = np.concatenate([h.reshape(-1) for h in rs.H1])
+    Ar = np.concatenate([a.reshape(-1) for a in rs.A])
+    return Lr, Hr, Ar, (None if U is None else np.ascontiguousarray(U))

@@ -593,3 +593,102 @@ def test_half_store_slots(mesh):
     assert B.ls_slots(mesh) == brute
     pairs = sum(1 for Q in range(len(negq)) if Q < negq[Q])
     assert brute == pairs + sum(1 for Q in range(len(negq)) if Q == negq[Q])
+
+
+# ---------------------------------------------------------------------------
+# two-determinant (collinear) walkers
+# ---------------------------------------------------------------------------
+
+def spin_pair():
+    """A valid up/down pair: one system (same L), own walker arrays, different nocc."""
+    a, b = good_problem(), good_problem()
+    a.spin, b.spin = 1, 2
+    b.nocc = 3
+    addr = 0x1000000
+    for name in ("A", "Lh", "h1h", "Lh32", "U", "Gh", "logdet", "weight", "status"):
+        setattr(b, name, addr)
+        addr += 0x10000
+    return (B.Problem * 2)(a, b)
+
+
+def test_spin_pair_validation(L):
+    from tests.conftest import gpu_available
+    ws = ctypes.c_void_p(0x10000000)
+    g = L.afqmc_kpt_greens
+    if not gpu_available():
+        # valid: the device check is the first failure
+        assert g(spin_pair(), 2, ws, 1 << 40, None) == -5
+    for mutate in (
+            lambda a: setattr(a[0], "spin", 3),            # no such spin
+            lambda a: setattr(a[0], "spin", -1),
+            lambda a: setattr(a[1], "spin", 0),            # up half without its down half
+            lambda a: setattr(a[0], "spin", 2),            # down half first
+            lambda a: setattr(a[1], "m", 20),              # different systems
+            lambda a: setattr(a[1], "nchol", 100),
+            lambda a: setattr(a[1], "nwalk", 32),
+            lambda a: setattr(a[1], "prec", 1),
+            lambda a: setattr(a[1], "dt", 0.01),
+            lambda a: setattr(a[1], "L", 0x7770000),
+            lambda a: setattr(a[1], "U", a[0].U),          # shared walker arrays
+            lambda a: setattr(a[1], "weight", a[0].weight),
+            lambda a: setattr(a[1], "logdet", a[0].logdet),
+            lambda a: setattr(a[1], "status", a[0].status),
+            lambda a: setattr(a[1], "Lh", a[0].Lh)):
+        arr = spin_pair()
+        mutate(arr)
+        assert g(arr, 2, ws, 1 << 40, None) == -1
+    arr = spin_pair()
+    arr[1].mesh[2] = 1
+    arr[1].nk = 9
+    assert g(arr, 2, ws, 1 << 40, None) == -1
+    # a lone half
+    one = spin_pair()
+    assert g(ctypes.byref(one[0]), 1, ws, 1 << 40, None) == -1
+    assert g(ctypes.byref(one[1]), 1, ws, 1 << 40, None) == -1
+    # a pair inside a larger batch, after a closed-shell problem
+    arr3 = (B.Problem * 3)(good_problem(), *spin_pair())
+    if not gpu_available():
+        assert g(arr3, 3, ws, 1 << 40, None) == -5
+    arr3 = (B.Problem * 3)(*spin_pair(), good_problem())
+    arr3[2].spin = 2
+    assert g(arr3, 3, ws, 1 << 40, None) == -1
+
+
+def test_spin_pair_population_ignores_down_xi(L):
+    """The down half draws with the up half's xi: its own entry is not read or checked."""
+    from tests.conftest import gpu_available
+    arr = spin_pair()
+    out = ctypes.c_size_t()
+    assert L.afqmc_kpt_workspace_bytes(arr, 2, 9, ctypes.byref(out)) == 0
+    ws = ctypes.c_void_p(0x10000000)
+    f = L.afqmc_kpt_population_control
+    xs = (ctypes.c_double * 2)(0.5, float("nan"))
+    if not gpu_available():
+        assert f(arr, 2, xs, None, ws, out.value, None) == -5
+    xs = (ctypes.c_double * 2)(1.5, 0.5)
+    assert f(arr, 2, xs, None, ws, out.value, None) == -1
+
+
+def test_band_padding_validation(L):
+    from tests.conftest import gpu_available
+    p = good_problem()
+    p.mesh[0], p.mesh[1], p.mesh[2], p.nk, p.m, p.nocc = 2, 1, 1, 2, 8, 2
+    mk = (ctypes.c_int32 * 2)(5, 8)
+    a, b = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000)
+    f, g = L.afqmc_kpt_pad_bands, L.afqmc_kpt_unpad_bands
+    n = None
+    if not gpu_available():
+        assert f(ctypes.byref(p), 1, mk, a, n, n, n, b, n, n, n, None) == -5
+        assert g(ctypes.byref(p), 1, mk, a, n, b, n, None) == -5
+    assert f(ctypes.byref(p), 1, None, a, n, n, n, b, n, n, n, None) == -2
+    assert f(ctypes.byref(p), 1, mk, a, n, n, n, None, n, n, n, None) == -2  # no output
+    assert f(ctypes.byref(p), 1, mk, ctypes.c_void_p(0x10008), n, n, n, b, n, n, n, None) == -3
+    assert f(ctypes.byref(p), 2, mk, a, n, n, n, b, n, n, n, None) == -1
+    for bad in ((1, 8), (5, 9)):  # below nocc, above m
+        mb = (ctypes.c_int32 * 2)(*bad)
+        assert f(ctypes.byref(p), 1, mb, a, n, n, n, b, n, n, n, None) == -1
+        assert g(ctypes.byref(p), 1, mb, a, n, b, n, None) == -1
+    big = good_problem()
+    big.mesh[0], big.mesh[1], big.mesh[2], big.nk, big.nocc = 4, 4, 9, 144, 1
+    mkb = (ctypes.c_int32 * 144)(*([26] * 144))
+    assert f(ctypes.byref(big), 1, mkb, a, n, n, n, b, n, n, n, None) == -7

@@ -609,3 +609,256 @@ def test_energy_shift_is_a_common_factor():
     assert abs(kp.mixed_energy(E, a["weight"]) - kp.mixed_energy(E, b["weight"])) < 1e-12
     for xi in (0.1, 0.6):
         assert np.array_equal(wk.comb_parents(a["weight"], xi), wk.comb_parents(b["weight"], xi))
+
+
+# ---------------------------------------------------------------------------
+# The standard (dense) representation of a k-point system (oracle/dense.py)
+from oracle import dense as dn  # noqa: E402
+
+
+def _dense_system(s):
+    Ld = dn.dense_cholesky(s.L, s.mesh)
+    H1d, Ad = dn.dense_one_body(s.H1, s.A)
+    return Ld, H1d, Ad
+
+
+@pytest.mark.parametrize("mesh", [(2, 1, 1), (3, 1, 1), (2, 3, 1), (1, 2, 3)])
+def test_dense_vectors_reproduce_integrals(mesh):
+    """The dense vectors are Hermitian and give the explicit 4-index integrals and V0 of the
+    unfolded k-point operators; their number is Nk C."""
+    s, _, _ = tiny(mesh, m=3, nocc=1, nchol=4)
+    Ld, _, _ = _dense_system(s)
+    N = s.nk * s.m
+    assert Ld.shape == (1, 1, N, N, s.nk * s.nchol)
+    D = Ld[0, 0].transpose(2, 0, 1)  # [g, P, R]
+    assert np.abs(D - D.conj().transpose(0, 2, 1)).max() < 1e-15
+    LL = sc.unfold_cholesky(s.L, s.mesh)
+    assert np.abs(sc.eri(D) - sc.eri(LL)).max() < 1e-13
+    assert np.abs(sc.v0_full(D) - sc.v0_full(LL)).max() < 1e-13
+
+
+@pytest.mark.parametrize("mesh", [(2, 1, 1), (3, 1, 1), (2, 3, 1)])
+def test_dense_energy_and_step_equal_kpoint(mesh):
+    """The same walkers in both representations: equal local energies, and one step with the
+    mapped fields gives the same walkers, log overlaps and weights."""
+    s, U, x = tiny(mesh, m=4, nocc=2, nchol=5, nw=3)
+    Ld, H1d, Ad = _dense_system(s)
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    pred = kp.prepare(Ld, H1d, Ad, s.dt)
+    Gh, ld = kp.greens(U, s.A)
+    Ghd, ldd = kp.greens(U, Ad)
+    assert np.abs(Gh - Ghd).max() < 1e-12
+    E = kp.local_energy(pre["Lh"], pre["h1h"], Gh, s.mesh)
+    Ed = kp.local_energy(pred["Lh"], pred["h1h"], Ghd, (1, 1, 1))
+    assert np.abs(E.sum(1) - Ed.sum(1)).max() < 1e-11 * np.abs(E).sum(1).max()
+    # E1B agrees part by part; the two-body parts only in total (the dense EC takes what the
+    # k-point exchange of Q != 0 pairs carries in its direct term and vice versa)
+    assert np.abs(E[:, 0] - Ed[:, 0]).max() < 1e-12 * np.abs(E[:, 0]).max()
+    xd = dn.dense_fields(x, s.mesh)
+    w = np.ones(U.shape[0])
+    a = kp.step(U, ld, w, x, pre, s.A, s.L, s.mesh, s.dt)
+    b = kp.step(U, ldd, w, xd, pred, Ad, Ld, (1, 1, 1), s.dt)
+    assert np.abs(a["U"] - b["U"]).max() < 1e-12
+    np.testing.assert_allclose(b["weight"], a["weight"], rtol=1e-12)
+    assert np.abs(np.exp(a["logdet"] - b["logdet"]) - 1).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# collinear (two-determinant) walkers
+# ---------------------------------------------------------------------------
+
+from synth import make_spin_trial, spin_view  # noqa: E402
+from oracle import spin as sp  # noqa: E402
+
+
+def spin_case(mesh, m=4, n_up=2, n_dn=1, nchol=5, nw=2, seed=21, walkers="dense"):
+    s, rng = make_system(mesh, m, n_up, nchol, seed=seed, trial="random")
+    A_dn = make_spin_trial(s, n_dn, rng)
+    U_up = make_walkers(s, nw, rng, kind=walkers)
+    U_dn = make_walkers(spin_view(s, A_dn), nw, rng, kind=walkers)
+    x = make_fields(s, nw, 1, rng)[0]
+    return s, (s.A, A_dn), (U_up, U_dn), x
+
+
+@pytest.mark.parametrize("mesh", [(1, 1, 1), (2, 1, 1), (2, 3, 1), (2, 2, 2)])
+def test_spin_equal_spins_reduce_to_closed_shell(mesh):
+    """Equal up and down determinants: the closed-shell energy, force bias and weights, and
+    each spin's gradient is half the closed-shell one (E_cs(G) = E(G, G))."""
+    s, U, x = tiny(mesh, trial="random")
+    pre = kp.prepare(s.L, s.H1, s.A, s.dt)
+    ps = sp.prepare(s.L, s.H1, s.A, s.A, s.dt)
+    Gh, ld = kp.greens(U, s.A)
+    E = kp.local_energy(pre["Lh"], pre["h1h"], Gh, mesh)
+    Es = sp.local_energy(ps["Lh"], ps["h1h"], (Gh, Gh), mesh)
+    assert np.abs(Es - E).max() < 1e-12 * np.abs(E).max()
+    xb, X = kp.force_bias(pre["Lh"], Gh, mesh, s.dt)
+    xbs, Xs = sp.force_bias(ps["Lh"], (Gh, Gh), mesh, s.dt)
+    assert np.abs(xbs - xb).max() < 1e-14 and np.abs(Xs - X).max() < 1e-13
+    g = kp.energy_gradient(pre["Lh"], pre["h1h"], Gh, mesh)
+    gu, gd = sp.energy_gradient(ps["Lh"], ps["h1h"], (Gh, Gh), mesh)
+    assert np.abs(gu - 0.5 * g).max() < 1e-13 and np.abs(gd - 0.5 * g).max() < 1e-13
+    w0 = np.array([1.0, 0.7])
+    r = kp.step(U, ld, w0, x, pre, s.A, s.L, mesh, s.dt, etrial=-1.5)
+    rs = sp.step((U, U), (ld, ld), w0, x, ps, (s.A, s.A), s.L, mesh, s.dt, etrial=-1.5)
+    for q in range(2):
+        assert np.abs(rs["U"][q] - r["U"]).max() < 1e-14
+        assert np.abs(rs["logdet"][q] - r["logdet"]).max() < 1e-13
+    np.testing.assert_allclose(rs["weight"], r["weight"], rtol=1e-13)
+
+
+@pytest.mark.parametrize("mesh", [(1, 1, 1), (2, 1, 1), (2, 3, 1), (1, 1, 2)])
+@pytest.mark.parametrize("nocc", [(2, 1), (1, 2), (2, 2), (3, 0)])
+def test_spin_energy_equals_4index(mesh, nocc):
+    """The energy of two different determinants against the spin-resolved expression with
+    explicit supercell integrals (Hamiltonian of "Introduction to AFQMC", Wick's theorem):
+    E = sum_s sum h_PQ G^s_PQ + 1/2 sum v_PQRS [(G^u + G^d)_PR (G^u + G^d)_QS
+                                               - sum_s G^s_PS G^s_QR]."""
+    n_up, n_dn = nocc
+    s, A, U, _ = spin_case(mesh, m=4, n_up=n_up, n_dn=max(n_dn, 1))
+    if n_dn == 0:  # no down electrons: an empty determinant (Gh with zero rows, overlap 1)
+        A = (A[0], A[1][:, :, :0])
+        U = (U[0], U[1][:, :, :0])
+    ps = sp.prepare(s.L, s.H1, A[0], A[1], s.dt)
+    Gh = tuple(kp.greens(U[q], A[q])[0] for q in range(2))
+    E = sp.local_energy(ps["Lh"], ps["h1h"], Gh, mesh)
+    LL, v, h, _ = supercell_objects(s)
+    for w in range(U[0].shape[1] and U[0].shape[0]):
+        G = []
+        for q in range(2):
+            Af = sc.block_diag(A[q])
+            G.append(sc.greens_full(U[q][w], Af) if A[q].shape[2] else np.zeros_like(h))
+        Gt = G[0] + G[1]
+        e1 = sum(np.sum(h * G[q]) for q in range(2))
+        ec = 0.5 * np.einsum("pqrs,pr,qs->", v, Gt, Gt, optimize=True)
+        ex = -0.5 * sum(np.einsum("pqrs,ps,qr->", v, G[q], G[q], optimize=True)
+                        for q in range(2))
+        ref = np.array([e1, ec, ex])
+        assert np.abs(E[w] - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_spin_energy_swap_and_force_bias_derivative():
+    """Swapping the spins leaves energy and force bias unchanged; the force bias is the
+    derivative of the log of the two-determinant overlap."""
+    mesh = (2, 3, 1)
+    s, A, U, _ = spin_case(mesh, m=3, n_up=2, n_dn=1, nchol=3)
+    ps = sp.prepare(s.L, s.H1, A[0], A[1], s.dt)
+    pw = sp.prepare(s.L, s.H1, A[1], A[0], s.dt)
+    Gh = tuple(kp.greens(U[q], A[q])[0] for q in range(2))
+    E = sp.local_energy(ps["Lh"], ps["h1h"], Gh, mesh)
+    Ew = sp.local_energy(pw["Lh"], pw["h1h"], Gh[::-1], mesh)
+    assert np.abs(E - Ew).max() < 1e-13 * np.abs(E).max()
+    _, X = sp.force_bias(ps["Lh"], Gh, mesh, s.dt)
+    LL, _, _, _ = supercell_objects(s)
+    Af = [sc.block_diag(A[q]) for q in range(2)]
+    eps = 1e-5
+    w = 1
+    for gam in range(LL.shape[0]):
+        Q, g = divmod(gam, s.nchol)
+
+        def f(e):
+            out = 0.0
+            for q in range(2):
+                M = Af[q].conj().T @ scipy.linalg.expm(e * LL[gam]) @ U[q][w]
+                sgn, la = np.linalg.slogdet(M)
+                out = out + la + 1j * np.angle(sgn)
+            return out
+
+        fd = (f(eps) - f(-eps)) / (2 * eps)
+        assert abs(fd - X[w, Q, g]) < 1e-7 * max(1.0, abs(X[w, Q, g]))
+
+
+def test_spin_gradient_finite_difference():
+    """The per-spin adjoint against central differences of the energy (a quadratic
+    polynomial in Gh: the difference is exact up to rounding)."""
+    mesh = (2, 1, 1)
+    s, A, U, _ = spin_case(mesh, m=4, n_up=2, n_dn=1, nchol=4)
+    ps = sp.prepare(s.L, s.H1, A[0], A[1], s.dt)
+    Gh = tuple(kp.greens(U[q], A[q])[0] for q in range(2))
+    g = sp.energy_gradient(ps["Lh"], ps["h1h"], Gh, mesh)
+    rng = np.random.default_rng(7)
+    for q in range(2):
+        D = rng.standard_normal(Gh[q].shape) + 1j * rng.standard_normal(Gh[q].shape)
+        eps = 1e-3
+
+        def E(e):
+            G2 = list(Gh)
+            G2[q] = Gh[q] + e * D
+            return sp.local_energy(ps["Lh"], ps["h1h"], tuple(G2), mesh).sum(axis=1)
+
+        fd = (E(eps) - E(-eps)) / (2 * eps)
+        an = np.einsum("wij,wij->w", g[q], D)
+        assert np.abs(fd - an).max() < 1e-9 * max(1.0, np.abs(an).max())
+
+
+def test_spin_step_overlap_ratio_dense():
+    """One step of different up and down determinants: each spin's walker is the dense
+    supercell propagator applied to it, and the weight's overlap ratio is the product of the
+    two spins' dense determinant ratios."""
+    mesh = (2, 1, 1)
+    s, A, U, x = spin_case(mesh, m=4, n_up=2, n_dn=1, nchol=4)
+    ps = sp.prepare(s.L, s.H1, A[0], A[1], s.dt)
+    ld = tuple(kp.greens(U[q], A[q])[1] for q in range(2))
+    w0 = np.array([1.0, 2.0])
+    r = sp.step(U, ld, w0, x, ps, A, s.L, mesh, s.dt)
+    LL, _, h, _ = supercell_objects(s)
+    V0 = sc.v0_full(LL)
+    for w in range(2):
+        V = sc.hs_matrix_full(LL, x[w].reshape(-1, 2), r["xbar"][w].reshape(-1, 2), s.dt)
+        ratio = 1.0
+        for q in range(2):
+            Af = sc.block_diag(A[q])
+            Un = sc.propagate_full(U[q][w], V, h, V0, s.dt)
+            assert np.abs(r["U"][q][w] - Un).max() < 1e-13
+            ratio *= np.linalg.det(Af.conj().T @ Un) / np.linalg.det(Af.conj().T @ U[q][w])
+        log_r = r["log_I"][w] - np.sum(x[w] * r["xbar"][w] - 0.5 * r["xbar"][w] ** 2)
+        assert abs(np.exp(log_r) / ratio - 1.0) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# non-uniform band counts: the zero-padded uniform system is the ragged system
+# ---------------------------------------------------------------------------
+
+from synth import make_ragged_system, make_ragged_walkers  # noqa: E402
+from oracle import bands as bd  # noqa: E402
+
+RAGGED = [((2, 1, 1), (4, 6)), ((2, 3, 1), (4, 5, 3, 4, 6, 5)), ((1, 1, 2), (5, 3)),
+          ((2, 2, 1), (3, 5, 4, 4))]
+
+
+@pytest.mark.parametrize("mesh,mk", RAGGED)
+def test_padded_bands_equal_supercell(mesh, mk):
+    """Energy, force bias, one step (walkers, log overlaps, weights) of the padded system
+    against the supercell route of the ragged system, which knows nothing of padding."""
+    rs, rng = make_ragged_system(mesh, mk, 2, 5, seed=4)
+    Ur = make_ragged_walkers(rs, 2, rng)
+    x = rng.standard_normal((2, rs.nk, rs.nchol, 2))
+    m = max(mk) + 1  # one band of padding beyond the largest count
+    L, H1, A = bd.pad(rs, m)
+    U = bd.pad_walkers(Ur, mk, m)
+    assert np.array_equal(bd.unpad_walkers(U, mk, m), Ur)
+    pre = kp.prepare(L, H1, A, rs.dt)
+    Gh, ld = kp.greens(U, A)
+    E = kp.local_energy(pre["Lh"], pre["h1h"], Gh, mesh)
+    xbar, _ = kp.force_bias(pre["Lh"], Gh, mesh, rs.dt)
+    r = kp.step(U, ld, np.ones(2), x, pre, A, L, mesh, rs.dt)
+    LL, h, Af = bd.supercell(rs)
+    v = sc.eri(LL)
+    V0 = sc.v0_full(LL)
+    for w in range(2):
+        assert np.abs(bd.unpad_greens(Gh, mk, m)[w] - sc.half_greens_full(Ur[w], Af)).max() \
+            < 1e-12
+        G = sc.greens_full(Ur[w], Af)
+        ref = sc.energy_4index(h, v, G)
+        assert np.abs(E[w] - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+        xb = sc.force_bias_full(LL, G, rs.dt).reshape(rs.nk, rs.nchol, 2)
+        assert np.abs(xbar[w] - xb).max() < 1e-14
+        V = sc.hs_matrix_full(LL, x[w].reshape(-1, 2), xb.reshape(-1, 2), rs.dt)
+        Un = sc.propagate_full(Ur[w], V, h, V0, rs.dt)
+        assert np.abs(bd.unpad_walkers(r["U"], mk, m)[w] - Un).max() < 1e-13
+        # the padded rows stay zero
+        pad_rows = np.ones(rs.nk * m, dtype=bool)
+        for k in range(rs.nk):
+            pad_rows[k * m:k * m + mk[k]] = False
+        assert np.abs(r["U"][w][pad_rows]).max() < 1e-15
+        ratio = np.linalg.det(Af.conj().T @ Un) / np.linalg.det(Af.conj().T @ Ur[w])
+        assert abs(np.exp(r["logdet"][w] - ld[w]) / ratio - 1.0) < 1e-11
