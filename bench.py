@@ -841,6 +841,158 @@ def bench_dense(args, torch):
     }
 
 
+def time_batch_block(b, fields, args, torch, reset_fn):
+    """Mean time of one block (afqmc_kpt_step over the packed fields with the last step's
+    re-orthonormalisation and the local energy) after the warmup blocks."""
+    for _ in range(args.warmup):
+        reset_fn()
+        b.step(fields, ortho=True, energy=True)
+    torch.cuda.synchronize()
+    t = 0.0
+    for _ in range(max(args.steps, 1)):
+        reset_fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(fields, ortho=True, energy=True)
+        torch.cuda.synchronize()
+        t += time.perf_counter() - t0
+    return t / max(args.steps, 1) * 1e3
+
+
+def bench_spin(args, torch):
+    """Two-determinant (collinear) walkers at the c1 size: mesh 3x3x3, m=26, nchol=208, 64
+    walkers, 4 up and 3 down electrons per k-point, against the closed-shell system with 4
+    of each; one block = 20 steps + QR + local energy through afqmc_kpt_step, in FP64 and in
+    the placed BF16X3-step / INT8X4-energy precision.  The energies of the initial walkers
+    in the placed precision are compared with FP64."""
+    import numpy as np
+    from synth.kpt_inputs import (make_system, make_walkers, make_fields, make_spin_trial,
+                                  spin_view)
+    import paper_2003_09468_amd as lib
+    W, nsteps, nu, nd = 64, 20, 4, 3
+    s, rng = make_system((3, 3, 3), 26, nu, 208, seed=0)
+    A_dn = make_spin_trial(s, nd, rng)
+    U_up = torch.from_numpy(make_walkers(s, W, rng)).cuda()
+    U_dn = torch.from_numpy(make_walkers(spin_view(s, A_dn), W, rng)).cuda()
+    x = torch.from_numpy(make_fields(s, W, nsteps, rng)).cuda()
+    L, A, Ad, H1 = (torch.from_numpy(v).cuda() for v in (s.L, s.A, A_dn, s.H1))
+    res, E0 = {}, {}
+    placed = lib.prec_place(lib.PREC_BF16X3, lib.PREC_INT8X4)
+    for pname, prec in (("fp64", lib.PREC_FP64), ("bf16x3+int8x4E", placed)):
+        pr = lib.KptSpinPair(s.mesh, s.m, nu, nd, s.nchol, W, s.dt, L, A, Ad, prec=prec)
+        pr.prepare(H1)
+        cs = lib.KptProblem(s.mesh, s.m, nu, s.nchol, W, s.dt, L, A, prec=prec)
+        cs.prepare(H1)
+        cb = lib.KptBatch([cs])
+
+        def reset_pair():
+            pr.set_walkers(U_up, U_dn)
+            pr.greens()
+
+        def reset_closed():
+            cs.set_walkers(U_up)
+            cs.greens()
+
+        reset_pair()
+        pr.autotune()
+        reset_closed()
+        cb.autotune()
+        reset_pair()
+        pr.local_energy()
+        E0[pname] = pr.energy(0).sum(1).cpu().numpy() / s.nk
+        fp = pr.step_fields(x)
+        fc = cb.fields([x])
+        tp = time_batch_block(pr, fp, args, torch, reset_pair)
+        tc = time_batch_block(cb, fc, args, torch, reset_closed)
+        res[pname] = {"pair_ms_per_block": round(tp, 3), "closed_ms_per_block": round(tc, 3),
+                      "pair_walker_steps_per_s": round(W * nsteps / tp * 1e3, 1),
+                      "closed_walker_steps_per_s": round(W * nsteps / tc * 1e3, 1),
+                      "pair_over_closed": round(tp / tc, 3)}
+        log(f"[{pname}] two-determinant block {tp:.2f} ms, closed shell {tc:.2f} ms "
+            f"({tp / tc:.2f}x)")
+        del pr, cs, cb
+        torch.cuda.empty_cache()
+    dE = float(np.abs(E0["bf16x3+int8x4E"] - E0["fp64"]).max())
+    res["bf16x3+int8x4E"]["initial_energy_err_per_cell"] = dE
+    log(f"initial-walker energy, placed vs FP64: {dE:.2e} Ha/cell")
+    r = res["bf16x3+int8x4E"]
+    return {
+        "metric": "walker-steps/s, two-determinant walkers, Nk=27 M=26",
+        "value": r["pair_walker_steps_per_s"], "unit": "walker-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["pair_ms_per_block"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16x3+int8x4+f64", "data": "synthetic",
+        "config": {"workload": "mesh 3x3x3, m=26, nchol=208, 64 walkers, 4 up + 3 down "
+                               "electrons per k-point; one step = one block of 20 steps + QR + "
+                               "local energy", "path": "bf16x3+int8x4E"},
+        "paths": res, "kernel_source_hash": kernel_source_hash(),
+    }
+
+
+def bench_bands(args, torch):
+    """Non-uniform bands: a 3x3x3 system whose k-points hold 20 to 26 bands (drawn
+    uniformly, seeded), 4 occupied, 208 Cholesky vectors per Q, 64 walkers, padded to 26
+    bands on the device; FP64 blocks of 20 steps + QR + local energy, against the uniform
+    26-band system of the same sizes.  Reports the padding entry's time and the padded
+    block's throughput."""
+    import numpy as np
+    from synth.kpt_inputs import make_ragged_system, make_ragged_walkers, pack_ragged
+    from synth.kpt_inputs import make_system, make_walkers
+    import paper_2003_09468_amd as lib
+    W, nsteps, m, nocc, C = 64, 20, 26, 4, 208
+    rng0 = np.random.Generator(np.random.PCG64(5))
+    mk = tuple(int(v) for v in rng0.integers(20, 27, size=27))
+    rs, rng = make_ragged_system((3, 3, 3), mk, nocc, C, seed=5)
+    Ur = make_ragged_walkers(rs, W, rng)
+    x = torch.from_numpy(rng.standard_normal((nsteps, W, 27, C, 2))).cuda()
+    Lr, Hr, Ar, Urp = (torch.from_numpy(np.ascontiguousarray(v)).cuda()
+                       for v in pack_ragged(rs, Ur))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L, H1, A, U = lib.pad_bands(rs.mesh, mk, m, nocc, C, Lr, Hr, Ar, Urp)
+    torch.cuda.synchronize()
+    tpad = (time.perf_counter() - t0) * 1e3
+    del Lr
+    res = {}
+    us, rng2 = make_system((3, 3, 3), m, nocc, C, seed=5)
+    Uu = torch.from_numpy(make_walkers(us, W, rng2)).cuda()
+    for name, (LL, AA, HH, UU) in (("padded", (L, A, H1, U)),
+                                   ("uniform", (torch.from_numpy(us.L).cuda(),
+                                                torch.from_numpy(us.A).cuda(),
+                                                torch.from_numpy(us.H1).cuda(), Uu))):
+        p = lib.KptProblem((3, 3, 3), m, nocc, C, W, rs.dt, LL, AA)
+        p.prepare(HH)
+        b = lib.KptBatch([p])
+
+        def reset_fn():
+            p.set_walkers(UU)
+            p.greens()
+
+        reset_fn()
+        b.autotune()
+        t = time_batch_block(b, b.fields([x]), args, torch, reset_fn)
+        res[name] = {"ms_per_block": round(t, 3),
+                     "walker_steps_per_s": round(W * nsteps / t * 1e3, 1)}
+        log(f"[{name}] block {t:.2f} ms")
+        del p, b
+        torch.cuda.empty_cache()
+    res["padded"]["pad_entry_ms"] = round(tpad, 3)
+    res["padded"]["mean_bands"] = float(np.mean(mk))
+    log(f"padding entry {tpad:.2f} ms; mean bands {np.mean(mk):.2f} of {m}")
+    r = res["padded"]
+    return {
+        "metric": "walker-steps/s, non-uniform bands (20-26 per k-point, padded to 26)",
+        "value": r["walker_steps_per_s"], "unit": "walker-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_block"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"mesh 3x3x3, bands per k-point {list(mk)} padded to 26, "
+                               "nocc=4, nchol=208, 64 walkers; one step = one FP64 block of 20 "
+                               "steps + QR + local energy", "path": "fp64"},
+        "paths": res, "kernel_source_hash": kernel_source_hash(),
+    }
+
+
 def bench_c2(args, torch):
     """4x4x4 mesh, m=52, nocc=4, nchol=400, 32 walkers (L: 70.9 GB complex128, streamed to
     the GPU block by block as it is drawn).  The local energy of the initial walkers with
@@ -961,7 +1113,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1, help="untimed blocks")
     ap.add_argument("--config", default="c1",
                     help="c1 (headline), c0, c2 (4x4x4 energy precisions), c3 (uneven batch modes), "
-                         "c4 (energy adjoint) or dense (k-point vs standard representation)")
+                         "c4 (energy adjoint), dense (k-point vs standard representation), "
+                         "spin (two-determinant walkers) or bands (non-uniform bands)")
     ap.add_argument("--prec", default="all",
                     help="all, or a comma-separated list of paths: " + ", ".join(PATHS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -1005,6 +1158,12 @@ def main():
         return
     if args.config == "dense":
         print(json.dumps(bench_dense(args, torch)), flush=True)
+        return
+    if args.config == "spin":
+        print(json.dumps(bench_spin(args, torch)), flush=True)
+        return
+    if args.config == "bands":
+        print(json.dumps(bench_bands(args, torch)), flush=True)
         return
     cfg = config_shapes(args.config)
     log(f"generating {args.config}: {cfg}")

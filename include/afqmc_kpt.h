@@ -223,7 +223,9 @@ typedef struct afqmc_kpt_problem {
  *   fields: the down half uses the up half's fields x (its own slot is not read);
  *   force bias: X = sum over both spins of tr(Lh^s Gh^s) (half the sum of the two
  *     halves' closed-shell traces), xbar from it; both halves' xbar and X slots hold them;
- *   propagation: both determinants take the same one- and two-body operators;
+ *   propagation: both determinants take the same one- and two-body operators
+ *     (afqmc_kpt_step forms the HS potential once per pair, in the up half's vhs slice, and
+ *     leaves the down half's slice unwritten);
  *   weights: the overlap is det(O_up) det(O_down); the update multiplies both halves'
  *     weights by the same factor (the phaseless angle of the product's ratio, the up half's
  *     etrial), writes each half's own logdet and ORs the status bits of either half into

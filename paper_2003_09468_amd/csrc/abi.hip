@@ -287,12 +287,21 @@ hipError_t run_steps(std::vector<Job>& jobs, const int* orig_prec, const double*
   const int n = (int)jobs.size();
   std::vector<const double*> x0(n);
   for (int i = 0; i < n; ++i) x0[i] = jobs[i].x;
+  // the halves of a two-determinant pair have one field and one force bias, hence one HS
+  // potential: the down half propagates with the up half's
+  std::vector<int> vh;
+  for (int i = 0; i < n; ++i) {
+    if (jobs[i].p.spin == AFQMC_SPIN_DOWN) jobs[i].vhs = jobs[i - 1].vhs;
+    else vh.push_back(i);
+  }
+  std::vector<Job> vj(vh.size());
   hipError_t e = hipSuccess;
   for (int st = 0; st < nsteps && e == hipSuccess; ++st) {
     for (int i = 0; i < n; ++i)
       jobs[i].x = (const double*)((const char*)x0[i] + (size_t)st * stride);
+    for (size_t q = 0; q < vh.size(); ++q) vj[q] = jobs[vh[q]];
     e = run_vbias(jobs.data(), n, s);
-    if (e == hipSuccess) e = run_vhs(jobs.data(), n, s);
+    if (e == hipSuccess) e = run_vhs(vj.data(), (int)vj.size(), s);
     // every Gh but that of a last step without re-orthonormalisation only feeds the next
     // force bias
     const bool last = st == nsteps - 1;
