@@ -325,12 +325,22 @@ hipError_t launch_vbias_group(const Job* jobs, const int* ids, int c, int choice
   return vbias_tiles<double>(ops, c, choice, s);
 }
 
+// Launch group of job i of the force-bias contraction: its precision, or a launch of its own
+// when its output tiles (W nk C entries in 64 x 32 tiles, times the K slices) alone fill
+// the device.
+static int vbias_group(const Job* J, int i, int ncu) {
+  const afqmc_kpt_problem& p = J[i].p;
+  const int64_t tiles = ((int64_t)p.nwalk * p.nk * p.nchol + 2047) / 2048;
+  return solo_key(p.prec, i, tiles * vbias_splits(dims_of(p)), ncu);
+}
+
 // X (and xbar where requested) for the current Gh of every job.
 hipError_t launch_cholesky_trace(const Job* jobs, int n, void* const* X, void* const* xbar,
                                  void* const* parts, hipStream_t s) {
   TimedScope ts(KC_VBIAS, s);
+  const int ncu = device_cus();
   hipError_t e = for_groups(
-      n, [&](int i) { return jobs[i].p.prec; },
+      n, [&](int i) { return vbias_group(jobs, i, ncu); },
       [&](const int* ids, int c) -> hipError_t {
         const int choice = tune_lookup(tune_key(TS_VBIAS, jobs, ids, c));
         return launch_vbias_group(jobs, ids, c, choice, parts, s);
@@ -396,8 +406,9 @@ hipError_t tune_vbias(const Job* jobs, int n, hipStream_t s) {
       carve_vbias(cv, dims_of(J[q].p), v);
       parts[q] = v.parts;
     }
+    const int ncu = device_cus();
     const hipError_t e = for_groups(
-        c, [&](int i) { return J[i].p.prec; },
+        c, [&](int i) { return vbias_group(J, i, ncu); },
         [&](const int* ids, int g) -> hipError_t {
           return tune_group(
               TS_VBIAS, J, ids, g,
@@ -878,6 +889,14 @@ static size_t zeta_bytes(const afqmc_kpt_problem& p) {
 // tiles), so that every problem gets its default tile shape.
 static int vhs_key(const afqmc_kpt_problem& p) { return p.prec * 2 + (p.nwalk <= 32 ? 1 : 0); }
 
+// Launch group of job i of the HS potential: its key, or a launch of its own when its
+// 64 x 64 output tiles (W nk^2 m^2 entries) alone fill the device.
+static int vhs_group(const Job* J, int i, int ncu) {
+  const afqmc_kpt_problem& p = J[i].p;
+  const int64_t ent = (int64_t)p.nwalk * p.nk * p.nk * p.m * p.m;
+  return solo_key(vhs_key(p), i, (ent + 4095) / 4096, ncu);
+}
+
 hipError_t run_vhs(const Job* jobs, int n, hipStream_t s) {
   TimedScope ts(KC_VHS, s);
   void* zeta[64];
@@ -888,8 +907,9 @@ hipError_t run_vhs(const Job* jobs, int n, hipStream_t s) {
       Carve cv(J[q].ws);
       zeta[q] = cv.take(zeta_bytes(J[q].p));
     }
+    const int ncu = device_cus();
     hipError_t e = for_groups(
-        c, [&](int i) { return vhs_key(J[i].p); },
+        c, [&](int i) { return vhs_group(J, i, ncu); },
         [&](const int* ids, int g) -> hipError_t {
           if (J[ids[0]].p.prec == AFQMC_PREC_BF16X3) return launch_vhs_bf16x3(J, ids, g, zeta, s);
           Batch<FieldArgs> B;
@@ -932,8 +952,9 @@ hipError_t tune_vhs(const Job* jobs, int n, hipStream_t s) {
       Carve cv(J[q].ws);
       zeta[q] = cv.take(zeta_bytes(J[q].p));
     }
+    const int ncu = device_cus();
     const hipError_t e = for_groups(
-        c, [&](int i) { return vhs_key(J[i].p); },
+        c, [&](int i) { return vhs_group(J, i, ncu); },
         [&](const int* ids, int g) -> hipError_t {
           // the BF16X3 HS potential has a single variant
           if (J[ids[0]].p.prec == AFQMC_PREC_BF16X3) return hipSuccess;

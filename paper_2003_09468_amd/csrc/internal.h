@@ -127,6 +127,23 @@ hipError_t for_groups(int n, KeyFn key, Fn fn) {
   return e;
 }
 
+// Compute units of the current device (1 if the query fails).
+inline int device_cus() {
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 1;
+  return ncu > 0 ? ncu : 1;
+}
+
+// Launch-group key of a problem in a batched GEMM stage: a problem whose own launch would
+// give at least two workgroups per compute unit fills the device alone, and batching it
+// with others only mixes tiles of different cost (and one tile shape for all), so it gets a
+// key, and a launch, of its own; smaller problems share launches by their base key.
+inline int solo_key(int base, int index, int64_t workgroups, int ncu) {
+  return workgroups >= 2LL * ncu ? ((index + 1) << 12) | base : base;
+}
+
 // Launch sequences over a batch of jobs (arguments already validated).
 hipError_t run_prepare(const afqmc_kpt_problem& p, const void* H1, void* ws, hipStream_t s);
 hipError_t run_greens(const Job* jobs, int n, bool write_logdet_new_only, hipStream_t s,

@@ -656,6 +656,14 @@ void propagate_slots(const Job& j, void** acc, void** t0, void** t1, void** tc) 
 
 static int taylor_key(const afqmc_kpt_problem& p) { return p.prec * 16 + taylor_class(p); }
 
+// Launch group of job i of a Taylor stage: its tile class, or a launch of its own when its
+// 64 x 32 output tiles alone fill the device.
+static int taylor_group(const Job* J, int i, int ncu) {
+  const afqmc_kpt_problem& p = J[i].p;
+  const int64_t M = (int64_t)p.nk * p.m, N = (int64_t)p.nk * p.nocc;
+  return solo_key(taylor_key(p), i, (int64_t)p.nwalk * ((M + 63) / 64) * ((N + 31) / 32), ncu);
+}
+
 // U <- bhalf T6(-sqrt(dt) vhs) bhalf U for every job.
 static hipError_t propagate_jobs(const Job* J, int c, hipStream_t s) {
   void *acc[AFQMC_MAXP], *t0[AFQMC_MAXP], *t1[AFQMC_MAXP], *tc[AFQMC_MAXP], *U[AFQMC_MAXP];
@@ -663,8 +671,9 @@ static hipError_t propagate_jobs(const Job* J, int c, hipStream_t s) {
     propagate_slots(J[q], &acc[q], &t0[q], &t1[q], &tc[q]);
     U[q] = J[q].p.U;
   }
+  const int ncu = device_cus();
   return for_groups(
-      c, [&](int i) { return taylor_key(J[i].p); },
+      c, [&](int i) { return taylor_group(J, i, ncu); },
       [&](const int* ids, int g) -> hipError_t {
         const bool f32 = low_prec(J[ids[0]].p.prec);
         hipError_t e;
@@ -706,8 +715,9 @@ hipError_t tune_taylor(const Job* jobs, int n, hipStream_t s) {
     const Job* J = jobs + c0;
     void *acc[AFQMC_MAXP], *t0[AFQMC_MAXP], *t1[AFQMC_MAXP], *tc[AFQMC_MAXP];
     for (int q = 0; q < c; ++q) propagate_slots(J[q], &acc[q], &t0[q], &t1[q], &tc[q]);
+    const int ncu = device_cus();
     const hipError_t e = for_groups(
-        c, [&](int i) { return taylor_key(J[i].p); },
+        c, [&](int i) { return taylor_group(J, i, ncu); },
         [&](const int* ids, int g) -> hipError_t {
           // the BF16X3 steps have a single variant
           if (J[ids[0]].p.prec == AFQMC_PREC_BF16X3) return hipSuccess;
