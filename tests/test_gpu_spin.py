@@ -161,3 +161,29 @@ def test_spin_population_and_graph():
     for i in range(3):
         assert torch.equal(b1.energy(i), b2.energy(i))
     g.close()
+
+
+@pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
+def test_equal_spins_placed_int8_energy():
+    """Equal halves in the placed BF16X3-step / INT8X5-energy precision reproduce the
+    closed shell in the same placement: steps bit for bit, one-body and exchange energies
+    bit for bit (the halves' means of equal values), the Coulomb energy to rounding."""
+    from tests.gpu_cases import build
+    pl = lib.prec_place(lib.PREC_BF16X3, lib.PREC_INT8X5)
+    s, U, x, p, pre = build("wide", prec=pl)
+    pr = lib.KptSpinPair(s.mesh, s.m, s.nocc, s.nocc, s.nchol, U.shape[0], s.dt,
+                         torch.from_numpy(s.L), torch.from_numpy(s.A), torch.from_numpy(s.A),
+                         prec=pl)
+    pr.prepare(torch.from_numpy(s.H1))
+    pr.set_walkers(torch.from_numpy(U), torch.from_numpy(U))
+    pr.greens()
+    cb = lib.KptBatch([p])
+    pr.step(pr.step_fields(torch.from_numpy(x)), ortho=True, energy=True)
+    cb.step(cb.fields([torch.from_numpy(x)]), ortho=True, energy=True)
+    torch.cuda.synchronize()
+    for h in (pr.up, pr.dn):
+        assert torch.equal(h.U, p.U) and torch.equal(h.weight, p.weight)
+    E, Ec = host(pr.energy(0)), host(cb.energy(0))
+    assert np.array_equal(E[:, [0, 2]], Ec[:, [0, 2]])
+    assert np.abs(E[:, 1] - Ec[:, 1]).max() < 1e-13 * np.abs(Ec[:, 1]).max()
+    assert np.array_equal(host(pr.energy(1)), E)
