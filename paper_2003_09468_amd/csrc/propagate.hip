@@ -253,7 +253,7 @@ struct TaylorBfArgs {
 
 template <int BM, int NB, bool VEC, int NCW>
 __global__ __launch_bounds__(64 * NCW + 256) void taylor_bf16x3_kernel(const Batch<TaylorBfArgs> B) {
-  constexpr int BN = 16 * NB, BKC = 32, RS = BKC + 8;
+  constexpr int BN = 16 * NB, BKC = 32, RS = BKC;
   // NCW consumer waves in a 2 x NCW / 2 grid, then 4 producer waves
   constexpr int NT = 64 * NCW + 256, GM = 2, GN = NCW / GM;
   constexpr int RB = BM / (16 * GM);  // 16-row blocks per consumer wave
@@ -267,6 +267,11 @@ __global__ __launch_bounds__(64 * NCW + 256) void taylor_bf16x3_kernel(const Bat
   // units, and unpadded plane strides (a multiple of 256 bytes) would put them in one bank
   // group
   constexpr int PSB = BN * RS + 32;
+  // 16-byte slot of the 8 k at k8 = k / 8 in row (or column) r of a stage: k8 ^ ((r / 4) % 4).
+  // A fragment read takes rows r0 .. r0 + 15 at one k8 (lanes 0-15) and the next k8 in
+  // each further group of 16 lanes: 64-byte rows put the 16 lanes of a group, and the four
+  // lanes of equal lane % 16 across the groups, in distinct banks.
+  auto sw = [](int r, int k) { return ((((k >> 3) ^ (r >> 2)) & 3) << 3) | (k & 7); };
   constexpr int SA_BYTES = 2 * 4 * BM * RS * 2, SB_BYTES = 2 * 4 * PSB * 2;
   constexpr int RST = BN + 1;  // row stride of the result tile (float2)
   constexpr int RES_BYTES = BM * RST * 8;
@@ -334,12 +339,12 @@ __global__ __launch_bounds__(64 * NCW + 256) void taylor_bf16x3_kernel(const Bat
         bf16_split2(ok0 ? v.y : 0.f, ok1 ? v.w : 0.f, h[2], h[3]);
 #pragma unroll
         for (int pl = 0; pl < 4; ++pl)
-          *reinterpret_cast<unsigned int*>(&sA[st][pl][r][kk]) = h[pl];
+          *reinterpret_cast<unsigned int*>(&sA[st][pl][r][sw(r, kk)]) = h[pl];
       }
 #pragma unroll
       for (int e = 0; e < NB; ++e) {
         const int u = pt + 256 * e;
-        *reinterpret_cast<u32x4*>(&sB[st][(u >> 2) & 3][(u >> 4) * RS + 8 * (u & 3)]) = xb[e];
+        *reinterpret_cast<u32x4*>(&sB[st][(u >> 2) & 3][(u >> 4) * RS + sw(u >> 4, 8 * (u & 3))]) = xb[e];
       }
     };
 #pragma unroll
@@ -387,7 +392,7 @@ __global__ __launch_bounds__(64 * NCW + 256) void taylor_bf16x3_kernel(const Bat
           for (int i = 0; i < RB; ++i) {
 #pragma unroll
             for (int pl = 0; pl < 4; ++pl)
-              fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][pl][wm * 16 * RB + i * 16 + (lane & 15)][kq]);
+              fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][pl][wm * 16 * RB + i * 16 + (lane & 15)][sw(lane & 15, kq)]);
             fn[i][0] = bf16_neg(fa[i][2]);
             fn[i][1] = bf16_neg(fa[i][3]);
           }
@@ -397,7 +402,7 @@ __global__ __launch_bounds__(64 * NCW + 256) void taylor_bf16x3_kernel(const Bat
               u16x8 fb[4];
 #pragma unroll
               for (int pl = 0; pl < 4; ++pl)
-                fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][(16 * (cb0 + j) + (lane & 15)) * RS + kq]);
+                fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][(16 * (cb0 + j) + (lane & 15)) * RS + sw(lane & 15, kq)]);
 #pragma unroll
               for (int i = 0; i < RB; ++i) {
                 // re += Vr Tr - Vi Ti,  im += Vr Ti + Vi Tr  (fn: -Vi)
