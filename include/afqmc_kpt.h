@@ -415,8 +415,9 @@ afqmc_status afqmc_kpt_reblock(const double* x, int64_t n, afqmc_reblock_level* 
  *   Ld:  [1][1][N][N][nk nchol] complex128, Hermitian per vector
  *   H1d: [1][N][N] complex128, block diagonal of H1 ([nk][m][m] complex128, device)
  *   Ad:  [1][N][n] complex128, block diagonal of the trial A
- * Reads L and A of the first problem of p (nprob = 1).  The dense walkers are the k-point
- * ones unchanged ([nwalk][N][n]). */
+ * Reads L and A of the first problem of p (nprob = 1, closed shell).  The dense walkers are
+ * the k-point ones unchanged ([nwalk][N][n]).  Returns AFQMC_EUNSUPPORTED when the dense
+ * problem exceeds the sizes the kernels run (N > 64 or n > 16). */
 afqmc_status afqmc_kpt_dense_system(const afqmc_kpt_problem* p, int nprob, const void* H1,
                                     void* Ld, void* H1d, void* Ad, void* stream);
 

@@ -587,6 +587,9 @@ afqmc_status afqmc_kpt_dense_system(const afqmc_kpt_problem* p, int nprob, const
                                     void* Ld, void* H1d, void* Ad, void* stream) {
   AFQMC_TRY(check_problems(p, nprob, N_LD | N_A));
   if (nprob != 1) return AFQMC_EINVAL;
+  // the dense problem (m = nk m, nocc = nk nocc on a 1x1x1 mesh) must be one the kernels run
+  if ((int64_t)p[0].nk * p[0].m > 64 || (int64_t)p[0].nk * p[0].nocc > 16)
+    return AFQMC_EUNSUPPORTED;
   AFQMC_TRY(check_ptr(H1, 16));
   AFQMC_TRY(check_ptr(Ld, 16));
   AFQMC_TRY(check_ptr(H1d, 16));

@@ -692,3 +692,21 @@ def test_band_padding_validation(L):
     big.mesh[0], big.mesh[1], big.mesh[2], big.nk, big.nocc = 4, 4, 9, 144, 1
     mkb = (ctypes.c_int32 * 144)(*([26] * 144))
     assert f(ctypes.byref(big), 1, mkb, a, n, n, n, b, n, n, n, None) == -7
+
+
+def test_dense_system_validation(L):
+    from tests.conftest import gpu_available
+    p = good_problem()  # 3x3x3, m = 26: the dense problem (702 orbitals) is out of range
+    a = ctypes.c_void_p(0x10000)
+    f = L.afqmc_kpt_dense_system
+    assert f(ctypes.byref(p), 1, a, a, a, a, None) == -7
+    q = good_problem()
+    q.mesh[0], q.mesh[1], q.mesh[2], q.nk, q.m, q.nocc = 2, 2, 2, 8, 8, 2
+    if not gpu_available():
+        assert f(ctypes.byref(q), 1, a, a, a, a, None) == -5
+    q.nocc = 3  # 24 occupied orbitals in the dense problem
+    assert f(ctypes.byref(q), 1, a, a, a, a, None) == -7
+    q.nocc = 2
+    assert f(ctypes.byref(q), 1, None, a, a, a, None) == -2
+    arr = (B.Problem * 2)(q, q)
+    assert f(arr, 2, a, a, a, a, None) == -1
