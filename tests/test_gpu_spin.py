@@ -187,3 +187,21 @@ def test_equal_spins_placed_int8_energy():
     assert np.array_equal(E[:, [0, 2]], Ec[:, [0, 2]])
     assert np.abs(E[:, 1] - Ec[:, 1]).max() < 1e-13 * np.abs(Ec[:, 1]).max()
     assert np.array_equal(host(pr.energy(1)), E)
+
+
+@pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
+def test_spin_energy_noalloc_equals_energy():
+    """The entry point without a workspace gives a pair the same energies, bit for bit."""
+    import ctypes
+    from paper_2003_09468_amd import binding as Bd
+    s, A, U, x, pr, pre = build_pair("line3")
+    pr.local_energy()
+    torch.cuda.synchronize()
+    E = [host(pr.energy(i)).copy() for i in range(2)]
+    out = torch.zeros_like(pr._E)
+    Bd.check("afqmc_kpt_energy_noalloc",
+             Bd.lib().afqmc_kpt_energy_noalloc(pr.arr, 2, out.data_ptr(), Bd._stream()))
+    torch.cuda.synchronize()
+    for i in range(2):
+        got = host(pr._view(out, "energy", i, torch.complex128, (pr.problems[i].nwalk, 3)))
+        assert np.array_equal(got, E[i])
