@@ -147,10 +147,15 @@ struct VbBfArgs {
 };
 
 __global__ __launch_bounds__(256) void vbias_bf16x3_kernel(const Batch<VbBfArgs> B) {
-  constexpr int BG = 64, BW = 64, RS = 40;
-  // (no plane padding: the two stages fill exactly half of the LDS, two workgroups per CU)
-  __shared__ __attribute__((aligned(16))) unsigned short sA[2][4][BG][RS];
-  __shared__ __attribute__((aligned(16))) unsigned short sB[2][4][BW][RS];
+  constexpr int BG = 64, BW = 64, RS = 32;
+  // planes padded by 64 bytes (a 16-byte staging store of 16 lanes covers 4 planes x 4
+  // units); the two stages take 66 KB, two workgroups per CU
+  constexpr int PS = 64 * RS + 32;
+  __shared__ __attribute__((aligned(16))) unsigned short sA[2][4][PS];
+  __shared__ __attribute__((aligned(16))) unsigned short sB[2][4][PS];
+  // 16-byte slot of the 8 k at k8 = k / 8 in row r: k8 ^ ((r / 4) % 4), so that the 16 rows
+  // of a fragment read (and the four lane groups at one row) fall in distinct banks
+  auto sw = [](int r, int k) { return ((((k >> 3) ^ (r >> 2)) & 3) << 3) | (k & 7); };
   long long loc;
   const int pb = batch_find(B, blockIdx.x, loc);
   const VbBfArgs& a = B.a[pb];
@@ -207,7 +212,7 @@ __global__ __launch_bounds__(256) void vbias_bf16x3_kernel(const Batch<VbBfArgs>
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int u = tid + 256 * e;
-      *reinterpret_cast<u4*>(&sA[st][(u >> 2) & 3][u >> 4][8 * (u & 3)]) = xa[e];
+      *reinterpret_cast<u4*>(&sA[st][(u >> 2) & 3][(u >> 4) * RS + sw(u >> 4, 8 * (u & 3))]) = xa[e];
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -219,7 +224,7 @@ __global__ __launch_bounds__(256) void vbias_bf16x3_kernel(const Batch<VbBfArgs>
       bf16_split2(ok0 ? (float)xb[e][0].im : 0.f, ok1 ? (float)xb[e][1].im : 0.f, h[2], h[3]);
 #pragma unroll
       for (int pl = 0; pl < 4; ++pl)
-        *reinterpret_cast<unsigned int*>(&sB[st][pl][u >> 4][2 * (u & 15)]) = h[pl];
+        *reinterpret_cast<unsigned int*>(&sB[st][pl][(u >> 4) * RS + sw(u >> 4, 2 * (u & 15))]) = h[pl];
     }
   };
   v4f acr[2][2], aci[2][2];
@@ -249,8 +254,10 @@ __global__ __launch_bounds__(256) void vbias_bf16x3_kernel(const Batch<VbBfArgs>
         for (int i = 0; i < 2; ++i)
 #pragma unroll
           for (int pl = 0; pl < 4; ++pl) {
-            fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][pl][wm * 32 + i * 16 + (lane & 15)][kq]);
-            fb[i][pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][wn * 32 + i * 16 + (lane & 15)][kq]);
+            fa[i][pl] = *reinterpret_cast<const u16x8*>(
+                &sA[st][pl][(wm * 32 + i * 16 + (lane & 15)) * RS + sw(lane & 15, kq)]);
+            fb[i][pl] = *reinterpret_cast<const u16x8*>(
+                &sB[st][pl][(wn * 32 + i * 16 + (lane & 15)) * RS + sw(lane & 15, kq)]);
           }
         const u16x8 fn[2][2] = {{bf16_neg(fa[0][2]), bf16_neg(fa[0][3])},
                                 {bf16_neg(fa[1][2]), bf16_neg(fa[1][3])}};
@@ -535,12 +542,17 @@ struct VhsPos {
 
 __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> B) {
   // 96 columns per tile: the stages of both fields and of L then fit the 160 KB of LDS
-  constexpr int BM = 64, BN = 96, BKC = 32, RS = BKC + 8, DEPTH = 2;
+  constexpr int BM = 64, BN = 96, BKC = 32, RS = BKC, DEPTH = 2;
   constexpr int NUB = BN / 16;   // B units per producer thread
   constexpr int NJ = BN / 32;    // 16-column blocks per consumer wave
   // planes padded by 64 bytes: a 16-byte staging store of 16 lanes covers 4 planes x 4
   // units, which unpadded plane strides (multiples of 256 bytes) put in one bank group
   constexpr int PSA = BM * RS + 32, PSB = BN * RS + 32;
+  // 16-byte slot of the 8 k at k8 = k / 8 in row r of a stage: k8 ^ ((r / 4) % 4).  A
+  // fragment read takes rows r0 .. r0 + 15 at one k8 (lanes 0-15) and the next k8 in each
+  // further group of 16 lanes: 64-byte rows put the 16 lanes of a group, and the four lanes
+  // of equal lane % 16 across the groups, in distinct banks.
+  auto sw = [](int r, int k) { return ((((k >> 3) ^ (r >> 2)) & 3) << 3) | (k & 7); };
   __shared__ __attribute__((aligned(16))) unsigned short sA[2][2][4][PSA];  // [stage][Q / -Q]
   __shared__ __attribute__((aligned(16))) unsigned short sB[2][4][PSB];
   const long long ntiles = B.first[B.nprob];
@@ -619,13 +631,13 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
       for (int e = 0; e < 8; ++e) {
         const int u = pt + 256 * (e & 3);
         const u4 z = {0u, 0u, 0u, 0u};
-        *reinterpret_cast<u4*>(&sA[st][e >> 2][(u >> 2) & 3][(u >> 4) * RS + 8 * (u & 3)]) =
+        *reinterpret_cast<u4*>(&sA[st][e >> 2][(u >> 2) & 3][(u >> 4) * RS + sw(u >> 4, 8 * (u & 3))]) =
             row0 + (u >> 4) < a.W ? xa[e] : z;
       }
 #pragma unroll
       for (int e = 0; e < NUB; ++e) {
         const int u = pt + 256 * e;
-        *reinterpret_cast<u4*>(&sB[st][(u >> 2) & 3][(u >> 4) * RS + 8 * (u & 3)]) = xb[e];
+        *reinterpret_cast<u4*>(&sB[st][(u >> 2) & 3][(u >> 4) * RS + sw(u >> 4, 8 * (u & 3))]) = xb[e];
       }
     };
 #pragma unroll
@@ -677,7 +689,7 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
         for (int i = 0; i < 2; ++i)
 #pragma unroll
           for (int pl = 0; pl < 4; ++pl)
-            fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][0][pl][(wm * 32 + i * 16 + (lane & 15)) * RS + kq]);
+            fa[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][0][pl][(wm * 32 + i * 16 + (lane & 15)) * RS + sw(lane & 15, kq)]);
         const u16x8 fn[2][2] = {{bf16_neg(fa[0][2]), bf16_neg(fa[0][3])},
                                 {bf16_neg(fa[1][2]), bf16_neg(fa[1][3])}};
 #pragma unroll
@@ -685,7 +697,7 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
           u16x8 fb[4];
 #pragma unroll
           for (int pl = 0; pl < 4; ++pl)
-            fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][(wn * (BN / 2) + j * 16 + (lane & 15)) * RS + kq]);
+            fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][(wn * (BN / 2) + j * 16 + (lane & 15)) * RS + sw(lane & 15, kq)]);
 #pragma unroll
           for (int i = 0; i < 2; ++i) {
             // re += Zr Lr - Zi Li,  im += Zr Li + Zi Lr  (fn: -Zi)
@@ -702,7 +714,7 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
           for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int pl = 0; pl < 4; ++pl)
-              ga[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][1][pl][(wm * 32 + i * 16 + (lane & 15)) * RS + kq]);
+              ga[i][pl] = *reinterpret_cast<const u16x8*>(&sA[st][1][pl][(wm * 32 + i * 16 + (lane & 15)) * RS + sw(lane & 15, kq)]);
           const u16x8 gn[2][2] = {{bf16_neg(ga[0][0]), bf16_neg(ga[0][1])},
                                   {bf16_neg(ga[1][0]), bf16_neg(ga[1][1])}};
 #pragma unroll
@@ -710,7 +722,7 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
             u16x8 fb[4];
 #pragma unroll
             for (int pl = 0; pl < 4; ++pl)
-              fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][(wn * (BN / 2) + j * 16 + (lane & 15)) * RS + kq]);
+              fb[pl] = *reinterpret_cast<const u16x8*>(&sB[st][pl][(wn * (BN / 2) + j * 16 + (lane & 15)) * RS + sw(lane & 15, kq)]);
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
               bcr[i][j] = mul3(ga[i][0], ga[i][1], fb[0], fb[1], bcr[i][j]);

@@ -488,10 +488,15 @@ __global__ __launch_bounds__(64 * NCW + 256) void taylor_bf16x3_kernel(const Bat
   unsigned short* __restrict__ To = a.Tout + (int64_t)w * N * 4 * KP;
   constexpr int QPC = BM / 4;                        // row quads per column
   constexpr int NQ = (QPC * BN + NT - 1) / NT;
+  static_assert(BM % 32 == 0, "row tile of whole 32-row chunks");
 #pragma unroll
   for (int e = 0; e < NQ; ++e) {
+    // eight consecutive units: the eight row quads of one 32-row chunk of one column (64
+    // contiguous bytes of each plane; their result rows fall in distinct LDS banks), then
+    // the next column
     const int u = tid + NT * e;
-    const int cl = u / QPC, rq = 4 * (u % QPC);
+    const int t = u >> 3;
+    const int cl = t % BN, rq = 32 * (t / BN) + 4 * (u & 7);
     const int col = col0 + cl, rb = row0 + rq;
     if (u >= QPC * BN || col >= N || rb >= KP) continue;
     const float2 t0 = res[rq][cl], t1 = res[rq + 1][cl], t2 = res[rq + 2][cl],
