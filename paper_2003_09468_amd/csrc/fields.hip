@@ -514,14 +514,14 @@ __global__ __launch_bounds__(256) void field_split_kernel(const Batch<FieldArgs>
 //   vhs[w][((k-Q) r), (k p)] = sum_g zeta[w][-Q][g] conj(L[Q][k][p][r][g]),
 // a second product on the same B operand.  The product streams the half store once from
 // HBM, so the kernel is persistent and pipelined: each 512-thread workgroup walks its tiles
-// (64 walkers x 96 columns of a slot, tile index blockIdx.x + i gridDim.x over every
-// problem of the batch) as one stream of K chunks of 32.  Waves 4-7 produce: they keep
-// DEPTH chunks of the operands (zeta of Q, of -Q for a paired slot, and L) in flight in
-// registers and copy the oldest into one of two LDS stages; waves 0-3 consume, in 2 x 2
-// (each 32 walkers x 48 columns, 12 BF16 MFMAs per complex 16 x 16 x 32 block and product,
-// FP32 accumulation) and scatter a finished tile straight from registers (the partner
-// block transposed).  One block barrier per chunk; loads are unconditional (clamped
-// addresses, zeros selected afterwards).
+// (64 walkers x 96 columns of a slot, tile index b0 + i gridDim.x over every problem of
+// the batch, b0 a per-XCD regrouping of blockIdx.x) as one stream of K chunks of 32.
+// Waves 4-7 produce: they keep DEPTH chunks of the operands (zeta of Q, of -Q for a paired
+// slot, and L) in flight in registers and copy the oldest into one of two LDS stages;
+// waves 0-3 consume, in 2 x 2 (each 32 walkers x 48 columns, 12 BF16 MFMAs per complex
+// 16 x 16 x 32 block and product, FP32 accumulation) and scatter a finished tile straight
+// from registers (the partner block transposed).  One block barrier per chunk; loads are
+// unconditional (clamped addresses, zeros selected afterwards).
 struct VhsBfArgs {
   int W, nk, m, C, CP, tiles_m, tiles_n;
   KMesh mesh;
@@ -559,7 +559,13 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
   const long long G = gridDim.x;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if ((long long)blockIdx.x >= ntiles) return;
+  // first tile of this workgroup: workgroups are dealt to the 8 XCDs round robin, so with
+  // b0 = (b % 8) (G / 8) + b / 8 the G / 8 workgroups of one XCD take consecutive tiles at
+  // every pass.  Neighbouring column tiles write interleaved short runs of the same rows of
+  // the partner block; on one XCD those partial lines meet in its L2 before write-back.
+  const long long b0 = (G % 8 == 0) ? (long long)(blockIdx.x % 8) * (G / 8) + blockIdx.x / 8
+                                    : (long long)blockIdx.x;
+  if (b0 >= ntiles) return;
   auto decode = [&](long long t, VhsPos& ps) {
     ps.tile = t;
     ps.chunk = 0;
@@ -578,7 +584,7 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
   };
   // the stream length of this workgroup
   long long total = 0;
-  for (long long t = blockIdx.x; t < ntiles; t += G) {
+  for (long long t = b0; t < ntiles; t += G) {
     long long loc;
     total += B.a[batch_find(B, t, loc)].CP / BKC;
   }
@@ -593,7 +599,7 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
     typedef unsigned int u4 __attribute__((ext_vector_type(4)));
     u4 ra[DEPTH][8], rb[DEPTH][NUB];
     VhsPos ip, sp;
-    decode(blockIdx.x, ip);
+    decode(b0, ip);
     sp = ip;
     long long issued = 0;
     auto issue = [&](u4 (&xa)[8], u4 (&xb)[NUB]) {
@@ -675,7 +681,7 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
   };
   zero();
   VhsPos cp;
-  decode(blockIdx.x, cp);
+  decode(b0, cp);
   __syncthreads();
   for (long long s0 = 0; s0 < total; s0 += DEPTH) {
 #pragma unroll
