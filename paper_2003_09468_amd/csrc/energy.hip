@@ -779,24 +779,35 @@ __global__ __launch_bounds__(256) void exchange_int8_kernel(const Batch<ExchArgs
   int e1 = 0, e2 = 0;
   bool bad = false;
   {
-    double v1r[KB][16], v1i[KB][16], v2r[KB][16], v2i[KB][16];
+    // INT8X4: two passes over the column's Gh entries (the second hits the cache), the row
+    // maxima first, then the digits, so that no more than one entry is held at a time; the
+    // register peak then is the chunk loop's and three waves fit a SIMD.  INT8X5's chunk
+    // loop needs more registers than the held entries, so it keeps them from the first pass.
+    constexpr bool RELOAD = (I8_ND == 4);
+    double hv[RELOAD ? 1 : KB][RELOAD ? 1 : 16][4];
+    auto load = [&](int kb, int i, double& x1r, double& x1i, double& x2r, double& x2i) {
+      const int pos = 64 * kb + 16 * (lane >> 4) + i;
+      const bool re = pos < m;
+      const int r = re ? pos : pos - m;
+      x1r = 0.0; x1i = 0.0; x2r = 0.0; x2i = 0.0;
+      if (colok && pos < 2 * m) {
+        const cpx<double> g1 = Gh[((int64_t)wl * nn + (int64_t)kpq * nocc + b_l) * Nn + (int64_t)kq * m + r];
+        const cpx<double> g2 = Gh[((int64_t)wl * nn + (int64_t)k * nocc + b_l) * Nn + (int64_t)kp * m + r];
+        x1r = re ? g1.re : -g1.im; x1i = re ? g1.im : g1.re;
+        x2r = re ? g2.re : -g2.im; x2i = re ? g2.im : g2.re;
+      }
+    };
     double a1 = 0.0, a2 = 0.0;
     int nf = 0;  // a non-finite entry (fmax would drop a NaN)
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        const int pos = 64 * kb + 16 * (lane >> 4) + i;
-        const bool re = pos < m;
-        const int r = re ? pos : pos - m;
-        double x1r = 0.0, x1i = 0.0, x2r = 0.0, x2i = 0.0;
-        if (colok && pos < 2 * m) {
-          const cpx<double> g1 = Gh[((int64_t)wl * nn + (int64_t)kpq * nocc + b_l) * Nn + (int64_t)kq * m + r];
-          const cpx<double> g2 = Gh[((int64_t)wl * nn + (int64_t)k * nocc + b_l) * Nn + (int64_t)kp * m + r];
-          x1r = re ? g1.re : -g1.im; x1i = re ? g1.im : g1.re;
-          x2r = re ? g2.re : -g2.im; x2i = re ? g2.im : g2.re;
+        double x1r, x1i, x2r, x2i;
+        load(kb, i, x1r, x1i, x2r, x2i);
+        if constexpr (!RELOAD) {
+          hv[kb][i][0] = x1r; hv[kb][i][1] = x1i; hv[kb][i][2] = x2r; hv[kb][i][3] = x2i;
         }
-        v1r[kb][i] = x1r; v1i[kb][i] = x1i; v2r[kb][i] = x2r; v2i[kb][i] = x2i;
         a1 = fmax(a1, fmax(fabs(x1r), fabs(x1i)));
         a2 = fmax(a2, fmax(fabs(x2r), fabs(x2i)));
         nf |= !(isfinite(x1r) && isfinite(x1i) && isfinite(x2r) && isfinite(x2i));
@@ -818,19 +829,25 @@ __global__ __launch_bounds__(256) void exchange_int8_kernel(const Batch<ExchArgs
         int w1r[I8_ND] = {}, w1i[I8_ND] = {}, w2r[I8_ND] = {}, w2i[I8_ND] = {};
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int i = 4 * q + u;
+          double x1r, x1i, x2r, x2i;
+          if constexpr (RELOAD) {
+            load(kb, 4 * q + u, x1r, x1i, x2r, x2i);
+          } else {
+            x1r = hv[kb][4 * q + u][0]; x1i = hv[kb][4 * q + u][1];
+            x2r = hv[kb][4 * q + u][2]; x2i = hv[kb][4 * q + u][3];
+          }
           int d[I8_ND];
           static_assert(sizeof(d) == I8_ND * sizeof(int), "");
-          i8_digits(bad ? 0.0 : v1r[kb][i], e1, d);
+          i8_digits(bad ? 0.0 : x1r, e1, d);
 #pragma unroll
           for (int j = 0; j < I8_ND; ++j) w1r[j] |= (d[j] & 0xff) << (8 * u);
-          i8_digits(bad ? 0.0 : v1i[kb][i], e1, d);
+          i8_digits(bad ? 0.0 : x1i, e1, d);
 #pragma unroll
           for (int j = 0; j < I8_ND; ++j) w1i[j] |= (d[j] & 0xff) << (8 * u);
-          i8_digits(bad ? 0.0 : v2r[kb][i], e2, d);
+          i8_digits(bad ? 0.0 : x2r, e2, d);
 #pragma unroll
           for (int j = 0; j < I8_ND; ++j) w2r[j] |= (d[j] & 0xff) << (8 * u);
-          i8_digits(bad ? 0.0 : v2i[kb][i], e2, d);
+          i8_digits(bad ? 0.0 : x2i, e2, d);
 #pragma unroll
           for (int j = 0; j < I8_ND; ++j) w2i[j] |= (d[j] & 0xff) << (8 * u);
         }

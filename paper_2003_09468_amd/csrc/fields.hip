@@ -156,8 +156,10 @@ __global__ __launch_bounds__(256) void vbias_bf16x3_kernel(const Batch<VbBfArgs>
   // 16-byte slot of the 8 k at k8 = k / 8 in row r: k8 ^ ((r / 4) % 4), so that the 16 rows
   // of a fragment read (and the four lane groups at one row) fall in distinct banks
   auto sw = [](int r, int k) { return ((((k >> 3) ^ (r >> 2)) & 3) << 3) | (k & 7); };
+  // the g tiles of one (Q, slice) read the same Gh rows: consecutive tiles, which
+  // xcd_remap keeps on one XCD, share them in its L2
   long long loc;
-  const int pb = batch_find(B, blockIdx.x, loc);
+  const int pb = batch_find(B, xcd_remap(blockIdx.x, gridDim.x), loc);
   const VbBfArgs& a = B.a[pb];
   const int tw = (int)(loc % a.tiles_w);
   long long rest = loc / a.tiles_w;
@@ -559,12 +561,9 @@ __global__ __launch_bounds__(512) void vhs_bf16x3_kernel(const Batch<VhsBfArgs> 
   const long long G = gridDim.x;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  // first tile of this workgroup: workgroups are dealt to the 8 XCDs round robin, so with
-  // b0 = (b % 8) (G / 8) + b / 8 the G / 8 workgroups of one XCD take consecutive tiles at
-  // every pass.  Neighbouring column tiles write interleaved short runs of the same rows of
-  // the partner block; on one XCD those partial lines meet in its L2 before write-back.
-  const long long b0 = (G % 8 == 0) ? (long long)(blockIdx.x % 8) * (G / 8) + blockIdx.x / 8
-                                    : (long long)blockIdx.x;
+  // first tile of this workgroup: the workgroups of one XCD take consecutive tiles at every
+  // pass, so the fields of Q and -Q that neighbouring column tiles share stay in its L2
+  const long long b0 = xcd_remap(blockIdx.x, G);
   if (b0 >= ntiles) return;
   auto decode = [&](long long t, VhsPos& ps) {
     ps.tile = t;

@@ -971,9 +971,15 @@ hipError_t run_greens(const Job* jobs, int n, bool write_logdet_new_only, hipStr
     if (e != hipSuccess) return e;
     e = launch_gj_blocked(J, c, omat, oinvT, ldo, s);
     if (e != hipSuccess) return e;
-    if (nd) e = launch_ops<64, 64, 16, 2, 2>(sv, nd, s);
+    // up to 112 rows (nk nocc) in one row tile, so that every U column is read once
+    int md = 0, mf = 0;
+    for (int q = 0; q < nd; ++q) md = sv[q].M > md ? sv[q].M : md;
+    for (int q = 0; q < nf; ++q) mf = sf[q].M > mf ? sf[q].M : mf;
+    if (nd) e = (md <= 112) ? launch_ops<112, 64, 16, 1, 4>(sv, nd, s)
+                            : launch_ops<64, 64, 16, 2, 2>(sv, nd, s);
     if (e != hipSuccess) return e;
-    if (nf) e = launch_ops<64, 64, 16, 2, 2>(sf, nf, s);
+    if (nf) e = (mf <= 112) ? launch_ops<112, 64, 16, 1, 4>(sf, nf, s)
+                            : launch_ops<64, 64, 16, 2, 2>(sf, nf, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
