@@ -756,15 +756,22 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const Batch<CholArgs> B) 
 
 // ---------------------------------------------------------------------------
 // The same for n <= 128 with the lower triangle in LDS (n (n + 1) / 2 complex entries,
-// 132 KB at n = 128), one 256-thread workgroup per walker.  Cholesky column j
-// (left-looking): thread r >= j forms t_r = S[r][j] - sum_{k<j} L[r][k] conj(L[j][k]) from
+// 132 KB at n = 128), one 512-thread workgroup per walker, four threads per row (each
+// takes every fourth term of a row's sum, combined by lane exchanges).  Cholesky column j
+// (left-looking): row r >= j forms t_r = S[r][j] - sum_{k<j} L[r][k] conj(L[j][k]) from
 // LDS.  Then the factor is inverted in place, column by column from the last: with
 // X = L^{-1}, X L = I gives X[i][j] = -(sum_{k=j+1}^{i} X[i][k] L[k][j]) / L[j][j] (i > j),
 // which needs only the columns of X to the right of j and column j of L.  Output as the
 // L2 version: out[c][i] = conj(X[i][c]), the rows of R^{-1} = X^H.
 __device__ __forceinline__ int tri(int r, int k) { return r * (r + 1) / 2 + k; }
 
-__global__ __launch_bounds__(256) void chol_inv_lds_kernel(const Batch<CholArgs> B) {
+__device__ __forceinline__ double quad_sum(double v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(512) void chol_inv_lds_kernel(const Batch<CholArgs> B) {
   constexpr int NMAX = 128;
   __shared__ cpx<double> T[NMAX * (NMAX + 1) / 2];
   __shared__ double diag[NMAX];
@@ -776,29 +783,35 @@ __global__ __launch_bounds__(256) void chol_inv_lds_kernel(const Batch<CholArgs>
   const cpx<double>* __restrict__ S = B.a[pb].S + (int64_t)w * n * n;
   cpx<double>* __restrict__ out = B.a[pb].out + (int64_t)w * n * n;
   const int tid = threadIdx.x;
+  const int r = tid >> 2, sub = tid & 3;  // row, and the residue of its terms mod 4
   if (tid == 0) flag_s = 0;
-  for (int e = tid; e < n * n; e += 256) {
-    const int r = e / n, k = e % n;
-    if (k <= r) T[tri(r, k)] = S[e];
+  for (int e = tid; e < n * n; e += 512) {
+    const int rr = e / n, k = e % n;
+    if (k <= rr) T[tri(rr, k)] = S[e];
   }
   __syncthreads();
   int bad = 0;  // 1: non-positive pivot, 2: non-finite
   for (int j = 0; j < n; ++j) {
-    const int r = tid;
     double tr = 0.0, ti = 0.0;
-    if (r >= j && r < n) {
+    const bool act = r >= j && r < n;
+    if (act) {
       const cpx<double>* Lr = T + tri(r, 0);
       const cpx<double>* Lj = T + tri(j, 0);
-      tr = Lr[j].re;
-      ti = Lr[j].im;
 #pragma unroll 4
-      for (int k = 0; k < j; ++k) {
+      for (int k = sub; k < j; k += 4) {
         const cpx<double> a = Lr[k], b = Lj[k];
-        tr -= a.re * b.re + a.im * b.im;
-        ti -= a.im * b.re - a.re * b.im;
+        tr += a.re * b.re + a.im * b.im;
+        ti += a.im * b.re - a.re * b.im;
       }
     }
-    if (r == j) {
+    tr = quad_sum(tr);
+    ti = quad_sum(ti);
+    if (act) {
+      const cpx<double> sv = T[tri(r, j)];
+      tr = sv.re - tr;
+      ti = sv.im - ti;
+    }
+    if (act && r == j && sub == 0) {
       double d = tr;
       if (!(d > 0.0) || !isfinite(d)) {
         bad |= isfinite(d) ? 1 : 2;
@@ -807,7 +820,7 @@ __global__ __launch_bounds__(256) void chol_inv_lds_kernel(const Batch<CholArgs>
       diag[j] = sqrt(d);
     }
     __syncthreads();
-    if (r >= j && r < n) {
+    if (act && sub == 0) {
       const double sd = diag[j];
       T[tri(r, j)] = (r == j) ? cpx<double>{sd, 0.0} : cpx<double>{tr / sd, ti / sd};
     }
@@ -818,28 +831,29 @@ __global__ __launch_bounds__(256) void chol_inv_lds_kernel(const Batch<CholArgs>
   const int fl = flag_s;
   if (!fl) {
     for (int j = n - 1; j >= 0; --j) {
-      const int i = tid;
+      const int i = r;
+      const bool act = i > j && i < n;
       double xr = 0.0, xi = 0.0;
-      if (i > j && i < n) {
+      if (act) {
         const cpx<double>* Xi = T + tri(i, 0);
 #pragma unroll 4
-        for (int k = j + 1; k <= i; ++k) {
+        for (int k = j + 1 + sub; k <= i; k += 4) {
           const cpx<double> x = Xi[k], l = T[tri(k, j)];  // X[i][k] L[k][j]
           xr += x.re * l.re - x.im * l.im;
           xi += x.re * l.im + x.im * l.re;
         }
-        const double id = 1.0 / diag[j];
-        xr *= -id;
-        xi *= -id;
       }
+      xr = quad_sum(xr);
+      xi = quad_sum(xi);
+      const double id = 1.0 / diag[j];
       __syncthreads();
-      if (i > j && i < n) T[tri(i, j)] = cpx<double>{xr, xi};
-      if (i == j) T[tri(j, j)] = cpx<double>{1.0 / diag[j], 0.0};
+      if (act && sub == 0) T[tri(i, j)] = cpx<double>{-xr * id, -xi * id};
+      if (tid == 0) T[tri(j, j)] = cpx<double>{id, 0.0};
       __syncthreads();
     }
   }
   // out[c][i] = conj(X[i][c]) for i >= c, 0 below; identity for a flagged walker
-  for (int e = tid; e < n * n; e += 256) {
+  for (int e = tid; e < n * n; e += 512) {
     const int c = e / n, i = e % n;
     cpx<double> v{0.0, 0.0};
     if (fl) {
@@ -876,7 +890,7 @@ static hipError_t launch_chol_inv(const Job* jobs, const int* ids, int c, void* 
   if (g < 0) return hipErrorInvalidValue;
   if (g == 0) return hipSuccess;
   if (B.a[0].n <= 128)
-    hipLaunchKernelGGL(chol_inv_lds_kernel, dim3((unsigned)g), dim3(256), 0, s, B);
+    hipLaunchKernelGGL(chol_inv_lds_kernel, dim3((unsigned)g), dim3(512), 0, s, B);
   else
     hipLaunchKernelGGL(chol_inv_kernel, dim3((unsigned)g), dim3(256), 0, s, B);
   return hipGetLastError();
