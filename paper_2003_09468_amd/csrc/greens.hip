@@ -397,11 +397,21 @@ __global__ __launch_bounds__(512) void gj_reg_kernel(const Batch<GjbArgs> B) {
         }
         const int q = 255 - (int)(kmax & 0xffull);
         const int ql = q & 63, qsl = q >> 6;
+        // the pivot row by readlane from the lane that holds it (qsl is wave-uniform: a
+        // branch, not a select per value)
         double br[PW], bi[PW];
+        if (qsl) {
 #pragma unroll
-        for (int c = 0; c < PW; ++c) {
-          br[c] = dbl_readlane(qsl ? AR(1, c) : AR(0, c), ql);
-          bi[c] = dbl_readlane(qsl ? AI(1, c) : AI(0, c), ql);
+          for (int c = 0; c < PW; ++c) {
+            br[c] = dbl_readlane(AR(1, c), ql);
+            bi[c] = dbl_readlane(AI(1, c), ql);
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < PW; ++c) {
+            br[c] = dbl_readlane(AR(0, c), ql);
+            bi[c] = dbl_readlane(AI(0, c), ql);
+          }
         }
         double vr = br[jj], vi = bi[jj];
         double den = vr * vr + vi * vi;
@@ -430,8 +440,9 @@ __global__ __launch_bounds__(512) void gj_reg_kernel(const Batch<GjbArgs> B) {
             const double gr = fr * ir - fi * ii, gi = fr * ii + fi * ir;
 #pragma unroll
             for (int c = 0; c < PW; ++c) {
-              const double ur = AR(sl, c) - (gr * br[c] - gi * bi[c]);
-              const double ui = AI(sl, c) - (gr * bi[c] + gi * br[c]);
+              // a - g b as two fused steps per component
+              const double ur = fma(-gr, br[c], fma(gi, bi[c], AR(sl, c)));
+              const double ui = fma(-gr, bi[c], fma(-gi, br[c], AI(sl, c)));
               AR(sl, c) = (c == jj) ? -gr : ur;
               AI(sl, c) = (c == jj) ? -gi : ui;
             }
