@@ -295,6 +295,41 @@ def test_large_ortho_rank_deficient_walker():
     assert rel(Uo[[0, 2]], Q) < 1e-11
 
 
+# ---------------------------------------------------------------------------
+# occupied dimensions at the limits of the register-resident inverse (nk*nocc = 112) and of
+# the LDS-resident Cholesky factor (128: every row of the four-lanes-per-row kernel in use)
+
+@pytest.mark.parametrize("nocc", [14, 16])
+def test_inverse_and_cholesky_size_limits(nocc):
+    """nk*nocc = 112 and 128 on a 2x2x2 mesh: Green's function, log overlap and the QR."""
+    s, U, x, p, pre = build(((2, 2, 2), 17, nocc, 9, 3, "random", "dense"))
+    Gh, ld = kp.greens(U, s.A)
+    assert rel(host(p.Gh), Gh) < 1e-10
+    assert phase_err(host(p.logdet), ld) < 1e-10
+    assert int(host(p.status).max()) == 0
+    Ub = U * 2.0 + 0.3 * np.roll(U, 1, axis=2)
+    p.set_walkers(torch.from_numpy(Ub))
+    check_ortho(p, s, Ub)
+
+
+def test_lds_ortho_rank_deficient_walker():
+    """nk*nocc = 128 (the LDS Cholesky): a walker with a zero orbital is flagged and left
+    unchanged, the others are re-orthonormalised."""
+    s, U, x, p, pre = build(((2, 2, 2), 17, 16, 9, 3, "random", "dense"))
+    Ub = U.copy()
+    Ub[1][:, 11] = 0.0
+    p.set_walkers(torch.from_numpy(Ub))
+    p.orthonormalize()
+    torch.cuda.synchronize()
+    st = host(p.status)
+    assert st[1] & 1
+    assert st[0] == 0 and st[2] == 0
+    Uo = host(p.U)
+    assert np.array_equal(Uo[1], Ub[1])
+    Q = kp.orthonormalize(Ub[[0, 2]])
+    assert rel(Uo[[0, 2]], Q) < 1e-11
+
+
 def test_mixed_energy():
     """The weighted average of the walkers' energies after a step, on the GPU's own energies
     and weights, against the oracle's formula; also on every system of a batch."""
