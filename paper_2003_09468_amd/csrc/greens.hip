@@ -1033,7 +1033,7 @@ struct WeightArgs {
   int* status2;
 };
 
-__global__ __launch_bounds__(256) void weight_kernel(const Batch<WeightArgs> B) {
+__global__ __launch_bounds__(1024) void weight_kernel(const Batch<WeightArgs> B) {
   long long wloc;
   const int pb = batch_find(B, blockIdx.x, wloc);
   const int64_t nf = B.a[pb].nf;
@@ -1045,19 +1045,21 @@ __global__ __launch_bounds__(256) void weight_kernel(const Batch<WeightArgs> B) 
   int* __restrict__ status = B.a[pb].status;
   const int w = (int)wloc;
   const int tid = threadIdx.x;
-  __shared__ double sr[256], si[256];
+  constexpr int NT = 1024;
+  __shared__ double sr[NT], si[NT];
   double ar = 0.0, ai = 0.0;
   const double* xw = x + (int64_t)w * nf;
   const cpx<double>* bw = xbar + (int64_t)w * nf;
   // eight elements per thread and pass, all loads issued before the sums (one workgroup per
-  // walker: the latency of the loads, not their bytes, bounds this loop)
+  // walker: the latency of the loads, not their bytes, bounds this loop, so the workgroup
+  // is as wide as allowed and a c1 walker takes two passes)
   constexpr int U = 8;
-  for (int64_t i0 = tid; i0 < nf; i0 += 256 * U) {
+  for (int64_t i0 = tid; i0 < nf; i0 += NT * U) {
     double xv[U];
     cpx<double> b[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t i = i0 + 256 * u;
+      const int64_t i = i0 + NT * u;
       xv[u] = i < nf ? xw[i] : 0.0;
       b[u] = i < nf ? bw[i] : cpx<double>{0.0, 0.0};
     }
@@ -1071,7 +1073,7 @@ __global__ __launch_bounds__(256) void weight_kernel(const Batch<WeightArgs> B) 
   sr[tid] = ar;
   si[tid] = ai;
   __syncthreads();
-  for (int o = 128; o >= 1; o >>= 1) {
+  for (int o = NT / 2; o >= 1; o >>= 1) {
     if (tid < o) { sr[tid] += sr[tid + o]; si[tid] += si[tid + o]; }
     __syncthreads();
   }
@@ -1162,7 +1164,7 @@ hipError_t launch_weights(const Job* jobs, int n, hipStream_t s) {
     const long long g = batch_close(B, cnt);
     if (g < 0) return hipErrorInvalidValue;
     if (g == 0) continue;
-    hipLaunchKernelGGL(weight_kernel, dim3((unsigned)g), dim3(256), 0, s, B);
+    hipLaunchKernelGGL(weight_kernel, dim3((unsigned)g), dim3(1024), 0, s, B);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
