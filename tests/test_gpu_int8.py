@@ -124,9 +124,14 @@ def test_int8x5_placed_with_bf16x3_step_block():
 
 
 @pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
-def test_int8x5_nonfinite_green_function_gives_nonfinite_energy():
-    s, U, x, p, pre = build("c0", prec=lib.prec_place(lib.PREC_FP64, lib.PREC_INT8X5))
+@pytest.mark.parametrize("digits", [5, 4])
+@pytest.mark.parametrize("bad", ["nan", "inf"])
+def test_int8_nonfinite_green_function_gives_nonfinite_energy(digits, bad):
+    """A non-finite Gh entry of one walker gives that walker a non-finite exchange and leaves
+    the others finite (both digit counts: INT8X4 forms its digits in a second pass)."""
+    ep = lib.PREC_INT8X5 if digits == 5 else lib.PREC_INT8X4
+    s, U, x, p, pre = build("c0", prec=lib.prec_place(lib.PREC_FP64, ep))
     G = p.Gh.clone()
-    G[1, 0, 3] = complex("nan")
+    G[1, 0, 3] = complex(bad)
     E = host(p.energy(Gh=G))
     assert not np.isfinite(E[1, 2]) and np.all(np.isfinite(E[[0, 2, 3], 2]))
